@@ -1,0 +1,202 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the smoke check.
+
+This module only draws data.  It holds none of the selection method's
+arithmetic (no objective, no counts, no cutting plane, no residual of a
+regression candidate), so that the CPU oracle and the HIP library can both
+consume its arrays without sharing any code with each other.
+
+Every array is a pure function of (tag, seed, array id, size, dtype): the
+bits come from numpy's Philox-4x64 counter-based generator (Salmon, Moraes,
+Dror and Shaw, SC'11).  Large arrays are generated in fixed chunks of
+``CHUNK`` elements; chunk ``c`` uses the key's stream advanced by ``c`` jumps,
+so the result does not depend on the number of worker threads.
+
+Distributions follow the paper's empirical study (Section 5.1: uniform,
+normal, half-normal, beta(2,5) and five two-component mixtures, plus arrays
+with a few ~1e9 outliers) and the workloads the benchmark is quoted on
+(Cauchy, normal quantised to 1024 levels, lognormal, seeded permutations).
+"""
+from __future__ import annotations
+
+import hashlib
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+CHUNK = 1 << 20
+
+DISTRIBUTIONS = (
+    "uniform", "normal", "cauchy", "quantized_normal", "lognormal",
+    "halfnormal", "beta25", "mix1", "mix2", "mix3", "mix4", "mix5",
+    "outliers", "permutation", "constant", "smallint",
+)
+
+
+def _key(tag: str, seed: int, array_id: int) -> int:
+    h = hashlib.sha256(f"{tag}|{seed}|{array_id}".encode()).digest()
+    return int.from_bytes(h[:16], "little")
+
+
+def generator(tag: str, seed: int, array_id: int = 0, chunk: int = 0) -> np.random.Generator:
+    """A numpy Generator on the Philox stream for (tag, seed, array_id), advanced by `chunk` jumps."""
+    bg = np.random.Philox(key=_key(tag, seed, array_id))
+    if chunk:
+        bg = bg.jumped(chunk)
+    return np.random.Generator(bg)
+
+
+def _threads() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _chunk_values(dist: str, rng: np.random.Generator, m: int, dtype) -> np.ndarray:
+    f32 = np.dtype(dtype) == np.float32
+    if dist == "uniform":
+        # f32: 24 random bits scaled by 2^-24; f64: 53 bits by 2^-53 (never rounds up to 1.0)
+        return rng.random(m, dtype=np.float32 if f32 else np.float64)
+    if dist == "normal":
+        return rng.standard_normal(m).astype(dtype)
+    if dist == "cauchy":
+        return rng.standard_cauchy(m).astype(dtype)
+    if dist == "quantized_normal":
+        z = rng.standard_normal(m)
+        level = np.clip(np.floor((z + 4.0) * 128.0), 0, 1023)
+        return (-4.0 + (level + 0.5) / 128.0).astype(dtype)
+    if dist == "lognormal":
+        return np.exp(rng.standard_normal(m)).astype(dtype)
+    if dist == "halfnormal":
+        return np.abs(rng.standard_normal(m)).astype(dtype)
+    if dist == "beta25":
+        return rng.beta(2.0, 5.0, m).astype(dtype)
+    if dist in ("mix1", "mix2", "mix4", "mix5"):
+        # first component N(0,1) (mix1, mix2) or half-normal (mix4, mix5); second N(100,1)
+        frac = 2.0 / 3.0 if dist in ("mix1", "mix4") else 0.5
+        first = rng.random(m) < frac
+        a = rng.standard_normal(m)
+        if dist in ("mix4", "mix5"):
+            a = np.abs(a)
+        b = 100.0 + rng.standard_normal(m)
+        return np.where(first, a, b).astype(dtype)
+    if dist == "mix3":
+        a = np.abs(rng.standard_normal(m))
+        ten = rng.random(m) < 0.1
+        return np.where(ten, 10.0, a).astype(dtype)
+    if dist == "outliers":
+        x = rng.standard_normal(m)
+        hit = rng.random(m) < 1e-5
+        return np.where(hit, 1e9 * (1.0 + rng.random(m)), x).astype(dtype)
+    if dist == "smallint":
+        return rng.integers(0, 16, m).astype(dtype)
+    raise ValueError(f"unknown distribution {dist!r}")
+
+
+def single_array(dist: str, n: int, dtype=np.float32, seed: int = 0, array_id: int = 0,
+                 tag: str = "single") -> np.ndarray:
+    """One seeded array of n values of `dtype` drawn from `dist`."""
+    dtype = np.dtype(dtype)
+    if n < 0:
+        raise ValueError("n must be >= 0")
+    if dist == "permutation":
+        # a seeded permutation of 0..n-1: the k-th smallest is exactly k-1
+        rng = generator(tag + ":perm", seed, array_id)
+        return rng.permutation(n).astype(dtype)
+    if dist == "constant":
+        rng = generator(tag + ":const", seed, array_id)
+        v = float(rng.standard_normal())
+        return np.full(n, v, dtype=dtype)
+    if dist == "mix2" or dist == "mix5":
+        # "50% of the elements plus one" from the first component, the rest from N(100,1):
+        # exact proportions, then a seeded shuffle.
+        rng = generator(tag + ":" + dist, seed, array_id)
+        n1 = n // 2 + 1 if n else 0
+        a = rng.standard_normal(n1)
+        if dist == "mix5":
+            a = np.abs(a)
+        b = 100.0 + rng.standard_normal(n - n1)
+        x = np.concatenate([a, b])
+        rng.shuffle(x)
+        return x.astype(dtype)
+    out = np.empty(n, dtype=dtype)
+    nchunks = (n + CHUNK - 1) // CHUNK
+
+    def fill(c: int) -> None:
+        lo, hi = c * CHUNK, min(n, (c + 1) * CHUNK)
+        rng = generator(tag + ":" + dist, seed, array_id, chunk=c)
+        out[lo:hi] = _chunk_values(dist, rng, hi - lo, dtype)
+
+    if nchunks <= 1:
+        for c in range(nchunks):
+            fill(c)
+    else:
+        with ThreadPoolExecutor(_threads()) as ex:
+            list(ex.map(fill, range(nchunks)))
+    return out
+
+
+def ks_for(n: int) -> list[int]:
+    """The four ranks the single-array workloads use: 1, n/100, the lower median, n-1 (1-based)."""
+    ks = [1, max(1, n // 100), (n + 1) // 2, max(1, n - 1)]
+    return ks
+
+
+def batched_sizes(count: int, seed: int = 0, lo_exp: float = 3.0, hi_exp: float = 6.0) -> np.ndarray:
+    """Sizes floor(10^(lo_exp + (hi_exp-lo_exp)*u)), u ~ U[0,1) seeded (log-uniform)."""
+    rng = generator("batched:sizes", seed)
+    u = rng.random(count)
+    return np.floor(10.0 ** (lo_exp + (hi_exp - lo_exp) * u)).astype(np.int64)
+
+
+def batched_arrays(count: int, seed: int = 0, dtype=np.float32, lo_exp: float = 3.0,
+                   hi_exp: float = 6.0, dist: str = "lognormal"):
+    """`count` arrays with log-uniform sizes, values from `dist`; returns (list of arrays, sizes, median ks)."""
+    sizes = batched_sizes(count, seed, lo_exp, hi_exp)
+    arrays = [None] * count
+
+    def one(i: int) -> None:
+        rng = generator("batched:" + dist, seed, i)
+        arrays[i] = _chunk_values(dist, rng, int(sizes[i]), dtype)
+
+    with ThreadPoolExecutor(_threads()) as ex:
+        list(ex.map(one, range(count)))
+    ks = (sizes + 1) // 2
+    return arrays, sizes, ks
+
+
+def _fixed_order_dot(X: np.ndarray, b: np.ndarray) -> np.ndarray:
+    # sum_j X[:, j] * b[j] accumulated left to right; numpy elementwise ops are
+    # IEEE round-to-nearest with no fused multiply-add.
+    s = X[:, 0] * b[0]
+    for j in range(1, X.shape[1]):
+        s = s + X[:, j] * b[j]
+    return s
+
+
+def lms_problem(n: int, p: int = 8, m: int = 1024, seed: int = 0, contamination: float = 0.3,
+                shift: float = 10.0, noise: float = 0.1):
+    """Robust-regression inputs: X (n x p, row-major f64), y, the true beta, and m candidate betas.
+
+    y = X beta* + N(0, noise^2), with exactly floor(contamination*n) seeded rows shifted
+    by +shift.  Each candidate solves the p x p system of a seeded p-row elemental subset
+    (LU with partial pivoting from LAPACK; subsets with a tiny pivot are redrawn).
+    """
+    rng = generator("lms", seed)
+    X = rng.standard_normal((n, p))
+    beta_true = rng.standard_normal(p)
+    y = _fixed_order_dot(X, beta_true) + noise * rng.standard_normal(n)
+    bad = rng.choice(n, size=int(np.floor(contamination * n)), replace=False)
+    y[bad] += shift
+    betas = np.empty((m, p))
+    j = 0
+    while j < m:
+        rows = rng.choice(n, size=p, replace=False)
+        A = X[rows]
+        try:
+            sol = np.linalg.solve(A, y[rows])
+        except np.linalg.LinAlgError:
+            continue
+        if not np.all(np.isfinite(sol)) or np.min(np.abs(np.linalg.svd(A, compute_uv=False))) < 1e-12:
+            continue
+        betas[j] = sol
+        j += 1
+    return np.ascontiguousarray(X), y, beta_true, betas
