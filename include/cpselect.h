@@ -1,0 +1,192 @@
+/*
+ * cpselect.h - exact k-th order statistic selection on one MI355X (gfx950) GPU,
+ * by Kelley's cutting-plane minimisation of a convex piecewise-linear objective.
+ *
+ * Method (Beliakov, "Parallel calculation of the median and order statistics on
+ * GPUs with application to robust regression"):
+ *   - Section 1: x_(k) is the k-th smallest element of x (1-based k); the median
+ *     is x_([(n+1)/2]), the lower median for even n.
+ *   - Section 3, Eq. 2: x_(k) minimises f(y) = sum_i max(alpha (x_i - y), beta (y - x_i))
+ *     with alpha = k - 1/2 and beta = n - k + 1/2 (this orientation is the one whose
+ *     minimiser is the k-th smallest; the printed weights are swapped).  Its Clarke
+ *     subdifferential at y is [n (L - k + 1/2), n (L + E - k + 1/2)] with L = #(x<y),
+ *     E = #(x=y), so 0 lies in it exactly when L < k <= L + E.
+ *   - Section 4, Algorithm 1: Kelley's cutting plane keeps a bracket [y_L, y_R] and
+ *     moves to the intersection of the two supporting lines at its ends; step 0 takes
+ *     the data extremes, with f and g there from min, max and sum(x) in one reduction.
+ *     The hybrid at the end of Section 4 stops the iterations early, copies the
+ *     elements inside the open bracket to a smaller array and selects there exactly.
+ *
+ * Every call is asynchronous on `stream` (a hipStream_t; NULL means the default
+ * stream) and returns CPS_OK or a negative synchronous error code.  Results land in
+ * caller-owned DEVICE memory; nothing is copied to the host and the library never
+ * synchronises the stream.  Input arrays are caller-owned device memory, read only,
+ * and must stay valid until the stream reaches the call.  Errors found on the device
+ * while running (NaN in the data, a wait that timed out) are reported in the result's
+ * `status` field, not as a return code.
+ *
+ * Data types: CPS_F32 (float) and CPS_F64 (double).  Ordering is IEEE "<": -0.0 and
+ * +0.0 are equal, and the selected value is returned with +0.0 for zero.  NaN is not
+ * ordered: an input holding NaN yields status CPS_STATUS_NAN.
+ */
+#ifndef CPSELECT_H
+#define CPSELECT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ codes */
+
+enum cps_dtype { CPS_F32 = 0, CPS_F64 = 1 };
+
+enum cps_error {
+  CPS_OK = 0,
+  CPS_EINVAL = -1,   /* bad argument: null pointer, n < 1, k outside [1, n], bad dtype or size */
+  CPS_ENOMEM = -2,   /* the workspace could not be allocated */
+  CPS_EHIP = -3,     /* a HIP runtime call failed (see cps_last_hip_error) */
+  CPS_ECAPTURE = -4, /* the call would have to allocate while the stream is being captured */
+  CPS_ENODEV = -5,   /* no usable gfx950 device */
+  CPS_ESTATE = -6    /* the handle is in an unusable state */
+};
+
+/* Asynchronous status, written by the device into cps_result.status. */
+enum cps_status {
+  CPS_STATUS_OK = 0,
+  CPS_STATUS_NAN = 1,     /* the array holds NaN; value is NaN, counts are 0 */
+  CPS_STATUS_TIMEOUT = 2, /* a device-side wait exceeded the spin limit; result invalid */
+  CPS_STATUS_INTERNAL = 3 /* an internal consistency check failed; result invalid */
+};
+
+/* ------------------------------------------------------------------ records */
+
+/* Result of one selection (48 bytes, device memory).
+ * value_bits: raw bits of the selected element in its own type, zero-extended (f32 in
+ *             the low 32 bits); the bit-exact comparison key.
+ * value:      the selected element widened to double.
+ * less, equal, greater: #(x < value), #(x == value), #(x > value).
+ * passes:     full reads of the input array (pass 0 included) the call made.
+ * status:     a cps_status value. */
+typedef struct cps_result {
+  uint64_t value_bits;
+  double value;
+  int64_t less, equal, greater;
+  int32_t passes;
+  int32_t status;
+} cps_result;
+
+/* Objective and counts at one trial point y (Section 3), 80 bytes, device memory.
+ * f = alpha A + beta B; A = sum over x_i > y of (x_i - y); B = sum over x_i < y of (y - x_i);
+ * L, E, G = #(x<y), #(x=y), #(x>y); pred = largest x_i < y (-inf if none), succ = smallest
+ * x_i > y (+inf if none); gminus = n (L - k + 1/2), gplus = n (L + E - k + 1/2).
+ * Comparisons and terms are taken in double precision on the widened element. */
+typedef struct cps_eval {
+  double f, A, B;
+  int64_t L, E, G;
+  double pred, succ;
+  double gminus, gplus;
+} cps_eval;
+
+/* Tuning and test options for select_kth_ex.  Fill with cps_default_options first.
+ * maxit:            cutting-plane iterations before the method falls back to bisection of
+ *                   the bracket in the ordered bit pattern of T (which bounds the passes).
+ * final_threshold:  when the bracket holds at most this many elements, one workgroup
+ *                   finishes with an exact radix select (Section 4's final exact step).
+ * partition_fraction: once the bracket holds at most this fraction of n, each pass also
+ *                   splits the bracket's elements at the trial point into a workspace
+ *                   buffer, and later passes read only the side that still holds x_(k)
+ *                   (the count-and-compact of Section 4, applied at every later pass).
+ *                   0 disables splitting (plain passes over x, then one compaction).
+ * grid_blocks, block_threads: launch shape; 0 picks the tuned default.
+ * spin_limit:       bound on device-side waiting loops (iterations); 0 = default.
+ * bracket_lo/hi, use_bracket: a caller-supplied starting bracket (tests; the proposal
+ *                   path).  It is verified by counts and ignored when it does not hold
+ *                   x_(k); the result never depends on it. */
+typedef struct cps_options {
+  int32_t maxit;
+  int32_t final_threshold;
+  double partition_fraction;
+  int32_t grid_blocks;
+  int32_t block_threads;
+  int64_t spin_limit;
+  int32_t use_bracket;
+  int32_t reserved0;
+  double bracket_lo, bracket_hi;
+} cps_options;
+
+#define CPS_STATS_MAX_PASSES 96
+
+/* Per-call trace written by select_kth_ex when stats_dev is not NULL (device memory).
+ * passes:       full reads of the input (pass 0 included).
+ * work_passes:  all reduction passes, including those over the split buffers.
+ * kelley_steps, bisect_steps: how each trial point was chosen.
+ * elements_read, elements_written: elements the passes moved (algorithmic traffic).
+ * population[i]: elements inside the open bracket after pass i.
+ * working[i]:   elements pass i read. */
+typedef struct cps_stats {
+  int32_t passes;
+  int32_t work_passes;
+  int32_t kelley_steps;
+  int32_t bisect_steps;
+  int32_t final_select_size;
+  int32_t bracket_used;
+  int64_t elements_read;
+  int64_t elements_written;
+  int64_t population[CPS_STATS_MAX_PASSES];
+  int64_t working[CPS_STATS_MAX_PASSES];
+} cps_stats;
+
+typedef struct cps_handle cps_handle;
+
+/* ------------------------------------------------------------------ handle */
+
+/* Create a handle bound to HIP device `device` (which must be gfx950).  The handle owns
+ * the workspace (grown on demand outside stream capture) and the launch configuration.
+ * Returns CPS_ENODEV when the device is missing or not gfx950. */
+int cps_create(int device, cps_handle **out);
+
+/* Destroy a handle.  The caller must have synchronised every stream used with it. */
+int cps_destroy(cps_handle *h);
+
+/* Human-readable text for a cps_error or cps_status code (static storage). */
+const char *cps_status_string(int code);
+
+/* The last HIP error code seen by the library in this thread (0 if none). */
+int cps_last_hip_error(void);
+
+/* Defaults for select_kth_ex. */
+void cps_default_options(cps_options *opt);
+
+/* Make sure the workspace can serve a single-array call of n elements of `dtype`, so
+ * that a later call made under stream capture does not need to allocate. */
+int cps_reserve(cps_handle *h, int64_t n, int dtype);
+
+/* ------------------------------------------------------------------ selection */
+
+/* The k-th smallest element of x[0..n) (1-based k), with its counts.
+ * x: device pointer to n elements of `dtype` (any alignment of the element type).
+ * out_dev: device pointer to one cps_result.
+ * Errors: CPS_EINVAL for a null pointer, n < 1, k outside [1, n] or a bad dtype. */
+int select_kth(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
+               cps_result *out_dev, void *stream);
+
+/* select_kth with options (may be NULL) and an optional device-side trace (may be NULL). */
+int select_kth_ex(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
+                  const cps_options *opt, cps_result *out_dev, cps_stats *stats_dev,
+                  void *stream);
+
+/* f, A, B, counts, neighbours and subgradient end points at each of ny points ys_dev
+ * (device doubles), for the rank-k objective of x[0..n) (Section 3, Eq. 2).  This is the
+ * evaluation each cutting-plane pass performs; it is exported for checking.
+ * out_dev: device pointer to ny cps_eval records. */
+int cps_objective(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
+                  const double *ys_dev, int64_t ny, cps_eval *out_dev, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPSELECT_H */

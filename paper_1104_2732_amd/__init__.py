@@ -1,0 +1,211 @@
+"""Exact k-th order statistic selection on MI355X by Kelley's cutting plane.
+
+A thin ctypes binding of ``libcpselect.so`` (built from ``csrc/`` by
+``build.py``).  The binding only marshals arguments: every step of the method
+runs in the library's HIP kernels.  PyTorch supplies device memory (tensors)
+and the current HIP stream.  There is no fallback: if the library is not
+built, importing the binding's entry points raises.
+
+Entry points (same names as the C ABI in ``include/cpselect.h``):
+
+- ``Selector.select_kth(x, k)``: the k-th smallest element of a float32 or
+  float64 CUDA tensor (1-based k) with its counts.
+- ``Selector.objective(x, k, ys)``: the cutting plane's objective, its parts,
+  counts and subgradient end points at given trial points.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcpselect.so")
+
+CPS_F32, CPS_F64 = 0, 1
+CPS_OK = 0
+STATUS_OK, STATUS_NAN, STATUS_TIMEOUT, STATUS_INTERNAL = 0, 1, 2, 3
+STATS_MAX_PASSES = 96
+
+RESULT_DTYPE = np.dtype([("value_bits", "<u8"), ("value", "<f8"), ("less", "<i8"),
+                         ("equal", "<i8"), ("greater", "<i8"), ("passes", "<i4"),
+                         ("status", "<i4")])
+EVAL_DTYPE = np.dtype([("f", "<f8"), ("A", "<f8"), ("B", "<f8"), ("L", "<i8"), ("E", "<i8"),
+                       ("G", "<i8"), ("pred", "<f8"), ("succ", "<f8"), ("gminus", "<f8"),
+                       ("gplus", "<f8")])
+STATS_DTYPE = np.dtype([("passes", "<i4"), ("work_passes", "<i4"), ("kelley_steps", "<i4"),
+                        ("bisect_steps", "<i4"), ("final_select_size", "<i4"),
+                        ("bracket_used", "<i4"), ("elements_read", "<i8"),
+                        ("elements_written", "<i8"),
+                        ("population", "<i8", (STATS_MAX_PASSES,)),
+                        ("working", "<i8", (STATS_MAX_PASSES,))])
+assert RESULT_DTYPE.itemsize == 48 and EVAL_DTYPE.itemsize == 80
+
+
+class Options(ctypes.Structure):
+    """Mirror of cps_options (see include/cpselect.h)."""
+    _fields_ = [("maxit", ctypes.c_int32), ("final_threshold", ctypes.c_int32),
+                ("partition_fraction", ctypes.c_double), ("grid_blocks", ctypes.c_int32),
+                ("block_threads", ctypes.c_int32), ("spin_limit", ctypes.c_int64),
+                ("use_bracket", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("bracket_lo", ctypes.c_double), ("bracket_hi", ctypes.c_double)]
+
+
+class CpsError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        msg = lib().cps_status_string(code).decode() if _lib is not None else str(code)
+        extra = ""
+        if _lib is not None and code == -3:
+            extra = f" (hip error {_lib.cps_last_hip_error()})"
+        super().__init__(f"{what}: {msg}{extra} [{code}]")
+        self.code = code
+
+
+_lib = None
+
+EXPORTS = ("cps_create", "cps_destroy", "cps_status_string", "cps_last_hip_error",
+           "cps_default_options", "cps_reserve", "select_kth", "select_kth_ex", "cps_objective")
+
+
+def lib() -> ctypes.CDLL:
+    """Load libcpselect.so; raises ImportError when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, c_int = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int
+    L.cps_create.argtypes = [c_int, ctypes.POINTER(vp)]
+    L.cps_create.restype = c_int
+    L.cps_destroy.argtypes = [vp]
+    L.cps_destroy.restype = c_int
+    L.cps_status_string.argtypes = [c_int]
+    L.cps_status_string.restype = ctypes.c_char_p
+    L.cps_last_hip_error.argtypes = []
+    L.cps_last_hip_error.restype = c_int
+    L.cps_default_options.argtypes = [ctypes.POINTER(Options)]
+    L.cps_default_options.restype = None
+    L.cps_reserve.argtypes = [vp, i64, c_int]
+    L.cps_reserve.restype = c_int
+    L.select_kth.argtypes = [vp, vp, i64, i64, c_int, vp, vp]
+    L.select_kth.restype = c_int
+    L.select_kth_ex.argtypes = [vp, vp, i64, i64, c_int, ctypes.POINTER(Options), vp, vp, vp]
+    L.select_kth_ex.restype = c_int
+    L.cps_objective.argtypes = [vp, vp, i64, i64, c_int, vp, i64, vp, vp]
+    L.cps_objective.restype = c_int
+    _lib = L
+    return L
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    lib().cps_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float32:
+        return CPS_F32
+    if t.dtype == torch.float64:
+        return CPS_F64
+    raise TypeError(f"unsupported dtype {t.dtype}; expected float32 or float64")
+
+
+def _stream_ptr(device) -> int:
+    import torch
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != CPS_OK:
+        raise CpsError(rc, what)
+
+
+def _as_records(buf, dtype: np.dtype) -> np.ndarray:
+    return buf.cpu().numpy().view(dtype)
+
+
+class Selector:
+    """A library handle bound to one GPU (owns the workspace)."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.device = torch.device("cuda", device)
+        self._h = ctypes.c_void_p()
+        _check(lib().cps_create(device, ctypes.byref(self._h)), "cps_create")
+
+    def close(self) -> None:
+        if self._h:
+            import torch
+            torch.cuda.synchronize(self.device)
+            lib().cps_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            if self._h and _lib is not None:
+                _lib.cps_destroy(self._h)
+        except Exception:
+            pass
+
+    # -- raw, asynchronous entry points (no host synchronisation) --------------------
+
+    def new_results(self, count: int = 1):
+        import torch
+        return torch.empty(count * RESULT_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
+
+    def new_stats(self):
+        import torch
+        return torch.zeros(STATS_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
+
+    def select_kth_async(self, x, k: int, out, stats=None, options: Options | None = None) -> None:
+        """Enqueue select_kth_ex on the current stream; results land in `out` (device bytes)."""
+        if not x.is_cuda or not x.is_contiguous():
+            raise ValueError("x must be a contiguous CUDA tensor")
+        code = _dtype_code(x)
+        rc = lib().select_kth_ex(self._h, ctypes.c_void_p(x.data_ptr()), x.numel(), int(k), code,
+                                 ctypes.byref(options) if options is not None else None,
+                                 ctypes.c_void_p(out.data_ptr()),
+                                 ctypes.c_void_p(stats.data_ptr()) if stats is not None else None,
+                                 ctypes.c_void_p(_stream_ptr(self.device)))
+        _check(rc, "select_kth_ex")
+
+    def reserve(self, n: int, dtype_code: int) -> None:
+        _check(lib().cps_reserve(self._h, int(n), int(dtype_code)), "cps_reserve")
+
+    # -- convenience (synchronising) wrappers ------------------------------------------
+
+    def select_kth(self, x, k: int, options: Options | None = None, stats: bool = False):
+        """Synchronous select_kth: returns a dict (and the stats record when asked)."""
+        import torch
+        out = self.new_results(1)
+        st = self.new_stats() if stats else None
+        self.select_kth_async(x, k, out, st, options)
+        torch.cuda.synchronize(self.device)
+        r = _as_records(out, RESULT_DTYPE)[0]
+        res = {name: r[name].item() for name in RESULT_DTYPE.names}
+        if stats:
+            return res, _as_records(st, STATS_DTYPE)[0]
+        return res
+
+    def objective(self, x, k: int, ys) -> np.ndarray:
+        """cps_objective at every y in `ys` (array-like of float64); returns EVAL_DTYPE records."""
+        import torch
+        if not x.is_cuda or not x.is_contiguous():
+            raise ValueError("x must be a contiguous CUDA tensor")
+        ys_t = torch.as_tensor(np.ascontiguousarray(ys, dtype=np.float64), device=self.device)
+        out = torch.empty(ys_t.numel() * EVAL_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
+        rc = lib().cps_objective(self._h, ctypes.c_void_p(x.data_ptr()), x.numel(), int(k),
+                                 _dtype_code(x), ctypes.c_void_p(ys_t.data_ptr()), ys_t.numel(),
+                                 ctypes.c_void_p(out.data_ptr()),
+                                 ctypes.c_void_p(_stream_ptr(self.device)))
+        _check(rc, "cps_objective")
+        torch.cuda.synchronize(self.device)
+        return _as_records(out, EVAL_DTYPE).copy()

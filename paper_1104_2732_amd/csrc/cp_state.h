@@ -1,0 +1,394 @@
+// Cutting-plane state machine for exact k-th element selection.
+//
+// One instance describes one selection in flight.  It is advanced once per
+// reduction pass by a single thread (the last workgroup to finish the pass on
+// the GPU; a plain host loop in the CPU unit tests), so everything here is
+// scalar code usable from host and device.
+//
+// Notation (Section 3, Eq. 2, with the orientation whose minimiser is the k-th
+// smallest): alpha = k - 1/2, beta = n - k + 1/2,
+//   A(y) = sum_{x_i > y} (x_i - y),  B(y) = sum_{x_i < y} (y - x_i),
+//   f(y) = alpha A(y) + beta B(y),
+//   L = #(x < y), E = #(x = y),  subdifferential [n (L - k + 1/2), n (L + E - k + 1/2)].
+//
+// Bracket (Section 4, Algorithm 1): x_(k) lies strictly inside (yL, yR) and
+//   cL = #(x <= yL) < k <= cR = #(x < yR).
+// The cut at yL uses the right derivative gL = n (cL - k + 1/2) < 0 and the cut at
+// yR the left derivative gR = n (cR - k + 1/2) > 0; both are subgradients, so the
+// two supporting lines meet strictly inside and the update of Algorithm 1 step 1.1
+// never divides by zero.  Decisions are made on the integer counts (step 1.4 with
+// the set-valued subgradient): L < k <= L + E means the trial point is x_(k).
+//
+// Working set.  Pass 0 and the first evaluation passes read the whole input.  Once
+// the bracket holds few enough elements, a pass also writes the bracket's elements
+// below and above the trial point to the two ends of a workspace buffer (the
+// count-and-compact of Section 4, done as part of the evaluation pass), and the next
+// pass reads only the side that still holds x_(k).  Reading only the bracket's
+// elements changes f by a positive factor and an affine term on the bracket, so the
+// cutting-plane trial points are unchanged: A and B of the full array are rebuilt
+// from the bracket-only sums as
+//   A(t) = A_W(t) + A(yR) + (n - cR)(yR - t),   B(t) = B_W(t) + B(yL) + cL (t - yL),
+// where every term is non-negative.
+//
+// Termination: an exact hit; one distinct value left inside the bracket (the smallest
+// element above yL equals the largest below yR, the exact step at the end of
+// Section 4); or few enough elements left for a one-workgroup exact radix select.
+// After `maxit` cutting-plane steps the trial point becomes the midpoint of the
+// bracket in the ordered bit pattern of T, which bounds the number of passes.
+#pragma once
+
+#include <stdint.h>
+
+#ifdef __HIPCC__
+#define CPS_HD __host__ __device__
+#else
+#define CPS_HD
+#endif
+
+namespace cps {
+
+enum Phase : int32_t { PH_PASS0 = 0, PH_EVAL = 1, PH_FINAL = 2, PH_DONE = 3 };
+
+// status values mirror enum cps_status in cpselect.h
+enum : int32_t { ST_OK = 0, ST_NAN = 1, ST_TIMEOUT = 2, ST_INTERNAL = 3 };
+
+struct CpConfig {
+  int32_t maxit;
+  int32_t dtype;            // 0 = f32, 1 = f64
+  int64_t final_threshold;  // bracket population handled by one workgroup
+  int64_t final_direct_max; // largest unsplit input one workgroup may scan directly
+  double theta;             // start splitting once population <= theta * n (0 = never)
+  int64_t zcap;             // capacity of each split buffer (elements)
+  int32_t use_bracket;
+  int32_t pad0;
+  double bracket_lo, bracket_hi;
+};
+
+// Results of pass 0 over the whole input (Section 4, step 0: min, max and sum in
+// one reduction; here with the multiplicity of min and max, the sum over finite
+// values and the counts of NaN and infinities).
+struct Pass0Result {
+  double sum;           // sum of finite elements
+  double fmin, fmax;    // min and max over finite elements (+inf / -inf if none)
+  int64_t cmin, cmax;   // multiplicities of fmin and fmax
+  int64_t nnan, nneg, npos;  // counts of NaN, -inf, +inf
+  // two-point check of a proposed bracket (a, b): #(x <= a), #(x < b) and the
+  // finite-element parts of A and B at a and at b
+  int64_t c_le_a, c_lt_b;
+  double A_a, B_a, A_b, B_b;
+};
+
+// Results of one evaluation pass over the working set W at trial point t.
+struct EvalResult {
+  double A, B;          // sums over W of (w - t) for w > t and (t - w) for w < t
+  int64_t L, G;         // #(w < t), #(w > t) within W
+  double pred, succ;    // largest w < t, smallest w > t in W (-inf / +inf if none)
+  int64_t written;      // elements the pass wrote to the split buffer
+};
+
+struct CpState {
+  int64_t n, k;
+  int32_t phase, status;
+  double yL, yR;
+  double AL, BL, AR, BR;   // A and B of the full array at yL and yR
+  int64_t cL, cR;
+  double lo, hi;           // a value of T inside (yL, yR) known to be <= / >= every element there
+  int32_t lo_data, hi_data;// lo / hi are actual elements of x
+  double t;                // trial point of the pass about to run
+  int32_t split;           // the pass about to run writes (yL,t) and (t,yR) to buffer zout
+  int32_t filter;          // that pass reads x, so the split keeps only elements inside (yL,yR)
+  int32_t on_bracket;      // the working set is exactly the elements inside (yL, yR)
+  int32_t has_inf;         // evaluate with values clamped into [fmin, fmax]
+  double fmin, fmax;
+  int32_t wbuf;            // -1: the input; 0/1: split buffer holding the working set
+  int32_t zout;            // buffer the next split writes
+  int64_t woff, wlen;      // working set = buffer[woff, woff + wlen)
+  int32_t passes;          // full reads of the input
+  int32_t work_passes;     // all passes
+  int32_t kelley, bisect;
+  int64_t elements_read, elements_written;
+  double value;            // result (as T widened to double)
+  int64_t less, equal;
+  int64_t final_size;
+  int32_t bracket_used, pad1;
+};
+
+static_assert(sizeof(CpState) % 8 == 0, "state is copied in 8-byte words");
+
+// ---------------------------------------------------------------- T helpers
+
+CPS_HD inline uint32_t f32_bits(float v) { return __builtin_bit_cast(uint32_t, v); }
+CPS_HD inline uint64_t f64_bits(double v) { return __builtin_bit_cast(uint64_t, v); }
+CPS_HD inline float f32_from(uint32_t b) { return __builtin_bit_cast(float, b); }
+CPS_HD inline double f64_from(uint64_t b) { return __builtin_bit_cast(double, b); }
+
+// Monotone map from T (no NaN) to unsigned integers: a < b  <=>  key(a) < key(b),
+// with -0.0 mapped like +0.0.
+CPS_HD inline uint32_t key32(float v) {
+  uint32_t b = f32_bits(v + 0.0f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+CPS_HD inline float unkey32(uint32_t k) {
+  uint32_t b = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+  return f32_from(b);
+}
+CPS_HD inline uint64_t key64(double v) {
+  uint64_t b = f64_bits(v + 0.0);
+  return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+}
+CPS_HD inline double unkey64(uint64_t k) {
+  uint64_t b = (k & 0x8000000000000000ull) ? (k & 0x7fffffffffffffffull) : ~k;
+  return f64_from(b);
+}
+
+// Round a double to the nearest value of T (dtype 0: float), returned widened.
+CPS_HD inline double to_T(double v, int32_t dtype) { return dtype == 0 ? (double)(float)v : v; }
+
+// The next representable value of T above / below v (v finite).  The ordered bit
+// patterns hold both zeros; a step that lands on the other zero steps once more.
+CPS_HD inline double next_up(double v, int32_t dtype) {
+  if (dtype == 0) {
+    double r = (double)unkey32(key32((float)v) + 1u);
+    return r == v ? (double)unkey32(key32((float)v) + 2u) : r;
+  }
+  double r = unkey64(key64(v) + 1ull);
+  return r == v ? unkey64(key64(v) + 2ull) : r;
+}
+CPS_HD inline double next_down(double v, int32_t dtype) {
+  if (dtype == 0) {
+    double r = (double)unkey32(key32((float)v) - 1u);
+    return r == v ? (double)unkey32(key32((float)v) - 2u) : r;
+  }
+  double r = unkey64(key64(v) - 1ull);
+  return r == v ? unkey64(key64(v) - 2ull) : r;
+}
+
+// Midpoint of [a, b] in the ordered bit pattern of T.
+CPS_HD inline double key_mid(double a, double b, int32_t dtype) {
+  if (dtype == 0) {
+    uint32_t ka = key32((float)a), kb = key32((float)b);
+    return (double)unkey32(ka + (kb - ka) / 2u);
+  }
+  uint64_t ka = key64(a), kb = key64(b);
+  return unkey64(ka + (kb - ka) / 2ull);
+}
+
+CPS_HD inline bool inside(double t, double a, double b) { return t > a && t < b; }
+
+// ---------------------------------------------------------------- transitions
+
+CPS_HD inline void cp_finish(CpState &s, double value, int64_t less, int64_t equal) {
+  s.value = value;
+  s.less = less;
+  s.equal = equal;
+  s.phase = PH_DONE;
+}
+
+// Choose the next trial point inside (yL, yR): the intersection of the supporting
+// lines at the bracket ends (Algorithm 1, step 1.1), safeguarded, rounded to T and
+// clamped to [lo, hi]; or the bit-pattern midpoint once maxit steps are spent.
+CPS_HD inline double cp_trial_point(CpState &s, const CpConfig &c) {
+  const double n = (double)s.n, k = (double)s.k;
+  const double alpha = k - 0.5, beta = n - k + 0.5;
+  double t = 0.0;
+  bool ok = false;
+  if (s.kelley < c.maxit) {
+    const double gL = n * ((double)s.cL - k + 0.5);
+    const double gR = n * ((double)s.cR - k + 0.5);
+    const double fL = alpha * s.AL + beta * s.BL;
+    const double fR = alpha * s.AR + beta * s.BR;
+    const double D = s.yR - s.yL;
+    t = s.yL + (fR - fL - gR * D) / (gL - gR);
+    ok = inside(t, s.yL, s.yR);
+    if (!ok) {
+      t = 0.5 * s.yL + 0.5 * s.yR;
+      ok = inside(t, s.yL, s.yR);
+    }
+    s.kelley++;
+  } else {
+    s.bisect++;
+  }
+  if (!ok) t = key_mid(s.lo, s.hi, c.dtype);
+  t = to_T(t, c.dtype);
+  if (t < s.lo) t = s.lo;
+  if (t > s.hi) t = s.hi;
+  return t;
+}
+
+// Decide what the next pass does, given the current bracket.
+CPS_HD inline void cp_plan(CpState &s, const CpConfig &c) {
+  const int64_t pop = s.cR - s.cL;
+  if (pop < 1) {  // the bracket always holds x_(k); anything else is a bug
+    s.status = ST_INTERNAL;
+    cp_finish(s, 0.0, 0, 0);
+    return;
+  }
+  if (s.lo_data && s.hi_data && s.lo == s.hi) {
+    // one distinct value strictly inside the bracket: it is x_(k)
+    cp_finish(s, s.lo, s.cL, pop);
+    return;
+  }
+  s.split = 0;
+  s.filter = 0;
+  if (pop <= c.final_threshold) {
+    if (s.on_bracket || s.wlen <= c.final_direct_max) {
+      s.phase = PH_FINAL;
+      s.final_size = s.wlen;
+      return;
+    }
+    // Compaction only: a split at t = yR sends every element of (yL, yR) to the low side.
+    s.phase = PH_EVAL;
+    s.split = 1;
+    s.filter = 1;
+    s.zout = 0;
+    s.t = s.yR;
+    return;
+  }
+  if (s.on_bracket) {
+    s.split = 1;
+    s.zout = 1 - s.wbuf;
+  } else if (c.theta > 0.0 && (double)pop <= c.theta * (double)s.n && pop <= c.zcap) {
+    s.split = 1;
+    s.filter = 1;
+    s.zout = 0;
+  }
+  s.phase = PH_EVAL;
+  s.t = cp_trial_point(s, c);
+}
+
+// After pass 0 (Section 4, step 0).  Returns with phase DONE when the answer is an
+// extreme value (or NaN is present), else with the first trial point planned.
+CPS_HD inline void cp_after_pass0(CpState &s, const Pass0Result &r, const CpConfig &c) {
+  const int64_t n = s.n, k = s.k;
+  s.passes = 1;
+  s.work_passes = 1;
+  s.elements_read = n;
+  s.elements_written = 0;
+  s.kelley = s.bisect = 0;
+  s.status = ST_OK;
+  s.bracket_used = 0;
+  s.final_size = 0;
+  if (r.nnan > 0) {
+    s.status = ST_NAN;
+    cp_finish(s, __builtin_nan(""), 0, 0);
+    return;
+  }
+  const int64_t nf = n - r.nneg - r.npos;
+  if (k <= r.nneg) { cp_finish(s, -__builtin_inf(), 0, r.nneg); return; }
+  if (k > n - r.npos) { cp_finish(s, __builtin_inf(), n - r.npos, r.npos); return; }
+  if (k <= r.nneg + r.cmin) { cp_finish(s, r.fmin, r.nneg, r.cmin); return; }
+  if (k > n - r.npos - r.cmax) { cp_finish(s, r.fmax, n - r.npos - r.cmax, r.cmax); return; }
+  // x_(k) lies strictly between the finite extremes.
+  s.fmin = r.fmin;
+  s.fmax = r.fmax;
+  s.has_inf = (r.nneg + r.npos) > 0;
+  const double span = r.fmax - r.fmin;
+  s.yL = r.fmin;
+  s.yR = r.fmax;
+  s.cL = r.nneg + r.cmin;
+  s.cR = n - r.npos - r.cmax;
+  // f at the extremes in closed form from the sum (Section 4, step 0); infinities are
+  // evaluated as if clamped to the finite extremes, which leaves f' unchanged inside.
+  double al = (r.sum - (double)nf * r.fmin) + (double)r.npos * span;
+  double br = ((double)nf * r.fmax - r.sum) + (double)r.nneg * span;
+  s.AL = al > 0.0 ? al : 0.0;
+  s.BL = 0.0;
+  s.AR = 0.0;
+  s.BR = br > 0.0 ? br : 0.0;
+  s.lo = next_up(s.yL, c.dtype);
+  s.hi = next_down(s.yR, c.dtype);
+  s.lo_data = s.hi_data = 0;
+  s.wbuf = -1;
+  s.woff = 0;
+  s.wlen = n;
+  s.on_bracket = 0;
+  // A proposed bracket (a, b) replaces an end only when the counts prove it holds
+  // x_(k): #(x <= a) < k <= #(x < b).  f at the new ends comes from the two-point
+  // sums of the same pass (infinities again evaluated as the finite extremes).
+  if (c.use_bracket) {
+    const double a = to_T(c.bracket_lo, c.dtype), b = to_T(c.bracket_hi, c.dtype);
+    if (a < b && r.c_le_a < k && k <= r.c_lt_b) {
+      s.bracket_used = 1;
+      if (a > s.yL) {
+        s.yL = a;
+        s.cL = r.c_le_a;
+        s.lo = next_up(a, c.dtype);
+        s.lo_data = 0;
+        s.AL = r.A_a + (double)r.npos * (r.fmax - a);
+        s.BL = r.B_a + (double)r.nneg * (a - r.fmin);
+      }
+      if (b < s.yR) {
+        s.yR = b;
+        s.cR = r.c_lt_b;
+        s.hi = next_down(b, c.dtype);
+        s.hi_data = 0;
+        s.AR = r.A_b + (double)r.npos * (r.fmax - b);
+        s.BR = r.B_b + (double)r.nneg * (b - r.fmin);
+      }
+    }
+  }
+  cp_plan(s, c);
+}
+
+// After an evaluation pass at s.t over the working set.
+CPS_HD inline void cp_after_eval(CpState &s, const EvalResult &r, const CpConfig &c) {
+  const int64_t n = s.n, k = s.k;
+  const double t = s.t;
+  s.work_passes++;
+  if (s.wbuf < 0) s.passes++;
+  s.elements_read += s.wlen;
+  s.elements_written += r.written;
+  int64_t L = r.L, G = r.G;
+  double A = r.A, B = r.B;
+  if (s.on_bracket) {
+    L += s.cL;
+    G += n - s.cR;
+    A += s.AR + (double)(n - s.cR) * (s.yR - t);
+    B += s.BL + (double)s.cL * (t - s.yL);
+  }
+  const int64_t E = n - L - G;
+  const bool did_split = s.split != 0;
+  const int32_t zout = s.zout;
+  s.split = 0;
+  if (L < k && k <= L + E) {
+    cp_finish(s, t, L, E);
+    return;
+  }
+  if (L + E < k) {  // x_(k) > t: move the left end (Algorithm 1, step 1.4)
+    const int64_t nright = s.cR - (L + E);
+    s.yL = t;
+    s.AL = A;
+    s.BL = B;
+    s.cL = L + E;
+    s.lo = r.succ;
+    s.lo_data = 1;
+    if (did_split) {
+      s.wbuf = zout;
+      s.woff = c.zcap - nright;
+      s.wlen = nright;
+      s.on_bracket = 1;
+    }
+  } else {  // x_(k) < t: move the right end
+    const int64_t nleft = L - s.cL;
+    s.yR = t;
+    s.AR = A;
+    s.BR = B;
+    s.cR = L;
+    s.hi = r.pred;
+    s.hi_data = 1;
+    if (did_split) {
+      s.wbuf = zout;
+      s.woff = 0;
+      s.wlen = nleft;
+      s.on_bracket = 1;
+    }
+  }
+  if (s.work_passes >= 4 * 96) {  // cannot happen with the bisection bound; guard anyway
+    s.status = ST_INTERNAL;
+    cp_finish(s, 0.0, 0, 0);
+    return;
+  }
+  cp_plan(s, c);
+}
+
+}  // namespace cps

@@ -1,0 +1,162 @@
+// Device-side building blocks shared by the selection kernels: element traits,
+// wave64 reductions, agent-scope synchronisation and the one-workgroup radix select.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cp_state.h"
+
+namespace cps {
+
+constexpr int kWave = 64;
+
+template <typename T> struct Traits;
+template <> struct Traits<float> {
+  using Vec = float4;   // 16-byte loads
+  using Key = uint32_t;
+  static constexpr int kVec = 4;
+  static constexpr int kDigits = 4;   // 8-bit radix digits in the key
+  __device__ static Key key(float v) { return key32(v); }
+  __device__ static float unkey(Key k) { return unkey32(k); }
+};
+template <> struct Traits<double> {
+  using Vec = double2;
+  using Key = uint64_t;
+  static constexpr int kVec = 2;
+  static constexpr int kDigits = 8;
+  __device__ static Key key(double v) { return key64(v); }
+  __device__ static double unkey(Key k) { return unkey64(k); }
+};
+
+template <typename T> __device__ inline void vec_to_arr(const typename Traits<T>::Vec &v, T *e);
+template <> __device__ inline void vec_to_arr<float>(const float4 &v, float *e) {
+  e[0] = v.x; e[1] = v.y; e[2] = v.z; e[3] = v.w;
+}
+template <> __device__ inline void vec_to_arr<double>(const double2 &v, double *e) {
+  e[0] = v.x; e[1] = v.y;
+}
+
+// ------------------------------------------------------------------ wave helpers
+
+__device__ inline uint64_t ballot(bool p) { return __ballot(p); }
+__device__ inline uint32_t popc(uint64_t m) { return (uint32_t)__popcll(m); }
+// number of set bits of m in lanes below this lane
+__device__ inline uint32_t lane_rank(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ inline double wave_min(double v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ inline int64_t wave_sum_i64(int64_t v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// ------------------------------------------------------------------ agent-scope sync
+// The eight XCDs have separate L2 caches; agent-scope release/acquire makes the
+// compiler write back / invalidate them around the synchronising operation.
+
+__device__ inline uint32_t atomic_add_acq_rel(uint32_t *p, uint32_t v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint64_t atomic_add_relaxed(uint64_t *p, uint64_t v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint32_t load_acquire(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint32_t load_relaxed(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void store_release(uint32_t *p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void store_relaxed(uint32_t *p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+__device__ inline void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+
+// ------------------------------------------------------------------ radix select
+// Exact select of the element of rank r (1-based) among the elements w of W[0..m)
+// with lo_ex < w < hi_ex (when `filter`), by most-significant-digit radix select on
+// the ordered keys: one histogram of 256 bins per 8-bit digit, kept in LDS.  Run by
+// one whole workgroup of BLOCK threads.  Returns the key of the selected element,
+// the number of candidates strictly below it and its multiplicity.
+template <typename T, int BLOCK>
+__device__ void block_radix_select(const T *__restrict__ W, int64_t m, bool filter, T lo_ex,
+                                   T hi_ex, int64_t r, uint32_t *hist /* 256 in LDS */,
+                                   int64_t *s_misc /* 4 in LDS */,
+                                   typename Traits<T>::Key &key_out, int64_t &below_out,
+                                   int64_t &equal_out) {
+  using Key = typename Traits<T>::Key;
+  const int tid = threadIdx.x;
+  Key prefix = 0, mask = 0;
+  int64_t below = 0, rr = r, eq = 0;
+  for (int d = Traits<T>::kDigits - 1; d >= 0; --d) {
+    const int shift = 8 * d;
+    for (int b = tid; b < 256; b += BLOCK) hist[b] = 0;
+    __syncthreads();
+    for (int64_t i = tid; i < m; i += BLOCK) {
+      const T v = W[i];
+      const bool in = !filter || (v > lo_ex && v < hi_ex);
+      const Key kk = Traits<T>::key(v);
+      if (in && (kk & mask) == prefix) atomicAdd(&hist[(uint32_t)(kk >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (tid < kWave) {
+      // lane l owns bins 4l .. 4l+3
+      uint32_t c0 = hist[4 * tid], c1 = hist[4 * tid + 1], c2 = hist[4 * tid + 2],
+               c3 = hist[4 * tid + 3];
+      int64_t own = (int64_t)c0 + c1 + c2 + c3;
+      int64_t incl = own;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        int64_t up = __shfl_up(incl, o);
+        if (tid >= o) incl += up;
+      }
+      const int64_t excl = incl - own;
+      if (excl < rr && rr <= incl) {
+        int64_t acc = excl;
+        int bin = 4 * tid;
+        uint32_t cs[4] = {c0, c1, c2, c3};
+        for (int j = 0; j < 4; ++j) {
+          if (rr <= acc + cs[j]) { bin = 4 * tid + j; break; }
+          acc += cs[j];
+        }
+        s_misc[0] = bin;
+        s_misc[1] = acc;
+        s_misc[2] = hist[bin];
+      }
+    }
+    __syncthreads();
+    const int bin = (int)s_misc[0];
+    const int64_t acc = s_misc[1];
+    eq = s_misc[2];
+    below += acc;
+    rr -= acc;
+    prefix |= (Key)bin << shift;
+    mask |= (Key)255 << shift;
+    __syncthreads();
+  }
+  key_out = prefix;
+  below_out = below;
+  equal_out = eq;
+}
+
+}  // namespace cps

@@ -1,0 +1,138 @@
+// Host-side driver of the cutting-plane state machine (paper_1104_2732_amd/csrc/cp_state.h).
+//
+// Test infrastructure: it runs the same sequence of passes the GPU kernel runs (pass 0,
+// evaluation passes with the optional split of the bracket into a buffer, final exact
+// select) with plain loops, so that every branch of the state machine can be exercised
+// on the CPU.  The final exact select here sorts the remaining candidates.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "../../paper_1104_2732_amd/csrc/cp_state.h"
+
+using namespace cps;
+
+struct SimResult {
+  double value;
+  int64_t less, equal;
+  int32_t status, passes, work_passes, kelley, bisect, bracket_used;
+  int64_t elements_read, elements_written;
+};
+
+template <typename T>
+static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_threshold,
+               double theta, int use_bracket, double blo, double bhi, SimResult *out) {
+  CpConfig c{};
+  c.maxit = maxit;
+  c.dtype = sizeof(T) == 4 ? 0 : 1;
+  c.final_threshold = final_threshold;
+  c.final_direct_max = 4 * final_threshold;
+  c.theta = theta;
+  int64_t zcap = final_threshold;
+  if (theta > 0) zcap = std::max<int64_t>(zcap, (int64_t)(theta * (double)n) + 1);
+  c.zcap = zcap;
+  c.use_bracket = use_bracket;
+  c.bracket_lo = blo;
+  c.bracket_hi = bhi;
+  std::vector<T> z[2] = {std::vector<T>(zcap), std::vector<T>(zcap)};
+
+  // pass 0
+  Pass0Result r{};
+  r.fmin = INFINITY;
+  r.fmax = -INFINITY;
+  const T ba = (T)blo, bb = (T)bhi;
+  for (int64_t i = 0; i < n; i++) {
+    const T v = x[i];
+    if (std::isnan(v)) { r.nnan++; continue; }
+    if (v == (T)-INFINITY) r.nneg++;
+    else if (v == (T)INFINITY) r.npos++;
+    else {
+      if (v < r.fmin) { r.fmin = v; r.cmin = 1; } else if (v == r.fmin) r.cmin++;
+      if (v > r.fmax) { r.fmax = v; r.cmax = 1; } else if (v == r.fmax) r.cmax++;
+      r.sum += v;
+      if (use_bracket) {
+        if (v > ba) r.A_a += (double)(v - ba);
+        if (v < ba) r.B_a += (double)(ba - v);
+        if (v > bb) r.A_b += (double)(v - bb);
+        if (v < bb) r.B_b += (double)(bb - v);
+      }
+    }
+    if (use_bracket) {
+      if (v <= ba) r.c_le_a++;
+      if (v < bb) r.c_lt_b++;
+    }
+  }
+  CpState s{};
+  s.n = n;
+  s.k = k;
+  cp_after_pass0(s, r, c);
+  while (s.phase == PH_EVAL) {
+    const T *W = s.wbuf < 0 ? x : z[s.wbuf].data() + s.woff;
+    const T t = (T)s.t, yL = (T)s.yL, yR = (T)s.yR;
+    const bool clamp = s.has_inf && s.wbuf < 0;
+    EvalResult e{};
+    e.pred = -INFINITY;
+    e.succ = INFINITY;
+    int64_t nl = 0, nr = 0;
+    T *zo = z[s.zout].data();
+    for (int64_t i = 0; i < s.wlen; i++) {
+      T v = W[i];
+      if (clamp) v = std::min(std::max(v, (T)s.fmin), (T)s.fmax);
+      if (v < t) { e.L++; e.B += (double)(t - v); e.pred = std::max<double>(e.pred, v); }
+      if (v > t) { e.G++; e.A += (double)(v - t); e.succ = std::min<double>(e.succ, v); }
+      if (s.split) {
+        const bool inb = !s.filter || (v > yL && v < yR);
+        if (inb && v < t) zo[nl++] = v;
+        if (inb && v > t) zo[zcap - 1 - nr++] = v;
+      }
+    }
+    e.written = nl + nr;
+    if (nl + nr > zcap) return -10;
+    cp_after_eval(s, e, c);
+  }
+  if (s.phase == PH_FINAL) {
+    const T *W = s.wbuf < 0 ? x : z[s.wbuf].data() + s.woff;
+    std::vector<T> cand;
+    for (int64_t i = 0; i < s.wlen; i++) {
+      const T v = W[i];
+      if (s.on_bracket || (v > (T)s.yL && v < (T)s.yR)) cand.push_back(v);
+    }
+    const int64_t rr = s.k - s.cL;
+    if (rr < 1 || rr > (int64_t)cand.size()) return -11;
+    std::sort(cand.begin(), cand.end());
+    const T v = cand[rr - 1];
+    int64_t below = 0, eq = 0;
+    for (T c2 : cand) { if (c2 < v) below++; else if (c2 == v) eq++; }
+    s.work_passes++;
+    s.elements_read += s.wlen;
+    if (s.wbuf < 0) s.passes++;
+    cp_finish(s, (double)v, s.cL + below, eq);
+  }
+  if (s.phase != PH_DONE) return -12;
+  out->value = (double)((T)s.value + (T)0);
+  out->less = s.less;
+  out->equal = s.equal;
+  out->status = s.status;
+  out->passes = s.passes;
+  out->work_passes = s.work_passes;
+  out->kelley = s.kelley;
+  out->bisect = s.bisect;
+  out->bracket_used = s.bracket_used;
+  out->elements_read = s.elements_read;
+  out->elements_written = s.elements_written;
+  return 0;
+}
+
+extern "C" {
+
+int sim_select_f32(const float *x, int64_t n, int64_t k, int maxit, int64_t ft, double theta,
+                   int ub, double blo, double bhi, SimResult *out) {
+  return sim<float>(x, n, k, maxit, ft, theta, ub, blo, bhi, out);
+}
+int sim_select_f64(const double *x, int64_t n, int64_t k, int maxit, int64_t ft, double theta,
+                   int ub, double blo, double bhi, SimResult *out) {
+  return sim<double>(x, n, k, maxit, ft, theta, ub, blo, bhi, out);
+}
+}

@@ -1,0 +1,119 @@
+"""The cutting-plane state machine (csrc/cp_state.h) driven on the CPU.
+
+tests/cpp/cp_state_sim.cpp runs the kernel's sequence of passes with plain
+loops around the same header the GPU uses; its results are compared with the
+oracle bit for bit, for every option that changes the path: final thresholds,
+splitting on/off, bisection only (maxit 0), proposed brackets that hold or miss
+x_(k), infinities, duplicates and outliers (Section 5.3's ~1e9 values).
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import workloads
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+class SimResult(ctypes.Structure):
+    _fields_ = [("value", ctypes.c_double), ("less", ctypes.c_int64), ("equal", ctypes.c_int64),
+                ("status", ctypes.c_int32), ("passes", ctypes.c_int32),
+                ("work_passes", ctypes.c_int32), ("kelley", ctypes.c_int32),
+                ("bisect", ctypes.c_int32), ("bracket_used", ctypes.c_int32),
+                ("elements_read", ctypes.c_int64), ("elements_written", ctypes.c_int64)]
+
+
+@pytest.fixture(scope="module")
+def sim(tmp_path_factory):
+    out = tmp_path_factory.mktemp("sim") / "libcpsim.so"
+    src = os.path.join(HERE, "cpp", "cp_state_sim.cpp")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", str(out), src], check=True)
+    L = ctypes.CDLL(str(out))
+    for name in ("sim_select_f32", "sim_select_f64"):
+        fn = getattr(L, name)
+        fn.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int64,
+                       ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                       ctypes.POINTER(SimResult)]
+        fn.restype = ctypes.c_int
+
+    def run(x, k, maxit=64, final_threshold=64, theta=0.5, bracket=None):
+        r = SimResult()
+        fn = L.sim_select_f32 if x.dtype == np.float32 else L.sim_select_f64
+        ub = 1 if bracket is not None else 0
+        blo, bhi = bracket if bracket is not None else (0.0, 0.0)
+        rc = fn(x.ctypes.data, x.size, k, maxit, final_threshold, theta, ub, blo, bhi, ctypes.byref(r))
+        assert rc == 0, rc
+        return r
+    return run
+
+
+def _check(r, ref, ctx):
+    assert r.status == 0, ctx
+    assert r.value == ref["value"], (ctx, r.value, ref["value"])
+    assert (r.less, r.equal) == (ref["less"], ref["equal"]), ctx
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("dist", ["uniform", "normal", "cauchy", "quantized_normal", "lognormal",
+                                  "mix2", "mix3", "smallint", "outliers", "constant", "permutation"])
+def test_state_machine_matches_oracle(sim, oracle_mod, dist, dtype):
+    for n in (1, 2, 3, 10, 333, 4096, 50_001):
+        x = workloads.single_array(dist, n, dtype, seed=n, tag="sim")
+        for k in sorted({1, 2, n // 100 or 1, n // 3 or 1, (n + 1) // 2, n - 1 or 1, n}):
+            if k > n:
+                continue
+            ref = oracle_mod.select_kth(x, k)
+            for opts in (dict(), dict(final_threshold=1), dict(final_threshold=4, theta=0.0),
+                         dict(maxit=0, final_threshold=8), dict(maxit=2, final_threshold=2, theta=1.0)):
+                _check(sim(x, k, **opts), ref, (dist, n, k, opts))
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_infinities_and_zeros(sim, oracle_mod, dtype):
+    rng = np.random.default_rng(2)
+    base = [np.inf, -np.inf, 0.0, -0.0, 1.0, -1.0, 2.5, np.inf, -np.inf, 3.0, -0.0]
+    for trial in range(40):
+        x = np.array(rng.choice(base, size=int(rng.integers(1, 60))), dtype=dtype)
+        for k in range(1, x.size + 1):
+            ref = oracle_mod.select_kth(x, k)
+            for opts in (dict(final_threshold=1), dict(maxit=0, final_threshold=1)):
+                _check(sim(x, k, **opts), ref, (x, k, opts))
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_proposed_brackets(sim, oracle_mod, dtype):
+    x = workloads.single_array("normal", 100_000, dtype, seed=4)
+    s = np.sort(x)
+    for k in (1, 10, 5000, 50_000, 99_999, 100_000):
+        ref = oracle_mod.select_kth(x, k)
+        v = s[k - 1]
+        for (a, b) in [(v - 0.01, v + 0.01), (v - 1e-7, v + 1e-7), (v, v + 1.0), (v - 1.0, v),
+                       (-10.0, 10.0), (v + 0.5, v + 1.0), (v - 1.0, v - 0.5), (3.0, -3.0)]:
+            r = sim(x, k, final_threshold=16, bracket=(float(a), float(b)))
+            _check(r, ref, (k, a, b))
+            holds = np.sum(x <= np.array(a, dtype)) < k <= np.sum(x < np.array(b, dtype))
+            if not holds:
+                assert r.bracket_used == 0
+
+
+def test_passes_halve_on_smooth_data(sim):
+    # The cutting plane behaves like bisection near x_(k) (end of Section 4): the number of
+    # passes grows like log2(n / final_threshold), far below the bisection safeguard's bound.
+    n = 1 << 20
+    x = workloads.single_array("uniform", n, np.float32, seed=0)
+    r = sim(x, (n + 1) // 2, final_threshold=4096)
+    assert r.work_passes <= 14
+    assert r.passes <= 4  # pass 0, two evaluations of the whole input and the split pass
+    assert r.elements_read <= 6 * n
+
+
+def test_bisection_bound(sim, oracle_mod):
+    # maxit = 0: only bit-pattern bisection; at most 32 halvings of the key range for float32
+    x = workloads.single_array("cauchy", 20_000, np.float32, seed=1)
+    ref = oracle_mod.select_kth(x, 777)
+    r = sim(x, 777, maxit=0, final_threshold=1)
+    _check(r, ref, "bisect")
+    assert r.kelley == 0 and r.bisect <= 34

@@ -1,0 +1,167 @@
+"""GPU parity of select_kth / select_kth_ex against the CPU oracle.
+
+Element by element on the same seeded inputs: the selected value is compared
+bit for bit and its counts exactly (Section 1's definition of x_(k)).  Options
+force every branch of the cutting-plane path: tiny final thresholds (many
+passes and splits), no splitting, bisection only (maxit = 0), one workgroup,
+ragged grids, unaligned starts, duplicates, infinities, signed zeros,
+denormals, NaN.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from tests.gpu_util import assert_same_result, invariant_holds
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sel():
+    import paper_1104_2732_amd as cps
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    s = cps.Selector(0)
+    yield s
+    s.close()
+
+
+def _dev(x: np.ndarray):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def _run(sel, x, k, ctx, **opt):
+    import paper_1104_2732_amd as cps
+    o = cps.default_options(**opt) if opt else None
+    print(f"case {ctx} n={x.size} k={k} dtype={x.dtype} opt={opt}", flush=True)
+    return sel.select_kth(_dev(x), k, options=o)
+
+
+SMALL_DISTS = ["uniform", "normal", "cauchy", "quantized_normal", "lognormal", "mix1", "mix2",
+               "mix3", "mix5", "smallint", "outliers", "beta25", "halfnormal"]
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("dist", SMALL_DISTS)
+def test_parity_default_options(sel, oracle_mod, dist, dtype):
+    for n in (1, 2, 3, 5, 31, 1000, 4099, 70_001, 300_007):
+        x = workloads.single_array(dist, n, dtype, seed=n, tag="gpu-parity")
+        for k in sorted({1, 2, n // 100 or 1, (n + 1) // 2, max(1, n - 1), n}):
+            if k > n:
+                continue
+            res = _run(sel, x, k, f"{dist}")
+            assert_same_result(res, oracle_mod.select_kth(x, k), f"{dist} n={n} k={k}")
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("opt", [
+    dict(final_threshold=16),
+    dict(final_threshold=16, partition_fraction=0.0),
+    dict(final_threshold=1, partition_fraction=1.0),
+    dict(final_threshold=64, maxit=0),
+    dict(final_threshold=64, maxit=1),
+    dict(final_threshold=32, grid_blocks=1),
+    dict(final_threshold=32, grid_blocks=7),
+    dict(final_threshold=100, grid_blocks=3, partition_fraction=0.25),
+])
+def test_parity_forced_paths(sel, oracle_mod, dtype, opt):
+    for dist in ("uniform", "quantized_normal", "cauchy", "mix2", "smallint"):
+        for n in (2, 9, 257, 5003, 131_073):
+            x = workloads.single_array(dist, n, dtype, seed=7 * n + 1, tag="gpu-forced")
+            for k in sorted({1, (n + 1) // 2, max(1, n // 3), n - 1 or 1, n}):
+                res = _run(sel, x, k, dist, **opt)
+                assert_same_result(res, oracle_mod.select_kth(x, k), f"{dist} n={n} k={k} {opt}")
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_unaligned_and_ragged(sel, oracle_mod, dtype):
+    import paper_1104_2732_amd as cps
+    base = workloads.single_array("normal", 100_003, dtype, seed=3)
+    xt = _dev(base)
+    for off in (1, 2, 3):
+        for n in (5, 1021, 99_000):
+            view = xt[off:off + n]
+            assert view.is_contiguous()
+            x = base[off:off + n]
+            for k in (1, (n + 1) // 2, n):
+                print(f"case unaligned off={off} n={n} k={k}", flush=True)
+                res = sel.select_kth(view, k, options=cps.default_options(final_threshold=8))
+                assert_same_result(res, oracle_mod.select_kth(x, k), f"off={off} n={n} k={k}")
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_special_values(sel, oracle_mod, dtype):
+    info = np.finfo(dtype)
+    tiny = info.smallest_subnormal
+    cases = {
+        "signed_zeros": np.array([0.0, -0.0, -0.0, 0.0, 1.0, -1.0, -0.0] * 50, dtype=dtype),
+        "denormals": np.array([tiny, -tiny, 2 * tiny, 0.0, -0.0, 3 * tiny, -2 * tiny] * 40, dtype=dtype),
+        "infinities": np.array([np.inf, -np.inf, 1.0, 2.0, -np.inf, 0.5, np.inf, 3.0, np.inf] * 30,
+                               dtype=dtype),
+        "only_inf": np.array([np.inf, -np.inf, np.inf, -np.inf, -np.inf], dtype=dtype),
+        "huge": np.array([info.max, -info.max, 1.0, info.max, 0.0, -info.max, 2.0] * 20, dtype=dtype),
+        "constant": np.full(10_000, 2.5, dtype=dtype),
+        "two_values": np.array([1.0, 2.0] * 5000, dtype=dtype),
+        "sorted": np.sort(workloads.single_array("normal", 20_000, dtype, seed=1)),
+        "reversed": np.sort(workloads.single_array("normal", 20_000, dtype, seed=1))[::-1].copy(),
+    }
+    rng = np.random.default_rng(0)
+    for name, x in cases.items():
+        x = x.copy()
+        if name not in ("sorted", "reversed"):
+            rng.shuffle(x)
+        n = x.size
+        for k in sorted({1, 2, n // 3 or 1, (n + 1) // 2, n - 1 or 1, n}):
+            for opt in ({}, {"final_threshold": 2}):
+                res = _run(sel, x, k, name, **opt)
+                assert_same_result(res, oracle_mod.select_kth(x, k), f"{name} k={k} {opt}")
+
+
+def test_nan_status(sel):
+    import paper_1104_2732_amd as cps
+    x = np.array([1.0, np.nan, 3.0, 4.0], dtype=np.float32)
+    res = _run(sel, x, 2, "nan")
+    assert res["status"] == cps.STATUS_NAN
+
+
+def test_argument_errors(sel):
+    import paper_1104_2732_amd as cps
+    x = _dev(np.arange(10, dtype=np.float32))
+    for k in (0, 11, -5):
+        with pytest.raises(cps.CpsError):
+            sel.select_kth(x, k)
+    with pytest.raises(cps.CpsError):
+        sel.select_kth(x, 1, options=cps.default_options(final_threshold=0))
+    with pytest.raises(TypeError):
+        sel.select_kth(_dev(np.arange(10, dtype=np.int32)), 1)
+
+
+def test_permutation_invariance(sel):
+    x = workloads.single_array("mix4", 200_000, np.float32, seed=5)
+    ref = None
+    for y in (x, np.sort(x), np.sort(x)[::-1].copy()):
+        r = _run(sel, y, 123_456, "perm")
+        v = (r["value_bits"], r["less"], r["equal"])
+        ref = ref or v
+        assert v == ref
+
+
+def test_stats_and_invariants(sel):
+    import paper_1104_2732_amd as cps
+    n = 1 << 20
+    x = workloads.single_array("uniform", n, np.float32, seed=0)
+    k = (n + 1) // 2
+    print("case stats uniform 2^20", flush=True)
+    res, st = sel.select_kth(_dev(x), k, stats=True)
+    invariant_holds(x, k, res)
+    assert res["passes"] == st["passes"] >= 2
+    wp = st["work_passes"]
+    assert 2 <= wp <= 4 * 96
+    pops = st["population"][: min(wp, cps.STATS_MAX_PASSES)]
+    # the bracket population never grows (Section 4: the bracket only shrinks)
+    nz = pops[pops > 0]
+    assert np.all(np.diff(nz) <= 0)
+    # bisection-like halving on smooth data (end of Section 4): far fewer passes than log2(n) + 8
+    assert wp <= 24
