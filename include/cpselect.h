@@ -125,7 +125,11 @@ typedef struct cps_options {
  * kelley_steps, bisect_steps: how each trial point was chosen.
  * elements_read, elements_written: elements the passes moved (algorithmic traffic).
  * population[i]: elements inside the open bracket after pass i.
- * working[i]:   elements pass i read. */
+ * working[i]:   elements pass i read.
+ * t_start, t_arrive[i], t_publish[i]: device wall clock (100 MHz ticks) at the launch, when
+ *               the last workgroup finished pass i, and when the state after pass i was
+ *               published (the difference is the cutting-plane update and, on the last
+ *               pass, the exact select). */
 typedef struct cps_stats {
   int32_t passes;
   int32_t work_passes;
@@ -137,6 +141,9 @@ typedef struct cps_stats {
   int64_t elements_written;
   int64_t population[CPS_STATS_MAX_PASSES];
   int64_t working[CPS_STATS_MAX_PASSES];
+  uint64_t t_start;
+  uint64_t t_arrive[CPS_STATS_MAX_PASSES];
+  uint64_t t_publish[CPS_STATS_MAX_PASSES];
 } cps_stats;
 
 typedef struct cps_handle cps_handle;

@@ -39,7 +39,10 @@ STATS_DTYPE = np.dtype([("passes", "<i4"), ("work_passes", "<i4"), ("kelley_step
                         ("bracket_used", "<i4"), ("elements_read", "<i8"),
                         ("elements_written", "<i8"),
                         ("population", "<i8", (STATS_MAX_PASSES,)),
-                        ("working", "<i8", (STATS_MAX_PASSES,))])
+                        ("working", "<i8", (STATS_MAX_PASSES,)),
+                        ("t_start", "<u8"),
+                        ("t_arrive", "<u8", (STATS_MAX_PASSES,)),
+                        ("t_publish", "<u8", (STATS_MAX_PASSES,))])
 assert RESULT_DTYPE.itemsize == 48 and EVAL_DTYPE.itemsize == 80
 
 

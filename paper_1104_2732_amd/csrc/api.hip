@@ -32,13 +32,15 @@ struct cps_handle {
 
 namespace {
 
-// Workspace layout of a single-array selection.
+// Workspace layout of a single-array selection: state, synchronisation words, per-workgroup
+// partials, two split buffers (one region of seg_R elements per workgroup each) and the
+// gather buffer.
 struct SelectLayout {
-  size_t st, sync, sd, si, z0, z1, total;
-  int64_t slot_stride, zcap;
+  size_t st, sync, sd, si, z0, z1, zf, total;
+  int64_t slot_stride, seg_R, zcap;
 };
 
-SelectLayout select_layout(int64_t zcap, int gmax, size_t esize) {
+SelectLayout select_layout(int64_t seg_R, int grid, int64_t zcap, int gmax, size_t esize) {
   SelectLayout L;
   size_t off = 0;
   L.st = off;
@@ -50,10 +52,14 @@ SelectLayout select_layout(int64_t zcap, int gmax, size_t esize) {
   off = align_up(off + 8 * (size_t)gmax * sizeof(double), 256);
   L.si = off;
   off = align_up(off + 8 * (size_t)gmax * sizeof(int64_t), 256);
-  L.zcap = zcap;
+  L.seg_R = seg_R;
   L.z0 = off;
-  off = align_up(off + (size_t)zcap * esize, 256);
+  const size_t zbytes = (size_t)seg_R * grid * (cps::kSelectBlock / cps::kWaveSize) * esize;
+  off = align_up(off + zbytes, 256);
   L.z1 = off;
+  off = align_up(off + zbytes, 256);
+  L.zcap = zcap;
+  L.zf = off;
   off = align_up(off + (size_t)zcap * esize, 256);
   L.total = off;
   return L;
@@ -83,7 +89,7 @@ int ensure_workspace(cps_handle *h, size_t bytes, hipStream_t stream) {
     h->ws = nullptr;
     return CPS_ENOMEM;
   }
-  e = hipMemset(h->ws, 0, want < (1 << 20) ? want : (1 << 20));
+  e = hipMemset(h->ws, 0, want < (1 << 21) ? want : (1 << 21));
   if (e != hipSuccess) return hip_fail(e);
   h->ws_bytes = want;
   return CPS_OK;
@@ -94,6 +100,7 @@ inline size_t dtype_size(int dtype) { return dtype == CPS_F32 ? 4 : (dtype == CP
 struct Resolved {
   cps::CpConfig cfg;
   int grid;
+  int64_t seg_R;
   int64_t spin_limit;
 };
 
@@ -111,12 +118,7 @@ int resolve(cps_handle *h, int64_t n, int dtype, const cps_options *opt, Resolve
   r.cfg.final_threshold = o.final_threshold;
   r.cfg.final_direct_max = 4 * (int64_t)o.final_threshold;
   r.cfg.theta = o.partition_fraction;
-  int64_t zcap = o.final_threshold;
-  if (o.partition_fraction > 0.0) {
-    const int64_t want = (int64_t)(o.partition_fraction * (double)n) + 1;
-    if (want > zcap) zcap = want;
-  }
-  r.cfg.zcap = zcap;
+  r.cfg.zcap = o.final_threshold;
   r.cfg.use_bracket = o.use_bracket ? 1 : 0;
   r.cfg.bracket_lo = o.bracket_lo;
   r.cfg.bracket_hi = o.bracket_hi;
@@ -128,8 +130,23 @@ int resolve(cps_handle *h, int64_t n, int dtype, const cps_options *opt, Resolve
   const int64_t tiles = (n + tile - 1) / tile;
   if (g > tiles) g = tiles;
   if (g > gmax) g = gmax;
+  if (g > (int64_t)cps::kGroup * cps::kMaxGroups) g = (int64_t)cps::kGroup * cps::kMaxGroups;
   if (g < 1) g = 1;
   r.grid = (int)g;
+  // Each wavefront's split region holds everything it can read in the first split (a
+  // pass over the input with half the unroll): its share of each of its workgroup's
+  // steps, plus the unaligned edge elements, rounded to 64 elements.
+  int64_t seg = 0;
+  if (o.partition_fraction > 0.0) {
+    const int64_t vec = 16 / (int64_t)dtype_size(dtype);
+    const int64_t su = cps::kSelectUnroll / 2 > 0 ? cps::kSelectUnroll / 2 : 1;
+    const int64_t step_vecs = (int64_t)cps::kSelectBlock * su;
+    const int64_t nvec = n / vec + 1;
+    const int64_t steps = (nvec + step_vecs - 1) / step_vecs;
+    const int64_t steps_per_wg = (steps + g - 1) / g;
+    seg = (steps_per_wg * cps::kWaveSize * su * vec + 8 + 63) / 64 * 64;
+  }
+  r.seg_R = seg;
   r.spin_limit = o.spin_limit ? o.spin_limit : (int64_t)1 << 22;
   return CPS_OK;
 }
@@ -141,7 +158,7 @@ int run_select(cps_handle *h, const T *x, int64_t n, int64_t k, const cps_option
   int rc = resolve(h, n, sizeof(T) == 4 ? CPS_F32 : CPS_F64, opt, r);
   if (rc) return rc;
   const int per_cu = sizeof(T) == 4 ? h->max_blocks_f32 : h->max_blocks_f64;
-  const SelectLayout L = select_layout(r.cfg.zcap, h->cu_count * per_cu, sizeof(T));
+  const SelectLayout L = select_layout(r.seg_R, r.grid, r.cfg.zcap, h->cu_count * per_cu, sizeof(T));
   rc = ensure_workspace(h, L.total, stream);
   if (rc) return rc;
   char *base = (char *)h->ws;
@@ -156,6 +173,8 @@ int run_select(cps_handle *h, const T *x, int64_t n, int64_t k, const cps_option
   a.slot_stride = L.slot_stride;
   a.z[0] = (T *)(base + L.z0);
   a.z[1] = (T *)(base + L.z1);
+  a.seg_R = L.seg_R;
+  a.zf = (T *)(base + L.zf);
   a.out = out;
   a.stats = stats;
   a.cfg = r.cfg;
@@ -250,7 +269,8 @@ int cps_reserve(cps_handle *h, int64_t n, int dtype) {
   int rc = resolve(h, n, dtype, nullptr, r);
   if (rc) return rc;
   const int per_cu = dtype == CPS_F32 ? h->max_blocks_f32 : h->max_blocks_f64;
-  const SelectLayout L = select_layout(r.cfg.zcap, h->cu_count * per_cu, dtype_size(dtype));
+  const SelectLayout L =
+      select_layout(r.seg_R, r.grid, r.cfg.zcap, h->cu_count * per_cu, dtype_size(dtype));
   return ensure_workspace(h, L.total, nullptr);
 }
 
@@ -285,8 +305,8 @@ int cps_objective(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
   if (nb < 1) nb = 1;
   const size_t pd_bytes = align_up((size_t)ny * nb * 4 * sizeof(double), 256);
   const size_t pi_bytes = align_up((size_t)ny * nb * 3 * sizeof(int64_t), 256);
-  // keep clear of the select layout's synchronisation words at the start
-  const size_t off = 4096;
+  // keep clear of the select layout's state and synchronisation words at the start
+  const size_t off = align_up(sizeof(cps::CpState), 256) + align_up(sizeof(cps::SyncCtl), 256);
   rc = ensure_workspace(h, off + pd_bytes + pi_bytes, s);
   if (rc) return rc;
   double *pd = (double *)((char *)h->ws + off);

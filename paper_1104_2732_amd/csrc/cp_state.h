@@ -21,9 +21,11 @@
 //
 // Working set.  Pass 0 and the first evaluation passes read the whole input.  Once
 // the bracket holds few enough elements, a pass also writes the bracket's elements
-// below and above the trial point to the two ends of a workspace buffer (the
-// count-and-compact of Section 4, done as part of the evaluation pass), and the next
-// pass reads only the side that still holds x_(k).  Reading only the bracket's
+// below and above the trial point to the two ends of each workgroup's private region
+// of a workspace buffer (the count-and-compact of Section 4, done as part of the
+// evaluation pass), and the next pass reads only the side that still holds x_(k).
+// Once the bracket is small, a gather pass copies its elements into one contiguous
+// buffer for the exact select.  Reading only the bracket's
 // elements changes f by a positive factor and an affine term on the bracket, so the
 // cutting-plane trial points are unchanged: A and B of the full array are rebuilt
 // from the bracket-only sums as
@@ -47,7 +49,7 @@
 
 namespace cps {
 
-enum Phase : int32_t { PH_PASS0 = 0, PH_EVAL = 1, PH_FINAL = 2, PH_DONE = 3 };
+enum Phase : int32_t { PH_PASS0 = 0, PH_EVAL = 1, PH_GATHER = 2, PH_FINAL = 3, PH_DONE = 4 };
 
 // status values mirror enum cps_status in cpselect.h
 enum : int32_t { ST_OK = 0, ST_NAN = 1, ST_TIMEOUT = 2, ST_INTERNAL = 3 };
@@ -58,7 +60,7 @@ struct CpConfig {
   int64_t final_threshold;  // bracket population handled by one workgroup
   int64_t final_direct_max; // largest unsplit input one workgroup may scan directly
   double theta;             // start splitting once population <= theta * n (0 = never)
-  int64_t zcap;             // capacity of each split buffer (elements)
+  int64_t zcap;             // capacity of the gather buffer (elements, >= final_threshold)
   int32_t use_bracket;
   int32_t pad0;
   double bracket_lo, bracket_hi;
@@ -68,6 +70,8 @@ struct CpConfig {
 // one reduction; here with the multiplicity of min and max, the sum over finite
 // values and the counts of NaN and infinities).
 struct Pass0Result {
+  int32_t classified;   // 1: NaN and infinities were classified (nneg, npos, finite min/max)
+  int32_t pad0;
   double sum;           // sum of finite elements
   double fmin, fmax;    // min and max over finite elements (+inf / -inf if none)
   int64_t cmin, cmax;   // multiplicities of fmin and fmax
@@ -100,9 +104,12 @@ struct CpState {
   int32_t on_bracket;      // the working set is exactly the elements inside (yL, yR)
   int32_t has_inf;         // evaluate with values clamped into [fmin, fmax]
   double fmin, fmax;
-  int32_t wbuf;            // -1: the input; 0/1: split buffer holding the working set
+  int32_t wbuf;            // -1: the input; 0/1: split buffer holding the working set;
+                           // 2: the gather buffer (contiguous, wlen elements)
   int32_t zout;            // buffer the next split writes
-  int64_t woff, wlen;      // working set = buffer[woff, woff + wlen)
+  int32_t side;            // split buffers: 0 = the low part of each region, 1 = the high part
+  int32_t pad2;
+  int64_t wlen;            // elements in the working set
   int32_t passes;          // full reads of the input
   int32_t work_passes;     // all passes
   int32_t kelley, bisect;
@@ -110,7 +117,8 @@ struct CpState {
   double value;            // result (as T widened to double)
   int64_t less, equal;
   int64_t final_size;
-  int32_t bracket_used, pad1;
+  int32_t bracket_used;
+  int32_t p0_slow;         // pass 0 must classify infinities (the fast pass saw one)
 };
 
 static_assert(sizeof(CpState) % 8 == 0, "state is copied in 8-byte words");
@@ -231,23 +239,20 @@ CPS_HD inline void cp_plan(CpState &s, const CpConfig &c) {
   s.split = 0;
   s.filter = 0;
   if (pop <= c.final_threshold) {
-    if (s.on_bracket || s.wlen <= c.final_direct_max) {
-      s.phase = PH_FINAL;
+    if (s.wbuf < 0 && s.wlen <= c.final_direct_max) {
+      s.phase = PH_FINAL;  // small input: select straight from x, keeping (yL, yR) only
       s.final_size = s.wlen;
       return;
     }
-    // Compaction only: a split at t = yR sends every element of (yL, yR) to the low side.
-    s.phase = PH_EVAL;
-    s.split = 1;
-    s.filter = 1;
-    s.zout = 0;
-    s.t = s.yR;
+    s.phase = PH_GATHER;  // copy the bracket's elements into one contiguous buffer
+    s.filter = s.on_bracket ? 0 : 1;
     return;
   }
   if (s.on_bracket) {
     s.split = 1;
     s.zout = 1 - s.wbuf;
-  } else if (c.theta > 0.0 && (double)pop <= c.theta * (double)s.n && pop <= c.zcap) {
+  } else if (c.theta > 0.0 && !s.has_inf && (double)pop <= c.theta * (double)s.n) {
+    // (inputs holding infinities keep reading x until the gather: no clamped split)
     s.split = 1;
     s.filter = 1;
     s.zout = 0;
@@ -260,14 +265,20 @@ CPS_HD inline void cp_plan(CpState &s, const CpConfig &c) {
 // extreme value (or NaN is present), else with the first trial point planned.
 CPS_HD inline void cp_after_pass0(CpState &s, const Pass0Result &r, const CpConfig &c) {
   const int64_t n = s.n, k = s.k;
-  s.passes = 1;
-  s.work_passes = 1;
-  s.elements_read = n;
-  s.elements_written = 0;
-  s.kelley = s.bisect = 0;
+  s.passes++;
+  s.work_passes++;
+  s.elements_read += n;
   s.status = ST_OK;
   s.bracket_used = 0;
   s.final_size = 0;
+  if (!r.classified && r.nnan == 0 &&
+      (r.fmin == -__builtin_inf() || r.fmax == __builtin_inf())) {
+    // The fast pass 0 does not separate infinities from the finite extremes; repeat it
+    // with the classification (only inputs holding an infinity pay for this).
+    s.phase = PH_PASS0;
+    s.p0_slow = 1;
+    return;
+  }
   if (r.nnan > 0) {
     s.status = ST_NAN;
     cp_finish(s, __builtin_nan(""), 0, 0);
@@ -299,7 +310,7 @@ CPS_HD inline void cp_after_pass0(CpState &s, const Pass0Result &r, const CpConf
   s.hi = next_down(s.yR, c.dtype);
   s.lo_data = s.hi_data = 0;
   s.wbuf = -1;
-  s.woff = 0;
+  s.side = 0;
   s.wlen = n;
   s.on_bracket = 0;
   // A proposed bracket (a, b) replaces an end only when the counts prove it holds
@@ -364,7 +375,7 @@ CPS_HD inline void cp_after_eval(CpState &s, const EvalResult &r, const CpConfig
     s.lo_data = 1;
     if (did_split) {
       s.wbuf = zout;
-      s.woff = c.zcap - nright;
+      s.side = 1;
       s.wlen = nright;
       s.on_bracket = 1;
     }
@@ -378,7 +389,7 @@ CPS_HD inline void cp_after_eval(CpState &s, const EvalResult &r, const CpConfig
     s.hi_data = 1;
     if (did_split) {
       s.wbuf = zout;
-      s.woff = 0;
+      s.side = 0;
       s.wlen = nleft;
       s.on_bracket = 1;
     }
@@ -389,6 +400,35 @@ CPS_HD inline void cp_after_eval(CpState &s, const EvalResult &r, const CpConfig
     return;
   }
   cp_plan(s, c);
+}
+
+// After the gather pass: the bracket's elements now sit contiguously in the gather
+// buffer (`gathered` of them; anything else means the counts and the data disagree).
+CPS_HD inline void cp_after_gather(CpState &s, int64_t gathered) {
+  s.work_passes++;
+  if (s.wbuf < 0) s.passes++;
+  s.elements_read += s.wlen;
+  s.elements_written += gathered;
+  if (gathered != s.cR - s.cL) {
+    s.status = ST_INTERNAL;
+    cp_finish(s, 0.0, 0, 0);
+    return;
+  }
+  s.wbuf = 2;
+  s.wlen = gathered;
+  s.on_bracket = 1;
+  s.filter = 0;
+  s.phase = PH_FINAL;
+  s.final_size = gathered;
+}
+
+// After the exact select of rank k - cL among the working set's elements inside the
+// bracket: `value` has `below` candidates under it and multiplicity `eq`.
+CPS_HD inline void cp_after_final(CpState &s, double value, int64_t below, int64_t eq) {
+  s.work_passes++;
+  if (s.wbuf < 0) s.passes++;
+  s.elements_read += s.wlen;
+  cp_finish(s, value, s.cL + below, eq);
 }
 
 }  // namespace cps

@@ -74,6 +74,9 @@ __device__ inline int64_t wave_sum_i64(int64_t v) {
 __device__ inline uint32_t atomic_add_acq_rel(uint32_t *p, uint32_t v) {
   return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ inline uint32_t atomic_add_release(uint32_t *p, uint32_t v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ inline uint64_t atomic_add_relaxed(uint64_t *p, uint64_t v) {
   return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -99,7 +102,7 @@ __device__ inline void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE
 // one whole workgroup of BLOCK threads.  Returns the key of the selected element,
 // the number of candidates strictly below it and its multiplicity.
 template <typename T, int BLOCK>
-__device__ void block_radix_select(const T *__restrict__ W, int64_t m, bool filter, T lo_ex,
+__device__ __noinline__ void block_radix_select(const T *__restrict__ W, int64_t m, bool filter, T lo_ex,
                                    T hi_ex, int64_t r, uint32_t *hist /* 256 in LDS */,
                                    int64_t *s_misc /* 4 in LDS */,
                                    typename Traits<T>::Key &key_out, int64_t &below_out,

@@ -9,17 +9,23 @@
 
 namespace cps {
 
-constexpr int kSelectBlock = 256;
+constexpr int kWaveSize = 64;
+constexpr int kSelectBlock = 512;
 constexpr int kSelectUnroll = 4;
+constexpr int kGroup = 16;       // workgroups per first-level arrival counter
+constexpr int kMaxGroups = 256;  // so at most 4096 workgroups
 
-// Grid-synchronisation words of the single-array kernel.  `arrive` counts workgroups
-// that finished the current pass; `gen` is bumped by the last one when the next pass
-// may start; curL / curR hand out write offsets for the split of the current pass.
+// Grid-synchronisation words of the single-array kernel, each on its own 128-byte line.
+// Workgroups arrive on grp[bid / kGroup]; the last of each group arrives on `top`; the last
+// overall advances the state and bumps `gen`, on which the others wait.  gcur hands out
+// write offsets in the gather buffer.
 struct SyncCtl {
-  uint32_t arrive;
+  uint32_t top;
   uint32_t gen;
-  uint32_t pad0, pad1;
-  uint64_t curL, curR;
+  uint32_t pad0[30];
+  uint64_t gcur;
+  uint64_t pad1[15];
+  uint32_t grp[kMaxGroups][32];
 };
 
 template <typename T> struct SelectArgs {
@@ -30,7 +36,9 @@ template <typename T> struct SelectArgs {
   double *sd;          // per-workgroup partials, 8 fields x slot_stride
   int64_t *si;         // per-workgroup integer partials, 8 fields x slot_stride
   int64_t slot_stride;
-  T *z[2];             // split buffers, zcap elements each
+  T *z[2];             // split buffers: one region of seg_R elements per wavefront
+  int64_t seg_R;
+  T *zf;               // gather buffer, cfg.zcap elements
   cps_result *out;
   cps_stats *stats;    // may be null
   CpConfig cfg;

@@ -2,19 +2,23 @@
 //
 // One persistent kernel runs every pass of the method (Section 4, Algorithm 1 and the
 // hybrid that ends it):
-//   pass 0      min, max (with multiplicities), sum and NaN/infinity counts of x in one
-//               reduction (step 0), optionally with the two-point check of a proposed
-//               bracket;
+//   pass 0      min, max (with multiplicities) and sum of x in one reduction (step 0),
+//               with NaN detection; repeated with infinity classification only when
+//               an extreme is infinite; optionally with the two-point check of a
+//               proposed bracket;
 //   eval passes A(t), B(t), #(w<t), #(w>t), largest w<t and smallest w>t over the working
 //               set at the trial point t (the objective and subgradient of Section 3 in
 //               one fused reduction); once the bracket is small the same pass splits the
-//               bracket's elements at t into a workspace buffer (count-and-compact);
+//               bracket's elements at t into per-wavefront private regions of a
+//               workspace buffer (count-and-compact, with no atomics), and later passes
+//               read only the side that holds x_(k);
+//   gather      the bracket's remaining elements are copied into one contiguous buffer;
 //   final       one workgroup selects the remaining rank exactly (radix select on the
 //               ordered keys), in place of the paper's sort of the compacted array.
-// Between passes the grid synchronises through an arrival counter; the last workgroup
-// to arrive reduces the per-workgroup partials in a fixed order and advances the
-// cutting-plane state (cp_state.h), so no pass needs the host.  The kernel is launched
-// cooperatively, which guarantees that every workgroup is resident.
+// Between passes the grid synchronises through two-level arrival counters; the last
+// workgroup to arrive reduces the per-workgroup partials in a fixed order and advances
+// the cutting-plane state (cp_state.h), so no pass needs the host.  The kernel is
+// launched cooperatively, which guarantees that every workgroup is resident.
 #include "cps_device.h"
 #include "cps_kernels.h"
 
@@ -28,14 +32,14 @@ __device__ __noinline__ void dev_after_pass0(CpState &s, const Pass0Result &r, c
 __device__ __noinline__ void dev_after_eval(CpState &s, const EvalResult &r, const CpConfig &c) {
   cp_after_eval(s, r, c);
 }
+__device__ __noinline__ void dev_after_gather(CpState &s, int64_t gathered) {
+  cp_after_gather(s, gathered);
+}
+__device__ __noinline__ void dev_after_final(CpState &s, double v, int64_t below, int64_t eq) {
+  cp_after_final(s, v, below, eq);
+}
 
 // ------------------------------------------------------------------ per-element work
-
-template <typename T> struct EvalAcc {
-  double A, B;
-  T pred, succ;
-  uint64_t L, G;  // wave-uniform
-};
 
 template <typename T> __device__ inline T t_inf();
 template <> __device__ inline float t_inf<float>() { return __builtin_inff(); }
@@ -44,31 +48,26 @@ template <> __device__ inline double t_inf<double>() { return __builtin_inf(); }
 template <typename T> __device__ inline T tmin(T a, T b) { return a < b ? a : b; }
 template <typename T> __device__ inline T tmax(T a, T b) { return a > b ? a : b; }
 
-// Evaluate one loaded vector at t.  Invalid lanes contribute nothing.
+template <typename T> struct EvalAcc {
+  double A, B;
+  T pred, succ;
+  uint64_t L, G;  // wave-uniform
+};
+
+// Evaluate one element at t.  Invalid lanes contribute nothing.
 template <typename T, bool CLAMP>
-__device__ inline void eval_vec(T (&e)[Traits<T>::kVec], bool valid, T t, T fmin, T fmax,
+__device__ inline void eval_one(T &v, bool valid, T t, T fmin, T fmax, T &a_part, T &b_part,
                                 EvalAcc<T> &acc) {
-  constexpr int V = Traits<T>::kVec;
-  T a_part = 0, b_part = 0;
-#pragma unroll
-  for (int j = 0; j < V; ++j) {
-    T v = e[j];
-    if (CLAMP) {
-      v = tmin(tmax(v, fmin), fmax);
-      e[j] = v;
-    }
-    const bool l = valid && (v < t);
-    const bool g = valid && (v > t);
-    const T d = v - t;
-    a_part += g ? d : T(0);
-    b_part -= l ? d : T(0);
-    acc.pred = tmax(acc.pred, l ? v : -t_inf<T>());
-    acc.succ = tmin(acc.succ, g ? v : t_inf<T>());
-    acc.L += popc(ballot(l));
-    acc.G += popc(ballot(g));
-  }
-  acc.A += (double)a_part;
-  acc.B += (double)b_part;
+  if (CLAMP) v = tmin(tmax(v, fmin), fmax);
+  const bool l = valid && (v < t);
+  const bool g = valid && (v > t);
+  const T d = v - t;
+  a_part += g ? d : T(0);
+  b_part -= l ? d : T(0);
+  acc.pred = tmax(acc.pred, l ? v : -t_inf<T>());
+  acc.succ = tmin(acc.succ, g ? v : t_inf<T>());
+  acc.L += popc(ballot(l));
+  acc.G += popc(ballot(g));
 }
 
 template <typename T> struct P0Acc {
@@ -80,42 +79,36 @@ template <typename T> struct P0Acc {
   double Aa, Ba, Ab, Bb;
 };
 
-template <typename T, bool BRACKET>
-__device__ inline void pass0_vec(const T (&e)[Traits<T>::kVec], bool valid, T ba, T bb,
-                                 P0Acc<T> &acc) {
-  constexpr int V = Traits<T>::kVec;
-  T s_part = 0;
-  T aa = 0, bA = 0, ab = 0, bB = 0;
-#pragma unroll
-  for (int j = 0; j < V; ++j) {
-    const T v = e[j];
-    const bool isnan_ = valid && (v != v);
+// Pass 0 on one element.  CLASSIFY: separate NaN and infinities from the finite values
+// (the slow variant); otherwise only NaN is detected and infinities, if any, show up as
+// an infinite extreme, which makes the state machine ask for the slow variant.
+template <typename T, bool CLASSIFY, bool BRACKET>
+__device__ inline void pass0_one(T v, bool valid, T ba, T bb, T &s_part, T &aa, T &bA, T &ab,
+                                 T &bB, P0Acc<T> &acc) {
+  const bool isnan_ = valid && (v != v);
+  acc.nnan += popc(ballot(isnan_));
+  bool fin = valid;
+  if (CLASSIFY) {
     const bool ni = valid && (v == -t_inf<T>());
     const bool pi = valid && (v == t_inf<T>());
-    const bool fin = valid && !isnan_ && !ni && !pi;
-    if (fin && v < acc.mn) { acc.mn = v; acc.cmn = 1u; }
-    else if (fin && v == acc.mn) { acc.cmn++; }
-    if (fin && v > acc.mx) { acc.mx = v; acc.cmx = 1u; }
-    else if (fin && v == acc.mx) { acc.cmx++; }
-    s_part += fin ? v : T(0);
-    acc.nnan += popc(ballot(isnan_));
     acc.nneg += popc(ballot(ni));
     acc.npos += popc(ballot(pi));
-    if (BRACKET) {
-      acc.cle_a += popc(ballot(valid && v <= ba));
-      acc.clt_b += popc(ballot(valid && v < bb));
-      aa += (fin && v > ba) ? v - ba : T(0);
-      bA += (fin && v < ba) ? ba - v : T(0);
-      ab += (fin && v > bb) ? v - bb : T(0);
-      bB += (fin && v < bb) ? bb - v : T(0);
-    }
+    fin = valid && !isnan_ && !ni && !pi;
   }
-  acc.sum += (double)s_part;
+  const bool lt = fin && v < acc.mn, eqn = fin && v == acc.mn;
+  acc.cmn = lt ? 1u : acc.cmn + (eqn ? 1u : 0u);
+  acc.mn = lt ? v : acc.mn;
+  const bool gt = fin && v > acc.mx, eqx = fin && v == acc.mx;
+  acc.cmx = gt ? 1u : acc.cmx + (eqx ? 1u : 0u);
+  acc.mx = gt ? v : acc.mx;
+  s_part += fin ? v : T(0);
   if (BRACKET) {
-    acc.Aa += (double)aa;
-    acc.Ba += (double)bA;
-    acc.Ab += (double)ab;
-    acc.Bb += (double)bB;
+    acc.cle_a += popc(ballot(valid && v <= ba));
+    acc.clt_b += popc(ballot(valid && v < bb));
+    aa += (fin && v > ba) ? v - ba : T(0);
+    bA += (fin && v < ba) ? ba - v : T(0);
+    ab += (fin && v > bb) ? v - bb : T(0);
+    bB += (fin && v < bb) ? bb - v : T(0);
   }
 }
 
@@ -147,221 +140,209 @@ template <typename T> __device__ inline int64_t edge_index(const Span<T> &s, int
   return i < s.head ? i : s.tail_start + (i - s.head);
 }
 
+// How the threads of a workgroup walk the working set.  BLOCK mode: the whole input,
+// tiles of BLOCK*U vectors dealt round-robin to workgroups (vector u*BLOCK + tid of a
+// tile belongs to thread tid).  WAVE mode: each wavefront walks its own segment of a
+// split buffer, 64*U vectors at a time.  The edge elements of a span go to the first
+// lanes of its owner.
+template <typename T> struct Walk {
+  Span<T> sp;
+  bool wave_mode;
+  bool edge_owner;
+};
+
 // ------------------------------------------------------------------ kernel
 
-template <typename T, int BLOCK, int UNROLL> struct Shared {
+template <typename T, int BLOCK> struct Shared {
   CpState st;
   double d[8][BLOCK / kWave];
   int64_t i[8][BLOCK / kWave];
-  uint64_t wbase[2][BLOCK / kWave];
-  uint32_t wcnt[2][BLOCK / kWave];
+  int64_t wseg[2][BLOCK / kWave];  // per wavefront: low / high counts of its last split
+  uint64_t gbase[BLOCK / kWave];
   uint32_t hist[256];
   int64_t misc[8];
   int last;
+  int timed_out;
 };
 
-template <typename T, int BLOCK>
-__device__ inline void wave_pair_min(T &m, uint32_t &c) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) {
-    T m2 = __shfl_xor(m, o);
-    uint32_t c2 = __shfl_xor(c, o);
-    if (m2 < m) { m = m2; c = c2; }
-    else if (m2 == m) { c += c2; }
-  }
-}
-template <typename T, int BLOCK>
-__device__ inline void wave_pair_max(T &m, uint32_t &c) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) {
-    T m2 = __shfl_xor(m, o);
-    uint32_t c2 = __shfl_xor(c, o);
-    if (m2 > m) { m = m2; c = c2; }
-    else if (m2 == m) { c += c2; }
-  }
-}
-
-// Split the tile's elements: those in (lo_ex, t) go up from the start of zout, those in
-// (t, hi_ex) go down from its end (FILTER: the working set is the whole input, so the
-// bracket ends are checked too; otherwise every element is inside the bracket).
-// Offsets come from one atomic per side per tile; within a wave the elements of one
-// slot are written contiguously.
+// Which side of the trial point an element goes to in a split: the bracket's elements
+// below t to the low part, above t to the high part.  FILTER: the working set is the
+// whole input, so the bracket ends are tested too.
 template <typename T, bool FILTER>
-__device__ inline bool goes_left(T v, bool valid, T t, T lo_ex) {
+__device__ inline bool goes_low(T v, bool valid, T t, T lo_ex) {
   return valid && v < t && (!FILTER || v > lo_ex);
 }
 template <typename T, bool FILTER>
-__device__ inline bool goes_right(T v, bool valid, T t, T hi_ex) {
+__device__ inline bool goes_high(T v, bool valid, T t, T hi_ex) {
   return valid && v > t && (!FILTER || v < hi_ex);
 }
 
-template <typename T, int BLOCK, int UNROLL, bool FILTER, bool EDGE = false>
-__device__ inline void split_tile(T (&e)[UNROLL][Traits<T>::kVec], const bool (&valid)[UNROLL],
-                                  T t, T lo_ex, T hi_ex, T *__restrict__ zout, int64_t zcap,
-                                  SyncCtl *sync, Shared<T, BLOCK, UNROLL> &sh, int64_t &written) {
-  constexpr int V = Traits<T>::kVec;
-  const int tid = threadIdx.x, wv = tid / kWave, lane = tid % kWave;
-  uint32_t wl = 0, wr = 0;
-#pragma unroll
-  for (int u = 0; u < UNROLL; ++u)
-#pragma unroll
-    for (int j = 0; j < V; ++j) {
-      if (EDGE && (u > 0 || j > 0)) continue;  // edge tiles hold one element per thread
-      wl += popc(ballot(goes_left<T, FILTER>(e[u][j], valid[u], t, lo_ex)));
-      wr += popc(ballot(goes_right<T, FILTER>(e[u][j], valid[u], t, hi_ex)));
-    }
-  if (lane == 0) {
-    sh.wcnt[0][wv] = wl;
-    sh.wcnt[1][wv] = wr;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    uint64_t tl = 0, tr = 0;
-    for (int w = 0; w < BLOCK / kWave; ++w) {
-      sh.wbase[0][w] = tl;
-      tl += sh.wcnt[0][w];
-      sh.wbase[1][w] = tr;
-      tr += sh.wcnt[1][w];
-    }
-    const uint64_t bl = tl ? atomic_add_relaxed(&sync->curL, tl) : 0;
-    const uint64_t br = tr ? atomic_add_relaxed(&sync->curR, tr) : 0;
-    for (int w = 0; w < BLOCK / kWave; ++w) {
-      sh.wbase[0][w] += bl;
-      sh.wbase[1][w] += br;
-    }
-    written += (int64_t)(tl + tr);
-  }
-  __syncthreads();
-  // recompute the side tests below instead of keeping 2 x UNROLL x V lane masks alive
-#pragma unroll
-  for (int u = 0; u < UNROLL; ++u)
-#pragma unroll
-    for (int j = 0; j < V; ++j) asm volatile("" : "+v"(e[u][j]));
-  uint64_t ol = sh.wbase[0][wv], orr = sh.wbase[1][wv];
-#pragma unroll
-  for (int u = 0; u < UNROLL; ++u)
-#pragma unroll
-    for (int j = 0; j < V; ++j) {
-      if (EDGE && (u > 0 || j > 0)) continue;
-      const bool l = goes_left<T, FILTER>(e[u][j], valid[u], t, lo_ex);
-      const uint64_t ml = ballot(l);
-      if (l) zout[ol + lane_rank(ml)] = e[u][j];
-      ol += popc(ml);
-      const bool r = goes_right<T, FILTER>(e[u][j], valid[u], t, hi_ex);
-      const uint64_t mr = ballot(r);
-      if (r) zout[zcap - 1 - (int64_t)(orr + lane_rank(mr))] = e[u][j];
-      orr += popc(mr);
-    }
-  __syncthreads();
+// Per-wavefront split output: the low part grows up from the start of the wavefront's
+// region, the high part down from its end.  The cursors are wave-uniform.
+template <typename T> struct WaveOut {
+  T *region;
+  int64_t Rw;
+  int64_t lo, hi;
+};
+
+template <typename T, bool FILTER>
+__device__ inline void split_one(T v, bool valid, T t, T yL, T yR, WaveOut<T> &o) {
+  const bool l = goes_low<T, FILTER>(v, valid, t, yL);
+  const uint64_t ml = ballot(l);
+  if (l) o.region[o.lo + lane_rank(ml)] = v;
+  o.lo += popc(ml);
+  const bool r = goes_high<T, FILTER>(v, valid, t, yR);
+  const uint64_t mr = ballot(r);
+  if (r) o.region[o.Rw - 1 - (o.hi + (int64_t)lane_rank(mr))] = v;
+  o.hi += popc(mr);
 }
 
-// One evaluation pass over this workgroup's tiles of the working set.
-template <typename T, int BLOCK, int UNROLL, bool CLAMP, bool SPLIT, bool FILTER>
-__device__ void eval_pass(const Span<T> &sp, T t, T yL, T yR, T fmin, T fmax, T *zout,
-                          int64_t zcap, SyncCtl *sync, Shared<T, BLOCK, UNROLL> &sh,
-                          EvalAcc<T> &acc, int64_t &written) {
+// One evaluation pass (optionally splitting) over this thread's share of the walk.
+template <typename T, int BLOCK, int U, bool CLAMP, bool SPLIT, bool FILTER>
+__device__ inline void eval_pass(const Walk<T> &wk, T t, T yL, T yR, T fmin, T fmax,
+                                       WaveOut<T> &o, EvalAcc<T> &acc) {
   constexpr int V = Traits<T>::kVec;
   using Vec = typename Traits<T>::Vec;
-  const int tid = threadIdx.x;
-  const int G = gridDim.x, bid = blockIdx.x;
-  const int64_t tile_vecs = (int64_t)BLOCK * UNROLL;
-  const int64_t ntiles = (sp.nvec + tile_vecs - 1) / tile_vecs;
-  for (int64_t ti = bid; ti < ntiles; ti += G) {
-    const int64_t base = ti * tile_vecs;
-    T e[UNROLL][V];
-    bool valid[UNROLL];
-    Vec raw[UNROLL];
+  const int tid = threadIdx.x, lane = tid % kWave;
+  const Span<T> &sp = wk.sp;
+  const int64_t step_vecs = wk.wave_mode ? (int64_t)kWave * U : (int64_t)BLOCK * U;
+  const int64_t first = wk.wave_mode ? 0 : (int64_t)blockIdx.x * step_vecs;
+  const int64_t stride = wk.wave_mode ? step_vecs : (int64_t)gridDim.x * step_vecs;
+  const int me = wk.wave_mode ? lane : tid;
+  const int per_u = wk.wave_mode ? kWave : BLOCK;
+  for (int64_t base = first; base < sp.nvec; base += stride) {
+    Vec raw[U];
+    bool valid[U];
 #pragma unroll
-    for (int u = 0; u < UNROLL; ++u) {
-      const int64_t vi = base + (int64_t)u * BLOCK + tid;
+    for (int u = 0; u < U; ++u) {
+      const int64_t vi = base + (int64_t)u * per_u + me;
       valid[u] = vi < sp.nvec;
       if (valid[u]) raw[u] = sp.V[vi];
     }
 #pragma unroll
-    for (int u = 0; u < UNROLL; ++u) {
-      vec_to_arr<T>(raw[u], e[u]);
-      eval_vec<T, CLAMP>(e[u], valid[u], t, fmin, fmax, acc);
-    }
-    if (SPLIT) split_tile<T, BLOCK, UNROLL, FILTER>(e, valid, t, yL, yR, zout, zcap, sync, sh, written);
-  }
-  // unaligned head and tail elements: the last workgroup takes them as one partial tile,
-  // one element per thread in slot (0, 0)
-  if (sp.nedge > 0 && bid == G - 1) {
-    T e[UNROLL][V];
-    bool valid[UNROLL];
-#pragma unroll
-    for (int u = 0; u < UNROLL; ++u) {
-      valid[u] = false;
-#pragma unroll
-      for (int j = 0; j < V; ++j) e[u][j] = T(0);
-    }
-    const bool have = tid < sp.nedge;
-    T v = have ? sp.W[edge_index(sp, tid)] : T(0);
-    if (CLAMP) v = tmin(tmax(v, fmin), fmax);
-    const bool l = have && v < t, g = have && v > t;
-    const T d = v - t;
-    acc.A += g ? (double)d : 0.0;
-    acc.B += l ? -(double)d : 0.0;
-    acc.pred = tmax(acc.pred, l ? v : -t_inf<T>());
-    acc.succ = tmin(acc.succ, g ? v : t_inf<T>());
-    acc.L += popc(ballot(l));
-    acc.G += popc(ballot(g));
-    if (SPLIT) {
-      e[0][0] = v;
-      valid[0] = have;
-      split_tile<T, BLOCK, UNROLL, FILTER, true>(e, valid, t, yL, yR, zout, zcap, sync, sh, written);
-    }
-  }
-}
-
-template <typename T, int BLOCK, int UNROLL, bool BRACKET>
-__device__ void pass0(const Span<T> &sp, T ba, T bb, P0Acc<T> &acc) {
-  constexpr int V = Traits<T>::kVec;
-  using Vec = typename Traits<T>::Vec;
-  const int tid = threadIdx.x;
-  const int G = gridDim.x, bid = blockIdx.x;
-  const int64_t tile_vecs = (int64_t)BLOCK * UNROLL;
-  const int64_t ntiles = (sp.nvec + tile_vecs - 1) / tile_vecs;
-  for (int64_t ti = bid; ti < ntiles; ti += G) {
-    const int64_t base = ti * tile_vecs;
-    Vec raw[UNROLL];
-    bool valid[UNROLL];
-#pragma unroll
-    for (int u = 0; u < UNROLL; ++u) {
-      const int64_t vi = base + (int64_t)u * BLOCK + tid;
-      valid[u] = vi < sp.nvec;
-      if (valid[u]) raw[u] = sp.V[vi];
-    }
-#pragma unroll
-    for (int u = 0; u < UNROLL; ++u) {
+    for (int u = 0; u < U; ++u) {
       T e[V];
       vec_to_arr<T>(raw[u], e);
-      pass0_vec<T, BRACKET>(e, valid[u], ba, bb, acc);
+      T a_part = 0, b_part = 0;
+#pragma unroll
+      for (int j = 0; j < V; ++j) eval_one<T, CLAMP>(e[j], valid[u], t, fmin, fmax, a_part, b_part, acc);
+      acc.A += (double)a_part;
+      acc.B += (double)b_part;
+      if (SPLIT) {
+#pragma unroll
+        for (int j = 0; j < V; ++j) split_one<T, FILTER>(e[j], valid[u], t, yL, yR, o);
+      }
     }
   }
-  if (sp.nedge > 0 && bid == G - 1) {
-    // unaligned head and tail elements, one per thread of the last workgroup
-    const bool have = tid < sp.nedge;
-    const T v = have ? sp.W[edge_index(sp, tid)] : T(0);
-    const bool isnan_ = have && (v != v);
-    const bool ni = have && (v == -t_inf<T>());
-    const bool pi = have && (v == t_inf<T>());
-    const bool fin = have && !isnan_ && !ni && !pi;
-    if (fin && v < acc.mn) { acc.mn = v; acc.cmn = 1u; }
-    else if (fin && v == acc.mn) { acc.cmn++; }
-    if (fin && v > acc.mx) { acc.mx = v; acc.cmx = 1u; }
-    else if (fin && v == acc.mx) { acc.cmx++; }
-    acc.sum += fin ? (double)v : 0.0;
-    acc.nnan += popc(ballot(isnan_));
-    acc.nneg += popc(ballot(ni));
-    acc.npos += popc(ballot(pi));
+  if (sp.nedge > 0 && wk.edge_owner && (wk.wave_mode || tid < kWave)) {
+    const bool have = lane < sp.nedge;
+    T v = have ? sp.W[edge_index(sp, lane)] : T(0);
+    T a_part = 0, b_part = 0;
+    eval_one<T, CLAMP>(v, have, t, fmin, fmax, a_part, b_part, acc);
+    acc.A += (double)a_part;
+    acc.B += (double)b_part;
+    if (SPLIT) split_one<T, FILTER>(v, have, t, yL, yR, o);
+  }
+}
+
+template <typename T, int BLOCK, int U, bool CLASSIFY, bool BRACKET>
+__device__ inline void pass0(const Walk<T> &wk, T ba, T bb, P0Acc<T> &acc) {
+  constexpr int V = Traits<T>::kVec;
+  using Vec = typename Traits<T>::Vec;
+  const int tid = threadIdx.x, lane = tid % kWave;
+  const Span<T> &sp = wk.sp;
+  const int64_t step_vecs = (int64_t)BLOCK * U;
+  for (int64_t base = (int64_t)blockIdx.x * step_vecs; base < sp.nvec;
+       base += (int64_t)gridDim.x * step_vecs) {
+    Vec raw[U];
+    bool valid[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t vi = base + (int64_t)u * BLOCK + tid;
+      valid[u] = vi < sp.nvec;
+      if (valid[u]) raw[u] = sp.V[vi];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      T e[V];
+      vec_to_arr<T>(raw[u], e);
+      T s_part = 0, aa = 0, bA = 0, ab = 0, bB = 0;
+#pragma unroll
+      for (int j = 0; j < V; ++j)
+        pass0_one<T, CLASSIFY, BRACKET>(e[j], valid[u], ba, bb, s_part, aa, bA, ab, bB, acc);
+      acc.sum += (double)s_part;
+      if (BRACKET) {
+        acc.Aa += (double)aa;
+        acc.Ba += (double)bA;
+        acc.Ab += (double)ab;
+        acc.Bb += (double)bB;
+      }
+    }
+  }
+  if (sp.nedge > 0 && wk.edge_owner && tid < kWave) {
+    const bool have = lane < sp.nedge;
+    const T v = have ? sp.W[edge_index(sp, lane)] : T(0);
+    T s_part = 0, aa = 0, bA = 0, ab = 0, bB = 0;
+    pass0_one<T, CLASSIFY, BRACKET>(v, have, ba, bb, s_part, aa, bA, ab, bB, acc);
+    acc.sum += (double)s_part;
     if (BRACKET) {
-      acc.cle_a += popc(ballot(have && v <= ba));
-      acc.clt_b += popc(ballot(have && v < bb));
-      acc.Aa += (fin && v > ba) ? (double)(v - ba) : 0.0;
-      acc.Ba += (fin && v < ba) ? (double)(ba - v) : 0.0;
-      acc.Ab += (fin && v > bb) ? (double)(v - bb) : 0.0;
-      acc.Bb += (fin && v < bb) ? (double)(bb - v) : 0.0;
+      acc.Aa += (double)aa;
+      acc.Ba += (double)bA;
+      acc.Ab += (double)ab;
+      acc.Bb += (double)bB;
+    }
+  }
+}
+
+// Gather from the whole input: every element inside (yL, yR) goes to the gather buffer.
+// Offsets come from one atomic per wavefront-step that holds any such element (the
+// bracket holds few elements when this runs).
+template <typename T, int BLOCK, int U>
+__device__ inline void gather_from_input(const Walk<T> &wk, T yL, T yR, T *zf,
+                                               uint64_t *gcur, int64_t &written) {
+  constexpr int V = Traits<T>::kVec;
+  using Vec = typename Traits<T>::Vec;
+  const int tid = threadIdx.x, lane = tid % kWave;
+  const Span<T> &sp = wk.sp;
+  const int64_t step_vecs = (int64_t)BLOCK * U;
+  for (int64_t base = (int64_t)blockIdx.x * step_vecs; base < sp.nvec;
+       base += (int64_t)gridDim.x * step_vecs) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t vi = base + (int64_t)u * BLOCK + tid;
+      const bool valid = vi < sp.nvec;
+      Vec raw;
+      if (valid) raw = sp.V[vi];
+      T e[V];
+      vec_to_arr<T>(raw, e);
+      uint32_t cnt = 0;
+#pragma unroll
+      for (int j = 0; j < V; ++j) cnt += popc(ballot(valid && e[j] > yL && e[j] < yR));
+      if (cnt == 0) continue;
+      uint64_t off = 0;
+      if (lane == 0) off = atomic_add_relaxed(gcur, cnt);
+      off = __shfl(off, 0);
+      written += cnt;
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        const bool in = valid && e[j] > yL && e[j] < yR;
+        const uint64_t m = ballot(in);
+        if (in) zf[off + lane_rank(m)] = e[j];
+        off += popc(m);
+      }
+    }
+  }
+  if (sp.nedge > 0 && wk.edge_owner && tid < kWave) {
+    const bool have = lane < sp.nedge;
+    const T v = have ? sp.W[edge_index(sp, lane)] : T(0);
+    const bool in = have && v > yL && v < yR;
+    const uint64_t m = ballot(in);
+    if (m) {
+      uint64_t off = 0;
+      if (lane == 0) off = atomic_add_relaxed(gcur, (uint64_t)popc(m));
+      off = __shfl(off, 0);
+      if (in) zf[off + lane_rank(m)] = v;
+      written += popc(m);
     }
   }
 }
@@ -470,240 +451,332 @@ __device__ inline void write_result(const SelectArgs<T> &a, const CpState &s) {
   }
 }
 
+// Arrive at the end of a pass.  Workgroups arrive in groups of kGroup on their own
+// counter; the last of a group arrives at the top counter.  Returns true in exactly one
+// workgroup (the last to arrive overall), which then sees every partial written before
+// the arrivals.  Called by thread 0 only.
+__device__ inline bool arrive(SyncCtl *sync, int bid, int G) {
+  const int g = bid / kGroup;
+  const int ng = (G + kGroup - 1) / kGroup;
+  const int gsz = (g + 1) * kGroup <= G ? kGroup : G - g * kGroup;
+  const uint32_t p = atomic_add_release(&sync->grp[g][0], 1u);
+  if (p != (uint32_t)(gsz - 1)) return false;
+  fence_acquire();
+  store_relaxed(&sync->grp[g][0], 0u);
+  const uint32_t q = atomic_add_release(&sync->top, 1u);
+  if (q != (uint32_t)(ng - 1)) return false;
+  fence_acquire();
+  store_relaxed(&sync->top, 0u);
+  return true;
+}
+
+// One pass by this workgroup; leaves the workgroup's partial in thread 0's dv / iv.
 template <typename T, int BLOCK, int UNROLL>
-__global__ __launch_bounds__(BLOCK) void cp_select_kernel(SelectArgs<T> a) {
-  __shared__ Shared<T, BLOCK, UNROLL> sh;
+__device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, int phase,
+                                      bool p0_slow, double (&dv)[8], int64_t (&iv)[8]) {
+  // passes that also write or check a bracket hold fewer vectors in flight
+  constexpr int SU = UNROLL / 2 > 0 ? UNROLL / 2 : 1;
+  constexpr int WPB = BLOCK / kWave;
+  const int tid = threadIdx.x, wv = tid / kWave, lane = tid % kWave;
+  const int bid = blockIdx.x;
+  int dop[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  Walk<T> wk;
+  if (phase == PH_PASS0) {
+    const bool use_br = a.cfg.use_bracket != 0;
+    const T ba = (T)a.cfg.bracket_lo, bb = (T)a.cfg.bracket_hi;
+    wk.sp = make_span(a.x, a.n);
+    wk.wave_mode = false;
+    wk.edge_owner = bid == 0;
+    P0Acc<T> acc;
+    acc.sum = 0;
+    acc.mn = t_inf<T>();
+    acc.mx = -t_inf<T>();
+    acc.cmn = acc.cmx = 0;
+    acc.nnan = acc.nneg = acc.npos = acc.cle_a = acc.clt_b = 0;
+    acc.Aa = acc.Ba = acc.Ab = acc.Bb = 0;
+    if (!p0_slow) {
+      if (use_br) pass0<T, BLOCK, SU, false, true>(wk, ba, bb, acc);
+      else pass0<T, BLOCK, UNROLL, false, false>(wk, ba, bb, acc);
+    } else {
+      if (use_br) pass0<T, BLOCK, SU, true, true>(wk, ba, bb, acc);
+      else pass0<T, BLOCK, SU, true, false>(wk, ba, bb, acc);
+    }
+    double mn = (double)acc.mn, mx = (double)acc.mx;
+    int64_t cmn = acc.cmn, cmx = acc.cmx;
+    block_pair_fold<BLOCK>(mn, cmn, mx, cmx, sh.d, sh.i);
+    dv[0] = acc.sum; dv[1] = acc.Aa; dv[2] = acc.Ba; dv[3] = acc.Ab; dv[4] = acc.Bb;
+    dv[5] = dv[6] = dv[7] = 0;
+    iv[0] = (int64_t)acc.nnan; iv[1] = (int64_t)acc.nneg; iv[2] = (int64_t)acc.npos;
+    iv[3] = (int64_t)acc.cle_a; iv[4] = (int64_t)acc.clt_b;
+    iv[5] = iv[6] = iv[7] = 0;
+    block_reduce<BLOCK, 5, 5>(dv, dop, iv, true, sh.d, sh.i);
+    if (tid == 0) {
+      dv[5] = mn; dv[6] = mx; iv[5] = cmn; iv[6] = cmx;
+    }
+    return;
+  }
+  const CpState &s = sh.st;
+  const T t = (T)s.t, yL = (T)s.yL, yR = (T)s.yR, fmn = (T)s.fmin, fmx = (T)s.fmax;
+  const int64_t Rw = a.seg_R;  // elements per wavefront region of a split buffer
+  if (s.wbuf < 0) {
+    wk.sp = make_span(a.x, a.n);
+    wk.wave_mode = false;
+    wk.edge_owner = bid == 0;
+  } else {
+    // this wavefront's segment of its region in split buffer wbuf
+    const T *region = a.z[s.wbuf] + ((int64_t)bid * WPB + wv) * Rw;
+    const int64_t len = sh.wseg[s.side][wv];
+    wk.sp = make_span(s.side == 0 ? region : region + (Rw - len), len);
+    wk.wave_mode = true;
+    wk.edge_owner = true;
+  }
+  EvalAcc<T> acc;
+  acc.A = acc.B = 0;
+  acc.pred = -t_inf<T>();
+  acc.succ = t_inf<T>();
+  acc.L = acc.G = 0;
+  int64_t written = 0;
+  if (s.phase == PH_GATHER) {
+    if (s.wbuf < 0) {
+      gather_from_input<T, BLOCK, SU>(wk, yL, yR, a.zf, &a.sync->gcur, written);
+    } else {
+      // every element of a segment lies inside the bracket: one offset per workgroup
+      const int64_t len = wk.sp.m;
+      if (lane == 0) sh.gbase[wv] = (uint64_t)len;
+      __syncthreads();
+      if (tid == 0) {
+        uint64_t tot = 0;
+        for (int w = 0; w < WPB; ++w) {
+          const uint64_t l = sh.gbase[w];
+          sh.gbase[w] = tot;
+          tot += l;
+        }
+        const uint64_t base = tot ? atomic_add_relaxed(&a.sync->gcur, tot) : 0;
+        for (int w = 0; w < WPB; ++w) sh.gbase[w] += base;
+      }
+      __syncthreads();
+      const uint64_t off = sh.gbase[wv];
+      for (int64_t i = lane; i < len; i += kWave) a.zf[off + i] = wk.sp.W[i];
+      if (lane == 0) written = len;
+    }
+  } else {
+    WaveOut<T> o;
+    o.region = a.z[s.zout] + ((int64_t)bid * WPB + wv) * Rw;
+    o.Rw = Rw;
+    o.lo = o.hi = 0;
+    const bool clamp = s.has_inf && s.wbuf < 0;
+    if (!s.split) {
+      if (clamp) eval_pass<T, BLOCK, SU, true, false, false>(wk, t, yL, yR, fmn, fmx, o, acc);
+      else eval_pass<T, BLOCK, UNROLL, false, false, false>(wk, t, yL, yR, fmn, fmx, o, acc);
+    } else if (s.filter) {
+      eval_pass<T, BLOCK, SU, false, true, true>(wk, t, yL, yR, fmn, fmx, o, acc);
+    } else {
+      eval_pass<T, BLOCK, SU, false, true, false>(wk, t, yL, yR, fmn, fmx, o, acc);
+    }
+    if (s.split && lane == 0) {
+      sh.wseg[0][wv] = o.lo;
+      sh.wseg[1][wv] = o.hi;
+      written = o.lo + o.hi;
+    }
+  }
+  dv[0] = acc.A; dv[1] = acc.B; dv[2] = (double)acc.pred; dv[3] = (double)acc.succ;
+  dop[2] = 2; dop[3] = 1;
+  dv[4] = dv[5] = dv[6] = dv[7] = 0;
+  iv[0] = (int64_t)acc.L; iv[1] = (int64_t)acc.G;
+  iv[2] = lane == 0 ? written : 0;  // per wavefront, counted once
+  iv[3] = iv[4] = iv[5] = iv[6] = iv[7] = 0;
+  block_reduce<BLOCK, 4, 3>(dv, dop, iv, true, sh.d, sh.i);
+}
+
+// The last workgroup to arrive: reduce every workgroup's partial in a fixed order, advance
+// the cutting-plane state, run the exact select when the bracket is small, and write the
+// new state to global memory (the caller then releases it).
+template <typename T, int BLOCK>
+__device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, int phase,
+                                         bool p0_slow) {
   const int tid = threadIdx.x;
+  const int G = gridDim.x;
+  const int64_t stride = a.slot_stride;
+  const uint64_t t_arrive = wall_clock64();
+  int pidx = 0;  // index of the pass that just ended
+  double rd[8];
+  int64_t ri[8];
+  int rop[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (phase == PH_PASS0) {
+    for (int f = 0; f < 8; ++f) { rd[f] = 0; ri[f] = 0; }
+    for (int b = tid; b < G; b += BLOCK) {
+      for (int f = 0; f < 5; ++f) rd[f] += a.sd[f * stride + b];
+      for (int f = 0; f < 5; ++f) ri[f] += a.si[f * stride + b];
+    }
+    block_reduce<BLOCK, 5, 5>(rd, rop, ri, false, sh.d, sh.i);
+    // (min, count) and (max, count) pairs: strided fold per thread, then a fixed tree
+    double mn = __builtin_inf(), mx = -__builtin_inf();
+    int64_t cmn = 0, cmx = 0;
+    for (int b = tid; b < G; b += BLOCK) {
+      const double m2 = a.sd[5 * stride + b], x2 = a.sd[6 * stride + b];
+      const int64_t c2 = a.si[5 * stride + b], d2 = a.si[6 * stride + b];
+      if (m2 < mn) { mn = m2; cmn = c2; } else if (m2 == mn) cmn += c2;
+      if (x2 > mx) { mx = x2; cmx = d2; } else if (x2 == mx) cmx += d2;
+    }
+    block_pair_fold<BLOCK>(mn, cmn, mx, cmx, sh.d, sh.i);
+    if (tid == 0) {
+      Pass0Result r;
+      r.classified = p0_slow ? 1 : 0;
+      r.sum = rd[0]; r.A_a = rd[1]; r.B_a = rd[2]; r.A_b = rd[3]; r.B_b = rd[4];
+      r.nnan = ri[0]; r.nneg = ri[1]; r.npos = ri[2]; r.c_le_a = ri[3]; r.c_lt_b = ri[4];
+      r.fmin = mn; r.fmax = mx; r.cmin = cmn; r.cmax = cmx;
+      CpState &s = sh.st;
+      if (!p0_slow) {
+        s = CpState{};
+        s.n = a.n;
+        s.k = a.k;
+      }
+      pidx = s.work_passes;
+      s.phase = PH_PASS0;
+      dev_after_pass0(s, r, a.cfg);
+      if (a.stats && pidx < CPS_STATS_MAX_PASSES) {
+        a.stats->population[pidx] = s.phase == PH_DONE ? 0 : s.cR - s.cL;
+        a.stats->working[pidx] = a.n;
+      }
+    }
+  } else {
+    rop[2] = 2; rop[3] = 1;
+    for (int f = 0; f < 8; ++f) { rd[f] = 0; ri[f] = 0; }
+    rd[2] = -__builtin_inf();
+    rd[3] = __builtin_inf();
+    for (int b = tid; b < G; b += BLOCK) {
+      rd[0] += a.sd[0 * stride + b];
+      rd[1] += a.sd[1 * stride + b];
+      rd[2] = fmax(rd[2], a.sd[2 * stride + b]);
+      rd[3] = fmin(rd[3], a.sd[3 * stride + b]);
+      ri[0] += a.si[0 * stride + b];
+      ri[1] += a.si[1 * stride + b];
+      ri[2] += a.si[2 * stride + b];
+    }
+    block_reduce<BLOCK, 4, 3>(rd, rop, ri, false, sh.d, sh.i);
+    if (tid == 0) {
+      CpState &s = sh.st;
+      pidx = s.work_passes;
+      const int64_t wl = s.wlen;
+      if (s.phase == PH_GATHER) {
+        dev_after_gather(s, ri[2]);
+      } else {
+        EvalResult r;
+        r.A = rd[0]; r.B = rd[1]; r.pred = rd[2]; r.succ = rd[3];
+        r.L = ri[0]; r.G = ri[1]; r.written = ri[2];
+        dev_after_eval(s, r, a.cfg);
+      }
+      if (a.stats && pidx < CPS_STATS_MAX_PASSES) {
+        a.stats->population[pidx] = s.phase == PH_DONE ? 0 : s.cR - s.cL;
+        a.stats->working[pidx] = wl;
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == 0 && a.stats && pidx < CPS_STATS_MAX_PASSES) {
+    a.stats->t_arrive[pidx] = t_arrive;
+    a.stats->t_publish[pidx] = wall_clock64();
+  }
+  // ---- exact finish in this workgroup when the bracket is small
+  if (sh.st.phase == PH_FINAL) {
+    const CpState &s = sh.st;
+    const T *W = s.wbuf < 0 ? a.x : a.zf;
+    typename Traits<T>::Key key;
+    int64_t below, eq;
+    block_radix_select<T, BLOCK>(W, s.wlen, !s.on_bracket, (T)s.yL, (T)s.yR, s.k - s.cL,
+                                 sh.hist, sh.misc, key, below, eq);
+    if (tid == 0) {
+      CpState &w = sh.st;
+      const int fi = w.work_passes;
+      const int64_t wl = w.wlen;
+      dev_after_final(w, (double)Traits<T>::unkey(key), below, eq);
+      if (a.stats && fi < CPS_STATS_MAX_PASSES) {
+        a.stats->population[fi] = 0;
+        a.stats->working[fi] = wl;
+        a.stats->t_arrive[fi] = wall_clock64();
+        a.stats->t_publish[fi] = a.stats->t_arrive[fi];
+      }
+    }
+    __syncthreads();
+  }
+  // write the new state: every thread copies words; the waits before the workgroup
+  // barrier that follows make the stores complete, and thread 0's release covers them
+  constexpr int NW = sizeof(CpState) / 8;
+  for (int w = tid; w < NW; w += BLOCK)
+    reinterpret_cast<uint64_t *>(a.st)[w] = reinterpret_cast<const uint64_t *>(&sh.st)[w];
+  if (tid == 0) {
+    const CpState &s = sh.st;
+    if (s.phase == PH_DONE) write_result<T>(a, s);
+    if (s.phase == PH_GATHER) a.sync->gcur = 0;
+  }
+}
+
+template <typename T, int BLOCK, int UNROLL>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_num_vgpr(128))) void cp_select_kernel(SelectArgs<T> a) {
+  __shared__ Shared<T, BLOCK> sh;
+  const int tid = threadIdx.x, wv = tid / kWave, lane = tid % kWave;
   const int G = gridDim.x, bid = blockIdx.x;
   uint32_t gen = 0;
   if (tid == 0) {
-    gen = load_acquire(&a.sync->gen);
+    gen = load_relaxed(&a.sync->gen);
     if (bid == 0) {
       // a pending record; overwritten on completion, left in place if a wait times out
       cps_result r = {};
       r.status = ST_TIMEOUT;
       *a.out = r;
+      if (a.stats) a.stats->t_start = wall_clock64();
     }
   }
-  const bool use_br = a.cfg.use_bracket != 0;
-  const T ba = (T)a.cfg.bracket_lo, bb = (T)a.cfg.bracket_hi;
+  if (lane == 0) sh.wseg[0][wv] = sh.wseg[1][wv] = 0;
   int phase = PH_PASS0;
+  bool p0_slow = false;
   for (;;) {
     double dv[8];
     int64_t iv[8];
-    int dop[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (phase == PH_PASS0) {
-      const Span<T> sp = make_span(a.x, a.n);
-      P0Acc<T> acc;
-      acc.sum = 0;
-      acc.mn = t_inf<T>();
-      acc.mx = -t_inf<T>();
-      acc.cmn = acc.cmx = 0;
-      acc.nnan = acc.nneg = acc.npos = acc.cle_a = acc.clt_b = 0;
-      acc.Aa = acc.Ba = acc.Ab = acc.Bb = 0;
-      if (use_br) pass0<T, BLOCK, UNROLL, true>(sp, ba, bb, acc);
-      else pass0<T, BLOCK, UNROLL, false>(sp, ba, bb, acc);
-      wave_pair_min<T, BLOCK>(acc.mn, acc.cmn);
-      wave_pair_max<T, BLOCK>(acc.mx, acc.cmx);
-      // fold the (min, count) pairs across waves through LDS
-      const int wv = tid / kWave, lane = tid % kWave;
-      if (lane == 0) {
-        sh.d[0][wv] = (double)acc.mn;
-        sh.i[0][wv] = acc.cmn;
-        sh.d[1][wv] = (double)acc.mx;
-        sh.i[1][wv] = acc.cmx;
-      }
-      __syncthreads();
-      double mn = 0, mx = 0;
-      int64_t cmn = 0, cmx = 0;
-      if (tid == 0) {
-        mn = sh.d[0][0]; cmn = sh.i[0][0]; mx = sh.d[1][0]; cmx = sh.i[1][0];
-        for (int w = 1; w < BLOCK / kWave; ++w) {
-          if (sh.d[0][w] < mn) { mn = sh.d[0][w]; cmn = sh.i[0][w]; }
-          else if (sh.d[0][w] == mn) cmn += sh.i[0][w];
-          if (sh.d[1][w] > mx) { mx = sh.d[1][w]; cmx = sh.i[1][w]; }
-          else if (sh.d[1][w] == mx) cmx += sh.i[1][w];
-        }
-      }
-      __syncthreads();
-      dv[0] = acc.sum; dv[1] = acc.Aa; dv[2] = acc.Ba; dv[3] = acc.Ab; dv[4] = acc.Bb;
-      dv[5] = dv[6] = dv[7] = 0;
-      iv[0] = (int64_t)acc.nnan; iv[1] = (int64_t)acc.nneg; iv[2] = (int64_t)acc.npos;
-      iv[3] = (int64_t)acc.cle_a; iv[4] = (int64_t)acc.clt_b;
-      iv[5] = iv[6] = iv[7] = 0;
-      block_reduce<BLOCK, 5, 5>(dv, dop, iv, true, sh.d, sh.i);
-      if (tid == 0) {
-        dv[5] = mn; dv[6] = mx; iv[5] = cmn; iv[6] = cmx;
-      }
-    } else {
-      const CpState &s = sh.st;
-      const T t = (T)s.t, yL = (T)s.yL, yR = (T)s.yR, fmn = (T)s.fmin, fmx = (T)s.fmax;
-      const T *W = s.wbuf < 0 ? a.x : (a.z[s.wbuf] + s.woff);
-      const Span<T> sp = make_span(W, s.wlen);
-      T *zout = a.z[s.zout];
-      EvalAcc<T> acc;
-      acc.A = acc.B = 0;
-      acc.pred = -t_inf<T>();
-      acc.succ = t_inf<T>();
-      acc.L = acc.G = 0;
-      int64_t written = 0;
-      const bool clamp = s.has_inf && s.wbuf < 0;
-      if (!s.split) {
-        if (clamp) eval_pass<T, BLOCK, UNROLL, true, false, false>(sp, t, yL, yR, fmn, fmx, zout, a.cfg.zcap, a.sync, sh, acc, written);
-        else eval_pass<T, BLOCK, UNROLL, false, false, false>(sp, t, yL, yR, fmn, fmx, zout, a.cfg.zcap, a.sync, sh, acc, written);
-      } else if (s.filter) {
-        if (clamp) eval_pass<T, BLOCK, UNROLL, true, true, true>(sp, t, yL, yR, fmn, fmx, zout, a.cfg.zcap, a.sync, sh, acc, written);
-        else eval_pass<T, BLOCK, UNROLL, false, true, true>(sp, t, yL, yR, fmn, fmx, zout, a.cfg.zcap, a.sync, sh, acc, written);
-      } else {
-        eval_pass<T, BLOCK, UNROLL, false, true, false>(sp, t, yL, yR, fmn, fmx, zout, a.cfg.zcap, a.sync, sh, acc, written);
-      }
-      dv[0] = acc.A; dv[1] = acc.B; dv[2] = (double)acc.pred; dv[3] = (double)acc.succ;
-      dop[2] = 2; dop[3] = 1;
-      dv[4] = dv[5] = dv[6] = dv[7] = 0;
-      iv[0] = (int64_t)acc.L; iv[1] = (int64_t)acc.G;
-      iv[2] = iv[3] = iv[4] = iv[5] = iv[6] = iv[7] = 0;
-      block_reduce<BLOCK, 4, 2>(dv, dop, iv, true, sh.d, sh.i);
-      if (tid == 0) iv[2] = written;  // thread 0 counted the block's writes
-    }
-
+    run_pass<T, BLOCK, UNROLL>(a, sh, phase, p0_slow, dv, iv);
     // ---- publish this workgroup's partial and arrive
-    const int64_t stride = a.slot_stride;
     if (tid == 0) {
+      const int64_t stride = a.slot_stride;
 #pragma unroll
       for (int f = 0; f < 8; ++f) {
         a.sd[f * stride + bid] = dv[f];
         a.si[f * stride + bid] = iv[f];
       }
-      const uint32_t prev = atomic_add_acq_rel(&a.sync->arrive, 1u);
-      sh.last = (prev == (uint32_t)(G - 1));
+      sh.last = arrive(a.sync, bid, G) ? 1 : 0;  // the last arrival has acquired already
     }
     __syncthreads();
-
     if (sh.last) {
-      fence_acquire();
-      // ---- reduce every workgroup's partial in a fixed order
-      double rd[8];
-      int64_t ri[8];
-      int rop[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      if (phase == PH_PASS0) {
-        for (int f = 0; f < 8; ++f) { rd[f] = 0; ri[f] = 0; }
-        for (int b = tid; b < G; b += BLOCK) {
-          for (int f = 0; f < 5; ++f) rd[f] += a.sd[f * stride + b];
-          for (int f = 0; f < 5; ++f) ri[f] += a.si[f * stride + b];
-        }
-        block_reduce<BLOCK, 5, 5>(rd, rop, ri, false, sh.d, sh.i);
-        // (min, count) and (max, count) pairs: strided fold per thread, then a fixed tree
-        double mn = __builtin_inf(), mx = -__builtin_inf();
-        int64_t cmn = 0, cmx = 0;
-        for (int b = tid; b < G; b += BLOCK) {
-          const double m2 = a.sd[5 * stride + b], x2 = a.sd[6 * stride + b];
-          const int64_t c2 = a.si[5 * stride + b], d2 = a.si[6 * stride + b];
-          if (m2 < mn) { mn = m2; cmn = c2; } else if (m2 == mn) cmn += c2;
-          if (x2 > mx) { mx = x2; cmx = d2; } else if (x2 == mx) cmx += d2;
-        }
-        block_pair_fold<BLOCK>(mn, cmn, mx, cmx, sh.d, sh.i);
-        if (tid == 0) {
-          Pass0Result r;
-          r.sum = rd[0]; r.A_a = rd[1]; r.B_a = rd[2]; r.A_b = rd[3]; r.B_b = rd[4];
-          r.nnan = ri[0]; r.nneg = ri[1]; r.npos = ri[2]; r.c_le_a = ri[3]; r.c_lt_b = ri[4];
-          r.fmin = mn; r.fmax = mx; r.cmin = cmn; r.cmax = cmx;
-          CpState &s = sh.st;
-          s = CpState{};
-          s.n = a.n;
-          s.k = a.k;
-          s.phase = PH_PASS0;
-          dev_after_pass0(s, r, a.cfg);
-          if (a.stats) {
-            a.stats->population[0] = s.cR - s.cL;
-            a.stats->working[0] = a.n;
-          }
-        }
-      } else {
-        rop[2] = 2; rop[3] = 1;
-        for (int f = 0; f < 8; ++f) { rd[f] = 0; ri[f] = 0; }
-        rd[2] = -__builtin_inf();
-        rd[3] = __builtin_inf();
-        for (int b = tid; b < G; b += BLOCK) {
-          rd[0] += a.sd[0 * stride + b];
-          rd[1] += a.sd[1 * stride + b];
-          rd[2] = fmax(rd[2], a.sd[2 * stride + b]);
-          rd[3] = fmin(rd[3], a.sd[3 * stride + b]);
-          ri[0] += a.si[0 * stride + b];
-          ri[1] += a.si[1 * stride + b];
-          ri[2] += a.si[2 * stride + b];
-        }
-        block_reduce<BLOCK, 4, 3>(rd, rop, ri, false, sh.d, sh.i);
-        if (tid == 0) {
-          EvalResult r;
-          r.A = rd[0]; r.B = rd[1]; r.pred = rd[2]; r.succ = rd[3];
-          r.L = ri[0]; r.G = ri[1]; r.written = ri[2];
-          CpState &s = sh.st;
-          const int64_t wl = s.wlen;
-          dev_after_eval(s, r, a.cfg);
-          const int p = s.work_passes - 1;
-          if (a.stats && p < CPS_STATS_MAX_PASSES) {
-            a.stats->population[p] = s.phase == PH_DONE ? 0 : s.cR - s.cL;
-            a.stats->working[p] = wl;
-          }
-        }
-      }
-      __syncthreads();
-      // ---- exact finish in this workgroup when the bracket is small
-      if (sh.st.phase == PH_FINAL) {
-        const CpState &s = sh.st;
-        const T *W = s.wbuf < 0 ? a.x : (a.z[s.wbuf] + s.woff);
-        typename Traits<T>::Key key;
-        int64_t below, eq;
-        block_radix_select<T, BLOCK>(W, s.wlen, !s.on_bracket, (T)s.yL, (T)s.yR, s.k - s.cL,
-                                     sh.hist, sh.misc, key, below, eq);
-        if (tid == 0) {
-          CpState &w = sh.st;
-          w.work_passes++;
-          w.elements_read += w.wlen;
-          if (w.wbuf < 0) w.passes++;
-          cp_finish(w, (double)Traits<T>::unkey(key), w.cL + below, eq);
-        }
-        __syncthreads();
-      }
-      // publish the new state: every thread copies words, each wave releases its stores
-      constexpr int NW = sizeof(CpState) / 8;
-      for (int w = tid; w < NW; w += BLOCK)
-        reinterpret_cast<uint64_t *>(a.st)[w] = reinterpret_cast<const uint64_t *>(&sh.st)[w];
-      if (tid == 0) {
-        const CpState &s = sh.st;
-        if (s.phase == PH_DONE) write_result<T>(a, s);
-        if (s.split) {
-          a.sync->curL = 0;
-          a.sync->curR = 0;
-        }
-      }
-      fence_release();
+      last_update<T, BLOCK>(a, sh, phase, p0_slow);
       __syncthreads();
       if (tid == 0) {
-        store_relaxed(&a.sync->arrive, 0u);
         store_release(&a.sync->gen, gen + 1u);
         gen = gen + 1u;
       }
     } else {
       if (tid == 0) {
+        // poll without acquire semantics (an acquire per poll would invalidate this XCD's
+        // L2 under the workgroups still streaming); acquire once the flag has moved
         int64_t spins = 0;
         bool timed_out = false;
-        while (load_acquire(&a.sync->gen) == gen) {
+        while (load_relaxed(&a.sync->gen) == gen) {
           __builtin_amdgcn_s_sleep(2);
           if (++spins > a.spin_limit) { timed_out = true; break; }
         }
-        sh.misc[7] = timed_out ? 1 : 0;
-        if (!timed_out) gen = gen + 1u;
+        sh.timed_out = timed_out ? 1 : 0;
+        if (!timed_out) {
+          gen = gen + 1u;
+          fence_acquire();
+        }
       }
       __syncthreads();
-      if (sh.misc[7]) {
+      if (sh.timed_out) {
         if (tid == 0) {
           sh.st.phase = PH_DONE;
           sh.st.status = ST_TIMEOUT;
         }
       } else {
-        // read the state the last workgroup published
-        fence_acquire();
+        // read the state the last workgroup published (thread 0's acquire above
+        // invalidated this CU's and this XCD's caches before the workgroup barrier)
         constexpr int NW = sizeof(CpState) / 8;
         for (int w = tid; w < NW; w += BLOCK)
           reinterpret_cast<uint64_t *>(&sh.st)[w] = reinterpret_cast<const uint64_t *>(a.st)[w];
@@ -711,6 +784,7 @@ __global__ __launch_bounds__(BLOCK) void cp_select_kernel(SelectArgs<T> a) {
     }
     __syncthreads();
     phase = sh.st.phase;
+    p0_slow = sh.st.p0_slow != 0;
     if (phase == PH_DONE) break;
   }
 }

@@ -36,48 +36,80 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
   c.use_bracket = use_bracket;
   c.bracket_lo = blo;
   c.bracket_hi = bhi;
-  std::vector<T> z[2] = {std::vector<T>(zcap), std::vector<T>(zcap)};
+  // one workgroup: a single region per split buffer, as large as the input
+  const int64_t R = n + 8;
+  std::vector<T> z[2] = {std::vector<T>(R), std::vector<T>(R)};
+  std::vector<T> zf(zcap);
+  int64_t my_l = 0, my_r = 0;  // this "workgroup's" split counts
 
-  // pass 0
-  Pass0Result r{};
-  r.fmin = INFINITY;
-  r.fmax = -INFINITY;
-  const T ba = (T)blo, bb = (T)bhi;
-  for (int64_t i = 0; i < n; i++) {
-    const T v = x[i];
-    if (std::isnan(v)) { r.nnan++; continue; }
-    if (v == (T)-INFINITY) r.nneg++;
-    else if (v == (T)INFINITY) r.npos++;
-    else {
-      if (v < r.fmin) { r.fmin = v; r.cmin = 1; } else if (v == r.fmin) r.cmin++;
-      if (v > r.fmax) { r.fmax = v; r.cmax = 1; } else if (v == r.fmax) r.cmax++;
-      r.sum += v;
-      if (use_bracket) {
-        if (v > ba) r.A_a += (double)(v - ba);
-        if (v < ba) r.B_a += (double)(ba - v);
-        if (v > bb) r.A_b += (double)(v - bb);
-        if (v < bb) r.B_b += (double)(bb - v);
-      }
-    }
-    if (use_bracket) {
-      if (v <= ba) r.c_le_a++;
-      if (v < bb) r.c_lt_b++;
-    }
-  }
   CpState s{};
   s.n = n;
   s.k = k;
-  cp_after_pass0(s, r, c);
-  while (s.phase == PH_EVAL) {
-    const T *W = s.wbuf < 0 ? x : z[s.wbuf].data() + s.woff;
+  const T ba = (T)blo, bb = (T)bhi;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    // pass 0: first without classifying infinities (as the GPU's fast pass), then, if
+    // the state asks for it, with the classification
+    const bool classify = attempt == 1;
+    Pass0Result r{};
+    r.classified = classify ? 1 : 0;
+    r.fmin = INFINITY;
+    r.fmax = -INFINITY;
+    for (int64_t i = 0; i < n; i++) {
+      const T v = x[i];
+      if (std::isnan(v)) { r.nnan++; continue; }
+      const bool fin = !classify || std::isfinite(v);
+      if (classify && v == (T)-INFINITY) r.nneg++;
+      else if (classify && v == (T)INFINITY) r.npos++;
+      if (fin) {
+        if (v < r.fmin) { r.fmin = v; r.cmin = 1; } else if (v == r.fmin) r.cmin++;
+        if (v > r.fmax) { r.fmax = v; r.cmax = 1; } else if (v == r.fmax) r.cmax++;
+        r.sum += v;
+        if (use_bracket) {
+          if (v > ba) r.A_a += (double)(v - ba);
+          if (v < ba) r.B_a += (double)(ba - v);
+          if (v > bb) r.A_b += (double)(v - bb);
+          if (v < bb) r.B_b += (double)(bb - v);
+        }
+      }
+      if (use_bracket) {
+        if (v <= ba) r.c_le_a++;
+        if (v < bb) r.c_lt_b++;
+      }
+    }
+    cp_after_pass0(s, r, c);
+    if (!(s.phase == PH_PASS0 && s.p0_slow)) break;
+  }
+  if (s.phase == PH_PASS0) return -15;
+  auto working = [&](int64_t &len) -> const T * {
+    if (s.wbuf < 0) { len = s.wlen; return x; }
+    if (s.wbuf == 2) { len = s.wlen; return zf.data(); }
+    if (s.side == 0) { len = my_l; return z[s.wbuf].data(); }
+    len = my_r;
+    return z[s.wbuf].data() + (R - my_r);
+  };
+  while (s.phase == PH_EVAL || s.phase == PH_GATHER) {
+    int64_t wl = 0;
+    const T *W = working(wl);
+    if (s.wbuf >= 0 && s.wbuf < 2 && wl != s.wlen) return -13;
     const T t = (T)s.t, yL = (T)s.yL, yR = (T)s.yR;
+    if (s.phase == PH_GATHER) {
+      int64_t g = 0;
+      for (int64_t i = 0; i < wl; i++) {
+        const T v = W[i];
+        if (s.filter && !(v > yL && v < yR)) continue;
+        if (g >= zcap) return -14;
+        zf[g++] = v;
+      }
+      cp_after_gather(s, g);
+      continue;
+    }
     const bool clamp = s.has_inf && s.wbuf < 0;
     EvalResult e{};
     e.pred = -INFINITY;
     e.succ = INFINITY;
     int64_t nl = 0, nr = 0;
     T *zo = z[s.zout].data();
-    for (int64_t i = 0; i < s.wlen; i++) {
+    for (int64_t i = 0; i < wl; i++) {
       T v = W[i];
       if (clamp) v = std::min(std::max(v, (T)s.fmin), (T)s.fmax);
       if (v < t) { e.L++; e.B += (double)(t - v); e.pred = std::max<double>(e.pred, v); }
@@ -85,17 +117,18 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
       if (s.split) {
         const bool inb = !s.filter || (v > yL && v < yR);
         if (inb && v < t) zo[nl++] = v;
-        if (inb && v > t) zo[zcap - 1 - nr++] = v;
+        if (inb && v > t) zo[R - 1 - nr++] = v;
       }
     }
     e.written = nl + nr;
-    if (nl + nr > zcap) return -10;
+    if (s.split) { my_l = nl; my_r = nr; }
     cp_after_eval(s, e, c);
   }
   if (s.phase == PH_FINAL) {
-    const T *W = s.wbuf < 0 ? x : z[s.wbuf].data() + s.woff;
+    int64_t wl = 0;
+    const T *W = working(wl);
     std::vector<T> cand;
-    for (int64_t i = 0; i < s.wlen; i++) {
+    for (int64_t i = 0; i < wl; i++) {
       const T v = W[i];
       if (s.on_bracket || (v > (T)s.yL && v < (T)s.yR)) cand.push_back(v);
     }
@@ -105,10 +138,7 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
     const T v = cand[rr - 1];
     int64_t below = 0, eq = 0;
     for (T c2 : cand) { if (c2 < v) below++; else if (c2 == v) eq++; }
-    s.work_passes++;
-    s.elements_read += s.wlen;
-    if (s.wbuf < 0) s.passes++;
-    cp_finish(s, (double)v, s.cL + below, eq);
+    cp_after_final(s, (double)v, below, eq);
   }
   if (s.phase != PH_DONE) return -12;
   out->value = (double)((T)s.value + (T)0);
