@@ -1,0 +1,214 @@
+"""Benchmark: exact k-th element selection on one MI355X.
+
+Workload (one "step"): every single-array case of the full-scale selection sweep,
+    n in {2^24, 2^28} x {float32, float64}
+      x {uniform[0,1), N(0,1), Cauchy(0,1), N(0,1) quantised to 1024 levels}
+      x k in {1, floor(n/100), floor((n+1)/2), n-1},
+i.e. 64 calls of select_kth on inputs already resident in HBM, enqueued
+back to back on one stream.  The metric is exact-selection elements/s
+(sum of n over the step's calls / step time); the JSON line also carries the
+HBM roofline of the selection kernel and the CPU oracle timed on a bounded
+sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+SIZES = (24, 28)
+DTYPES = (np.float32, np.float64)
+DISTS = ("uniform", "normal", "cauchy", "quantized_normal")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cp_select_kernel_traffic.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1104_2732_amd", "csrc")
+    for fn in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, fn), "rb") as f:
+            h.update(fn.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if still current."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(budget_s: float = 20.0):
+    """The CPU oracle on a bounded sample of the same workload, one thread, ~budget_s seconds:
+    the 32 n=2^24 cases, then n=2^28 float32 cases while the budget lasts."""
+    import oracle
+    import workloads
+    elems = 0
+    spent = 0.0
+    done = 0
+    for lg, dtypes in ((24, DTYPES), (28, (np.float32,))):
+        for dtype in dtypes:
+            for dist in DISTS:
+                if spent > budget_s:
+                    break
+                x = workloads.single_array(dist, 1 << lg, dtype, seed=0, tag="bench")
+                for k in workloads.ks_for(x.size):
+                    t0 = time.perf_counter()
+                    oracle.select_kth(x, k)
+                    spent += time.perf_counter() - t0
+                    elems += x.size
+                    done += 1
+                del x
+    return {"value": elems / spent, "unit": "elements/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} of the 64 calls (all n=2^24, then n=2^28 float32 until "
+                      f"~{budget_s:.0f} s), single-threaded quickselect with its counting scan, "
+                      f"{spent:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build runs the selection on a single "
+              "MI355X; multi-GPU runs are not part of it.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1104_2732_amd as cps
+    import workloads
+
+    dev = torch.device("cuda", 0)
+    sel = cps.Selector(0)
+
+    # ---- resident inputs
+    t_gen = time.time()
+    inputs = []  # (tensor, n, k, dtype)
+    for lg in SIZES:
+        n = 1 << lg
+        for dtype in DTYPES:
+            for dist in DISTS:
+                x = workloads.single_array(dist, n, dtype, seed=0, tag="bench")
+                xt = torch.from_numpy(x).to(dev)
+                del x
+                for k in workloads.ks_for(n):
+                    inputs.append((xt, n, k, np.dtype(dtype)))
+    for dtype in DTYPES:
+        sel.reserve(1 << max(SIZES), cps.CPS_F32 if dtype == np.float32 else cps.CPS_F64)
+    torch.cuda.synchronize()
+    gen_s = time.time() - t_gen
+
+    outs = sel.new_results(len(inputs))
+    res_views = [outs[i * 48:(i + 1) * 48] for i in range(len(inputs))]
+
+    # ---- algorithmic traffic per call from the kernel's own trace (untimed run)
+    stats_buf = sel.new_stats()
+    alg_bytes = []
+    for (xt, n, k, dt), out in zip(inputs, res_views):
+        sel.select_kth_async(xt, k, out, stats_buf)
+        torch.cuda.synchronize()
+        st = stats_buf.cpu().numpy().view(cps.STATS_DTYPE)[0]
+        alg_bytes.append(int(st["elements_read"] + st["elements_written"]) * dt.itemsize)
+    res = outs.cpu().numpy().view(cps.RESULT_DTYPE)
+    assert np.all(res["status"] == 0), "a selection reported a non-zero status"
+
+    def step(events=None):
+        for i, ((xt, n, k, dt), out) in enumerate(zip(inputs, res_views)):
+            if events is not None:
+                events[i][0].record()
+            sel.select_kth_async(xt, k, out)
+            if events is not None:
+                events[i][1].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in inputs] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(ev[s])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    kern_ms = np.array([[a.elapsed_time(b) for (a, b) in evs] for evs in ev])  # steps x calls
+    per_call_ms = kern_ms.mean(axis=0)
+    elems_per_step = sum(n for (_, n, _, _) in inputs)
+    ms_per_step = wall * 1e3 / args.steps
+    value = elems_per_step * args.steps / wall
+
+    # roofline of the selection kernel: algorithmic bytes per launch / launch duration
+    bytes_per_launch = float(np.mean(alg_bytes))
+    avg_launch_ms = float(per_call_ms.mean())
+    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+    big = [i for i, (_, n, _, _) in enumerate(inputs) if n == 1 << max(SIZES)]
+    big_gbs = float(np.sum([alg_bytes[i] for i in big]) / (np.sum(per_call_ms[big]) * 1e-3) / 1e9)
+    traffic = load_traffic()
+
+    detail = {}
+    for lg in SIZES:
+        for dt in DTYPES:
+            idx = [i for i, (_, n, _, d) in enumerate(inputs) if n == 1 << lg and d == np.dtype(dt)]
+            t_ms = float(np.sum(per_call_ms[idx]))
+            detail[f"{np.dtype(dt).name}_2^{lg}"] = {
+                "ms_per_call": round(t_ms / len(idx), 4),
+                "elements_per_s": (1 << lg) * len(idx) / (t_ms * 1e-3),
+                "alg_GBps": float(np.sum([alg_bytes[i] for i in idx]) / (t_ms * 1e-3) / 1e9),
+                "passes_over_x": float(np.mean(res["passes"][idx])),
+            }
+
+    line = {
+        "metric": "exact-selection elements/s",
+        "value": value,
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic (seeded Philox; uniform, normal, Cauchy, 1024-level quantised normal)",
+        "config": {"workload": "single-array select_kth sweep: n in {2^24, 2^28} x {f32, f64} x "
+                               "{uniform, normal, cauchy, quantized normal} x k in {1, n/100, "
+                               "median, n-1} (64 calls per step)",
+                   "calls_per_step": len(inputs), "elements_per_step": elems_per_step},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "cp_select_kernel", "avg_launch_ms": avg_launch_ms,
+                     "alg_bytes_per_launch": bytes_per_launch,
+                     "n2^28_only_GBps": big_gbs},
+        "detail": detail,
+        "setup_s": round(gen_s, 1),
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+    sel.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -58,7 +58,8 @@ enum cps_status {
   CPS_STATUS_OK = 0,
   CPS_STATUS_NAN = 1,     /* the array holds NaN; value is NaN, counts are 0 */
   CPS_STATUS_TIMEOUT = 2, /* a device-side wait exceeded the spin limit; result invalid */
-  CPS_STATUS_INTERNAL = 3 /* an internal consistency check failed; result invalid */
+  CPS_STATUS_INTERNAL = 3, /* an internal consistency check failed; result invalid */
+  CPS_STATUS_BADARG = 4    /* batched calls: this array's pointer, size or rank is invalid */
 };
 
 /* ------------------------------------------------------------------ records */
@@ -191,6 +192,74 @@ int select_kth_ex(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
  * out_dev: device pointer to ny cps_eval records. */
 int cps_objective(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
                   const double *ys_dev, int64_t ny, cps_eval *out_dev, void *stream);
+
+/* ------------------------------------------------------------------ batched selection */
+
+/* Tuning of the batched kernel.  Fill with cps_default_batch_options first; 0 fields pick
+ * the tuned (or default) value.
+ * block_threads:   workgroup size, 256, 512 or 1024 (one workgroup runs one array at a time).
+ * blocks_per_cu:   resident workgroups per compute unit.
+ * split_capacity:  elements of each of a workgroup's two split buffers; a bracket is split
+ *                  (count-and-compact, end of Section 4) once it holds at most this many.
+ * final_threshold, maxit, partition_fraction: as in cps_options. */
+typedef struct cps_batch_options {
+  int32_t block_threads;
+  int32_t blocks_per_cu;
+  int64_t split_capacity;
+  int32_t final_threshold;
+  int32_t maxit;
+  double partition_fraction;
+} cps_batch_options;
+
+void cps_default_batch_options(cps_batch_options *opt);
+
+/* The k-th smallest element of each of `count` arrays of uneven sizes, in one launch: the
+ * method of Sections 3-4 run per array by one workgroup of a persistent grid that takes
+ * arrays largest first (the paper motivates batching when many medians are needed,
+ * Section 2).  The launch allocates nothing and leaves its queue reset, so it may be
+ * captured in a graph and replayed once the workspace is reserved (cps_reserve_batched).
+ * ptrs_dev:  device array of `count` device pointers to the arrays (each aligned to its
+ *            element type); sizes_dev, ks_dev: device arrays of int64 sizes and 1-based ranks.
+ * out_dev:   device array of `count` cps_result.  An invalid array (null pointer, size < 1,
+ *            rank outside [1, size]) gets status CPS_STATUS_BADARG; the others are unaffected.
+ * Errors: CPS_EINVAL for a null handle or descriptor pointer, count < 1 or a bad dtype. */
+int select_kth_batched(cps_handle *h, const void *const *ptrs_dev, const int64_t *sizes_dev,
+                       const int64_t *ks_dev, int64_t count, int dtype, cps_result *out_dev,
+                       void *stream);
+
+/* select_kth_batched with explicit tuning (NULL: the handle's autotuned choice, else the
+ * defaults). */
+int select_kth_batched_ex(cps_handle *h, const void *const *ptrs_dev, const int64_t *sizes_dev,
+                          const int64_t *ks_dev, int64_t count, int dtype,
+                          const cps_batch_options *opt, cps_result *out_dev, void *stream);
+
+/* Allocate the batched workspace for `opt` (NULL: the current choice) ahead of stream capture. */
+int cps_reserve_batched(cps_handle *h, int dtype, const cps_batch_options *opt);
+
+/* Autotuner: time each candidate launch shape and split capacity on this very batch (the
+ * call synchronises `stream`), keep the fastest as the handle's choice for `dtype`, and
+ * return it in best (may be NULL) with its time in *best_ms (may be NULL).  The results in
+ * out_dev are those of the last timed candidate. */
+int cps_autotune_batched(cps_handle *h, const void *const *ptrs_dev, const int64_t *sizes_dev,
+                         const int64_t *ks_dev, int64_t count, int dtype, cps_result *out_dev,
+                         void *stream, cps_batch_options *best, double *best_ms);
+
+/* ------------------------------------------------------------------ least median of squares */
+
+/* For each of m candidate parameter vectors b (rows of betas_dev, m x p, row-major doubles),
+ * the lower median (rank floor((n+1)/2)) of the squared residuals
+ *     r_i = (y_i - sum_{j=0..p-1} X_ij b_j)^2,   i = 0..n-1,
+ * the objective of the least-median-of-squares estimator (Section 6).  The sum runs left to
+ * right in j and every product and sum is rounded on its own (no fused multiply-add), so the
+ * residuals are bit-identical to that sequence in IEEE double precision; the medians are
+ * then exact.  out_dev[c] receives candidate c's median with its counts among the r_i.
+ * X_dev: n x p row-major doubles; y_dev: n doubles (device memory, caller-owned).
+ * The residuals are materialised in the handle's workspace (m * n doubles) and selected
+ * with the batched kernel, in two launches plus one for the descriptors.
+ * Errors: CPS_EINVAL for null pointers, n < 1, p outside [1, 16], m < 1 or m > 1048560. */
+int lms_median_sq_residuals(cps_handle *h, const double *X_dev, const double *y_dev,
+                            const double *betas_dev, int64_t n, int32_t p, int64_t m,
+                            cps_result *out_dev, void *stream);
 
 #ifdef __cplusplus
 }

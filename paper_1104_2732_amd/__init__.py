@@ -55,6 +55,13 @@ class Options(ctypes.Structure):
                 ("bracket_lo", ctypes.c_double), ("bracket_hi", ctypes.c_double)]
 
 
+class BatchOptions(ctypes.Structure):
+    """Mirror of cps_batch_options (see include/cpselect.h)."""
+    _fields_ = [("block_threads", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("split_capacity", ctypes.c_int64), ("final_threshold", ctypes.c_int32),
+                ("maxit", ctypes.c_int32), ("partition_fraction", ctypes.c_double)]
+
+
 class CpsError(RuntimeError):
     def __init__(self, code: int, what: str):
         msg = lib().cps_status_string(code).decode() if _lib is not None else str(code)
@@ -68,7 +75,10 @@ class CpsError(RuntimeError):
 _lib = None
 
 EXPORTS = ("cps_create", "cps_destroy", "cps_status_string", "cps_last_hip_error",
-           "cps_default_options", "cps_reserve", "select_kth", "select_kth_ex", "cps_objective")
+           "cps_default_options", "cps_reserve", "select_kth", "select_kth_ex", "cps_objective",
+           "cps_default_batch_options", "select_kth_batched", "select_kth_batched_ex",
+           "cps_reserve_batched", "cps_autotune_batched", "lms_median_sq_residuals")
+STATUS_BADARG = 4
 
 
 def lib() -> ctypes.CDLL:
@@ -98,6 +108,20 @@ def lib() -> ctypes.CDLL:
     L.select_kth_ex.restype = c_int
     L.cps_objective.argtypes = [vp, vp, i64, i64, c_int, vp, i64, vp, vp]
     L.cps_objective.restype = c_int
+    L.cps_default_batch_options.argtypes = [ctypes.POINTER(BatchOptions)]
+    L.cps_default_batch_options.restype = None
+    L.select_kth_batched.argtypes = [vp, vp, vp, vp, i64, c_int, vp, vp]
+    L.select_kth_batched.restype = c_int
+    L.select_kth_batched_ex.argtypes = [vp, vp, vp, vp, i64, c_int, ctypes.POINTER(BatchOptions),
+                                        vp, vp]
+    L.select_kth_batched_ex.restype = c_int
+    L.cps_reserve_batched.argtypes = [vp, c_int, ctypes.POINTER(BatchOptions)]
+    L.cps_reserve_batched.restype = c_int
+    L.cps_autotune_batched.argtypes = [vp, vp, vp, vp, i64, c_int, vp, vp,
+                                       ctypes.POINTER(BatchOptions), ctypes.POINTER(ctypes.c_double)]
+    L.cps_autotune_batched.restype = c_int
+    L.lms_median_sq_residuals.argtypes = [vp, vp, vp, vp, i64, i32, i64, vp, vp]
+    L.lms_median_sq_residuals.restype = c_int
     _lib = L
     return L
 
@@ -105,6 +129,16 @@ def lib() -> ctypes.CDLL:
 def default_options(**kw) -> Options:
     o = Options()
     lib().cps_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def default_batch_options(**kw) -> BatchOptions:
+    o = BatchOptions()
+    lib().cps_default_batch_options(ctypes.byref(o))
     for k, v in kw.items():
         if not hasattr(o, k):
             raise KeyError(k)
@@ -197,6 +231,86 @@ class Selector:
         if stats:
             return res, _as_records(st, STATS_DTYPE)[0]
         return res
+
+    # -- batched ---------------------------------------------------------------------
+
+    def batch_descriptors(self, arrays, ks):
+        """Device descriptor arrays (pointers, sizes, ranks) for a list of CUDA tensors."""
+        import torch
+        if not arrays:
+            raise ValueError("empty batch")
+        dt = arrays[0].dtype
+        for a in arrays:
+            if not a.is_cuda or not a.is_contiguous() or a.dtype != dt:
+                raise ValueError("batch arrays must be contiguous CUDA tensors of one dtype")
+        ptrs = torch.tensor([a.data_ptr() for a in arrays], dtype=torch.int64, device=self.device)
+        sizes = torch.tensor([a.numel() for a in arrays], dtype=torch.int64, device=self.device)
+        kk = torch.tensor([int(k) for k in ks], dtype=torch.int64, device=self.device)
+        return ptrs, sizes, kk, _dtype_code(arrays[0])
+
+    def select_kth_batched_async(self, ptrs, sizes, ks, count: int, dtype_code: int, out,
+                                 options: BatchOptions | None = None) -> None:
+        """Enqueue select_kth_batched(_ex) on the current stream (device descriptors)."""
+        rc = lib().select_kth_batched_ex(self._h, ctypes.c_void_p(ptrs.data_ptr()),
+                                         ctypes.c_void_p(sizes.data_ptr()),
+                                         ctypes.c_void_p(ks.data_ptr()), int(count), int(dtype_code),
+                                         ctypes.byref(options) if options is not None else None,
+                                         ctypes.c_void_p(out.data_ptr()),
+                                         ctypes.c_void_p(_stream_ptr(self.device)))
+        _check(rc, "select_kth_batched")
+
+    def reserve_batched(self, dtype_code: int, options: BatchOptions | None = None) -> None:
+        _check(lib().cps_reserve_batched(self._h, int(dtype_code),
+                                         ctypes.byref(options) if options is not None else None),
+               "cps_reserve_batched")
+
+    def autotune_batched(self, ptrs, sizes, ks, count: int, dtype_code: int, out):
+        """Run the library's autotuner on this batch; returns (options, ms)."""
+        best = BatchOptions()
+        ms = ctypes.c_double()
+        rc = lib().cps_autotune_batched(self._h, ctypes.c_void_p(ptrs.data_ptr()),
+                                        ctypes.c_void_p(sizes.data_ptr()),
+                                        ctypes.c_void_p(ks.data_ptr()), int(count), int(dtype_code),
+                                        ctypes.c_void_p(out.data_ptr()),
+                                        ctypes.c_void_p(_stream_ptr(self.device)),
+                                        ctypes.byref(best), ctypes.byref(ms))
+        _check(rc, "cps_autotune_batched")
+        return best, ms.value
+
+    def select_kth_batched(self, arrays, ks, options: BatchOptions | None = None) -> np.ndarray:
+        """Synchronous batched selection over a list of CUDA tensors; returns RESULT_DTYPE records."""
+        import torch
+        ptrs, sizes, kk, code = self.batch_descriptors(arrays, ks)
+        out = self.new_results(len(arrays))
+        self.select_kth_batched_async(ptrs, sizes, kk, len(arrays), code, out, options)
+        torch.cuda.synchronize(self.device)
+        return _as_records(out, RESULT_DTYPE).copy()
+
+    # -- least median of squares -------------------------------------------------------
+
+    def lms_median_sq_residuals_async(self, X, y, betas, out) -> None:
+        """Enqueue lms_median_sq_residuals: X (n x p), y (n), betas (m x p), float64 CUDA tensors."""
+        import torch
+        for t in (X, y, betas):
+            if not t.is_cuda or not t.is_contiguous() or t.dtype != torch.float64:
+                raise ValueError("X, y and betas must be contiguous float64 CUDA tensors")
+        n, p = X.shape
+        m = betas.shape[0]
+        if y.numel() != n or betas.shape[1] != p:
+            raise ValueError("shape mismatch between X, y and betas")
+        rc = lib().lms_median_sq_residuals(self._h, ctypes.c_void_p(X.data_ptr()),
+                                           ctypes.c_void_p(y.data_ptr()),
+                                           ctypes.c_void_p(betas.data_ptr()), n, p, m,
+                                           ctypes.c_void_p(out.data_ptr()),
+                                           ctypes.c_void_p(_stream_ptr(self.device)))
+        _check(rc, "lms_median_sq_residuals")
+
+    def lms_median_sq_residuals(self, X, y, betas) -> np.ndarray:
+        import torch
+        out = self.new_results(betas.shape[0])
+        self.lms_median_sq_residuals_async(X, y, betas, out)
+        torch.cuda.synchronize(self.device)
+        return _as_records(out, RESULT_DTYPE).copy()
 
     def objective(self, x, k: int, ys) -> np.ndarray:
         """cps_objective at every y in `ys` (array-like of float64); returns EVAL_DTYPE records."""

@@ -25,8 +25,14 @@ struct cps_handle {
   int cu_count = 0;
   int max_blocks_f32 = 0;
   int max_blocks_f64 = 0;
-  void *ws = nullptr;
+  void *ws = nullptr;   // single-array workspace
   size_t ws_bytes = 0;
+  void *bws = nullptr;  // batched workspace (queue counters first)
+  size_t bws_bytes = 0;
+  void *lws = nullptr;  // least-median-of-squares residuals and descriptors
+  size_t lws_bytes = 0;
+  cps_batch_options tuned[2];
+  bool has_tuned[2] = {false, false};
   std::mutex mu;
 };
 
@@ -65,10 +71,16 @@ SelectLayout select_layout(int64_t seg_R, int grid, int64_t zcap, int gmax, size
   return L;
 }
 
-// Grow the workspace to at least `bytes`.  The synchronisation words at the start of
+// Grow a workspace buffer to at least `bytes`.  The synchronisation words at the start of
 // every layout must be zero on first use, so fresh memory is cleared synchronously.
+int ensure_buffer(void *&buf, size_t &have, size_t bytes, hipStream_t stream);
+
 int ensure_workspace(cps_handle *h, size_t bytes, hipStream_t stream) {
-  if (bytes <= h->ws_bytes) return CPS_OK;
+  return ensure_buffer(h->ws, h->ws_bytes, bytes, stream);
+}
+
+int ensure_buffer(void *&buf, size_t &have, size_t bytes, hipStream_t stream) {
+  if (bytes <= have) return CPS_OK;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (stream != nullptr) {
     hipError_t e = hipStreamIsCapturing(stream, &cs);
@@ -77,21 +89,21 @@ int ensure_workspace(cps_handle *h, size_t bytes, hipStream_t stream) {
   }
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e);
-  if (h->ws) {
-    (void)hipFree(h->ws);
-    h->ws = nullptr;
-    h->ws_bytes = 0;
+  if (buf) {
+    (void)hipFree(buf);
+    buf = nullptr;
+    have = 0;
   }
   size_t want = align_up(bytes + bytes / 8, 1 << 20);
-  e = hipMalloc(&h->ws, want);
+  e = hipMalloc(&buf, want);
   if (e != hipSuccess) {
     g_last_hip = (int)e;
-    h->ws = nullptr;
+    buf = nullptr;
     return CPS_ENOMEM;
   }
-  e = hipMemset(h->ws, 0, want < (1 << 21) ? want : (1 << 21));
+  e = hipMemset(buf, 0, want < (1 << 21) ? want : (1 << 21));
   if (e != hipSuccess) return hip_fail(e);
-  h->ws_bytes = want;
+  have = want;
   return CPS_OK;
 }
 
@@ -126,7 +138,7 @@ int resolve(cps_handle *h, int64_t n, int dtype, const cps_options *opt, Resolve
   const int gmax = h->cu_count * per_cu;
   if (gmax < 1) return CPS_ENODEV;
   const int64_t tile = (int64_t)cps::kSelectBlock * cps::kSelectUnroll * (16 / dtype_size(dtype));
-  int64_t g = o.grid_blocks ? o.grid_blocks : (int64_t)h->cu_count * (per_cu < 2 ? per_cu : 2);
+  int64_t g = o.grid_blocks ? o.grid_blocks : (int64_t)h->cu_count * per_cu;
   const int64_t tiles = (n + tile - 1) / tile;
   if (g > tiles) g = tiles;
   if (g > gmax) g = gmax;
@@ -139,7 +151,7 @@ int resolve(cps_handle *h, int64_t n, int dtype, const cps_options *opt, Resolve
   int64_t seg = 0;
   if (o.partition_fraction > 0.0) {
     const int64_t vec = 16 / (int64_t)dtype_size(dtype);
-    const int64_t su = cps::kSelectUnroll / 2 > 0 ? cps::kSelectUnroll / 2 : 1;
+    const int64_t su = cps::kSplitUnroll;
     const int64_t step_vecs = (int64_t)cps::kSelectBlock * su;
     const int64_t nvec = n / vec + 1;
     const int64_t steps = (nvec + step_vecs - 1) / step_vecs;
@@ -192,9 +204,203 @@ int check_common(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype) 
   return CPS_OK;
 }
 
+// ---- batched selection
+
+struct BatchResolved {
+  cps::CpConfig cfg;
+  int grid, block;
+  int64_t cap, ws_stride;
+  size_t bytes;
+};
+
+int resolve_batched(cps_handle *h, int dtype, const cps_batch_options *opt, BatchResolved &r) {
+  cps_batch_options o;
+  cps_default_batch_options(&o);
+  const int di = dtype == CPS_F32 ? 0 : 1;
+  if (opt) o = *opt;
+  else if (h->has_tuned[di]) o = h->tuned[di];
+  if (o.block_threads == 0) o.block_threads = 512;
+  if (o.block_threads != 256 && o.block_threads != 512 && o.block_threads != 1024) return CPS_EINVAL;
+  if (o.blocks_per_cu < 0 || o.split_capacity < 0 || o.final_threshold < 0 || o.maxit < 0 ||
+      !(o.partition_fraction >= 0.0) || o.partition_fraction > 1.0)
+    return CPS_EINVAL;
+  const size_t es = dtype_size(dtype);
+  const int per_cu = dtype == CPS_F32 ? cps::batched_max_blocks_per_cu<float>(o.block_threads)
+                                      : cps::batched_max_blocks_per_cu<double>(o.block_threads);
+  if (per_cu < 1) return CPS_ENODEV;
+  int bpc = o.blocks_per_cu ? o.blocks_per_cu : per_cu;
+  if (bpc > per_cu) bpc = per_cu;
+  r.block = o.block_threads;
+  r.grid = h->cu_count * bpc;
+  const int64_t ft = o.final_threshold ? o.final_threshold : 4096;
+  r.cap = o.split_capacity ? o.split_capacity : ((int64_t)1 << 17);
+  if (r.cap < ft) r.cap = ft;
+  r.cap = (r.cap + 63) / 64 * 64;
+  r.ws_stride = 2 * r.cap + (ft + 63) / 64 * 64;
+  r.bytes = align_up(sizeof(cps::BatchCtl), 256) + (size_t)r.grid * r.ws_stride * es;
+  r.cfg = cps::CpConfig{};
+  r.cfg.maxit = o.maxit ? o.maxit : 64;
+  r.cfg.dtype = dtype;
+  r.cfg.final_threshold = ft;
+  r.cfg.final_direct_max = 4 * ft;
+  r.cfg.theta = o.partition_fraction;
+  r.cfg.zcap = ft;
+  r.cfg.split_cap = r.cap;
+  return CPS_OK;
+}
+
+template <typename T>
+int run_batched(cps_handle *h, const void *const *ptrs, const int64_t *sizes, const int64_t *ks,
+                int64_t count, const cps_batch_options *opt, cps_result *out, hipStream_t stream) {
+  BatchResolved r;
+  int rc = resolve_batched(h, sizeof(T) == 4 ? CPS_F32 : CPS_F64, opt, r);
+  if (rc) return rc;
+  rc = ensure_buffer(h->bws, h->bws_bytes, r.bytes, stream);
+  if (rc) return rc;
+  cps::BatchArgs<T> a;
+  a.ptrs = (const T *const *)ptrs;
+  a.sizes = sizes;
+  a.ks = ks;
+  a.count = count;
+  a.out = out;
+  a.ctl = (cps::BatchCtl *)h->bws;
+  a.zbuf = (T *)((char *)h->bws + align_up(sizeof(cps::BatchCtl), 256));
+  a.cap = r.cap;
+  a.ws_stride = r.ws_stride;
+  a.cfg = r.cfg;
+  hipError_t e = cps::launch_batched<T>(a, r.grid, r.block, stream);
+  if (e != hipSuccess) return hip_fail(e);
+  return CPS_OK;
+}
+
+int check_batched(cps_handle *h, const void *const *ptrs, const int64_t *sizes, const int64_t *ks,
+                  int64_t count, int dtype, cps_result *out) {
+  if (!h || !ptrs || !sizes || !ks || !out || count < 1 || !dtype_size(dtype)) return CPS_EINVAL;
+  return CPS_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+void cps_default_batch_options(cps_batch_options *opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->block_threads = 512;
+  opt->blocks_per_cu = 0;
+  opt->split_capacity = (int64_t)1 << 17;
+  opt->final_threshold = 4096;
+  opt->maxit = 64;
+  opt->partition_fraction = 0.5;
+}
+
+int select_kth_batched_ex(cps_handle *h, const void *const *ptrs_dev, const int64_t *sizes_dev,
+                          const int64_t *ks_dev, int64_t count, int dtype,
+                          const cps_batch_options *opt, cps_result *out_dev, void *stream) {
+  int rc = check_batched(h, ptrs_dev, sizes_dev, ks_dev, count, dtype, out_dev);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(h->mu);
+  if (dtype == CPS_F32)
+    return run_batched<float>(h, ptrs_dev, sizes_dev, ks_dev, count, opt, out_dev, (hipStream_t)stream);
+  return run_batched<double>(h, ptrs_dev, sizes_dev, ks_dev, count, opt, out_dev, (hipStream_t)stream);
+}
+
+int select_kth_batched(cps_handle *h, const void *const *ptrs_dev, const int64_t *sizes_dev,
+                       const int64_t *ks_dev, int64_t count, int dtype, cps_result *out_dev,
+                       void *stream) {
+  return select_kth_batched_ex(h, ptrs_dev, sizes_dev, ks_dev, count, dtype, nullptr, out_dev, stream);
+}
+
+int cps_reserve_batched(cps_handle *h, int dtype, const cps_batch_options *opt) {
+  if (!h || !dtype_size(dtype)) return CPS_EINVAL;
+  std::lock_guard<std::mutex> lk(h->mu);
+  BatchResolved r;
+  int rc = resolve_batched(h, dtype, opt, r);
+  if (rc) return rc;
+  return ensure_buffer(h->bws, h->bws_bytes, r.bytes, nullptr);
+}
+
+int lms_median_sq_residuals(cps_handle *h, const double *X_dev, const double *y_dev,
+                            const double *betas_dev, int64_t n, int32_t p, int64_t m,
+                            cps_result *out_dev, void *stream) {
+  if (!h || !X_dev || !y_dev || !betas_dev || !out_dev || n < 1 || p < 1 || p > 16 || m < 1 ||
+      m > (int64_t)65535 * 16)
+    return CPS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  size_t off_desc, bytes;
+  {
+    std::lock_guard<std::mutex> lk(h->mu);
+    off_desc = align_up((size_t)m * (size_t)n * sizeof(double), 256);
+    bytes = off_desc + 3 * align_up((size_t)m * 8, 256);
+    int rc = ensure_buffer(h->lws, h->lws_bytes, bytes, s);
+    if (rc) return rc;
+    char *base = (char *)h->lws;
+    double *R = (double *)base;
+    const double **ptrs = (const double **)(base + off_desc);
+    int64_t *sizes = (int64_t *)(base + off_desc + align_up((size_t)m * 8, 256));
+    int64_t *ks = (int64_t *)(base + off_desc + 2 * align_up((size_t)m * 8, 256));
+    hipError_t e = cps::launch_lms_residuals(X_dev, y_dev, betas_dev, n, p, m, R, ptrs, sizes, ks,
+                                             h->cu_count, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  char *base = (char *)h->lws;
+  return select_kth_batched_ex(h, (const void *const *)(base + off_desc),
+                               (const int64_t *)(base + off_desc + align_up((size_t)m * 8, 256)),
+                               (const int64_t *)(base + off_desc + 2 * align_up((size_t)m * 8, 256)),
+                               m, CPS_F64, nullptr, out_dev, stream);
+}
+
+int cps_autotune_batched(cps_handle *h, const void *const *ptrs_dev, const int64_t *sizes_dev,
+                         const int64_t *ks_dev, int64_t count, int dtype, cps_result *out_dev,
+                         void *stream, cps_batch_options *best, double *best_ms) {
+  int rc = check_batched(h, ptrs_dev, sizes_dev, ks_dev, count, dtype, out_dev);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int blocks[3] = {256, 512, 1024};
+  const int64_t caps[3] = {(int64_t)1 << 15, (int64_t)1 << 17, (int64_t)1 << 19};
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return CPS_EHIP;
+  double best_t = 1e300;
+  cps_batch_options best_o;
+  cps_default_batch_options(&best_o);
+  int last_rc = CPS_OK;
+  for (int b : blocks) {
+    for (int64_t c : caps) {
+      cps_batch_options o;
+      cps_default_batch_options(&o);
+      o.block_threads = b;
+      o.split_capacity = c;
+      rc = select_kth_batched_ex(h, ptrs_dev, sizes_dev, ks_dev, count, dtype, &o, out_dev, stream);
+      if (rc == CPS_ENOMEM) continue;  // this candidate's workspace does not fit
+      if (rc) { last_rc = rc; break; }
+      (void)hipEventRecord(e0, s);
+      for (int rep = 0; rep < 2; ++rep)
+        rc = select_kth_batched_ex(h, ptrs_dev, sizes_dev, ks_dev, count, dtype, &o, out_dev, stream);
+      (void)hipEventRecord(e1, s);
+      if (hipEventSynchronize(e1) != hipSuccess) { last_rc = CPS_EHIP; break; }
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms / 2 < best_t) {
+        best_t = ms / 2;
+        best_o = o;
+      }
+    }
+    if (last_rc) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (last_rc) return last_rc;
+  {
+    std::lock_guard<std::mutex> lk(h->mu);
+    const int di = dtype == CPS_F32 ? 0 : 1;
+    h->tuned[di] = best_o;
+    h->has_tuned[di] = true;
+  }
+  if (best) *best = best_o;
+  if (best_ms) *best_ms = best_t;
+  return CPS_OK;
+}
+
 
 void cps_default_options(cps_options *opt) {
   if (!opt) return;
@@ -258,6 +464,8 @@ int cps_create(int device, cps_handle **out) {
 int cps_destroy(cps_handle *h) {
   if (!h) return CPS_EINVAL;
   if (h->ws) (void)hipFree(h->ws);
+  if (h->bws) (void)hipFree(h->bws);
+  if (h->lws) (void)hipFree(h->lws);
   delete h;
   return CPS_OK;
 }

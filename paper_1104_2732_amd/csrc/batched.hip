@@ -1,0 +1,428 @@
+// Batched exact selection: many independent arrays of uneven sizes in one launch.
+//
+// A persistent grid of workgroups pulls arrays from a device-side queue, largest first
+// (every workgroup sorts the sizes in LDS on its own, so no grid-wide wait is needed),
+// and runs the whole cutting-plane method of Section 4 on each array by itself: pass 0,
+// evaluation passes, splits of the bracket into the workgroup's private buffers once the
+// bracket is small, a gather, and the exact radix select.  The state machine is the one
+// of the single-array kernel (cp_state.h), kept in LDS; every synchronisation is a
+// workgroup barrier, so workgroups never wait on each other and the launch needs no
+// co-residency.  The queue and exit counters reset themselves at the end, so the launch
+// can be captured in a graph and replayed.
+#include "cps_device.h"
+#include "cps_kernels.h"
+#include "cps_passes.h"
+
+namespace cps {
+
+__device__ __noinline__ void bdev_after_pass0(CpState &s, const Pass0Result &r, const CpConfig &c) {
+  cp_after_pass0(s, r, c);
+}
+__device__ __noinline__ void bdev_after_eval(CpState &s, const EvalResult &r, const CpConfig &c) {
+  cp_after_eval(s, r, c);
+}
+__device__ __noinline__ void bdev_after_gather(CpState &s, int64_t gathered) {
+  cp_after_gather(s, gathered);
+}
+__device__ __noinline__ void bdev_after_final(CpState &s, double v, int64_t below, int64_t eq) {
+  cp_after_final(s, v, below, eq);
+}
+
+template <typename T, int BLOCK> struct BShared {
+  CpState st;
+  double d[8][BLOCK / kWave];
+  int64_t i[8][BLOCK / kWave];
+  uint32_t wcnt[2][BLOCK / kWave];
+  uint64_t wbase[2][BLOCK / kWave];
+  uint32_t hist[256];
+  int64_t misc[8];
+  int64_t cur[2];
+  int64_t job;
+  uint64_t order[kBatchSortMax];  // (size << 12 | index), sorted by size, largest first
+};
+
+// Split (or gather) one tile's elements into this workgroup's buffer: the low side grows
+// up from out[0], the high side down from out[cap-1].  GATHER: every valid element inside
+// (lo_ex, hi_ex) goes low.  Two workgroup barriers per tile; the cursors live in LDS.
+template <typename T, int BLOCK, int U, bool FILTER, bool GATHER>
+__device__ inline void block_split_tile(const T (&e)[U][Traits<T>::kVec], const bool (&valid)[U],
+                                        int nslot, T t, T lo_ex, T hi_ex, CPS_GLOBAL T *out,
+                                        int64_t cap, BShared<T, BLOCK> &sh) {
+  constexpr int V = Traits<T>::kVec;
+  const int tid = threadIdx.x, wv = tid / kWave, lane = tid % kWave;
+  auto low = [&](T v, bool ok) -> bool {
+    if (GATHER) return ok && (!FILTER || (v > lo_ex && v < hi_ex));
+    return ok && v < t && (!FILTER || v > lo_ex);
+  };
+  auto high = [&](T v, bool ok) -> bool {
+    if (GATHER) return false;
+    return ok && v > t && (!FILTER || v < hi_ex);
+  };
+  uint32_t wl = 0, wr = 0;
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      if (u * V + j >= nslot) continue;
+      wl += popc(ballot(low(e[u][j], valid[u])));
+      wr += popc(ballot(high(e[u][j], valid[u])));
+    }
+  if (lane == 0) {
+    sh.wcnt[0][wv] = wl;
+    sh.wcnt[1][wv] = wr;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint64_t bl = (uint64_t)sh.cur[0], br = (uint64_t)sh.cur[1];
+    for (int w = 0; w < BLOCK / kWave; ++w) {
+      sh.wbase[0][w] = bl;
+      bl += sh.wcnt[0][w];
+      sh.wbase[1][w] = br;
+      br += sh.wcnt[1][w];
+    }
+    sh.cur[0] = (int64_t)bl;
+    sh.cur[1] = (int64_t)br;
+  }
+  __syncthreads();
+  uint64_t ol = sh.wbase[0][wv], orr = sh.wbase[1][wv];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      if (u * V + j >= nslot) continue;
+      const bool l = low(e[u][j], valid[u]);
+      const uint64_t ml = ballot(l);
+      if (l) out[ol + lane_rank(ml)] = e[u][j];
+      ol += popc(ml);
+      if (!GATHER) {
+        const bool r = high(e[u][j], valid[u]);
+        const uint64_t mr = ballot(r);
+        if (r) out[cap - 1 - (int64_t)(orr + lane_rank(mr))] = e[u][j];
+        orr += popc(mr);
+      }
+    }
+  __syncthreads();
+}
+
+// One evaluation pass of this workgroup over span sp, optionally splitting into `out`.
+template <typename T, int BLOCK, int U, bool CLAMP, bool SPLIT, bool FILTER, bool GATHER>
+__device__ void block_pass(const Span<T> &sp, T t, T yL, T yR, T fmin, T fmax,
+                           CPS_GLOBAL T *out, int64_t cap, BShared<T, BLOCK> &sh,
+                           EvalAcc<T> &acc) {
+  constexpr int V = Traits<T>::kVec;
+  using Vec = typename Traits<T>::Vec;
+  const int tid = threadIdx.x, lane = tid % kWave;
+  for (int64_t base = 0; base < sp.nvec; base += (int64_t)BLOCK * U) {
+    Vec raw[U];
+    bool valid[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t vi = base + (int64_t)u * BLOCK + tid;
+      valid[u] = vi < sp.nvec;
+      if (valid[u]) raw[u] = sp.V[vi];
+    }
+    T e[U][V];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      vec_to_arr<T>(raw[u], e[u]);
+      if (!GATHER) {
+        T a_part = 0, b_part = 0;
+#pragma unroll
+        for (int j = 0; j < V; ++j) eval_one<T, CLAMP>(e[u][j], valid[u], t, fmin, fmax, a_part, b_part, acc);
+        acc.A += (double)a_part;
+        acc.B += (double)b_part;
+      }
+    }
+    if (SPLIT || GATHER)
+      block_split_tile<T, BLOCK, U, FILTER, GATHER>(e, valid, U * V, t, yL, yR, out, cap, sh);
+  }
+  if (sp.nedge > 0) {
+    // the unaligned head and tail, one element per lane of the first wavefront
+    const bool have = tid < sp.nedge;
+    T v = have ? sp.W[edge_index(sp, tid)] : T(0);
+    if (!GATHER) {
+      T a_part = 0, b_part = 0;
+      eval_one<T, CLAMP>(v, have, t, fmin, fmax, a_part, b_part, acc);
+      acc.A += (double)a_part;
+      acc.B += (double)b_part;
+    }
+    if (SPLIT || GATHER) {
+      T e[U][V];
+      bool valid[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        valid[u] = false;
+#pragma unroll
+        for (int j = 0; j < V; ++j) e[u][j] = v;
+      }
+      valid[0] = have;
+      block_split_tile<T, BLOCK, U, FILTER, GATHER>(e, valid, 1, t, yL, yR, out, cap, sh);
+    }
+  }
+  (void)lane;
+}
+
+template <typename T, int BLOCK, int U, bool CLASSIFY>
+__device__ void block_pass0(const Span<T> &sp, P0Acc<T> &acc) {
+  constexpr int V = Traits<T>::kVec;
+  using Vec = typename Traits<T>::Vec;
+  const int tid = threadIdx.x;
+  const T ba = 0, bb = 0;
+  for (int64_t base = 0; base < sp.nvec; base += (int64_t)BLOCK * U) {
+    Vec raw[U];
+    bool valid[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t vi = base + (int64_t)u * BLOCK + tid;
+      valid[u] = vi < sp.nvec;
+      if (valid[u]) raw[u] = sp.V[vi];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      T e[V];
+      vec_to_arr<T>(raw[u], e);
+      T s_part = 0, aa = 0, bA = 0, ab = 0, bB = 0;
+#pragma unroll
+      for (int j = 0; j < V; ++j)
+        pass0_one<T, CLASSIFY, false>(e[j], valid[u], ba, bb, s_part, aa, bA, ab, bB, acc);
+      acc.sum += (double)s_part;
+    }
+  }
+  if (sp.nedge > 0) {
+    const bool have = tid < sp.nedge;
+    const T v = have ? sp.W[edge_index(sp, tid)] : T(0);
+    T s_part = 0, aa = 0, bA = 0, ab = 0, bB = 0;
+    pass0_one<T, CLASSIFY, false>(v, have, ba, bb, s_part, aa, bA, ab, bB, acc);
+    acc.sum += (double)s_part;
+  }
+}
+
+template <typename T> __device__ inline void write_batch_result(cps_result *out, const CpState &s) {
+  cps_result r;
+  const T v = (T)s.value + T(0);
+  uint64_t bits;
+  if (sizeof(T) == 4) bits = (uint64_t)__builtin_bit_cast(uint32_t, (float)v);
+  else bits = __builtin_bit_cast(uint64_t, (double)v);
+  r.value_bits = bits;
+  r.value = (double)v;
+  r.less = s.less;
+  r.equal = s.equal;
+  r.greater = s.n - s.less - s.equal;
+  r.passes = s.passes;
+  r.status = s.status;
+  if (s.status != ST_OK) r.less = r.equal = r.greater = 0;
+  *out = r;
+}
+
+// The whole method on one array, by this workgroup.
+template <typename T, int BLOCK, int U>
+__device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out,
+                           const BatchArgs<T> &a, BShared<T, BLOCK> &sh) {
+  const int tid = threadIdx.x;
+  constexpr int SU = U / 2 > 0 ? U / 2 : 1;
+  const int64_t cap = a.cap;
+  CPS_GLOBAL T *zb[2] = {(CPS_GLOBAL T *)(a.zbuf + (int64_t)blockIdx.x * a.ws_stride),
+                         (CPS_GLOBAL T *)(a.zbuf + (int64_t)blockIdx.x * a.ws_stride + cap)};
+  CPS_GLOBAL T *gb = (CPS_GLOBAL T *)(a.zbuf + (int64_t)blockIdx.x * a.ws_stride + 2 * cap);
+  if (!x || n < 1 || k < 1 || k > n || ((uintptr_t)x % sizeof(T)) != 0) {
+    if (tid == 0) {
+      cps_result r = {};
+      r.status = ST_BADARG;
+      *out = r;
+    }
+    return;
+  }
+  const Span<T> sx = make_span(x, n);
+  bool slow = false;
+  for (;;) {  // pass 0 (repeated once with infinity classification if needed)
+    P0Acc<T> acc;
+    acc.sum = 0;
+    acc.mn = t_inf<T>();
+    acc.mx = -t_inf<T>();
+    acc.cmn = acc.cmx = 0;
+    acc.nnan = acc.nneg = acc.npos = acc.cle_a = acc.clt_b = 0;
+    acc.Aa = acc.Ba = acc.Ab = acc.Bb = 0;
+    if (slow) block_pass0<T, BLOCK, SU, true>(sx, acc);
+    else block_pass0<T, BLOCK, U, false>(sx, acc);
+    double mn = (double)acc.mn, mx = (double)acc.mx;
+    int64_t cmn = acc.cmn, cmx = acc.cmx;
+    block_pair_fold<BLOCK>(mn, cmn, mx, cmx, sh.d, sh.i);
+    double dv[8] = {acc.sum, 0, 0, 0, 0, 0, 0, 0};
+    int64_t iv[8] = {(int64_t)acc.nnan, (int64_t)acc.nneg, (int64_t)acc.npos, 0, 0, 0, 0, 0};
+    int dop[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    block_reduce<BLOCK, 1, 3>(dv, dop, iv, true, sh.d, sh.i);
+    if (tid == 0) {
+      Pass0Result r = {};
+      r.classified = slow ? 1 : 0;
+      r.sum = dv[0];
+      r.nnan = iv[0];
+      r.nneg = iv[1];
+      r.npos = iv[2];
+      r.fmin = mn;
+      r.fmax = mx;
+      r.cmin = cmn;
+      r.cmax = cmx;
+      CpState &s = sh.st;
+      if (!slow) {
+        s = CpState{};
+        s.n = n;
+        s.k = k;
+      }
+      s.phase = PH_PASS0;
+      bdev_after_pass0(s, r, a.cfg);
+    }
+    __syncthreads();
+    if (sh.st.phase == PH_PASS0 && sh.st.p0_slow && !slow) {
+      slow = true;
+      continue;
+    }
+    break;
+  }
+  while (sh.st.phase == PH_EVAL || sh.st.phase == PH_GATHER) {
+    const CpState &s = sh.st;
+    const T t = (T)s.t, yL = (T)s.yL, yR = (T)s.yR, fmn = (T)s.fmin, fmx = (T)s.fmax;
+    const T *W;
+    if (s.wbuf < 0) W = x;
+    else if (s.wbuf == 2) W = (const T *)gb;
+    else W = (const T *)zb[s.wbuf] + (s.side == 0 ? 0 : cap - s.wlen);
+    const Span<T> sp = make_span(W, s.wbuf < 0 ? n : s.wlen);
+    EvalAcc<T> acc;
+    acc.A = acc.B = 0;
+    acc.pred = -t_inf<T>();
+    acc.succ = t_inf<T>();
+    acc.L = acc.G = 0;
+    if (tid == 0) sh.cur[0] = sh.cur[1] = 0;
+    __syncthreads();
+    const bool gather = s.phase == PH_GATHER;
+    const bool clamp = s.has_inf && s.wbuf < 0;
+    if (gather) {
+      if (s.filter) block_pass<T, BLOCK, SU, false, false, true, true>(sp, t, yL, yR, fmn, fmx, gb, cap, sh, acc);
+      else block_pass<T, BLOCK, SU, false, false, false, true>(sp, t, yL, yR, fmn, fmx, gb, cap, sh, acc);
+    } else if (!s.split) {
+      if (clamp) block_pass<T, BLOCK, SU, true, false, false, false>(sp, t, yL, yR, fmn, fmx, nullptr, cap, sh, acc);
+      else block_pass<T, BLOCK, U, false, false, false, false>(sp, t, yL, yR, fmn, fmx, nullptr, cap, sh, acc);
+    } else if (s.filter) {
+      block_pass<T, BLOCK, SU, false, true, true, false>(sp, t, yL, yR, fmn, fmx, zb[s.zout], cap, sh, acc);
+    } else {
+      block_pass<T, BLOCK, SU, false, true, false, false>(sp, t, yL, yR, fmn, fmx, zb[s.zout], cap, sh, acc);
+    }
+    double dv[8] = {acc.A, acc.B, (double)acc.pred, (double)acc.succ, 0, 0, 0, 0};
+    int dop[8] = {0, 0, 2, 1, 0, 0, 0, 0};
+    int64_t iv[8] = {(int64_t)acc.L, (int64_t)acc.G, 0, 0, 0, 0, 0, 0};
+    block_reduce<BLOCK, 4, 2>(dv, dop, iv, true, sh.d, sh.i);
+    if (tid == 0) {
+      CpState &w = sh.st;
+      if (gather) {
+        bdev_after_gather(w, sh.cur[0]);
+      } else {
+        EvalResult r;
+        r.A = dv[0]; r.B = dv[1]; r.pred = dv[2]; r.succ = dv[3];
+        r.L = iv[0]; r.G = iv[1];
+        r.written = sh.cur[0] + sh.cur[1];
+        bdev_after_eval(w, r, a.cfg);
+      }
+    }
+    __syncthreads();
+  }
+  if (sh.st.phase == PH_FINAL) {
+    const CpState &s = sh.st;
+    const T *W = s.wbuf < 0 ? x : (const T *)gb;
+    typename Traits<T>::Key key;
+    int64_t below, eq;
+    block_radix_select<T, BLOCK>(W, s.wlen, !s.on_bracket, (T)s.yL, (T)s.yR, s.k - s.cL,
+                                 sh.hist, sh.misc, key, below, eq);
+    if (tid == 0) bdev_after_final(sh.st, (double)Traits<T>::unkey(key), below, eq);
+    __syncthreads();
+  }
+  if (tid == 0) write_batch_result<T>(out, sh.st);
+  __syncthreads();
+}
+
+template <typename T, int BLOCK, int U>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_num_vgpr(128)))
+void batched_select_kernel(BatchArgs<T> a) {
+  __shared__ BShared<T, BLOCK> sh;
+  const int tid = threadIdx.x;
+  const int64_t count = a.count;
+  // Largest first: every workgroup sorts (size, index) in LDS by itself.
+  const bool sorted = count <= kBatchSortMax;
+  if (sorted) {
+    int64_t m = 1;
+    while (m < count) m <<= 1;
+    for (int64_t j = tid; j < m; j += BLOCK) {
+      uint64_t key = 0;
+      if (j < count) {
+        int64_t sz = a.sizes[j];
+        if (sz < 0) sz = 0;
+        if (sz > ((int64_t)1 << 50)) sz = (int64_t)1 << 50;
+        key = ((uint64_t)sz << 12) | (uint64_t)(kBatchSortMax - 1 - j);
+      }
+      sh.order[j] = key;
+    }
+    __syncthreads();
+    // bitonic sort, descending
+    for (int64_t kk = 2; kk <= m; kk <<= 1) {
+      for (int64_t jj = kk >> 1; jj > 0; jj >>= 1) {
+        for (int64_t i = tid; i < m; i += BLOCK) {
+          const int64_t p = i ^ jj;
+          if (p > i) {
+            const uint64_t x0 = sh.order[i], x1 = sh.order[p];
+            const bool desc = (i & kk) == 0;
+            if (desc ? (x0 < x1) : (x0 > x1)) {
+              sh.order[i] = x1;
+              sh.order[p] = x0;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+  for (;;) {
+    if (tid == 0) sh.job = (int64_t)atomic_add_relaxed(&a.ctl->queue, 1ull);
+    __syncthreads();
+    const int64_t j = sh.job;
+    __syncthreads();
+    if (j >= count) break;
+    const int64_t i = sorted ? (int64_t)(kBatchSortMax - 1 - (sh.order[j] & (kBatchSortMax - 1))) : j;
+    select_one<T, BLOCK, U>(a.ptrs[i], a.sizes[i], a.ks[i], a.out + i, a, sh);
+  }
+  // the last workgroup out resets the queue for the next launch (graph replays included)
+  if (tid == 0) {
+    const uint64_t e = atomic_add_relaxed(&a.ctl->exits, 1ull);
+    if (e == (uint64_t)gridDim.x - 1) {
+      __hip_atomic_store(&a.ctl->queue, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&a.ctl->exits, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_batched(const BatchArgs<T> &a, int grid, int block, hipStream_t stream) {
+  if (block == 256)
+    batched_select_kernel<T, 256, kSelectUnroll><<<dim3(grid), dim3(256), 0, stream>>>(a);
+  else if (block == 512)
+    batched_select_kernel<T, 512, kSelectUnroll><<<dim3(grid), dim3(512), 0, stream>>>(a);
+  else
+    batched_select_kernel<T, 1024, kSelectUnroll><<<dim3(grid), dim3(1024), 0, stream>>>(a);
+  return hipGetLastError();
+}
+
+template <typename T> int batched_max_blocks_per_cu(int block) {
+  int nb = 0;
+  hipError_t e;
+  if (block == 256)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batched_select_kernel<T, 256, kSelectUnroll>, 256, 0);
+  else if (block == 512)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batched_select_kernel<T, 512, kSelectUnroll>, 512, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batched_select_kernel<T, 1024, kSelectUnroll>, 1024, 0);
+  return e == hipSuccess ? nb : 0;
+}
+
+template hipError_t launch_batched<float>(const BatchArgs<float> &, int, int, hipStream_t);
+template hipError_t launch_batched<double>(const BatchArgs<double> &, int, int, hipStream_t);
+template int batched_max_blocks_per_cu<float>(int);
+template int batched_max_blocks_per_cu<double>(int);
+
+}  // namespace cps

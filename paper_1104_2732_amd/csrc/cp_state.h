@@ -52,7 +52,7 @@ namespace cps {
 enum Phase : int32_t { PH_PASS0 = 0, PH_EVAL = 1, PH_GATHER = 2, PH_FINAL = 3, PH_DONE = 4 };
 
 // status values mirror enum cps_status in cpselect.h
-enum : int32_t { ST_OK = 0, ST_NAN = 1, ST_TIMEOUT = 2, ST_INTERNAL = 3 };
+enum : int32_t { ST_OK = 0, ST_NAN = 1, ST_TIMEOUT = 2, ST_INTERNAL = 3, ST_BADARG = 4 };
 
 struct CpConfig {
   int32_t maxit;
@@ -64,6 +64,7 @@ struct CpConfig {
   int32_t use_bracket;
   int32_t pad0;
   double bracket_lo, bracket_hi;
+  int64_t split_cap;        // the first split needs population <= split_cap (0 = no limit)
 };
 
 // Results of pass 0 over the whole input (Section 4, step 0: min, max and sum in
@@ -251,7 +252,8 @@ CPS_HD inline void cp_plan(CpState &s, const CpConfig &c) {
   if (s.on_bracket) {
     s.split = 1;
     s.zout = 1 - s.wbuf;
-  } else if (c.theta > 0.0 && !s.has_inf && (double)pop <= c.theta * (double)s.n) {
+  } else if (c.theta > 0.0 && !s.has_inf && (double)pop <= c.theta * (double)s.n &&
+             (c.split_cap == 0 || pop <= c.split_cap)) {
     // (inputs holding infinities keep reading x until the gather: no clamped split)
     s.split = 1;
     s.filter = 1;

@@ -11,9 +11,13 @@ namespace cps {
 
 constexpr int kWave = 64;
 
+// Global-memory pointers: loads and stores through them compile to global_* instructions
+// (with a scalar base where the compiler can prove it) instead of flat_* ones.
+#define CPS_GLOBAL __attribute__((address_space(1)))
+
 template <typename T> struct Traits;
 template <> struct Traits<float> {
-  using Vec = float4;   // 16-byte loads
+  using Vec = float __attribute__((ext_vector_type(4)));  // 16-byte loads
   using Key = uint32_t;
   static constexpr int kVec = 4;
   static constexpr int kDigits = 4;   // 8-bit radix digits in the key
@@ -21,7 +25,7 @@ template <> struct Traits<float> {
   __device__ static float unkey(Key k) { return unkey32(k); }
 };
 template <> struct Traits<double> {
-  using Vec = double2;
+  using Vec = double __attribute__((ext_vector_type(2)));
   using Key = uint64_t;
   static constexpr int kVec = 2;
   static constexpr int kDigits = 8;
@@ -29,18 +33,22 @@ template <> struct Traits<double> {
   __device__ static double unkey(Key k) { return unkey64(k); }
 };
 
-template <typename T> __device__ inline void vec_to_arr(const typename Traits<T>::Vec &v, T *e);
-template <> __device__ inline void vec_to_arr<float>(const float4 &v, float *e) {
-  e[0] = v.x; e[1] = v.y; e[2] = v.z; e[3] = v.w;
-}
-template <> __device__ inline void vec_to_arr<double>(const double2 &v, double *e) {
-  e[0] = v.x; e[1] = v.y;
+template <typename T> __device__ inline void vec_to_arr(const typename Traits<T>::Vec &v, T *e) {
+#pragma unroll
+  for (int j = 0; j < Traits<T>::kVec; ++j) e[j] = v[j];
 }
 
 // ------------------------------------------------------------------ wave helpers
 
-__device__ inline uint64_t ballot(bool p) { return __ballot(p); }
+__device__ inline uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 __device__ inline uint32_t popc(uint64_t m) { return (uint32_t)__popcll(m); }
+// A pointer every lane of the wavefront holds, moved to scalar registers.
+template <typename P> __device__ inline P *uniform_ptr(P *p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (P *)(((uint64_t)hi << 32) | lo);
+}
 // number of set bits of m in lanes below this lane
 __device__ inline uint32_t lane_rank(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));

@@ -9,9 +9,20 @@
 
 namespace cps {
 
+// Launch shape of the single-array kernel (build-time tunables).
+#ifndef CPS_SELECT_BLOCK
+#define CPS_SELECT_BLOCK 1024
+#endif
+#ifndef CPS_SELECT_UNROLL
+#define CPS_SELECT_UNROLL 4
+#endif
+#ifndef CPS_SPLIT_UNROLL
+#define CPS_SPLIT_UNROLL 2
+#endif
 constexpr int kWaveSize = 64;
-constexpr int kSelectBlock = 512;
-constexpr int kSelectUnroll = 4;
+constexpr int kSelectBlock = CPS_SELECT_BLOCK;
+constexpr int kSelectUnroll = CPS_SELECT_UNROLL;  // 16-byte loads in flight per thread, plain passes
+constexpr int kSplitUnroll = CPS_SPLIT_UNROLL;    // the same for passes that also write
 constexpr int kGroup = 16;       // workgroups per first-level arrival counter
 constexpr int kMaxGroups = 256;  // so at most 4096 workgroups
 
@@ -44,6 +55,40 @@ template <typename T> struct SelectArgs {
   CpConfig cfg;
   int64_t spin_limit;
 };
+
+// ---- batched selection
+
+constexpr int kBatchSortMax = 4096;  // arrays sorted largest-first in LDS up to this count
+
+// Work queue of the batched kernel (each counter on its own 128-byte line).  Both reset
+// to zero when the last workgroup leaves, so consecutive launches need no clearing.
+struct BatchCtl {
+  uint64_t queue;
+  uint64_t pad0[15];
+  uint64_t exits;
+  uint64_t pad1[15];
+};
+
+template <typename T> struct BatchArgs {
+  const T *const *ptrs;  // device array of `count` device pointers
+  const int64_t *sizes;  // device array
+  const int64_t *ks;     // device array (1-based ranks)
+  int64_t count;
+  cps_result *out;       // device array of `count` results
+  BatchCtl *ctl;
+  T *zbuf;               // per workgroup: two split buffers of `cap` and a gather buffer
+  int64_t cap;
+  int64_t ws_stride;     // elements of workspace per workgroup
+  CpConfig cfg;
+};
+
+template <typename T>
+hipError_t launch_batched(const BatchArgs<T> &a, int grid, int block, hipStream_t stream);
+template <typename T> int batched_max_blocks_per_cu(int block);
+
+hipError_t launch_lms_residuals(const double *X, const double *y, const double *betas, int64_t n,
+                                int32_t p, int64_t m, double *R, const double **ptrs,
+                                int64_t *sizes, int64_t *ks, int cu_count, hipStream_t stream);
 
 template <typename T> hipError_t launch_select(const SelectArgs<T> &a, int grid, hipStream_t stream);
 template <typename T> int select_max_blocks_per_cu();

@@ -1,0 +1,83 @@
+// Least median of squares (Section 6): the lower median of the squared residuals of many
+// candidate parameter vectors, via the batched selection.
+//
+// The residual kernel forms r_i = (y_i - sum_j X_ij b_j)^2 for a group of candidates per
+// thread row: each X row and y_i are read once per group, the sum runs left to right in
+// j with every product and sum rounded on its own (the library is built without fused
+// multiply-add), and the squares land candidate-major in the workspace, one array of n
+// per candidate.  A second tiny kernel writes the batched call's descriptors on the device,
+// and the batched kernel then selects rank floor((n+1)/2) of every candidate's array.
+#include "cps_device.h"
+#include "cps_kernels.h"
+
+namespace cps {
+
+constexpr int kLmsGroup = 16;   // candidates per thread row
+constexpr int kLmsBlock = 256;
+
+template <int P>
+__global__ __launch_bounds__(kLmsBlock) void lms_residual_kernel(
+    const double *__restrict__ X, const double *__restrict__ y, const double *__restrict__ betas,
+    int64_t n, int32_t p, int64_t m, double *__restrict__ R) {
+  __shared__ double sb[kLmsGroup * 16];
+  const int64_t c0 = (int64_t)blockIdx.y * kLmsGroup;
+  const int nc = (int)((m - c0) < kLmsGroup ? (m - c0) : kLmsGroup);
+  for (int q = threadIdx.x; q < nc * p; q += kLmsBlock) sb[q] = betas[c0 * p + q];
+  __syncthreads();
+  const CPS_GLOBAL double *Xg = (const CPS_GLOBAL double *)X;
+  const CPS_GLOBAL double *yg = (const CPS_GLOBAL double *)y;
+  CPS_GLOBAL double *Rg = (CPS_GLOBAL double *)R;
+  for (int64_t i = (int64_t)blockIdx.x * kLmsBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kLmsBlock) {
+    double row[P > 0 ? P : 16];
+    const int pp = P > 0 ? P : p;
+#pragma unroll
+    for (int j = 0; j < (P > 0 ? P : 16); ++j)
+      if (j < pp) row[j] = Xg[i * pp + j];
+    const double yi = yg[i];
+    for (int c = 0; c < nc; ++c) {
+      const double *b = sb + c * pp;
+      double s = row[0] * b[0];
+#pragma unroll
+      for (int j = 1; j < (P > 0 ? P : 16); ++j) {
+        if (j < pp) {
+          const double prod = row[j] * b[j];
+          s = s + prod;
+        }
+      }
+      const double d = yi - s;
+      Rg[(c0 + c) * n + i] = d * d;
+    }
+  }
+}
+
+__global__ void lms_descriptor_kernel(const double *R, int64_t n, int64_t m, const double **ptrs,
+                                      int64_t *sizes, int64_t *ks) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < m;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    ptrs[c] = R + c * n;
+    sizes[c] = n;
+    ks[c] = (n + 1) / 2;
+  }
+}
+
+hipError_t launch_lms_residuals(const double *X, const double *y, const double *betas, int64_t n,
+                                int32_t p, int64_t m, double *R, const double **ptrs,
+                                int64_t *sizes, int64_t *ks, int cu_count, hipStream_t stream) {
+  const int64_t groups = (m + kLmsGroup - 1) / kLmsGroup;
+  int64_t bx = (n + kLmsBlock - 1) / kLmsBlock;
+  const int64_t want = (int64_t)cu_count * 8 / (groups < 1 ? 1 : groups) + 1;
+  if (bx > want) bx = want;
+  if (bx < 1) bx = 1;
+  const dim3 grid((unsigned)bx, (unsigned)groups);
+  if (p == 8)
+    lms_residual_kernel<8><<<grid, dim3(kLmsBlock), 0, stream>>>(X, y, betas, n, p, m, R);
+  else
+    lms_residual_kernel<0><<<grid, dim3(kLmsBlock), 0, stream>>>(X, y, betas, n, p, m, R);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  lms_descriptor_kernel<<<dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream>>>(R, n, m, ptrs, sizes, ks);
+  return hipGetLastError();
+}
+
+}  // namespace cps

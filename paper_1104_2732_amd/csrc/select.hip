@@ -21,6 +21,7 @@
 // launched cooperatively, which guarantees that every workgroup is resident.
 #include "cps_device.h"
 #include "cps_kernels.h"
+#include "cps_passes.h"
 
 namespace cps {
 
@@ -37,107 +38,6 @@ __device__ __noinline__ void dev_after_gather(CpState &s, int64_t gathered) {
 }
 __device__ __noinline__ void dev_after_final(CpState &s, double v, int64_t below, int64_t eq) {
   cp_after_final(s, v, below, eq);
-}
-
-// ------------------------------------------------------------------ per-element work
-
-template <typename T> __device__ inline T t_inf();
-template <> __device__ inline float t_inf<float>() { return __builtin_inff(); }
-template <> __device__ inline double t_inf<double>() { return __builtin_inf(); }
-
-template <typename T> __device__ inline T tmin(T a, T b) { return a < b ? a : b; }
-template <typename T> __device__ inline T tmax(T a, T b) { return a > b ? a : b; }
-
-template <typename T> struct EvalAcc {
-  double A, B;
-  T pred, succ;
-  uint64_t L, G;  // wave-uniform
-};
-
-// Evaluate one element at t.  Invalid lanes contribute nothing.
-template <typename T, bool CLAMP>
-__device__ inline void eval_one(T &v, bool valid, T t, T fmin, T fmax, T &a_part, T &b_part,
-                                EvalAcc<T> &acc) {
-  if (CLAMP) v = tmin(tmax(v, fmin), fmax);
-  const bool l = valid && (v < t);
-  const bool g = valid && (v > t);
-  const T d = v - t;
-  a_part += g ? d : T(0);
-  b_part -= l ? d : T(0);
-  acc.pred = tmax(acc.pred, l ? v : -t_inf<T>());
-  acc.succ = tmin(acc.succ, g ? v : t_inf<T>());
-  acc.L += popc(ballot(l));
-  acc.G += popc(ballot(g));
-}
-
-template <typename T> struct P0Acc {
-  double sum;
-  T mn, mx;
-  uint32_t cmn, cmx;
-  uint64_t nnan, nneg, npos;  // wave-uniform
-  uint64_t cle_a, clt_b;      // wave-uniform
-  double Aa, Ba, Ab, Bb;
-};
-
-// Pass 0 on one element.  CLASSIFY: separate NaN and infinities from the finite values
-// (the slow variant); otherwise only NaN is detected and infinities, if any, show up as
-// an infinite extreme, which makes the state machine ask for the slow variant.
-template <typename T, bool CLASSIFY, bool BRACKET>
-__device__ inline void pass0_one(T v, bool valid, T ba, T bb, T &s_part, T &aa, T &bA, T &ab,
-                                 T &bB, P0Acc<T> &acc) {
-  const bool isnan_ = valid && (v != v);
-  acc.nnan += popc(ballot(isnan_));
-  bool fin = valid;
-  if (CLASSIFY) {
-    const bool ni = valid && (v == -t_inf<T>());
-    const bool pi = valid && (v == t_inf<T>());
-    acc.nneg += popc(ballot(ni));
-    acc.npos += popc(ballot(pi));
-    fin = valid && !isnan_ && !ni && !pi;
-  }
-  const bool lt = fin && v < acc.mn, eqn = fin && v == acc.mn;
-  acc.cmn = lt ? 1u : acc.cmn + (eqn ? 1u : 0u);
-  acc.mn = lt ? v : acc.mn;
-  const bool gt = fin && v > acc.mx, eqx = fin && v == acc.mx;
-  acc.cmx = gt ? 1u : acc.cmx + (eqx ? 1u : 0u);
-  acc.mx = gt ? v : acc.mx;
-  s_part += fin ? v : T(0);
-  if (BRACKET) {
-    acc.cle_a += popc(ballot(valid && v <= ba));
-    acc.clt_b += popc(ballot(valid && v < bb));
-    aa += (fin && v > ba) ? v - ba : T(0);
-    bA += (fin && v < ba) ? ba - v : T(0);
-    ab += (fin && v > bb) ? v - bb : T(0);
-    bB += (fin && v < bb) ? bb - v : T(0);
-  }
-}
-
-// ------------------------------------------------------------------ working-set geometry
-
-template <typename T> struct Span {
-  const typename Traits<T>::Vec *V;  // aligned body
-  const T *W;
-  int64_t m, head, nvec, tail_start, nedge;
-};
-
-template <typename T> __device__ inline Span<T> make_span(const T *W, int64_t m) {
-  Span<T> s;
-  s.W = W;
-  s.m = m;
-  const uintptr_t addr = (uintptr_t)W;
-  int64_t head = (int64_t)(((16u - (addr & 15u)) & 15u) / sizeof(T));
-  if (head > m) head = m;
-  s.head = head;
-  s.V = reinterpret_cast<const typename Traits<T>::Vec *>(W + head);
-  s.nvec = (m - head) / Traits<T>::kVec;
-  s.tail_start = head + s.nvec * Traits<T>::kVec;
-  s.nedge = head + (m - s.tail_start);
-  return s;
-}
-
-// Edge element i (< nedge): the unaligned head, then the tail.
-template <typename T> __device__ inline int64_t edge_index(const Span<T> &s, int64_t i) {
-  return i < s.head ? i : s.tail_start + (i - s.head);
 }
 
 // How the threads of a workgroup walk the working set.  BLOCK mode: the whole input,
@@ -180,9 +80,9 @@ __device__ inline bool goes_high(T v, bool valid, T t, T hi_ex) {
 // Per-wavefront split output: the low part grows up from the start of the wavefront's
 // region, the high part down from its end.  The cursors are wave-uniform.
 template <typename T> struct WaveOut {
-  T *region;
-  int64_t Rw;
-  int64_t lo, hi;
+  CPS_GLOBAL T *region;  // wave-uniform
+  uint32_t top;          // Rw - 1
+  uint32_t lo, hi;       // wave-uniform cursors (a region holds fewer than 2^32 elements)
 };
 
 template <typename T, bool FILTER>
@@ -193,7 +93,7 @@ __device__ inline void split_one(T v, bool valid, T t, T yL, T yR, WaveOut<T> &o
   o.lo += popc(ml);
   const bool r = goes_high<T, FILTER>(v, valid, t, yR);
   const uint64_t mr = ballot(r);
-  if (r) o.region[o.Rw - 1 - (o.hi + (int64_t)lane_rank(mr))] = v;
+  if (r) o.region[o.top - (o.hi + lane_rank(mr))] = v;
   o.hi += popc(mr);
 }
 
@@ -347,79 +247,6 @@ __device__ inline void gather_from_input(const Walk<T> &wk, T yL, T yR, T *zf,
   }
 }
 
-// Block reduction of up to 8 double fields (op per field: 0 sum, 1 min, 2 max) and
-// 8 int64 sums.  The int fields are either per-thread or wave-uniform (`iuniform`).
-// The result is valid in thread 0.  Fixed order, hence deterministic.
-template <int BLOCK, int ND, int NI>
-__device__ inline void block_reduce(double (&dv)[8], const int (&dop)[8], int64_t (&iv)[8],
-                                    bool iuniform, double (&sd)[8][BLOCK / kWave],
-                                    int64_t (&si)[8][BLOCK / kWave]) {
-  const int tid = threadIdx.x, wv = tid / kWave, lane = tid % kWave;
-#pragma unroll
-  for (int f = 0; f < ND; ++f) {
-    if (dop[f] == 0) dv[f] = wave_sum(dv[f]);
-    else if (dop[f] == 1) dv[f] = wave_min(dv[f]);
-    else dv[f] = wave_max(dv[f]);
-  }
-  if (!iuniform) {
-#pragma unroll
-    for (int f = 0; f < NI; ++f) iv[f] = wave_sum_i64(iv[f]);
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int f = 0; f < ND; ++f) sd[f][wv] = dv[f];
-#pragma unroll
-    for (int f = 0; f < NI; ++f) si[f][wv] = iv[f];
-  }
-  __syncthreads();
-  if (tid == 0) {
-#pragma unroll
-    for (int f = 0; f < ND; ++f) {
-      double r = sd[f][0];
-      for (int w = 1; w < BLOCK / kWave; ++w) {
-        const double x = sd[f][w];
-        r = dop[f] == 0 ? r + x : (dop[f] == 1 ? fmin(r, x) : fmax(r, x));
-      }
-      dv[f] = r;
-    }
-#pragma unroll
-    for (int f = 0; f < NI; ++f) {
-      int64_t r = 0;
-      for (int w = 0; w < BLOCK / kWave; ++w) r += si[f][w];
-      iv[f] = r;
-    }
-  }
-  __syncthreads();
-}
-
-// Fold (min, multiplicity) and (max, multiplicity) pairs over the workgroup; valid in
-// thread 0.
-template <int BLOCK>
-__device__ inline void block_pair_fold(double &mn, int64_t &cmn, double &mx, int64_t &cmx,
-                                       double (&sd)[8][BLOCK / kWave],
-                                       int64_t (&si)[8][BLOCK / kWave]) {
-  const int tid = threadIdx.x, wv = tid / kWave, lane = tid % kWave;
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) {
-    const double m2 = __shfl_xor(mn, o), x2 = __shfl_xor(mx, o);
-    const int64_t c2 = __shfl_xor(cmn, o), d2 = __shfl_xor(cmx, o);
-    if (m2 < mn) { mn = m2; cmn = c2; } else if (m2 == mn) cmn += c2;
-    if (x2 > mx) { mx = x2; cmx = d2; } else if (x2 == mx) cmx += d2;
-  }
-  if (lane == 0) {
-    sd[0][wv] = mn; si[0][wv] = cmn; sd[1][wv] = mx; si[1][wv] = cmx;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    mn = sd[0][0]; cmn = si[0][0]; mx = sd[1][0]; cmx = si[1][0];
-    for (int w = 1; w < BLOCK / kWave; ++w) {
-      if (sd[0][w] < mn) { mn = sd[0][w]; cmn = si[0][w]; } else if (sd[0][w] == mn) cmn += si[0][w];
-      if (sd[1][w] > mx) { mx = sd[1][w]; cmx = si[1][w]; } else if (sd[1][w] == mx) cmx += si[1][w];
-    }
-  }
-  __syncthreads();
-}
-
 template <typename T>
 __device__ inline void write_result(const SelectArgs<T> &a, const CpState &s) {
   cps_result r;
@@ -475,7 +302,7 @@ template <typename T, int BLOCK, int UNROLL>
 __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, int phase,
                                       bool p0_slow, double (&dv)[8], int64_t (&iv)[8]) {
   // passes that also write or check a bracket hold fewer vectors in flight
-  constexpr int SU = UNROLL / 2 > 0 ? UNROLL / 2 : 1;
+  constexpr int SU = kSplitUnroll;
   constexpr int WPB = BLOCK / kWave;
   const int tid = threadIdx.x, wv = tid / kWave, lane = tid % kWave;
   const int bid = blockIdx.x;
@@ -556,13 +383,15 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
       }
       __syncthreads();
       const uint64_t off = sh.gbase[wv];
-      for (int64_t i = lane; i < len; i += kWave) a.zf[off + i] = wk.sp.W[i];
+      CPS_GLOBAL T *zf = (CPS_GLOBAL T *)a.zf;
+      for (int64_t i = lane; i < len; i += kWave) zf[off + i] = wk.sp.W[i];
       if (lane == 0) written = len;
     }
   } else {
     WaveOut<T> o;
-    o.region = a.z[s.zout] + ((int64_t)bid * WPB + wv) * Rw;
-    o.Rw = Rw;
+    const int wvu = __builtin_amdgcn_readfirstlane(wv);
+    o.region = (CPS_GLOBAL T *)uniform_ptr(a.z[s.zout] + ((int64_t)bid * WPB + wvu) * Rw);
+    o.top = (uint32_t)(Rw - 1);
     o.lo = o.hi = 0;
     const bool clamp = s.has_inf && s.wbuf < 0;
     if (!s.split) {
@@ -576,7 +405,7 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
     if (s.split && lane == 0) {
       sh.wseg[0][wv] = o.lo;
       sh.wseg[1][wv] = o.hi;
-      written = o.lo + o.hi;
+      written = (int64_t)o.lo + o.hi;
     }
   }
   dv[0] = acc.A; dv[1] = acc.B; dv[2] = (double)acc.pred; dv[3] = (double)acc.succ;

@@ -1,0 +1,157 @@
+"""GPU parity of select_kth_batched against the CPU oracle, array by array.
+
+Every array's selected value is compared bit for bit and its counts exactly
+(Section 1), over mixed sizes and distributions, every launch shape and forced
+split/gather paths, invalid descriptors (status only for that array), repeated
+launches (the queue resets itself), graph capture with replays, and a sample
+of the full-size workload (4096 lognormal arrays, sizes log-uniform in
+[10^3, 10^6], median ranks) with the defining invariant checked for all.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from tests.gpu_util import assert_same_result
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sel():
+    import paper_1104_2732_amd as cps
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    s = cps.Selector(0)
+    yield s
+    s.close()
+
+
+def _mixed_batch(dtype, count, seed, max_size=60_000):
+    rng = np.random.default_rng(seed)
+    dists = ["uniform", "normal", "cauchy", "quantized_normal", "lognormal", "smallint", "mix2",
+             "constant"]
+    arrays, ks = [], []
+    for i in range(count):
+        if i < 4:
+            n = i + 1
+        else:
+            n = int(np.floor(10 ** rng.uniform(0, np.log10(max_size))))
+        x = workloads.single_array(dists[i % len(dists)], n, dtype, seed=seed * 1000 + i,
+                                   tag="gpu-batched")
+        arrays.append(x)
+        choice = i % 4
+        k = [1, n, (n + 1) // 2, int(rng.integers(1, n + 1))][choice]
+        ks.append(k)
+    return arrays, ks
+
+
+def _check_all(res, arrays, ks, oracle_mod, ctx):
+    for i, (x, k) in enumerate(zip(arrays, ks)):
+        r = {name: res[i][name].item() for name in res.dtype.names}
+        assert_same_result(r, oracle_mod.select_kth(x, k), f"{ctx} array {i} n={x.size} k={k}")
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("opt", [
+    dict(),
+    dict(block_threads=256),
+    dict(block_threads=1024),
+    dict(block_threads=512, split_capacity=64, final_threshold=16),
+    dict(block_threads=256, split_capacity=4096, final_threshold=64, partition_fraction=1.0),
+    dict(block_threads=1024, final_threshold=8, partition_fraction=0.0),
+    dict(block_threads=512, maxit=0, final_threshold=32, split_capacity=128),
+    dict(block_threads=256, blocks_per_cu=1),
+])
+def test_batched_parity(sel, oracle_mod, dtype, opt):
+    import paper_1104_2732_amd as cps
+    arrays, ks = _mixed_batch(dtype, 150, seed=len(opt) + (7 if dtype == np.float64 else 0))
+    dev = [torch.from_numpy(a).cuda() for a in arrays]
+    o = cps.default_batch_options(**opt)
+    print(f"case batched {np.dtype(dtype).name} {opt}", flush=True)
+    res = sel.select_kth_batched(dev, ks, o)
+    _check_all(res, arrays, ks, oracle_mod, str(opt))
+
+
+def test_invalid_descriptors(sel, oracle_mod):
+    import paper_1104_2732_amd as cps
+    arrays, ks = _mixed_batch(np.float32, 20, seed=3)
+    dev = [torch.from_numpy(a).cuda() for a in arrays]
+    ptrs, sizes, kk, code = sel.batch_descriptors(dev, ks)
+    bad = {3: "k0", 5: "kbig", 7: "null", 9: "size0", 11: "unaligned"}
+    kk[3] = 0
+    kk[5] = sizes[5] + 1
+    ptrs[7] = 0
+    sizes[9] = 0
+    ptrs[11] = ptrs[11] + 2  # not a multiple of the element size
+    out = sel.new_results(len(dev))
+    print("case batched invalid descriptors", flush=True)
+    sel.select_kth_batched_async(ptrs, sizes, kk, len(dev), code, out)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy().view(cps.RESULT_DTYPE)
+    for i, (x, k) in enumerate(zip(arrays, ks)):
+        if i in bad:
+            assert res[i]["status"] == cps.STATUS_BADARG, (i, bad[i])
+        else:
+            r = {name: res[i][name].item() for name in res.dtype.names}
+            assert_same_result(r, oracle_mod.select_kth(x, k), f"array {i}")
+
+
+def test_repeated_launches_and_graph_replay(sel, oracle_mod):
+    import paper_1104_2732_amd as cps
+    arrays, ks = _mixed_batch(np.float32, 64, seed=11)
+    dev = [torch.from_numpy(a).cuda() for a in arrays]
+    ptrs, sizes, kk, code = sel.batch_descriptors(dev, ks)
+    refs = [oracle_mod.select_kth(x, k) for x, k in zip(arrays, ks)]
+    out = sel.new_results(len(dev))
+    print("case batched repeated launches", flush=True)
+    for _ in range(3):
+        out.zero_()
+        sel.select_kth_batched_async(ptrs, sizes, kk, len(dev), code, out)
+        torch.cuda.synchronize()
+        res = out.cpu().numpy().view(cps.RESULT_DTYPE)
+        for i, ref in enumerate(refs):
+            assert_same_result({n: res[i][n].item() for n in res.dtype.names}, ref, f"array {i}")
+    # capture one launch in a graph and replay it with eager work in between
+    sel.reserve_batched(code)
+    print("case batched graph capture", flush=True)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            sel.select_kth_batched_async(ptrs, sizes, kk, len(dev), code, out)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        out.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        res = out.cpu().numpy().view(cps.RESULT_DTYPE)
+        for i, ref in enumerate(refs):
+            assert_same_result({n: res[i][n].item() for n in res.dtype.names}, ref,
+                               f"replay {rep} array {i}")
+        _ = (dev[0] * 2).sum().item()  # eager work between replays
+
+
+def test_full_size_workload_sampled(sel, oracle_mod):
+    """4096 lognormal float32 arrays, sizes log-uniform in [1e3, 1e6], median ranks."""
+    import paper_1104_2732_amd as cps
+    arrays, sizes, ks = workloads.batched_arrays(4096, seed=0)
+    dev = [torch.from_numpy(a).cuda() for a in arrays]
+    print(f"case batched full workload total={int(sizes.sum())}", flush=True)
+    res = sel.select_kth_batched(dev, ks)
+    assert np.all(res["status"] == 0)
+    # the defining invariant for every array (Section 1), computed on the host
+    for i, (x, k) in enumerate(zip(arrays, ks)):
+        v = np.float32(res[i]["value"])
+        less = int(np.count_nonzero(x < v))
+        eq = int(np.count_nonzero(x == v))
+        assert less < k <= less + eq and (less, eq) == (res[i]["less"], res[i]["equal"]), i
+    # the oracle on a seeded sample
+    rng = np.random.default_rng(0)
+    for i in rng.choice(4096, size=64, replace=False):
+        r = {n: res[i][n].item() for n in res.dtype.names}
+        assert_same_result(r, oracle_mod.select_kth(arrays[i], int(ks[i])), f"array {i}")
+    del dev

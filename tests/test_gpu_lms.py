@@ -1,0 +1,85 @@
+"""GPU parity of lms_median_sq_residuals against the CPU oracle (Section 6).
+
+The residuals are formed left to right without fused multiply-add on both
+sides, so the medians must agree bit for bit and the counts exactly.  Small
+problems are compared candidate by candidate; the full-size problem (2^20 rows,
+p = 8, 1024 candidates, 30 % of rows shifted) on a seeded sample of candidates,
+and every candidate through the defining invariant (Section 1) against
+residuals recomputed by the oracle.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from tests.gpu_util import assert_same_result
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sel():
+    import paper_1104_2732_amd as cps
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    s = cps.Selector(0)
+    yield s
+    s.close()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("n,p,m", [(1, 1, 1), (7, 3, 5), (1001, 8, 40), (50_000, 8, 33),
+                                   (20_001, 5, 17), (4096, 16, 3)])
+def test_lms_small(sel, oracle_mod, n, p, m):
+    X, y, beta, betas = workloads.lms_problem(n, p, m, seed=n + p, contamination=0.3) if n >= p \
+        else (np.random.default_rng(0).standard_normal((n, p)), np.zeros(n), None,
+              np.random.default_rng(1).standard_normal((m, p)))
+    print(f"case lms n={n} p={p} m={m}", flush=True)
+    res = sel.lms_median_sq_residuals(_dev(X), _dev(y), _dev(betas))
+    ref = oracle_mod.lms_median_sq(X, y, betas)
+    for c in range(m):
+        r = {f: res[c][f].item() for f in res.dtype.names}
+        assert_same_result(r, ref[c], f"candidate {c}")
+
+
+def test_lms_exact_fit_zero_median(sel):
+    rng = np.random.default_rng(5)
+    n, p = 30_001, 8
+    X = rng.standard_normal((n, p))
+    beta = rng.standard_normal(p)
+    s = X[:, 0] * beta[0]
+    for j in range(1, p):
+        s = s + X[:, j] * beta[j]
+    y = s.copy()
+    bad = rng.choice(n, size=int(0.3 * n), replace=False)
+    y[bad] += 10.0
+    res = sel.lms_median_sq_residuals(_dev(X), _dev(y), _dev(beta[None, :]))
+    assert res[0]["status"] == 0 and res[0]["value"] == 0.0
+    assert res[0]["less"] == 0 and res[0]["equal"] == n - bad.size
+
+
+def test_lms_full_size_sampled(sel, oracle_mod):
+    n, p, m = 1 << 20, 8, 1024
+    X, y, beta, betas = workloads.lms_problem(n, p, m, seed=0)
+    print("case lms full size", flush=True)
+    res = sel.lms_median_sq_residuals(_dev(X), _dev(y), _dev(betas))
+    assert np.all(res["status"] == 0)
+    k = (n + 1) // 2
+    rng = np.random.default_rng(1)
+    sample = rng.choice(m, size=12, replace=False)
+    for c in sample:
+        r = oracle_mod.lms_residuals(X, y, betas[c])
+        v = res[c]["value"]
+        less = int(np.count_nonzero(r < v))
+        eq = int(np.count_nonzero(r == v))
+        assert less < k <= less + eq and (less, eq) == (res[c]["less"], res[c]["equal"])
+    for c in sample[:3]:
+        ref = oracle_mod.lms_median_sq(X, y, betas[c:c + 1])[0]
+        assert_same_result({f: res[c][f].item() for f in res.dtype.names}, ref, f"candidate {c}")
+    # the estimate: the candidate with the least median of squares fits the clean rows
+    best = int(np.argmin(res["value"]))
+    assert np.max(np.abs(betas[best] - beta)) < 0.5
