@@ -200,3 +200,133 @@ def lms_problem(n: int, p: int = 8, m: int = 1024, seed: int = 0, contamination:
         betas[j] = sol
         j += 1
     return np.ascontiguousarray(X), y, beta_true, betas
+
+
+# ---------------------------------------------------------------------------
+# Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as
+# 1, 2, 3", SC'11) and the mixture arrays of the learned-proposal workload.
+#
+# The library's training generator draws the same arrays on the GPU from its own
+# implementation of the same published definition; both use only integer
+# arithmetic and correctly rounded double-precision +, -, *, /, floor and scaling by
+# powers of two, so the two sides agree bit for bit.
+
+PHILOX_M0 = 0xD2511F53
+PHILOX_M1 = 0xCD9E8D57
+PHILOX_W0 = 0x9E3779B9
+PHILOX_W1 = 0xBB67AE85
+_MASK32 = np.uint64(0xFFFFFFFF)
+
+
+def philox4x32_10(c0, c1, c2, c3, k0, k1):
+    """Vectorised Philox4x32 with 10 rounds; arguments are uint32 arrays (or scalars)."""
+    c0, c1, c2, c3 = (np.asarray(v, dtype=np.uint64) & _MASK32 for v in (c0, c1, c2, c3))
+    k0 = np.asarray(k0, dtype=np.uint64) & _MASK32
+    k1 = np.asarray(k1, dtype=np.uint64) & _MASK32
+    for _ in range(10):
+        p0 = np.uint64(PHILOX_M0) * c0
+        p1 = np.uint64(PHILOX_M1) * c2
+        hi0, lo0 = p0 >> np.uint64(32), p0 & _MASK32
+        hi1, lo1 = p1 >> np.uint64(32), p1 & _MASK32
+        c0, c1, c2, c3 = (hi1 ^ c1 ^ k0) & _MASK32, lo1, (hi0 ^ c3 ^ k1) & _MASK32, lo0
+        k0 = (k0 + np.uint64(PHILOX_W0)) & _MASK32
+        k1 = (k1 + np.uint64(PHILOX_W1)) & _MASK32
+    return tuple(v.astype(np.uint32) for v in (c0, c1, c2, c3))
+
+
+_LOG2E = 1.4426950408889634
+_LN2 = 0.6931471805599453
+_INV_FACT = [1.0]
+for _j in range(1, 15):
+    _INV_FACT.append(_INV_FACT[-1] / _j)
+
+
+def exp_basic(z: np.ndarray) -> np.ndarray:
+    """exp from IEEE basic operations only: 2^floor(t) * e^(f ln 2), t = z log2(e), f = t - floor(t),
+    with e^(f ln 2) as its Taylor polynomial of degree 14 in Horner form."""
+    z = np.asarray(z, dtype=np.float64)
+    t = z * _LOG2E
+    kf = np.floor(t)
+    g = (t - kf) * _LN2
+    p = np.full_like(g, _INV_FACT[14])
+    for j in range(13, -1, -1):
+        p = p * g + _INV_FACT[j]
+    return np.ldexp(p, kf.astype(np.int64))
+
+
+MIX_GAUSS, MIX_LOGNORMAL, MIX_UNIFORM = 0, 1, 2
+
+
+def mixture_params(seed: int, n: int):
+    """Random mixture of 1-4 components (Gaussian, lognormal, uniform) and a uniform rank k.
+
+    Returns a dict: weights (cumulative, float64), types, p1, p2 (per component) and k.
+    Gaussian: p1 = mean ~ U(-100, 100), p2 = sd = 10^U(-2, 1); lognormal: p1 ~ U(-2, 2),
+    p2 ~ U(0.25, 1.5) (log-mean, log-sd); uniform on [p1, p1 + p2], p1 ~ U(-100, 100),
+    p2 = 10^U(-2, 2).  Weights are Dirichlet(1).
+    """
+    rng = generator("mixture:params", seed)
+    c = int(rng.integers(1, 5))
+    w = rng.dirichlet(np.ones(c))
+    cum = np.cumsum(w)
+    cum[-1] = 1.0
+    types = rng.integers(0, 3, c)
+    p1 = np.empty(c)
+    p2 = np.empty(c)
+    for j in range(c):
+        if types[j] == MIX_GAUSS:
+            p1[j] = rng.uniform(-100, 100)
+            p2[j] = 10.0 ** rng.uniform(-2, 1)
+        elif types[j] == MIX_LOGNORMAL:
+            p1[j] = rng.uniform(-2, 2)
+            p2[j] = rng.uniform(0.25, 1.5)
+        else:
+            p1[j] = rng.uniform(-100, 100)
+            p2[j] = 10.0 ** rng.uniform(-2, 2)
+    k = int(rng.integers(1, n + 1))
+    cum4 = np.ones(4)
+    cum4[:c] = cum
+    t4 = np.zeros(4, dtype=np.int32)
+    t4[:c] = types
+    a4 = np.zeros(4)
+    a4[:c] = p1
+    b4 = np.zeros(4)
+    b4[:c] = p2
+    return {"ncomp": c, "cum": cum4, "types": t4, "p1": a4, "p2": b4, "k": k}
+
+
+def mixture_array(params: dict, n: int, seed: int, array_id: int = 0) -> np.ndarray:
+    """Element i of array (seed, array_id): four Philox4x32-10 blocks at counters
+    (i mod 2^32, i div 2^32, array_id, j), j = 0..3, key (seed mod 2^32, seed div 2^32).
+    Blocks 0-2 give twelve 24-bit uniforms u = (r >> 8) 2^-24, summed minus 6 into an
+    approximately normal g (exact in double precision); block 3's first word picks the
+    component (r 2^-32 against the cumulative weights) and its second word is the uniform
+    of a uniform component.  Values are formed in double precision and rounded to float32.
+    """
+    i = np.arange(n, dtype=np.uint64)
+    lo = (i & _MASK32).astype(np.uint32)
+    hi = (i >> np.uint64(32)).astype(np.uint32)
+    k0 = np.uint32(seed & 0xFFFFFFFF)
+    k1 = np.uint32((seed >> 32) & 0xFFFFFFFF)
+    a = np.uint32(array_id)
+    g = np.zeros(n)
+    for j in range(3):
+        r = philox4x32_10(lo, hi, np.full(n, a, np.uint32), np.full(n, j, np.uint32), k0, k1)
+        for word in r:
+            g = g + (word >> np.uint32(8)).astype(np.float64) * (2.0 ** -24)
+    g = g - 6.0
+    r3 = philox4x32_10(lo, hi, np.full(n, a, np.uint32), np.full(n, 3, np.uint32), k0, k1)
+    uc = r3[0].astype(np.float64) * (2.0 ** -32)
+    uu = r3[1].astype(np.float64) * (2.0 ** -32)
+    comp = np.zeros(n, dtype=np.int64)
+    for j in range(3):
+        comp += (uc >= params["cum"][j]).astype(np.int64)
+    comp = np.minimum(comp, params["ncomp"] - 1)
+    t = params["types"][comp]
+    p1 = params["p1"][comp]
+    p2 = params["p2"][comp]
+    gauss = p1 + p2 * g
+    logn = exp_basic(p1 + p2 * g)
+    unif = p1 + p2 * uu
+    v = np.where(t == MIX_GAUSS, gauss, np.where(t == MIX_LOGNORMAL, logn, unif))
+    return v.astype(np.float32)
