@@ -11,6 +11,15 @@ HBM roofline of the selection kernel and the CPU oracle timed on a bounded
 sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+HBM traffic of the selection kernel comes from two rocprofv3 counter runs of
+this same program with --copy-calibration (FETCH_SIZE, then WRITE_SIZE), each
+scaled by what the counter reads for a plain elementwise copy of 2^28 float32
+values (1 GiB read, 1 GiB written) in the same run:
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR_F -- python3 bench.py \
+        --steps 1 --warmup 0 --no-cpu-baseline --copy-calibration
+    rocprofv3 --pmc WRITE_SIZE ... (same, into DIR_W)
+    python bench.py --traffic-from DIR_F DIR_W   # writes the traffic record
 """
 import argparse
 import hashlib
@@ -53,6 +62,46 @@ def load_traffic():
     return t.get("bytes_per_launch")
 
 
+def _counter_rows(directory: str, counter: str):
+    """(kernel name, value in KiB) per dispatch from a rocprofv3 counter-collection CSV tree."""
+    import csv
+    rows = []
+    for root, _, files in os.walk(directory):
+        for fn in files:
+            if not fn.endswith("counter_collection.csv"):
+                continue
+            with open(os.path.join(root, fn), newline="") as f:
+                for r in csv.DictReader(f):
+                    if r.get("Counter_Name") == counter:
+                        rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return rows
+
+
+def traffic_from(fetch_dir: str, write_dir: str) -> dict:
+    """Calibrate FETCH_SIZE and WRITE_SIZE on the copy of known size and scale the selection
+    kernel's per-dispatch readings; writes and returns the traffic record."""
+    copy_bytes = float(4 << 28)
+    out = {"kernel_source_hash": kernel_source_hash(), "kernel": "cp_select_kernel"}
+    per_launch = 0.0
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = _counter_rows(d, counter)
+        copies = [v for (name, v) in rows if "elementwise" in name and v * 1024 > 0.5 * copy_bytes]
+        sel = [v for (name, v) in rows if "cp_select_kernel" in name]
+        if not copies or not sel:
+            raise SystemExit(f"{counter}: no calibration copy or no selection dispatch in {d}")
+        factor = copy_bytes / (float(np.mean(copies)) * 1024.0)
+        kib = float(np.mean(sel))
+        out[counter] = {"copy_KiB": float(np.mean(copies)), "factor": factor,
+                        "select_KiB_per_dispatch": kib, "select_dispatches": len(sel),
+                        "bytes_per_launch": kib * 1024.0 * factor}
+        per_launch += kib * 1024.0 * factor
+    out["bytes_per_launch"] = per_launch
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    return out
+
+
 def cpu_baseline(budget_s: float = 20.0):
     """The CPU oracle on a bounded sample of the same workload, one thread, ~budget_s seconds:
     the 32 n=2^24 cases, then n=2^28 float32 cases while the budget lasts."""
@@ -86,7 +135,14 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain 1 GiB elementwise copy first (counter calibration)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the traffic record from two rocprofv3 counter runs and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        print(json.dumps(traffic_from(*args.traffic_from)))
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build runs the selection on a single "
@@ -117,6 +173,14 @@ def main():
         sel.reserve(1 << max(SIZES), cps.CPS_F32 if dtype == np.float32 else cps.CPS_F64)
     torch.cuda.synchronize()
     gen_s = time.time() - t_gen
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     outs = sel.new_results(len(inputs))
     res_views = [outs[i * 48:(i + 1) * 48] for i in range(len(inputs))]

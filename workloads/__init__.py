@@ -255,44 +255,55 @@ def exp_basic(z: np.ndarray) -> np.ndarray:
 
 
 MIX_GAUSS, MIX_LOGNORMAL, MIX_UNIFORM = 0, 1, 2
+_LN10 = 2.302585092994046
 
 
-def mixture_params(seed: int, n: int):
-    """Random mixture of 1-4 components (Gaussian, lognormal, uniform) and a uniform rank k.
+def mixture_params(seed: int, array_id: int, n: int):
+    """Random mixture of 1-4 components (Gaussian, lognormal, uniform) and a uniform rank k,
+    for array (seed, array_id) of size n.
 
-    Returns a dict: weights (cumulative, float64), types, p1, p2 (per component) and k.
-    Gaussian: p1 = mean ~ U(-100, 100), p2 = sd = 10^U(-2, 1); lognormal: p1 ~ U(-2, 2),
-    p2 ~ U(0.25, 1.5) (log-mean, log-sd); uniform on [p1, p1 + p2], p1 ~ U(-100, 100),
-    p2 = 10^U(-2, 2).  Weights are Dirichlet(1).
+    Twenty words w[0..19] come from the Philox4x32-10 blocks at counters (0, 0, array_id, j),
+    j = 4..8 (disjoint from the element counters), key (seed mod 2^32, seed div 2^32):
+      ncomp = 1 + (w0 >> 30); type_c = (3 w[1+c]) >> 32;
+      ua = w[5+c] 2^-32, ub = w[9+c] 2^-32, integer weight q_c = 1 + (w[13+c] >> 8);
+      cumulative weight cum_c = (q_0 + ... + q_c) / (q_0 + ... + q_(ncomp-1)) (one rounding);
+      Gaussian: mean -100 + 200 ua, sd exp((-2 + 3 ub) ln 10);
+      lognormal: log-mean -2 + 4 ua, log-sd 0.25 + 1.25 ub;
+      uniform on [p1, p1 + p2]: p1 = -100 + 200 ua, p2 = exp((-2 + 4 ub) ln 10);
+      k = 1 + floor(((w17 << 32) | w18) n / 2^64).
+    Every step is an integer operation or one correctly rounded double operation (exp is
+    exp_basic), so a device implementation reproduces it bit for bit.
     """
-    rng = generator("mixture:params", seed)
-    c = int(rng.integers(1, 5))
-    w = rng.dirichlet(np.ones(c))
-    cum = np.cumsum(w)
-    cum[-1] = 1.0
-    types = rng.integers(0, 3, c)
-    p1 = np.empty(c)
-    p2 = np.empty(c)
+    k0 = np.uint32(seed & 0xFFFFFFFF)
+    k1 = np.uint32((seed >> 32) & 0xFFFFFFFF)
+    w = []
+    for j in range(4, 9):
+        w.extend(int(v) for v in philox4x32_10(0, 0, array_id, j, k0, k1))
+    c = 1 + (w[0] >> 30)
+    types = np.zeros(4, dtype=np.int32)
+    p1 = np.zeros(4)
+    p2 = np.zeros(4)
+    q = [1 + (w[13 + j] >> 8) for j in range(4)]
+    tot = float(sum(q[:c]))
+    cum = np.ones(4)
+    acc = 0
     for j in range(c):
+        acc += q[j]
+        cum[j] = float(acc) / tot
+        types[j] = (3 * w[1 + j]) >> 32
+        ua = float(w[5 + j]) * (2.0 ** -32)
+        ub = float(w[9 + j]) * (2.0 ** -32)
         if types[j] == MIX_GAUSS:
-            p1[j] = rng.uniform(-100, 100)
-            p2[j] = 10.0 ** rng.uniform(-2, 1)
+            p1[j] = -100.0 + 200.0 * ua
+            p2[j] = float(exp_basic((-2.0 + 3.0 * ub) * _LN10))
         elif types[j] == MIX_LOGNORMAL:
-            p1[j] = rng.uniform(-2, 2)
-            p2[j] = rng.uniform(0.25, 1.5)
+            p1[j] = -2.0 + 4.0 * ua
+            p2[j] = 0.25 + 1.25 * ub
         else:
-            p1[j] = rng.uniform(-100, 100)
-            p2[j] = 10.0 ** rng.uniform(-2, 2)
-    k = int(rng.integers(1, n + 1))
-    cum4 = np.ones(4)
-    cum4[:c] = cum
-    t4 = np.zeros(4, dtype=np.int32)
-    t4[:c] = types
-    a4 = np.zeros(4)
-    a4[:c] = p1
-    b4 = np.zeros(4)
-    b4[:c] = p2
-    return {"ncomp": c, "cum": cum4, "types": t4, "p1": a4, "p2": b4, "k": k}
+            p1[j] = -100.0 + 200.0 * ua
+            p2[j] = float(exp_basic((-2.0 + 4.0 * ub) * _LN10))
+    k = 1 + ((((w[17] << 32) | w[18]) * n) >> 64)
+    return {"ncomp": c, "cum": cum, "types": types, "p1": p1, "p2": p2, "k": int(k)}
 
 
 def mixture_array(params: dict, n: int, seed: int, array_id: int = 0) -> np.ndarray:
