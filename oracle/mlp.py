@@ -10,7 +10,8 @@ learned proposal compute in float32:
   / (hi - lo))) in double precision (bin 0 when hi == lo); plus lo / (1 + |lo|),
   hi / (1 + |hi|) and k / n.  Each of the 67 features is formed in double
   precision and rounded once to float32, so the device's features agree bit
-  for bit.  A sample holding NaN or an infinity gives no proposal (None).
+  for bit (lo and hi are taken as values: a zero extreme is +0).  A sample
+  holding NaN or an infinity gives no proposal (None).
 - ``forward``: the network 67 -> 64 -> 64 -> 2 with ReLU on both hidden layers.
 - ``loss_and_grad``: the training loss and its gradient by back-propagation.
   With u = o_0, omega = exp(clamp(o_1, -20, 4)) and d = u - u*, one example's
@@ -19,7 +20,7 @@ learned proposal compute in float32:
   strictly inside (-20, 4).
 - ``bracket``: the proposed bracket y0 -+ w with y0 = lo + (hi - lo) u and
   w = (hi - lo) omega.
-- ``target``: the label u* = (x_(k) - lo) / (hi - lo).
+- ``target``: the label u* = (x_(k) - lo) / (hi - lo) (0 when hi == lo).
 - ``adam_step``: one Adam update (Kingma and Ba, 2015) with bias correction.
 
 The method's exactness never rests on the network: the proposed ends are
@@ -75,7 +76,7 @@ def sample_features(x: np.ndarray, k: int):
     v = [float(x[i * stride]) for i in range(s)]
     if not all(math.isfinite(t) for t in v):
         return None
-    lo, hi = min(v), max(v)
+    lo, hi = min(v) + 0.0, max(v) + 0.0  # -0 becomes +0: the extremes are values, not bits
     counts = [0] * BINS
     for t in v:
         if hi > lo:
@@ -159,7 +160,10 @@ def bracket(o: np.ndarray, lo: float, hi: float):
 
 
 def target(value: float, lo: float, hi: float) -> float:
-    """The label u* of an array whose k-th element is `value`, on the sample range [lo, hi]."""
+    """The label u* of an array whose k-th element is `value`, on the sample range [lo, hi]
+    (0 when the sample is constant: the bracket then has zero width whatever u is)."""
+    if not hi > lo:
+        return 0.0
     return (value - lo) / (hi - lo)
 
 

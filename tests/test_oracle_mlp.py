@@ -93,6 +93,7 @@ def test_bracket_and_target_closed_form():
     assert a == pytest.approx(2.8, rel=1e-15) and b == pytest.approx(3.2, rel=1e-15)
     assert mlp.target(3.0, 2.0, 4.0) == 0.5
     assert mlp.target(2.0, 2.0, 4.0) == 0.0 and mlp.target(4.0, 2.0, 4.0) == 1.0
+    assert mlp.target(7.0, 2.0, 2.0) == 0.0
 
 
 def test_histogram_against_numpy_histogram():
@@ -126,6 +127,13 @@ def test_features_degenerate_and_small():
     assert abs(float(f[:64].astype(np.float64).sum()) - 1.0) < 1e-6
     # the largest sample value lands in the last bin, the smallest in the first
     assert f[63] > 0 and f[0] > 0
+
+
+def test_signed_zero_extremes_are_values():
+    x = np.array([-0.0, 1.0, 0.0, 2.0] * 2000, dtype=np.float32)
+    f, lo, hi = mlp.sample_features(x, 1)
+    assert lo == 0.0 and math.copysign(1.0, lo) == 1.0
+    assert np.signbit(f[64]) == False  # noqa: E712
 
 
 def test_nonfinite_sample_gives_no_proposal():
