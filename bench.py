@@ -85,7 +85,7 @@ def traffic_from(fetch_dir: str, write_dir: str) -> dict:
     per_launch = 0.0
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = _counter_rows(d, counter)
-        copies = [v for (name, v) in rows if "elementwise" in name and v * 1024 > 0.5 * copy_bytes]
+        copies = [v for (name, v) in rows if "neg_kernel" in name]
         sel = [v for (name, v) in rows if "cp_select_kernel" in name]
         if not copies or not sel:
             raise SystemExit(f"{counter}: no calibration copy or no selection dispatch in {d}")

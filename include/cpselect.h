@@ -104,8 +104,13 @@ typedef struct cps_eval {
  * grid_blocks, block_threads: launch shape; 0 picks the tuned default.
  * spin_limit:       bound on device-side waiting loops (iterations); 0 = default.
  * bracket_lo/hi, use_bracket: a caller-supplied starting bracket (tests; the proposal
- *                   path).  It is verified by counts and ignored when it does not hold
- *                   x_(k); the result never depends on it. */
+ *                   path).  Pass 0 counts #(x <= lo) and #(x < hi) and keeps each end only
+ *                   where the counts prove it (#(x <= lo) < k, k <= #(x < hi)); the result
+ *                   never depends on it.
+ * compact_proposal: with a proposed bracket, pass 0 also writes the elements strictly
+ *                   inside it to the split workspace (at most 1/8 of each wavefront's
+ *                   share); when both ends hold and everything fit, later passes read only
+ *                   those elements and the input is read once.  1 (default) or 0. */
 typedef struct cps_options {
   int32_t maxit;
   int32_t final_threshold;
@@ -114,7 +119,7 @@ typedef struct cps_options {
   int32_t block_threads;
   int64_t spin_limit;
   int32_t use_bracket;
-  int32_t reserved0;
+  int32_t compact_proposal;
   double bracket_lo, bracket_hi;
 } cps_options;
 
@@ -124,6 +129,9 @@ typedef struct cps_options {
  * passes:       full reads of the input (pass 0 included).
  * work_passes:  all reduction passes, including those over the split buffers.
  * kelley_steps, bisect_steps: how each trial point was chosen.
+ * final_select_size: elements the exact select read.
+ * bracket_used: which proposed bracket ends the counts proved and pass 0 adopted (bit 0:
+ *               the lower end, bit 1: the upper end).
  * elements_read, elements_written: elements the passes moved (algorithmic traffic).
  * population[i]: elements inside the open bracket after pass i.
  * working[i]:   elements pass i read.
@@ -260,6 +268,133 @@ int cps_autotune_batched(cps_handle *h, const void *const *ptrs_dev, const int64
 int lms_median_sq_residuals(cps_handle *h, const double *X_dev, const double *y_dev,
                             const double *betas_dev, int64_t n, int32_t p, int64_t m,
                             cps_result *out_dev, void *stream);
+
+/* ------------------------------------------------------------------ learned bracket proposal
+ *
+ * An extension of the method (not in the paper): a small network reads a sketch of the
+ * array and proposes a bracket around x_(k), which the two-point pass 0 checks by counts
+ * (see cps_options.use_bracket); a wrong proposal costs nothing in exactness.
+ *
+ * Features of an array (n elements, rank k): the fixed-stride sample
+ * x[i * floor(n / S)], i < S = min(n, 4096); its minimum lo and maximum hi (a zero extreme
+ * as +0); the fractions of the sample in 64 equal bins over [lo, hi], bin = min(63,
+ * floor(64 (v - lo) / (hi - lo))) in double precision (all in bin 0 when hi == lo);
+ * lo / (1 + |lo|), hi / (1 + |hi|) and k / n.  Each of the 67 features is formed in double
+ * precision and rounded once to float.  A sample holding NaN or an infinity gives no
+ * proposal.
+ *
+ * Network: 67 -> 64 (ReLU) -> 64 (ReLU) -> 2 in float, outputs (u, s).  Parameters are one
+ * float array of CPS_MLP_PARAMS values: W1 (64 x 67, row-major, row = hidden unit), b1 (64),
+ * W2 (64 x 64), b2 (64), W3 (2 x 64), b3 (2).  Proposed bracket: y0 -+ w with
+ * y0 = lo + (hi - lo) u, w = (hi - lo) exp(clamp(s, -20, 4)), formed in double precision.
+ *
+ * Training loss of one example with label u* = (x_(k) - lo) / (hi - lo) (0 when hi == lo),
+ * d = u - u*, omega = exp(clamp(s, -20, 4)):
+ *     100 d^2 + max(0, |d| - omega) + 0.02 omega,
+ * averaged over the batch.  ReLU'(0) = 0, sign(0) = 0, and the clamp passes gradient only
+ * strictly inside (-20, 4). */
+
+#define CPS_MLP_INPUTS 67
+#define CPS_MLP_HIDDEN 64
+#define CPS_MLP_OUTPUTS 2
+#define CPS_MLP_PARAMS 8642
+
+/* Synthetic training and test arrays: `count` float arrays of n elements, array
+ * first_id + a at x_dev + a * n, each drawn from a random mixture of 1-4 components
+ * (Gaussian, lognormal, uniform), with its rank k in ks_dev[a] (may be NULL).  Array
+ * (seed, id) is defined by the Philox4x32-10 counter-based generator (Salmon et al.,
+ * SC'11) at counters (i mod 2^32, i div 2^32, id, j), key (seed mod 2^32, seed div 2^32):
+ *   parameters from the blocks at counters (0, 0, id, 4..8), twenty words w0..w19:
+ *     ncomp = 1 + (w0 >> 30); type_c = (3 w_{1+c}) >> 32 (0 Gaussian, 1 lognormal,
+ *     2 uniform); ua = w_{5+c} 2^-32, ub = w_{9+c} 2^-32; weight q_c = 1 + (w_{13+c} >> 8),
+ *     cumulative weights (q_0 + .. + q_c) / (q_0 + .. + q_{ncomp-1});
+ *     Gaussian mean -100 + 200 ua, sd exp((-2 + 3 ub) ln 10); lognormal log-mean
+ *     -2 + 4 ua, log-sd 0.25 + 1.25 ub; uniform on [p1, p1 + p2] with p1 = -100 + 200 ua,
+ *     p2 = exp((-2 + 4 ub) ln 10); k = 1 + floor(((w17 << 32) | w18) n / 2^64);
+ *   element i from the blocks j = 0..3 at its counter: g = (sum of the twelve words of
+ *     blocks 0-2, each as (w >> 8) 2^-24) - 6; block 3's first word r picks the component
+ *     (the number of cumulative weights <= r 2^-32 among the first three, capped at
+ *     ncomp - 1) and its second word v gives the uniform v 2^-32; the value is p1 + p2 g,
+ *     exp(p1 + p2 g) or p1 + p2 v in double precision, rounded to float.
+ * exp here is 2^floor(t) times the degree-14 Taylor polynomial of e^(f ln 2) in Horner
+ * form, t = z log2(e), f = t - floor(t), with coefficients 1/j! formed by successive
+ * division; every step is an integer or a correctly rounded double operation, so any
+ * implementation of this definition gives the same bits.
+ * Errors: CPS_EINVAL for null x_dev, count < 1, n < 1, or ids beyond 2^32. */
+int cps_mixture_generate(cps_handle *h, uint64_t seed, int64_t first_id, int64_t count,
+                         int64_t n, float *x_dev, int64_t *ks_dev, void *stream);
+
+/* Features of `count` arrays (descriptors as in select_kth_batched; dtype CPS_F32 or
+ * CPS_F64): feat_dev receives count x 67 floats, range_dev count x 2 doubles (lo, hi),
+ * valid_dev count int32 (1, or 0 when the sample is not finite or the descriptor is
+ * invalid; the features are then zero). */
+int cps_features(cps_handle *h, const void *const *ptrs_dev, const int64_t *sizes_dev,
+                 const int64_t *ks_dev, int64_t count, int dtype, float *feat_dev,
+                 double *range_dev, int32_t *valid_dev, void *stream);
+
+/* Network outputs (u, s) for `count` feature rows: out_dev count x 2 floats. */
+int cps_mlp_forward(cps_handle *h, const float *params_dev, const float *feat_dev,
+                    int64_t count, float *out_dev, void *stream);
+
+/* Mean training loss (loss_dev: one float, may be NULL) and its gradient (grad_dev:
+ * CPS_MLP_PARAMS floats) over `count` examples (feature rows and labels ustar_dev),
+ * by back-propagation in float with a fixed summation order (deterministic).  Uses the
+ * handle's workspace (about count / 32 x 35 KB). */
+int cps_mlp_loss_grad(cps_handle *h, const float *params_dev, const float *feat_dev,
+                      const float *ustar_dev, int64_t count, float *grad_dev, float *loss_dev,
+                      void *stream);
+
+/* One Adam step (Kingma and Ba, 2015), step = 1, 2, ...: m = b1 m + (1 - b1) g,
+ * v = b2 v + (1 - b2) g^2, p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps). */
+int cps_mlp_adam(cps_handle *h, float *params_dev, const float *grad_dev, float *m_dev,
+                 float *v_dev, int64_t step, float lr, float beta1, float beta2, float eps,
+                 void *stream);
+
+/* Initial parameters: weights uniform in +-sqrt(6 / fan_in) from Philox4x32-10 (key
+ * seed, counter (index, 0, 0, 0xC0FFEE), first word's top 24 bits), W3 scaled by 0.01,
+ * b1 = b2 = 0 and b3 = (0.5, ln 0.05). */
+int cps_mlp_init(cps_handle *h, uint64_t seed, float *params_dev, void *stream);
+
+/* The proposed bracket for one array: bracket_dev receives three doubles (a, b, use), use
+ * = 0 when the sample gives no proposal. */
+int cps_learned_bracket(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
+                        const float *params_dev, double *bracket_dev, void *stream);
+
+/* select_kth with the learned proposal: the bracket kernel, then the selection whose pass 0
+ * checks the proposal by counts (and, where it holds, compacts its elements).  Results are
+ * identical to select_kth's; only the number of passes changes.  opt may be NULL. */
+int select_kth_learned(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
+                       const float *params_dev, const cps_options *opt, cps_result *out_dev,
+                       cps_stats *stats_dev, void *stream);
+
+/* Training driver: draws n_arrays arrays of array_size elements (cps_mixture_generate,
+ * seed, ids 0..n_arrays-1), labels them exactly with select_kth_batched, and runs `epochs`
+ * passes of Adam over them in minibatches of `batch`; then measures the trained proposal
+ * on `holdout` arrays of seed holdout_seed.  init = 1 starts from cps_mlp_init(seed).
+ * Synchronises `stream` at the end. */
+typedef struct cps_train_options {
+  uint64_t seed;
+  int64_t n_arrays;
+  int64_t array_size;
+  int32_t epochs;
+  int32_t batch;
+  float lr;
+  int32_t init;
+  int64_t holdout;
+  uint64_t holdout_seed;
+} cps_train_options;
+
+typedef struct cps_train_report {
+  double first_loss;       /* mean loss of the first minibatch */
+  double final_loss;       /* mean loss over the last epoch's minibatches */
+  double holdout_coverage; /* fraction of holdout arrays whose x_(k) lies strictly inside */
+  double holdout_width;    /* mean 2 w / (hi - lo) over the holdout arrays */
+  int64_t steps;           /* Adam steps taken */
+  int64_t examples;        /* training examples with a valid sample */
+} cps_train_report;
+
+int cps_mlp_train(cps_handle *h, const cps_train_options *opt, float *params_dev,
+                  cps_train_report *report, void *stream);
 
 #ifdef __cplusplus
 }

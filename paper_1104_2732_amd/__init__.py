@@ -12,6 +12,11 @@ Entry points (same names as the C ABI in ``include/cpselect.h``):
   float64 CUDA tensor (1-based k) with its counts.
 - ``Selector.objective(x, k, ys)``: the cutting plane's objective, its parts,
   counts and subgradient end points at given trial points.
+- ``Selector.select_kth_batched`` / ``lms_median_sq_residuals``: many
+  selections in one persistent launch; least median of squares.
+- ``Selector.select_kth_learned`` and the ``cps_mlp_*`` / ``cps_features`` /
+  ``cps_mixture_generate`` wrappers: the learned bracket proposal, its
+  network's forward, gradient, Adam and training driver.
 """
 from __future__ import annotations
 
@@ -51,7 +56,7 @@ class Options(ctypes.Structure):
     _fields_ = [("maxit", ctypes.c_int32), ("final_threshold", ctypes.c_int32),
                 ("partition_fraction", ctypes.c_double), ("grid_blocks", ctypes.c_int32),
                 ("block_threads", ctypes.c_int32), ("spin_limit", ctypes.c_int64),
-                ("use_bracket", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("use_bracket", ctypes.c_int32), ("compact_proposal", ctypes.c_int32),
                 ("bracket_lo", ctypes.c_double), ("bracket_hi", ctypes.c_double)]
 
 
@@ -60,6 +65,24 @@ class BatchOptions(ctypes.Structure):
     _fields_ = [("block_threads", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("split_capacity", ctypes.c_int64), ("final_threshold", ctypes.c_int32),
                 ("maxit", ctypes.c_int32), ("partition_fraction", ctypes.c_double)]
+
+
+class TrainOptions(ctypes.Structure):
+    """Mirror of cps_train_options (see include/cpselect.h)."""
+    _fields_ = [("seed", ctypes.c_uint64), ("n_arrays", ctypes.c_int64),
+                ("array_size", ctypes.c_int64), ("epochs", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("lr", ctypes.c_float), ("init", ctypes.c_int32),
+                ("holdout", ctypes.c_int64), ("holdout_seed", ctypes.c_uint64)]
+
+
+class TrainReport(ctypes.Structure):
+    """Mirror of cps_train_report."""
+    _fields_ = [("first_loss", ctypes.c_double), ("final_loss", ctypes.c_double),
+                ("holdout_coverage", ctypes.c_double), ("holdout_width", ctypes.c_double),
+                ("steps", ctypes.c_int64), ("examples", ctypes.c_int64)]
+
+
+MLP_INPUTS, MLP_HIDDEN, MLP_OUTPUTS, MLP_PARAMS = 67, 64, 2, 8642
 
 
 class CpsError(RuntimeError):
@@ -77,7 +100,10 @@ _lib = None
 EXPORTS = ("cps_create", "cps_destroy", "cps_status_string", "cps_last_hip_error",
            "cps_default_options", "cps_reserve", "select_kth", "select_kth_ex", "cps_objective",
            "cps_default_batch_options", "select_kth_batched", "select_kth_batched_ex",
-           "cps_reserve_batched", "cps_autotune_batched", "lms_median_sq_residuals")
+           "cps_reserve_batched", "cps_autotune_batched", "lms_median_sq_residuals",
+           "cps_mixture_generate", "cps_features", "cps_mlp_forward", "cps_mlp_loss_grad",
+           "cps_mlp_adam", "cps_mlp_init", "cps_learned_bracket", "select_kth_learned",
+           "cps_mlp_train")
 STATUS_BADARG = 4
 
 
@@ -122,6 +148,22 @@ def lib() -> ctypes.CDLL:
     L.cps_autotune_batched.restype = c_int
     L.lms_median_sq_residuals.argtypes = [vp, vp, vp, vp, i64, i32, i64, vp, vp]
     L.lms_median_sq_residuals.restype = c_int
+    u64, f32 = ctypes.c_uint64, ctypes.c_float
+    L.cps_mixture_generate.argtypes = [vp, u64, i64, i64, i64, vp, vp, vp]
+    L.cps_features.argtypes = [vp, vp, vp, vp, i64, c_int, vp, vp, vp, vp]
+    L.cps_mlp_forward.argtypes = [vp, vp, vp, i64, vp, vp]
+    L.cps_mlp_loss_grad.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp]
+    L.cps_mlp_adam.argtypes = [vp, vp, vp, vp, vp, i64, f32, f32, f32, f32, vp]
+    L.cps_mlp_init.argtypes = [vp, u64, vp, vp]
+    L.cps_learned_bracket.argtypes = [vp, vp, i64, i64, c_int, vp, vp, vp]
+    L.select_kth_learned.argtypes = [vp, vp, i64, i64, c_int, vp, ctypes.POINTER(Options), vp,
+                                     vp, vp]
+    L.cps_mlp_train.argtypes = [vp, ctypes.POINTER(TrainOptions), vp, ctypes.POINTER(TrainReport),
+                                vp]
+    for name in ("cps_mixture_generate", "cps_features", "cps_mlp_forward", "cps_mlp_loss_grad",
+                 "cps_mlp_adam", "cps_mlp_init", "cps_learned_bracket", "select_kth_learned",
+                 "cps_mlp_train"):
+        getattr(L, name).restype = c_int
     _lib = L
     return L
 
@@ -326,3 +368,123 @@ class Selector:
         _check(rc, "cps_objective")
         torch.cuda.synchronize(self.device)
         return _as_records(out, EVAL_DTYPE).copy()
+
+    # -- learned bracket proposal ------------------------------------------------------
+
+    def _ptr(self, t) -> ctypes.c_void_p:
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("expected a contiguous CUDA tensor")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _float_params(self, params):
+        import torch
+        if params.dtype != torch.float32 or params.numel() != MLP_PARAMS:
+            raise ValueError(f"params must be {MLP_PARAMS} float32 values")
+        return self._ptr(params)
+
+    def new_params(self):
+        import torch
+        return torch.zeros(MLP_PARAMS, dtype=torch.float32, device=self.device)
+
+    def mixture_generate(self, seed: int, first_id: int, count: int, n: int):
+        """(arrays count x n float32, ranks) of the synthetic mixture family."""
+        import torch
+        x = torch.empty((count, n), dtype=torch.float32, device=self.device)
+        ks = torch.empty(count, dtype=torch.int64, device=self.device)
+        _check(lib().cps_mixture_generate(self._h, int(seed), int(first_id), int(count), int(n),
+                                          self._ptr(x), self._ptr(ks),
+                                          ctypes.c_void_p(_stream_ptr(self.device))),
+               "cps_mixture_generate")
+        return x, ks
+
+    def features(self, ptrs, sizes, ks, count: int, dtype_code: int):
+        """(features count x 67 float32, ranges count x 2 float64, valid int32) tensors."""
+        import torch
+        feat = torch.empty((count, MLP_INPUTS), dtype=torch.float32, device=self.device)
+        rng = torch.empty((count, 2), dtype=torch.float64, device=self.device)
+        valid = torch.empty(count, dtype=torch.int32, device=self.device)
+        _check(lib().cps_features(self._h, self._ptr(ptrs), self._ptr(sizes), self._ptr(ks),
+                                  int(count), int(dtype_code), self._ptr(feat), self._ptr(rng),
+                                  self._ptr(valid), ctypes.c_void_p(_stream_ptr(self.device))),
+               "cps_features")
+        return feat, rng, valid
+
+    def mlp_forward(self, params, feat):
+        import torch
+        out = torch.empty((feat.shape[0], MLP_OUTPUTS), dtype=torch.float32, device=self.device)
+        _check(lib().cps_mlp_forward(self._h, self._float_params(params), self._ptr(feat),
+                                     int(feat.shape[0]), self._ptr(out),
+                                     ctypes.c_void_p(_stream_ptr(self.device))), "cps_mlp_forward")
+        return out
+
+    def mlp_loss_grad(self, params, feat, ustar):
+        """(loss tensor of 1, gradient tensor of MLP_PARAMS) for one batch."""
+        import torch
+        grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=self.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        _check(lib().cps_mlp_loss_grad(self._h, self._float_params(params), self._ptr(feat),
+                                       self._ptr(ustar), int(feat.shape[0]), self._ptr(grad),
+                                       self._ptr(loss), ctypes.c_void_p(_stream_ptr(self.device))),
+               "cps_mlp_loss_grad")
+        return loss, grad
+
+    def mlp_adam(self, params, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999,
+                 eps=1e-8) -> None:
+        _check(lib().cps_mlp_adam(self._h, self._float_params(params), self._ptr(grad),
+                                  self._ptr(m), self._ptr(v), int(step), float(lr), float(beta1),
+                                  float(beta2), float(eps),
+                                  ctypes.c_void_p(_stream_ptr(self.device))), "cps_mlp_adam")
+
+    def mlp_init(self, seed: int, params=None):
+        params = self.new_params() if params is None else params
+        _check(lib().cps_mlp_init(self._h, int(seed), self._float_params(params),
+                                  ctypes.c_void_p(_stream_ptr(self.device))), "cps_mlp_init")
+        return params
+
+    def learned_bracket(self, x, k: int, params):
+        """(a, b, use) the network proposes for x and rank k."""
+        import torch
+        br = torch.empty(3, dtype=torch.float64, device=self.device)
+        _check(lib().cps_learned_bracket(self._h, self._ptr(x), x.numel(), int(k), _dtype_code(x),
+                                         self._float_params(params), self._ptr(br),
+                                         ctypes.c_void_p(_stream_ptr(self.device))),
+               "cps_learned_bracket")
+        torch.cuda.synchronize(self.device)
+        a, b, use = br.cpu().tolist()
+        return a, b, int(use)
+
+    def select_kth_learned_async(self, x, k: int, params, out, stats=None,
+                                 options: Options | None = None) -> None:
+        rc = lib().select_kth_learned(self._h, self._ptr(x), x.numel(), int(k), _dtype_code(x),
+                                      self._float_params(params),
+                                      ctypes.byref(options) if options is not None else None,
+                                      self._ptr(out),
+                                      self._ptr(stats) if stats is not None else None,
+                                      ctypes.c_void_p(_stream_ptr(self.device)))
+        _check(rc, "select_kth_learned")
+
+    def select_kth_learned(self, x, k: int, params, options: Options | None = None,
+                           stats: bool = False):
+        import torch
+        out = self.new_results(1)
+        st = self.new_stats() if stats else None
+        self.select_kth_learned_async(x, k, params, out, st, options)
+        torch.cuda.synchronize(self.device)
+        r = _as_records(out, RESULT_DTYPE)[0]
+        res = {name: r[name].item() for name in RESULT_DTYPE.names}
+        if stats:
+            return res, _as_records(st, STATS_DTYPE)[0]
+        return res
+
+    def mlp_train(self, params, seed: int, n_arrays: int, array_size: int, epochs: int,
+                  batch: int = 256, lr: float = 1e-3, init: bool = True, holdout: int = 0,
+                  holdout_seed: int = 1) -> dict:
+        """Run the library's training driver (synchronises); returns the report as a dict."""
+        o = TrainOptions(seed=int(seed), n_arrays=int(n_arrays), array_size=int(array_size),
+                         epochs=int(epochs), batch=int(batch), lr=float(lr), init=1 if init else 0,
+                         holdout=int(holdout), holdout_seed=int(holdout_seed))
+        rep = TrainReport()
+        _check(lib().cps_mlp_train(self._h, ctypes.byref(o), self._float_params(params),
+                                   ctypes.byref(rep), ctypes.c_void_p(_stream_ptr(self.device))),
+               "cps_mlp_train")
+        return {name: getattr(rep, name) for name, _ in TrainReport._fields_}

@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "cps_kernels.h"
 
@@ -31,6 +32,9 @@ struct cps_handle {
   size_t bws_bytes = 0;
   void *lws = nullptr;  // least-median-of-squares residuals and descriptors
   size_t lws_bytes = 0;
+  void *mws = nullptr;  // per-workgroup gradient partials of the proposal network
+  size_t mws_bytes = 0;
+  double *bracket = nullptr;  // the learned proposal handed to the selection (a, b, use)
   cps_batch_options tuned[2];
   bool has_tuned[2] = {false, false};
   std::mutex mu;
@@ -114,6 +118,7 @@ struct Resolved {
   int grid;
   int64_t seg_R;
   int64_t spin_limit;
+  int compact_proposal;
 };
 
 int resolve(cps_handle *h, int64_t n, int dtype, const cps_options *opt, Resolved &r) {
@@ -160,12 +165,15 @@ int resolve(cps_handle *h, int64_t n, int dtype, const cps_options *opt, Resolve
   }
   r.seg_R = seg;
   r.spin_limit = o.spin_limit ? o.spin_limit : (int64_t)1 << 22;
+  r.compact_proposal = o.compact_proposal ? 1 : 0;
   return CPS_OK;
 }
 
+// bracket_dev: a device-side proposal (a, b, use) read by pass 0, or null.
 template <typename T>
 int run_select(cps_handle *h, const T *x, int64_t n, int64_t k, const cps_options *opt,
-               cps_result *out, cps_stats *stats, hipStream_t stream) {
+               cps_result *out, cps_stats *stats, hipStream_t stream,
+               const double *bracket_dev = nullptr) {
   Resolved r;
   int rc = resolve(h, n, sizeof(T) == 4 ? CPS_F32 : CPS_F64, opt, r);
   if (rc) return rc;
@@ -191,6 +199,10 @@ int run_select(cps_handle *h, const T *x, int64_t n, int64_t k, const cps_option
   a.stats = stats;
   a.cfg = r.cfg;
   a.spin_limit = r.spin_limit;
+  a.bracket = bracket_dev;
+  // a proposed bracket's interior may take up to 1/8 of each wavefront's region in pass 0
+  const bool proposal = bracket_dev != nullptr || r.cfg.use_bracket != 0;
+  a.p0_cap = (proposal && r.compact_proposal) ? L.seg_R / 8 : 0;
   hipError_t e = cps::launch_select<T>(a, r.grid, stream);
   if (e != hipSuccess) return hip_fail(e);
   return CPS_OK;
@@ -412,6 +424,7 @@ void cps_default_options(cps_options *opt) {
   opt->block_threads = 0;
   opt->spin_limit = 0;
   opt->use_bracket = 0;
+  opt->compact_proposal = 1;
 }
 
 int cps_last_hip_error(void) { return g_last_hip; }
@@ -457,6 +470,12 @@ int cps_create(int device, cps_handle **out) {
     delete h;
     return CPS_ENODEV;
   }
+  e = hipMalloc(&h->bracket, 4 * sizeof(double));
+  if (e != hipSuccess) {
+    delete h;
+    g_last_hip = (int)e;
+    return CPS_ENOMEM;
+  }
   *out = h;
   return CPS_OK;
 }
@@ -466,6 +485,8 @@ int cps_destroy(cps_handle *h) {
   if (h->ws) (void)hipFree(h->ws);
   if (h->bws) (void)hipFree(h->bws);
   if (h->lws) (void)hipFree(h->lws);
+  if (h->mws) (void)hipFree(h->mws);
+  if (h->bracket) (void)hipFree(h->bracket);
   delete h;
   return CPS_OK;
 }
@@ -525,6 +546,262 @@ int cps_objective(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
   else
     e = cps::launch_objective<double>((const double *)x, n, k, ys_dev, ny, out_dev, pd, pi, (int)nb, s);
   if (e != hipSuccess) return hip_fail(e);
+  return CPS_OK;
+}
+
+// ------------------------------------------------------------------ learned proposal
+
+int cps_mixture_generate(cps_handle *h, uint64_t seed, int64_t first_id, int64_t count,
+                         int64_t n, float *x_dev, int64_t *ks_dev, void *stream) {
+  if (!h || !x_dev || count < 1 || n < 1 || first_id < 0 ||
+      first_id + count > ((int64_t)1 << 32))
+    return CPS_EINVAL;
+  hipError_t e = cps::launch_mixture_gen(seed, first_id, count, n, x_dev, ks_dev,
+                                         (hipStream_t)stream);
+  return e == hipSuccess ? CPS_OK : hip_fail(e);
+}
+
+int cps_features(cps_handle *h, const void *const *ptrs_dev, const int64_t *sizes_dev,
+                 const int64_t *ks_dev, int64_t count, int dtype, float *feat_dev,
+                 double *range_dev, int32_t *valid_dev, void *stream) {
+  if (!h || !ptrs_dev || !sizes_dev || !ks_dev || !feat_dev || !range_dev || !valid_dev ||
+      count < 1 || !dtype_size(dtype))
+    return CPS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (dtype == CPS_F32)
+    e = cps::launch_features<float>((const float *const *)ptrs_dev, sizes_dev, ks_dev, count,
+                                    feat_dev, range_dev, valid_dev, s);
+  else
+    e = cps::launch_features<double>((const double *const *)ptrs_dev, sizes_dev, ks_dev, count,
+                                     feat_dev, range_dev, valid_dev, s);
+  return e == hipSuccess ? CPS_OK : hip_fail(e);
+}
+
+int cps_mlp_forward(cps_handle *h, const float *params_dev, const float *feat_dev, int64_t count,
+                    float *out_dev, void *stream) {
+  if (!h || !params_dev || !feat_dev || !out_dev || count < 1 || count > ((int64_t)1 << 36))
+    return CPS_EINVAL;
+  hipError_t e = cps::launch_mlp_forward(params_dev, feat_dev, count, out_dev, (hipStream_t)stream);
+  return e == hipSuccess ? CPS_OK : hip_fail(e);
+}
+
+int cps_mlp_loss_grad(cps_handle *h, const float *params_dev, const float *feat_dev,
+                      const float *ustar_dev, int64_t count, float *grad_dev, float *loss_dev,
+                      void *stream) {
+  if (!h || !params_dev || !feat_dev || !ustar_dev || !grad_dev || count < 1 ||
+      count > ((int64_t)1 << 26))
+    return CPS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lk(h->mu);
+  int rc = ensure_buffer(h->mws, h->mws_bytes, cps::mlp_grad_workspace(count), s);
+  if (rc) return rc;
+  hipError_t e = cps::launch_mlp_loss_grad(params_dev, feat_dev, ustar_dev, count, grad_dev,
+                                           loss_dev, (float *)h->mws, s);
+  return e == hipSuccess ? CPS_OK : hip_fail(e);
+}
+
+int cps_mlp_adam(cps_handle *h, float *params_dev, const float *grad_dev, float *m_dev,
+                 float *v_dev, int64_t step, float lr, float beta1, float beta2, float eps,
+                 void *stream) {
+  if (!h || !params_dev || !grad_dev || !m_dev || !v_dev || step < 1 || !(lr > 0.0f) ||
+      !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+    return CPS_EINVAL;
+  hipError_t e = cps::launch_mlp_adam(params_dev, grad_dev, m_dev, v_dev, step, lr, beta1, beta2,
+                                      eps, (hipStream_t)stream);
+  return e == hipSuccess ? CPS_OK : hip_fail(e);
+}
+
+int cps_mlp_init(cps_handle *h, uint64_t seed, float *params_dev, void *stream) {
+  if (!h || !params_dev) return CPS_EINVAL;
+  hipError_t e = cps::launch_mlp_init(seed, params_dev, (hipStream_t)stream);
+  return e == hipSuccess ? CPS_OK : hip_fail(e);
+}
+
+int cps_learned_bracket(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
+                        const float *params_dev, double *bracket_dev, void *stream) {
+  int rc = check_common(h, x, n, k, dtype);
+  if (rc) return rc;
+  if (!params_dev || !bracket_dev) return CPS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (dtype == CPS_F32)
+    e = cps::launch_learned_bracket<float>((const float *)x, n, k, params_dev, bracket_dev, s);
+  else
+    e = cps::launch_learned_bracket<double>((const double *)x, n, k, params_dev, bracket_dev, s);
+  return e == hipSuccess ? CPS_OK : hip_fail(e);
+}
+
+int select_kth_learned(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
+                       const float *params_dev, const cps_options *opt, cps_result *out_dev,
+                       cps_stats *stats_dev, void *stream) {
+  int rc = check_common(h, x, n, k, dtype);
+  if (rc) return rc;
+  if (!params_dev || !out_dev) return CPS_EINVAL;
+  std::lock_guard<std::mutex> lk(h->mu);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (dtype == CPS_F32)
+    e = cps::launch_learned_bracket<float>((const float *)x, n, k, params_dev, h->bracket, s);
+  else
+    e = cps::launch_learned_bracket<double>((const double *)x, n, k, params_dev, h->bracket, s);
+  if (e != hipSuccess) return hip_fail(e);
+  if (dtype == CPS_F32)
+    return run_select<float>(h, (const float *)x, n, k, opt, out_dev, stats_dev, s, h->bracket);
+  return run_select<double>(h, (const double *)x, n, k, opt, out_dev, stats_dev, s, h->bracket);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Device buffers of one training run, freed together.
+struct TrainBuffers {
+  std::vector<void *> bufs;
+  ~TrainBuffers() {
+    for (void *p : bufs) (void)hipFree(p);
+  }
+  template <typename P> int get(P *&p, size_t bytes) {
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes < 256 ? 256 : bytes);
+    if (e != hipSuccess) {
+      g_last_hip = (int)e;
+      return CPS_ENOMEM;
+    }
+    bufs.push_back(q);
+    p = (P *)q;
+    return CPS_OK;
+  }
+};
+
+// Generate arrays [first, first + count) of `seed` in chunks, with features, ranges,
+// validity and exact labels; optionally the network outputs and the coverage counters.
+int label_arrays(cps_handle *h, uint64_t seed, int64_t count, int64_t n, int64_t chunk,
+                 float *xbuf, int64_t *ks, const float **ptrs, int64_t *sizes, cps_result *res,
+                 float *feat, double *range, int32_t *valid, float *ustar, const float *params,
+                 float *outs, double *acc, hipStream_t s) {
+  for (int64_t c0 = 0; c0 < count; c0 += chunk) {
+    const int64_t c = count - c0 < chunk ? count - c0 : chunk;
+    int rc = cps_mixture_generate(h, seed, c0, c, n, xbuf, ks, s);
+    if (rc) return rc;
+    hipError_t e = cps::launch_batch_descriptors(xbuf, n, c, ptrs, sizes, s);
+    if (e != hipSuccess) return hip_fail(e);
+    float *f = feat + (feat && !outs ? c0 * CPS_MLP_INPUTS : 0);
+    double *rg = range + (outs ? 0 : 2 * c0);
+    int32_t *vd = valid + (outs ? 0 : c0);
+    rc = cps_features(h, (const void *const *)ptrs, sizes, ks, c, CPS_F32, f, rg, vd, s);
+    if (rc) return rc;
+    rc = select_kth_batched_ex(h, (const void *const *)ptrs, sizes, ks, c, CPS_F32, nullptr, res, s);
+    if (rc) return rc;
+    if (!outs) {
+      e = cps::launch_labels(res, rg, vd, c, ustar + c0, s);
+      if (e != hipSuccess) return hip_fail(e);
+    } else {
+      rc = cps_mlp_forward(h, params, f, c, outs, s);
+      if (rc) return rc;
+      e = cps::launch_holdout(outs, rg, vd, res, c, acc, s);
+      if (e != hipSuccess) return hip_fail(e);
+    }
+  }
+  return CPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cps_mlp_train(cps_handle *h, const cps_train_options *opt, float *params_dev,
+                  cps_train_report *report, void *stream) {
+  if (!h || !opt || !params_dev || opt->n_arrays < 1 || opt->array_size < 1 || opt->epochs < 0 ||
+      opt->batch < 1 || opt->batch > (1 << 20) || !(opt->lr > 0.0f) || opt->holdout < 0 ||
+      opt->n_arrays > ((int64_t)1 << 32) || opt->holdout > ((int64_t)1 << 32))
+    return CPS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t N = opt->n_arrays, n = opt->array_size;
+  // arrays in flight: up to 4096 per chunk and about 2 GiB of values
+  int64_t chunk = (((int64_t)1 << 29) + n - 1) / n;
+  if (chunk > 4096) chunk = 4096;
+  if (chunk < 1) chunk = 1;
+  const int64_t cmax = chunk > opt->holdout ? chunk : opt->holdout;
+  TrainBuffers tb;
+  float *xbuf, *feat, *ustar, *grad, *m, *v, *losses, *outs, *hfeat;
+  int64_t *ks, *sizes;
+  const float **ptrs;
+  cps_result *res;
+  double *range, *hrange, *acc;
+  int32_t *valid, *hvalid;
+  const int64_t spe = N / opt->batch > 0 ? N / opt->batch : 1;  // steps per epoch
+  const int64_t B = N / opt->batch > 0 ? opt->batch : N;
+  const int64_t steps = spe * opt->epochs;
+  int rc = CPS_OK;
+  if ((rc = tb.get(xbuf, (size_t)chunk * n * sizeof(float))) ||
+      (rc = tb.get(ks, (size_t)cmax * sizeof(int64_t))) ||
+      (rc = tb.get(sizes, (size_t)cmax * sizeof(int64_t))) ||
+      (rc = tb.get(ptrs, (size_t)cmax * sizeof(float *))) ||
+      (rc = tb.get(res, (size_t)cmax * sizeof(cps_result))) ||
+      (rc = tb.get(feat, (size_t)N * CPS_MLP_INPUTS * sizeof(float))) ||
+      (rc = tb.get(range, (size_t)N * 2 * sizeof(double))) ||
+      (rc = tb.get(valid, (size_t)N * sizeof(int32_t))) ||
+      (rc = tb.get(ustar, (size_t)N * sizeof(float))) ||
+      (rc = tb.get(grad, CPS_MLP_PARAMS * sizeof(float))) ||
+      (rc = tb.get(m, CPS_MLP_PARAMS * sizeof(float))) ||
+      (rc = tb.get(v, CPS_MLP_PARAMS * sizeof(float))) ||
+      (rc = tb.get(losses, (size_t)(steps > 0 ? steps : 1) * sizeof(float))) ||
+      (rc = tb.get(outs, (size_t)chunk * 2 * sizeof(float))) ||
+      (rc = tb.get(hfeat, (size_t)chunk * CPS_MLP_INPUTS * sizeof(float))) ||
+      (rc = tb.get(hrange, (size_t)chunk * 2 * sizeof(double))) ||
+      (rc = tb.get(hvalid, (size_t)chunk * sizeof(int32_t))) ||
+      (rc = tb.get(acc, 4 * sizeof(double))))
+    return rc;
+  hipError_t e;
+  if ((e = hipMemsetAsync(m, 0, CPS_MLP_PARAMS * sizeof(float), s)) != hipSuccess ||
+      (e = hipMemsetAsync(v, 0, CPS_MLP_PARAMS * sizeof(float), s)) != hipSuccess ||
+      (e = hipMemsetAsync(acc, 0, 4 * sizeof(double), s)) != hipSuccess)
+    return hip_fail(e);
+  if (opt->init && (rc = cps_mlp_init(h, opt->seed, params_dev, s))) return rc;
+  // the training set: features and exact labels of every array
+  rc = label_arrays(h, opt->seed, N, n, chunk, xbuf, ks, ptrs, sizes, res, feat, range, valid,
+                    ustar, params_dev, nullptr, nullptr, s);
+  if (rc) return rc;
+  // Adam over minibatches of consecutive examples (the arrays are independent draws)
+  int64_t step = 0;
+  for (int ep = 0; ep < opt->epochs; ++ep) {
+    for (int64_t b = 0; b < spe; ++b) {
+      const int64_t r0 = b * B;
+      rc = cps_mlp_loss_grad(h, params_dev, feat + r0 * CPS_MLP_INPUTS, ustar + r0, B, grad,
+                             losses + step, s);
+      if (rc) return rc;
+      ++step;
+      rc = cps_mlp_adam(h, params_dev, grad, m, v, step, opt->lr, 0.9f, 0.999f, 1e-8f, s);
+      if (rc) return rc;
+    }
+  }
+  // held-out arrays: coverage and width of the trained proposal
+  if (opt->holdout > 0) {
+    rc = label_arrays(h, opt->holdout_seed, opt->holdout, n, chunk, xbuf, ks, ptrs, sizes, res,
+                      hfeat, hrange, hvalid, nullptr, params_dev, outs, acc, s);
+    if (rc) return rc;
+  }
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e);
+  if (report) {
+    std::vector<float> hl((size_t)(steps > 0 ? steps : 0));
+    double ha[4] = {0, 0, 0, 0};
+    if (steps > 0 &&
+        (e = hipMemcpy(hl.data(), losses, hl.size() * sizeof(float), hipMemcpyDeviceToHost)) !=
+            hipSuccess)
+      return hip_fail(e);
+    if ((e = hipMemcpy(ha, acc, sizeof(ha), hipMemcpyDeviceToHost)) != hipSuccess)
+      return hip_fail(e);
+    report->first_loss = steps > 0 ? hl[0] : 0.0;
+    double last = 0.0;
+    for (int64_t i = steps - spe; i < steps; ++i)
+      if (i >= 0) last += hl[(size_t)i];
+    report->final_loss = steps > 0 ? last / (double)spe : 0.0;
+    report->holdout_coverage = ha[2] > 0 ? ha[0] / ha[2] : 0.0;
+    report->holdout_width = ha[2] > 0 ? ha[1] / ha[2] : 0.0;
+    report->steps = steps;
+    report->examples = N;
+  }
   return CPS_OK;
 }
 

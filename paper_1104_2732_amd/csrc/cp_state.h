@@ -62,7 +62,7 @@ struct CpConfig {
   double theta;             // start splitting once population <= theta * n (0 = never)
   int64_t zcap;             // capacity of the gather buffer (elements, >= final_threshold)
   int32_t use_bracket;
-  int32_t pad0;
+  int32_t p0_split;         // pass 0 with a bracket also writes the elements inside it
   double bracket_lo, bracket_hi;
   int64_t split_cap;        // the first split needs population <= split_cap (0 = no limit)
 };
@@ -81,6 +81,9 @@ struct Pass0Result {
   // finite-element parts of A and B at a and at b
   int64_t c_le_a, c_lt_b;
   double A_a, B_a, A_b, B_b;
+  // pass 0 that also wrote the elements strictly inside (a, b) to split buffer 0: the
+  // number of wavefronts whose share did not fit their region (0 = all written)
+  int64_t split_overflow;
 };
 
 // Results of one evaluation pass over the working set W at trial point t.
@@ -315,29 +318,39 @@ CPS_HD inline void cp_after_pass0(CpState &s, const Pass0Result &r, const CpConf
   s.side = 0;
   s.wlen = n;
   s.on_bracket = 0;
-  // A proposed bracket (a, b) replaces an end only when the counts prove it holds
-  // x_(k): #(x <= a) < k <= #(x < b).  f at the new ends comes from the two-point
-  // sums of the same pass (infinities again evaluated as the finite extremes).
+  // A proposed end replaces the bracket's end only when the counts of the same pass
+  // prove it: a is a valid left end when #(x <= a) < k, b a valid right end when
+  // k <= #(x < b) (the bracket invariant above); each end is judged on its own, so a
+  // proposal that misses on one side still tightens the other.  f at the new ends comes
+  // from the two-point sums of the same pass (infinities evaluated as the finite extremes).
   if (c.use_bracket) {
     const double a = to_T(c.bracket_lo, c.dtype), b = to_T(c.bracket_hi, c.dtype);
-    if (a < b && r.c_le_a < k && k <= r.c_lt_b) {
-      s.bracket_used = 1;
-      if (a > s.yL) {
-        s.yL = a;
-        s.cL = r.c_le_a;
-        s.lo = next_up(a, c.dtype);
-        s.lo_data = 0;
-        s.AL = r.A_a + (double)r.npos * (r.fmax - a);
-        s.BL = r.B_a + (double)r.nneg * (a - r.fmin);
-      }
-      if (b < s.yR) {
-        s.yR = b;
-        s.cR = r.c_lt_b;
-        s.hi = next_down(b, c.dtype);
-        s.hi_data = 0;
-        s.AR = r.A_b + (double)r.npos * (r.fmax - b);
-        s.BR = r.B_b + (double)r.nneg * (b - r.fmin);
-      }
+    if (r.c_le_a < k && a > s.yL) {
+      s.bracket_used |= 1;
+      s.yL = a;
+      s.cL = r.c_le_a;
+      s.lo = next_up(a, c.dtype);
+      s.lo_data = 0;
+      s.AL = r.A_a + (double)r.npos * (r.fmax - a);
+      s.BL = r.B_a + (double)r.nneg * (a - r.fmin);
+    }
+    if (k <= r.c_lt_b && b < s.yR) {
+      s.bracket_used |= 2;
+      s.yR = b;
+      s.cR = r.c_lt_b;
+      s.hi = next_down(b, c.dtype);
+      s.hi_data = 0;
+      s.AR = r.A_b + (double)r.npos * (r.fmax - b);
+      s.BR = r.B_b + (double)r.nneg * (b - r.fmin);
+    }
+    // With both ends proven, the elements pass 0 wrote (those strictly inside (a, b))
+    // are exactly the bracket's, cR - cL of them: later passes read only those.
+    if (c.p0_split && s.bracket_used == 3 && r.split_overflow == 0) {
+      s.wbuf = 0;
+      s.side = 0;
+      s.wlen = s.cR - s.cL;
+      s.on_bracket = 1;
+      s.elements_written += s.wlen;
     }
   }
   cp_plan(s, c);

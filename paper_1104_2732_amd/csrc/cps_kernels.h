@@ -54,6 +54,8 @@ template <typename T> struct SelectArgs {
   cps_stats *stats;    // may be null
   CpConfig cfg;
   int64_t spin_limit;
+  const double *bracket;  // device [a, b, use] read by pass 0 in place of cfg's, or null
+  int64_t p0_cap;      // elements per wavefront region a bracketed pass 0 may write (0: none)
 };
 
 // ---- batched selection
@@ -95,5 +97,32 @@ template <typename T> int select_max_blocks_per_cu();
 template <typename T>
 hipError_t launch_objective(const T *x, int64_t n, int64_t k, const double *ys, int64_t ny,
                             cps_eval *out, double *pd, int64_t *pi, int nb, hipStream_t stream);
+
+// ---- learned bracket proposal
+
+hipError_t launch_mixture_gen(uint64_t seed, int64_t first_id, int64_t count, int64_t n,
+                              float *out, int64_t *ks, hipStream_t stream);
+template <typename T>
+hipError_t launch_features(const T *const *ptrs, const int64_t *sizes, const int64_t *ks,
+                           int64_t count, float *feat, double *range, int32_t *valid,
+                           hipStream_t stream);
+hipError_t launch_mlp_forward(const float *P, const float *feat, int64_t count, float *out,
+                              hipStream_t stream);
+size_t mlp_grad_workspace(int64_t count);
+hipError_t launch_mlp_loss_grad(const float *P, const float *feat, const float *ustar,
+                                int64_t count, float *grad, float *loss, float *ws,
+                                hipStream_t stream);
+hipError_t launch_mlp_adam(float *P, const float *g, float *m, float *v, int64_t step, float lr,
+                           float b1, float b2, float eps, hipStream_t stream);
+hipError_t launch_mlp_init(uint64_t seed, float *P, hipStream_t stream);
+template <typename T>
+hipError_t launch_learned_bracket(const T *x, int64_t n, int64_t k, const float *P,
+                                  double *bracket, hipStream_t stream);
+hipError_t launch_batch_descriptors(const float *base, int64_t n, int64_t count, const float **ptrs,
+                                    int64_t *sizes, hipStream_t stream);
+hipError_t launch_labels(const cps_result *res, const double *range, const int32_t *valid,
+                         int64_t count, float *ustar, hipStream_t stream);
+hipError_t launch_holdout(const float *out, const double *range, const int32_t *valid,
+                          const cps_result *res, int64_t count, double *acc, hipStream_t stream);
 
 }  // namespace cps

@@ -145,8 +145,21 @@ __device__ inline void eval_pass(const Walk<T> &wk, T t, T yL, T yR, T fmin, T f
   }
 }
 
-template <typename T, int BLOCK, int U, bool CLASSIFY, bool BRACKET>
-__device__ inline void pass0(const Walk<T> &wk, T ba, T bb, P0Acc<T> &acc) {
+// Pass 0 with a proposed bracket (a, b) may also write the elements strictly inside it to
+// its wavefront's region, up to `cap` of them (the count goes on past the cap, so an
+// overflowing region is seen and its contents are not used).
+template <typename T>
+__device__ inline void split_inside(T v, bool valid, T a, T b, WaveOut<T> &o, uint32_t cap) {
+  const bool in = valid && v > a && v < b;
+  const uint64_t m = ballot(in);
+  const uint32_t pos = o.lo + lane_rank(m);
+  if (in && pos < cap) o.region[pos] = v;
+  o.lo += popc(m);
+}
+
+template <typename T, int BLOCK, int U, bool CLASSIFY, bool BRACKET, bool SPLIT>
+__device__ inline void pass0(const Walk<T> &wk, T ba, T bb, P0Acc<T> &acc, WaveOut<T> &o,
+                             uint32_t cap) {
   constexpr int V = Traits<T>::kVec;
   using Vec = typename Traits<T>::Vec;
   const int tid = threadIdx.x, lane = tid % kWave;
@@ -170,6 +183,10 @@ __device__ inline void pass0(const Walk<T> &wk, T ba, T bb, P0Acc<T> &acc) {
 #pragma unroll
       for (int j = 0; j < V; ++j)
         pass0_one<T, CLASSIFY, BRACKET>(e[j], valid[u], ba, bb, s_part, aa, bA, ab, bB, acc);
+      if (SPLIT) {
+#pragma unroll
+        for (int j = 0; j < V; ++j) split_inside<T>(e[j], valid[u], ba, bb, o, cap);
+      }
       acc.sum += (double)s_part;
       if (BRACKET) {
         acc.Aa += (double)aa;
@@ -184,6 +201,7 @@ __device__ inline void pass0(const Walk<T> &wk, T ba, T bb, P0Acc<T> &acc) {
     const T v = have ? sp.W[edge_index(sp, lane)] : T(0);
     T s_part = 0, aa = 0, bA = 0, ab = 0, bB = 0;
     pass0_one<T, CLASSIFY, BRACKET>(v, have, ba, bb, s_part, aa, bA, ab, bB, acc);
+    if (SPLIT) split_inside<T>(v, have, ba, bb, o, cap);
     acc.sum += (double)s_part;
     if (BRACKET) {
       acc.Aa += (double)aa;
@@ -309,8 +327,21 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
   int dop[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   Walk<T> wk;
   if (phase == PH_PASS0) {
-    const bool use_br = a.cfg.use_bracket != 0;
-    const T ba = (T)a.cfg.bracket_lo, bb = (T)a.cfg.bracket_hi;
+    bool use_br = a.cfg.use_bracket != 0;
+    double bl = a.cfg.bracket_lo, bh = a.cfg.bracket_hi;
+    if (a.bracket) {
+      use_br = a.bracket[2] != 0.0;
+      bl = a.bracket[0];
+      bh = a.bracket[1];
+    }
+    const T ba = (T)bl, bb = (T)bh;
+    const bool p0s = use_br && a.p0_cap > 0;
+    const uint32_t cap = (uint32_t)a.p0_cap;
+    WaveOut<T> o;
+    const int wvu = __builtin_amdgcn_readfirstlane(wv);
+    o.region = (CPS_GLOBAL T *)uniform_ptr(a.z[0] + ((int64_t)bid * WPB + wvu) * a.seg_R);
+    o.top = (uint32_t)(a.seg_R - 1);
+    o.lo = o.hi = 0;
     wk.sp = make_span(a.x, a.n);
     wk.wave_mode = false;
     wk.edge_owner = bid == 0;
@@ -322,11 +353,17 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
     acc.nnan = acc.nneg = acc.npos = acc.cle_a = acc.clt_b = 0;
     acc.Aa = acc.Ba = acc.Ab = acc.Bb = 0;
     if (!p0_slow) {
-      if (use_br) pass0<T, BLOCK, SU, false, true>(wk, ba, bb, acc);
-      else pass0<T, BLOCK, UNROLL, false, false>(wk, ba, bb, acc);
+      if (p0s) pass0<T, BLOCK, SU, false, true, true>(wk, ba, bb, acc, o, cap);
+      else if (use_br) pass0<T, BLOCK, SU, false, true, false>(wk, ba, bb, acc, o, cap);
+      else pass0<T, BLOCK, UNROLL, false, false, false>(wk, ba, bb, acc, o, cap);
     } else {
-      if (use_br) pass0<T, BLOCK, SU, true, true>(wk, ba, bb, acc);
-      else pass0<T, BLOCK, SU, true, false>(wk, ba, bb, acc);
+      if (p0s) pass0<T, BLOCK, SU, true, true, true>(wk, ba, bb, acc, o, cap);
+      else if (use_br) pass0<T, BLOCK, SU, true, true, false>(wk, ba, bb, acc, o, cap);
+      else pass0<T, BLOCK, SU, true, false, false>(wk, ba, bb, acc, o, cap);
+    }
+    if (p0s && lane == 0) {
+      sh.wseg[0][wv] = o.lo;
+      sh.wseg[1][wv] = 0;
     }
     double mn = (double)acc.mn, mx = (double)acc.mx;
     int64_t cmn = acc.cmn, cmx = acc.cmx;
@@ -335,10 +372,11 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
     dv[5] = dv[6] = dv[7] = 0;
     iv[0] = (int64_t)acc.nnan; iv[1] = (int64_t)acc.nneg; iv[2] = (int64_t)acc.npos;
     iv[3] = (int64_t)acc.cle_a; iv[4] = (int64_t)acc.clt_b;
-    iv[5] = iv[6] = iv[7] = 0;
-    block_reduce<BLOCK, 5, 5>(dv, dop, iv, true, sh.d, sh.i);
+    iv[5] = (p0s && lane == 0 && o.lo > cap) ? 1 : 0;  // overflowing wavefronts
+    iv[6] = iv[7] = 0;
+    block_reduce<BLOCK, 5, 6>(dv, dop, iv, true, sh.d, sh.i);
     if (tid == 0) {
-      dv[5] = mn; dv[6] = mx; iv[5] = cmn; iv[6] = cmx;
+      dv[5] = mn; dv[6] = mx; iv[6] = cmn; iv[7] = cmx;
     }
     return;
   }
@@ -435,15 +473,15 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
     for (int f = 0; f < 8; ++f) { rd[f] = 0; ri[f] = 0; }
     for (int b = tid; b < G; b += BLOCK) {
       for (int f = 0; f < 5; ++f) rd[f] += a.sd[f * stride + b];
-      for (int f = 0; f < 5; ++f) ri[f] += a.si[f * stride + b];
+      for (int f = 0; f < 6; ++f) ri[f] += a.si[f * stride + b];
     }
-    block_reduce<BLOCK, 5, 5>(rd, rop, ri, false, sh.d, sh.i);
+    block_reduce<BLOCK, 5, 6>(rd, rop, ri, false, sh.d, sh.i);
     // (min, count) and (max, count) pairs: strided fold per thread, then a fixed tree
     double mn = __builtin_inf(), mx = -__builtin_inf();
     int64_t cmn = 0, cmx = 0;
     for (int b = tid; b < G; b += BLOCK) {
       const double m2 = a.sd[5 * stride + b], x2 = a.sd[6 * stride + b];
-      const int64_t c2 = a.si[5 * stride + b], d2 = a.si[6 * stride + b];
+      const int64_t c2 = a.si[6 * stride + b], d2 = a.si[7 * stride + b];
       if (m2 < mn) { mn = m2; cmn = c2; } else if (m2 == mn) cmn += c2;
       if (x2 > mx) { mx = x2; cmx = d2; } else if (x2 == mx) cmx += d2;
     }
@@ -454,6 +492,14 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
       r.sum = rd[0]; r.A_a = rd[1]; r.B_a = rd[2]; r.A_b = rd[3]; r.B_b = rd[4];
       r.nnan = ri[0]; r.nneg = ri[1]; r.npos = ri[2]; r.c_le_a = ri[3]; r.c_lt_b = ri[4];
       r.fmin = mn; r.fmax = mx; r.cmin = cmn; r.cmax = cmx;
+      r.split_overflow = ri[5];
+      CpConfig c = a.cfg;
+      if (a.bracket) {
+        c.use_bracket = a.bracket[2] != 0.0 ? 1 : 0;
+        c.bracket_lo = a.bracket[0];
+        c.bracket_hi = a.bracket[1];
+      }
+      c.p0_split = (c.use_bracket && a.p0_cap > 0) ? 1 : 0;
       CpState &s = sh.st;
       if (!p0_slow) {
         s = CpState{};
@@ -462,7 +508,7 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
       }
       pidx = s.work_passes;
       s.phase = PH_PASS0;
-      dev_after_pass0(s, r, a.cfg);
+      dev_after_pass0(s, r, c);
       if (a.stats && pidx < CPS_STATS_MAX_PASSES) {
         a.stats->population[pidx] = s.phase == PH_DONE ? 0 : s.cR - s.cL;
         a.stats->working[pidx] = a.n;

@@ -23,7 +23,8 @@ struct SimResult {
 
 template <typename T>
 static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_threshold,
-               double theta, int use_bracket, double blo, double bhi, SimResult *out) {
+               double theta, int use_bracket, double blo, double bhi, int p0_split,
+               int64_t p0_cap, SimResult *out) {
   CpConfig c{};
   c.maxit = maxit;
   c.dtype = sizeof(T) == 4 ? 0 : 1;
@@ -36,6 +37,7 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
   c.use_bracket = use_bracket;
   c.bracket_lo = blo;
   c.bracket_hi = bhi;
+  c.p0_split = p0_split;
   // one workgroup: a single region per split buffer, as large as the input
   const int64_t R = n + 8;
   std::vector<T> z[2] = {std::vector<T>(R), std::vector<T>(R)};
@@ -54,8 +56,14 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
     r.classified = classify ? 1 : 0;
     r.fmin = INFINITY;
     r.fmax = -INFINITY;
+    my_l = my_r = 0;
     for (int64_t i = 0; i < n; i++) {
       const T v = x[i];
+      if (use_bracket && p0_split && v > ba && v < bb) {
+        // the bracket's interior goes to the low part of split buffer 0, while it fits
+        if (my_l < p0_cap) z[0][my_l] = v;
+        my_l++;
+      }
       if (std::isnan(v)) { r.nnan++; continue; }
       const bool fin = !classify || std::isfinite(v);
       if (classify && v == (T)-INFINITY) r.nneg++;
@@ -76,6 +84,7 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
         if (v < bb) r.c_lt_b++;
       }
     }
+    r.split_overflow = (use_bracket && p0_split && my_l > p0_cap) ? 1 : 0;
     cp_after_pass0(s, r, c);
     if (!(s.phase == PH_PASS0 && s.p0_slow)) break;
   }
@@ -158,11 +167,11 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
 extern "C" {
 
 int sim_select_f32(const float *x, int64_t n, int64_t k, int maxit, int64_t ft, double theta,
-                   int ub, double blo, double bhi, SimResult *out) {
-  return sim<float>(x, n, k, maxit, ft, theta, ub, blo, bhi, out);
+                   int ub, double blo, double bhi, int p0_split, int64_t p0_cap, SimResult *out) {
+  return sim<float>(x, n, k, maxit, ft, theta, ub, blo, bhi, p0_split, p0_cap, out);
 }
 int sim_select_f64(const double *x, int64_t n, int64_t k, int maxit, int64_t ft, double theta,
-                   int ub, double blo, double bhi, SimResult *out) {
-  return sim<double>(x, n, k, maxit, ft, theta, ub, blo, bhi, out);
+                   int ub, double blo, double bhi, int p0_split, int64_t p0_cap, SimResult *out) {
+  return sim<double>(x, n, k, maxit, ft, theta, ub, blo, bhi, p0_split, p0_cap, out);
 }
 }

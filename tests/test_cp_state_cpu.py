@@ -36,15 +36,18 @@ def sim(tmp_path_factory):
         fn = getattr(L, name)
         fn.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int64,
                        ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                       ctypes.POINTER(SimResult)]
+                       ctypes.c_int, ctypes.c_int64, ctypes.POINTER(SimResult)]
         fn.restype = ctypes.c_int
 
-    def run(x, k, maxit=64, final_threshold=64, theta=0.5, bracket=None):
+    def run(x, k, maxit=64, final_threshold=64, theta=0.5, bracket=None, p0_split=False,
+            p0_cap=None):
         r = SimResult()
         fn = L.sim_select_f32 if x.dtype == np.float32 else L.sim_select_f64
         ub = 1 if bracket is not None else 0
         blo, bhi = bracket if bracket is not None else (0.0, 0.0)
-        rc = fn(x.ctypes.data, x.size, k, maxit, final_threshold, theta, ub, blo, bhi, ctypes.byref(r))
+        cap = x.size if p0_cap is None else p0_cap
+        rc = fn(x.ctypes.data, x.size, k, maxit, final_threshold, theta, ub, blo, bhi,
+                1 if p0_split else 0, cap, ctypes.byref(r))
         assert rc == 0, rc
         return r
     return run
@@ -83,20 +86,40 @@ def test_infinities_and_zeros(sim, oracle_mod, dtype):
                 _check(sim(x, k, **opts), ref, (x, k, opts))
 
 
+def _expected_ends(x, k, a, b):
+    """Which proposed ends the counts prove (bit 0: a, bit 1: b), or 0 when pass 0 already
+    answers (x_(k) is the minimum or the maximum)."""
+    lo, hi = x.min(), x.max()
+    if k <= np.sum(x == lo) or k > x.size - np.sum(x == hi):
+        return 0
+    a, b = np.array(a, x.dtype), np.array(b, x.dtype)
+    left = np.sum(x <= a) < k and a > lo
+    right = k <= np.sum(x < b) and b < hi
+    return int(left) | (int(right) << 1)
+
+
+@pytest.mark.parametrize("p0_split", [False, True])
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
-def test_proposed_brackets(sim, oracle_mod, dtype):
+def test_proposed_brackets(sim, oracle_mod, dtype, p0_split):
     x = workloads.single_array("normal", 100_000, dtype, seed=4)
     s = np.sort(x)
-    for k in (1, 10, 5000, 50_000, 99_999, 100_000):
+    for k in (1, 2, 10, 5000, 50_000, 99_999, 100_000):
         ref = oracle_mod.select_kth(x, k)
         v = s[k - 1]
         for (a, b) in [(v - 0.01, v + 0.01), (v - 1e-7, v + 1e-7), (v, v + 1.0), (v - 1.0, v),
-                       (-10.0, 10.0), (v + 0.5, v + 1.0), (v - 1.0, v - 0.5), (3.0, -3.0)]:
-            r = sim(x, k, final_threshold=16, bracket=(float(a), float(b)))
-            _check(r, ref, (k, a, b))
-            holds = np.sum(x <= np.array(a, dtype)) < k <= np.sum(x < np.array(b, dtype))
-            if not holds:
-                assert r.bracket_used == 0
+                       (-10.0, 10.0), (v + 0.5, v + 1.0), (v - 1.0, v - 0.5), (3.0, -3.0),
+                       (v - 0.3, v + 1e-9), (-np.inf, v + 0.2), (v - 0.2, np.inf),
+                       (np.nan, v + 0.1), (v - 0.1, np.nan)]:
+            for cap in (None, 10):
+                r = sim(x, k, final_threshold=16, bracket=(float(a), float(b)),
+                        p0_split=p0_split, p0_cap=cap)
+                _check(r, ref, (k, a, b, cap))
+                assert r.bracket_used == _expected_ends(x, k, a, b), (k, a, b)
+                inside = int(np.sum((x > np.array(a, dtype)) & (x < np.array(b, dtype))))
+                adopted = p0_split and r.bracket_used == 3 and (cap is None or inside <= cap)
+                # an adopted pass-0 split spares the evaluation passes over x
+                if adopted:
+                    assert r.passes == 1, (k, a, b, r.passes)
 
 
 def test_passes_halve_on_smooth_data(sim):
