@@ -110,7 +110,12 @@ typedef struct cps_eval {
  * compact_proposal: with a proposed bracket, pass 0 also writes the elements strictly
  *                   inside it to the split workspace (at most 1/8 of each wavefront's
  *                   share); when both ends hold and everything fit, later passes read only
- *                   those elements and the input is read once.  1 (default) or 0. */
+ *                   those elements and the input is read once.  1 (default) or 0.
+ * hist_bits:        once the bracket's elements are compacted, finish with exact passes
+ *                   that count them in 2^hist_bits bins of their ordered bit patterns and
+ *                   keep the bin holding the rank (a multi-workgroup radix select on the
+ *                   compacted elements; the paper sorts them).  1..12, default 12; 0 keeps
+ *                   cutting-plane passes to the end. */
 typedef struct cps_options {
   int32_t maxit;
   int32_t final_threshold;
@@ -121,6 +126,8 @@ typedef struct cps_options {
   int32_t use_bracket;
   int32_t compact_proposal;
   double bracket_lo, bracket_hi;
+  int32_t hist_bits;
+  int32_t reserved0;
 } cps_options;
 
 #define CPS_STATS_MAX_PASSES 96

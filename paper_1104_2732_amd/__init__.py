@@ -57,7 +57,8 @@ class Options(ctypes.Structure):
                 ("partition_fraction", ctypes.c_double), ("grid_blocks", ctypes.c_int32),
                 ("block_threads", ctypes.c_int32), ("spin_limit", ctypes.c_int64),
                 ("use_bracket", ctypes.c_int32), ("compact_proposal", ctypes.c_int32),
-                ("bracket_lo", ctypes.c_double), ("bracket_hi", ctypes.c_double)]
+                ("bracket_lo", ctypes.c_double), ("bracket_hi", ctypes.c_double),
+                ("hist_bits", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
 
 
 class BatchOptions(ctypes.Structure):

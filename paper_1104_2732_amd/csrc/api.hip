@@ -46,7 +46,7 @@ namespace {
 // partials, two split buffers (one region of seg_R elements per workgroup each) and the
 // gather buffer.
 struct SelectLayout {
-  size_t st, sync, sd, si, z0, z1, zf, total;
+  size_t st, sync, gh, sd, si, z0, z1, zf, total;
   int64_t slot_stride, seg_R, zcap;
 };
 
@@ -57,6 +57,8 @@ SelectLayout select_layout(int64_t seg_R, int grid, int64_t zcap, int gmax, size
   off = align_up(off + sizeof(cps::CpState), 256);
   L.sync = off;
   off = align_up(off + sizeof(cps::SyncCtl), 256);
+  L.gh = off;  // histogram counters, inside the cleared first part of fresh memory
+  off = align_up(off + cps::kHistMaxBins * sizeof(uint64_t), 256);
   L.slot_stride = gmax;
   L.sd = off;
   off = align_up(off + 8 * (size_t)gmax * sizeof(double), 256);
@@ -129,6 +131,7 @@ int resolve(cps_handle *h, int64_t n, int dtype, const cps_options *opt, Resolve
       o.partition_fraction > 1.0 || o.grid_blocks < 0 || o.spin_limit < 0)
     return CPS_EINVAL;
   if (o.block_threads != 0 && o.block_threads != cps::kSelectBlock) return CPS_EINVAL;
+  if (o.hist_bits < 0 || (1 << o.hist_bits) > cps::kHistMaxBins) return CPS_EINVAL;
   r.cfg = cps::CpConfig{};
   r.cfg.maxit = o.maxit;
   r.cfg.dtype = dtype;
@@ -139,6 +142,7 @@ int resolve(cps_handle *h, int64_t n, int dtype, const cps_options *opt, Resolve
   r.cfg.use_bracket = o.use_bracket ? 1 : 0;
   r.cfg.bracket_lo = o.bracket_lo;
   r.cfg.bracket_hi = o.bracket_hi;
+  r.cfg.hist_bits = o.hist_bits;
   const int per_cu = dtype == CPS_F32 ? h->max_blocks_f32 : h->max_blocks_f64;
   const int gmax = h->cu_count * per_cu;
   if (gmax < 1) return CPS_ENODEV;
@@ -203,6 +207,7 @@ int run_select(cps_handle *h, const T *x, int64_t n, int64_t k, const cps_option
   // a proposed bracket's interior may take up to 1/8 of each wavefront's region in pass 0
   const bool proposal = bracket_dev != nullptr || r.cfg.use_bracket != 0;
   a.p0_cap = (proposal && r.compact_proposal) ? L.seg_R / 8 : 0;
+  a.ghist = (uint64_t *)(base + L.gh);
   hipError_t e = cps::launch_select<T>(a, r.grid, stream);
   if (e != hipSuccess) return hip_fail(e);
   return CPS_OK;
@@ -425,6 +430,7 @@ void cps_default_options(cps_options *opt) {
   opt->spin_limit = 0;
   opt->use_bracket = 0;
   opt->compact_proposal = 1;
+  opt->hist_bits = 12;
 }
 
 int cps_last_hip_error(void) { return g_last_hip; }
@@ -535,7 +541,8 @@ int cps_objective(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
   const size_t pd_bytes = align_up((size_t)ny * nb * 4 * sizeof(double), 256);
   const size_t pi_bytes = align_up((size_t)ny * nb * 3 * sizeof(int64_t), 256);
   // keep clear of the select layout's state and synchronisation words at the start
-  const size_t off = align_up(sizeof(cps::CpState), 256) + align_up(sizeof(cps::SyncCtl), 256);
+  const size_t off = align_up(sizeof(cps::CpState), 256) + align_up(sizeof(cps::SyncCtl), 256) +
+                     align_up(cps::kHistMaxBins * sizeof(uint64_t), 256);
   rc = ensure_workspace(h, off + pd_bytes + pi_bytes, s);
   if (rc) return rc;
   double *pd = (double *)((char *)h->ws + off);

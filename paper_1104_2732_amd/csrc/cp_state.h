@@ -49,7 +49,9 @@
 
 namespace cps {
 
-enum Phase : int32_t { PH_PASS0 = 0, PH_EVAL = 1, PH_GATHER = 2, PH_FINAL = 3, PH_DONE = 4 };
+enum Phase : int32_t {
+  PH_PASS0 = 0, PH_EVAL = 1, PH_GATHER = 2, PH_FINAL = 3, PH_DONE = 4, PH_HIST = 5
+};
 
 // status values mirror enum cps_status in cpselect.h
 enum : int32_t { ST_OK = 0, ST_NAN = 1, ST_TIMEOUT = 2, ST_INTERNAL = 3, ST_BADARG = 4 };
@@ -65,6 +67,9 @@ struct CpConfig {
   int32_t p0_split;         // pass 0 with a bracket also writes the elements inside it
   double bracket_lo, bracket_hi;
   int64_t split_cap;        // the first split needs population <= split_cap (0 = no limit)
+  int32_t hist_bits;        // exact select on the compacted bracket by key histograms of
+                            // 2^hist_bits bins (0: cutting-plane passes to the end)
+  int32_t pad1;
 };
 
 // Results of pass 0 over the whole input (Section 4, step 0: min, max and sum in
@@ -112,7 +117,8 @@ struct CpState {
                            // 2: the gather buffer (contiguous, wlen elements)
   int32_t zout;            // buffer the next split writes
   int32_t side;            // split buffers: 0 = the low part of each region, 1 = the high part
-  int32_t pad2;
+  int32_t narrowed;        // a histogram pass narrowed the bracket: the working set holds
+                           // elements outside it, and f at the ends is no longer known
   int64_t wlen;            // elements in the working set
   int32_t passes;          // full reads of the input
   int32_t work_passes;     // all passes
@@ -250,6 +256,12 @@ CPS_HD inline void cp_plan(CpState &s, const CpConfig &c) {
     }
     s.phase = PH_GATHER;  // copy the bracket's elements into one contiguous buffer
     s.filter = s.on_bracket ? 0 : 1;
+    return;
+  }
+  if (c.hist_bits > 0 && (s.on_bracket || s.narrowed) && s.wbuf >= 0) {
+    // the bracket's elements are compacted: finish with the exact select by key
+    // histograms over them (the paper sorts the compacted elements instead)
+    s.phase = PH_HIST;
     return;
   }
   if (s.on_bracket) {
@@ -435,6 +447,69 @@ CPS_HD inline void cp_after_gather(CpState &s, int64_t gathered) {
   s.filter = 0;
   s.phase = PH_FINAL;
   s.final_size = gathered;
+}
+
+// Key-histogram geometry of the bracket's possible values [lo, hi]: bin of an element
+// with ordered key K is (K - klo) >> shift, with at most 2^bits bins.
+template <typename K> struct HistGeom {
+  K klo, khi;
+  int32_t shift;
+  int32_t nbins;
+};
+
+CPS_HD inline HistGeom<uint64_t> hist_geometry(double lo, double hi, int32_t dtype, int32_t bits) {
+  HistGeom<uint64_t> g;
+  g.klo = dtype == 0 ? (uint64_t)key32((float)lo) : key64(lo);
+  g.khi = dtype == 0 ? (uint64_t)key32((float)hi) : key64(hi);
+  const uint64_t span = g.khi - g.klo;
+  int32_t sh = 0;
+  while ((span >> sh) >= ((uint64_t)1 << bits)) ++sh;
+  g.shift = sh;
+  g.nbins = (int32_t)(span >> sh) + 1;
+  return g;
+}
+
+CPS_HD inline double unkey_T(uint64_t k, int32_t dtype) {
+  return dtype == 0 ? (double)unkey32((uint32_t)k) : unkey64(k);
+}
+
+// After a histogram pass over the working set: bin `b` holds rank k - cL of the bracket's
+// elements, with `below` of them in lower bins and `cnt` in bin b.  The bracket narrows to
+// the values of that bin (an exact step: every element of the bracket lies in exactly one
+// bin), counts follow from the histogram, and one key left means the value is x_(k).
+CPS_HD inline void cp_after_hist(CpState &s, int32_t b, int64_t below, int64_t cnt,
+                                 const CpConfig &c) {
+  s.work_passes++;
+  if (s.wbuf < 0) s.passes++;
+  s.elements_read += s.wlen;
+  const int64_t r = s.k - s.cL;
+  if (cnt < 1 || below >= r || below + cnt < r) {  // the counts and the data disagree
+    s.status = ST_INTERNAL;
+    cp_finish(s, 0.0, 0, 0);
+    return;
+  }
+  const HistGeom<uint64_t> g = hist_geometry(s.lo, s.hi, c.dtype, c.hist_bits);
+  const uint64_t nlo = g.klo + ((uint64_t)b << g.shift);
+  uint64_t nhi = nlo + (((uint64_t)1 << g.shift) - 1);
+  if (nhi > g.khi || nhi < nlo) nhi = g.khi;
+  if (nlo == nhi) {
+    cp_finish(s, unkey_T(nlo, c.dtype), s.cL + below, cnt);
+    return;
+  }
+  if (nlo > g.klo) {  // everything at or below the bin's predecessor key is below the bin
+    // (the key just below +0's is no value's key: it decodes to -0, which equals +0)
+    const uint64_t hole = c.dtype == 0 ? 0x7fffffffull : 0x7fffffffffffffffull;
+    s.yL = unkey_T(nlo - 1 == hole ? nlo - 2 : nlo - 1, c.dtype);
+    s.cL += below;
+  }
+  if (nhi < g.khi) s.yR = unkey_T(nhi + 1, c.dtype);
+  s.cR = s.cL + cnt;
+  s.lo = unkey_T(nlo, c.dtype);
+  s.hi = unkey_T(nhi, c.dtype);
+  s.lo_data = s.hi_data = 0;
+  s.on_bracket = 0;
+  s.narrowed = 1;
+  cp_plan(s, c);
 }
 
 // After the exact select of rank k - cL among the working set's elements inside the

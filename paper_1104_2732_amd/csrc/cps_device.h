@@ -75,6 +75,24 @@ __device__ inline int64_t wave_sum_i64(int64_t v) {
   return v;
 }
 
+// Exclusive prefix sum over the workgroup in thread order (wsum: one slot per wavefront).
+template <int BLOCK>
+__device__ inline uint64_t block_exclusive_scan(uint64_t v, uint64_t *wsum) {
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  uint64_t x = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint64_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == kWave - 1) wsum[wv] = x;
+  __syncthreads();
+  uint64_t off = 0;
+  for (int w = 0; w < wv; ++w) off += wsum[w];
+  __syncthreads();
+  return off + x - v;
+}
+
 // ------------------------------------------------------------------ agent-scope sync
 // The eight XCDs have separate L2 caches; agent-scope release/acquire makes the
 // compiler write back / invalidate them around the synchronising operation.

@@ -12,9 +12,13 @@
 //               bracket's elements at t into per-wavefront private regions of a
 //               workspace buffer (count-and-compact, with no atomics), and later passes
 //               read only the side that holds x_(k);
+//   histogram   once the bracket's elements are compacted, each pass counts them in
+//               key bins of the bracket's value range and narrows the bracket to the
+//               bin holding the remaining rank (an exact select on the compacted
+//               elements, in place of the paper's sort of them);
 //   gather      the bracket's remaining elements are copied into one contiguous buffer;
 //   final       one workgroup selects the remaining rank exactly (radix select on the
-//               ordered keys), in place of the paper's sort of the compacted array.
+//               ordered keys).
 // Between passes the grid synchronises through two-level arrival counters; the last
 // workgroup to arrive reduces the per-workgroup partials in a fixed order and advances
 // the cutting-plane state (cp_state.h), so no pass needs the host.  The kernel is
@@ -38,6 +42,10 @@ __device__ __noinline__ void dev_after_gather(CpState &s, int64_t gathered) {
 }
 __device__ __noinline__ void dev_after_final(CpState &s, double v, int64_t below, int64_t eq) {
   cp_after_final(s, v, below, eq);
+}
+__device__ __noinline__ void dev_after_hist(CpState &s, int32_t b, int64_t below, int64_t cnt,
+                                            const CpConfig &c) {
+  cp_after_hist(s, b, below, cnt, c);
 }
 
 // How the threads of a workgroup walk the working set.  BLOCK mode: the whole input,
@@ -63,6 +71,7 @@ template <typename T, int BLOCK> struct Shared {
   int64_t misc[8];
   int last;
   int timed_out;
+  uint32_t rh[kHistMaxBins];  // key histogram of a histogram pass
 };
 
 // Which side of the trial point an element goes to in a split: the bracket's elements
@@ -212,22 +221,25 @@ __device__ inline void pass0(const Walk<T> &wk, T ba, T bb, P0Acc<T> &acc, WaveO
   }
 }
 
-// Gather from the whole input: every element inside (yL, yR) goes to the gather buffer.
-// Offsets come from one atomic per wavefront-step that holds any such element (the
-// bracket holds few elements when this runs).
+// Gather: every element of the walk inside (yL, yR) goes to the gather buffer.  Offsets
+// come from one atomic per wavefront-step that holds any such element (the bracket holds
+// few elements when this runs).
 template <typename T, int BLOCK, int U>
-__device__ inline void gather_from_input(const Walk<T> &wk, T yL, T yR, T *zf,
-                                               uint64_t *gcur, int64_t &written) {
+__device__ inline void gather_walk(const Walk<T> &wk, T yL, T yR, T *zf, uint64_t *gcur,
+                                   int64_t &written) {
   constexpr int V = Traits<T>::kVec;
   using Vec = typename Traits<T>::Vec;
   const int tid = threadIdx.x, lane = tid % kWave;
   const Span<T> &sp = wk.sp;
-  const int64_t step_vecs = (int64_t)BLOCK * U;
-  for (int64_t base = (int64_t)blockIdx.x * step_vecs; base < sp.nvec;
-       base += (int64_t)gridDim.x * step_vecs) {
+  const int64_t step_vecs = wk.wave_mode ? (int64_t)kWave * U : (int64_t)BLOCK * U;
+  const int64_t first = wk.wave_mode ? 0 : (int64_t)blockIdx.x * step_vecs;
+  const int64_t stride = wk.wave_mode ? step_vecs : (int64_t)gridDim.x * step_vecs;
+  const int me = wk.wave_mode ? lane : tid;
+  const int per_u = wk.wave_mode ? kWave : BLOCK;
+  for (int64_t base = first; base < sp.nvec; base += stride) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t vi = base + (int64_t)u * BLOCK + tid;
+      const int64_t vi = base + (int64_t)u * per_u + me;
       const bool valid = vi < sp.nvec;
       Vec raw;
       if (valid) raw = sp.V[vi];
@@ -250,7 +262,7 @@ __device__ inline void gather_from_input(const Walk<T> &wk, T yL, T yR, T *zf,
       }
     }
   }
-  if (sp.nedge > 0 && wk.edge_owner && tid < kWave) {
+  if (sp.nedge > 0 && wk.edge_owner && (wk.wave_mode || tid < kWave)) {
     const bool have = lane < sp.nedge;
     const T v = have ? sp.W[edge_index(sp, lane)] : T(0);
     const bool in = have && v > yL && v < yR;
@@ -261,6 +273,49 @@ __device__ inline void gather_from_input(const Walk<T> &wk, T yL, T yR, T *zf,
       off = __shfl(off, 0);
       if (in) zf[off + lane_rank(m)] = v;
       written += popc(m);
+    }
+  }
+}
+
+// Histogram pass: every element of the walk whose ordered key lies in [klo, khi] is counted
+// in LDS bin (key - klo) >> shift.
+template <typename T, int BLOCK, int U>
+__device__ inline void hist_walk(const Walk<T> &wk, typename Traits<T>::Key klo,
+                                 typename Traits<T>::Key khi, int shift, uint32_t *rh) {
+  constexpr int V = Traits<T>::kVec;
+  using Vec = typename Traits<T>::Vec;
+  using Key = typename Traits<T>::Key;
+  const int tid = threadIdx.x, lane = tid % kWave;
+  const Span<T> &sp = wk.sp;
+  const int64_t step_vecs = wk.wave_mode ? (int64_t)kWave * U : (int64_t)BLOCK * U;
+  const int64_t first = wk.wave_mode ? 0 : (int64_t)blockIdx.x * step_vecs;
+  const int64_t stride = wk.wave_mode ? step_vecs : (int64_t)gridDim.x * step_vecs;
+  const int me = wk.wave_mode ? lane : tid;
+  const int per_u = wk.wave_mode ? kWave : BLOCK;
+  for (int64_t base = first; base < sp.nvec; base += stride) {
+    Vec raw[U];
+    bool valid[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t vi = base + (int64_t)u * per_u + me;
+      valid[u] = vi < sp.nvec;
+      if (valid[u]) raw[u] = sp.V[vi];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      T e[V];
+      vec_to_arr<T>(raw[u], e);
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        const Key K = Traits<T>::key(e[j]);
+        if (valid[u] && K >= klo && K <= khi) atomicAdd(&rh[(uint32_t)((K - klo) >> shift)], 1u);
+      }
+    }
+  }
+  if (sp.nedge > 0 && wk.edge_owner && (wk.wave_mode || tid < kWave)) {
+    if (lane < sp.nedge) {
+      const Key K = Traits<T>::key(sp.W[edge_index(sp, lane)]);
+      if (K >= klo && K <= khi) atomicAdd(&rh[(uint32_t)((K - klo) >> shift)], 1u);
     }
   }
 }
@@ -365,6 +420,8 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
       sh.wseg[0][wv] = o.lo;
       sh.wseg[1][wv] = 0;
     }
+    if (bid == 0 && a.cfg.hist_bits > 0)
+      for (int b = tid; b < (1 << a.cfg.hist_bits); b += BLOCK) a.ghist[b] = 0;
     double mn = (double)acc.mn, mx = (double)acc.mx;
     int64_t cmn = acc.cmn, cmx = acc.cmx;
     block_pair_fold<BLOCK>(mn, cmn, mx, cmx, sh.d, sh.i);
@@ -401,9 +458,20 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
   acc.succ = t_inf<T>();
   acc.L = acc.G = 0;
   int64_t written = 0;
-  if (s.phase == PH_GATHER) {
-    if (s.wbuf < 0) {
-      gather_from_input<T, BLOCK, SU>(wk, yL, yR, a.zf, &a.sync->gcur, written);
+  if (s.phase == PH_HIST) {
+    const HistGeom<uint64_t> g = hist_geometry(s.lo, s.hi, a.cfg.dtype, a.cfg.hist_bits);
+    for (int b = tid; b < g.nbins; b += BLOCK) sh.rh[b] = 0u;
+    __syncthreads();
+    hist_walk<T, BLOCK, UNROLL>(wk, (typename Traits<T>::Key)g.klo, (typename Traits<T>::Key)g.khi,
+                                g.shift, sh.rh);
+    __syncthreads();
+    for (int b = tid; b < g.nbins; b += BLOCK) {
+      const uint32_t c = sh.rh[b];
+      if (c) atomic_add_relaxed(&a.ghist[b], (uint64_t)c);
+    }
+  } else if (s.phase == PH_GATHER) {
+    if (s.wbuf < 0 || s.filter) {
+      gather_walk<T, BLOCK, SU>(wk, yL, yR, a.zf, &a.sync->gcur, written);
     } else {
       // every element of a segment lies inside the bracket: one offset per workgroup
       const int64_t len = wk.sp.m;
@@ -512,6 +580,44 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
       if (a.stats && pidx < CPS_STATS_MAX_PASSES) {
         a.stats->population[pidx] = s.phase == PH_DONE ? 0 : s.cR - s.cL;
         a.stats->working[pidx] = a.n;
+      }
+    }
+  } else if (phase == PH_HIST) {
+    // the bin holding rank k - cL: an exclusive scan of the bin counts in a fixed order
+    const CpState &s0 = sh.st;
+    const HistGeom<uint64_t> g = hist_geometry(s0.lo, s0.hi, a.cfg.dtype, a.cfg.hist_bits);
+    const uint64_t r = (uint64_t)(s0.k - s0.cL);
+    constexpr int BPT = kHistMaxBins / BLOCK;
+    uint64_t hv[BPT];
+    uint64_t tot = 0;
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const int b = tid * BPT + j;
+      hv[j] = b < g.nbins ? a.ghist[b] : 0;
+      tot += hv[j];
+    }
+    if (tid == 0) sh.misc[0] = -1;
+    uint64_t cum = block_exclusive_scan<BLOCK>(tot, sh.gbase);
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      if (cum < r && r <= cum + hv[j]) {
+        sh.misc[0] = tid * BPT + j;
+        sh.misc[1] = (int64_t)cum;
+        sh.misc[2] = (int64_t)hv[j];
+      }
+      cum += hv[j];
+    }
+    __syncthreads();
+    for (int b = tid; b < g.nbins; b += BLOCK) a.ghist[b] = 0;  // ready for the next pass
+    if (tid == 0) {
+      CpState &s = sh.st;
+      pidx = s.work_passes;
+      const int64_t wl = s.wlen;
+      const int32_t bsel = (int32_t)sh.misc[0];
+      dev_after_hist(s, bsel, bsel < 0 ? 0 : sh.misc[1], bsel < 0 ? 0 : sh.misc[2], a.cfg);
+      if (a.stats && pidx < CPS_STATS_MAX_PASSES) {
+        a.stats->population[pidx] = s.phase == PH_DONE ? 0 : s.cR - s.cL;
+        a.stats->working[pidx] = wl;
       }
     }
   } else {

@@ -24,7 +24,7 @@ struct SimResult {
 template <typename T>
 static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_threshold,
                double theta, int use_bracket, double blo, double bhi, int p0_split,
-               int64_t p0_cap, SimResult *out) {
+               int64_t p0_cap, int hist_bits, SimResult *out) {
   CpConfig c{};
   c.maxit = maxit;
   c.dtype = sizeof(T) == 4 ? 0 : 1;
@@ -38,6 +38,7 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
   c.bracket_lo = blo;
   c.bracket_hi = bhi;
   c.p0_split = p0_split;
+  c.hist_bits = hist_bits;
   // one workgroup: a single region per split buffer, as large as the input
   const int64_t R = n + 8;
   std::vector<T> z[2] = {std::vector<T>(R), std::vector<T>(R)};
@@ -96,11 +97,28 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
     len = my_r;
     return z[s.wbuf].data() + (R - my_r);
   };
-  while (s.phase == PH_EVAL || s.phase == PH_GATHER) {
+  while (s.phase == PH_EVAL || s.phase == PH_GATHER || s.phase == PH_HIST) {
     int64_t wl = 0;
     const T *W = working(wl);
     if (s.wbuf >= 0 && s.wbuf < 2 && wl != s.wlen) return -13;
     const T t = (T)s.t, yL = (T)s.yL, yR = (T)s.yR;
+    if (s.phase == PH_HIST) {
+      // key histogram of the working set's elements inside [lo, hi], then the bin of
+      // rank k - cL
+      const HistGeom<uint64_t> g = hist_geometry(s.lo, s.hi, c.dtype, c.hist_bits);
+      std::vector<int64_t> h((size_t)g.nbins, 0);
+      for (int64_t i = 0; i < wl; i++) {
+        const uint64_t K = sizeof(T) == 4 ? (uint64_t)key32((float)W[i]) : key64((double)W[i]);
+        if (K >= g.klo && K <= g.khi) h[(size_t)((K - g.klo) >> g.shift)]++;
+      }
+      const int64_t r = s.k - s.cL;
+      int64_t below = 0;
+      int32_t b = 0;
+      while (b < g.nbins && below + h[(size_t)b] < r) below += h[(size_t)b++];
+      if (b >= g.nbins) return -16;
+      cp_after_hist(s, b, below, h[(size_t)b], c);
+      continue;
+    }
     if (s.phase == PH_GATHER) {
       int64_t g = 0;
       for (int64_t i = 0; i < wl; i++) {
@@ -167,11 +185,13 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
 extern "C" {
 
 int sim_select_f32(const float *x, int64_t n, int64_t k, int maxit, int64_t ft, double theta,
-                   int ub, double blo, double bhi, int p0_split, int64_t p0_cap, SimResult *out) {
-  return sim<float>(x, n, k, maxit, ft, theta, ub, blo, bhi, p0_split, p0_cap, out);
+                   int ub, double blo, double bhi, int p0_split, int64_t p0_cap, int hist_bits,
+                   SimResult *out) {
+  return sim<float>(x, n, k, maxit, ft, theta, ub, blo, bhi, p0_split, p0_cap, hist_bits, out);
 }
 int sim_select_f64(const double *x, int64_t n, int64_t k, int maxit, int64_t ft, double theta,
-                   int ub, double blo, double bhi, int p0_split, int64_t p0_cap, SimResult *out) {
-  return sim<double>(x, n, k, maxit, ft, theta, ub, blo, bhi, p0_split, p0_cap, out);
+                   int ub, double blo, double bhi, int p0_split, int64_t p0_cap, int hist_bits,
+                   SimResult *out) {
+  return sim<double>(x, n, k, maxit, ft, theta, ub, blo, bhi, p0_split, p0_cap, hist_bits, out);
 }
 }

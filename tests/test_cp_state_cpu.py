@@ -36,18 +36,18 @@ def sim(tmp_path_factory):
         fn = getattr(L, name)
         fn.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int64,
                        ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                       ctypes.c_int, ctypes.c_int64, ctypes.POINTER(SimResult)]
+                       ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(SimResult)]
         fn.restype = ctypes.c_int
 
     def run(x, k, maxit=64, final_threshold=64, theta=0.5, bracket=None, p0_split=False,
-            p0_cap=None):
+            p0_cap=None, hist_bits=0):
         r = SimResult()
         fn = L.sim_select_f32 if x.dtype == np.float32 else L.sim_select_f64
         ub = 1 if bracket is not None else 0
         blo, bhi = bracket if bracket is not None else (0.0, 0.0)
         cap = x.size if p0_cap is None else p0_cap
         rc = fn(x.ctypes.data, x.size, k, maxit, final_threshold, theta, ub, blo, bhi,
-                1 if p0_split else 0, cap, ctypes.byref(r))
+                1 if p0_split else 0, cap, hist_bits, ctypes.byref(r))
         assert rc == 0, rc
         return r
     return run
@@ -70,7 +70,9 @@ def test_state_machine_matches_oracle(sim, oracle_mod, dist, dtype):
                 continue
             ref = oracle_mod.select_kth(x, k)
             for opts in (dict(), dict(final_threshold=1), dict(final_threshold=4, theta=0.0),
-                         dict(maxit=0, final_threshold=8), dict(maxit=2, final_threshold=2, theta=1.0)):
+                         dict(maxit=0, final_threshold=8), dict(maxit=2, final_threshold=2, theta=1.0),
+                         dict(hist_bits=12), dict(hist_bits=2, final_threshold=1),
+                         dict(hist_bits=1, final_threshold=1, theta=1.0)):
                 _check(sim(x, k, **opts), ref, (dist, n, k, opts))
 
 
@@ -82,7 +84,9 @@ def test_infinities_and_zeros(sim, oracle_mod, dtype):
         x = np.array(rng.choice(base, size=int(rng.integers(1, 60))), dtype=dtype)
         for k in range(1, x.size + 1):
             ref = oracle_mod.select_kth(x, k)
-            for opts in (dict(final_threshold=1), dict(maxit=0, final_threshold=1)):
+            for opts in (dict(final_threshold=1), dict(maxit=0, final_threshold=1),
+                         dict(final_threshold=1, theta=1.0, hist_bits=1),
+                         dict(final_threshold=1, theta=1.0, hist_bits=3)):
                 _check(sim(x, k, **opts), ref, (x, k, opts))
 
 
@@ -110,10 +114,10 @@ def test_proposed_brackets(sim, oracle_mod, dtype, p0_split):
                        (-10.0, 10.0), (v + 0.5, v + 1.0), (v - 1.0, v - 0.5), (3.0, -3.0),
                        (v - 0.3, v + 1e-9), (-np.inf, v + 0.2), (v - 0.2, np.inf),
                        (np.nan, v + 0.1), (v - 0.1, np.nan)]:
-            for cap in (None, 10):
+            for cap, hb in ((None, 0), (10, 0), (None, 12), (None, 3)):
                 r = sim(x, k, final_threshold=16, bracket=(float(a), float(b)),
-                        p0_split=p0_split, p0_cap=cap)
-                _check(r, ref, (k, a, b, cap))
+                        p0_split=p0_split, p0_cap=cap, hist_bits=hb)
+                _check(r, ref, (k, a, b, cap, hb))
                 assert r.bracket_used == _expected_ends(x, k, a, b), (k, a, b)
                 inside = int(np.sum((x > np.array(a, dtype)) & (x < np.array(b, dtype))))
                 adopted = p0_split and r.bracket_used == 3 and (cap is None or inside <= cap)
@@ -140,3 +144,26 @@ def test_bisection_bound(sim, oracle_mod):
     r = sim(x, 777, maxit=0, final_threshold=1)
     _check(r, ref, "bisect")
     assert r.kelley == 0 and r.bisect <= 34
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_histogram_select_edges(sim, oracle_mod, dtype):
+    """The key-histogram finish around signed zeros, denormals and one-key bins."""
+    tiny = np.finfo(dtype).smallest_subnormal
+    vals = np.array([-0.0, 0.0, tiny, -tiny, 2 * tiny, -2 * tiny, 1.0, -1.0, 1e-30, -1e-30],
+                    dtype=dtype)
+    rng = np.random.default_rng(9)
+    for trial in range(30):
+        x = rng.choice(vals, size=int(rng.integers(50, 400))).astype(dtype)
+        for k in (1, 2, x.size // 3, x.size // 2, x.size - 1, x.size):
+            ref = oracle_mod.select_kth(x, k)
+            for hb in (1, 2, 4, 12):
+                _check(sim(x, k, final_threshold=1, theta=1.0, hist_bits=hb), ref, (trial, k, hb))
+
+
+def test_histogram_finish_cuts_passes(sim):
+    n = 1 << 20
+    x = workloads.single_array("normal", n, np.float32, seed=3)
+    plain = sim(x, (n + 1) // 2, final_threshold=4096)
+    hist = sim(x, (n + 1) // 2, final_threshold=4096, hist_bits=12)
+    assert hist.work_passes < plain.work_passes and hist.work_passes <= 7

@@ -65,6 +65,10 @@ def test_parity_default_options(sel, oracle_mod, dist, dtype):
     dict(final_threshold=32, grid_blocks=1),
     dict(final_threshold=32, grid_blocks=7),
     dict(final_threshold=100, grid_blocks=3, partition_fraction=0.25),
+    dict(final_threshold=16, hist_bits=0),
+    dict(final_threshold=1, partition_fraction=1.0, hist_bits=1),
+    dict(final_threshold=1, partition_fraction=1.0, hist_bits=3, grid_blocks=5),
+    dict(final_threshold=64, partition_fraction=1.0, hist_bits=12),
 ])
 def test_parity_forced_paths(sel, oracle_mod, dtype, opt):
     for dist in ("uniform", "quantized_normal", "cauchy", "mix2", "smallint"):
@@ -165,3 +169,20 @@ def test_stats_and_invariants(sel):
     assert np.all(np.diff(nz) <= 0)
     # bisection-like halving on smooth data (end of Section 4): far fewer passes than log2(n) + 8
     assert wp <= 24
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_histogram_finish_signed_zeros_and_denormals(sel, oracle_mod, dtype):
+    """Key-histogram narrowing around -0/+0 and subnormals, with one-key bins."""
+    tiny = np.finfo(dtype).smallest_subnormal
+    vals = np.array([-0.0, 0.0, tiny, -tiny, 2 * tiny, -2 * tiny, 1.0, -1.0, 1e-30, -1e-30],
+                    dtype=dtype)
+    rng = np.random.default_rng(9)
+    for trial in range(6):
+        x = rng.choice(vals, size=int(rng.integers(5000, 90_000))).astype(dtype)
+        for k in (1, 2, x.size // 3, x.size // 2, x.size - 1, x.size):
+            ref = oracle_mod.select_kth(x, k)
+            for hb in (1, 2, 12):
+                res = _run(sel, x, k, f"zeros trial {trial}", final_threshold=1,
+                           partition_fraction=1.0, hist_bits=hb)
+                assert_same_result(res, ref, (trial, k, hb))
