@@ -216,7 +216,8 @@ int cps_objective(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
  * blocks_per_cu:   resident workgroups per compute unit.
  * split_capacity:  elements of each of a workgroup's two split buffers; a bracket is split
  *                  (count-and-compact, end of Section 4) once it holds at most this many.
- * final_threshold, maxit, partition_fraction: as in cps_options. */
+ * final_threshold, maxit, partition_fraction, hist_bits: as in cps_options (the histogram
+ *                  passes count in the workgroup's LDS). */
 typedef struct cps_batch_options {
   int32_t block_threads;
   int32_t blocks_per_cu;
@@ -224,6 +225,8 @@ typedef struct cps_batch_options {
   int32_t final_threshold;
   int32_t maxit;
   double partition_fraction;
+  int32_t hist_bits;
+  int32_t reserved0;
 } cps_batch_options;
 
 void cps_default_batch_options(cps_batch_options *opt);

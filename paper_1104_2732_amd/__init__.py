@@ -65,7 +65,8 @@ class BatchOptions(ctypes.Structure):
     """Mirror of cps_batch_options (see include/cpselect.h)."""
     _fields_ = [("block_threads", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("split_capacity", ctypes.c_int64), ("final_threshold", ctypes.c_int32),
-                ("maxit", ctypes.c_int32), ("partition_fraction", ctypes.c_double)]
+                ("maxit", ctypes.c_int32), ("partition_fraction", ctypes.c_double),
+                ("hist_bits", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
 
 
 class TrainOptions(ctypes.Structure):

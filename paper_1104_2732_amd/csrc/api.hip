@@ -239,7 +239,8 @@ int resolve_batched(cps_handle *h, int dtype, const cps_batch_options *opt, Batc
   if (o.block_threads == 0) o.block_threads = 512;
   if (o.block_threads != 256 && o.block_threads != 512 && o.block_threads != 1024) return CPS_EINVAL;
   if (o.blocks_per_cu < 0 || o.split_capacity < 0 || o.final_threshold < 0 || o.maxit < 0 ||
-      !(o.partition_fraction >= 0.0) || o.partition_fraction > 1.0)
+      !(o.partition_fraction >= 0.0) || o.partition_fraction > 1.0 || o.hist_bits < 0 ||
+      (1 << o.hist_bits) > cps::kHistMaxBins)
     return CPS_EINVAL;
   const size_t es = dtype_size(dtype);
   const int per_cu = dtype == CPS_F32 ? cps::batched_max_blocks_per_cu<float>(o.block_threads)
@@ -263,6 +264,7 @@ int resolve_batched(cps_handle *h, int dtype, const cps_batch_options *opt, Batc
   r.cfg.theta = o.partition_fraction;
   r.cfg.zcap = ft;
   r.cfg.split_cap = r.cap;
+  r.cfg.hist_bits = o.hist_bits;
   return CPS_OK;
 }
 
@@ -309,6 +311,7 @@ void cps_default_batch_options(cps_batch_options *opt) {
   opt->final_threshold = 4096;
   opt->maxit = 64;
   opt->partition_fraction = 0.5;
+  opt->hist_bits = 12;
 }
 
 int select_kth_batched_ex(cps_handle *h, const void *const *ptrs_dev, const int64_t *sizes_dev,

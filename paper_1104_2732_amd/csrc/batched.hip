@@ -27,6 +27,10 @@ __device__ __noinline__ void bdev_after_gather(CpState &s, int64_t gathered) {
 __device__ __noinline__ void bdev_after_final(CpState &s, double v, int64_t below, int64_t eq) {
   cp_after_final(s, v, below, eq);
 }
+__device__ __noinline__ void bdev_after_hist(CpState &s, int32_t b, int64_t below, int64_t cnt,
+                                             const CpConfig &c) {
+  cp_after_hist(s, b, below, cnt, c);
+}
 
 template <typename T, int BLOCK> struct BShared {
   CpState st;
@@ -39,6 +43,7 @@ template <typename T, int BLOCK> struct BShared {
   int64_t cur[2];
   int64_t job;
   uint64_t order[kBatchSortMax];  // (size << 12 | index), sorted by size, largest first
+  uint32_t rh[kHistMaxBins];      // key histogram of a histogram pass
 };
 
 // Split (or gather) one tile's elements into this workgroup's buffer: the low side grows
@@ -162,6 +167,41 @@ __device__ void block_pass(const Span<T> &sp, T t, T yL, T yR, T fmin, T fmax,
   (void)lane;
 }
 
+// Histogram pass of this workgroup over span sp: elements whose ordered key lies in
+// [klo, khi] are counted in LDS bin (key - klo) >> shift.
+template <typename T, int BLOCK, int U>
+__device__ void block_hist(const Span<T> &sp, typename Traits<T>::Key klo,
+                           typename Traits<T>::Key khi, int shift, uint32_t *rh) {
+  constexpr int V = Traits<T>::kVec;
+  using Vec = typename Traits<T>::Vec;
+  using Key = typename Traits<T>::Key;
+  const int tid = threadIdx.x;
+  for (int64_t base = 0; base < sp.nvec; base += (int64_t)BLOCK * U) {
+    Vec raw[U];
+    bool valid[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t vi = base + (int64_t)u * BLOCK + tid;
+      valid[u] = vi < sp.nvec;
+      if (valid[u]) raw[u] = sp.V[vi];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      T e[V];
+      vec_to_arr<T>(raw[u], e);
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        const Key K = Traits<T>::key(e[j]);
+        if (valid[u] && K >= klo && K <= khi) atomicAdd(&rh[(uint32_t)((K - klo) >> shift)], 1u);
+      }
+    }
+  }
+  if (sp.nedge > 0 && tid < sp.nedge) {
+    const Key K = Traits<T>::key(sp.W[edge_index(sp, tid)]);
+    if (K >= klo && K <= khi) atomicAdd(&rh[(uint32_t)((K - klo) >> shift)], 1u);
+  }
+}
+
 template <typename T, int BLOCK, int U, bool CLASSIFY>
 __device__ void block_pass0(const Span<T> &sp, P0Acc<T> &acc) {
   constexpr int V = Traits<T>::kVec;
@@ -278,7 +318,7 @@ __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out,
     }
     break;
   }
-  while (sh.st.phase == PH_EVAL || sh.st.phase == PH_GATHER) {
+  while (sh.st.phase == PH_EVAL || sh.st.phase == PH_GATHER || sh.st.phase == PH_HIST) {
     const CpState &s = sh.st;
     const T t = (T)s.t, yL = (T)s.yL, yR = (T)s.yR, fmn = (T)s.fmin, fmx = (T)s.fmax;
     const T *W;
@@ -286,6 +326,43 @@ __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out,
     else if (s.wbuf == 2) W = (const T *)gb;
     else W = (const T *)zb[s.wbuf] + (s.side == 0 ? 0 : cap - s.wlen);
     const Span<T> sp = make_span(W, s.wbuf < 0 ? n : s.wlen);
+    if (s.phase == PH_HIST) {
+      // key histogram of the compacted bracket in LDS, then the bin holding rank k - cL
+      const HistGeom<uint64_t> g = hist_geometry(s.lo, s.hi, a.cfg.dtype, a.cfg.hist_bits);
+      for (int b = tid; b < g.nbins; b += BLOCK) sh.rh[b] = 0u;
+      if (tid == 0) sh.misc[0] = -1;
+      __syncthreads();
+      block_hist<T, BLOCK, U>(sp, (typename Traits<T>::Key)g.klo, (typename Traits<T>::Key)g.khi,
+                              g.shift, sh.rh);
+      __syncthreads();
+      constexpr int BPT = kHistMaxBins / BLOCK;
+      const uint64_t r = (uint64_t)(s.k - s.cL);
+      uint64_t hv[BPT];
+      uint64_t tot = 0;
+#pragma unroll
+      for (int j = 0; j < BPT; ++j) {
+        const int b = tid * BPT + j;
+        hv[j] = b < g.nbins ? sh.rh[b] : 0u;
+        tot += hv[j];
+      }
+      uint64_t cum = block_exclusive_scan<BLOCK>(tot, &sh.wbase[0][0]);
+#pragma unroll
+      for (int j = 0; j < BPT; ++j) {
+        if (cum < r && r <= cum + hv[j]) {
+          sh.misc[0] = tid * BPT + j;
+          sh.misc[1] = (int64_t)cum;
+          sh.misc[2] = (int64_t)hv[j];
+        }
+        cum += hv[j];
+      }
+      __syncthreads();
+      if (tid == 0) {
+        const int32_t bsel = (int32_t)sh.misc[0];
+        bdev_after_hist(sh.st, bsel, bsel < 0 ? 0 : sh.misc[1], bsel < 0 ? 0 : sh.misc[2], a.cfg);
+      }
+      __syncthreads();
+      continue;
+    }
     EvalAcc<T> acc;
     acc.A = acc.B = 0;
     acc.pred = -t_inf<T>();

@@ -63,6 +63,9 @@ def _check_all(res, arrays, ks, oracle_mod, ctx):
     dict(block_threads=1024, final_threshold=8, partition_fraction=0.0),
     dict(block_threads=512, maxit=0, final_threshold=32, split_capacity=128),
     dict(block_threads=256, blocks_per_cu=1),
+    dict(block_threads=512, hist_bits=0),
+    dict(block_threads=256, final_threshold=1, partition_fraction=1.0, hist_bits=2),
+    dict(block_threads=1024, final_threshold=16, partition_fraction=1.0, hist_bits=12),
 ])
 def test_batched_parity(sel, oracle_mod, dtype, opt):
     import paper_1104_2732_amd as cps
