@@ -8,7 +8,12 @@ i.e. 64 calls of select_kth on inputs already resident in HBM, enqueued
 back to back on one stream.  The metric is exact-selection elements/s
 (sum of n over the step's calls / step time); the JSON line also carries the
 HBM roofline of the selection kernel and the CPU oracle timed on a bounded
-sample of the same workload.
+sample of the same workload.  Three more legs compare the other forms with
+the plain single-array method on the same GPU (their own keys in the line):
+"batched" (4096 lognormal arrays of log-uniform sizes in one graph-captured
+launch vs a loop of single-array calls), "lms" (1024 least-median-of-squares
+candidates over 2^20 rows) and "learned" (the learned bracket proposal vs the
+plain method on held-out 2^26-element mixture arrays; training untimed).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 
@@ -102,6 +107,112 @@ def traffic_from(fetch_dir: str, write_dir: str) -> dict:
     return out
 
 
+def _time_ms(torch, fn, reps: int) -> float:
+    """Mean device time of fn() over reps calls, bracketed by events on the current stream."""
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def batched_leg(sel, cps, torch, reps: int = 5) -> dict:
+    """4096 lognormal float32 arrays, sizes log-uniform in [1e3, 1e6], median ranks: one
+    autotuned, graph-captured persistent launch against a loop of single-array calls."""
+    import workloads
+    arrays, sizes, ks = workloads.batched_arrays(4096, seed=0)
+    dev = [torch.from_numpy(a).cuda() for a in arrays]
+    del arrays
+    ptrs, szs, kk, code = sel.batch_descriptors(dev, ks)
+    out = sel.new_results(len(dev))
+    best, tuned_ms = sel.autotune_batched(ptrs, szs, kk, len(dev), code, out)
+    sel.reserve_batched(code)
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(g, stream=stream):
+            sel.select_kth_batched_async(ptrs, szs, kk, len(dev), code, out)
+    torch.cuda.current_stream().wait_stream(stream)
+    graph_ms = _time_ms(torch, g.replay, reps)
+    res_b = out.cpu().numpy().view(cps.RESULT_DTYPE).copy()
+    outs1 = sel.new_results(len(dev))
+    views = [outs1[i * 48:(i + 1) * 48] for i in range(len(dev))]
+    for d in dev:
+        sel.reserve(d.numel(), code)
+
+    def loop():
+        for d, k, o in zip(dev, ks, views):
+            sel.select_kth_async(d, int(k), o)
+    loop_ms = _time_ms(torch, loop, 2)
+    res_p = outs1.cpu().numpy().view(cps.RESULT_DTYPE)
+    same = bool(np.array_equal(res_b["value_bits"], res_p["value_bits"]) and
+                np.array_equal(res_b["less"], res_p["less"]) and
+                np.array_equal(res_b["equal"], res_p["equal"]) and np.all(res_b["status"] == 0))
+    total = int(np.sum(sizes))
+    del dev
+    return {"workload": "4096 lognormal(0,1) float32 arrays, sizes log-uniform in [1e3, 1e6], "
+                        "median ranks (one persistent launch, captured in a graph)",
+            "elements": total, "graph_ms": graph_ms, "elements_per_s": total / (graph_ms * 1e-3),
+            "tuned": {"block_threads": best.block_threads, "split_capacity": best.split_capacity},
+            "plain_loop_ms": loop_ms, "plain_loop_elements_per_s": total / (loop_ms * 1e-3),
+            "speedup_vs_plain": loop_ms / graph_ms, "results_identical": same}
+
+
+def lms_leg(sel, torch, reps: int = 5) -> dict:
+    """Least median of squares: 2^20 rows, p = 8, 1024 candidates, 30 % of rows shifted."""
+    import workloads
+    n, p, m = 1 << 20, 8, 1024
+    X, y, _, betas = workloads.lms_problem(n, p, m, seed=0)
+    Xd, yd, bd = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (X, y, betas))
+    out = sel.new_results(m)
+    ms = _time_ms(torch, lambda: sel.lms_median_sq_residuals_async(Xd, yd, bd, out), reps)
+    return {"workload": "n=2^20 rows, p=8, 1024 candidates (residuals fixed order, no FMA)",
+            "ms": ms, "residuals_per_s": n * m / (ms * 1e-3)}
+
+
+def learned_leg(sel, cps, torch, reps: int = 5) -> dict:
+    """The learned proposal on held-out float32 mixture arrays of n = 2^26 with uniform ranks,
+    against the plain method on the same arrays (training untimed)."""
+    P = sel.new_params()
+    t0 = time.time()
+    rep = sel.mlp_train(P, seed=1, n_arrays=100_000, array_size=1 << 18, epochs=8, batch=256,
+                        lr=2e-3, holdout=4096, holdout_seed=2)
+    train_s = time.time() - t0
+    n, count = 1 << 26, 8
+    x, ks = sel.mixture_generate(3, 0, count, n)
+    ks = [int(v) for v in ks.cpu().numpy()]
+    rows = [x[a] for a in range(count)]
+    sel.reserve(n, cps.CPS_F32)
+    out_p, out_l = sel.new_results(count), sel.new_results(count)
+    vp = [out_p[i * 48:(i + 1) * 48] for i in range(count)]
+    vl = [out_l[i * 48:(i + 1) * 48] for i in range(count)]
+    plain_ms = _time_ms(torch, lambda: [sel.select_kth_async(r, k, o) for r, k, o in
+                                        zip(rows, ks, vp)], reps) / count
+    learned_ms = _time_ms(torch, lambda: [sel.select_kth_learned_async(r, k, P, o) for r, k, o in
+                                          zip(rows, ks, vl)], reps) / count
+    rp = out_p.cpu().numpy().view(cps.RESULT_DTYPE)
+    rl = out_l.cpu().numpy().view(cps.RESULT_DTYPE)
+    same = bool(np.array_equal(rp["value_bits"], rl["value_bits"]) and
+                np.array_equal(rp["less"], rl["less"]) and np.array_equal(rp["equal"], rl["equal"]))
+    del x, rows
+    return {"workload": "8 held-out mixture arrays (1-4 Gaussian/lognormal/uniform components), "
+                        "float32, n=2^26, k uniform in [1, n]",
+            "plain_ms_per_call": plain_ms, "learned_ms_per_call": learned_ms,
+            "speedup_vs_plain": plain_ms / learned_ms,
+            "plain_passes_over_x": float(np.mean(rp["passes"])),
+            "learned_passes_over_x": float(np.mean(rl["passes"])),
+            "results_identical": same, "train_s": round(train_s, 2),
+            "train": {"arrays": 100_000, "array_size": 1 << 18, "epochs": 8,
+                      "first_loss": rep["first_loss"], "final_loss": rep["final_loss"],
+                      "holdout_coverage": rep["holdout_coverage"],
+                      "holdout_width": rep["holdout_width"]}}
+
+
 def cpu_baseline(budget_s: float = 20.0):
     """The CPU oracle on a bounded sample of the same workload, one thread, ~budget_s seconds:
     the 32 n=2^24 cases, then n=2^28 float32 cases while the budget lasts."""
@@ -135,6 +246,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched, least-median-of-squares and learned-proposal legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB elementwise copy first (counter calibration)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -268,6 +381,14 @@ def main():
         "detail": detail,
         "setup_s": round(gen_s, 1),
     }
+    if not args.no_extras:
+        del inputs
+        torch.cuda.empty_cache()
+        line["batched"] = batched_leg(sel, cps, torch)
+        torch.cuda.empty_cache()
+        line["lms"] = lms_leg(sel, torch)
+        torch.cuda.empty_cache()
+        line["learned"] = learned_leg(sel, cps, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
