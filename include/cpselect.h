@@ -377,6 +377,16 @@ int select_kth_learned(cps_handle *h, const void *x, int64_t n, int64_t k, int d
                        const float *params_dev, const cps_options *opt, cps_result *out_dev,
                        cps_stats *stats_dev, void *stream);
 
+/* select_kth with the non-learned baseline of the proposal: the fixed-stride sample of
+ * S = min(n, 4096) elements sorted on the device, and the bracket between its order
+ * statistics of 0-based ranks floor(c - z sd) - 1 and ceil(c + z sd), c = S k / n,
+ * sd = sqrt(S p (1 - p)) + 1 with p = k / n (an end beyond the sample is open).  Checked
+ * by counts like any proposal; results are identical to select_kth's.
+ * Errors: as select_kth, and CPS_EINVAL for z < 0. */
+int select_kth_sampled(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype, double z,
+                       const cps_options *opt, cps_result *out_dev, cps_stats *stats_dev,
+                       void *stream);
+
 /* Training driver: draws n_arrays arrays of array_size elements (cps_mixture_generate,
  * seed, ids 0..n_arrays-1), labels them exactly with select_kth_batched, and runs `epochs`
  * passes of Adam over them in minibatches of `batch`; then measures the trained proposal

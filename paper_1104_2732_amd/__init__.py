@@ -105,7 +105,7 @@ EXPORTS = ("cps_create", "cps_destroy", "cps_status_string", "cps_last_hip_error
            "cps_reserve_batched", "cps_autotune_batched", "lms_median_sq_residuals",
            "cps_mixture_generate", "cps_features", "cps_mlp_forward", "cps_mlp_loss_grad",
            "cps_mlp_adam", "cps_mlp_init", "cps_learned_bracket", "select_kth_learned",
-           "cps_mlp_train")
+           "cps_mlp_train", "select_kth_sampled")
 STATUS_BADARG = 4
 
 
@@ -162,9 +162,11 @@ def lib() -> ctypes.CDLL:
                                      vp, vp]
     L.cps_mlp_train.argtypes = [vp, ctypes.POINTER(TrainOptions), vp, ctypes.POINTER(TrainReport),
                                 vp]
+    L.select_kth_sampled.argtypes = [vp, vp, i64, i64, c_int, ctypes.c_double,
+                                     ctypes.POINTER(Options), vp, vp, vp]
     for name in ("cps_mixture_generate", "cps_features", "cps_mlp_forward", "cps_mlp_loss_grad",
                  "cps_mlp_adam", "cps_mlp_init", "cps_learned_bracket", "select_kth_learned",
-                 "cps_mlp_train"):
+                 "cps_mlp_train", "select_kth_sampled"):
         getattr(L, name).restype = c_int
     _lib = L
     return L
@@ -471,6 +473,29 @@ class Selector:
         out = self.new_results(1)
         st = self.new_stats() if stats else None
         self.select_kth_learned_async(x, k, params, out, st, options)
+        torch.cuda.synchronize(self.device)
+        r = _as_records(out, RESULT_DTYPE)[0]
+        res = {name: r[name].item() for name in RESULT_DTYPE.names}
+        if stats:
+            return res, _as_records(st, STATS_DTYPE)[0]
+        return res
+
+    def select_kth_sampled_async(self, x, k: int, out, z: float = 4.0, stats=None,
+                                 options: Options | None = None) -> None:
+        rc = lib().select_kth_sampled(self._h, self._ptr(x), x.numel(), int(k), _dtype_code(x),
+                                      float(z),
+                                      ctypes.byref(options) if options is not None else None,
+                                      self._ptr(out),
+                                      self._ptr(stats) if stats is not None else None,
+                                      ctypes.c_void_p(_stream_ptr(self.device)))
+        _check(rc, "select_kth_sampled")
+
+    def select_kth_sampled(self, x, k: int, z: float = 4.0, options: Options | None = None,
+                           stats: bool = False):
+        import torch
+        out = self.new_results(1)
+        st = self.new_stats() if stats else None
+        self.select_kth_sampled_async(x, k, out, z, st, options)
         torch.cuda.synchronize(self.device)
         r = _as_records(out, RESULT_DTYPE)[0]
         res = {name: r[name].item() for name in RESULT_DTYPE.names}

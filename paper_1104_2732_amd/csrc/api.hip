@@ -661,6 +661,25 @@ int select_kth_learned(cps_handle *h, const void *x, int64_t n, int64_t k, int d
   return run_select<double>(h, (const double *)x, n, k, opt, out_dev, stats_dev, s, h->bracket);
 }
 
+int select_kth_sampled(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype, double z,
+                       const cps_options *opt, cps_result *out_dev, cps_stats *stats_dev,
+                       void *stream) {
+  int rc = check_common(h, x, n, k, dtype);
+  if (rc) return rc;
+  if (!out_dev || !(z >= 0.0) || z > 1e6) return CPS_EINVAL;
+  std::lock_guard<std::mutex> lk(h->mu);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (dtype == CPS_F32)
+    e = cps::launch_sample_bracket<float>((const float *)x, n, k, z, h->bracket, s);
+  else
+    e = cps::launch_sample_bracket<double>((const double *)x, n, k, z, h->bracket, s);
+  if (e != hipSuccess) return hip_fail(e);
+  if (dtype == CPS_F32)
+    return run_select<float>(h, (const float *)x, n, k, opt, out_dev, stats_dev, s, h->bracket);
+  return run_select<double>(h, (const double *)x, n, k, opt, out_dev, stats_dev, s, h->bracket);
+}
+
 }  // extern "C"
 
 namespace {

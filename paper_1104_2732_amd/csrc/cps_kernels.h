@@ -120,6 +120,9 @@ hipError_t launch_mlp_init(uint64_t seed, float *P, hipStream_t stream);
 template <typename T>
 hipError_t launch_learned_bracket(const T *x, int64_t n, int64_t k, const float *P,
                                   double *bracket, hipStream_t stream);
+template <typename T>
+hipError_t launch_sample_bracket(const T *x, int64_t n, int64_t k, double z, double *bracket,
+                                 hipStream_t stream);
 hipError_t launch_batch_descriptors(const float *base, int64_t n, int64_t count, const float **ptrs,
                                     int64_t *sizes, hipStream_t stream);
 hipError_t launch_labels(const cps_result *res, const double *range, const int32_t *valid,

@@ -632,6 +632,78 @@ hipError_t launch_learned_bracket(const T *x, int64_t n, int64_t k, const float 
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ sample-quantile proposal
+// The non-learned baseline of the proposal: the same fixed-stride sample, sorted in LDS,
+// and the bracket between its order statistics z standard deviations of the sample rank
+// (binomial, sqrt(S p (1 - p)) + 1) below and above the expected rank S k / n.
+
+constexpr int kSortBlock = 1024;
+
+template <typename T>
+__global__ __launch_bounds__(kSortBlock) void sample_bracket_kernel(const T *x, int64_t n,
+                                                                   int64_t k, double z,
+                                                                   double *bracket) {
+  __shared__ double sv[kSample];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  const int64_t S = n < kSample ? n : kSample;
+  const int64_t stride = n / S;
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int i = tid; i < kSample; i += kSortBlock) {
+    double v = __builtin_inf();
+    if (i < S) {
+      v = (double)x[i * stride];
+      if (!__builtin_isfinite(v)) bad = 1;
+    }
+    sv[i] = v;
+  }
+  __syncthreads();
+  if (bad) {
+    if (tid == 0) bracket[0] = bracket[1] = bracket[2] = 0.0;
+    return;
+  }
+  // bitonic sort, ascending
+  for (int kk = 2; kk <= kSample; kk <<= 1) {
+    for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+      for (int i = tid; i < kSample; i += kSortBlock) {
+        const int p = i ^ jj;
+        if (p > i) {
+          const double a = sv[i], b = sv[p];
+          const bool up = (i & kk) == 0;
+          if (up ? a > b : a < b) {
+            sv[i] = b;
+            sv[p] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) {
+    const double pr = (double)k / (double)n;
+    const double c = pr * (double)S;
+    const double sd = sqrt((double)S * pr * (1.0 - pr)) + 1.0;
+    const int64_t lo_r = (int64_t)floor(c - z * sd) - 1;
+    const int64_t hi_r = (int64_t)ceil(c + z * sd);
+    bracket[0] = lo_r >= 0 ? sv[lo_r] : -__builtin_inf();
+    bracket[1] = hi_r <= S - 1 ? sv[hi_r] : __builtin_inf();
+    bracket[2] = 1.0;
+  }
+}
+
+template <typename T>
+hipError_t launch_sample_bracket(const T *x, int64_t n, int64_t k, double z, double *bracket,
+                                 hipStream_t stream) {
+  sample_bracket_kernel<T><<<dim3(1), dim3(kSortBlock), 0, stream>>>(x, n, k, z, bracket);
+  return hipGetLastError();
+}
+
+template hipError_t launch_sample_bracket<float>(const float *, int64_t, int64_t, double, double *,
+                                                 hipStream_t);
+template hipError_t launch_sample_bracket<double>(const double *, int64_t, int64_t, double,
+                                                  double *, hipStream_t);
+
 // ------------------------------------------------------------------ training helpers
 
 __global__ void batch_descriptor_kernel(const float *base, int64_t n, int64_t count,

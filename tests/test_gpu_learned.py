@@ -279,3 +279,23 @@ def test_training_reduces_passes(sel, oracle_mod):
         learned_passes.append(r_learn["passes"])
     print("passes plain", plain_passes, "learned", learned_passes, flush=True)
     assert np.mean(learned_passes) < np.mean(plain_passes)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_sampled_proposal_parity(sel, oracle_mod, dtype):
+    """The sample-quantile baseline: identical results for any width, fewer full reads."""
+    rng = np.random.default_rng(13)
+    for n in (1, 3, 4095, 4096, 100_001, 1 << 21):
+        for dist in ("normal", "quantized_normal", "cauchy"):
+            x = workloads.single_array(dist, n, dtype, seed=n, tag="gpu-sampled")
+            for k in sorted({1, n, (n + 1) // 2, int(rng.integers(1, n + 1))}):
+                ref = oracle_mod.select_kth(x, k)
+                for z in (0.0, 1.0, 4.0, 1e3):
+                    print(f"case sampled {dist} n={n} k={k} z={z}", flush=True)
+                    res = sel.select_kth_sampled(_dev(x), k, z=z)
+                    assert_same_result(res, ref, (dist, n, k, z))
+    x = workloads.single_array("normal", 1 << 22, dtype, seed=5, tag="gpu-sampled")
+    k = (x.size + 1) // 2
+    r_plain = sel.select_kth(_dev(x), k)
+    r_s = sel.select_kth_sampled(_dev(x), k, z=4.0)
+    assert r_s["passes"] < r_plain["passes"]
