@@ -290,7 +290,7 @@ __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out,
     double dv[8] = {acc.sum, 0, 0, 0, 0, 0, 0, 0};
     int64_t iv[8] = {(int64_t)acc.nnan, (int64_t)acc.nneg, (int64_t)acc.npos, 0, 0, 0, 0, 0};
     int dop[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    block_reduce<BLOCK, 1, 3>(dv, dop, iv, true, sh.d, sh.i);
+    block_reduce<BLOCK, 1, 3>(dv, dop, iv, false, sh.d, sh.i);
     if (tid == 0) {
       Pass0Result r = {};
       r.classified = slow ? 1 : 0;
@@ -386,7 +386,7 @@ __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out,
     double dv[8] = {acc.A, acc.B, (double)acc.pred, (double)acc.succ, 0, 0, 0, 0};
     int dop[8] = {0, 0, 2, 1, 0, 0, 0, 0};
     int64_t iv[8] = {(int64_t)acc.L, (int64_t)acc.G, 0, 0, 0, 0, 0, 0};
-    block_reduce<BLOCK, 4, 2>(dv, dop, iv, true, sh.d, sh.i);
+    block_reduce<BLOCK, 4, 2>(dv, dop, iv, false, sh.d, sh.i);
     if (tid == 0) {
       CpState &w = sh.st;
       if (gather) {

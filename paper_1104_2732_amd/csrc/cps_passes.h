@@ -15,10 +15,12 @@ template <> __device__ inline double t_inf<double>() { return __builtin_inf(); }
 template <typename T> __device__ inline T tmin(T a, T b) { return a < b ? a : b; }
 template <typename T> __device__ inline T tmax(T a, T b) { return a > b ? a : b; }
 
+// The counters are per lane (one VALU add-with-carry per element, no scalar work in the
+// streaming loop); the workgroup reduction sums them.
 template <typename T> struct EvalAcc {
   double A, B;
   T pred, succ;
-  uint64_t L, G;  // wave-uniform
+  uint32_t L, G;
 };
 
 // Evaluate one element at t.  Invalid lanes contribute nothing.
@@ -33,16 +35,16 @@ __device__ inline void eval_one(T &v, bool valid, T t, T fmin, T fmax, T &a_part
   b_part -= l ? d : T(0);
   acc.pred = tmax(acc.pred, l ? v : -t_inf<T>());
   acc.succ = tmin(acc.succ, g ? v : t_inf<T>());
-  acc.L += popc(ballot(l));
-  acc.G += popc(ballot(g));
+  acc.L += l ? 1u : 0u;
+  acc.G += g ? 1u : 0u;
 }
 
 template <typename T> struct P0Acc {
   double sum;
   T mn, mx;
   uint32_t cmn, cmx;
-  uint64_t nnan, nneg, npos;  // wave-uniform
-  uint64_t cle_a, clt_b;      // wave-uniform
+  uint32_t nnan, nneg, npos;  // per lane
+  uint32_t cle_a, clt_b;      // per lane
   double Aa, Ba, Ab, Bb;
 };
 
@@ -53,13 +55,13 @@ template <typename T, bool CLASSIFY, bool BRACKET>
 __device__ inline void pass0_one(T v, bool valid, T ba, T bb, T &s_part, T &aa, T &bA, T &ab,
                                  T &bB, P0Acc<T> &acc) {
   const bool isnan_ = valid && (v != v);
-  acc.nnan += popc(ballot(isnan_));
+  acc.nnan += isnan_ ? 1u : 0u;
   bool fin = valid;
   if (CLASSIFY) {
     const bool ni = valid && (v == -t_inf<T>());
     const bool pi = valid && (v == t_inf<T>());
-    acc.nneg += popc(ballot(ni));
-    acc.npos += popc(ballot(pi));
+    acc.nneg += ni ? 1u : 0u;
+    acc.npos += pi ? 1u : 0u;
     fin = valid && !isnan_ && !ni && !pi;
   }
   const bool lt = fin && v < acc.mn, eqn = fin && v == acc.mn;
@@ -70,8 +72,8 @@ __device__ inline void pass0_one(T v, bool valid, T ba, T bb, T &s_part, T &aa, 
   acc.mx = gt ? v : acc.mx;
   s_part += fin ? v : T(0);
   if (BRACKET) {
-    acc.cle_a += popc(ballot(valid && v <= ba));
-    acc.clt_b += popc(ballot(valid && v < bb));
+    acc.cle_a += (valid && v <= ba) ? 1u : 0u;
+    acc.clt_b += (valid && v < bb) ? 1u : 0u;
     aa += (fin && v > ba) ? v - ba : T(0);
     bA += (fin && v < ba) ? ba - v : T(0);
     ab += (fin && v > bb) ? v - bb : T(0);

@@ -431,7 +431,7 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
     iv[3] = (int64_t)acc.cle_a; iv[4] = (int64_t)acc.clt_b;
     iv[5] = (p0s && lane == 0 && o.lo > cap) ? 1 : 0;  // overflowing wavefronts
     iv[6] = iv[7] = 0;
-    block_reduce<BLOCK, 5, 6>(dv, dop, iv, true, sh.d, sh.i);
+    block_reduce<BLOCK, 5, 6>(dv, dop, iv, false, sh.d, sh.i);
     if (tid == 0) {
       dv[5] = mn; dv[6] = mx; iv[6] = cmn; iv[7] = cmx;
     }
@@ -520,7 +520,7 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
   iv[0] = (int64_t)acc.L; iv[1] = (int64_t)acc.G;
   iv[2] = lane == 0 ? written : 0;  // per wavefront, counted once
   iv[3] = iv[4] = iv[5] = iv[6] = iv[7] = 0;
-  block_reduce<BLOCK, 4, 3>(dv, dop, iv, true, sh.d, sh.i);
+  block_reduce<BLOCK, 4, 3>(dv, dop, iv, false, sh.d, sh.i);
 }
 
 // The last workgroup to arrive: reduce every workgroup's partial in a fixed order, advance
