@@ -158,7 +158,8 @@ def batched_leg(sel, cps, torch, reps: int = 5) -> dict:
     return {"workload": "4096 lognormal(0,1) float32 arrays, sizes log-uniform in [1e3, 1e6], "
                         "median ranks (one persistent launch, captured in a graph)",
             "elements": total, "graph_ms": graph_ms, "elements_per_s": total / (graph_ms * 1e-3),
-            "tuned": {"block_threads": best.block_threads, "split_capacity": best.split_capacity},
+            "tuned": {"block_threads": best.block_threads, "split_capacity": best.split_capacity,
+                      "partition_fraction": best.partition_fraction},
             "plain_loop_ms": loop_ms, "plain_loop_elements_per_s": total / (loop_ms * 1e-3),
             "speedup_vs_plain": loop_ms / graph_ms, "results_identical": same}
 
