@@ -254,8 +254,9 @@ int select_kth_batched_ex(cps_handle *h, const void *const *ptrs_dev, const int6
 /* Allocate the batched workspace for `opt` (NULL: the current choice) ahead of stream capture. */
 int cps_reserve_batched(cps_handle *h, int dtype, const cps_batch_options *opt);
 
-/* Autotuner: time each candidate launch shape and split capacity on this very batch (the
- * call synchronises `stream`), keep the fastest as the handle's choice for `dtype`, and
+/* Autotuner: time each candidate launch shape, split capacity and split fraction on this
+ * very batch (the call synchronises `stream`), keep the fastest as the handle's choice for
+ * `dtype`, and
  * return it in best (may be NULL) with its time in *best_ms (may be NULL).  The results in
  * out_dev are those of the last timed candidate. */
 int cps_autotune_batched(cps_handle *h, const void *const *ptrs_dev, const int64_t *sizes_dev,
