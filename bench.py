@@ -43,6 +43,7 @@ SIZES = (24, 28)
 DTYPES = (np.float32, np.float64)
 DISTS = ("uniform", "normal", "cauchy", "quantized_normal")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cp_select_kernel_traffic.json")
+EPOCHS = 30  # training epochs of the learned proposal (untimed setup)
 
 
 def kernel_source_hash() -> str:
@@ -181,8 +182,8 @@ def learned_leg(sel, cps, torch, reps: int = 5) -> dict:
     against the plain method on the same arrays (training untimed)."""
     P = sel.new_params()
     t0 = time.time()
-    rep = sel.mlp_train(P, seed=1, n_arrays=100_000, array_size=1 << 18, epochs=8, batch=256,
-                        lr=2e-3, holdout=4096, holdout_seed=2)
+    rep = sel.mlp_train(P, seed=1, n_arrays=100_000, array_size=1 << 18, epochs=EPOCHS,
+                        batch=256, lr=2e-3, holdout=4096, holdout_seed=2)
     train_s = time.time() - t0
     n, count = 1 << 26, 8
     x, ks = sel.mixture_generate(3, 0, count, n)
@@ -196,10 +197,15 @@ def learned_leg(sel, cps, torch, reps: int = 5) -> dict:
                                         zip(rows, ks, vp)], reps) / count
     learned_ms = _time_ms(torch, lambda: [sel.select_kth_learned_async(r, k, P, o) for r, k, o in
                                           zip(rows, ks, vl)], reps) / count
+    out_s = sel.new_results(count)
+    vs = [out_s[i * 48:(i + 1) * 48] for i in range(count)]
+    sampled_ms = _time_ms(torch, lambda: [sel.select_kth_sampled_async(r, k, o, 4.0) for r, k, o in
+                                          zip(rows, ks, vs)], reps) / count
     rp = out_p.cpu().numpy().view(cps.RESULT_DTYPE)
     rl = out_l.cpu().numpy().view(cps.RESULT_DTYPE)
-    same = bool(np.array_equal(rp["value_bits"], rl["value_bits"]) and
-                np.array_equal(rp["less"], rl["less"]) and np.array_equal(rp["equal"], rl["equal"]))
+    rs = out_s.cpu().numpy().view(cps.RESULT_DTYPE)
+    same = all(bool(np.array_equal(rp[f], r[f])) for r in (rl, rs)
+               for f in ("value_bits", "less", "equal"))
     del x, rows
     return {"workload": "8 held-out mixture arrays (1-4 Gaussian/lognormal/uniform components), "
                         "float32, n=2^26, k uniform in [1, n]",
@@ -207,8 +213,11 @@ def learned_leg(sel, cps, torch, reps: int = 5) -> dict:
             "speedup_vs_plain": plain_ms / learned_ms,
             "plain_passes_over_x": float(np.mean(rp["passes"])),
             "learned_passes_over_x": float(np.mean(rl["passes"])),
+            "sampled_ms_per_call": sampled_ms,
+            "sampled_passes_over_x": float(np.mean(rs["passes"])),
+            "sampled_note": "non-learned baseline: sorted stride sample, +-4 sd of the sample rank",
             "results_identical": same, "train_s": round(train_s, 2),
-            "train": {"arrays": 100_000, "array_size": 1 << 18, "epochs": 8,
+            "train": {"arrays": 100_000, "array_size": 1 << 18, "epochs": EPOCHS,
                       "first_loss": rep["first_loss"], "final_loss": rep["final_loss"],
                       "holdout_coverage": rep["holdout_coverage"],
                       "holdout_width": rep["holdout_width"]}}

@@ -101,6 +101,7 @@ typedef struct cps_eval {
  *                   buffer, and later passes read only the side that still holds x_(k)
  *                   (the count-and-compact of Section 4, applied at every later pass).
  *                   0 disables splitting (plain passes over x, then one compaction).
+ *                   Default 0.75.
  * grid_blocks, block_threads: launch shape; 0 picks the tuned default.
  * spin_limit:       bound on device-side waiting loops (iterations); 0 = default.
  * bracket_lo/hi, use_bracket: a caller-supplied starting bracket (tests; the proposal
@@ -108,7 +109,7 @@ typedef struct cps_eval {
  *                   where the counts prove it (#(x <= lo) < k, k <= #(x < hi)); the result
  *                   never depends on it.
  * compact_proposal: with a proposed bracket, pass 0 also writes the elements strictly
- *                   inside it to the split workspace (at most 1/8 of each wavefront's
+ *                   inside it to the split workspace (at most half of each wavefront's
  *                   share); when both ends hold and everything fit, later passes read only
  *                   those elements and the input is read once.  1 (default) or 0.
  * hist_bits:        once the bracket's elements are compacted, finish with exact passes
@@ -288,8 +289,9 @@ int lms_median_sq_residuals(cps_handle *h, const double *X_dev, const double *y_
  *
  * Features of an array (n elements, rank k): the fixed-stride sample
  * x[i * floor(n / S)], i < S = min(n, 4096); its minimum lo and maximum hi (a zero extreme
- * as +0); the fractions of the sample in 64 equal bins over [lo, hi], bin = min(63,
- * floor(64 (v - lo) / (hi - lo))) in double precision (all in bin 0 when hi == lo);
+ * as +0); its histogram in 64 equal bins over [lo, hi], bin = min(63,
+ * floor(64 (v - lo) / (hi - lo))) in double precision (all in bin 0 when hi == lo), as
+ * cumulative fractions (feature b: the fraction of the sample in bins 0..b);
  * lo / (1 + |lo|), hi / (1 + |hi|) and k / n.  Each of the 67 features is formed in double
  * precision and rounded once to float.  A sample holding NaN or an infinity gives no
  * proposal.

@@ -5,9 +5,10 @@ library).  It computes, plainly and in float64, what the device kernels of the
 learned proposal compute in float32:
 
 - ``sample_features``: a fixed-stride sample of S = min(n, 4096) elements,
-  x[i * floor(n / S)] for i < S; its minimum lo and maximum hi; the fractions
-  of the sample in 64 equal bins over [lo, hi], bin = min(63, floor(64 (v - lo)
-  / (hi - lo))) in double precision (bin 0 when hi == lo); plus lo / (1 + |lo|),
+  x[i * floor(n / S)] for i < S; its minimum lo and maximum hi; its histogram
+  in 64 equal bins over [lo, hi], bin = min(63, floor(64 (v - lo) / (hi - lo)))
+  in double precision (bin 0 when hi == lo), given as cumulative fractions
+  (the fraction of the sample in bins 0..b, for b = 0..63); plus lo / (1 + |lo|),
   hi / (1 + |hi|) and k / n.  Each of the 67 features is formed in double
   precision and rounded once to float32, so the device's features agree bit
   for bit (lo and hi are taken as values: a zero extreme is +0).  A sample
@@ -86,8 +87,10 @@ def sample_features(x: np.ndarray, k: int):
             b = 0
         counts[b] += 1
     f = np.empty(N_IN, dtype=np.float32)
+    cum = 0
     for b in range(BINS):
-        f[b] = np.float32(counts[b] / s)
+        cum += counts[b]
+        f[b] = np.float32(cum / s)
     f[BINS] = np.float32(lo / (1.0 + abs(lo)))
     f[BINS + 1] = np.float32(hi / (1.0 + abs(hi)))
     f[BINS + 2] = np.float32(k / n)

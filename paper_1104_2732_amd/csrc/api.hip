@@ -204,9 +204,11 @@ int run_select(cps_handle *h, const T *x, int64_t n, int64_t k, const cps_option
   a.cfg = r.cfg;
   a.spin_limit = r.spin_limit;
   a.bracket = bracket_dev;
-  // a proposed bracket's interior may take up to 1/8 of each wavefront's region in pass 0
+  // a proposed bracket's interior may take up to half of each wavefront's region in pass 0
+  // (past about two thirds of the input, the passes over x that compaction would spare
+  // cost less than reading the compacted elements again)
   const bool proposal = bracket_dev != nullptr || r.cfg.use_bracket != 0;
-  a.p0_cap = (proposal && r.compact_proposal) ? L.seg_R / 8 : 0;
+  a.p0_cap = (proposal && r.compact_proposal) ? L.seg_R / 2 : 0;
   a.ghist = (uint64_t *)(base + L.gh);
   hipError_t e = cps::launch_select<T>(a, r.grid, stream);
   if (e != hipSuccess) return hip_fail(e);
@@ -430,7 +432,7 @@ void cps_default_options(cps_options *opt) {
   std::memset(opt, 0, sizeof(*opt));
   opt->maxit = 64;
   opt->final_threshold = 8192;
-  opt->partition_fraction = 0.5;
+  opt->partition_fraction = 0.75;
   opt->grid_blocks = 0;
   opt->block_threads = 0;
   opt->spin_limit = 0;

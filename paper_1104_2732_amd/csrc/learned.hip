@@ -260,10 +260,17 @@ __device__ void array_features(const T *x, int64_t n, int64_t k, FeatShared &fs,
   if (tid < kIn) {
     float fv = 0.0f;
     if (valid) {
-      if (tid < kBins) fv = (float)((double)fs.hist[tid] / (double)S);
-      else if (tid == kBins) fv = (float)(lo / (1.0 + fabs(lo)));
-      else if (tid == kBins + 1) fv = (float)(hi / (1.0 + fabs(hi)));
-      else fv = (float)((double)k / (double)n);
+      if (tid < kBins) {
+        uint32_t cum = 0;  // the fraction of the sample in bins 0..tid
+        for (int b = 0; b <= tid; ++b) cum += fs.hist[b];
+        fv = (float)((double)cum / (double)S);
+      } else if (tid == kBins) {
+        fv = (float)(lo / (1.0 + fabs(lo)));
+      } else if (tid == kBins + 1) {
+        fv = (float)(hi / (1.0 + fabs(hi)));
+      } else {
+        fv = (float)((double)k / (double)n);
+      }
     }
     f[tid] = fv;
   }

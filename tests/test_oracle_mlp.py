@@ -108,7 +108,7 @@ def test_histogram_against_numpy_histogram():
     samp = x[np.arange(4096) * stride].astype(np.float64)
     assert (lo, hi) == (samp.min(), samp.max()) == (0.0, 4095.0)
     ref, _ = np.histogram(samp, bins=64, range=(0.0, 4095.0))
-    assert np.array_equal(f[:64], (ref / 4096).astype(np.float32))
+    assert np.array_equal(f[:64], (np.cumsum(ref) / 4096).astype(np.float32))
     assert f[64] == np.float32(0.0) and f[65] == np.float32(4095.0 / 4096.0)
     assert f[66] == np.float32(17 / n)
 
@@ -116,17 +116,17 @@ def test_histogram_against_numpy_histogram():
 def test_features_degenerate_and_small():
     x = np.full(1000, 2.5, dtype=np.float64)
     f, lo, hi = mlp.sample_features(x, 1000)
-    assert lo == hi == 2.5 and f[0] == 1.0 and np.all(f[1:64] == 0.0)
+    assert lo == hi == 2.5 and np.all(f[:64] == 1.0)
     assert f[64] == f[65] == np.float32(2.5 / 3.5) and f[66] == 1.0
     # n < 4096: the whole array is the sample; brute-force bins by the definition's formula
     x = np.random.default_rng(1).standard_normal(777).astype(np.float32)
     f, lo, hi = mlp.sample_features(x, 5)
     v = x.astype(np.float64)
     bins = np.minimum(63, np.floor(64.0 * (v - lo) / (hi - lo))).astype(int)
-    assert np.array_equal(f[:64], (np.bincount(bins, minlength=64) / 777).astype(np.float32))
-    assert abs(float(f[:64].astype(np.float64).sum()) - 1.0) < 1e-6
-    # the largest sample value lands in the last bin, the smallest in the first
-    assert f[63] > 0 and f[0] > 0
+    want = np.cumsum(np.bincount(bins, minlength=64)) / 777
+    assert np.array_equal(f[:64], want.astype(np.float32))
+    # the smallest sample value lands in the first bin, every value in some bin
+    assert f[0] > 0 and f[63] == 1.0 and np.all(np.diff(f[:64]) >= 0)
 
 
 def test_signed_zero_extremes_are_values():
