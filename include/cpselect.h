@@ -298,11 +298,14 @@ int lms_median_sq_residuals(cps_handle *h, const double *X_dev, const double *y_
  *
  * Network: 67 -> 64 (ReLU) -> 64 (ReLU) -> 2 in float, outputs (u, s).  Parameters are one
  * float array of CPS_MLP_PARAMS values: W1 (64 x 67, row-major, row = hidden unit), b1 (64),
- * W2 (64 x 64), b2 (64), W3 (2 x 64), b3 (2).  Proposed bracket: y0 -+ w with
- * y0 = lo + (hi - lo) u, w = (hi - lo) exp(clamp(s, -20, 4)), formed in double precision.
+ * W2 (64 x 64), b2 (64), W3 (2 x 64), b3 (2).  The histogram position h is where the
+ * cumulative features F cross the k/n feature p: (b + (p - F_{b-1}) / (F_b - F_{b-1})) / 64,
+ * b the first bin with F_b >= p (F_{-1} = 0), in double precision.  Proposed bracket:
+ * y0 -+ w with y0 = lo + (hi - lo)(h + u), w = (hi - lo) exp(clamp(s, -20, 4)), formed in
+ * double precision.
  *
- * Training loss of one example with label u* = (x_(k) - lo) / (hi - lo) (0 when hi == lo),
- * d = u - u*, omega = exp(clamp(s, -20, 4)):
+ * Training loss of one example with label u* = (x_(k) - lo) / (hi - lo) - h (0 when
+ * hi == lo), d = u - u*, omega = exp(clamp(s, -20, 4)):
  *     100 d^2 + max(0, |d| - omega) + 0.02 omega,
  * averaged over the batch.  ReLU'(0) = 0, sign(0) = 0, and the clamp passes gradient only
  * strictly inside (-20, 4). */
@@ -365,7 +368,7 @@ int cps_mlp_adam(cps_handle *h, float *params_dev, const float *grad_dev, float 
 
 /* Initial parameters: weights uniform in +-sqrt(6 / fan_in) from Philox4x32-10 (key
  * seed, counter (index, 0, 0, 0xC0FFEE), first word's top 24 bits), W3 scaled by 0.01,
- * b1 = b2 = 0 and b3 = (0.5, ln 0.05). */
+ * b1 = b2 = 0 and b3 = (0, ln 0.05): the histogram position with a 5 % half-width. */
 int cps_mlp_init(cps_handle *h, uint64_t seed, float *params_dev, void *stream);
 
 /* The proposed bracket for one array: bracket_dev receives three doubles (a, b, use), use

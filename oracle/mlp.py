@@ -19,9 +19,13 @@ learned proposal compute in float32:
   loss is C_SQ d^2 + C_COV max(0, |d| - omega) + C_W omega; the batch loss is
   the mean.  ReLU'(0) = 0, sign(0) = 0, and the clamp passes gradient only
   strictly inside (-20, 4).
-- ``bracket``: the proposed bracket y0 -+ w with y0 = lo + (hi - lo) u and
-  w = (hi - lo) omega.
-- ``target``: the label u* = (x_(k) - lo) / (hi - lo) (0 when hi == lo).
+- ``hist_position``: the histogram's own estimate of the rank's position,
+  (b + (p - F_{b-1}) / (F_b - F_{b-1})) / 64 with F the cumulative features,
+  p the k/n feature and b the first bin with F_b >= p (F_{-1} = 0), in double
+  precision from the float features; the network predicts the offset from it.
+- ``bracket``: the proposed bracket y0 -+ w with y0 = lo + (hi - lo)(h + u),
+  h the histogram position, and w = (hi - lo) omega.
+- ``target``: the label u* = (x_(k) - lo) / (hi - lo) - h (0 when hi == lo).
 - ``adam_step``: one Adam update (Kingma and Ba, 2015) with bias correction.
 
 The method's exactness never rests on the network: the proposed ends are
@@ -154,20 +158,36 @@ def loss_and_grad(theta: np.ndarray, F: np.ndarray, ustar: np.ndarray):
     return L, grad
 
 
-def bracket(o: np.ndarray, lo: float, hi: float):
-    """The proposed bracket (a, b) for one example's outputs o = (o_0, o_1)."""
+def hist_position(f: np.ndarray) -> float:
+    """Where the cumulative histogram features cross the k/n feature, as a fraction of the
+    sample range (linear inside the crossing bin)."""
+    F = [float(v) for v in np.asarray(f, dtype=np.float32)[:BINS]]
+    p = float(np.float32(f[BINS + 2]))
+    b = 0
+    while b < BINS - 1 and F[b] < p:
+        b += 1
+    prev = F[b - 1] if b > 0 else 0.0
+    if not F[b] > prev:
+        return (b + 0.5) / BINS
+    return (b + (p - prev) / (F[b] - prev)) / BINS
+
+
+def bracket(o: np.ndarray, lo: float, hi: float, h: float):
+    """The proposed bracket (a, b) for one example's outputs o = (o_0, o_1) and histogram
+    position h."""
     span = hi - lo
-    y0 = lo + span * float(o[0])
+    y0 = lo + span * (h + float(o[0]))
     w = span * math.exp(float(_clamp_logw(np.float64(o[1]))))
     return y0 - w, y0 + w
 
 
-def target(value: float, lo: float, hi: float) -> float:
-    """The label u* of an array whose k-th element is `value`, on the sample range [lo, hi]
-    (0 when the sample is constant: the bracket then has zero width whatever u is)."""
+def target(value: float, lo: float, hi: float, h: float) -> float:
+    """The label of an array whose k-th element is `value`, on the sample range [lo, hi],
+    relative to the histogram position h (0 when the sample is constant: the bracket then
+    has zero width whatever the output)."""
     if not hi > lo:
         return 0.0
-    return (value - lo) / (hi - lo)
+    return (value - lo) / (hi - lo) - h
 
 
 def adam_step(theta, grad, m, v, t: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,

@@ -728,12 +728,12 @@ int label_arrays(cps_handle *h, uint64_t seed, int64_t count, int64_t n, int64_t
     rc = select_kth_batched_ex(h, (const void *const *)ptrs, sizes, ks, c, CPS_F32, nullptr, res, s);
     if (rc) return rc;
     if (!outs) {
-      e = cps::launch_labels(res, rg, vd, c, ustar + c0, s);
+      e = cps::launch_labels(res, f, rg, vd, c, ustar + c0, s);
       if (e != hipSuccess) return hip_fail(e);
     } else {
       rc = cps_mlp_forward(h, params, f, c, outs, s);
       if (rc) return rc;
-      e = cps::launch_holdout(outs, rg, vd, res, c, acc, s);
+      e = cps::launch_holdout(outs, f, rg, vd, res, c, acc, s);
       if (e != hipSuccess) return hip_fail(e);
     }
   }

@@ -356,13 +356,26 @@ CPS_HD inline void cp_after_pass0(CpState &s, const Pass0Result &r, const CpConf
       s.BR = r.B_b + (double)r.nneg * (b - r.fmin);
     }
     // With both ends proven, the elements pass 0 wrote (those strictly inside (a, b))
-    // are exactly the bracket's, cR - cL of them: later passes read only those.
-    if (c.p0_split && s.bracket_used == 3 && r.split_overflow == 0) {
-      s.wbuf = 0;
-      s.side = 0;
-      s.wlen = s.cR - s.cL;
-      s.on_bracket = 1;
-      s.elements_written += s.wlen;
+    // are exactly the bracket's, cR - cL of them: later passes read only those.  With the
+    // exact finish by histograms, an end beyond the data (a <= min, b >= max) may stand
+    // in for a proven one: the written elements then hold the bracket's and those equal
+    // to that extreme, #(a < x < b) of them, and the histogram passes skip the extras.
+    const bool left_ok = (s.bracket_used & 1) || a <= r.fmin;
+    const bool right_ok = (s.bracket_used & 2) || b >= r.fmax;
+    if (c.p0_split && r.split_overflow == 0 && left_ok && right_ok && a < b) {
+      if (s.bracket_used == 3) {
+        s.wbuf = 0;
+        s.side = 0;
+        s.wlen = s.cR - s.cL;
+        s.on_bracket = 1;
+        s.elements_written += s.wlen;
+      } else if (c.hist_bits > 0) {
+        s.wbuf = 0;
+        s.side = 0;
+        s.wlen = r.c_lt_b - r.c_le_a;
+        s.narrowed = 1;
+        s.elements_written += s.wlen;
+      }
     }
   }
   cp_plan(s, c);

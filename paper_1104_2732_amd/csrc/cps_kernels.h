@@ -125,9 +125,10 @@ hipError_t launch_sample_bracket(const T *x, int64_t n, int64_t k, double z, dou
                                  hipStream_t stream);
 hipError_t launch_batch_descriptors(const float *base, int64_t n, int64_t count, const float **ptrs,
                                     int64_t *sizes, hipStream_t stream);
-hipError_t launch_labels(const cps_result *res, const double *range, const int32_t *valid,
-                         int64_t count, float *ustar, hipStream_t stream);
-hipError_t launch_holdout(const float *out, const double *range, const int32_t *valid,
-                          const cps_result *res, int64_t count, double *acc, hipStream_t stream);
+hipError_t launch_labels(const cps_result *res, const float *feat, const double *range,
+                         const int32_t *valid, int64_t count, float *ustar, hipStream_t stream);
+hipError_t launch_holdout(const float *out, const float *feat, const double *range,
+                          const int32_t *valid, const cps_result *res, int64_t count, double *acc,
+                          hipStream_t stream);
 
 }  // namespace cps

@@ -587,7 +587,7 @@ __global__ __launch_bounds__(256) void mlp_init_kernel(uint64_t seed, float *__r
                              (uint32_t)(seed >> 32));
   const float u = (float)(r.x >> 8) * 0x1p-24f;
   float val = (2.0f * u - 1.0f) * bound;
-  if (p == kOffB3) val = 0.5f;
+  if (p == kOffB3) val = 0.0f;  // start at the histogram's position
   if (p == kOffB3 + 1) val = logf(0.05f);
   P[p] = val;
 }
@@ -599,11 +599,24 @@ hipError_t launch_mlp_init(uint64_t seed, float *P, hipStream_t stream) {
 
 // ------------------------------------------------------------------ proposal of one array
 
-__device__ inline void proposal_from_outputs(float u, float s, double lo, double hi, bool valid,
-                                             double &a, double &b, bool &use) {
+// The histogram's own estimate of the rank's position in the sample range: where the
+// cumulative features cross the k/n feature, linear inside the crossing bin.  The network
+// predicts the offset from it.
+__device__ inline double hist_position(const float *f) {
+  const double p = (double)f[kBins + 2];
+  int b = 0;
+  while (b < kBins - 1 && (double)f[b] < p) ++b;
+  const double prev = b > 0 ? (double)f[b - 1] : 0.0;
+  const double fb = (double)f[b];
+  if (!(fb > prev)) return ((double)b + 0.5) / (double)kBins;
+  return ((double)b + (p - prev) / (fb - prev)) / (double)kBins;
+}
+
+__device__ inline void proposal_from_outputs(float u, float s, double h, double lo, double hi,
+                                             bool valid, double &a, double &b, bool &use) {
   const double span = hi - lo;
   const double sc = fmin(fmax((double)s, (double)kLogWMin), (double)kLogWMax);
-  const double y0 = lo + span * (double)u;
+  const double y0 = lo + span * (h + (double)u);
   const double w = span * exp(sc);
   a = y0 - w;
   b = y0 + w;
@@ -625,7 +638,8 @@ __global__ __launch_bounds__(kMlpBlock) void learned_bracket_kernel(const T *x, 
   if (threadIdx.x == 0) {
     double a, b;
     bool use;
-    proposal_from_outputs(sh.O[0][0], sh.O[0][1], lo, hi, ok != 0, a, b, use);
+    proposal_from_outputs(sh.O[0][0], sh.O[0][1], hist_position(&sh.X[0][0]), lo, hi, ok != 0,
+                          a, b, use);
     bracket[0] = use ? a : 0.0;
     bracket[1] = use ? b : 0.0;
     bracket[2] = use ? 1.0 : 0.0;
@@ -722,31 +736,34 @@ __global__ void batch_descriptor_kernel(const float *base, int64_t n, int64_t co
   }
 }
 
-// Labels u* = (x_(k) - lo) / (hi - lo), 0 where the sample was constant or invalid.
-__global__ void label_kernel(const cps_result *res, const double *range, const int32_t *valid,
-                             int64_t count, float *ustar) {
+// Labels (x_(k) - lo) / (hi - lo) - h with h the histogram position, 0 where the sample
+// was constant or invalid.
+__global__ void label_kernel(const cps_result *res, const float *feat, const double *range,
+                             const int32_t *valid, int64_t count, float *ustar) {
   for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < count;
        a += (int64_t)gridDim.x * blockDim.x) {
     const double lo = range[2 * a], hi = range[2 * a + 1];
     float u = 0.0f;
-    if (valid[a] && res[a].status == 0 && hi > lo) u = (float)((res[a].value - lo) / (hi - lo));
+    if (valid[a] && res[a].status == 0 && hi > lo)
+      u = (float)((res[a].value - lo) / (hi - lo) - hist_position(feat + a * kIn));
     ustar[a] = u;
   }
 }
 
 // Coverage of held-out arrays: acc[0] += #(a < x_(k) < b), acc[1] += sum of 2 w / (hi - lo),
 // acc[2] += #valid (one workgroup, in a fixed order).
-__global__ __launch_bounds__(256) void holdout_kernel(const float *out, const double *range,
-                                                      const int32_t *valid, const cps_result *res,
-                                                      int64_t count, double *acc) {
+__global__ __launch_bounds__(256) void holdout_kernel(const float *out, const float *feat,
+                                                      const double *range, const int32_t *valid,
+                                                      const cps_result *res, int64_t count,
+                                                      double *acc) {
   __shared__ double s0[256], s1[256], s2[256];
   double c = 0, wsum = 0, nv = 0;
   for (int64_t e = threadIdx.x; e < count; e += 256) {
     if (!valid[e] || res[e].status != 0) continue;
     double a, b;
     bool use;
-    proposal_from_outputs(out[2 * e], out[2 * e + 1], range[2 * e], range[2 * e + 1], true, a, b,
-                          use);
+    proposal_from_outputs(out[2 * e], out[2 * e + 1], hist_position(feat + e * kIn), range[2 * e],
+                          range[2 * e + 1], true, a, b, use);
     const double v = res[e].value, span = range[2 * e + 1] - range[2 * e];
     nv += 1;
     if (use && a < v && v < b) c += 1;
@@ -776,16 +793,17 @@ hipError_t launch_batch_descriptors(const float *base, int64_t n, int64_t count,
   return hipGetLastError();
 }
 
-hipError_t launch_labels(const cps_result *res, const double *range, const int32_t *valid,
-                         int64_t count, float *ustar, hipStream_t stream) {
-  label_kernel<<<dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream>>>(res, range, valid,
-                                                                               count, ustar);
+hipError_t launch_labels(const cps_result *res, const float *feat, const double *range,
+                         const int32_t *valid, int64_t count, float *ustar, hipStream_t stream) {
+  label_kernel<<<dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream>>>(res, feat, range,
+                                                                               valid, count, ustar);
   return hipGetLastError();
 }
 
-hipError_t launch_holdout(const float *out, const double *range, const int32_t *valid,
-                          const cps_result *res, int64_t count, double *acc, hipStream_t stream) {
-  holdout_kernel<<<dim3(1), dim3(256), 0, stream>>>(out, range, valid, res, count, acc);
+hipError_t launch_holdout(const float *out, const float *feat, const double *range,
+                          const int32_t *valid, const cps_result *res, int64_t count, double *acc,
+                          hipStream_t stream) {
+  holdout_kernel<<<dim3(1), dim3(256), 0, stream>>>(out, feat, range, valid, res, count, acc);
   return hipGetLastError();
 }
 

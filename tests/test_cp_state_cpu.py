@@ -119,11 +119,15 @@ def test_proposed_brackets(sim, oracle_mod, dtype, p0_split):
                         p0_split=p0_split, p0_cap=cap, hist_bits=hb)
                 _check(r, ref, (k, a, b, cap, hb))
                 assert r.bracket_used == _expected_ends(x, k, a, b), (k, a, b)
-                inside = int(np.sum((x > np.array(a, dtype)) & (x < np.array(b, dtype))))
-                adopted = p0_split and r.bracket_used == 3 and (cap is None or inside <= cap)
+                xa, xb = np.array(a, dtype), np.array(b, dtype)
+                inside = int(np.sum((x > xa) & (x < xb)))
+                fits = cap is None or inside <= cap
+                beyond = (r.bracket_used & 1 or xa <= x.min()) and (r.bracket_used & 2 or xb >= x.max())
+                adopted = p0_split and fits and (r.bracket_used == 3 or
+                                                 (hb > 0 and r.bracket_used and beyond and xa < xb))
                 # an adopted pass-0 split spares the evaluation passes over x
                 if adopted:
-                    assert r.passes == 1, (k, a, b, r.passes)
+                    assert r.passes == 1, (k, a, b, hb, r.passes)
 
 
 def test_passes_halve_on_smooth_data(sim):

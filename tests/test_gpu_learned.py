@@ -158,7 +158,7 @@ def test_init_is_deterministic_and_bounded(sel):
     assert np.max(np.abs(blocks["W1"])) <= math.sqrt(6 / 67) and np.all(blocks["b1"] == 0)
     assert np.max(np.abs(blocks["W2"])) <= math.sqrt(6 / 64) and np.all(blocks["b2"] == 0)
     assert np.max(np.abs(blocks["W3"])) <= 0.01 * math.sqrt(6 / 64) + 1e-9
-    assert blocks["b3"][0] == 0.5 and blocks["b3"][1] == pytest.approx(math.log(0.05), rel=1e-6)
+    assert blocks["b3"][0] == 0.0 and blocks["b3"][1] == pytest.approx(math.log(0.05), rel=1e-6)
 
 
 def _proposal_params(u, logw):
@@ -180,7 +180,7 @@ def test_bracket_matches_reference(sel):
         a, b, use = sel.learned_bracket(_dev(x), k, P)
         f, lo, hi = mlp.sample_features(x, k)
         o, _ = mlp.forward(theta.astype(np.float64), f.astype(np.float64)[None, :])
-        ra, rb = mlp.bracket(o[0], lo, hi)
+        ra, rb = mlp.bracket(o[0], lo, hi, mlp.hist_position(f))
         assert use == 1
         assert abs(a - ra) <= 1e-5 * (hi - lo) and abs(b - rb) <= 1e-5 * (hi - lo), (a, ra, b, rb)
     # a sample with an infinity gives no proposal
@@ -209,12 +209,14 @@ def test_learned_select_parity_with_any_proposal(sel, dtype):
             f = mlp.sample_features(x, k)
             lo, hi = f[1], f[2]
             span = hi - lo if hi > lo else 1.0
-            ustar = (float(xs[k - 1]) - lo) / span
+            # the network's first output is the offset from the histogram position
+            ustar = (float(xs[k - 1]) - lo) / span - mlp.hist_position(f[0])
+            h = mlp.hist_position(f[0])
             cases = {
                 "tight": (ustar, math.log(0.02)),       # both ends hold
                 "high": (ustar + 0.3, math.log(0.05)),  # misses above: only the lower end holds
                 "low": (ustar - 0.3, math.log(0.05)),   # misses below
-                "wide": (0.5, math.log(2.0)),           # covers everything: no end inside data
+                "wide": (0.5 - h, math.log(2.0)),       # covers everything: no end inside data
                 "overflow": (ustar, math.log(0.4)),     # holds but too many elements to compact
                 "tiny": (ustar, -30.0),                 # width e^-20 of the range after the clamp
             }

@@ -84,16 +84,41 @@ def test_width_clamp_stops_gradient():
     F = np.zeros((2, mlp.N_IN))
     _, g = mlp.loss_and_grad(theta, F, np.array([0.0, 0.1]))
     assert g[-1] == 0.0
-    a, b = mlp.bracket(np.array([0.0, 10.0]), 0.0, 1.0)
+    a, b = mlp.bracket(np.array([0.0, 10.0]), 0.0, 1.0, 0.0)
     assert (a, b) == (-math.exp(4.0), math.exp(4.0))
 
 
 def test_bracket_and_target_closed_form():
-    a, b = mlp.bracket(np.array([0.5, math.log(0.1)]), 2.0, 4.0)
+    a, b = mlp.bracket(np.array([0.5, math.log(0.1)]), 2.0, 4.0, 0.0)
     assert a == pytest.approx(2.8, rel=1e-15) and b == pytest.approx(3.2, rel=1e-15)
-    assert mlp.target(3.0, 2.0, 4.0) == 0.5
-    assert mlp.target(2.0, 2.0, 4.0) == 0.0 and mlp.target(4.0, 2.0, 4.0) == 1.0
-    assert mlp.target(7.0, 2.0, 2.0) == 0.0
+    a, b = mlp.bracket(np.array([0.25, math.log(0.1)]), 2.0, 4.0, 0.25)
+    assert a == pytest.approx(2.8, rel=1e-15) and b == pytest.approx(3.2, rel=1e-15)
+    assert mlp.target(3.0, 2.0, 4.0, 0.0) == 0.5 and mlp.target(3.0, 2.0, 4.0, 0.5) == 0.0
+    assert mlp.target(2.0, 2.0, 4.0, 0.0) == 0.0 and mlp.target(4.0, 2.0, 4.0, 0.0) == 1.0
+    assert mlp.target(7.0, 2.0, 2.0, 0.3) == 0.0
+
+
+def test_hist_position_closed_form():
+    """Uniform sample: F_b = (b+1)/64, so the crossing of p sits at p itself; a two-bin
+    sample interpolates inside its crossing bin."""
+    f = np.zeros(mlp.N_IN, np.float32)
+    f[:64] = (np.arange(64) + 1) / 64.0
+    for p in (0.25, 0.5, 0.75, 1.0):
+        f[66] = p
+        assert mlp.hist_position(f) == pytest.approx(p, abs=1e-15)
+    f[:64] = 0.0
+    f[10:] = 0.4     # 40 % of the sample in bin 10
+    f[40:] = 1.0     # the rest in bin 40
+    f[66] = 0.2      # half-way through bin 10's mass
+    assert mlp.hist_position(f) == pytest.approx(10.5 / 64, abs=1e-7)
+    f[66] = 0.7
+    assert mlp.hist_position(f) == pytest.approx(40.5 / 64, abs=1e-7)
+    # against the exact sample quantile of a smooth sample: within about one bin
+    x = np.random.default_rng(3).standard_normal(1 << 16).astype(np.float32)
+    for k in (100, 30_000, 60_000):
+        f, lo, hi = mlp.sample_features(x, k)
+        q = np.sort(x[:: 16])[int(k / x.size * 4096)]
+        assert abs(mlp.hist_position(f) - (q - lo) / (hi - lo)) < 1.5 / 64
 
 
 def test_histogram_against_numpy_histogram():
