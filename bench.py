@@ -43,7 +43,7 @@ SIZES = (24, 28)
 DTYPES = (np.float32, np.float64)
 DISTS = ("uniform", "normal", "cauchy", "quantized_normal")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cp_select_kernel_traffic.json")
-EPOCHS = 30  # training epochs of the learned proposal (untimed setup)
+EPOCHS = 20  # training epochs of the learned proposal (untimed setup)
 
 
 def kernel_source_hash() -> str:
