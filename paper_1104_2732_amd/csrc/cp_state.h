@@ -76,7 +76,8 @@ struct CpConfig {
 // one reduction; here with the multiplicity of min and max, the sum over finite
 // values and the counts of NaN and infinities).
 struct Pass0Result {
-  int32_t classified;   // 1: NaN and infinities were classified (nneg, npos, finite min/max)
+  int32_t classified;   // 1: NaN and infinities were classified (nnan, nneg, npos, finite
+                        // min/max); 0: nothing classified (nnan etc. are 0)
   int32_t pad0;
   double sum;           // sum of finite elements
   double fmin, fmax;    // min and max over finite elements (+inf / -inf if none)
@@ -288,10 +289,11 @@ CPS_HD inline void cp_after_pass0(CpState &s, const Pass0Result &r, const CpConf
   s.status = ST_OK;
   s.bracket_used = 0;
   s.final_size = 0;
-  if (!r.classified && r.nnan == 0 &&
-      (r.fmin == -__builtin_inf() || r.fmax == __builtin_inf())) {
-    // The fast pass 0 does not separate infinities from the finite extremes; repeat it
-    // with the classification (only inputs holding an infinity pay for this).
+  if (!r.classified &&
+      (r.sum != r.sum || r.fmin == -__builtin_inf() || r.fmax == __builtin_inf())) {
+    // The fast pass 0 classifies nothing: NaN (a NaN sum) or an infinity (an infinite
+    // extreme, or a NaN sum when both signs occur) makes it repeat with the classification;
+    // only such inputs pay for the second pass.
     s.phase = PH_PASS0;
     s.p0_slow = 1;
     return;

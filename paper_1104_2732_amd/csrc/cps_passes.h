@@ -48,16 +48,17 @@ template <typename T> struct P0Acc {
   double Aa, Ba, Ab, Bb;
 };
 
-// Pass 0 on one element.  CLASSIFY: separate NaN and infinities from the finite values
-// (the slow variant); otherwise only NaN is detected and infinities, if any, show up as
-// an infinite extreme, which makes the state machine ask for the slow variant.
+// Pass 0 on one element.  CLASSIFY: count NaN and infinities and keep them out of the
+// finite min, max and sum (the slow variant).  Otherwise nothing is classified: NaN makes
+// the sum NaN and an infinity shows up as an infinite extreme (or a NaN sum), either of
+// which makes the state machine ask for the slow variant.
 template <typename T, bool CLASSIFY, bool BRACKET>
 __device__ inline void pass0_one(T v, bool valid, T ba, T bb, T &s_part, T &aa, T &bA, T &ab,
                                  T &bB, P0Acc<T> &acc) {
-  const bool isnan_ = valid && (v != v);
-  acc.nnan += isnan_ ? 1u : 0u;
   bool fin = valid;
   if (CLASSIFY) {
+    const bool isnan_ = valid && (v != v);
+    acc.nnan += isnan_ ? 1u : 0u;
     const bool ni = valid && (v == -t_inf<T>());
     const bool pi = valid && (v == t_inf<T>());
     acc.nneg += ni ? 1u : 0u;

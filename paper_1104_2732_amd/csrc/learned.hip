@@ -210,13 +210,25 @@ __device__ void array_features(const T *x, int64_t n, int64_t k, FeatShared &fs,
   const int64_t stride = n / S;
   double mn = __builtin_inf(), mx = -__builtin_inf();
   int bad = 0;
-  for (int64_t i = tid; i < S; i += kFeatBlock) {
-    const double v = (double)x[i * stride];
-    fs.v[i] = v;
-    if (!__builtin_isfinite(v)) bad = 1;
-    else {
-      mn = fmin(mn, v);
-      mx = fmax(mx, v);
+  // all of this thread's strided loads in flight at once (each is its own cache line)
+  constexpr int PER = kSample / kFeatBlock;
+  double vv[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int64_t i = tid + (int64_t)j * kFeatBlock;
+    vv[j] = i < S ? (double)x[i * stride] : 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int64_t i = tid + (int64_t)j * kFeatBlock;
+    if (i < S) {
+      const double v = vv[j];
+      fs.v[i] = v;
+      if (!__builtin_isfinite(v)) bad = 1;
+      else {
+        mn = fmin(mn, v);
+        mx = fmax(mx, v);
+      }
     }
   }
   mn = wave_min(mn);
@@ -671,13 +683,18 @@ __global__ __launch_bounds__(kSortBlock) void sample_bracket_kernel(const T *x, 
   const int64_t stride = n / S;
   if (tid == 0) bad = 0;
   __syncthreads();
-  for (int i = tid; i < kSample; i += kSortBlock) {
-    double v = __builtin_inf();
-    if (i < S) {
-      v = (double)x[i * stride];
-      if (!__builtin_isfinite(v)) bad = 1;
-    }
-    sv[i] = v;
+  constexpr int PER = kSample / kSortBlock;
+  double vv[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {  // the strided loads all in flight
+    const int i = tid + j * kSortBlock;
+    vv[j] = i < S ? (double)x[i * stride] : __builtin_inf();
+  }
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int i = tid + j * kSortBlock;
+    if (i < S && !__builtin_isfinite(vv[j])) bad = 1;
+    sv[i] = vv[j];
   }
   __syncthreads();
   if (bad) {

@@ -106,12 +106,41 @@ __device__ inline void split_one(T v, bool valid, T t, T yL, T yR, WaveOut<T> &o
   o.hi += popc(mr);
 }
 
+// One tile of an evaluation pass: U vectors per thread.  FULL: every vector of the tile
+// lies inside the span (no bounds tests; every tile but a span's last is full).
+template <typename T, int U, bool CLAMP, bool SPLIT, bool FILTER, bool FULL>
+__device__ inline void eval_tile(const Span<T> &sp, int64_t base, int per_u, int me, T t, T yL,
+                                 T yR, T fmin, T fmax, WaveOut<T> &o, EvalAcc<T> &acc) {
+  constexpr int V = Traits<T>::kVec;
+  using Vec = typename Traits<T>::Vec;
+  Vec raw[U];
+  bool valid[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t vi = base + (int64_t)u * per_u + me;
+    valid[u] = FULL || vi < sp.nvec;
+    if (valid[u]) raw[u] = sp.V[vi];
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    T e[V];
+    vec_to_arr<T>(raw[u], e);
+    T a_part = 0, b_part = 0;
+#pragma unroll
+    for (int j = 0; j < V; ++j) eval_one<T, CLAMP>(e[j], valid[u], t, fmin, fmax, a_part, b_part, acc);
+    acc.A += (double)a_part;
+    acc.B += (double)b_part;
+    if (SPLIT) {
+#pragma unroll
+      for (int j = 0; j < V; ++j) split_one<T, FILTER>(e[j], valid[u], t, yL, yR, o);
+    }
+  }
+}
+
 // One evaluation pass (optionally splitting) over this thread's share of the walk.
 template <typename T, int BLOCK, int U, bool CLAMP, bool SPLIT, bool FILTER>
 __device__ inline void eval_pass(const Walk<T> &wk, T t, T yL, T yR, T fmin, T fmax,
                                        WaveOut<T> &o, EvalAcc<T> &acc) {
-  constexpr int V = Traits<T>::kVec;
-  using Vec = typename Traits<T>::Vec;
   const int tid = threadIdx.x, lane = tid % kWave;
   const Span<T> &sp = wk.sp;
   const int64_t step_vecs = wk.wave_mode ? (int64_t)kWave * U : (int64_t)BLOCK * U;
@@ -120,28 +149,10 @@ __device__ inline void eval_pass(const Walk<T> &wk, T t, T yL, T yR, T fmin, T f
   const int me = wk.wave_mode ? lane : tid;
   const int per_u = wk.wave_mode ? kWave : BLOCK;
   for (int64_t base = first; base < sp.nvec; base += stride) {
-    Vec raw[U];
-    bool valid[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t vi = base + (int64_t)u * per_u + me;
-      valid[u] = vi < sp.nvec;
-      if (valid[u]) raw[u] = sp.V[vi];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      T e[V];
-      vec_to_arr<T>(raw[u], e);
-      T a_part = 0, b_part = 0;
-#pragma unroll
-      for (int j = 0; j < V; ++j) eval_one<T, CLAMP>(e[j], valid[u], t, fmin, fmax, a_part, b_part, acc);
-      acc.A += (double)a_part;
-      acc.B += (double)b_part;
-      if (SPLIT) {
-#pragma unroll
-        for (int j = 0; j < V; ++j) split_one<T, FILTER>(e[j], valid[u], t, yL, yR, o);
-      }
-    }
+    if (base + (int64_t)U * per_u <= sp.nvec)
+      eval_tile<T, U, CLAMP, SPLIT, FILTER, true>(sp, base, per_u, me, t, yL, yR, fmin, fmax, o, acc);
+    else
+      eval_tile<T, U, CLAMP, SPLIT, FILTER, false>(sp, base, per_u, me, t, yL, yR, fmin, fmax, o, acc);
   }
   if (sp.nedge > 0 && wk.edge_owner && (wk.wave_mode || tid < kWave)) {
     const bool have = lane < sp.nedge;
@@ -166,44 +177,53 @@ __device__ inline void split_inside(T v, bool valid, T a, T b, WaveOut<T> &o, ui
   o.lo += popc(m);
 }
 
+template <typename T, int U, bool CLASSIFY, bool BRACKET, bool SPLIT, bool FULL>
+__device__ inline void pass0_tile(const Span<T> &sp, int64_t base, int per_u, int me, T ba, T bb,
+                                  P0Acc<T> &acc, WaveOut<T> &o, uint32_t cap) {
+  constexpr int V = Traits<T>::kVec;
+  using Vec = typename Traits<T>::Vec;
+  Vec raw[U];
+  bool valid[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t vi = base + (int64_t)u * per_u + me;
+    valid[u] = FULL || vi < sp.nvec;
+    if (valid[u]) raw[u] = sp.V[vi];
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    T e[V];
+    vec_to_arr<T>(raw[u], e);
+    T s_part = 0, aa = 0, bA = 0, ab = 0, bB = 0;
+#pragma unroll
+    for (int j = 0; j < V; ++j)
+      pass0_one<T, CLASSIFY, BRACKET>(e[j], valid[u], ba, bb, s_part, aa, bA, ab, bB, acc);
+    if (SPLIT) {
+#pragma unroll
+      for (int j = 0; j < V; ++j) split_inside<T>(e[j], valid[u], ba, bb, o, cap);
+    }
+    acc.sum += (double)s_part;
+    if (BRACKET) {
+      acc.Aa += (double)aa;
+      acc.Ba += (double)bA;
+      acc.Ab += (double)ab;
+      acc.Bb += (double)bB;
+    }
+  }
+}
+
 template <typename T, int BLOCK, int U, bool CLASSIFY, bool BRACKET, bool SPLIT>
 __device__ inline void pass0(const Walk<T> &wk, T ba, T bb, P0Acc<T> &acc, WaveOut<T> &o,
                              uint32_t cap) {
-  constexpr int V = Traits<T>::kVec;
-  using Vec = typename Traits<T>::Vec;
   const int tid = threadIdx.x, lane = tid % kWave;
   const Span<T> &sp = wk.sp;
   const int64_t step_vecs = (int64_t)BLOCK * U;
   for (int64_t base = (int64_t)blockIdx.x * step_vecs; base < sp.nvec;
        base += (int64_t)gridDim.x * step_vecs) {
-    Vec raw[U];
-    bool valid[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t vi = base + (int64_t)u * BLOCK + tid;
-      valid[u] = vi < sp.nvec;
-      if (valid[u]) raw[u] = sp.V[vi];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      T e[V];
-      vec_to_arr<T>(raw[u], e);
-      T s_part = 0, aa = 0, bA = 0, ab = 0, bB = 0;
-#pragma unroll
-      for (int j = 0; j < V; ++j)
-        pass0_one<T, CLASSIFY, BRACKET>(e[j], valid[u], ba, bb, s_part, aa, bA, ab, bB, acc);
-      if (SPLIT) {
-#pragma unroll
-        for (int j = 0; j < V; ++j) split_inside<T>(e[j], valid[u], ba, bb, o, cap);
-      }
-      acc.sum += (double)s_part;
-      if (BRACKET) {
-        acc.Aa += (double)aa;
-        acc.Ba += (double)bA;
-        acc.Ab += (double)ab;
-        acc.Bb += (double)bB;
-      }
-    }
+    if (base + step_vecs <= sp.nvec)
+      pass0_tile<T, U, CLASSIFY, BRACKET, SPLIT, true>(sp, base, BLOCK, tid, ba, bb, acc, o, cap);
+    else
+      pass0_tile<T, U, CLASSIFY, BRACKET, SPLIT, false>(sp, base, BLOCK, tid, ba, bb, acc, o, cap);
   }
   if (sp.nedge > 0 && wk.edge_owner && tid < kWave) {
     const bool have = lane < sp.nedge;
@@ -279,11 +299,36 @@ __device__ inline void gather_walk(const Walk<T> &wk, T yL, T yR, T *zf, uint64_
 
 // Histogram pass: every element of the walk whose ordered key lies in [klo, khi] is counted
 // in LDS bin (key - klo) >> shift.
+template <typename T, int U, bool FULL>
+__device__ inline void hist_tile(const Span<T> &sp, int64_t base, int per_u, int me,
+                                 typename Traits<T>::Key klo, typename Traits<T>::Key khi,
+                                 int shift, uint32_t *rh) {
+  constexpr int V = Traits<T>::kVec;
+  using Vec = typename Traits<T>::Vec;
+  using Key = typename Traits<T>::Key;
+  Vec raw[U];
+  bool valid[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t vi = base + (int64_t)u * per_u + me;
+    valid[u] = FULL || vi < sp.nvec;
+    if (valid[u]) raw[u] = sp.V[vi];
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    T e[V];
+    vec_to_arr<T>(raw[u], e);
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const Key K = Traits<T>::key(e[j]);
+      if (valid[u] && K >= klo && K <= khi) atomicAdd(&rh[(uint32_t)((K - klo) >> shift)], 1u);
+    }
+  }
+}
+
 template <typename T, int BLOCK, int U>
 __device__ inline void hist_walk(const Walk<T> &wk, typename Traits<T>::Key klo,
                                  typename Traits<T>::Key khi, int shift, uint32_t *rh) {
-  constexpr int V = Traits<T>::kVec;
-  using Vec = typename Traits<T>::Vec;
   using Key = typename Traits<T>::Key;
   const int tid = threadIdx.x, lane = tid % kWave;
   const Span<T> &sp = wk.sp;
@@ -293,24 +338,10 @@ __device__ inline void hist_walk(const Walk<T> &wk, typename Traits<T>::Key klo,
   const int me = wk.wave_mode ? lane : tid;
   const int per_u = wk.wave_mode ? kWave : BLOCK;
   for (int64_t base = first; base < sp.nvec; base += stride) {
-    Vec raw[U];
-    bool valid[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t vi = base + (int64_t)u * per_u + me;
-      valid[u] = vi < sp.nvec;
-      if (valid[u]) raw[u] = sp.V[vi];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      T e[V];
-      vec_to_arr<T>(raw[u], e);
-#pragma unroll
-      for (int j = 0; j < V; ++j) {
-        const Key K = Traits<T>::key(e[j]);
-        if (valid[u] && K >= klo && K <= khi) atomicAdd(&rh[(uint32_t)((K - klo) >> shift)], 1u);
-      }
-    }
+    if (base + (int64_t)U * per_u <= sp.nvec)
+      hist_tile<T, U, true>(sp, base, per_u, me, klo, khi, shift, rh);
+    else
+      hist_tile<T, U, false>(sp, base, per_u, me, klo, khi, shift, rh);
   }
   if (sp.nedge > 0 && wk.edge_owner && (wk.wave_mode || tid < kWave)) {
     if (lane < sp.nedge) {

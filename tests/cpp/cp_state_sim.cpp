@@ -65,7 +65,8 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
         if (my_l < p0_cap) z[0][my_l] = v;
         my_l++;
       }
-      if (std::isnan(v)) { r.nnan++; continue; }
+      // the fast pass classifies nothing: NaN reaches the sum (and compares false)
+      if (classify && std::isnan(v)) { r.nnan++; continue; }
       const bool fin = !classify || std::isfinite(v);
       if (classify && v == (T)-INFINITY) r.nneg++;
       else if (classify && v == (T)INFINITY) r.npos++;
