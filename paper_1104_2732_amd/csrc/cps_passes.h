@@ -135,22 +135,31 @@ __device__ inline void block_reduce(double (&dv)[8], const int (&dop)[8], int64_
     for (int f = 0; f < NI; ++f) si[f][wv] = iv[f];
   }
   __syncthreads();
+  // one thread per field folds the wavefronts' values in wavefront order (fixed order,
+  // and the fields in parallel), then thread 0 collects the results
+  if (tid < ND) {
+    const int f = tid;
+    int op = 0;  // dop[f] by selects (an indexed read would move dop to scratch memory)
+#pragma unroll
+    for (int g = 0; g < ND; ++g) op = g == f ? dop[g] : op;
+    double r = sd[f][0];
+    for (int w = 1; w < BLOCK / kWave; ++w) {
+      const double x = sd[f][w];
+      r = op == 0 ? r + x : (op == 1 ? fmin(r, x) : fmax(r, x));
+    }
+    sd[f][0] = r;
+  } else if (tid >= kWave && tid < kWave + NI) {
+    const int f = tid - kWave;
+    int64_t r = 0;
+    for (int w = 0; w < BLOCK / kWave; ++w) r += si[f][w];
+    si[f][0] = r;
+  }
+  __syncthreads();
   if (tid == 0) {
 #pragma unroll
-    for (int f = 0; f < ND; ++f) {
-      double r = sd[f][0];
-      for (int w = 1; w < BLOCK / kWave; ++w) {
-        const double x = sd[f][w];
-        r = dop[f] == 0 ? r + x : (dop[f] == 1 ? fmin(r, x) : fmax(r, x));
-      }
-      dv[f] = r;
-    }
+    for (int f = 0; f < ND; ++f) dv[f] = sd[f][0];
 #pragma unroll
-    for (int f = 0; f < NI; ++f) {
-      int64_t r = 0;
-      for (int w = 0; w < BLOCK / kWave; ++w) r += si[f][w];
-      iv[f] = r;
-    }
+    for (int f = 0; f < NI; ++f) iv[f] = si[f][0];
   }
   __syncthreads();
 }
@@ -173,12 +182,26 @@ __device__ inline void block_pair_fold(double &mn, int64_t &cmn, double &mx, int
     sd[0][wv] = mn; si[0][wv] = cmn; sd[1][wv] = mx; si[1][wv] = cmx;
   }
   __syncthreads();
+  // the minimum in thread 0 and the maximum in the first thread of wavefront 1, in
+  // wavefront order
   if (tid == 0) {
-    mn = sd[0][0]; cmn = si[0][0]; mx = sd[1][0]; cmx = si[1][0];
+    mn = sd[0][0]; cmn = si[0][0];
     for (int w = 1; w < BLOCK / kWave; ++w) {
       if (sd[0][w] < mn) { mn = sd[0][w]; cmn = si[0][w]; } else if (sd[0][w] == mn) cmn += si[0][w];
-      if (sd[1][w] > mx) { mx = sd[1][w]; cmx = si[1][w]; } else if (sd[1][w] == mx) cmx += si[1][w];
     }
+  } else if (tid == kWave) {
+    double m = sd[1][0];
+    int64_t c = si[1][0];
+    for (int w = 1; w < BLOCK / kWave; ++w) {
+      if (sd[1][w] > m) { m = sd[1][w]; c = si[1][w]; } else if (sd[1][w] == m) c += si[1][w];
+    }
+    sd[1][0] = m;
+    si[1][0] = c;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    mx = sd[1][0];
+    cmx = si[1][0];
   }
   __syncthreads();
 }
