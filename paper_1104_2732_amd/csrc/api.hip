@@ -366,10 +366,16 @@ int lms_median_sq_residuals(cps_handle *h, const double *X_dev, const double *y_
     if (e != hipSuccess) return hip_fail(e);
   }
   char *base = (char *)h->lws;
+  // every candidate's array has n elements: split buffers that hold a whole array let the
+  // first cutting-plane step that leaves at most the split fraction of n compact it
+  cps_batch_options o;
+  cps_default_batch_options(&o);
+  o.block_threads = 1024;
+  o.split_capacity = n < 64 ? 64 : n;
   return select_kth_batched_ex(h, (const void *const *)(base + off_desc),
                                (const int64_t *)(base + off_desc + align_up((size_t)m * 8, 256)),
                                (const int64_t *)(base + off_desc + 2 * align_up((size_t)m * 8, 256)),
-                               m, CPS_F64, nullptr, out_dev, stream);
+                               m, CPS_F64, &o, out_dev, stream);
 }
 
 int cps_autotune_batched(cps_handle *h, const void *const *ptrs_dev, const int64_t *sizes_dev,

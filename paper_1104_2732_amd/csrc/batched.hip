@@ -77,16 +77,29 @@ __device__ inline void block_split_tile(const T (&e)[U][Traits<T>::kVec], const 
     sh.wcnt[1][wv] = wr;
   }
   __syncthreads();
-  if (tid == 0) {
-    uint64_t bl = (uint64_t)sh.cur[0], br = (uint64_t)sh.cur[1];
-    for (int w = 0; w < BLOCK / kWave; ++w) {
-      sh.wbase[0][w] = bl;
-      bl += sh.wcnt[0][w];
-      sh.wbase[1][w] = br;
-      br += sh.wcnt[1][w];
+  if (wv == 0) {
+    // exclusive scan of the wavefronts' counts in wavefront order, by the first wavefront
+    constexpr int WPB = BLOCK / kWave;
+    const uint64_t cl = lane < WPB ? sh.wcnt[0][lane] : 0u;
+    const uint64_t cr = lane < WPB ? sh.wcnt[1][lane] : 0u;
+    uint64_t il = cl, ir = cr;
+#pragma unroll
+    for (int o = 1; o < WPB; o <<= 1) {
+      const uint64_t ul = __shfl_up(il, o), ur = __shfl_up(ir, o);
+      if (lane >= o) {
+        il += ul;
+        ir += ur;
+      }
     }
-    sh.cur[0] = (int64_t)bl;
-    sh.cur[1] = (int64_t)br;
+    const uint64_t bl = (uint64_t)sh.cur[0], br = (uint64_t)sh.cur[1];
+    if (lane < WPB) {
+      sh.wbase[0][lane] = bl + il - cl;
+      sh.wbase[1][lane] = br + ir - cr;
+    }
+    if (lane == WPB - 1) {
+      sh.cur[0] = (int64_t)(bl + il);
+      sh.cur[1] = (int64_t)(br + ir);
+    }
   }
   __syncthreads();
   uint64_t ol = sh.wbase[0][wv], orr = sh.wbase[1][wv];
