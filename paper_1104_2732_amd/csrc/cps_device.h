@@ -54,26 +54,48 @@ __device__ inline uint32_t lane_rank(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+// Wavefront reductions with DPP row moves (no LDS round trips): four row shifts fold each
+// 16-lane row into its lane 15, two row broadcasts fold the rows into lane 63, and lane 63
+// is read as a scalar.  The order of the operations is fixed, so the results are
+// deterministic; every lane receives the result.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_move(double v, double fill) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint64_t f = __builtin_bit_cast(uint64_t, fill);
+  const int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)f, (int)(uint32_t)b, CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(f >> 32), (int)(uint32_t)(b >> 32), CTRL,
+                                             ROWS, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
-__device__ inline double wave_max(double v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-  return v;
+
+__device__ inline double lane63(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
-__device__ inline double wave_min(double v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-  return v;
+
+// OP 0: sum, 1: min, 2: max
+template <int OP> __device__ inline double dpp_op(double a, double b) {
+  return OP == 0 ? a + b : (OP == 1 ? fmin(a, b) : fmax(a, b));
 }
-__device__ inline int64_t wave_sum_i64(int64_t v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+
+template <int OP> __device__ inline double wave_reduce(double v) {
+  const double id = OP == 0 ? 0.0 : (OP == 1 ? __builtin_inf() : -__builtin_inf());
+  v = dpp_op<OP>(v, dpp_move<0x111, 0xF>(v, id));  // row_shr:1
+  v = dpp_op<OP>(v, dpp_move<0x112, 0xF>(v, id));  // row_shr:2
+  v = dpp_op<OP>(v, dpp_move<0x114, 0xF>(v, id));  // row_shr:4
+  v = dpp_op<OP>(v, dpp_move<0x118, 0xF>(v, id));  // row_shr:8
+  v = dpp_op<OP>(v, dpp_move<0x142, 0xA>(v, id));  // row_bcast:15 into rows 1 and 3
+  v = dpp_op<OP>(v, dpp_move<0x143, 0xC>(v, id));  // row_bcast:31 into rows 2 and 3
+  return lane63(v);
 }
+
+__device__ inline double wave_sum(double v) { return wave_reduce<0>(v); }
+__device__ inline double wave_min(double v) { return wave_reduce<1>(v); }
+__device__ inline double wave_max(double v) { return wave_reduce<2>(v); }
+// integer sums through double: exact while the wavefront's total stays below 2^53
+__device__ inline int64_t wave_sum_i64(int64_t v) { return (int64_t)wave_reduce<0>((double)v); }
 
 // Exclusive prefix sum over the workgroup in thread order (wsum: one slot per wavefront).
 template <int BLOCK>
