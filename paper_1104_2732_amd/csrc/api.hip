@@ -58,7 +58,7 @@ SelectLayout select_layout(int64_t seg_R, int grid, int64_t zcap, int gmax, size
   L.sync = off;
   off = align_up(off + sizeof(cps::SyncCtl), 256);
   L.gh = off;  // histogram counters, inside the cleared first part of fresh memory
-  off = align_up(off + cps::kHistMaxBins * sizeof(uint64_t), 256);
+  off = align_up(off + cps::kHistWords * sizeof(uint64_t), 256);
   L.slot_stride = gmax;
   L.sd = off;
   off = align_up(off + 8 * (size_t)gmax * sizeof(double), 256);
@@ -556,7 +556,7 @@ int cps_objective(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
   const size_t pi_bytes = align_up((size_t)ny * nb * 3 * sizeof(int64_t), 256);
   // keep clear of the select layout's state and synchronisation words at the start
   const size_t off = align_up(sizeof(cps::CpState), 256) + align_up(sizeof(cps::SyncCtl), 256) +
-                     align_up(cps::kHistMaxBins * sizeof(uint64_t), 256);
+                     align_up(cps::kHistWords * sizeof(uint64_t), 256);
   rc = ensure_workspace(h, off + pd_bytes + pi_bytes, s);
   if (rc) return rc;
   double *pd = (double *)((char *)h->ws + off);

@@ -488,22 +488,18 @@ CPS_HD inline double unkey_T(uint64_t k, int32_t dtype) {
   return dtype == 0 ? (double)unkey32((uint32_t)k) : unkey64(k);
 }
 
-// After a histogram pass over the working set: bin `b` holds rank k - cL of the bracket's
-// elements, with `below` of them in lower bins and `cnt` in bin b.  The bracket narrows to
-// the values of that bin (an exact step: every element of the bracket lies in exactly one
-// bin), counts follow from the histogram, and one key left means the value is x_(k).
-CPS_HD inline void cp_after_hist(CpState &s, int32_t b, int64_t below, int64_t cnt,
-                                 const CpConfig &c) {
-  s.work_passes++;
-  if (s.wbuf < 0) s.passes++;
-  s.elements_read += s.wlen;
+// Narrow the bracket to bin `b` of the key bins `g`, which hold every element of the bracket:
+// rank k - cL has `below` of them in lower bins and `cnt` in bin b.  The bracket becomes the
+// values of that bin (an exact step: every element of the bracket lies in exactly one bin),
+// the counts follow from the histogram, and one key left means the value is x_(k).
+CPS_HD inline void cp_hist_narrow(CpState &s, const HistGeom<uint64_t> &g, int32_t b,
+                                  int64_t below, int64_t cnt, const CpConfig &c) {
   const int64_t r = s.k - s.cL;
-  if (cnt < 1 || below >= r || below + cnt < r) {  // the counts and the data disagree
-    s.status = ST_INTERNAL;
+  if (b < 0 || b >= g.nbins || cnt < 1 || below >= r || below + cnt < r) {
+    s.status = ST_INTERNAL;  // the counts and the data disagree
     cp_finish(s, 0.0, 0, 0);
     return;
   }
-  const HistGeom<uint64_t> g = hist_geometry(s.lo, s.hi, c.dtype, c.hist_bits);
   const uint64_t nlo = g.klo + ((uint64_t)b << g.shift);
   uint64_t nhi = nlo + (((uint64_t)1 << g.shift) - 1);
   if (nhi > g.khi || nhi < nlo) nhi = g.khi;
@@ -525,6 +521,38 @@ CPS_HD inline void cp_after_hist(CpState &s, int32_t b, int64_t below, int64_t c
   s.on_bracket = 0;
   s.narrowed = 1;
   cp_plan(s, c);
+}
+
+// After a histogram pass over the working set, in bins of [lo, hi].
+CPS_HD inline void cp_after_hist(CpState &s, int32_t b, int64_t below, int64_t cnt,
+                                 const CpConfig &c) {
+  s.work_passes++;
+  if (s.wbuf < 0) s.passes++;
+  s.elements_read += s.wlen;
+  cp_hist_narrow(s, hist_geometry(s.lo, s.hi, c.dtype, c.hist_bits), b, below, cnt, c);
+}
+
+// Key bins of the two parts of a split at the planned trial point t, for a split pass that
+// also counts each part's elements: the low part's elements lie in [lo, t^-], the high
+// part's in [t^+, hi] (t^- and t^+ the neighbours of t in T).  An empty range has no bins.
+// When the state that follows the split asks for a histogram pass over the part that holds
+// x_(k), the counts of that part are known already and cp_hist_narrow applies at once,
+// which saves that pass.
+CPS_HD inline HistGeom<uint64_t> split_part_geometry(const CpState &s, int part,
+                                                     const CpConfig &c) {
+  const double a = part == 0 ? s.lo : next_up(s.t, c.dtype);
+  const double b = part == 0 ? next_down(s.t, c.dtype) : s.hi;
+  const uint64_t ka = c.dtype == 0 ? (uint64_t)key32((float)a) : key64(a);
+  const uint64_t kb = c.dtype == 0 ? (uint64_t)key32((float)b) : key64(b);
+  if (ka > kb) {
+    HistGeom<uint64_t> g;
+    g.klo = 1;
+    g.khi = 0;
+    g.shift = 0;
+    g.nbins = 0;
+    return g;
+  }
+  return hist_geometry(a, b, c.dtype, c.hist_bits);
 }
 
 // After the exact select of rank k - cL among the working set's elements inside the

@@ -24,6 +24,7 @@ constexpr int kSelectBlock = CPS_SELECT_BLOCK;
 constexpr int kSelectUnroll = CPS_SELECT_UNROLL;  // 16-byte loads in flight per thread, plain passes
 constexpr int kSplitUnroll = CPS_SPLIT_UNROLL;    // the same for passes that also write
 constexpr int kHistMaxBins = 4096;  // bins of a histogram pass (2^hist_bits, hist_bits <= 12)
+constexpr int kHistWords = 2 * kHistMaxBins;  // global counters: one set per part of a split
 constexpr int kGroup = 16;       // workgroups per first-level arrival counter
 constexpr int kMaxGroups = 256;  // so at most 4096 workgroups
 
@@ -57,7 +58,8 @@ template <typename T> struct SelectArgs {
   int64_t spin_limit;
   const double *bracket;  // device [a, b, use] read by pass 0 in place of cfg's, or null
   int64_t p0_cap;      // elements per wavefront region a bracketed pass 0 may write (0: none)
-  uint64_t *ghist;     // kHistMaxBins counters of a histogram pass (zero between passes)
+  uint64_t *ghist;     // kHistWords counters (zero between passes): a histogram pass uses the
+                       // first kHistMaxBins, a split pass that counts its parts both halves
 };
 
 // ---- batched selection

@@ -47,6 +47,10 @@ __device__ __noinline__ void dev_after_hist(CpState &s, int32_t b, int64_t below
                                             const CpConfig &c) {
   cp_after_hist(s, b, below, cnt, c);
 }
+__device__ __noinline__ void dev_hist_narrow(CpState &s, const HistGeom<uint64_t> &g, int32_t b,
+                                             int64_t below, int64_t cnt, const CpConfig &c) {
+  cp_hist_narrow(s, g, b, below, cnt, c);
+}
 
 // How the threads of a workgroup walk the working set.  BLOCK mode: the whole input,
 // tiles of BLOCK*U vectors dealt round-robin to workgroups (vector u*BLOCK + tid of a
@@ -61,6 +65,16 @@ template <typename T> struct Walk {
 
 // ------------------------------------------------------------------ kernel
 
+// Split staging: each lane keeps the elements it sends to either part of a split in its own
+// column of an LDS block (slot-major, so a wavefront's writes fall in distinct banks) and
+// moves them to global memory one 16-byte vector at a time, at a place given by a prefix
+// count over the wavefront's lanes that hold a full vector.
+template <typename T> struct Stage {
+  static constexpr uint32_t kV = Traits<T>::kVec;  // elements per 16-byte vector
+  static constexpr uint32_t kS = 2 * kV;           // slots per lane and part
+  static constexpr uint32_t kSlots = kS * kWave;   // per part and wavefront
+};
+
 template <typename T, int BLOCK> struct Shared {
   CpState st;
   double d[8][BLOCK / kWave];
@@ -71,7 +85,8 @@ template <typename T, int BLOCK> struct Shared {
   int64_t misc[8];
   int last;
   int timed_out;
-  uint32_t rh[kHistMaxBins];  // key histogram of a histogram pass
+  uint32_t rh[kHistWords];  // key histogram of a histogram pass, or of both parts of a split
+  T ring[BLOCK / kWave][2][Stage<T>::kSlots];  // split staging, per wavefront and part
 };
 
 // Which side of the trial point an element goes to in a split: the bracket's elements
@@ -87,30 +102,115 @@ __device__ inline bool goes_high(T v, bool valid, T t, T hi_ex) {
 }
 
 // Per-wavefront split output: the low part grows up from the start of the wavefront's
-// region, the high part down from its end.  The cursors are wave-uniform.
+// region, the high part down from its end.  lo / hi count the elements in the region
+// (wave-uniform).  The pass-0 compaction writes the low part directly; evaluation splits
+// stage both parts in LDS first (per lane: cl / ch elements staged, fl / fh of them moved).
 template <typename T> struct WaveOut {
   CPS_GLOBAL T *region;  // wave-uniform
   uint32_t top;          // Rw - 1
-  uint32_t lo, hi;       // wave-uniform cursors (a region holds fewer than 2^32 elements)
+  uint32_t lo, hi;       // a region holds fewer than 2^32 elements
+  uint32_t cl, ch, fl, fh;
+  T *ring_lo, *ring_hi;  // Stage<T>::kSlots each
 };
 
-template <typename T, bool FILTER>
-__device__ inline void split_one(T v, bool valid, T t, T yL, T yR, WaveOut<T> &o) {
+// Stage v in this lane's column: it is always written to the next free slot, which is
+// kept only when `sel`.
+template <typename T>
+__device__ inline void stage_one(T v, bool sel, T *ring, uint32_t &c, int lane) {
+  ring[(c & (Stage<T>::kS - 1)) * kWave + lane] = v;
+  c += sel ? 1u : 0u;
+}
+
+// Key bins of the two parts of a split (low part: counters rh[0..), high part: counters
+// rh[kHistMaxBins..)), for a split pass that also counts the parts' elements.
+template <typename T> struct PartBins {
+  typename Traits<T>::Key klo[2];
+  uint32_t last[2];  // nbins - 1
+  int shift[2];
+  uint32_t *rh;
+};
+
+template <typename T, bool FILTER, bool HIST>
+__device__ inline void split_one(T v, bool valid, T t, T yL, T yR, WaveOut<T> &o, int lane,
+                                 const PartBins<T> &pb) {
+  using Key = typename Traits<T>::Key;
   const bool l = goes_low<T, FILTER>(v, valid, t, yL);
-  const uint64_t ml = ballot(l);
-  if (l) o.region[o.lo + lane_rank(ml)] = v;
-  o.lo += popc(ml);
-  const bool r = goes_high<T, FILTER>(v, valid, t, yR);
-  const uint64_t mr = ballot(r);
-  if (r) o.region[o.top - (o.hi + lane_rank(mr))] = v;
-  o.hi += popc(mr);
+  const bool h = goes_high<T, FILTER>(v, valid, t, yR);
+  stage_one<T>(v, l, o.ring_lo, o.cl, lane);
+  stage_one<T>(v, h, o.ring_hi, o.ch, lane);
+  if (HIST && (l || h)) {
+    // An element of a part lies in that part's key range (the ranges come from the bracket's
+    // bounds and the neighbours of t in T, and keys are monotone), so its bin is in range;
+    // the clamp only keeps the counters safe.
+    const int p = l ? 0 : 1;
+    const Key K = Traits<T>::key(v);
+    uint32_t bin = (uint32_t)((K - pb.klo[p]) >> pb.shift[p]);
+    bin = bin < pb.last[p] ? bin : pb.last[p];
+    atomicAdd(&pb.rh[p * kHistMaxBins + bin], 1u);
+  }
+}
+
+// Move every lane's full vector of either part to the region.  Called after each vector of
+// input, so a lane holds fewer than two vectors of a part and moves at most one.
+template <typename T, bool HIGH>
+__device__ inline void flush_part(WaveOut<T> &o, const T *ring, uint32_t c, uint32_t &f,
+                                  int lane) {
+  using S = Stage<T>;
+  using Vec = typename Traits<T>::Vec;
+  const bool full = c - f >= S::kV;
+  const uint64_t m = ballot(full);
+  if (m == 0) return;
+  if (full) {
+    // f is a multiple of kV, so the vector's slots do not wrap
+    const T *col = ring + (f & (S::kS - 1)) * kWave + lane;
+    Vec d;
+#pragma unroll
+    for (uint32_t j = 0; j < S::kV; ++j) d[j] = col[j * kWave];
+    const uint32_t at = S::kV * lane_rank(m);
+    const uint32_t pos = HIGH ? o.top + 1 - o.hi - at - S::kV : o.lo + at;
+    *reinterpret_cast<CPS_GLOBAL Vec *>(o.region + pos) = d;
+    f += S::kV;
+  }
+  if (HIGH) o.hi += S::kV * popc(m);
+  else o.lo += S::kV * popc(m);
+}
+
+template <typename T>
+__device__ inline void split_flush(WaveOut<T> &o, int lane) {
+  __builtin_amdgcn_wave_barrier();
+  flush_part<T, false>(o, o.ring_lo, o.cl, o.fl, lane);
+  flush_part<T, true>(o, o.ring_hi, o.ch, o.fh, lane);
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Move what is left (at most one vector per lane and part) at the end of a split pass.
+template <typename T>
+__device__ inline void split_drain(WaveOut<T> &o, int lane) {
+  using S = Stage<T>;
+  __builtin_amdgcn_wave_barrier();
+  const T *cl = o.ring_lo + (o.fl & (S::kS - 1)) * kWave + lane;  // fl, fh: multiples of kV
+  const T *ch = o.ring_hi + (o.fh & (S::kS - 1)) * kWave + lane;
+#pragma unroll
+  for (uint32_t j = 0; j < S::kV; ++j) {
+    const bool sl = o.cl - o.fl > j;
+    const uint64_t ml = ballot(sl);
+    if (sl) o.region[o.lo + lane_rank(ml)] = cl[j * kWave];
+    o.lo += popc(ml);
+    const bool sh = o.ch - o.fh > j;
+    const uint64_t mh = ballot(sh);
+    if (sh) o.region[o.top - (o.hi + lane_rank(mh))] = ch[j * kWave];
+    o.hi += popc(mh);
+  }
+  o.fl = o.cl;
+  o.fh = o.ch;
 }
 
 // One tile of an evaluation pass: U vectors per thread.  FULL: every vector of the tile
 // lies inside the span (no bounds tests; every tile but a span's last is full).
-template <typename T, int U, bool CLAMP, bool SPLIT, bool FILTER, bool FULL>
+template <typename T, int U, bool CLAMP, bool SPLIT, bool FILTER, bool HIST, bool FULL>
 __device__ inline void eval_tile(const Span<T> &sp, int64_t base, int per_u, int me, T t, T yL,
-                                 T yR, T fmin, T fmax, WaveOut<T> &o, EvalAcc<T> &acc) {
+                                 T yR, T fmin, T fmax, WaveOut<T> &o, EvalAcc<T> &acc,
+                                 const PartBins<T> &pb) {
   constexpr int V = Traits<T>::kVec;
   using Vec = typename Traits<T>::Vec;
   Vec raw[U];
@@ -132,15 +232,17 @@ __device__ inline void eval_tile(const Span<T> &sp, int64_t base, int per_u, int
     acc.B += (double)b_part;
     if (SPLIT) {
 #pragma unroll
-      for (int j = 0; j < V; ++j) split_one<T, FILTER>(e[j], valid[u], t, yL, yR, o);
+      for (int j = 0; j < V; ++j)
+        split_one<T, FILTER, HIST>(e[j], valid[u], t, yL, yR, o, me % kWave, pb);
+      split_flush<T>(o, me % kWave);
     }
   }
 }
 
 // One evaluation pass (optionally splitting) over this thread's share of the walk.
-template <typename T, int BLOCK, int U, bool CLAMP, bool SPLIT, bool FILTER>
+template <typename T, int BLOCK, int U, bool CLAMP, bool SPLIT, bool FILTER, bool HIST>
 __device__ inline void eval_pass(const Walk<T> &wk, T t, T yL, T yR, T fmin, T fmax,
-                                       WaveOut<T> &o, EvalAcc<T> &acc) {
+                                       WaveOut<T> &o, EvalAcc<T> &acc, const PartBins<T> &pb) {
   const int tid = threadIdx.x, lane = tid % kWave;
   const Span<T> &sp = wk.sp;
   const int64_t step_vecs = wk.wave_mode ? (int64_t)kWave * U : (int64_t)BLOCK * U;
@@ -150,9 +252,11 @@ __device__ inline void eval_pass(const Walk<T> &wk, T t, T yL, T yR, T fmin, T f
   const int per_u = wk.wave_mode ? kWave : BLOCK;
   for (int64_t base = first; base < sp.nvec; base += stride) {
     if (base + (int64_t)U * per_u <= sp.nvec)
-      eval_tile<T, U, CLAMP, SPLIT, FILTER, true>(sp, base, per_u, me, t, yL, yR, fmin, fmax, o, acc);
+      eval_tile<T, U, CLAMP, SPLIT, FILTER, HIST, true>(sp, base, per_u, me, t, yL, yR, fmin, fmax,
+                                                        o, acc, pb);
     else
-      eval_tile<T, U, CLAMP, SPLIT, FILTER, false>(sp, base, per_u, me, t, yL, yR, fmin, fmax, o, acc);
+      eval_tile<T, U, CLAMP, SPLIT, FILTER, HIST, false>(sp, base, per_u, me, t, yL, yR, fmin, fmax,
+                                                         o, acc, pb);
   }
   if (sp.nedge > 0 && wk.edge_owner && (wk.wave_mode || tid < kWave)) {
     const bool have = lane < sp.nedge;
@@ -161,8 +265,9 @@ __device__ inline void eval_pass(const Walk<T> &wk, T t, T yL, T yR, T fmin, T f
     eval_one<T, CLAMP>(v, have, t, fmin, fmax, a_part, b_part, acc);
     acc.A += (double)a_part;
     acc.B += (double)b_part;
-    if (SPLIT) split_one<T, FILTER>(v, have, t, yL, yR, o);
+    if (SPLIT) split_one<T, FILTER, HIST>(v, have, t, yL, yR, o, lane, pb);
   }
+  if (SPLIT) split_drain<T>(o, lane);
 }
 
 // Pass 0 with a proposed bracket (a, b) may also write the elements strictly inside it to
@@ -351,6 +456,36 @@ __device__ inline void hist_walk(const Walk<T> &wk, typename Traits<T>::Key klo,
   }
 }
 
+// The bin holding rank r of a histogram's counts: an exclusive scan of the counts in a fixed
+// order.  Leaves the bin in misc[0] (-1 when no bin holds it), the count below it in
+// misc[1] and its own count in misc[2]; ends with a workgroup barrier.
+template <int BLOCK>
+__device__ inline void hist_pick(const uint64_t *gh, int nbins, uint64_t r, uint64_t *wsum,
+                                 int64_t *misc) {
+  const int tid = threadIdx.x;
+  constexpr int BPT = kHistMaxBins / BLOCK;
+  uint64_t hv[BPT];
+  uint64_t tot = 0;
+#pragma unroll
+  for (int j = 0; j < BPT; ++j) {
+    const int b = tid * BPT + j;
+    hv[j] = b < nbins ? gh[b] : 0;
+    tot += hv[j];
+  }
+  if (tid == 0) misc[0] = -1;
+  uint64_t cum = block_exclusive_scan<BLOCK>(tot, wsum);
+#pragma unroll
+  for (int j = 0; j < BPT; ++j) {
+    if (cum < r && r <= cum + hv[j]) {
+      misc[0] = tid * BPT + j;
+      misc[1] = (int64_t)cum;
+      misc[2] = (int64_t)hv[j];
+    }
+    cum += hv[j];
+  }
+  __syncthreads();
+}
+
 template <typename T>
 __device__ inline void write_result(const SelectArgs<T> &a, const CpState &s) {
   cps_result r;
@@ -427,7 +562,8 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
     const int wvu = __builtin_amdgcn_readfirstlane(wv);
     o.region = (CPS_GLOBAL T *)uniform_ptr(a.z[0] + ((int64_t)bid * WPB + wvu) * a.seg_R);
     o.top = (uint32_t)(a.seg_R - 1);
-    o.lo = o.hi = 0;
+    o.lo = o.hi = o.cl = o.ch = o.fl = o.fh = 0;
+    o.ring_lo = o.ring_hi = nullptr;  // pass 0 writes the region directly
     wk.sp = make_span(a.x, a.n);
     wk.wave_mode = false;
     wk.edge_owner = bid == 0;
@@ -452,7 +588,8 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
       sh.wseg[1][wv] = 0;
     }
     if (bid == 0 && a.cfg.hist_bits > 0)
-      for (int b = tid; b < (1 << a.cfg.hist_bits); b += BLOCK) a.ghist[b] = 0;
+      for (int b = tid; b < (1 << a.cfg.hist_bits); b += BLOCK)
+        a.ghist[b] = a.ghist[kHistMaxBins + b] = 0;
     double mn = (double)acc.mn, mx = (double)acc.mx;
     int64_t cmn = acc.cmn, cmx = acc.cmx;
     block_pair_fold<BLOCK>(mn, cmn, mx, cmx, sh.d, sh.i);
@@ -529,20 +666,47 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
     const int wvu = __builtin_amdgcn_readfirstlane(wv);
     o.region = (CPS_GLOBAL T *)uniform_ptr(a.z[s.zout] + ((int64_t)bid * WPB + wvu) * Rw);
     o.top = (uint32_t)(Rw - 1);
-    o.lo = o.hi = 0;
+    o.lo = o.hi = o.cl = o.ch = o.fl = o.fh = 0;
+    o.ring_lo = sh.ring[wv][0];
+    o.ring_hi = sh.ring[wv][1];
     const bool clamp = s.has_inf && s.wbuf < 0;
+    const bool hist = s.split && a.cfg.hist_bits > 0;
+    PartBins<T> pb;
+    pb.rh = sh.rh;
+    int nb[2] = {0, 0};
+    if (hist) {
+      for (int p = 0; p < 2; ++p) {
+        const HistGeom<uint64_t> g = split_part_geometry(s, p, a.cfg);
+        pb.klo[p] = (typename Traits<T>::Key)g.klo;
+        pb.last[p] = g.nbins > 0 ? (uint32_t)(g.nbins - 1) : 0u;
+        pb.shift[p] = g.shift;
+        nb[p] = g.nbins;
+        for (int b = tid; b < g.nbins; b += BLOCK) sh.rh[p * kHistMaxBins + b] = 0u;
+      }
+      __syncthreads();
+    }
     if (!s.split) {
-      if (clamp) eval_pass<T, BLOCK, SU, true, false, false>(wk, t, yL, yR, fmn, fmx, o, acc);
-      else eval_pass<T, BLOCK, UNROLL, false, false, false>(wk, t, yL, yR, fmn, fmx, o, acc);
+      if (clamp) eval_pass<T, BLOCK, SU, true, false, false, false>(wk, t, yL, yR, fmn, fmx, o, acc, pb);
+      else eval_pass<T, BLOCK, UNROLL, false, false, false, false>(wk, t, yL, yR, fmn, fmx, o, acc, pb);
     } else if (s.filter) {
-      eval_pass<T, BLOCK, SU, false, true, true>(wk, t, yL, yR, fmn, fmx, o, acc);
+      if (hist) eval_pass<T, BLOCK, SU, false, true, true, true>(wk, t, yL, yR, fmn, fmx, o, acc, pb);
+      else eval_pass<T, BLOCK, SU, false, true, true, false>(wk, t, yL, yR, fmn, fmx, o, acc, pb);
     } else {
-      eval_pass<T, BLOCK, SU, false, true, false>(wk, t, yL, yR, fmn, fmx, o, acc);
+      if (hist) eval_pass<T, BLOCK, SU, false, true, false, true>(wk, t, yL, yR, fmn, fmx, o, acc, pb);
+      else eval_pass<T, BLOCK, SU, false, true, false, false>(wk, t, yL, yR, fmn, fmx, o, acc, pb);
     }
     if (s.split && lane == 0) {
       sh.wseg[0][wv] = o.lo;
       sh.wseg[1][wv] = o.hi;
       written = (int64_t)o.lo + o.hi;
+    }
+    if (hist) {
+      __syncthreads();
+      for (int p = 0; p < 2; ++p)
+        for (int b = tid; b < nb[p]; b += BLOCK) {
+          const uint32_t c = sh.rh[p * kHistMaxBins + b];
+          if (c) atomic_add_relaxed(&a.ghist[p * kHistMaxBins + b], (uint64_t)c);
+        }
     }
   }
   dv[0] = acc.A; dv[1] = acc.B; dv[2] = (double)acc.pred; dv[3] = (double)acc.succ;
@@ -614,31 +778,9 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
       }
     }
   } else if (phase == PH_HIST) {
-    // the bin holding rank k - cL: an exclusive scan of the bin counts in a fixed order
     const CpState &s0 = sh.st;
     const HistGeom<uint64_t> g = hist_geometry(s0.lo, s0.hi, a.cfg.dtype, a.cfg.hist_bits);
-    const uint64_t r = (uint64_t)(s0.k - s0.cL);
-    constexpr int BPT = kHistMaxBins / BLOCK;
-    uint64_t hv[BPT];
-    uint64_t tot = 0;
-#pragma unroll
-    for (int j = 0; j < BPT; ++j) {
-      const int b = tid * BPT + j;
-      hv[j] = b < g.nbins ? a.ghist[b] : 0;
-      tot += hv[j];
-    }
-    if (tid == 0) sh.misc[0] = -1;
-    uint64_t cum = block_exclusive_scan<BLOCK>(tot, sh.gbase);
-#pragma unroll
-    for (int j = 0; j < BPT; ++j) {
-      if (cum < r && r <= cum + hv[j]) {
-        sh.misc[0] = tid * BPT + j;
-        sh.misc[1] = (int64_t)cum;
-        sh.misc[2] = (int64_t)hv[j];
-      }
-      cum += hv[j];
-    }
-    __syncthreads();
+    hist_pick<BLOCK>(a.ghist, g.nbins, (uint64_t)(s0.k - s0.cL), sh.gbase, sh.misc);
     for (int b = tid; b < g.nbins; b += BLOCK) a.ghist[b] = 0;  // ready for the next pass
     if (tid == 0) {
       CpState &s = sh.st;
@@ -652,6 +794,13 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
       }
     }
   } else {
+    // a split pass that counted its parts: their key bins, from the state it ran with
+    const bool counted = sh.st.phase == PH_EVAL && sh.st.split && a.cfg.hist_bits > 0;
+    HistGeom<uint64_t> pg[2];
+    if (counted) {
+      pg[0] = split_part_geometry(sh.st, 0, a.cfg);
+      pg[1] = split_part_geometry(sh.st, 1, a.cfg);
+    }
     rop[2] = 2; rop[3] = 1;
     for (int f = 0; f < 8; ++f) { rd[f] = 0; ri[f] = 0; }
     rd[2] = -__builtin_inf();
@@ -682,6 +831,27 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
         a.stats->population[pidx] = s.phase == PH_DONE ? 0 : s.cR - s.cL;
         a.stats->working[pidx] = wl;
       }
+    }
+    if (counted) {
+      __syncthreads();
+      // the state asks for a histogram pass over the part that holds x_(k): its counts are
+      // here already, so the bracket narrows now
+      if (sh.st.phase == PH_HIST && sh.st.on_bracket) {
+        const CpState &s1 = sh.st;
+        const int p = s1.side;
+        hist_pick<BLOCK>(a.ghist + p * kHistMaxBins, pg[p].nbins, (uint64_t)(s1.k - s1.cL), sh.gbase,
+                         sh.misc);
+        if (tid == 0) {
+          CpState &s = sh.st;
+          const int32_t bsel = (int32_t)sh.misc[0];
+          dev_hist_narrow(s, pg[p], bsel, bsel < 0 ? 0 : sh.misc[1], bsel < 0 ? 0 : sh.misc[2],
+                          a.cfg);
+          if (a.stats && pidx < CPS_STATS_MAX_PASSES)
+            a.stats->population[pidx] = s.phase == PH_DONE ? 0 : s.cR - s.cL;
+        }
+      }
+      for (int p = 0; p < 2; ++p)  // ready for the next pass
+        for (int b = tid; b < pg[p].nbins; b += BLOCK) a.ghist[p * kHistMaxBins + b] = 0;
     }
   }
   __syncthreads();

@@ -132,6 +132,15 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
       continue;
     }
     const bool clamp = s.has_inf && s.wbuf < 0;
+    // a split with the histogram finish also counts each part in key bins
+    const bool counted = s.split && c.hist_bits > 0;
+    HistGeom<uint64_t> pg[2] = {};
+    std::vector<int64_t> ph[2];
+    if (counted)
+      for (int p = 0; p < 2; ++p) {
+        pg[p] = split_part_geometry(s, p, c);
+        ph[p].assign((size_t)pg[p].nbins, 0);
+      }
     EvalResult e{};
     e.pred = -INFINITY;
     e.succ = INFINITY;
@@ -146,11 +155,27 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
         const bool inb = !s.filter || (v > yL && v < yR);
         if (inb && v < t) zo[nl++] = v;
         if (inb && v > t) zo[R - 1 - nr++] = v;
+        if (counted && inb && v != t) {
+          const int p = v < t ? 0 : 1;
+          const uint64_t K = sizeof(T) == 4 ? (uint64_t)key32((float)v) : key64((double)v);
+          if (K < pg[p].klo || K > pg[p].khi) return -17;  // outside its part's range
+          ph[p][(size_t)((K - pg[p].klo) >> pg[p].shift)]++;
+        }
       }
     }
     e.written = nl + nr;
     if (s.split) { my_l = nl; my_r = nr; }
     cp_after_eval(s, e, c);
+    if (counted && s.phase == PH_HIST && s.on_bracket) {
+      // the part that holds x_(k) is counted already: narrow without a histogram pass
+      const std::vector<int64_t> &h = ph[s.side];
+      const int64_t r = s.k - s.cL;
+      int64_t below = 0;
+      int32_t b = 0;
+      while (b < pg[s.side].nbins && below + h[(size_t)b] < r) below += h[(size_t)b++];
+      if (b >= pg[s.side].nbins) return -18;
+      cp_hist_narrow(s, pg[s.side], b, below, h[(size_t)b], c);
+    }
   }
   if (s.phase == PH_FINAL) {
     int64_t wl = 0;
