@@ -101,7 +101,7 @@ typedef struct cps_eval {
  *                   buffer, and later passes read only the side that still holds x_(k)
  *                   (the count-and-compact of Section 4, applied at every later pass).
  *                   0 disables splitting (plain passes over x, then one compaction).
- *                   Default 0.75.
+ *                   Default 1.0 (split from the first trial point on).
  * grid_blocks, block_threads: launch shape; 0 picks the tuned default.
  * spin_limit:       bound on device-side waiting loops (iterations); 0 = default.
  * bracket_lo/hi, use_bracket: a caller-supplied starting bracket (tests; the proposal

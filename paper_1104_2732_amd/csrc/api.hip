@@ -438,7 +438,7 @@ void cps_default_options(cps_options *opt) {
   std::memset(opt, 0, sizeof(*opt));
   opt->maxit = 64;
   opt->final_threshold = 8192;
-  opt->partition_fraction = 0.75;
+  opt->partition_fraction = 1.0;
   opt->grid_blocks = 0;
   opt->block_threads = 0;
   opt->spin_limit = 0;

@@ -362,17 +362,29 @@ __device__ inline void gather_walk(const Walk<T> &wk, T yL, T yR, T *zf, uint64_
   const int me = wk.wave_mode ? lane : tid;
   const int per_u = wk.wave_mode ? kWave : BLOCK;
   for (int64_t base = first; base < sp.nvec; base += stride) {
+    // all of the step's loads first; most steps hold no element of the bracket.  `in`
+    // has a bit per element of this lane inside the bracket (bitwise tests: no branches).
+    Vec raw[U];
+    uint32_t in = 0;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t vi = base + (int64_t)u * per_u + me;
-      const bool valid = vi < sp.nvec;
-      Vec raw;
-      if (valid) raw = sp.V[vi];
+      const bool vld = vi < sp.nvec;
+      raw[u] = vld ? sp.V[vi] : Vec{};
       T e[V];
-      vec_to_arr<T>(raw, e);
+      vec_to_arr<T>(raw[u], e);
+#pragma unroll
+      for (int j = 0; j < V; ++j)
+        in |= (uint32_t)(vld & (e[j] > yL) & (e[j] < yR)) << (u * V + j);
+    }
+    if (ballot(in != 0) == 0) continue;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      T e[V];
+      vec_to_arr<T>(raw[u], e);
       uint32_t cnt = 0;
 #pragma unroll
-      for (int j = 0; j < V; ++j) cnt += popc(ballot(valid && e[j] > yL && e[j] < yR));
+      for (int j = 0; j < V; ++j) cnt += popc(ballot((in >> (u * V + j)) & 1u));
       if (cnt == 0) continue;
       uint64_t off = 0;
       if (lane == 0) off = atomic_add_relaxed(gcur, cnt);
@@ -380,9 +392,9 @@ __device__ inline void gather_walk(const Walk<T> &wk, T yL, T yR, T *zf, uint64_
       written += cnt;
 #pragma unroll
       for (int j = 0; j < V; ++j) {
-        const bool in = valid && e[j] > yL && e[j] < yR;
-        const uint64_t m = ballot(in);
-        if (in) zf[off + lane_rank(m)] = e[j];
+        const bool sel = (in >> (u * V + j)) & 1u;
+        const uint64_t m = ballot(sel);
+        if (sel) zf[off + lane_rank(m)] = e[j];
         off += popc(m);
       }
     }
@@ -417,8 +429,12 @@ __device__ inline void hist_tile(const Span<T> &sp, int64_t base, int per_u, int
   for (int u = 0; u < U; ++u) {
     const int64_t vi = base + (int64_t)u * per_u + me;
     valid[u] = FULL || vi < sp.nvec;
+    raw[u] = Vec{};
     if (valid[u]) raw[u] = sp.V[vi];
   }
+  // keys and range tests first: after the first narrowing most elements of a tile lie
+  // outside the bracket, and a wavefront with none in range skips the counting
+  uint32_t in = 0;  // a bit per element of this lane in range (bitwise tests: no branches)
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     T e[V];
@@ -426,7 +442,18 @@ __device__ inline void hist_tile(const Span<T> &sp, int64_t base, int per_u, int
 #pragma unroll
     for (int j = 0; j < V; ++j) {
       const Key K = Traits<T>::key(e[j]);
-      if (valid[u] && K >= klo && K <= khi) atomicAdd(&rh[(uint32_t)((K - klo) >> shift)], 1u);
+      in |= (uint32_t)(valid[u] & (K >= klo) & (K <= khi)) << (u * V + j);
+    }
+  }
+  if (ballot(in != 0) == 0) return;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    T e[V];
+    vec_to_arr<T>(raw[u], e);
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const Key K = Traits<T>::key(e[j]);
+      if ((in >> (u * V + j)) & 1u) atomicAdd(&rh[(uint32_t)((K - klo) >> shift)], 1u);
     }
   }
 }
@@ -639,7 +666,7 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
     }
   } else if (s.phase == PH_GATHER) {
     if (s.wbuf < 0 || s.filter) {
-      gather_walk<T, BLOCK, SU>(wk, yL, yR, a.zf, &a.sync->gcur, written);
+      gather_walk<T, BLOCK, UNROLL>(wk, yL, yR, a.zf, &a.sync->gcur, written);
     } else {
       // every element of a segment lies inside the bracket: one offset per workgroup
       const int64_t len = wk.sp.m;
