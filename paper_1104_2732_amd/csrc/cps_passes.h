@@ -164,6 +164,16 @@ __device__ inline void block_reduce(double (&dv)[8], const int (&dop)[8], int64_
   __syncthreads();
 }
 
+// Fold (min, multiplicity) and (max, multiplicity) pairs over the wavefront: the extreme
+// first, then the multiplicities of the lanes that hold it.  Every lane gets the result.
+__device__ inline void wave_pair_fold(double &mn, int64_t &cmn, double &mx, int64_t &cmx) {
+  const double wm = wave_min(mn), wx = wave_max(mx);
+  cmn = wave_sum_i64(mn == wm ? cmn : 0);
+  cmx = wave_sum_i64(mx == wx ? cmx : 0);
+  mn = wm;
+  mx = wx;
+}
+
 // Fold (min, multiplicity) and (max, multiplicity) pairs over the workgroup; valid in
 // thread 0.
 template <int BLOCK>
@@ -171,13 +181,7 @@ __device__ inline void block_pair_fold(double &mn, int64_t &cmn, double &mx, int
                                        double (&sd)[8][BLOCK / kWave],
                                        int64_t (&si)[8][BLOCK / kWave]) {
   const int tid = threadIdx.x, wv = tid / kWave, lane = tid % kWave;
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) {
-    const double m2 = __shfl_xor(mn, o), x2 = __shfl_xor(mx, o);
-    const int64_t c2 = __shfl_xor(cmn, o), d2 = __shfl_xor(cmx, o);
-    if (m2 < mn) { mn = m2; cmn = c2; } else if (m2 == mn) cmn += c2;
-    if (x2 > mx) { mx = x2; cmx = d2; } else if (x2 == mx) cmx += d2;
-  }
+  wave_pair_fold(mn, cmn, mx, cmx);
   if (lane == 0) {
     sd[0][wv] = mn; si[0][wv] = cmn; sd[1][wv] = mx; si[1][wv] = cmx;
   }

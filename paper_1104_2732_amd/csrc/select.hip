@@ -758,24 +758,25 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
   int pidx = 0;  // index of the pass that just ended
   double rd[8];
   int64_t ri[8];
-  int rop[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (phase == PH_PASS0) {
-    for (int f = 0; f < 8; ++f) { rd[f] = 0; ri[f] = 0; }
-    for (int b = tid; b < G; b += BLOCK) {
-      for (int f = 0; f < 5; ++f) rd[f] += a.sd[f * stride + b];
-      for (int f = 0; f < 6; ++f) ri[f] += a.si[f * stride + b];
-    }
-    block_reduce<BLOCK, 5, 6>(rd, rop, ri, false, sh.d, sh.i);
-    // (min, count) and (max, count) pairs: strided fold per thread, then a fixed tree
+    // the first wavefront folds the partials: lane l takes workgroups l, l + 64, ... in
+    // order, then the wavefront's fixed tree (deterministic); no workgroup barrier
     double mn = __builtin_inf(), mx = -__builtin_inf();
     int64_t cmn = 0, cmx = 0;
-    for (int b = tid; b < G; b += BLOCK) {
-      const double m2 = a.sd[5 * stride + b], x2 = a.sd[6 * stride + b];
-      const int64_t c2 = a.si[6 * stride + b], d2 = a.si[7 * stride + b];
-      if (m2 < mn) { mn = m2; cmn = c2; } else if (m2 == mn) cmn += c2;
-      if (x2 > mx) { mx = x2; cmx = d2; } else if (x2 == mx) cmx += d2;
+    if (tid < kWave) {
+      for (int f = 0; f < 8; ++f) { rd[f] = 0; ri[f] = 0; }
+      for (int b = tid; b < G; b += kWave) {
+        for (int f = 0; f < 5; ++f) rd[f] += a.sd[f * stride + b];
+        for (int f = 0; f < 6; ++f) ri[f] += a.si[f * stride + b];
+        const double m2 = a.sd[5 * stride + b], x2 = a.sd[6 * stride + b];
+        const int64_t c2 = a.si[6 * stride + b], d2 = a.si[7 * stride + b];
+        if (m2 < mn) { mn = m2; cmn = c2; } else if (m2 == mn) cmn += c2;
+        if (x2 > mx) { mx = x2; cmx = d2; } else if (x2 == mx) cmx += d2;
+      }
+      for (int f = 0; f < 5; ++f) rd[f] = wave_sum(rd[f]);
+      for (int f = 0; f < 6; ++f) ri[f] = wave_sum_i64(ri[f]);
+      wave_pair_fold(mn, cmn, mx, cmx);
     }
-    block_pair_fold<BLOCK>(mn, cmn, mx, cmx, sh.d, sh.i);
     if (tid == 0) {
       Pass0Result r;
       r.classified = p0_slow ? 1 : 0;
@@ -828,20 +829,27 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
       pg[0] = split_part_geometry(sh.st, 0, a.cfg);
       pg[1] = split_part_geometry(sh.st, 1, a.cfg);
     }
-    rop[2] = 2; rop[3] = 1;
-    for (int f = 0; f < 8; ++f) { rd[f] = 0; ri[f] = 0; }
-    rd[2] = -__builtin_inf();
-    rd[3] = __builtin_inf();
-    for (int b = tid; b < G; b += BLOCK) {
-      rd[0] += a.sd[0 * stride + b];
-      rd[1] += a.sd[1 * stride + b];
-      rd[2] = fmax(rd[2], a.sd[2 * stride + b]);
-      rd[3] = fmin(rd[3], a.sd[3 * stride + b]);
-      ri[0] += a.si[0 * stride + b];
-      ri[1] += a.si[1 * stride + b];
-      ri[2] += a.si[2 * stride + b];
+    __syncthreads();  // every thread has read the state before thread 0 advances it
+    // the first wavefront folds the partials (as after pass 0)
+    if (tid < kWave) {
+      for (int f = 0; f < 8; ++f) { rd[f] = 0; ri[f] = 0; }
+      rd[2] = -__builtin_inf();
+      rd[3] = __builtin_inf();
+      for (int b = tid; b < G; b += kWave) {
+        rd[0] += a.sd[0 * stride + b];
+        rd[1] += a.sd[1 * stride + b];
+        rd[2] = fmax(rd[2], a.sd[2 * stride + b]);
+        rd[3] = fmin(rd[3], a.sd[3 * stride + b]);
+        ri[0] += a.si[0 * stride + b];
+        ri[1] += a.si[1 * stride + b];
+        ri[2] += a.si[2 * stride + b];
+      }
+      rd[0] = wave_sum(rd[0]);
+      rd[1] = wave_sum(rd[1]);
+      rd[2] = wave_max(rd[2]);
+      rd[3] = wave_min(rd[3]);
+      for (int f = 0; f < 3; ++f) ri[f] = wave_sum_i64(ri[f]);
     }
-    block_reduce<BLOCK, 4, 3>(rd, rop, ri, false, sh.d, sh.i);
     if (tid == 0) {
       CpState &s = sh.st;
       pidx = s.work_passes;
