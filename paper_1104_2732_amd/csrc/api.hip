@@ -143,6 +143,7 @@ int resolve(cps_handle *h, int64_t n, int dtype, const cps_options *opt, Resolve
   r.cfg.bracket_lo = o.bracket_lo;
   r.cfg.bracket_hi = o.bracket_hi;
   r.cfg.hist_bits = o.hist_bits;
+  r.cfg.hist_compact = 1;  // the single-array kernel compacts in its histogram passes
   const int per_cu = dtype == CPS_F32 ? h->max_blocks_f32 : h->max_blocks_f64;
   const int gmax = h->cu_count * per_cu;
   if (gmax < 1) return CPS_ENODEV;

@@ -69,7 +69,8 @@ struct CpConfig {
   int64_t split_cap;        // the first split needs population <= split_cap (0 = no limit)
   int32_t hist_bits;        // exact select on the compacted bracket by key histograms of
                             // 2^hist_bits bins (0: cutting-plane passes to the end)
-  int32_t pad1;
+  int32_t hist_compact;     // histogram passes may also compact a narrowed bracket's
+                            // elements into the other split buffer (kernels that do so)
 };
 
 // Results of pass 0 over the whole input (Section 4, step 0: min, max and sum in
@@ -130,6 +131,9 @@ struct CpState {
   int64_t final_size;
   int32_t bracket_used;
   int32_t p0_slow;         // pass 0 must classify infinities (the fast pass saw one)
+  int32_t compact;         // the histogram pass about to run also copies the bracket's
+                           // elements to split buffer zout (low parts)
+  int32_t pad0;
 };
 
 static_assert(sizeof(CpState) % 8 == 0, "state is copied in 8-byte words");
@@ -249,6 +253,7 @@ CPS_HD inline void cp_plan(CpState &s, const CpConfig &c) {
   }
   s.split = 0;
   s.filter = 0;
+  s.compact = 0;
   if (pop <= c.final_threshold) {
     if (s.wbuf < 0 && s.wlen <= c.final_direct_max) {
       s.phase = PH_FINAL;  // small input: select straight from x, keeping (yL, yR) only
@@ -261,8 +266,14 @@ CPS_HD inline void cp_plan(CpState &s, const CpConfig &c) {
   }
   if (c.hist_bits > 0 && (s.on_bracket || s.narrowed) && s.wbuf >= 0) {
     // the bracket's elements are compacted: finish with the exact select by key
-    // histograms over them (the paper sorts the compacted elements instead)
+    // histograms over them (the paper sorts the compacted elements instead).  When a
+    // narrowed bracket holds at most a quarter of the working set, the pass also copies
+    // the bracket's elements to the other split buffer, so later passes read only those.
     s.phase = PH_HIST;
+    if (c.hist_compact && !s.on_bracket && s.wbuf < 2 && pop * 4 <= s.wlen) {
+      s.compact = 1;
+      s.zout = 1 - s.wbuf;
+    }
     return;
   }
   if (s.on_bracket) {
@@ -529,7 +540,18 @@ CPS_HD inline void cp_after_hist(CpState &s, int32_t b, int64_t below, int64_t c
   s.work_passes++;
   if (s.wbuf < 0) s.passes++;
   s.elements_read += s.wlen;
-  cp_hist_narrow(s, hist_geometry(s.lo, s.hi, c.dtype, c.hist_bits), b, below, cnt, c);
+  const HistGeom<uint64_t> g = hist_geometry(s.lo, s.hi, c.dtype, c.hist_bits);
+  if (s.compact) {
+    // the pass copied the elements inside the bracket, cR - cL of them, to buffer zout:
+    // they are the working set from now on
+    s.compact = 0;
+    s.wbuf = s.zout;
+    s.side = 0;
+    s.wlen = s.cR - s.cL;
+    s.on_bracket = 1;
+    s.elements_written += s.wlen;
+  }
+  cp_hist_narrow(s, g, b, below, cnt, c);
 }
 
 // Key bins of the two parts of a split at the planned trial point t, for a split pass that

@@ -416,10 +416,10 @@ __device__ inline void gather_walk(const Walk<T> &wk, T yL, T yR, T *zf, uint64_
 
 // Histogram pass: every element of the walk whose ordered key lies in [klo, khi] is counted
 // in LDS bin (key - klo) >> shift.
-template <typename T, int U, bool FULL>
+template <typename T, int U, bool COMPACT, bool FULL>
 __device__ inline void hist_tile(const Span<T> &sp, int64_t base, int per_u, int me,
                                  typename Traits<T>::Key klo, typename Traits<T>::Key khi,
-                                 int shift, uint32_t *rh) {
+                                 int shift, uint32_t *rh, WaveOut<T> &o) {
   constexpr int V = Traits<T>::kVec;
   using Vec = typename Traits<T>::Vec;
   using Key = typename Traits<T>::Key;
@@ -446,6 +446,7 @@ __device__ inline void hist_tile(const Span<T> &sp, int64_t base, int per_u, int
     }
   }
   if (ballot(in != 0) == 0) return;
+  const int lane = me % kWave;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     T e[V];
@@ -453,14 +454,26 @@ __device__ inline void hist_tile(const Span<T> &sp, int64_t base, int per_u, int
 #pragma unroll
     for (int j = 0; j < V; ++j) {
       const Key K = Traits<T>::key(e[j]);
-      if ((in >> (u * V + j)) & 1u) atomicAdd(&rh[(uint32_t)((K - klo) >> shift)], 1u);
+      if ((in >> (u * V + j)) & 1u) {
+        atomicAdd(&rh[(uint32_t)((K - klo) >> shift)], 1u);
+        if (COMPACT) {  // into this lane's staging column (low part)
+          o.ring_lo[(o.cl & (Stage<T>::kS - 1)) * kWave + lane] = e[j];
+          o.cl += 1;
+        }
+      }
+    }
+    if (COMPACT) {  // at most kV new elements per lane since the last call
+      __builtin_amdgcn_wave_barrier();
+      flush_part<T, false>(o, o.ring_lo, o.cl, o.fl, lane);
+      __builtin_amdgcn_wave_barrier();
     }
   }
 }
 
-template <typename T, int BLOCK, int U>
+template <typename T, int BLOCK, int U, bool COMPACT>
 __device__ inline void hist_walk(const Walk<T> &wk, typename Traits<T>::Key klo,
-                                 typename Traits<T>::Key khi, int shift, uint32_t *rh) {
+                                 typename Traits<T>::Key khi, int shift, uint32_t *rh,
+                                 WaveOut<T> &o) {
   using Key = typename Traits<T>::Key;
   const int tid = threadIdx.x, lane = tid % kWave;
   const Span<T> &sp = wk.sp;
@@ -471,16 +484,19 @@ __device__ inline void hist_walk(const Walk<T> &wk, typename Traits<T>::Key klo,
   const int per_u = wk.wave_mode ? kWave : BLOCK;
   for (int64_t base = first; base < sp.nvec; base += stride) {
     if (base + (int64_t)U * per_u <= sp.nvec)
-      hist_tile<T, U, true>(sp, base, per_u, me, klo, khi, shift, rh);
+      hist_tile<T, U, COMPACT, true>(sp, base, per_u, me, klo, khi, shift, rh, o);
     else
-      hist_tile<T, U, false>(sp, base, per_u, me, klo, khi, shift, rh);
+      hist_tile<T, U, COMPACT, false>(sp, base, per_u, me, klo, khi, shift, rh, o);
   }
   if (sp.nedge > 0 && wk.edge_owner && (wk.wave_mode || tid < kWave)) {
-    if (lane < sp.nedge) {
-      const Key K = Traits<T>::key(sp.W[edge_index(sp, lane)]);
-      if (K >= klo && K <= khi) atomicAdd(&rh[(uint32_t)((K - klo) >> shift)], 1u);
-    }
+    const bool have = lane < sp.nedge;
+    const T v = have ? sp.W[edge_index(sp, lane)] : T(0);
+    const Key K = Traits<T>::key(v);
+    const bool in = have && K >= klo && K <= khi;
+    if (in) atomicAdd(&rh[(uint32_t)((K - klo) >> shift)], 1u);
+    if (COMPACT) stage_one<T>(v, in, o.ring_lo, o.cl, lane);
   }
+  if (COMPACT) split_drain<T>(o, lane);
 }
 
 // The bin holding rank r of a histogram's counts: an exclusive scan of the counts in a fixed
@@ -657,8 +673,28 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
     const HistGeom<uint64_t> g = hist_geometry(s.lo, s.hi, a.cfg.dtype, a.cfg.hist_bits);
     for (int b = tid; b < g.nbins; b += BLOCK) sh.rh[b] = 0u;
     __syncthreads();
-    hist_walk<T, BLOCK, UNROLL>(wk, (typename Traits<T>::Key)g.klo, (typename Traits<T>::Key)g.khi,
-                                g.shift, sh.rh);
+    WaveOut<T> o;
+    o.lo = o.hi = o.cl = o.ch = o.fl = o.fh = 0;
+    if (s.compact) {  // the bracket's elements also go to this wavefront's region of zout
+      const int wvu = __builtin_amdgcn_readfirstlane(wv);
+      o.region = (CPS_GLOBAL T *)uniform_ptr(a.z[s.zout] + ((int64_t)bid * WPB + wvu) * Rw);
+      o.top = (uint32_t)(Rw - 1);
+      o.ring_lo = sh.ring[wv][0];
+      o.ring_hi = sh.ring[wv][1];
+      hist_walk<T, BLOCK, UNROLL, true>(wk, (typename Traits<T>::Key)g.klo,
+                                        (typename Traits<T>::Key)g.khi, g.shift, sh.rh, o);
+      if (lane == 0) {
+        sh.wseg[0][wv] = o.lo;
+        sh.wseg[1][wv] = 0;
+        written = o.lo;
+      }
+    } else {
+      o.region = nullptr;
+      o.top = 0;
+      o.ring_lo = o.ring_hi = nullptr;
+      hist_walk<T, BLOCK, UNROLL, false>(wk, (typename Traits<T>::Key)g.klo,
+                                         (typename Traits<T>::Key)g.khi, g.shift, sh.rh, o);
+    }
     __syncthreads();
     for (int b = tid; b < g.nbins; b += BLOCK) {
       const uint32_t c = sh.rh[b];

@@ -39,6 +39,7 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
   c.bracket_hi = bhi;
   c.p0_split = p0_split;
   c.hist_bits = hist_bits;
+  c.hist_compact = 1;  // as the single-array kernel
   // one workgroup: a single region per split buffer, as large as the input
   const int64_t R = n + 8;
   std::vector<T> z[2] = {std::vector<T>(R), std::vector<T>(R)};
@@ -108,9 +109,18 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
       // rank k - cL
       const HistGeom<uint64_t> g = hist_geometry(s.lo, s.hi, c.dtype, c.hist_bits);
       std::vector<int64_t> h((size_t)g.nbins, 0);
+      int64_t nc = 0;  // elements copied when the pass also compacts the bracket
       for (int64_t i = 0; i < wl; i++) {
         const uint64_t K = sizeof(T) == 4 ? (uint64_t)key32((float)W[i]) : key64((double)W[i]);
-        if (K >= g.klo && K <= g.khi) h[(size_t)((K - g.klo) >> g.shift)]++;
+        if (K >= g.klo && K <= g.khi) {
+          h[(size_t)((K - g.klo) >> g.shift)]++;
+          if (s.compact) z[s.zout][nc++] = W[i];
+        }
+      }
+      if (s.compact) {
+        if (nc != s.cR - s.cL) return -19;  // the key range holds exactly the bracket's elements
+        my_l = nc;
+        my_r = 0;
       }
       const int64_t r = s.k - s.cL;
       int64_t below = 0;
