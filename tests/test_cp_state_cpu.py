@@ -171,3 +171,19 @@ def test_histogram_finish_cuts_passes(sim):
     plain = sim(x, (n + 1) // 2, final_threshold=4096)
     hist = sim(x, (n + 1) // 2, final_threshold=4096, hist_bits=12)
     assert hist.work_passes < plain.work_passes and hist.work_passes <= 7
+
+
+@pytest.mark.parametrize("dist", ["normal", "uniform", "cauchy", "quantized_normal"])
+def test_counted_split_and_compaction(sim, oracle_mod, dist):
+    """Splitting from the first trial point with the histogram finish: the split counts
+    both parts in key bins, so the part holding x_(k) narrows without a pass of its own,
+    and a narrowed bracket far smaller than its part is compacted by the histogram pass
+    that follows.  Values stay exact; the passes read at most three inputs' worth (pass 0,
+    the split, and one pass over the part that holds x_(k))."""
+    n = 1 << 20
+    x = workloads.single_array(dist, n, np.float32, seed=11)
+    for k in (n // 100, (n + 1) // 2, n - n // 100):
+        r = sim(x, k, final_threshold=8192, theta=1.0, hist_bits=12)
+        _check(r, oracle_mod.select_kth(x, k), (dist, k))
+        assert r.elements_read <= 3 * n, (dist, k, r.elements_read / n)
+        assert r.work_passes <= 5, (dist, k, r.work_passes)
