@@ -13,7 +13,9 @@ the plain single-array method on the same GPU (their own keys in the line):
 "batched" (4096 lognormal arrays of log-uniform sizes in one graph-captured
 launch vs a loop of single-array calls), "lms" (1024 least-median-of-squares
 candidates over 2^20 rows) and "learned" (the learned bracket proposal vs the
-plain method on held-out 2^26-element mixture arrays; training untimed).
+plain method on held-out 2^26-element mixture arrays; training untimed).  A
+fourth, "schedules", times the method under three schedules of its compaction
+(cutting-plane passes to the end, split after one evaluation, the default).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 
@@ -223,6 +225,38 @@ def learned_leg(sel, cps, torch, reps: int = 5) -> dict:
                       "holdout_width": rep["holdout_width"]}}
 
 
+def schedules_leg(sel, cps, torch, reps: int = 3) -> dict:
+    """The same selections under three schedules of the method on 2^28 normal arrays:
+    cutting-plane passes until the bracket holds at most the final threshold, then the
+    gather and the exact select (no split, no histograms); the split after one evaluation
+    pass (partition fraction 0.75); and the default (split at the first trial point)."""
+    import workloads
+    scheds = {"cutting_plane_to_the_end": dict(partition_fraction=0.0, hist_bits=0),
+              "split_after_one_evaluation": dict(partition_fraction=0.75),
+              "default_split_at_first_trial_point": dict()}
+    out = {"workload": "n=2^28 N(0,1), k in {n/100, median}", "cases": {}}
+    res = sel.new_results(1)
+    stats = sel.new_stats()
+    for dtype in DTYPES:
+        n = 1 << 28
+        x = workloads.single_array("normal", n, dtype, seed=0, tag="bench")
+        xt = torch.from_numpy(x).cuda()
+        del x
+        for k in (n // 100, (n + 1) // 2):
+            for name, kw in scheds.items():
+                o = cps.default_options(**kw)
+                ms = _time_ms(torch, lambda: sel.select_kth_async(xt, k, res, options=o), reps)
+                sel.select_kth_async(xt, k, res, stats, options=o)
+                torch.cuda.synchronize()
+                st = stats.cpu().numpy().view(cps.STATS_DTYPE)[0]
+                out["cases"][f"{np.dtype(dtype).name} k={k} {name}"] = {
+                    "ms": round(ms, 4), "passes_over_x": int(st["passes"]),
+                    "work_passes": int(st["work_passes"]), "kelley_steps": int(st["kelley_steps"])}
+        del xt
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(budget_s: float = 20.0):
     """The CPU oracle on a bounded sample of the same workload, one thread, ~budget_s seconds:
     the 32 n=2^24 cases, then n=2^28 float32 cases while the budget lasts."""
@@ -399,6 +433,8 @@ def main():
         line["lms"] = lms_leg(sel, torch)
         torch.cuda.empty_cache()
         line["learned"] = learned_leg(sel, cps, torch)
+        torch.cuda.empty_cache()
+        line["schedules"] = schedules_leg(sel, cps, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

@@ -83,3 +83,27 @@ def test_lms_full_size_sampled(sel, oracle_mod):
     # the estimate: the candidate with the least median of squares fits the clean rows
     best = int(np.argmin(res["value"]))
     assert np.max(np.abs(betas[best] - beta)) < 0.5
+
+
+def test_lms_nonfinite_residuals(sel, oracle_mod):
+    """Step 0 taken inside the residual kernel classifies +inf (rows whose residual
+    overflows) and NaN (a NaN in y) as the selection's own pass 0 does."""
+    import oracle
+    import paper_1104_2732_amd as cps
+    rng = np.random.default_rng(17)
+    n, p, m = 2001, 4, 11
+    X = rng.standard_normal((n, p))
+    y = rng.standard_normal(n)
+    betas = rng.standard_normal((m, p))
+    X[rng.choice(n, size=40, replace=False)] *= 1e200  # residuals overflow to +inf
+    print("case lms +inf residuals", flush=True)
+    res = sel.lms_median_sq_residuals(_dev(X), _dev(y), _dev(betas))
+    ref = oracle_mod.lms_median_sq(X, y, betas)
+    for c in range(m):
+        assert_same_result({f: res[c][f].item() for f in res.dtype.names}, ref[c], f"candidate {c}")
+    y[5] = np.nan
+    print("case lms NaN residuals", flush=True)
+    res = sel.lms_median_sq_residuals(_dev(X), _dev(y), _dev(betas))
+    assert np.all(res["status"] == cps.STATUS_NAN)
+    with pytest.raises(oracle.OracleError):
+        oracle_mod.lms_median_sq(X, y, betas)
