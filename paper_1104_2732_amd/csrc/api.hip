@@ -386,7 +386,9 @@ int cps_autotune_batched(cps_handle *h, const void *const *ptrs_dev, const int64
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   const int blocks[3] = {256, 512, 1024};
-  const int64_t caps[3] = {(int64_t)1 << 15, (int64_t)1 << 17, (int64_t)1 << 19};
+  constexpr int kCaps = 4;
+  const int64_t caps[kCaps] = {(int64_t)1 << 15, (int64_t)1 << 17, (int64_t)1 << 19,
+                               (int64_t)1 << 20};
   const double fracs[2] = {0.5, 1.0};
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return CPS_EHIP;
@@ -395,13 +397,13 @@ int cps_autotune_batched(cps_handle *h, const void *const *ptrs_dev, const int64
   cps_default_batch_options(&best_o);
   int last_rc = CPS_OK;
   for (int b : blocks) {
-    for (int ci = 0; ci < 6 && !last_rc; ++ci) {
-      const int64_t c = caps[ci % 3];
+    for (int ci = 0; ci < 2 * kCaps && !last_rc; ++ci) {
+      const int64_t c = caps[ci % kCaps];
       cps_batch_options o;
       cps_default_batch_options(&o);
       o.block_threads = b;
       o.split_capacity = c;
-      o.partition_fraction = fracs[ci / 3];
+      o.partition_fraction = fracs[ci / kCaps];
       rc = select_kth_batched_ex(h, ptrs_dev, sizes_dev, ks_dev, count, dtype, &o, out_dev, stream);
       if (rc == CPS_ENOMEM) continue;  // this candidate's workspace does not fit
       if (rc) { last_rc = rc; break; }

@@ -186,3 +186,25 @@ def test_histogram_finish_signed_zeros_and_denormals(sel, oracle_mod, dtype):
                 res = _run(sel, x, k, f"zeros trial {trial}", final_threshold=1,
                            partition_fraction=1.0, hist_bits=hb)
                 assert_same_result(res, ref, (trial, k, hb))
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_default_path_counted_split_and_compaction(sel, oracle_mod, dtype):
+    """The default path at a few million elements: the split at the first trial point
+    counts both parts in key bins, the part that holds x_(k) narrows at once, a histogram
+    pass compacts a narrowed bracket, the gather and the final select end it.  Includes a
+    spike (90 % of the elements equal) and integer data, so narrowed brackets hold many
+    equal keys."""
+    n = (1 << 22) + 17
+    rng = np.random.default_rng(21)
+    spike = np.where(rng.random(n) < 0.9, 1.0, rng.standard_normal(n)).astype(dtype)
+    cases = [(d, workloads.single_array(d, n, dtype, seed=5, tag="gpu-default"))
+             for d in ("normal", "lognormal", "quantized_normal", "smallint")]
+    cases.append(("spike", spike))
+    for dist, x in cases:
+        xt = _dev(x)
+        for k in (1 + n // 100, n // 3, (n + 1) // 2, n - n // 100):
+            print(f"case default-path {dist} n={n} k={k} dtype={x.dtype}", flush=True)
+            res, st = sel.select_kth(xt, k, stats=True)
+            assert_same_result(res, oracle_mod.select_kth(x, k), f"{dist} k={k}")
+            assert st["passes"] <= 4, (dist, k, st["passes"])
