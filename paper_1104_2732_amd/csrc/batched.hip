@@ -36,11 +36,10 @@ template <typename T, int BLOCK> struct BShared {
   CpState st;
   double d[8][BLOCK / kWave];
   int64_t i[8][BLOCK / kWave];
-  uint32_t wcnt[2][BLOCK / kWave];
-  uint64_t wbase[2][BLOCK / kWave];
   uint32_t hist[256];
   int64_t misc[8];
   int64_t cur[2];
+  uint64_t wsum[BLOCK / kWave];  // wavefront totals of a workgroup scan
   int64_t job;
   uint64_t order[kBatchSortMax];  // (size << 12 | index), sorted by size, largest first
   uint32_t rh[kHistMaxBins];      // key histogram of a histogram pass
@@ -48,13 +47,17 @@ template <typename T, int BLOCK> struct BShared {
 
 // Split (or gather) one tile's elements into this workgroup's buffer: the low side grows
 // up from out[0], the high side down from out[cap-1].  GATHER: every valid element inside
-// (lo_ex, hi_ex) goes low.  Two workgroup barriers per tile; the cursors live in LDS.
+// (lo_ex, hi_ex) goes low.  Each wavefront reserves its place on either side with one LDS
+// atomic on the workgroup's cursors, so no workgroup barrier is needed; the order of the
+// elements in the buffer follows the wavefronts' arrival, which nothing downstream depends
+// on (the histograms, the gather and the final select are order-free; sums over a part only
+// position later trial points).
 template <typename T, int BLOCK, int U, bool FILTER, bool GATHER>
 __device__ inline void block_split_tile(const T (&e)[U][Traits<T>::kVec], const bool (&valid)[U],
                                         int nslot, T t, T lo_ex, T hi_ex, CPS_GLOBAL T *out,
                                         int64_t cap, BShared<T, BLOCK> &sh) {
   constexpr int V = Traits<T>::kVec;
-  const int tid = threadIdx.x, wv = tid / kWave, lane = tid % kWave;
+  const int tid = threadIdx.x, lane = tid % kWave;
   auto low = [&](T v, bool ok) -> bool {
     if (GATHER) return ok && (!FILTER || (v > lo_ex && v < hi_ex));
     return ok && v < t && (!FILTER || v > lo_ex);
@@ -72,37 +75,14 @@ __device__ inline void block_split_tile(const T (&e)[U][Traits<T>::kVec], const 
       wl += popc(ballot(low(e[u][j], valid[u])));
       wr += popc(ballot(high(e[u][j], valid[u])));
     }
+  if (wl == 0 && wr == 0) return;  // wave-uniform
+  uint64_t ol = 0, orr = 0;
   if (lane == 0) {
-    sh.wcnt[0][wv] = wl;
-    sh.wcnt[1][wv] = wr;
+    if (wl) ol = atomicAdd(reinterpret_cast<unsigned long long *>(&sh.cur[0]), (unsigned long long)wl);
+    if (wr) orr = atomicAdd(reinterpret_cast<unsigned long long *>(&sh.cur[1]), (unsigned long long)wr);
   }
-  __syncthreads();
-  if (wv == 0) {
-    // exclusive scan of the wavefronts' counts in wavefront order, by the first wavefront
-    constexpr int WPB = BLOCK / kWave;
-    const uint64_t cl = lane < WPB ? sh.wcnt[0][lane] : 0u;
-    const uint64_t cr = lane < WPB ? sh.wcnt[1][lane] : 0u;
-    uint64_t il = cl, ir = cr;
-#pragma unroll
-    for (int o = 1; o < WPB; o <<= 1) {
-      const uint64_t ul = __shfl_up(il, o), ur = __shfl_up(ir, o);
-      if (lane >= o) {
-        il += ul;
-        ir += ur;
-      }
-    }
-    const uint64_t bl = (uint64_t)sh.cur[0], br = (uint64_t)sh.cur[1];
-    if (lane < WPB) {
-      sh.wbase[0][lane] = bl + il - cl;
-      sh.wbase[1][lane] = br + ir - cr;
-    }
-    if (lane == WPB - 1) {
-      sh.cur[0] = (int64_t)(bl + il);
-      sh.cur[1] = (int64_t)(br + ir);
-    }
-  }
-  __syncthreads();
-  uint64_t ol = sh.wbase[0][wv], orr = sh.wbase[1][wv];
+  ol = __shfl(ol, 0);
+  orr = __shfl(orr, 0);
 #pragma unroll
   for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -119,7 +99,6 @@ __device__ inline void block_split_tile(const T (&e)[U][Traits<T>::kVec], const 
         orr += popc(mr);
       }
     }
-  __syncthreads();
 }
 
 // One evaluation pass of this workgroup over span sp, optionally splitting into `out`.
@@ -358,7 +337,7 @@ __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out,
         hv[j] = b < g.nbins ? sh.rh[b] : 0u;
         tot += hv[j];
       }
-      uint64_t cum = block_exclusive_scan<BLOCK>(tot, &sh.wbase[0][0]);
+      uint64_t cum = block_exclusive_scan<BLOCK>(tot, sh.wsum);
 #pragma unroll
       for (int j = 0; j < BPT; ++j) {
         if (cum < r && r <= cum + hv[j]) {
