@@ -368,11 +368,14 @@ int lms_median_sq_residuals(cps_handle *h, const double *X_dev, const double *y_
   }
   char *base = (char *)h->lws;
   // every candidate's array has n elements: split buffers that hold a whole array let the
-  // first cutting-plane step that leaves at most the split fraction of n compact it
+  // first cutting-plane step that leaves at most the split fraction of n compact it (0.75,
+  // measured: the outliers put the first trial point high, and splitting after the second
+  // evaluation writes least)
   cps_batch_options o;
   cps_default_batch_options(&o);
   o.block_threads = 1024;
   o.split_capacity = n < 64 ? 64 : n;
+  o.partition_fraction = 0.75;
   return select_kth_batched_ex(h, (const void *const *)(base + off_desc),
                                (const int64_t *)(base + off_desc + align_up((size_t)m * 8, 256)),
                                (const int64_t *)(base + off_desc + 2 * align_up((size_t)m * 8, 256)),
