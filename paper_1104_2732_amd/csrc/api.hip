@@ -35,6 +35,7 @@ struct cps_handle {
   void *mws = nullptr;  // per-workgroup gradient partials of the proposal network
   size_t mws_bytes = 0;
   double *bracket = nullptr;  // the learned proposal handed to the selection (a, b, use)
+  uint64_t *phist = nullptr;  // counters of the proposal's interior (same allocation)
   cps_batch_options tuned[2];
   bool has_tuned[2] = {false, false};
   std::mutex mu;
@@ -205,6 +206,8 @@ int run_select(cps_handle *h, const T *x, int64_t n, int64_t k, const cps_option
   a.cfg = r.cfg;
   a.spin_limit = r.spin_limit;
   a.bracket = bracket_dev;
+  // the proposal kernel that wrote bracket_dev also cleared the interior's counters
+  a.phist = (bracket_dev != nullptr && bracket_dev == h->bracket) ? h->phist : nullptr;
   // a proposed bracket's interior may take up to half of each wavefront's region in pass 0
   // (past about two thirds of the input, the passes over x that compaction would spare
   // cost less than reading the compacted elements again)
@@ -496,12 +499,13 @@ int cps_create(int device, cps_handle **out) {
     delete h;
     return CPS_ENODEV;
   }
-  e = hipMalloc(&h->bracket, 4 * sizeof(double));
+  e = hipMalloc(&h->bracket, 256 + cps::kHistMaxBins * sizeof(uint64_t));
   if (e != hipSuccess) {
     delete h;
     g_last_hip = (int)e;
     return CPS_ENOMEM;
   }
+  h->phist = (uint64_t *)((char *)h->bracket + 256);
   *out = h;
   return CPS_OK;
 }
@@ -653,9 +657,10 @@ int cps_learned_bracket(cps_handle *h, const void *x, int64_t n, int64_t k, int 
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
   if (dtype == CPS_F32)
-    e = cps::launch_learned_bracket<float>((const float *)x, n, k, params_dev, bracket_dev, s);
+    e = cps::launch_learned_bracket<float>((const float *)x, n, k, params_dev, nullptr, bracket_dev, s);
   else
-    e = cps::launch_learned_bracket<double>((const double *)x, n, k, params_dev, bracket_dev, s);
+    e = cps::launch_learned_bracket<double>((const double *)x, n, k, params_dev, nullptr, bracket_dev,
+                                            s);
   return e == hipSuccess ? CPS_OK : hip_fail(e);
 }
 
@@ -669,9 +674,11 @@ int select_kth_learned(cps_handle *h, const void *x, int64_t n, int64_t k, int d
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
   if (dtype == CPS_F32)
-    e = cps::launch_learned_bracket<float>((const float *)x, n, k, params_dev, h->bracket, s);
+    e = cps::launch_learned_bracket<float>((const float *)x, n, k, params_dev, h->phist, h->bracket,
+                                           s);
   else
-    e = cps::launch_learned_bracket<double>((const double *)x, n, k, params_dev, h->bracket, s);
+    e = cps::launch_learned_bracket<double>((const double *)x, n, k, params_dev, h->phist, h->bracket,
+                                            s);
   if (e != hipSuccess) return hip_fail(e);
   if (dtype == CPS_F32)
     return run_select<float>(h, (const float *)x, n, k, opt, out_dev, stats_dev, s, h->bracket);
@@ -688,9 +695,9 @@ int select_kth_sampled(cps_handle *h, const void *x, int64_t n, int64_t k, int d
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
   if (dtype == CPS_F32)
-    e = cps::launch_sample_bracket<float>((const float *)x, n, k, z, h->bracket, s);
+    e = cps::launch_sample_bracket<float>((const float *)x, n, k, z, h->phist, h->bracket, s);
   else
-    e = cps::launch_sample_bracket<double>((const double *)x, n, k, z, h->bracket, s);
+    e = cps::launch_sample_bracket<double>((const double *)x, n, k, z, h->phist, h->bracket, s);
   if (e != hipSuccess) return hip_fail(e);
   if (dtype == CPS_F32)
     return run_select<float>(h, (const float *)x, n, k, opt, out_dev, stats_dev, s, h->bracket);

@@ -60,6 +60,8 @@ template <typename T> struct SelectArgs {
   int64_t p0_cap;      // elements per wavefront region a bracketed pass 0 may write (0: none)
   uint64_t *ghist;     // kHistWords counters (zero between passes): a histogram pass uses the
                        // first kHistMaxBins, a split pass that counts its parts both halves
+  uint64_t *phist;     // kHistMaxBins counters, zeroed by the proposal kernel before this
+                       // launch: pass 0 counts a proposal's interior in them (or null)
 };
 
 // ---- batched selection
@@ -121,10 +123,10 @@ hipError_t launch_mlp_adam(float *P, const float *g, float *m, float *v, int64_t
 hipError_t launch_mlp_init(uint64_t seed, float *P, hipStream_t stream);
 template <typename T>
 hipError_t launch_learned_bracket(const T *x, int64_t n, int64_t k, const float *P,
-                                  double *bracket, hipStream_t stream);
+                                  uint64_t *zero_hist, double *bracket, hipStream_t stream);
 template <typename T>
-hipError_t launch_sample_bracket(const T *x, int64_t n, int64_t k, double z, double *bracket,
-                                 hipStream_t stream);
+hipError_t launch_sample_bracket(const T *x, int64_t n, int64_t k, double z, uint64_t *zero_hist,
+                                 double *bracket, hipStream_t stream);
 hipError_t launch_batch_descriptors(const float *base, int64_t n, int64_t count, const float **ptrs,
                                     int64_t *sizes, hipStream_t stream);
 hipError_t launch_labels(const cps_result *res, const float *feat, const double *range,

@@ -638,10 +638,14 @@ __device__ inline void proposal_from_outputs(float u, float s, double h, double 
 template <typename T>
 __global__ __launch_bounds__(kMlpBlock) void learned_bracket_kernel(const T *x, int64_t n, int64_t k,
                                                                     const float *__restrict__ P,
+                                                                    uint64_t *zero_hist,
                                                                     double *bracket) {
   static_assert(kMlpBlock == kFeatBlock, "one workgroup computes features and network");
   __shared__ FeatShared fs;
   __shared__ MlpTile<1> sh;
+  // the counters the selection's pass 0 fills with the proposal's interior start at zero
+  if (zero_hist)
+    for (int i = threadIdx.x; i < kHistMaxBins; i += kMlpBlock) zero_hist[i] = 0;
   double lo, hi;
   int ok;
   array_features<T>(x, n, k, fs, &sh.X[0][0], lo, hi, ok);
@@ -659,9 +663,9 @@ __global__ __launch_bounds__(kMlpBlock) void learned_bracket_kernel(const T *x, 
 }
 
 template <typename T>
-hipError_t launch_learned_bracket(const T *x, int64_t n, int64_t k, const float *P, double *bracket,
-                                  hipStream_t stream) {
-  learned_bracket_kernel<T><<<dim3(1), dim3(kMlpBlock), 0, stream>>>(x, n, k, P, bracket);
+hipError_t launch_learned_bracket(const T *x, int64_t n, int64_t k, const float *P,
+                                  uint64_t *zero_hist, double *bracket, hipStream_t stream) {
+  learned_bracket_kernel<T><<<dim3(1), dim3(kMlpBlock), 0, stream>>>(x, n, k, P, zero_hist, bracket);
   return hipGetLastError();
 }
 
@@ -675,10 +679,13 @@ constexpr int kSortBlock = 1024;
 template <typename T>
 __global__ __launch_bounds__(kSortBlock) void sample_bracket_kernel(const T *x, int64_t n,
                                                                    int64_t k, double z,
+                                                                   uint64_t *zero_hist,
                                                                    double *bracket) {
   __shared__ double sv[kSample];
   __shared__ int bad;
   const int tid = threadIdx.x;
+  if (zero_hist)
+    for (int i = tid; i < kHistMaxBins; i += kSortBlock) zero_hist[i] = 0;
   const int64_t S = n < kSample ? n : kSample;
   const int64_t stride = n / S;
   if (tid == 0) bad = 0;
@@ -731,15 +738,15 @@ __global__ __launch_bounds__(kSortBlock) void sample_bracket_kernel(const T *x, 
 }
 
 template <typename T>
-hipError_t launch_sample_bracket(const T *x, int64_t n, int64_t k, double z, double *bracket,
-                                 hipStream_t stream) {
-  sample_bracket_kernel<T><<<dim3(1), dim3(kSortBlock), 0, stream>>>(x, n, k, z, bracket);
+hipError_t launch_sample_bracket(const T *x, int64_t n, int64_t k, double z, uint64_t *zero_hist,
+                                 double *bracket, hipStream_t stream) {
+  sample_bracket_kernel<T><<<dim3(1), dim3(kSortBlock), 0, stream>>>(x, n, k, z, zero_hist, bracket);
   return hipGetLastError();
 }
 
-template hipError_t launch_sample_bracket<float>(const float *, int64_t, int64_t, double, double *,
-                                                 hipStream_t);
-template hipError_t launch_sample_bracket<double>(const double *, int64_t, int64_t, double,
+template hipError_t launch_sample_bracket<float>(const float *, int64_t, int64_t, double, uint64_t *,
+                                                 double *, hipStream_t);
+template hipError_t launch_sample_bracket<double>(const double *, int64_t, int64_t, double, uint64_t *,
                                                   double *, hipStream_t);
 
 // ------------------------------------------------------------------ training helpers
@@ -830,8 +837,8 @@ template hipError_t launch_features<double>(const double *const *, const int64_t
                                             const int64_t *, int64_t, float *, double *, int32_t *,
                                             hipStream_t);
 template hipError_t launch_learned_bracket<float>(const float *, int64_t, int64_t, const float *,
-                                                  double *, hipStream_t);
+                                                  uint64_t *, double *, hipStream_t);
 template hipError_t launch_learned_bracket<double>(const double *, int64_t, int64_t, const float *,
-                                                   double *, hipStream_t);
+                                                   uint64_t *, double *, hipStream_t);
 
 }  // namespace cps

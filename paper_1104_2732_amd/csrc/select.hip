@@ -273,18 +273,33 @@ __device__ inline void eval_pass(const Walk<T> &wk, T t, T yL, T yR, T fmin, T f
 // Pass 0 with a proposed bracket (a, b) may also write the elements strictly inside it to
 // its wavefront's region, up to `cap` of them (the count goes on past the cap, so an
 // overflowing region is seen and its contents are not used).
-template <typename T>
-__device__ inline void split_inside(T v, bool valid, T a, T b, WaveOut<T> &o, uint32_t cap) {
+// Key bins of a proposal's interior, counted by pass 0 (one set of counters in LDS).
+template <typename T> struct InteriorBins {
+  typename Traits<T>::Key klo;
+  uint32_t last;  // nbins - 1
+  int shift;
+  uint32_t *rh;
+};
+
+template <typename T, bool HIST>
+__device__ inline void split_inside(T v, bool valid, T a, T b, WaveOut<T> &o, uint32_t cap,
+                                    const InteriorBins<T> &ib) {
   const bool in = valid && v > a && v < b;
   const uint64_t m = ballot(in);
   const uint32_t pos = o.lo + lane_rank(m);
   if (in && pos < cap) o.region[pos] = v;
   o.lo += popc(m);
+  if (HIST && in) {
+    // an interior element's key lies in the interior's range; the clamp keeps LDS safe
+    uint32_t bin = (uint32_t)((Traits<T>::key(v) - ib.klo) >> ib.shift);
+    atomicAdd(&ib.rh[bin < ib.last ? bin : ib.last], 1u);
+  }
 }
 
-template <typename T, int U, bool CLASSIFY, bool BRACKET, bool SPLIT, bool FULL>
+template <typename T, int U, bool CLASSIFY, bool BRACKET, bool SPLIT, bool HIST, bool FULL>
 __device__ inline void pass0_tile(const Span<T> &sp, int64_t base, int per_u, int me, T ba, T bb,
-                                  P0Acc<T> &acc, WaveOut<T> &o, uint32_t cap) {
+                                  P0Acc<T> &acc, WaveOut<T> &o, uint32_t cap,
+                                  const InteriorBins<T> &ib) {
   constexpr int V = Traits<T>::kVec;
   using Vec = typename Traits<T>::Vec;
   Vec raw[U];
@@ -305,7 +320,7 @@ __device__ inline void pass0_tile(const Span<T> &sp, int64_t base, int per_u, in
       pass0_one<T, CLASSIFY, BRACKET>(e[j], valid[u], ba, bb, s_part, aa, bA, ab, bB, acc);
     if (SPLIT) {
 #pragma unroll
-      for (int j = 0; j < V; ++j) split_inside<T>(e[j], valid[u], ba, bb, o, cap);
+      for (int j = 0; j < V; ++j) split_inside<T, HIST>(e[j], valid[u], ba, bb, o, cap, ib);
     }
     acc.sum += (double)s_part;
     if (BRACKET) {
@@ -317,25 +332,27 @@ __device__ inline void pass0_tile(const Span<T> &sp, int64_t base, int per_u, in
   }
 }
 
-template <typename T, int BLOCK, int U, bool CLASSIFY, bool BRACKET, bool SPLIT>
+template <typename T, int BLOCK, int U, bool CLASSIFY, bool BRACKET, bool SPLIT, bool HIST = false>
 __device__ inline void pass0(const Walk<T> &wk, T ba, T bb, P0Acc<T> &acc, WaveOut<T> &o,
-                             uint32_t cap) {
+                             uint32_t cap, const InteriorBins<T> &ib) {
   const int tid = threadIdx.x, lane = tid % kWave;
   const Span<T> &sp = wk.sp;
   const int64_t step_vecs = (int64_t)BLOCK * U;
   for (int64_t base = (int64_t)blockIdx.x * step_vecs; base < sp.nvec;
        base += (int64_t)gridDim.x * step_vecs) {
     if (base + step_vecs <= sp.nvec)
-      pass0_tile<T, U, CLASSIFY, BRACKET, SPLIT, true>(sp, base, BLOCK, tid, ba, bb, acc, o, cap);
+      pass0_tile<T, U, CLASSIFY, BRACKET, SPLIT, HIST, true>(sp, base, BLOCK, tid, ba, bb, acc, o,
+                                                             cap, ib);
     else
-      pass0_tile<T, U, CLASSIFY, BRACKET, SPLIT, false>(sp, base, BLOCK, tid, ba, bb, acc, o, cap);
+      pass0_tile<T, U, CLASSIFY, BRACKET, SPLIT, HIST, false>(sp, base, BLOCK, tid, ba, bb, acc, o,
+                                                              cap, ib);
   }
   if (sp.nedge > 0 && wk.edge_owner && tid < kWave) {
     const bool have = lane < sp.nedge;
     const T v = have ? sp.W[edge_index(sp, lane)] : T(0);
     T s_part = 0, aa = 0, bA = 0, ab = 0, bB = 0;
     pass0_one<T, CLASSIFY, BRACKET>(v, have, ba, bb, s_part, aa, bA, ab, bB, acc);
-    if (SPLIT) split_inside<T>(v, have, ba, bb, o, cap);
+    if (SPLIT) split_inside<T, HIST>(v, have, ba, bb, o, cap, ib);
     acc.sum += (double)s_part;
     if (BRACKET) {
       acc.Aa += (double)aa;
@@ -579,6 +596,22 @@ __device__ inline bool arrive(SyncCtl *sync, int bid, int G) {
   return true;
 }
 
+// Key bins of the interior (ba, bb) of a device proposal, as the histogram pass after the
+// proposal's adoption takes them: [a+, b-], the neighbours of the ends inside in T.  None
+// when there are no counters for them.
+template <typename T>
+__device__ inline HistGeom<uint64_t> interior_geometry(const SelectArgs<T> &a, T ba, T bb) {
+  HistGeom<uint64_t> g;
+  g.klo = 1;
+  g.khi = 0;
+  g.shift = 0;
+  g.nbins = 0;
+  if (!a.phist || a.cfg.hist_bits <= 0 || !(ba < bb)) return g;
+  const double lo = next_up((double)ba, a.cfg.dtype), hi = next_down((double)bb, a.cfg.dtype);
+  if (!(lo <= hi)) return g;
+  return hist_geometry(lo, hi, a.cfg.dtype, a.cfg.hist_bits);
+}
+
 // One pass by this workgroup; leaves the workgroup's partial in thread 0's dv / iv.
 template <typename T, int BLOCK, int UNROLL>
 __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, int phase,
@@ -601,6 +634,19 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
     const T ba = (T)bl, bb = (T)bh;
     const bool p0s = use_br && a.p0_cap > 0;
     const uint32_t cap = (uint32_t)a.p0_cap;
+    // the fast pass 0 also counts the compacted interior in key bins when the proposal came
+    // from the device (its kernel cleared the counters); they serve the first histogram step
+    const HistGeom<uint64_t> g0 = interior_geometry(a, ba, bb);
+    const bool p0h = p0s && !p0_slow && g0.nbins > 0;
+    InteriorBins<T> ib;
+    ib.klo = (typename Traits<T>::Key)g0.klo;
+    ib.last = g0.nbins > 0 ? (uint32_t)(g0.nbins - 1) : 0u;
+    ib.shift = g0.shift;
+    ib.rh = sh.rh;
+    if (p0h) {
+      for (int b = tid; b < g0.nbins; b += BLOCK) sh.rh[b] = 0u;
+      __syncthreads();
+    }
     WaveOut<T> o;
     const int wvu = __builtin_amdgcn_readfirstlane(wv);
     o.region = (CPS_GLOBAL T *)uniform_ptr(a.z[0] + ((int64_t)bid * WPB + wvu) * a.seg_R);
@@ -618,13 +664,21 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
     acc.nnan = acc.nneg = acc.npos = acc.cle_a = acc.clt_b = 0;
     acc.Aa = acc.Ba = acc.Ab = acc.Bb = 0;
     if (!p0_slow) {
-      if (p0s) pass0<T, BLOCK, SU, false, true, true>(wk, ba, bb, acc, o, cap);
-      else if (use_br) pass0<T, BLOCK, SU, false, true, false>(wk, ba, bb, acc, o, cap);
-      else pass0<T, BLOCK, UNROLL, false, false, false>(wk, ba, bb, acc, o, cap);
+      if (p0h) pass0<T, BLOCK, SU, false, true, true, true>(wk, ba, bb, acc, o, cap, ib);
+      else if (p0s) pass0<T, BLOCK, SU, false, true, true>(wk, ba, bb, acc, o, cap, ib);
+      else if (use_br) pass0<T, BLOCK, SU, false, true, false>(wk, ba, bb, acc, o, cap, ib);
+      else pass0<T, BLOCK, UNROLL, false, false, false>(wk, ba, bb, acc, o, cap, ib);
     } else {
-      if (p0s) pass0<T, BLOCK, SU, true, true, true>(wk, ba, bb, acc, o, cap);
-      else if (use_br) pass0<T, BLOCK, SU, true, true, false>(wk, ba, bb, acc, o, cap);
-      else pass0<T, BLOCK, SU, true, false, false>(wk, ba, bb, acc, o, cap);
+      if (p0s) pass0<T, BLOCK, SU, true, true, true>(wk, ba, bb, acc, o, cap, ib);
+      else if (use_br) pass0<T, BLOCK, SU, true, true, false>(wk, ba, bb, acc, o, cap, ib);
+      else pass0<T, BLOCK, SU, true, false, false>(wk, ba, bb, acc, o, cap, ib);
+    }
+    if (p0h) {
+      __syncthreads();
+      for (int b = tid; b < g0.nbins; b += BLOCK) {
+        const uint32_t c = sh.rh[b];
+        if (c) atomic_add_relaxed(&a.phist[b], (uint64_t)c);
+      }
     }
     if (p0s && lane == 0) {
       sh.wseg[0][wv] = o.lo;
@@ -839,6 +893,25 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
       if (a.stats && pidx < CPS_STATS_MAX_PASSES) {
         a.stats->population[pidx] = s.phase == PH_DONE ? 0 : s.cR - s.cL;
         a.stats->working[pidx] = a.n;
+      }
+    }
+    __syncthreads();
+    // A proven proposal whose interior pass 0 compacted and counted: the first histogram
+    // step needs no pass (the counts are those of the interior, in the bins it would use).
+    const CpState &s1 = sh.st;
+    if (a.phist && a.bracket && a.bracket[2] != 0.0 && a.p0_cap > 0 && s1.phase == PH_HIST &&
+        s1.bracket_used == 3 && s1.on_bracket && s1.wbuf == 0) {
+      const HistGeom<uint64_t> g0 = interior_geometry(a, (T)a.bracket[0], (T)a.bracket[1]);
+      const HistGeom<uint64_t> g = hist_geometry(s1.lo, s1.hi, a.cfg.dtype, a.cfg.hist_bits);
+      if (g0.nbins > 0 && g.klo == g0.klo && g.khi == g0.khi && g.shift == g0.shift) {
+        hist_pick<BLOCK>(a.phist, g.nbins, (uint64_t)(s1.k - s1.cL), sh.gbase, sh.misc);
+        if (tid == 0) {
+          CpState &s = sh.st;
+          const int32_t bsel = (int32_t)sh.misc[0];
+          dev_hist_narrow(s, g, bsel, bsel < 0 ? 0 : sh.misc[1], bsel < 0 ? 0 : sh.misc[2], a.cfg);
+          if (a.stats && pidx < CPS_STATS_MAX_PASSES)
+            a.stats->population[pidx] = s.phase == PH_DONE ? 0 : s.cR - s.cL;
+        }
       }
     }
   } else if (phase == PH_HIST) {
