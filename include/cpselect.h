@@ -116,7 +116,14 @@ typedef struct cps_eval {
  *                   that count them in 2^hist_bits bins of their ordered bit patterns and
  *                   keep the bin holding the rank (a multi-workgroup radix select on the
  *                   compacted elements; the paper sorts them).  1..12, default 12; 0 keeps
- *                   cutting-plane passes to the end. */
+ *                   cutting-plane passes to the end.
+ * count_first:      with hist_bits > 0, the evaluation at which the first split from the
+ *                   input would happen counts the elements on either side of the trial point
+ *                   in those key bins instead of writing them; the bracket narrows to the
+ *                   bin holding the rank, and the next pass over the input counts that
+ *                   bin's elements and copies them to the workspace (when they are at most a
+ *                   quarter of n).  1 (default) or 0 (the split writes both sides and counts
+ *                   them as it goes). */
 typedef struct cps_options {
   int32_t maxit;
   int32_t final_threshold;
@@ -128,7 +135,7 @@ typedef struct cps_options {
   int32_t compact_proposal;
   double bracket_lo, bracket_hi;
   int32_t hist_bits;
-  int32_t reserved0;
+  int32_t count_first;
 } cps_options;
 
 #define CPS_STATS_MAX_PASSES 96

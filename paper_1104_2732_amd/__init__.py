@@ -58,7 +58,7 @@ class Options(ctypes.Structure):
                 ("block_threads", ctypes.c_int32), ("spin_limit", ctypes.c_int64),
                 ("use_bracket", ctypes.c_int32), ("compact_proposal", ctypes.c_int32),
                 ("bracket_lo", ctypes.c_double), ("bracket_hi", ctypes.c_double),
-                ("hist_bits", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
+                ("hist_bits", ctypes.c_int32), ("count_first", ctypes.c_int32)]
 
 
 class BatchOptions(ctypes.Structure):

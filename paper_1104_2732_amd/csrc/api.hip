@@ -145,6 +145,7 @@ int resolve(cps_handle *h, int64_t n, int dtype, const cps_options *opt, Resolve
   r.cfg.bracket_hi = o.bracket_hi;
   r.cfg.hist_bits = o.hist_bits;
   r.cfg.hist_compact = 1;  // the single-array kernel compacts in its histogram passes
+  r.cfg.count_first = o.count_first ? 1 : 0;
   const int per_cu = dtype == CPS_F32 ? h->max_blocks_f32 : h->max_blocks_f64;
   const int gmax = h->cu_count * per_cu;
   if (gmax < 1) return CPS_ENODEV;
@@ -156,18 +157,21 @@ int resolve(cps_handle *h, int64_t n, int dtype, const cps_options *opt, Resolve
   if (g > (int64_t)cps::kGroup * cps::kMaxGroups) g = (int64_t)cps::kGroup * cps::kMaxGroups;
   if (g < 1) g = 1;
   r.grid = (int)g;
-  // Each wavefront's split region holds everything it can read in the first split (a
-  // pass over the input with half the unroll): its share of each of its workgroup's
+  // Each wavefront's split region holds everything it can read in a pass over the input
+  // that writes to it (the first split, with half the unroll, or the histogram pass that
+  // compacts a counted bin, with the full unroll): its share of each of its workgroup's
   // steps, plus the unaligned edge elements, rounded to 64 elements.
   int64_t seg = 0;
   if (o.partition_fraction > 0.0) {
     const int64_t vec = 16 / (int64_t)dtype_size(dtype);
-    const int64_t su = cps::kSplitUnroll;
-    const int64_t step_vecs = (int64_t)cps::kSelectBlock * su;
     const int64_t nvec = n / vec + 1;
-    const int64_t steps = (nvec + step_vecs - 1) / step_vecs;
-    const int64_t steps_per_wg = (steps + g - 1) / g;
-    seg = (steps_per_wg * cps::kWaveSize * su * vec + 8 + 63) / 64 * 64;
+    for (const int64_t su : {(int64_t)cps::kSplitUnroll, (int64_t)cps::kSelectUnroll}) {
+      const int64_t step_vecs = (int64_t)cps::kSelectBlock * su;
+      const int64_t steps = (nvec + step_vecs - 1) / step_vecs;
+      const int64_t steps_per_wg = (steps + g - 1) / g;
+      const int64_t need = (steps_per_wg * cps::kWaveSize * su * vec + 8 + 63) / 64 * 64;
+      if (need > seg) seg = need;
+    }
   }
   r.seg_R = seg;
   r.spin_limit = o.spin_limit ? o.spin_limit : (int64_t)1 << 22;
@@ -454,6 +458,7 @@ void cps_default_options(cps_options *opt) {
   opt->use_bracket = 0;
   opt->compact_proposal = 1;
   opt->hist_bits = 12;
+  opt->count_first = 1;
 }
 
 int cps_last_hip_error(void) { return g_last_hip; }

@@ -71,6 +71,9 @@ struct CpConfig {
                             // 2^hist_bits bins (0: cutting-plane passes to the end)
   int32_t hist_compact;     // histogram passes may also compact a narrowed bracket's
                             // elements into the other split buffer (kernels that do so)
+  int32_t count_first;      // with hist_compact: where the first split from the input would
+                            // run, the evaluation counts both sides in key bins instead and
+                            // writes nothing; the next pass over the input compacts the bin
 };
 
 // Results of pass 0 over the whole input (Section 4, step 0: min, max and sum in
@@ -133,7 +136,8 @@ struct CpState {
   int32_t p0_slow;         // pass 0 must classify infinities (the fast pass saw one)
   int32_t compact;         // the histogram pass about to run also copies the bracket's
                            // elements to split buffer zout (low parts)
-  int32_t pad0;
+  int32_t counted;         // the evaluation pass about to run (over the input, no split)
+                           // counts the elements on either side of t in key bins
 };
 
 static_assert(sizeof(CpState) % 8 == 0, "state is copied in 8-byte words");
@@ -254,6 +258,7 @@ CPS_HD inline void cp_plan(CpState &s, const CpConfig &c) {
   s.split = 0;
   s.filter = 0;
   s.compact = 0;
+  s.counted = 0;
   if (pop <= c.final_threshold) {
     if (s.wbuf < 0 && s.wlen <= c.final_direct_max) {
       s.phase = PH_FINAL;  // small input: select straight from x, keeping (yL, yR) only
@@ -264,15 +269,16 @@ CPS_HD inline void cp_plan(CpState &s, const CpConfig &c) {
     s.filter = s.on_bracket ? 0 : 1;
     return;
   }
-  if (c.hist_bits > 0 && (s.on_bracket || s.narrowed) && s.wbuf >= 0) {
-    // the bracket's elements are compacted: finish with the exact select by key
-    // histograms over them (the paper sorts the compacted elements instead).  When a
-    // narrowed bracket holds at most a quarter of the working set, the pass also copies
-    // the bracket's elements to the other split buffer, so later passes read only those.
+  if (c.hist_bits > 0 && ((s.on_bracket && s.wbuf >= 0) || s.narrowed)) {
+    // the bracket's elements are compacted (or the bracket is one bin of a count): finish
+    // with the exact select by key histograms (the paper sorts the compacted elements
+    // instead).  When a narrowed bracket holds at most a quarter of the working set, the
+    // pass also copies the bracket's elements to a split buffer (the other one, or buffer 0
+    // when the pass reads the input), so later passes read only those.
     s.phase = PH_HIST;
     if (c.hist_compact && !s.on_bracket && s.wbuf < 2 && pop * 4 <= s.wlen) {
       s.compact = 1;
-      s.zout = 1 - s.wbuf;
+      s.zout = s.wbuf < 0 ? 0 : 1 - s.wbuf;
     }
     return;
   }
@@ -282,9 +288,13 @@ CPS_HD inline void cp_plan(CpState &s, const CpConfig &c) {
   } else if (c.theta > 0.0 && !s.has_inf && (double)pop <= c.theta * (double)s.n &&
              (c.split_cap == 0 || pop <= c.split_cap)) {
     // (inputs holding infinities keep reading x until the gather: no clamped split)
-    s.split = 1;
     s.filter = 1;
-    s.zout = 0;
+    if (c.count_first && c.hist_compact && c.hist_bits > 0) {
+      s.counted = 1;  // count both sides now; the bin holding x_(k) is compacted next
+    } else {
+      s.split = 1;
+      s.zout = 0;
+    }
   }
   s.phase = PH_EVAL;
   s.t = cp_trial_point(s, c);
@@ -412,8 +422,10 @@ CPS_HD inline void cp_after_eval(CpState &s, const EvalResult &r, const CpConfig
   }
   const int64_t E = n - L - G;
   const bool did_split = s.split != 0;
+  const bool did_count = s.counted != 0;
   const int32_t zout = s.zout;
   s.split = 0;
+  s.counted = 0;
   if (L < k && k <= L + E) {
     cp_finish(s, t, L, E);
     return;
@@ -432,6 +444,7 @@ CPS_HD inline void cp_after_eval(CpState &s, const EvalResult &r, const CpConfig
       s.wlen = nright;
       s.on_bracket = 1;
     }
+    if (did_count) s.side = 1;
   } else {  // x_(k) < t: move the right end
     const int64_t nleft = L - s.cL;
     s.yR = t;
@@ -446,7 +459,12 @@ CPS_HD inline void cp_after_eval(CpState &s, const EvalResult &r, const CpConfig
       s.wlen = nleft;
       s.on_bracket = 1;
     }
+    if (did_count) s.side = 0;
   }
+  // After a counting evaluation the bracket is one side of t, whose key bins the pass
+  // counted: the plan asks for a histogram step, and the caller narrows the bracket with
+  // those counts (cp_hist_narrow on split_part_geometry of part `side`) before any pass.
+  if (did_count) s.narrowed = 1;
   if (s.work_passes >= 4 * 96) {  // cannot happen with the bisection bound; guard anyway
     s.status = ST_INTERNAL;
     cp_finish(s, 0.0, 0, 0);

@@ -130,15 +130,11 @@ template <typename T> struct PartBins {
   uint32_t *rh;
 };
 
-template <typename T, bool FILTER, bool HIST>
-__device__ inline void split_one(T v, bool valid, T t, T yL, T yR, WaveOut<T> &o, int lane,
-                                 const PartBins<T> &pb) {
+// Count an element of the low part (l) or the high part (h) in that part's key bins.
+template <typename T>
+__device__ inline void count_part(T v, bool l, bool h, const PartBins<T> &pb) {
   using Key = typename Traits<T>::Key;
-  const bool l = goes_low<T, FILTER>(v, valid, t, yL);
-  const bool h = goes_high<T, FILTER>(v, valid, t, yR);
-  stage_one<T>(v, l, o.ring_lo, o.cl, lane);
-  stage_one<T>(v, h, o.ring_hi, o.ch, lane);
-  if (HIST && (l || h)) {
+  if (l || h) {
     // An element of a part lies in that part's key range (the ranges come from the bracket's
     // bounds and the neighbours of t in T, and keys are monotone), so its bin is in range;
     // the clamp only keeps the counters safe.
@@ -148,6 +144,23 @@ __device__ inline void split_one(T v, bool valid, T t, T yL, T yR, WaveOut<T> &o
     bin = bin < pb.last[p] ? bin : pb.last[p];
     atomicAdd(&pb.rh[p * kHistMaxBins + bin], 1u);
   }
+}
+
+template <typename T, bool FILTER, bool HIST>
+__device__ inline void split_one(T v, bool valid, T t, T yL, T yR, WaveOut<T> &o, int lane,
+                                 const PartBins<T> &pb) {
+  const bool l = goes_low<T, FILTER>(v, valid, t, yL);
+  const bool h = goes_high<T, FILTER>(v, valid, t, yR);
+  stage_one<T>(v, l, o.ring_lo, o.cl, lane);
+  stage_one<T>(v, h, o.ring_hi, o.ch, lane);
+  if (HIST) count_part<T>(v, l, h, pb);
+}
+
+// An evaluation that counts the bracket's elements on either side of t without writing them.
+template <typename T, bool FILTER>
+__device__ inline void count_one(T v, bool valid, T t, T yL, T yR, const PartBins<T> &pb) {
+  count_part<T>(v, goes_low<T, FILTER>(v, valid, t, yL), goes_high<T, FILTER>(v, valid, t, yR),
+                pb);
 }
 
 // Move every lane's full vector of either part to the region.  Called after each vector of
@@ -235,6 +248,9 @@ __device__ inline void eval_tile(const Span<T> &sp, int64_t base, int per_u, int
       for (int j = 0; j < V; ++j)
         split_one<T, FILTER, HIST>(e[j], valid[u], t, yL, yR, o, me % kWave, pb);
       split_flush<T>(o, me % kWave);
+    } else if (HIST) {
+#pragma unroll
+      for (int j = 0; j < V; ++j) count_one<T, FILTER>(e[j], valid[u], t, yL, yR, pb);
     }
   }
 }
@@ -266,6 +282,7 @@ __device__ inline void eval_pass(const Walk<T> &wk, T t, T yL, T yR, T fmin, T f
     acc.A += (double)a_part;
     acc.B += (double)b_part;
     if (SPLIT) split_one<T, FILTER, HIST>(v, have, t, yL, yR, o, lane, pb);
+    else if (HIST) count_one<T, FILTER>(v, have, t, yL, yR, pb);
   }
   if (SPLIT) split_drain<T>(o, lane);
 }
@@ -787,7 +804,7 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
     o.ring_lo = sh.ring[wv][0];
     o.ring_hi = sh.ring[wv][1];
     const bool clamp = s.has_inf && s.wbuf < 0;
-    const bool hist = s.split && a.cfg.hist_bits > 0;
+    const bool hist = (s.split || s.counted) && a.cfg.hist_bits > 0;
     PartBins<T> pb;
     pb.rh = sh.rh;
     int nb[2] = {0, 0};
@@ -802,7 +819,9 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
       }
       __syncthreads();
     }
-    if (!s.split) {
+    if (s.counted) {  // (never with infinities: those inputs do not split or count)
+      eval_pass<T, BLOCK, UNROLL, false, false, true, true>(wk, t, yL, yR, fmn, fmx, o, acc, pb);
+    } else if (!s.split) {
       if (clamp) eval_pass<T, BLOCK, SU, true, false, false, false>(wk, t, yL, yR, fmn, fmx, o, acc, pb);
       else eval_pass<T, BLOCK, UNROLL, false, false, false, false>(wk, t, yL, yR, fmn, fmx, o, acc, pb);
     } else if (s.filter) {
@@ -931,8 +950,11 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
       }
     }
   } else {
-    // a split pass that counted its parts: their key bins, from the state it ran with
-    const bool counted = sh.st.phase == PH_EVAL && sh.st.split && a.cfg.hist_bits > 0;
+    // a split pass that counted its parts, or an evaluation that only counted them: their
+    // key bins, from the state it ran with
+    const bool counted =
+        sh.st.phase == PH_EVAL && (sh.st.split || sh.st.counted) && a.cfg.hist_bits > 0;
+    const bool count_only = counted && !sh.st.split;
     HistGeom<uint64_t> pg[2];
     if (counted) {
       pg[0] = split_part_geometry(sh.st, 0, a.cfg);
@@ -980,7 +1002,7 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
       __syncthreads();
       // the state asks for a histogram pass over the part that holds x_(k): its counts are
       // here already, so the bracket narrows now
-      if (sh.st.phase == PH_HIST && sh.st.on_bracket) {
+      if (sh.st.phase == PH_HIST && (sh.st.on_bracket || count_only)) {
         const CpState &s1 = sh.st;
         const int p = s1.side;
         hist_pick<BLOCK>(a.ghist + p * kHistMaxBins, pg[p].nbins, (uint64_t)(s1.k - s1.cL), sh.gbase,

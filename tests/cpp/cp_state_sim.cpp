@@ -1,9 +1,10 @@
 // Host-side driver of the cutting-plane state machine (paper_1104_2732_amd/csrc/cp_state.h).
 //
 // Test infrastructure: it runs the same sequence of passes the GPU kernel runs (pass 0,
-// evaluation passes with the optional split of the bracket into a buffer, final exact
-// select) with plain loops, so that every branch of the state machine can be exercised
-// on the CPU.  The final exact select here sorts the remaining candidates.
+// evaluation passes with the optional split of the bracket into a buffer or the count of
+// its two sides, histogram passes, final exact select) with plain loops, so that every
+// branch of the state machine can be exercised on the CPU.  The final exact select here
+// sorts the remaining candidates.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -24,7 +25,7 @@ struct SimResult {
 template <typename T>
 static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_threshold,
                double theta, int use_bracket, double blo, double bhi, int p0_split,
-               int64_t p0_cap, int hist_bits, SimResult *out) {
+               int64_t p0_cap, int hist_bits, int count_first, SimResult *out) {
   CpConfig c{};
   c.maxit = maxit;
   c.dtype = sizeof(T) == 4 ? 0 : 1;
@@ -40,6 +41,7 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
   c.p0_split = p0_split;
   c.hist_bits = hist_bits;
   c.hist_compact = 1;  // as the single-array kernel
+  c.count_first = count_first;
   // one workgroup: a single region per split buffer, as large as the input
   const int64_t R = n + 8;
   std::vector<T> z[2] = {std::vector<T>(R), std::vector<T>(R)};
@@ -142,8 +144,10 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
       continue;
     }
     const bool clamp = s.has_inf && s.wbuf < 0;
-    // a split with the histogram finish also counts each part in key bins
-    const bool counted = s.split && c.hist_bits > 0;
+    // a split with the histogram finish also counts each part in key bins; a counting
+    // evaluation counts them without writing
+    const bool counted = (s.split || s.counted) && c.hist_bits > 0;
+    const bool count_only = counted && !s.split;
     HistGeom<uint64_t> pg[2] = {};
     std::vector<int64_t> ph[2];
     if (counted)
@@ -161,10 +165,10 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
       if (clamp) v = std::min(std::max(v, (T)s.fmin), (T)s.fmax);
       if (v < t) { e.L++; e.B += (double)(t - v); e.pred = std::max<double>(e.pred, v); }
       if (v > t) { e.G++; e.A += (double)(v - t); e.succ = std::min<double>(e.succ, v); }
-      if (s.split) {
+      if (s.split || count_only) {
         const bool inb = !s.filter || (v > yL && v < yR);
-        if (inb && v < t) zo[nl++] = v;
-        if (inb && v > t) zo[R - 1 - nr++] = v;
+        if (s.split && inb && v < t) zo[nl++] = v;
+        if (s.split && inb && v > t) zo[R - 1 - nr++] = v;
         if (counted && inb && v != t) {
           const int p = v < t ? 0 : 1;
           const uint64_t K = sizeof(T) == 4 ? (uint64_t)key32((float)v) : key64((double)v);
@@ -176,7 +180,7 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
     e.written = nl + nr;
     if (s.split) { my_l = nl; my_r = nr; }
     cp_after_eval(s, e, c);
-    if (counted && s.phase == PH_HIST && s.on_bracket) {
+    if (counted && s.phase == PH_HIST && (s.on_bracket || count_only)) {
       // the part that holds x_(k) is counted already: narrow without a histogram pass
       const std::vector<int64_t> &h = ph[s.side];
       const int64_t r = s.k - s.cL;
@@ -222,12 +226,14 @@ extern "C" {
 
 int sim_select_f32(const float *x, int64_t n, int64_t k, int maxit, int64_t ft, double theta,
                    int ub, double blo, double bhi, int p0_split, int64_t p0_cap, int hist_bits,
-                   SimResult *out) {
-  return sim<float>(x, n, k, maxit, ft, theta, ub, blo, bhi, p0_split, p0_cap, hist_bits, out);
+                   int count_first, SimResult *out) {
+  return sim<float>(x, n, k, maxit, ft, theta, ub, blo, bhi, p0_split, p0_cap, hist_bits,
+                    count_first, out);
 }
 int sim_select_f64(const double *x, int64_t n, int64_t k, int maxit, int64_t ft, double theta,
                    int ub, double blo, double bhi, int p0_split, int64_t p0_cap, int hist_bits,
-                   SimResult *out) {
-  return sim<double>(x, n, k, maxit, ft, theta, ub, blo, bhi, p0_split, p0_cap, hist_bits, out);
+                   int count_first, SimResult *out) {
+  return sim<double>(x, n, k, maxit, ft, theta, ub, blo, bhi, p0_split, p0_cap, hist_bits,
+                     count_first, out);
 }
 }

@@ -36,18 +36,19 @@ def sim(tmp_path_factory):
         fn = getattr(L, name)
         fn.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int64,
                        ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                       ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(SimResult)]
+                       ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                       ctypes.POINTER(SimResult)]
         fn.restype = ctypes.c_int
 
     def run(x, k, maxit=64, final_threshold=64, theta=0.5, bracket=None, p0_split=False,
-            p0_cap=None, hist_bits=0):
+            p0_cap=None, hist_bits=0, count_first=0):
         r = SimResult()
         fn = L.sim_select_f32 if x.dtype == np.float32 else L.sim_select_f64
         ub = 1 if bracket is not None else 0
         blo, bhi = bracket if bracket is not None else (0.0, 0.0)
         cap = x.size if p0_cap is None else p0_cap
         rc = fn(x.ctypes.data, x.size, k, maxit, final_threshold, theta, ub, blo, bhi,
-                1 if p0_split else 0, cap, hist_bits, ctypes.byref(r))
+                1 if p0_split else 0, cap, hist_bits, count_first, ctypes.byref(r))
         assert rc == 0, rc
         return r
     return run
@@ -72,7 +73,10 @@ def test_state_machine_matches_oracle(sim, oracle_mod, dist, dtype):
             for opts in (dict(), dict(final_threshold=1), dict(final_threshold=4, theta=0.0),
                          dict(maxit=0, final_threshold=8), dict(maxit=2, final_threshold=2, theta=1.0),
                          dict(hist_bits=12), dict(hist_bits=2, final_threshold=1),
-                         dict(hist_bits=1, final_threshold=1, theta=1.0)):
+                         dict(hist_bits=1, final_threshold=1, theta=1.0),
+                         dict(hist_bits=12, theta=1.0, count_first=1),
+                         dict(hist_bits=1, final_threshold=1, theta=1.0, count_first=1),
+                         dict(hist_bits=3, final_threshold=2, theta=0.5, count_first=1)):
                 _check(sim(x, k, **opts), ref, (dist, n, k, opts))
 
 
@@ -86,7 +90,8 @@ def test_infinities_and_zeros(sim, oracle_mod, dtype):
             ref = oracle_mod.select_kth(x, k)
             for opts in (dict(final_threshold=1), dict(maxit=0, final_threshold=1),
                          dict(final_threshold=1, theta=1.0, hist_bits=1),
-                         dict(final_threshold=1, theta=1.0, hist_bits=3)):
+                         dict(final_threshold=1, theta=1.0, hist_bits=3),
+                         dict(final_threshold=1, theta=1.0, hist_bits=2, count_first=1)):
                 _check(sim(x, k, **opts), ref, (x, k, opts))
 
 
@@ -116,7 +121,7 @@ def test_proposed_brackets(sim, oracle_mod, dtype, p0_split):
                        (np.nan, v + 0.1), (v - 0.1, np.nan)]:
             for cap, hb in ((None, 0), (10, 0), (None, 12), (None, 3)):
                 r = sim(x, k, final_threshold=16, bracket=(float(a), float(b)),
-                        p0_split=p0_split, p0_cap=cap, hist_bits=hb)
+                        p0_split=p0_split, p0_cap=cap, hist_bits=hb, count_first=int(hb == 3))
                 _check(r, ref, (k, a, b, cap, hb))
                 assert r.bracket_used == _expected_ends(x, k, a, b), (k, a, b)
                 xa, xb = np.array(a, dtype), np.array(b, dtype)
@@ -162,7 +167,9 @@ def test_histogram_select_edges(sim, oracle_mod, dtype):
         for k in (1, 2, x.size // 3, x.size // 2, x.size - 1, x.size):
             ref = oracle_mod.select_kth(x, k)
             for hb in (1, 2, 4, 12):
-                _check(sim(x, k, final_threshold=1, theta=1.0, hist_bits=hb), ref, (trial, k, hb))
+                for cf in (0, 1):
+                    _check(sim(x, k, final_threshold=1, theta=1.0, hist_bits=hb, count_first=cf),
+                           ref, (trial, k, hb, cf))
 
 
 def test_histogram_finish_cuts_passes(sim):
@@ -187,3 +194,27 @@ def test_counted_split_and_compaction(sim, oracle_mod, dist):
         _check(r, oracle_mod.select_kth(x, k), (dist, k))
         assert r.elements_read <= 3 * n, (dist, k, r.elements_read / n)
         assert r.work_passes <= 5, (dist, k, r.work_passes)
+
+
+@pytest.mark.parametrize("dist", ["normal", "uniform", "cauchy", "quantized_normal", "spike",
+                                  "smallint"])
+def test_count_first_then_compact(sim, oracle_mod, dist):
+    """The first evaluation counts both sides of its trial point in key bins and writes
+    nothing; the bracket narrows to the bin of the rank, and the next pass over the input
+    counts that bin's elements and copies them (they are far fewer than n).  Values stay
+    exact; the input is read at most three times and little is written (with a spike of
+    equal values the bin is too full to copy: one more pass over the input finds the key)."""
+    n = 1 << 20
+    if dist == "spike":  # 90 % of the elements equal
+        rng = np.random.default_rng(12)
+        x = np.where(rng.random(n) < 0.9, 1.0, rng.standard_normal(n)).astype(np.float32)
+    else:
+        x = workloads.single_array(dist, n, np.float32, seed=12)
+    for k in (n // 100, (n + 1) // 2, n - n // 100):
+        ref = oracle_mod.select_kth(x, k)
+        r = sim(x, k, final_threshold=8192, theta=1.0, hist_bits=12, count_first=1)
+        _check(r, ref, (dist, k))
+        most = 4 if dist == "spike" else 3
+        assert r.passes <= most, (dist, k, r.passes)
+        assert r.elements_read <= most * n + n // 4, (dist, k, r.elements_read / n)
+        assert r.elements_written <= n // 4 + 8192, (dist, k, r.elements_written)
