@@ -96,7 +96,10 @@ struct Pass0Result {
   int64_t split_overflow;
 };
 
-// Results of one evaluation pass over the working set W at trial point t.
+// Results of one evaluation pass over the working set W at trial point t.  A counting
+// evaluation (CpState::counted) fills in only L and G (and its key bins): A and B are 0,
+// pred and succ -inf and +inf, since the bracket narrows by the bins right after it and
+// neither f at the ends nor their neighbours are used again.
 struct EvalResult {
   double A, B;          // sums over W of (w - t) for w > t and (t - w) for w < t
   int64_t L, G;         // #(w < t), #(w > t) within W
@@ -436,8 +439,8 @@ CPS_HD inline void cp_after_eval(CpState &s, const EvalResult &r, const CpConfig
     s.AL = A;
     s.BL = B;
     s.cL = L + E;
-    s.lo = r.succ;
-    s.lo_data = 1;
+    s.lo = did_count ? next_up(t, c.dtype) : r.succ;
+    s.lo_data = did_count ? 0 : 1;
     if (did_split) {
       s.wbuf = zout;
       s.side = 1;
@@ -451,8 +454,8 @@ CPS_HD inline void cp_after_eval(CpState &s, const EvalResult &r, const CpConfig
     s.AR = A;
     s.BR = B;
     s.cR = L;
-    s.hi = r.pred;
-    s.hi_data = 1;
+    s.hi = did_count ? next_down(t, c.dtype) : r.pred;
+    s.hi_data = did_count ? 0 : 1;
     if (did_split) {
       s.wbuf = zout;
       s.side = 0;

@@ -52,7 +52,19 @@ template <typename T> struct P0Acc {
 // finite min, max and sum (the slow variant).  Otherwise nothing is classified: NaN makes
 // the sum NaN and an infinity shows up as an infinite extreme (or a NaN sum), either of
 // which makes the state machine ask for the slow variant.
-template <typename T, bool CLASSIFY, bool BRACKET>
+// Minimum and maximum with their multiplicities, one element (fin: it takes part).
+template <typename T> __device__ inline void p0_extremes(T v, bool fin, P0Acc<T> &acc) {
+  const bool lt = fin && v < acc.mn, eqn = fin && v == acc.mn;
+  acc.cmn = lt ? 1u : acc.cmn + (eqn ? 1u : 0u);
+  acc.mn = lt ? v : acc.mn;
+  const bool gt = fin && v > acc.mx, eqx = fin && v == acc.mx;
+  acc.cmx = gt ? 1u : acc.cmx + (eqx ? 1u : 0u);
+  acc.mx = gt ? v : acc.mx;
+}
+
+// SKIP_EXTREMES: the caller has established that no lane's element can change the running
+// minimum or maximum or their counts (none is <= the minimum or >= the maximum).
+template <typename T, bool CLASSIFY, bool BRACKET, bool SKIP_EXTREMES = false>
 __device__ inline void pass0_one(T v, bool valid, T ba, T bb, T &s_part, T &aa, T &bA, T &ab,
                                  T &bB, P0Acc<T> &acc) {
   bool fin = valid;
@@ -65,12 +77,7 @@ __device__ inline void pass0_one(T v, bool valid, T ba, T bb, T &s_part, T &aa, 
     acc.npos += pi ? 1u : 0u;
     fin = valid && !isnan_ && !ni && !pi;
   }
-  const bool lt = fin && v < acc.mn, eqn = fin && v == acc.mn;
-  acc.cmn = lt ? 1u : acc.cmn + (eqn ? 1u : 0u);
-  acc.mn = lt ? v : acc.mn;
-  const bool gt = fin && v > acc.mx, eqx = fin && v == acc.mx;
-  acc.cmx = gt ? 1u : acc.cmx + (eqx ? 1u : 0u);
-  acc.mx = gt ? v : acc.mx;
+  if (!SKIP_EXTREMES) p0_extremes<T>(v, fin, acc);
   s_part += fin ? v : T(0);
   if (BRACKET) {
     acc.cle_a += (valid && v <= ba) ? 1u : 0u;

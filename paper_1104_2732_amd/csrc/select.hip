@@ -156,12 +156,6 @@ __device__ inline void split_one(T v, bool valid, T t, T yL, T yR, WaveOut<T> &o
   if (HIST) count_part<T>(v, l, h, pb);
 }
 
-// An evaluation that counts the bracket's elements on either side of t without writing them.
-template <typename T, bool FILTER>
-__device__ inline void count_one(T v, bool valid, T t, T yL, T yR, const PartBins<T> &pb) {
-  count_part<T>(v, goes_low<T, FILTER>(v, valid, t, yL), goes_high<T, FILTER>(v, valid, t, yR),
-                pb);
-}
 
 // Move every lane's full vector of either part to the region.  Called after each vector of
 // input, so a lane holds fewer than two vectors of a part and moves at most one.
@@ -238,6 +232,18 @@ __device__ inline void eval_tile(const Span<T> &sp, int64_t base, int per_u, int
   for (int u = 0; u < U; ++u) {
     T e[V];
     vec_to_arr<T>(raw[u], e);
+    if (!SPLIT && HIST) {
+      // a counting evaluation: the counts on either side of t and the key bins only (the
+      // bracket narrows by the bins right after it, so f at t is not needed)
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        const bool lt = valid[u] & (e[j] < t), gt = valid[u] & (e[j] > t);
+        acc.L += lt ? 1u : 0u;
+        acc.G += gt ? 1u : 0u;
+        count_part<T>(e[j], lt & (!FILTER | (e[j] > yL)), gt & (!FILTER | (e[j] < yR)), pb);
+      }
+      continue;
+    }
     T a_part = 0, b_part = 0;
 #pragma unroll
     for (int j = 0; j < V; ++j) eval_one<T, CLAMP>(e[j], valid[u], t, fmin, fmax, a_part, b_part, acc);
@@ -248,9 +254,6 @@ __device__ inline void eval_tile(const Span<T> &sp, int64_t base, int per_u, int
       for (int j = 0; j < V; ++j)
         split_one<T, FILTER, HIST>(e[j], valid[u], t, yL, yR, o, me % kWave, pb);
       split_flush<T>(o, me % kWave);
-    } else if (HIST) {
-#pragma unroll
-      for (int j = 0; j < V; ++j) count_one<T, FILTER>(e[j], valid[u], t, yL, yR, pb);
     }
   }
 }
@@ -277,12 +280,18 @@ __device__ inline void eval_pass(const Walk<T> &wk, T t, T yL, T yR, T fmin, T f
   if (sp.nedge > 0 && wk.edge_owner && (wk.wave_mode || tid < kWave)) {
     const bool have = lane < sp.nedge;
     T v = have ? sp.W[edge_index(sp, lane)] : T(0);
-    T a_part = 0, b_part = 0;
-    eval_one<T, CLAMP>(v, have, t, fmin, fmax, a_part, b_part, acc);
-    acc.A += (double)a_part;
-    acc.B += (double)b_part;
-    if (SPLIT) split_one<T, FILTER, HIST>(v, have, t, yL, yR, o, lane, pb);
-    else if (HIST) count_one<T, FILTER>(v, have, t, yL, yR, pb);
+    if (!SPLIT && HIST) {
+      const bool lt = have && v < t, gt = have && v > t;
+      acc.L += lt ? 1u : 0u;
+      acc.G += gt ? 1u : 0u;
+      count_part<T>(v, lt && (!FILTER || v > yL), gt && (!FILTER || v < yR), pb);
+    } else {
+      T a_part = 0, b_part = 0;
+      eval_one<T, CLAMP>(v, have, t, fmin, fmax, a_part, b_part, acc);
+      acc.A += (double)a_part;
+      acc.B += (double)b_part;
+      if (SPLIT) split_one<T, FILTER, HIST>(v, have, t, yL, yR, o, lane, pb);
+    }
   }
   if (SPLIT) split_drain<T>(o, lane);
 }
@@ -332,9 +341,26 @@ __device__ inline void pass0_tile(const Span<T> &sp, int64_t base, int per_u, in
     T e[V];
     vec_to_arr<T>(raw[u], e);
     T s_part = 0, aa = 0, bA = 0, ab = 0, bB = 0;
+    if (!CLASSIFY) {
+      // Past the first tiles an element rarely reaches the running extremes: the wavefront
+      // tests that first (compares only) and updates the extremes and their counts only
+      // when some lane's element is <= the minimum or >= the maximum.  NaN compares false
+      // here as in the update, so the result is the same.
+      bool near = false;
 #pragma unroll
-    for (int j = 0; j < V; ++j)
-      pass0_one<T, CLASSIFY, BRACKET>(e[j], valid[u], ba, bb, s_part, aa, bA, ab, bB, acc);
+      for (int j = 0; j < V; ++j) near |= valid[u] & ((e[j] <= acc.mn) | (e[j] >= acc.mx));
+      if (ballot(near) != 0) {
+#pragma unroll
+        for (int j = 0; j < V; ++j) p0_extremes<T>(e[j], valid[u], acc);
+      }
+#pragma unroll
+      for (int j = 0; j < V; ++j)
+        pass0_one<T, false, BRACKET, true>(e[j], valid[u], ba, bb, s_part, aa, bA, ab, bB, acc);
+    } else {
+#pragma unroll
+      for (int j = 0; j < V; ++j)
+        pass0_one<T, true, BRACKET>(e[j], valid[u], ba, bb, s_part, aa, bA, ab, bB, acc);
+    }
     if (SPLIT) {
 #pragma unroll
       for (int j = 0; j < V; ++j) split_inside<T, HIST>(e[j], valid[u], ba, bb, o, cap, ib);

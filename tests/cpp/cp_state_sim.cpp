@@ -179,6 +179,11 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
     }
     e.written = nl + nr;
     if (s.split) { my_l = nl; my_r = nr; }
+    if (count_only) {  // as the kernel's counting evaluation: counts and bins only
+      e.A = e.B = 0.0;
+      e.pred = -INFINITY;
+      e.succ = INFINITY;
+    }
     cp_after_eval(s, e, c);
     if (counted && s.phase == PH_HIST && (s.on_bracket || count_only)) {
       // the part that holds x_(k) is counted already: narrow without a histogram pass
