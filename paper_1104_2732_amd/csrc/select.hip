@@ -29,25 +29,27 @@
 
 namespace cps {
 
-// The scalar cutting-plane update runs in one thread per pass; keeping it out of line
-// keeps its registers out of the streaming loops' budget.
-__device__ __noinline__ void dev_after_pass0(CpState &s, const Pass0Result &r, const CpConfig &c) {
+// The scalar cutting-plane update runs in one thread per pass, inside the out-of-line
+// last_update (so its registers stay out of the streaming loops' budget).  Inlined there,
+// its records live in registers: out of line they went through the stack in scratch
+// memory, a chain of dependent memory round trips that cost ~10 us per update.
+__device__ __attribute__((always_inline)) inline void dev_after_pass0(CpState &s, const Pass0Result &r, const CpConfig &c) {
   cp_after_pass0(s, r, c);
 }
-__device__ __noinline__ void dev_after_eval(CpState &s, const EvalResult &r, const CpConfig &c) {
+__device__ __attribute__((always_inline)) inline void dev_after_eval(CpState &s, const EvalResult &r, const CpConfig &c) {
   cp_after_eval(s, r, c);
 }
-__device__ __noinline__ void dev_after_gather(CpState &s, int64_t gathered) {
+__device__ __attribute__((always_inline)) inline void dev_after_gather(CpState &s, int64_t gathered) {
   cp_after_gather(s, gathered);
 }
-__device__ __noinline__ void dev_after_final(CpState &s, double v, int64_t below, int64_t eq) {
+__device__ __attribute__((always_inline)) inline void dev_after_final(CpState &s, double v, int64_t below, int64_t eq) {
   cp_after_final(s, v, below, eq);
 }
-__device__ __noinline__ void dev_after_hist(CpState &s, int32_t b, int64_t below, int64_t cnt,
+__device__ __attribute__((always_inline)) inline void dev_after_hist(CpState &s, int32_t b, int64_t below, int64_t cnt,
                                             const CpConfig &c) {
   cp_after_hist(s, b, below, cnt, c);
 }
-__device__ __noinline__ void dev_hist_narrow(CpState &s, const HistGeom<uint64_t> &g, int32_t b,
+__device__ __attribute__((always_inline)) inline void dev_hist_narrow(CpState &s, const HistGeom<uint64_t> &g, int32_t b,
                                              int64_t below, int64_t cnt, const CpConfig &c) {
   cp_hist_narrow(s, g, b, below, cnt, c);
 }
@@ -655,6 +657,9 @@ __device__ inline HistGeom<uint64_t> interior_geometry(const SelectArgs<T> &a, T
   return hist_geometry(lo, hi, a.cfg.dtype, a.cfg.hist_bits);
 }
 
+// Workgroup partials each lane of the folding wavefront loads at once.
+constexpr int kFold = 4;
+
 // One pass by this workgroup; leaves the workgroup's partial in thread 0's dv / iv.
 template <typename T, int BLOCK, int UNROLL>
 __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, int phase,
@@ -900,14 +905,35 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
     int64_t cmn = 0, cmx = 0;
     if (tid < kWave) {
       for (int f = 0; f < 8; ++f) { rd[f] = 0; ri[f] = 0; }
-      for (int b = tid; b < G; b += kWave) {
-        for (int f = 0; f < 5; ++f) rd[f] += a.sd[f * stride + b];
-        for (int f = 0; f < 6; ++f) ri[f] += a.si[f * stride + b];
-        const double m2 = a.sd[5 * stride + b], x2 = a.sd[6 * stride + b];
-        const int64_t c2 = a.si[6 * stride + b], d2 = a.si[7 * stride + b];
-        if (m2 < mn) { mn = m2; cmn = c2; } else if (m2 == mn) cmn += c2;
-        if (x2 > mx) { mx = x2; cmx = d2; } else if (x2 == mx) cmx += d2;
+      // the fields every pass 0 produces: kFold workgroups per lane at a time, all of
+      // their loads issued before the first is used (one memory round trip per round)
+      for (int b0 = tid; b0 < G; b0 += kWave * kFold) {
+        double sm[kFold], m2[kFold], x2[kFold];
+        int64_t c2[kFold], d2[kFold];
+#pragma unroll
+        for (int q = 0; q < kFold; ++q) {
+          const int b = b0 + q * kWave < G ? b0 + q * kWave : 0;
+          sm[q] = a.sd[0 * stride + b];
+          m2[q] = a.sd[5 * stride + b];
+          x2[q] = a.sd[6 * stride + b];
+          c2[q] = a.si[6 * stride + b];
+          d2[q] = a.si[7 * stride + b];
+        }
+#pragma unroll
+        for (int q = 0; q < kFold; ++q) {
+          if (b0 + q * kWave >= G) break;
+          rd[0] += sm[q];
+          if (m2[q] < mn) { mn = m2[q]; cmn = c2[q]; } else if (m2[q] == mn) cmn += c2[q];
+          if (x2[q] > mx) { mx = x2[q]; cmx = d2[q]; } else if (x2[q] == mx) cmx += d2[q];
+        }
       }
+      // the classification counts (slow pass 0) and the proposal's fields, when present
+      const bool more = p0_slow || a.cfg.use_bracket || (a.bracket && a.bracket[2] != 0.0);
+      if (more)
+        for (int b = tid; b < G; b += kWave) {
+          for (int f = 1; f < 5; ++f) rd[f] += a.sd[f * stride + b];
+          for (int f = 0; f < 6; ++f) ri[f] += a.si[f * stride + b];
+        }
       for (int f = 0; f < 5; ++f) rd[f] = wave_sum(rd[f]);
       for (int f = 0; f < 6; ++f) ri[f] = wave_sum_i64(ri[f]);
       wave_pair_fold(mn, cmn, mx, cmx);
@@ -992,14 +1018,37 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
       for (int f = 0; f < 8; ++f) { rd[f] = 0; ri[f] = 0; }
       rd[2] = -__builtin_inf();
       rd[3] = __builtin_inf();
-      for (int b = tid; b < G; b += kWave) {
-        rd[0] += a.sd[0 * stride + b];
-        rd[1] += a.sd[1 * stride + b];
-        rd[2] = fmax(rd[2], a.sd[2 * stride + b]);
-        rd[3] = fmin(rd[3], a.sd[3 * stride + b]);
-        ri[0] += a.si[0 * stride + b];
-        ri[1] += a.si[1 * stride + b];
-        ri[2] += a.si[2 * stride + b];
+      // kFold workgroups per lane at a time, all of their loads issued first; a counting
+      // evaluation has only its counts (A, B, pred and succ are not formed)
+      for (int b0 = tid; b0 < G; b0 += kWave * kFold) {
+        double A[kFold], B[kFold], pr[kFold], su[kFold];
+        int64_t L[kFold], Gt[kFold], W[kFold];
+#pragma unroll
+        for (int q = 0; q < kFold; ++q) {
+          const int b = b0 + q * kWave < G ? b0 + q * kWave : 0;
+          L[q] = a.si[0 * stride + b];
+          Gt[q] = a.si[1 * stride + b];
+          if (!count_only) {
+            A[q] = a.sd[0 * stride + b];
+            B[q] = a.sd[1 * stride + b];
+            pr[q] = a.sd[2 * stride + b];
+            su[q] = a.sd[3 * stride + b];
+            W[q] = a.si[2 * stride + b];
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < kFold; ++q) {
+          if (b0 + q * kWave >= G) break;
+          ri[0] += L[q];
+          ri[1] += Gt[q];
+          if (!count_only) {
+            rd[0] += A[q];
+            rd[1] += B[q];
+            rd[2] = fmax(rd[2], pr[q]);
+            rd[3] = fmin(rd[3], su[q]);
+            ri[2] += W[q];
+          }
+        }
       }
       rd[0] = wave_sum(rd[0]);
       rd[1] = wave_sum(rd[1]);
