@@ -1177,8 +1177,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_num_vgpr(128))) void c
       }
     } else {
       if (tid == 0) {
-        // poll without acquire semantics (an acquire per poll would invalidate this XCD's
-        // L2 under the workgroups still streaming); acquire once the flag has moved
+        // poll with device-scope loads, which are served coherently across the XCDs
         int64_t spins = 0;
         bool timed_out = false;
         while (load_relaxed(&a.sync->gen) == gen) {
@@ -1186,10 +1185,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_num_vgpr(128))) void c
           if (++spins > a.spin_limit) { timed_out = true; break; }
         }
         sh.timed_out = timed_out ? 1 : 0;
-        if (!timed_out) {
-          gen = gen + 1u;
-          fence_acquire();
-        }
+        if (!timed_out) gen = gen + 1u;
       }
       __syncthreads();
       if (sh.timed_out) {
@@ -1198,11 +1194,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_num_vgpr(128))) void c
           sh.st.status = ST_TIMEOUT;
         }
       } else {
-        // read the state the last workgroup published (thread 0's acquire above
-        // invalidated this CU's and this XCD's caches before the workgroup barrier)
+        // Read the state the last workgroup published, with device-scope loads as well:
+        // its release wrote the state back before the generation word moved, and these
+        // loads are served at the device's coherence point, so no acquire (an invalidation
+        // of this XCD's L2, which took up to ~10 us with the XCD's 32 workgroups issuing it
+        // together) is needed.  Nothing else another workgroup wrote is read by a waiting
+        // workgroup: each reads only its own split regions, the input and, through device
+        // atomics, the shared counters; the last workgroup acquires in `arrive`.
         constexpr int NW = sizeof(CpState) / 8;
         for (int w = tid; w < NW; w += BLOCK)
-          reinterpret_cast<uint64_t *>(&sh.st)[w] = reinterpret_cast<const uint64_t *>(a.st)[w];
+          reinterpret_cast<uint64_t *>(&sh.st)[w] =
+              load_relaxed(reinterpret_cast<const uint64_t *>(a.st) + w);
       }
     }
     __syncthreads();
