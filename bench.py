@@ -14,8 +14,9 @@ the plain single-array method on the same GPU (their own keys in the line):
 launch vs a loop of single-array calls), "lms" (1024 least-median-of-squares
 candidates over 2^20 rows) and "learned" (the learned bracket proposal vs the
 plain method on held-out 2^26-element mixture arrays; training untimed).  A
-fourth, "schedules", times the method under three schedules of its compaction
-(cutting-plane passes to the end, split after one evaluation, the default).
+fourth, "schedules", times the method under four schedules of its compaction
+(cutting-plane passes to the end, split after one evaluation, split at the first
+trial point, and the default: the first evaluation counts, the next pass compacts).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 
@@ -226,14 +227,17 @@ def learned_leg(sel, cps, torch, reps: int = 5) -> dict:
 
 
 def schedules_leg(sel, cps, torch, reps: int = 3) -> dict:
-    """The same selections under three schedules of the method on 2^28 normal arrays:
+    """The same selections under four schedules of the method on 2^28 normal arrays:
     cutting-plane passes until the bracket holds at most the final threshold, then the
     gather and the exact select (no split, no histograms); the split after one evaluation
-    pass (partition fraction 0.75); and the default (split at the first trial point)."""
+    pass (partition fraction 0.75); the split at the first trial point (both sides
+    written and counted); and the default (the first evaluation counts both sides in key
+    bins, the next pass over x compacts the bin of the rank)."""
     import workloads
     scheds = {"cutting_plane_to_the_end": dict(partition_fraction=0.0, hist_bits=0),
-              "split_after_one_evaluation": dict(partition_fraction=0.75),
-              "default_split_at_first_trial_point": dict()}
+              "split_after_one_evaluation": dict(partition_fraction=0.75, count_first=0),
+              "split_at_first_trial_point": dict(count_first=0),
+              "default_count_at_first_trial_point": dict()}
     out = {"workload": "n=2^28 N(0,1), k in {n/100, median}", "cases": {}}
     res = sel.new_results(1)
     stats = sel.new_stats()
