@@ -14,6 +14,7 @@ constexpr int kWave = 64;
 // Global-memory pointers: loads and stores through them compile to global_* instructions
 // (with a scalar base where the compiler can prove it) instead of flat_* ones.
 #define CPS_GLOBAL __attribute__((address_space(1)))
+#define CPS_LDS __attribute__((address_space(3)))
 
 template <typename T> struct Traits;
 template <> struct Traits<float> {

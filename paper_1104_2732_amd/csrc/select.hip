@@ -87,6 +87,7 @@ template <typename T, int BLOCK> struct Shared {
   int64_t misc[8];
   int last;
   int timed_out;
+  uint32_t lcnt;  // elements a gather pass staged in LDS
   uint32_t rh[kHistWords];  // key histogram of a histogram pass, or of both parts of a split
   T ring[BLOCK / kWave][2][Stage<T>::kSlots];  // split staging, per wavefront and part
 };
@@ -408,11 +409,15 @@ __device__ inline void pass0(const Walk<T> &wk, T ba, T bb, P0Acc<T> &acc, WaveO
   }
 }
 
-// Gather: every element of the walk inside (yL, yR) goes to the gather buffer.  Offsets
-// come from one atomic per wavefront-step that holds any such element (the bracket holds
-// few elements when this runs).
-template <typename T, int BLOCK, int U>
+// Gather: every element of the walk inside (yL, yR) goes to the gather buffer.  STAGE: the
+// elements go to the workgroup's LDS buffer `lbuf` first, at places taken with one LDS atomic
+// on `lcnt` per wavefront-step that holds any, and the caller moves them out with one device
+// atomic per workgroup (the bracket's population must fit the buffer).  Otherwise the places
+// come from one device atomic on `gcur` per such wavefront-step, which all workgroups contend
+// for.
+template <typename T, int BLOCK, int U, bool STAGE>
 __device__ inline void gather_walk(const Walk<T> &wk, T yL, T yR, T *zf, uint64_t *gcur,
+                                   CPS_LDS T *lbuf, CPS_LDS uint32_t *lcnt, uint32_t lcap,
                                    int64_t &written) {
   constexpr int V = Traits<T>::kVec;
   using Vec = typename Traits<T>::Vec;
@@ -449,14 +454,22 @@ __device__ inline void gather_walk(const Walk<T> &wk, T yL, T yR, T *zf, uint64_
       for (int j = 0; j < V; ++j) cnt += popc(ballot((in >> (u * V + j)) & 1u));
       if (cnt == 0) continue;
       uint64_t off = 0;
-      if (lane == 0) off = atomic_add_relaxed(gcur, cnt);
+      if (lane == 0) off = STAGE ? (uint64_t)atomicAdd((uint32_t *)lcnt, cnt) : atomic_add_relaxed(gcur, cnt);
       off = __shfl(off, 0);
-      written += cnt;
+      if (!STAGE) written += cnt;
 #pragma unroll
       for (int j = 0; j < V; ++j) {
         const bool sel = (in >> (u * V + j)) & 1u;
         const uint64_t m = ballot(sel);
-        if (sel) zf[off + lane_rank(m)] = e[j];
+        if (sel) {
+          // (a workgroup never holds more than the bracket's population, which fits; the test
+          // only keeps LDS safe should the counts and the data ever disagree)
+          if (STAGE) {
+            if (off + lane_rank(m) < lcap) lbuf[off + lane_rank(m)] = e[j];
+          } else {
+            zf[off + lane_rank(m)] = e[j];
+          }
+        }
         off += popc(m);
       }
     }
@@ -468,10 +481,18 @@ __device__ inline void gather_walk(const Walk<T> &wk, T yL, T yR, T *zf, uint64_
     const uint64_t m = ballot(in);
     if (m) {
       uint64_t off = 0;
-      if (lane == 0) off = atomic_add_relaxed(gcur, (uint64_t)popc(m));
+      if (lane == 0)
+        off = STAGE ? (uint64_t)atomicAdd((uint32_t *)lcnt, (uint32_t)popc(m))
+                    : atomic_add_relaxed(gcur, (uint64_t)popc(m));
       off = __shfl(off, 0);
-      if (in) zf[off + lane_rank(m)] = v;
-      written += popc(m);
+      if (in) {
+        if (STAGE) {
+          if (off + lane_rank(m) < lcap) lbuf[off + lane_rank(m)] = v;
+        } else {
+          zf[off + lane_rank(m)] = v;
+        }
+      }
+      if (!STAGE) written += popc(m);
     }
   }
 }
@@ -657,6 +678,45 @@ __device__ inline HistGeom<uint64_t> interior_geometry(const SelectArgs<T> &a, T
   return hist_geometry(lo, hi, a.cfg.dtype, a.cfg.hist_bits);
 }
 
+// A gather pass that tests the bracket (over the input, or a split buffer that holds elements
+// outside a narrowed bracket).  A workgroup holds at most the bracket's population `pop`: when
+// that fits the split staging block of LDS (idle in this pass), the elements are staged there
+// and reserved with one device atomic per workgroup.  Out of line (inlined into the pass loop,
+// its registers pushed the streaming loops into spills), with everything passed by value so
+// that nothing the loop reads can alias its stores.  Returns the count to report (thread 0).
+template <typename T, int BLOCK, int UNROLL>
+__device__ __noinline__ int64_t gather_filtered(Walk<T> wk, T yL, T yR, int64_t pop, T *zf,
+                                                uint64_t *gcur, int64_t zcap, T *ring,
+                                                uint32_t *lcnt, uint64_t *gbase) {
+  constexpr int WPB = BLOCK / kWave;
+  constexpr int64_t kCap = (int64_t)WPB * 2 * Stage<T>::kSlots;
+  const int tid = threadIdx.x;
+  CPS_LDS T *lbuf = (CPS_LDS T *)ring;
+  CPS_LDS uint32_t *lc = (CPS_LDS uint32_t *)lcnt;
+  int64_t written = 0;
+  if (pop <= kCap) {
+    if (tid == 0) *lc = 0;
+    __syncthreads();
+    gather_walk<T, BLOCK, UNROLL, true>(wk, yL, yR, zf, gcur, lbuf, lc, (uint32_t)kCap, written);
+    __syncthreads();
+    // more than kCap cannot happen while the counts hold; the gathered total then differs
+    // from the bracket's population and the state machine reports an internal error
+    const uint32_t got = *lc;
+    const uint32_t cnt = got < (uint32_t)kCap ? got : (uint32_t)kCap;
+    CPS_LDS uint64_t *gb = (CPS_LDS uint64_t *)gbase;
+    if (tid == 0) *gb = cnt ? atomic_add_relaxed(gcur, (uint64_t)cnt) : 0;
+    __syncthreads();
+    const uint64_t base = *gb;
+    CPS_GLOBAL T *z = (CPS_GLOBAL T *)zf;
+    for (uint32_t i = tid; i < cnt; i += BLOCK)
+      if (base + i < (uint64_t)zcap) z[base + i] = lbuf[i];
+    written = tid == 0 ? (int64_t)got : 0;  // counted once (lane 0 of wavefront 0)
+  } else {
+    gather_walk<T, BLOCK, UNROLL, false>(wk, yL, yR, zf, gcur, lbuf, lc, 0u, written);
+  }
+  return written;
+}
+
 // Workgroup partials each lane of the folding wavefront loads at once.
 constexpr int kFold = 4;
 
@@ -804,7 +864,9 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
     }
   } else if (s.phase == PH_GATHER) {
     if (s.wbuf < 0 || s.filter) {
-      gather_walk<T, BLOCK, UNROLL>(wk, yL, yR, a.zf, &a.sync->gcur, written);
+      written = gather_filtered<T, BLOCK, UNROLL>(wk, yL, yR, s.cR - s.cL, a.zf, &a.sync->gcur,
+                                                  a.cfg.zcap, &sh.ring[0][0][0], &sh.lcnt,
+                                                  &sh.gbase[0]);
     } else {
       // every element of a segment lies inside the bracket: one offset per workgroup
       const int64_t len = wk.sp.m;
