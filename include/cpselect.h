@@ -218,14 +218,20 @@ int cps_objective(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
 
 /* ------------------------------------------------------------------ batched selection */
 
-/* Tuning of the batched kernel.  Fill with cps_default_batch_options first; 0 fields pick
- * the tuned (or default) value.
+/* Tuning of the batched kernel.  Fill with cps_default_batch_options first (1024 threads,
+ * split capacity 2^17, final threshold 4096, split fraction 1, 2^12 bins, count first);
+ * 0 fields pick the tuned (or default) value.
  * block_threads:   workgroup size, 256, 512 or 1024 (one workgroup runs one array at a time).
  * blocks_per_cu:   resident workgroups per compute unit.
  * split_capacity:  elements of each of a workgroup's two split buffers; a bracket is split
  *                  (count-and-compact, end of Section 4) once it holds at most this many.
+ *                  Unused (no buffers) with count_first and hist_bits > 0, which never split.
  * final_threshold, maxit, partition_fraction, hist_bits: as in cps_options (the histogram
- *                  passes count in the workgroup's LDS). */
+ *                  passes count in the workgroup's LDS).
+ * count_first:     as in cps_options, with 2^11 bins per side (the two sides share the
+ *                  workgroup's LDS histogram); the bin's elements are then counted by
+ *                  histogram passes over the array (no copy) until few are left for the
+ *                  gather.  The split capacity does not limit it.  1 (default) or 0. */
 typedef struct cps_batch_options {
   int32_t block_threads;
   int32_t blocks_per_cu;
@@ -234,7 +240,7 @@ typedef struct cps_batch_options {
   int32_t maxit;
   double partition_fraction;
   int32_t hist_bits;
-  int32_t reserved0;
+  int32_t count_first;
 } cps_batch_options;
 
 void cps_default_batch_options(cps_batch_options *opt);
@@ -262,11 +268,12 @@ int select_kth_batched_ex(cps_handle *h, const void *const *ptrs_dev, const int6
 /* Allocate the batched workspace for `opt` (NULL: the current choice) ahead of stream capture. */
 int cps_reserve_batched(cps_handle *h, int dtype, const cps_batch_options *opt);
 
-/* Autotuner: time each candidate launch shape, split capacity and split fraction on this
- * very batch (the call synchronises `stream`), keep the fastest as the handle's choice for
- * `dtype`, and
- * return it in best (may be NULL) with its time in *best_ms (may be NULL).  The results in
- * out_dev are those of the last timed candidate. */
+/* Autotuner: time each candidate launch shape (256, 512, 1024 threads) with the counting
+ * evaluation at split fractions 0.5 and 1, and with splits at every split capacity
+ * (2^15 .. 2^20) and fraction, on this very batch (the call synchronises `stream`); keep
+ * the fastest as the handle's choice for `dtype`, and return it in best (may be NULL)
+ * with its time in *best_ms (may be NULL).  The results in out_dev are those of the last
+ * timed candidate. */
 int cps_autotune_batched(cps_handle *h, const void *const *ptrs_dev, const int64_t *sizes_dev,
                          const int64_t *ks_dev, int64_t count, int dtype, cps_result *out_dev,
                          void *stream, cps_batch_options *best, double *best_ms);

@@ -66,7 +66,7 @@ class BatchOptions(ctypes.Structure):
     _fields_ = [("block_threads", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("split_capacity", ctypes.c_int64), ("final_threshold", ctypes.c_int32),
                 ("maxit", ctypes.c_int32), ("partition_fraction", ctypes.c_double),
-                ("hist_bits", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
+                ("hist_bits", ctypes.c_int32), ("count_first", ctypes.c_int32)]
 
 
 class TrainOptions(ctypes.Structure):

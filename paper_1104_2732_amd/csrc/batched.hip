@@ -31,6 +31,14 @@ __device__ __noinline__ void bdev_after_hist(CpState &s, int32_t b, int64_t belo
                                              const CpConfig &c) {
   cp_after_hist(s, b, below, cnt, c);
 }
+__device__ __noinline__ void bdev_hist_narrow(CpState &s, const HistGeom<uint64_t> &g, int32_t b,
+                                              int64_t below, int64_t cnt, const CpConfig &c) {
+  cp_hist_narrow(s, g, b, below, cnt, c);
+}
+
+// Key bins per side of a counting evaluation: the two sides share the workgroup's LDS
+// histogram, half each.
+constexpr int kBatchSideBits = 11;
 
 template <typename T, int BLOCK> struct BShared {
   CpState st;
@@ -194,6 +202,87 @@ __device__ void block_hist(const Span<T> &sp, typename Traits<T>::Key klo,
   }
 }
 
+// Counting evaluation of this workgroup over the input: the counts below and above t, and
+// the bracket's elements on either side in the key bins of that side (LDS counters
+// rh[0..) for the low side, rh[kHistMaxBins / 2..) for the high side).  Nothing is written.
+template <typename T> struct SideBins {
+  typename Traits<T>::Key klo[2];
+  uint32_t last[2];  // nbins - 1
+  int shift[2];
+};
+
+template <typename T>
+__device__ inline void count_side(T v, bool valid, T t, T yL, T yR, const SideBins<T> &sb,
+                                  uint32_t *rh, EvalAcc<T> &acc) {
+  const bool lt = valid && v < t, gt = valid && v > t;
+  acc.L += lt ? 1u : 0u;
+  acc.G += gt ? 1u : 0u;
+  const bool l = lt && v > yL, h = gt && v < yR;
+  if (l || h) {
+    // an element of a side lies in that side's key range; the clamp keeps LDS safe
+    const int p = l ? 0 : 1;
+    uint32_t bin = (uint32_t)((Traits<T>::key(v) - sb.klo[p]) >> sb.shift[p]);
+    bin = bin < sb.last[p] ? bin : sb.last[p];
+    atomicAdd(&rh[p * (kHistMaxBins / 2) + bin], 1u);
+  }
+}
+
+template <typename T, int BLOCK, int U>
+__device__ void block_count(const Span<T> &sp, T t, T yL, T yR, const SideBins<T> &sb,
+                            uint32_t *rh, EvalAcc<T> &acc) {
+  constexpr int V = Traits<T>::kVec;
+  using Vec = typename Traits<T>::Vec;
+  const int tid = threadIdx.x;
+  for (int64_t base = 0; base < sp.nvec; base += (int64_t)BLOCK * U) {
+    Vec raw[U];
+    bool valid[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t vi = base + (int64_t)u * BLOCK + tid;
+      valid[u] = vi < sp.nvec;
+      if (valid[u]) raw[u] = sp.V[vi];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      T e[V];
+      vec_to_arr<T>(raw[u], e);
+#pragma unroll
+      for (int j = 0; j < V; ++j) count_side<T>(e[j], valid[u], t, yL, yR, sb, rh, acc);
+    }
+  }
+  if (sp.nedge > 0 && tid < sp.nedge)
+    count_side<T>(sp.W[edge_index(sp, tid)], true, t, yL, yR, sb, rh, acc);
+}
+
+// The bin holding rank r of `nbins` LDS counters: an exclusive scan in a fixed order.
+// Leaves the bin in misc[0] (-1 when none holds it), the count below it in misc[1] and its
+// own count in misc[2]; ends with a workgroup barrier.
+template <typename T, int BLOCK>
+__device__ void block_pick(const uint32_t *bins, int nbins, uint64_t r, BShared<T, BLOCK> &sh) {
+  const int tid = threadIdx.x;
+  constexpr int BPT = kHistMaxBins / BLOCK;
+  uint64_t hv[BPT];
+  uint64_t tot = 0;
+#pragma unroll
+  for (int j = 0; j < BPT; ++j) {
+    const int b = tid * BPT + j;
+    hv[j] = b < nbins ? bins[b] : 0u;
+    tot += hv[j];
+  }
+  if (tid == 0) sh.misc[0] = -1;
+  uint64_t cum = block_exclusive_scan<BLOCK>(tot, sh.wsum);
+#pragma unroll
+  for (int j = 0; j < BPT; ++j) {
+    if (cum < r && r <= cum + hv[j]) {
+      sh.misc[0] = tid * BPT + j;
+      sh.misc[1] = (int64_t)cum;
+      sh.misc[2] = (int64_t)hv[j];
+    }
+    cum += hv[j];
+  }
+  __syncthreads();
+}
+
 template <typename T, int BLOCK, int U, bool CLASSIFY>
 __device__ void block_pass0(const Span<T> &sp, P0Acc<T> &acc) {
   constexpr int V = Traits<T>::kVec;
@@ -322,32 +411,11 @@ __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out,
       // key histogram of the compacted bracket in LDS, then the bin holding rank k - cL
       const HistGeom<uint64_t> g = hist_geometry(s.lo, s.hi, a.cfg.dtype, a.cfg.hist_bits);
       for (int b = tid; b < g.nbins; b += BLOCK) sh.rh[b] = 0u;
-      if (tid == 0) sh.misc[0] = -1;
       __syncthreads();
       block_hist<T, BLOCK, U>(sp, (typename Traits<T>::Key)g.klo, (typename Traits<T>::Key)g.khi,
                               g.shift, sh.rh);
       __syncthreads();
-      constexpr int BPT = kHistMaxBins / BLOCK;
-      const uint64_t r = (uint64_t)(s.k - s.cL);
-      uint64_t hv[BPT];
-      uint64_t tot = 0;
-#pragma unroll
-      for (int j = 0; j < BPT; ++j) {
-        const int b = tid * BPT + j;
-        hv[j] = b < g.nbins ? sh.rh[b] : 0u;
-        tot += hv[j];
-      }
-      uint64_t cum = block_exclusive_scan<BLOCK>(tot, sh.wsum);
-#pragma unroll
-      for (int j = 0; j < BPT; ++j) {
-        if (cum < r && r <= cum + hv[j]) {
-          sh.misc[0] = tid * BPT + j;
-          sh.misc[1] = (int64_t)cum;
-          sh.misc[2] = (int64_t)hv[j];
-        }
-        cum += hv[j];
-      }
-      __syncthreads();
+      block_pick<T, BLOCK>(sh.rh, g.nbins, (uint64_t)(s.k - s.cL), sh);
       if (tid == 0) {
         const int32_t bsel = (int32_t)sh.misc[0];
         bdev_after_hist(sh.st, bsel, bsel < 0 ? 0 : sh.misc[1], bsel < 0 ? 0 : sh.misc[2], a.cfg);
@@ -360,6 +428,50 @@ __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out,
     acc.pred = -t_inf<T>();
     acc.succ = t_inf<T>();
     acc.L = acc.G = 0;
+    if (s.counted) {
+      // count both sides of t in key bins (half of the LDS histogram each), then narrow the
+      // bracket to the bin of the rank on the side that holds it
+      CpConfig cs = a.cfg;
+      cs.hist_bits = a.cfg.hist_bits > kBatchSideBits ? kBatchSideBits : a.cfg.hist_bits;
+      HistGeom<uint64_t> pg[2];
+      SideBins<T> sb;
+      for (int p = 0; p < 2; ++p) {
+        pg[p] = split_part_geometry(s, p, cs);
+        sb.klo[p] = (typename Traits<T>::Key)pg[p].klo;
+        sb.last[p] = pg[p].nbins > 0 ? (uint32_t)(pg[p].nbins - 1) : 0u;
+        sb.shift[p] = pg[p].shift;
+      }
+      for (int b = tid; b < kHistMaxBins; b += BLOCK) sh.rh[b] = 0u;
+      __syncthreads();
+      block_count<T, BLOCK, U>(sp, t, yL, yR, sb, sh.rh, acc);
+      double dv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      int dop[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      int64_t iv[8] = {(int64_t)acc.L, (int64_t)acc.G, 0, 0, 0, 0, 0, 0};
+      block_reduce<BLOCK, 0, 2>(dv, dop, iv, false, sh.d, sh.i);
+      if (tid == 0) {
+        EvalResult r;
+        r.A = r.B = 0.0;
+        r.pred = -__builtin_inf();
+        r.succ = __builtin_inf();
+        r.L = iv[0];
+        r.G = iv[1];
+        r.written = 0;
+        bdev_after_eval(sh.st, r, a.cfg);
+      }
+      __syncthreads();
+      if (sh.st.phase == PH_HIST) {
+        const int p = sh.st.side;
+        block_pick<T, BLOCK>(sh.rh + p * (kHistMaxBins / 2), pg[p].nbins,
+                             (uint64_t)(sh.st.k - sh.st.cL), sh);
+        if (tid == 0) {
+          const int32_t bsel = (int32_t)sh.misc[0];
+          bdev_hist_narrow(sh.st, pg[p], bsel, bsel < 0 ? 0 : sh.misc[1],
+                           bsel < 0 ? 0 : sh.misc[2], a.cfg);
+        }
+        __syncthreads();
+      }
+      continue;
+    }
     if (tid == 0) sh.cur[0] = sh.cur[1] = 0;
     __syncthreads();
     const bool gather = s.phase == PH_GATHER;

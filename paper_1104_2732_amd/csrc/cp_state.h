@@ -71,9 +71,10 @@ struct CpConfig {
                             // 2^hist_bits bins (0: cutting-plane passes to the end)
   int32_t hist_compact;     // histogram passes may also compact a narrowed bracket's
                             // elements into the other split buffer (kernels that do so)
-  int32_t count_first;      // with hist_compact: where the first split from the input would
-                            // run, the evaluation counts both sides in key bins instead and
-                            // writes nothing; the next pass over the input compacts the bin
+  int32_t count_first;      // with hist_bits: where the first split from the input would run,
+                            // the evaluation counts both sides in key bins instead and writes
+                            // nothing; the bracket narrows to a bin, whose elements the next
+                            // pass over the input compacts (hist_compact) or counts
 };
 
 // Results of pass 0 over the whole input (Section 4, step 0: min, max and sum in
@@ -288,14 +289,14 @@ CPS_HD inline void cp_plan(CpState &s, const CpConfig &c) {
   if (s.on_bracket) {
     s.split = 1;
     s.zout = 1 - s.wbuf;
-  } else if (c.theta > 0.0 && !s.has_inf && (double)pop <= c.theta * (double)s.n &&
-             (c.split_cap == 0 || pop <= c.split_cap)) {
+  } else if (c.theta > 0.0 && !s.has_inf && (double)pop <= c.theta * (double)s.n) {
     // (inputs holding infinities keep reading x until the gather: no clamped split)
-    s.filter = 1;
-    if (c.count_first && c.hist_compact && c.hist_bits > 0) {
-      s.counted = 1;  // count both sides now; the bin holding x_(k) is compacted next
-    } else {
+    if (c.count_first && c.hist_bits > 0) {
+      s.counted = 1;  // count both sides now (no buffer needed); the bin of x_(k) comes next
+      s.filter = 1;
+    } else if (c.split_cap == 0 || pop <= c.split_cap) {
       s.split = 1;
+      s.filter = 1;
       s.zout = 0;
     }
   }

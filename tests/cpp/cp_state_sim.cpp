@@ -25,7 +25,8 @@ struct SimResult {
 template <typename T>
 static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_threshold,
                double theta, int use_bracket, double blo, double bhi, int p0_split,
-               int64_t p0_cap, int hist_bits, int count_first, SimResult *out) {
+               int64_t p0_cap, int hist_bits, int count_first, int hist_compact,
+               SimResult *out) {
   CpConfig c{};
   c.maxit = maxit;
   c.dtype = sizeof(T) == 4 ? 0 : 1;
@@ -40,7 +41,7 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
   c.bracket_hi = bhi;
   c.p0_split = p0_split;
   c.hist_bits = hist_bits;
-  c.hist_compact = 1;  // as the single-array kernel
+  c.hist_compact = hist_compact;  // 1 as the single-array kernel, 0 as the batched one
   c.count_first = count_first;
   // one workgroup: a single region per split buffer, as large as the input
   const int64_t R = n + 8;
@@ -231,14 +232,14 @@ extern "C" {
 
 int sim_select_f32(const float *x, int64_t n, int64_t k, int maxit, int64_t ft, double theta,
                    int ub, double blo, double bhi, int p0_split, int64_t p0_cap, int hist_bits,
-                   int count_first, SimResult *out) {
+                   int count_first, int hist_compact, SimResult *out) {
   return sim<float>(x, n, k, maxit, ft, theta, ub, blo, bhi, p0_split, p0_cap, hist_bits,
-                    count_first, out);
+                    count_first, hist_compact, out);
 }
 int sim_select_f64(const double *x, int64_t n, int64_t k, int maxit, int64_t ft, double theta,
                    int ub, double blo, double bhi, int p0_split, int64_t p0_cap, int hist_bits,
-                   int count_first, SimResult *out) {
+                   int count_first, int hist_compact, SimResult *out) {
   return sim<double>(x, n, k, maxit, ft, theta, ub, blo, bhi, p0_split, p0_cap, hist_bits,
-                     count_first, out);
+                     count_first, hist_compact, out);
 }
 }

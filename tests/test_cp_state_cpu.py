@@ -36,19 +36,19 @@ def sim(tmp_path_factory):
         fn = getattr(L, name)
         fn.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int64,
                        ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                       ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                       ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                        ctypes.POINTER(SimResult)]
         fn.restype = ctypes.c_int
 
     def run(x, k, maxit=64, final_threshold=64, theta=0.5, bracket=None, p0_split=False,
-            p0_cap=None, hist_bits=0, count_first=0):
+            p0_cap=None, hist_bits=0, count_first=0, hist_compact=1):
         r = SimResult()
         fn = L.sim_select_f32 if x.dtype == np.float32 else L.sim_select_f64
         ub = 1 if bracket is not None else 0
         blo, bhi = bracket if bracket is not None else (0.0, 0.0)
         cap = x.size if p0_cap is None else p0_cap
         rc = fn(x.ctypes.data, x.size, k, maxit, final_threshold, theta, ub, blo, bhi,
-                1 if p0_split else 0, cap, hist_bits, count_first, ctypes.byref(r))
+                1 if p0_split else 0, cap, hist_bits, count_first, hist_compact, ctypes.byref(r))
         assert rc == 0, rc
         return r
     return run
@@ -76,7 +76,10 @@ def test_state_machine_matches_oracle(sim, oracle_mod, dist, dtype):
                          dict(hist_bits=1, final_threshold=1, theta=1.0),
                          dict(hist_bits=12, theta=1.0, count_first=1),
                          dict(hist_bits=1, final_threshold=1, theta=1.0, count_first=1),
-                         dict(hist_bits=3, final_threshold=2, theta=0.5, count_first=1)):
+                         dict(hist_bits=3, final_threshold=2, theta=0.5, count_first=1),
+                         dict(hist_bits=11, theta=1.0, count_first=1, hist_compact=0),
+                         dict(hist_bits=2, final_threshold=1, theta=0.5, count_first=1,
+                              hist_compact=0)):
                 _check(sim(x, k, **opts), ref, (dist, n, k, opts))
 
 

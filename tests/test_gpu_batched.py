@@ -66,6 +66,15 @@ def _check_all(res, arrays, ks, oracle_mod, ctx):
     dict(block_threads=512, hist_bits=0),
     dict(block_threads=256, final_threshold=1, partition_fraction=1.0, hist_bits=2),
     dict(block_threads=1024, final_threshold=16, partition_fraction=1.0, hist_bits=12),
+    # the split of the bracket instead of the counting evaluation
+    dict(block_threads=512, split_capacity=64, final_threshold=16, count_first=0),
+    dict(block_threads=256, split_capacity=4096, final_threshold=64, partition_fraction=1.0,
+         count_first=0),
+    dict(block_threads=512, maxit=0, final_threshold=32, split_capacity=128, count_first=0),
+    dict(block_threads=1024, final_threshold=16, partition_fraction=1.0, hist_bits=12,
+         count_first=0),
+    dict(block_threads=1024, final_threshold=1, partition_fraction=1.0, hist_bits=1,
+         count_first=1),
 ])
 def test_batched_parity(sel, oracle_mod, dtype, opt):
     import paper_1104_2732_amd as cps
