@@ -375,6 +375,7 @@ __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out,
     if (tid == 0) {
       Pass0Result r = {};
       r.classified = slow ? 1 : 0;
+      r.sums = 1;
       r.sum = dv[0];
       r.nnan = iv[0];
       r.nneg = iv[1];

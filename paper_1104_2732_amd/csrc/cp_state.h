@@ -83,7 +83,8 @@ struct CpConfig {
 struct Pass0Result {
   int32_t classified;   // 1: NaN and infinities were classified (nnan, nneg, npos, finite
                         // min/max); 0: nothing classified (nnan etc. are 0)
-  int32_t pad0;
+  int32_t sums;         // 1: A_a, B_a, A_b, B_b below were formed; 0: only the two counts
+                        // (a pass 0 that counts a proposal's interior in key bins)
   double sum;           // sum of finite elements
   double fmin, fmax;    // min and max over finite elements (+inf / -inf if none)
   int64_t cmin, cmax;   // multiplicities of fmin and fmax
@@ -382,6 +383,9 @@ CPS_HD inline void cp_after_pass0(CpState &s, const Pass0Result &r, const CpConf
       s.AR = r.A_b + (double)r.npos * (r.fmax - b);
       s.BR = r.B_b + (double)r.nneg * (b - r.fmin);
     }
+    // A pass 0 that formed only the counts at the ends leaves f at an adopted end unknown:
+    // the bracket is then finished by key histograms only (its ends are never cut again).
+    if (s.bracket_used && !r.sums) s.narrowed = 1;
     // With both ends proven, the elements pass 0 wrote (those strictly inside (a, b))
     // are exactly the bracket's, cR - cL of them: later passes read only those.  With the
     // exact finish by histograms, an end beyond the data (a <= min, b >= max) may stand

@@ -64,7 +64,9 @@ template <typename T> __device__ inline void p0_extremes(T v, bool fin, P0Acc<T>
 
 // SKIP_EXTREMES: the caller has established that no lane's element can change the running
 // minimum or maximum or their counts (none is <= the minimum or >= the maximum).
-template <typename T, bool CLASSIFY, bool BRACKET, bool SKIP_EXTREMES = false>
+// SUMS: with a proposed bracket, also the finite-element parts of A and B at its ends
+// (otherwise only the two counts).
+template <typename T, bool CLASSIFY, bool BRACKET, bool SKIP_EXTREMES = false, bool SUMS = true>
 __device__ inline void pass0_one(T v, bool valid, T ba, T bb, T &s_part, T &aa, T &bA, T &ab,
                                  T &bB, P0Acc<T> &acc) {
   bool fin = valid;
@@ -82,10 +84,12 @@ __device__ inline void pass0_one(T v, bool valid, T ba, T bb, T &s_part, T &aa, 
   if (BRACKET) {
     acc.cle_a += (valid && v <= ba) ? 1u : 0u;
     acc.clt_b += (valid && v < bb) ? 1u : 0u;
-    aa += (fin && v > ba) ? v - ba : T(0);
-    bA += (fin && v < ba) ? ba - v : T(0);
-    ab += (fin && v > bb) ? v - bb : T(0);
-    bB += (fin && v < bb) ? bb - v : T(0);
+    if (SUMS) {
+      aa += (fin && v > ba) ? v - ba : T(0);
+      bA += (fin && v < ba) ? ba - v : T(0);
+      ab += (fin && v > bb) ? v - bb : T(0);
+      bB += (fin && v < bb) ? bb - v : T(0);
+    }
   }
 }
 

@@ -358,7 +358,8 @@ __device__ inline void pass0_tile(const Span<T> &sp, int64_t base, int per_u, in
       }
 #pragma unroll
       for (int j = 0; j < V; ++j)
-        pass0_one<T, false, BRACKET, true>(e[j], valid[u], ba, bb, s_part, aa, bA, ab, bB, acc);
+        pass0_one<T, false, BRACKET, true, !HIST>(e[j], valid[u], ba, bb, s_part, aa, bA, ab, bB,
+                                                  acc);
     } else {
 #pragma unroll
       for (int j = 0; j < V; ++j)
@@ -397,7 +398,7 @@ __device__ inline void pass0(const Walk<T> &wk, T ba, T bb, P0Acc<T> &acc, WaveO
     const bool have = lane < sp.nedge;
     const T v = have ? sp.W[edge_index(sp, lane)] : T(0);
     T s_part = 0, aa = 0, bA = 0, ab = 0, bB = 0;
-    pass0_one<T, CLASSIFY, BRACKET>(v, have, ba, bb, s_part, aa, bA, ab, bB, acc);
+    pass0_one<T, CLASSIFY, BRACKET, false, !HIST>(v, have, ba, bb, s_part, aa, bA, ab, bB, acc);
     if (SPLIT) split_inside<T, HIST>(v, have, ba, bb, o, cap, ib);
     acc.sum += (double)s_part;
     if (BRACKET) {
@@ -772,7 +773,7 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
     acc.nnan = acc.nneg = acc.npos = acc.cle_a = acc.clt_b = 0;
     acc.Aa = acc.Ba = acc.Ab = acc.Bb = 0;
     if (!p0_slow) {
-      if (p0h) pass0<T, BLOCK, SU, false, true, true, true>(wk, ba, bb, acc, o, cap, ib);
+      if (p0h) pass0<T, BLOCK, UNROLL, false, true, true, true>(wk, ba, bb, acc, o, cap, ib);
       else if (p0s) pass0<T, BLOCK, SU, false, true, true>(wk, ba, bb, acc, o, cap, ib);
       else if (use_br) pass0<T, BLOCK, SU, false, true, false>(wk, ba, bb, acc, o, cap, ib);
       else pass0<T, BLOCK, UNROLL, false, false, false>(wk, ba, bb, acc, o, cap, ib);
@@ -1007,6 +1008,9 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
       r.nnan = ri[0]; r.nneg = ri[1]; r.npos = ri[2]; r.c_le_a = ri[3]; r.c_lt_b = ri[4];
       r.fmin = mn; r.fmax = mx; r.cmin = cmn; r.cmax = cmx;
       r.split_overflow = ri[5];
+      // the pass that counted the interior formed only the two counts at the ends
+      r.sums = (!p0_slow && a.phist && a.bracket && a.bracket[2] != 0.0 && a.p0_cap > 0 &&
+                interior_geometry(a, (T)a.bracket[0], (T)a.bracket[1]).nbins > 0) ? 0 : 1;
       CpConfig c = a.cfg;
       if (a.bracket) {
         c.use_bracket = a.bracket[2] != 0.0 ? 1 : 0;

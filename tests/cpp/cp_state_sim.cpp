@@ -25,7 +25,7 @@ struct SimResult {
 template <typename T>
 static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_threshold,
                double theta, int use_bracket, double blo, double bhi, int p0_split,
-               int64_t p0_cap, int hist_bits, int count_first, int hist_compact,
+               int64_t p0_cap, int hist_bits, int count_first, int hist_compact, int p0_sums,
                SimResult *out) {
   CpConfig c{};
   c.maxit = maxit;
@@ -59,6 +59,7 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
     const bool classify = attempt == 1;
     Pass0Result r{};
     r.classified = classify ? 1 : 0;
+    r.sums = p0_sums;  // 0: as a pass 0 that counts the interior (no sums at the ends)
     r.fmin = INFINITY;
     r.fmax = -INFINITY;
     my_l = my_r = 0;
@@ -91,6 +92,7 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
       }
     }
     r.split_overflow = (use_bracket && p0_split && my_l > p0_cap) ? 1 : 0;
+    if (!p0_sums) r.A_a = r.B_a = r.A_b = r.B_b = 0.0;
     cp_after_pass0(s, r, c);
     if (!(s.phase == PH_PASS0 && s.p0_slow)) break;
   }
@@ -232,14 +234,14 @@ extern "C" {
 
 int sim_select_f32(const float *x, int64_t n, int64_t k, int maxit, int64_t ft, double theta,
                    int ub, double blo, double bhi, int p0_split, int64_t p0_cap, int hist_bits,
-                   int count_first, int hist_compact, SimResult *out) {
+                   int count_first, int hist_compact, int p0_sums, SimResult *out) {
   return sim<float>(x, n, k, maxit, ft, theta, ub, blo, bhi, p0_split, p0_cap, hist_bits,
-                    count_first, hist_compact, out);
+                    count_first, hist_compact, p0_sums, out);
 }
 int sim_select_f64(const double *x, int64_t n, int64_t k, int maxit, int64_t ft, double theta,
                    int ub, double blo, double bhi, int p0_split, int64_t p0_cap, int hist_bits,
-                   int count_first, int hist_compact, SimResult *out) {
+                   int count_first, int hist_compact, int p0_sums, SimResult *out) {
   return sim<double>(x, n, k, maxit, ft, theta, ub, blo, bhi, p0_split, p0_cap, hist_bits,
-                     count_first, hist_compact, out);
+                     count_first, hist_compact, p0_sums, out);
 }
 }

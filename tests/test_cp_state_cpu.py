@@ -37,18 +37,19 @@ def sim(tmp_path_factory):
         fn.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int64,
                        ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                        ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                       ctypes.POINTER(SimResult)]
+                       ctypes.c_int, ctypes.POINTER(SimResult)]
         fn.restype = ctypes.c_int
 
     def run(x, k, maxit=64, final_threshold=64, theta=0.5, bracket=None, p0_split=False,
-            p0_cap=None, hist_bits=0, count_first=0, hist_compact=1):
+            p0_cap=None, hist_bits=0, count_first=0, hist_compact=1, p0_sums=1):
         r = SimResult()
         fn = L.sim_select_f32 if x.dtype == np.float32 else L.sim_select_f64
         ub = 1 if bracket is not None else 0
         blo, bhi = bracket if bracket is not None else (0.0, 0.0)
         cap = x.size if p0_cap is None else p0_cap
         rc = fn(x.ctypes.data, x.size, k, maxit, final_threshold, theta, ub, blo, bhi,
-                1 if p0_split else 0, cap, hist_bits, count_first, hist_compact, ctypes.byref(r))
+                1 if p0_split else 0, cap, hist_bits, count_first, hist_compact, p0_sums,
+                ctypes.byref(r))
         assert rc == 0, rc
         return r
     return run
@@ -122,9 +123,11 @@ def test_proposed_brackets(sim, oracle_mod, dtype, p0_split):
                        (-10.0, 10.0), (v + 0.5, v + 1.0), (v - 1.0, v - 0.5), (3.0, -3.0),
                        (v - 0.3, v + 1e-9), (-np.inf, v + 0.2), (v - 0.2, np.inf),
                        (np.nan, v + 0.1), (v - 0.1, np.nan)]:
-            for cap, hb in ((None, 0), (10, 0), (None, 12), (None, 3)):
+            for cap, hb, sums in ((None, 0, 1), (10, 0, 1), (None, 12, 1), (None, 3, 1),
+                                  (None, 12, 0), (10, 3, 0)):
                 r = sim(x, k, final_threshold=16, bracket=(float(a), float(b)),
-                        p0_split=p0_split, p0_cap=cap, hist_bits=hb, count_first=int(hb == 3))
+                        p0_split=p0_split, p0_cap=cap, hist_bits=hb, count_first=int(hb == 3),
+                        p0_sums=sums)
                 _check(r, ref, (k, a, b, cap, hb))
                 assert r.bracket_used == _expected_ends(x, k, a, b), (k, a, b)
                 xa, xb = np.array(a, dtype), np.array(b, dtype)
