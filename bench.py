@@ -163,7 +163,8 @@ def batched_leg(sel, cps, torch, reps: int = 5) -> dict:
                         "median ranks (one persistent launch, captured in a graph)",
             "elements": total, "graph_ms": graph_ms, "elements_per_s": total / (graph_ms * 1e-3),
             "tuned": {"block_threads": best.block_threads, "split_capacity": best.split_capacity,
-                      "partition_fraction": best.partition_fraction},
+                      "partition_fraction": best.partition_fraction,
+                      "count_first": best.count_first},
             "plain_loop_ms": loop_ms, "plain_loop_elements_per_s": total / (loop_ms * 1e-3),
             "speedup_vs_plain": loop_ms / graph_ms, "results_identical": same}
 
