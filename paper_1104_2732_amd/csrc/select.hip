@@ -310,18 +310,60 @@ template <typename T> struct InteriorBins {
   uint32_t *rh;
 };
 
+// An interior element goes to this lane's staging column (low part) and, with HIST, to its
+// key bin.
 template <typename T, bool HIST>
-__device__ inline void split_inside(T v, bool valid, T a, T b, WaveOut<T> &o, uint32_t cap,
+__device__ inline void stage_inside(T v, bool valid, T a, T b, WaveOut<T> &o, int lane,
                                     const InteriorBins<T> &ib) {
-  const bool in = valid && v > a && v < b;
-  const uint64_t m = ballot(in);
-  const uint32_t pos = o.lo + lane_rank(m);
-  if (in && pos < cap) o.region[pos] = v;
-  o.lo += popc(m);
+  const bool in = valid & (v > a) & (v < b);
+  if (in) {
+    o.ring_lo[(o.cl & (Stage<T>::kS - 1)) * kWave + lane] = v;
+    o.cl += 1;
+  }
   if (HIST && in) {
     // an interior element's key lies in the interior's range; the clamp keeps LDS safe
     uint32_t bin = (uint32_t)((Traits<T>::key(v) - ib.klo) >> ib.shift);
     atomicAdd(&ib.rh[bin < ib.last ? bin : ib.last], 1u);
+  }
+}
+
+// Move every lane's full staged vector to the region, at most `cap` elements in all (the
+// count goes on past the cap).  After each vector of input a lane holds fewer than two.
+template <typename T>
+__device__ inline void flush_inside(WaveOut<T> &o, int lane, uint32_t cap) {
+  using S = Stage<T>;
+  using Vec = typename Traits<T>::Vec;
+  __builtin_amdgcn_wave_barrier();
+  const bool full = o.cl - o.fl >= S::kV;
+  const uint64_t m = ballot(full);
+  if (m != 0) {
+    if (full) {
+      const T *col = o.ring_lo + (o.fl & (S::kS - 1)) * kWave + lane;
+      Vec d;
+#pragma unroll
+      for (uint32_t j = 0; j < S::kV; ++j) d[j] = col[j * kWave];
+      const uint32_t pos = o.lo + S::kV * lane_rank(m);  // a multiple of kV: aligned
+      if (pos + S::kV <= cap) *reinterpret_cast<CPS_GLOBAL Vec *>(o.region + pos) = d;
+      o.fl += S::kV;
+    }
+    o.lo += S::kV * popc(m);
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// What is left in the columns at the end of the pass, one element per lane at a time.
+template <typename T>
+__device__ inline void drain_inside(WaveOut<T> &o, int lane, uint32_t cap) {
+  using S = Stage<T>;
+  __builtin_amdgcn_wave_barrier();
+  const T *col = o.ring_lo + (o.fl & (S::kS - 1)) * kWave + lane;
+#pragma unroll
+  for (uint32_t j = 0; j < S::kV; ++j) {
+    const bool sel = o.cl - o.fl > j;
+    const uint64_t m = ballot(sel);
+    const uint32_t pos = o.lo + lane_rank(m);
+    if (sel && pos < cap) o.region[pos] = col[j * kWave];
+    o.lo += popc(m);
   }
 }
 
@@ -366,8 +408,12 @@ __device__ inline void pass0_tile(const Span<T> &sp, int64_t base, int per_u, in
         pass0_one<T, true, BRACKET>(e[j], valid[u], ba, bb, s_part, aa, bA, ab, bB, acc);
     }
     if (SPLIT) {
+      // staged in LDS and moved in 16-byte vectors (per-element stores of a small interior
+      // cost a store instruction per element position)
+      const int lane = me % kWave;
 #pragma unroll
-      for (int j = 0; j < V; ++j) split_inside<T, HIST>(e[j], valid[u], ba, bb, o, cap, ib);
+      for (int j = 0; j < V; ++j) stage_inside<T, HIST>(e[j], valid[u], ba, bb, o, lane, ib);
+      flush_inside<T>(o, lane, cap);
     }
     acc.sum += (double)s_part;
     if (BRACKET) {
@@ -399,7 +445,10 @@ __device__ inline void pass0(const Walk<T> &wk, T ba, T bb, P0Acc<T> &acc, WaveO
     const T v = have ? sp.W[edge_index(sp, lane)] : T(0);
     T s_part = 0, aa = 0, bA = 0, ab = 0, bB = 0;
     pass0_one<T, CLASSIFY, BRACKET, false, !HIST>(v, have, ba, bb, s_part, aa, bA, ab, bB, acc);
-    if (SPLIT) split_inside<T, HIST>(v, have, ba, bb, o, cap, ib);
+    if (SPLIT) {
+      stage_inside<T, HIST>(v, have, ba, bb, o, lane, ib);
+      flush_inside<T>(o, lane, cap);
+    }
     acc.sum += (double)s_part;
     if (BRACKET) {
       acc.Aa += (double)aa;
@@ -408,6 +457,7 @@ __device__ inline void pass0(const Walk<T> &wk, T ba, T bb, P0Acc<T> &acc, WaveO
       acc.Bb += (double)bB;
     }
   }
+  if (SPLIT) drain_inside<T>(o, lane, cap);
 }
 
 // Gather: every element of the walk inside (yL, yR) goes to the gather buffer.  STAGE: the
@@ -761,7 +811,8 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
     o.region = (CPS_GLOBAL T *)uniform_ptr(a.z[0] + ((int64_t)bid * WPB + wvu) * a.seg_R);
     o.top = (uint32_t)(a.seg_R - 1);
     o.lo = o.hi = o.cl = o.ch = o.fl = o.fh = 0;
-    o.ring_lo = o.ring_hi = nullptr;  // pass 0 writes the region directly
+    o.ring_lo = sh.ring[wv][0];  // the interior is staged in this wavefront's LDS columns
+    o.ring_hi = nullptr;
     wk.sp = make_span(a.x, a.n);
     wk.wave_mode = false;
     wk.edge_owner = bid == 0;
