@@ -75,6 +75,10 @@ struct CpConfig {
                             // the evaluation counts both sides in key bins instead and writes
                             // nothing; the bracket narrows to a bin, whose elements the next
                             // pass over the input compacts (hist_compact) or counts
+  int32_t pad1;
+  int64_t spec_min_n;       // inputs of at least this many elements (0: none): the counting
+                            // evaluation also copies the elements of a likely interval
+                            // [spec_a, spec_b] to split buffer 0 (see cp_adopt_spec)
 };
 
 // Results of pass 0 over the whole input (Section 4, step 0: min, max and sum in
@@ -143,6 +147,10 @@ struct CpState {
                            // elements to split buffer zout (low parts)
   int32_t counted;         // the evaluation pass about to run (over the input, no split)
                            // counts the elements on either side of t in key bins
+  int32_t spec;            // that counting evaluation also copies every element of
+                           // [spec_a, spec_b] to the low parts of split buffer 0
+  int32_t pad1;
+  double spec_a, spec_b;
 };
 
 static_assert(sizeof(CpState) % 8 == 0, "state is copied in 8-byte words");
@@ -263,7 +271,7 @@ CPS_HD inline void cp_plan(CpState &s, const CpConfig &c) {
   s.split = 0;
   s.filter = 0;
   s.compact = 0;
-  s.counted = 0;
+  s.counted = 0;  // (spec stays: the caller of a counting evaluation clears it, cp_adopt_spec)
   if (pop <= c.final_threshold) {
     if (s.wbuf < 0 && s.wlen <= c.final_direct_max) {
       s.phase = PH_FINAL;  // small input: select straight from x, keeping (yL, yR) only
@@ -478,6 +486,24 @@ CPS_HD inline void cp_after_eval(CpState &s, const EvalResult &r, const CpConfig
     cp_finish(s, 0.0, 0, 0);
     return;
   }
+  cp_plan(s, c);
+}
+
+// After a counting evaluation that also copied the `written` elements of [spec_a, spec_b]
+// to split buffer 0, and after the narrowing by its bins (if any): when every value of the
+// bracket lies in that interval, the copied elements hold all of the bracket's (and maybe
+// others, which the histogram passes and the gather skip) and become the working set, so
+// no further pass reads the input.  Otherwise nothing changes (the copy was only spent).
+CPS_HD inline void cp_adopt_spec(CpState &s, int64_t written, const CpConfig &c) {
+  const int32_t had = s.spec;
+  s.spec = 0;
+  if (!had || s.phase == PH_DONE || s.wbuf >= 0) return;
+  if (!(s.lo >= s.spec_a && s.hi <= s.spec_b)) return;
+  s.wbuf = 0;
+  s.side = 0;
+  s.wlen = written;
+  s.on_bracket = 0;
+  s.narrowed = 1;
   cp_plan(s, c);
 }
 

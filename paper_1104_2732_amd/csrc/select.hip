@@ -49,6 +49,10 @@ __device__ __attribute__((always_inline)) inline void dev_after_hist(CpState &s,
                                             const CpConfig &c) {
   cp_after_hist(s, b, below, cnt, c);
 }
+__device__ __attribute__((always_inline)) inline void dev_adopt_spec(CpState &s, int64_t written,
+                                                                    const CpConfig &c) {
+  cp_adopt_spec(s, written, c);
+}
 __device__ __attribute__((always_inline)) inline void dev_hist_narrow(CpState &s, const HistGeom<uint64_t> &g, int32_t b,
                                              int64_t below, int64_t cnt, const CpConfig &c) {
   cp_hist_narrow(s, g, b, below, cnt, c);
@@ -215,90 +219,6 @@ __device__ inline void split_drain(WaveOut<T> &o, int lane) {
   o.fh = o.ch;
 }
 
-// One tile of an evaluation pass: U vectors per thread.  FULL: every vector of the tile
-// lies inside the span (no bounds tests; every tile but a span's last is full).
-template <typename T, int U, bool CLAMP, bool SPLIT, bool FILTER, bool HIST, bool FULL>
-__device__ inline void eval_tile(const Span<T> &sp, int64_t base, int per_u, int me, T t, T yL,
-                                 T yR, T fmin, T fmax, WaveOut<T> &o, EvalAcc<T> &acc,
-                                 const PartBins<T> &pb) {
-  constexpr int V = Traits<T>::kVec;
-  using Vec = typename Traits<T>::Vec;
-  Vec raw[U];
-  bool valid[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int64_t vi = base + (int64_t)u * per_u + me;
-    valid[u] = FULL || vi < sp.nvec;
-    if (valid[u]) raw[u] = sp.V[vi];
-  }
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    T e[V];
-    vec_to_arr<T>(raw[u], e);
-    if (!SPLIT && HIST) {
-      // a counting evaluation: the counts on either side of t and the key bins only (the
-      // bracket narrows by the bins right after it, so f at t is not needed)
-#pragma unroll
-      for (int j = 0; j < V; ++j) {
-        const bool lt = valid[u] & (e[j] < t), gt = valid[u] & (e[j] > t);
-        acc.L += lt ? 1u : 0u;
-        acc.G += gt ? 1u : 0u;
-        count_part<T>(e[j], lt & (!FILTER | (e[j] > yL)), gt & (!FILTER | (e[j] < yR)), pb);
-      }
-      continue;
-    }
-    T a_part = 0, b_part = 0;
-#pragma unroll
-    for (int j = 0; j < V; ++j) eval_one<T, CLAMP>(e[j], valid[u], t, fmin, fmax, a_part, b_part, acc);
-    acc.A += (double)a_part;
-    acc.B += (double)b_part;
-    if (SPLIT) {
-#pragma unroll
-      for (int j = 0; j < V; ++j)
-        split_one<T, FILTER, HIST>(e[j], valid[u], t, yL, yR, o, me % kWave, pb);
-      split_flush<T>(o, me % kWave);
-    }
-  }
-}
-
-// One evaluation pass (optionally splitting) over this thread's share of the walk.
-template <typename T, int BLOCK, int U, bool CLAMP, bool SPLIT, bool FILTER, bool HIST>
-__device__ inline void eval_pass(const Walk<T> &wk, T t, T yL, T yR, T fmin, T fmax,
-                                       WaveOut<T> &o, EvalAcc<T> &acc, const PartBins<T> &pb) {
-  const int tid = threadIdx.x, lane = tid % kWave;
-  const Span<T> &sp = wk.sp;
-  const int64_t step_vecs = wk.wave_mode ? (int64_t)kWave * U : (int64_t)BLOCK * U;
-  const int64_t first = wk.wave_mode ? 0 : (int64_t)blockIdx.x * step_vecs;
-  const int64_t stride = wk.wave_mode ? step_vecs : (int64_t)gridDim.x * step_vecs;
-  const int me = wk.wave_mode ? lane : tid;
-  const int per_u = wk.wave_mode ? kWave : BLOCK;
-  for (int64_t base = first; base < sp.nvec; base += stride) {
-    if (base + (int64_t)U * per_u <= sp.nvec)
-      eval_tile<T, U, CLAMP, SPLIT, FILTER, HIST, true>(sp, base, per_u, me, t, yL, yR, fmin, fmax,
-                                                        o, acc, pb);
-    else
-      eval_tile<T, U, CLAMP, SPLIT, FILTER, HIST, false>(sp, base, per_u, me, t, yL, yR, fmin, fmax,
-                                                         o, acc, pb);
-  }
-  if (sp.nedge > 0 && wk.edge_owner && (wk.wave_mode || tid < kWave)) {
-    const bool have = lane < sp.nedge;
-    T v = have ? sp.W[edge_index(sp, lane)] : T(0);
-    if (!SPLIT && HIST) {
-      const bool lt = have && v < t, gt = have && v > t;
-      acc.L += lt ? 1u : 0u;
-      acc.G += gt ? 1u : 0u;
-      count_part<T>(v, lt && (!FILTER || v > yL), gt && (!FILTER || v < yR), pb);
-    } else {
-      T a_part = 0, b_part = 0;
-      eval_one<T, CLAMP>(v, have, t, fmin, fmax, a_part, b_part, acc);
-      acc.A += (double)a_part;
-      acc.B += (double)b_part;
-      if (SPLIT) split_one<T, FILTER, HIST>(v, have, t, yL, yR, o, lane, pb);
-    }
-  }
-  if (SPLIT) split_drain<T>(o, lane);
-}
-
 // Pass 0 with a proposed bracket (a, b) may also write the elements strictly inside it to
 // its wavefront's region, up to `cap` of them (the count goes on past the cap, so an
 // overflowing region is seen and its contents are not used).
@@ -365,6 +285,111 @@ __device__ inline void drain_inside(WaveOut<T> &o, int lane, uint32_t cap) {
     if (sel && pos < cap) o.region[pos] = col[j * kWave];
     o.lo += popc(m);
   }
+}
+
+// One tile of an evaluation pass: U vectors per thread.  FULL: every vector of the tile
+// lies inside the span (no bounds tests; every tile but a span's last is full).
+// SPEC (a counting evaluation only): the elements of [sa, sb] also go to the wavefront's
+// region of split buffer 0, staged in its LDS columns.
+template <typename T, int U, bool CLAMP, bool SPLIT, bool FILTER, bool HIST, bool FULL,
+          bool SPEC = false>
+__device__ inline void eval_tile(const Span<T> &sp, int64_t base, int per_u, int me, T t, T yL,
+                                 T yR, T fmin, T fmax, WaveOut<T> &o, EvalAcc<T> &acc,
+                                 const PartBins<T> &pb, T sa = T(0), T sb = T(0)) {
+  constexpr int V = Traits<T>::kVec;
+  using Vec = typename Traits<T>::Vec;
+  Vec raw[U];
+  bool valid[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t vi = base + (int64_t)u * per_u + me;
+    valid[u] = FULL || vi < sp.nvec;
+    if (valid[u]) raw[u] = sp.V[vi];
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    T e[V];
+    vec_to_arr<T>(raw[u], e);
+    if (!SPLIT && HIST) {
+      // a counting evaluation: the counts on either side of t and the key bins only (the
+      // bracket narrows by the bins right after it, so f at t is not needed)
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        const bool lt = valid[u] & (e[j] < t), gt = valid[u] & (e[j] > t);
+        acc.L += lt ? 1u : 0u;
+        acc.G += gt ? 1u : 0u;
+        count_part<T>(e[j], lt & (!FILTER | (e[j] > yL)), gt & (!FILTER | (e[j] < yR)), pb);
+        if (SPEC) {
+          const bool in = valid[u] & (e[j] >= sa) & (e[j] <= sb);
+          if (in) {
+            o.ring_lo[(o.cl & (Stage<T>::kS - 1)) * kWave + me % kWave] = e[j];
+            o.cl += 1;
+          }
+        }
+      }
+      if (SPEC) flush_inside<T>(o, me % kWave, o.top + 1);
+      continue;
+    }
+    T a_part = 0, b_part = 0;
+#pragma unroll
+    for (int j = 0; j < V; ++j) eval_one<T, CLAMP>(e[j], valid[u], t, fmin, fmax, a_part, b_part, acc);
+    acc.A += (double)a_part;
+    acc.B += (double)b_part;
+    if (SPLIT) {
+#pragma unroll
+      for (int j = 0; j < V; ++j)
+        split_one<T, FILTER, HIST>(e[j], valid[u], t, yL, yR, o, me % kWave, pb);
+      split_flush<T>(o, me % kWave);
+    }
+  }
+}
+
+// One evaluation pass (optionally splitting) over this thread's share of the walk.
+template <typename T, int BLOCK, int U, bool CLAMP, bool SPLIT, bool FILTER, bool HIST,
+          bool SPEC = false>
+__device__ inline void eval_pass(const Walk<T> &wk, T t, T yL, T yR, T fmin, T fmax,
+                                       WaveOut<T> &o, EvalAcc<T> &acc, const PartBins<T> &pb,
+                                       T sa = T(0), T sb = T(0)) {
+  const int tid = threadIdx.x, lane = tid % kWave;
+  const Span<T> &sp = wk.sp;
+  const int64_t step_vecs = wk.wave_mode ? (int64_t)kWave * U : (int64_t)BLOCK * U;
+  const int64_t first = wk.wave_mode ? 0 : (int64_t)blockIdx.x * step_vecs;
+  const int64_t stride = wk.wave_mode ? step_vecs : (int64_t)gridDim.x * step_vecs;
+  const int me = wk.wave_mode ? lane : tid;
+  const int per_u = wk.wave_mode ? kWave : BLOCK;
+  for (int64_t base = first; base < sp.nvec; base += stride) {
+    if (base + (int64_t)U * per_u <= sp.nvec)
+      eval_tile<T, U, CLAMP, SPLIT, FILTER, HIST, true, SPEC>(sp, base, per_u, me, t, yL, yR, fmin,
+                                                              fmax, o, acc, pb, sa, sb);
+    else
+      eval_tile<T, U, CLAMP, SPLIT, FILTER, HIST, false, SPEC>(sp, base, per_u, me, t, yL, yR, fmin,
+                                                               fmax, o, acc, pb, sa, sb);
+  }
+  if (sp.nedge > 0 && wk.edge_owner && (wk.wave_mode || tid < kWave)) {
+    const bool have = lane < sp.nedge;
+    T v = have ? sp.W[edge_index(sp, lane)] : T(0);
+    if (!SPLIT && HIST) {
+      const bool lt = have && v < t, gt = have && v > t;
+      acc.L += lt ? 1u : 0u;
+      acc.G += gt ? 1u : 0u;
+      count_part<T>(v, lt && (!FILTER || v > yL), gt && (!FILTER || v < yR), pb);
+      if (SPEC) {
+        if (have && v >= sa && v <= sb) {
+          o.ring_lo[(o.cl & (Stage<T>::kS - 1)) * kWave + lane] = v;
+          o.cl += 1;
+        }
+        flush_inside<T>(o, lane, o.top + 1);
+      }
+    } else {
+      T a_part = 0, b_part = 0;
+      eval_one<T, CLAMP>(v, have, t, fmin, fmax, a_part, b_part, acc);
+      acc.A += (double)a_part;
+      acc.B += (double)b_part;
+      if (SPLIT) split_one<T, FILTER, HIST>(v, have, t, yL, yR, o, lane, pb);
+    }
+  }
+  if (SPLIT) split_drain<T>(o, lane);
+  if (SPEC) drain_inside<T>(o, lane, o.top + 1);
 }
 
 template <typename T, int U, bool CLASSIFY, bool BRACKET, bool SPLIT, bool HIST, bool FULL>
@@ -768,6 +793,69 @@ __device__ __noinline__ int64_t gather_filtered(Walk<T> wk, T yL, T yR, int64_t 
   return written;
 }
 
+// The likely interval of a counting evaluation's copy, by the whole last workgroup after pass
+// 0: kSpecSample strided elements in the key bins of the bracket's range, then the bins of
+// the sample ranks q -/+ d around the rank's place q = p m among the m sampled elements
+// inside the bracket (p = (k - cL - 1/2) / (cR - cL), d = 4 sqrt(m p (1 - p)) + 2, four
+// binomial standard deviations).  The interval runs from the first key of the lower bin to
+// the last key of the upper one; with too few sampled elements nothing is set.
+constexpr int64_t kSpecSample = 4096;
+
+template <typename T, int BLOCK>
+__device__ __noinline__ void spec_interval(const T *x, int64_t n, const CpConfig &c,
+                                           Shared<T, BLOCK> &sh) {
+  using Key = typename Traits<T>::Key;
+  const int tid = threadIdx.x;
+  const CpState &s = sh.st;
+  const HistGeom<uint64_t> g = hist_geometry(s.lo, s.hi, c.dtype, c.hist_bits);
+  for (int b = tid; b < g.nbins; b += BLOCK) sh.rh[b] = 0u;
+  __syncthreads();
+  const int64_t S = n < kSpecSample ? n : kSpecSample, stride = n / S;
+  const Key klo = (Key)g.klo, khi = (Key)g.khi;
+  for (int64_t i = tid; i < S; i += BLOCK) {
+    const Key K = Traits<T>::key(x[i * stride]);
+    if (K >= klo && K <= khi) atomicAdd(&sh.rh[(uint32_t)((K - klo) >> g.shift)], 1u);
+  }
+  __syncthreads();
+  constexpr int BPT = kHistMaxBins / BLOCK;
+  uint64_t hv[BPT];
+  uint64_t tot = 0;
+#pragma unroll
+  for (int j = 0; j < BPT; ++j) {
+    const int b = tid * BPT + j;
+    hv[j] = b < g.nbins ? sh.rh[b] : 0u;
+    tot += hv[j];
+  }
+  uint64_t cum = block_exclusive_scan<BLOCK>(tot, sh.gbase);
+  if (tid == BLOCK - 1) sh.misc[3] = (int64_t)(cum + tot);
+  if (tid == 0) sh.misc[4] = sh.misc[5] = -1;
+  __syncthreads();
+  const double m = (double)sh.misc[3];
+  const double p = ((double)(s.k - s.cL) - 0.5) / (double)(s.cR - s.cL);
+  const double q = p * m, d = 4.0 * __builtin_sqrt(m * p * (1.0 - p)) + 2.0;
+  double rl = __builtin_floor(q - d), rh = __builtin_ceil(q + d);
+  rl = rl < 1.0 ? 1.0 : (rl > m ? m : rl);
+  rh = rh < rl ? rl : (rh > m ? m : rh);
+  const uint64_t r0 = (uint64_t)rl, r1 = (uint64_t)rh;
+#pragma unroll
+  for (int j = 0; j < BPT; ++j) {
+    if (cum < r0 && r0 <= cum + hv[j]) sh.misc[4] = tid * BPT + j;
+    if (cum < r1 && r1 <= cum + hv[j]) sh.misc[5] = tid * BPT + j;
+    cum += hv[j];
+  }
+  __syncthreads();
+  if (tid == 0 && m >= 16.0 && sh.misc[4] >= 0 && sh.misc[5] >= 0) {
+    CpState &w = sh.st;
+    const uint64_t a0 = g.klo + ((uint64_t)sh.misc[4] << g.shift);
+    uint64_t b1 = g.klo + (((uint64_t)sh.misc[5] + 1) << g.shift) - 1;
+    if (b1 > g.khi || b1 < a0) b1 = g.khi;
+    w.spec = 1;
+    w.spec_a = unkey_T(a0, c.dtype);
+    w.spec_b = unkey_T(b1, c.dtype);
+  }
+  __syncthreads();
+}
+
 // Workgroup partials each lane of the folding wavefront loads at once.
 constexpr int kFold = 4;
 
@@ -943,7 +1031,9 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
   } else {
     WaveOut<T> o;
     const int wvu = __builtin_amdgcn_readfirstlane(wv);
-    o.region = (CPS_GLOBAL T *)uniform_ptr(a.z[s.zout] + ((int64_t)bid * WPB + wvu) * Rw);
+    // (a counting evaluation's copy of the likely interval goes to split buffer 0)
+    const int zo = s.counted ? 0 : s.zout;
+    o.region = (CPS_GLOBAL T *)uniform_ptr(a.z[zo] + ((int64_t)bid * WPB + wvu) * Rw);
     o.top = (uint32_t)(Rw - 1);
     o.lo = o.hi = o.cl = o.ch = o.fl = o.fh = 0;
     o.ring_lo = sh.ring[wv][0];
@@ -965,7 +1055,17 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
       __syncthreads();
     }
     if (s.counted) {  // (never with infinities: those inputs do not split or count)
-      eval_pass<T, BLOCK, UNROLL, false, false, true, true>(wk, t, yL, yR, fmn, fmx, o, acc, pb);
+      if (s.spec && Rw > 0) {
+        eval_pass<T, BLOCK, UNROLL, false, false, true, true, true>(
+            wk, t, yL, yR, fmn, fmx, o, acc, pb, (T)s.spec_a, (T)s.spec_b);
+        if (lane == 0) {
+          sh.wseg[0][wv] = o.lo;
+          sh.wseg[1][wv] = 0;
+          written = o.lo;
+        }
+      } else {
+        eval_pass<T, BLOCK, UNROLL, false, false, true, true>(wk, t, yL, yR, fmn, fmx, o, acc, pb);
+      }
     } else if (!s.split) {
       if (clamp) eval_pass<T, BLOCK, SU, true, false, false, false>(wk, t, yL, yR, fmn, fmx, o, acc, pb);
       else eval_pass<T, BLOCK, UNROLL, false, false, false, false>(wk, t, yL, yR, fmn, fmx, o, acc, pb);
@@ -1102,6 +1202,11 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
         }
       }
     }
+    // a large input about to be counted from: the likely interval for the evaluation's copy
+    __syncthreads();
+    if (a.cfg.spec_min_n > 0 && a.n >= a.cfg.spec_min_n && a.seg_R > 0 &&
+        sh.st.phase == PH_EVAL && sh.st.counted && sh.st.wbuf < 0)
+      spec_interval<T, BLOCK>(a.x, a.n, a.cfg, sh);
   } else if (phase == PH_HIST) {
     const CpState &s0 = sh.st;
     const HistGeom<uint64_t> g = hist_geometry(s0.lo, s0.hi, a.cfg.dtype, a.cfg.hist_bits);
@@ -1145,12 +1250,12 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
           const int b = b0 + q * kWave < G ? b0 + q * kWave : 0;
           L[q] = a.si[0 * stride + b];
           Gt[q] = a.si[1 * stride + b];
+          W[q] = a.si[2 * stride + b];
           if (!count_only) {
             A[q] = a.sd[0 * stride + b];
             B[q] = a.sd[1 * stride + b];
             pr[q] = a.sd[2 * stride + b];
             su[q] = a.sd[3 * stride + b];
-            W[q] = a.si[2 * stride + b];
           }
         }
 #pragma unroll
@@ -1158,12 +1263,12 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
           if (b0 + q * kWave >= G) break;
           ri[0] += L[q];
           ri[1] += Gt[q];
+          ri[2] += W[q];
           if (!count_only) {
             rd[0] += A[q];
             rd[1] += B[q];
             rd[2] = fmax(rd[2], pr[q]);
             rd[3] = fmin(rd[3], su[q]);
-            ri[2] += W[q];
           }
         }
       }
@@ -1207,6 +1312,13 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
           if (a.stats && pidx < CPS_STATS_MAX_PASSES)
             a.stats->population[pidx] = s.phase == PH_DONE ? 0 : s.cR - s.cL;
         }
+      }
+      // a counting evaluation that also copied the likely interval: adopt the copy when the
+      // bracket now lies inside it
+      if (count_only && tid == 0) {
+        dev_adopt_spec(sh.st, ri[2], a.cfg);
+        if (a.stats && pidx < CPS_STATS_MAX_PASSES)
+          a.stats->population[pidx] = sh.st.phase == PH_DONE ? 0 : sh.st.cR - sh.st.cL;
       }
       for (int p = 0; p < 2; ++p)  // ready for the next pass
         for (int b = tid; b < pg[p].nbins; b += BLOCK) a.ghist[p * kHistMaxBins + b] = 0;

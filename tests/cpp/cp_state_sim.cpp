@@ -26,7 +26,7 @@ template <typename T>
 static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_threshold,
                double theta, int use_bracket, double blo, double bhi, int p0_split,
                int64_t p0_cap, int hist_bits, int count_first, int hist_compact, int p0_sums,
-               SimResult *out) {
+               int spec_mode, SimResult *out) {
   CpConfig c{};
   c.maxit = maxit;
   c.dtype = sizeof(T) == 4 ? 0 : 1;
@@ -43,6 +43,7 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
   c.hist_bits = hist_bits;
   c.hist_compact = hist_compact;  // 1 as the single-array kernel, 0 as the batched one
   c.count_first = count_first;
+  c.spec_min_n = spec_mode ? 1 : 0;
   // one workgroup: a single region per split buffer, as large as the input
   const int64_t R = n + 8;
   std::vector<T> z[2] = {std::vector<T>(R), std::vector<T>(R)};
@@ -97,6 +98,30 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
     if (!(s.phase == PH_PASS0 && s.p0_slow)) break;
   }
   if (s.phase == PH_PASS0) return -15;
+  if (s.phase == PH_EVAL && s.counted && c.spec_min_n && n >= c.spec_min_n) {
+    // the likely interval of the counting evaluation's copy: quantiles of a strided sample
+    // around the rank's fraction of the bracket (spec_mode 2 places it away from the rank,
+    // so that the copy is not adopted)
+    const int64_t S = n < 4096 ? n : 4096, stride = n / S;
+    std::vector<T> smp;
+    for (int64_t i = 0; i < S; ++i) {
+      const T v = x[i * stride];
+      if (v > (T)s.yL && v < (T)s.yR) smp.push_back(v);
+    }
+    if (smp.size() >= 16) {
+      std::sort(smp.begin(), smp.end());
+      const double m = (double)smp.size();
+      const double p = ((double)(s.k - s.cL) - 0.5) / (double)(s.cR - s.cL);
+      const double q = p * m, d = 4.0 * std::sqrt(m * p * (1.0 - p)) + 2.0;
+      int64_t rl = (int64_t)std::floor(q - d), rh = (int64_t)std::ceil(q + d);
+      if (spec_mode == 2) { rl = (int64_t)m - 2; rh = (int64_t)m - 1; }
+      rl = std::max<int64_t>(0, std::min<int64_t>(rl, (int64_t)m - 1));
+      rh = std::max<int64_t>(rl, std::min<int64_t>(rh, (int64_t)m - 1));
+      s.spec = 1;
+      s.spec_a = (double)smp[(size_t)rl];
+      s.spec_b = (double)smp[(size_t)rh];
+    }
+  }
   auto working = [&](int64_t &len) -> const T * {
     if (s.wbuf < 0) { len = s.wlen; return x; }
     if (s.wbuf == 2) { len = s.wlen; return zf.data(); }
@@ -151,6 +176,8 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
     // evaluation counts them without writing
     const bool counted = (s.split || s.counted) && c.hist_bits > 0;
     const bool count_only = counted && !s.split;
+    const bool spec = count_only && s.spec;
+    int64_t nspec = 0;  // elements of [spec_a, spec_b] copied to buffer 0
     HistGeom<uint64_t> pg[2] = {};
     std::vector<int64_t> ph[2];
     if (counted)
@@ -168,6 +195,7 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
       if (clamp) v = std::min(std::max(v, (T)s.fmin), (T)s.fmax);
       if (v < t) { e.L++; e.B += (double)(t - v); e.pred = std::max<double>(e.pred, v); }
       if (v > t) { e.G++; e.A += (double)(v - t); e.succ = std::min<double>(e.succ, v); }
+      if (spec && v >= (T)s.spec_a && v <= (T)s.spec_b) z[0][nspec++] = v;
       if (s.split || count_only) {
         const bool inb = !s.filter || (v > yL && v < yR);
         if (s.split && inb && v < t) zo[nl++] = v;
@@ -186,6 +214,7 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
       e.A = e.B = 0.0;
       e.pred = -INFINITY;
       e.succ = INFINITY;
+      e.written = nspec;
     }
     cp_after_eval(s, e, c);
     if (counted && s.phase == PH_HIST && (s.on_bracket || count_only)) {
@@ -197,6 +226,13 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
       while (b < pg[s.side].nbins && below + h[(size_t)b] < r) below += h[(size_t)b++];
       if (b >= pg[s.side].nbins) return -18;
       cp_hist_narrow(s, pg[s.side], b, below, h[(size_t)b], c);
+    }
+    if (count_only) {
+      cp_adopt_spec(s, nspec, c);
+      if (s.wbuf == 0) {
+        my_l = nspec;
+        my_r = 0;
+      }
     }
   }
   if (s.phase == PH_FINAL) {
@@ -234,14 +270,16 @@ extern "C" {
 
 int sim_select_f32(const float *x, int64_t n, int64_t k, int maxit, int64_t ft, double theta,
                    int ub, double blo, double bhi, int p0_split, int64_t p0_cap, int hist_bits,
-                   int count_first, int hist_compact, int p0_sums, SimResult *out) {
+                   int count_first, int hist_compact, int p0_sums, int spec_mode,
+                   SimResult *out) {
   return sim<float>(x, n, k, maxit, ft, theta, ub, blo, bhi, p0_split, p0_cap, hist_bits,
-                    count_first, hist_compact, p0_sums, out);
+                    count_first, hist_compact, p0_sums, spec_mode, out);
 }
 int sim_select_f64(const double *x, int64_t n, int64_t k, int maxit, int64_t ft, double theta,
                    int ub, double blo, double bhi, int p0_split, int64_t p0_cap, int hist_bits,
-                   int count_first, int hist_compact, int p0_sums, SimResult *out) {
+                   int count_first, int hist_compact, int p0_sums, int spec_mode,
+                   SimResult *out) {
   return sim<double>(x, n, k, maxit, ft, theta, ub, blo, bhi, p0_split, p0_cap, hist_bits,
-                     count_first, hist_compact, p0_sums, out);
+                     count_first, hist_compact, p0_sums, spec_mode, out);
 }
 }

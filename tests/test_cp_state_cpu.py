@@ -37,11 +37,11 @@ def sim(tmp_path_factory):
         fn.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int64,
                        ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                        ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                       ctypes.c_int, ctypes.POINTER(SimResult)]
+                       ctypes.c_int, ctypes.c_int, ctypes.POINTER(SimResult)]
         fn.restype = ctypes.c_int
 
     def run(x, k, maxit=64, final_threshold=64, theta=0.5, bracket=None, p0_split=False,
-            p0_cap=None, hist_bits=0, count_first=0, hist_compact=1, p0_sums=1):
+            p0_cap=None, hist_bits=0, count_first=0, hist_compact=1, p0_sums=1, spec_mode=0):
         r = SimResult()
         fn = L.sim_select_f32 if x.dtype == np.float32 else L.sim_select_f64
         ub = 1 if bracket is not None else 0
@@ -49,7 +49,7 @@ def sim(tmp_path_factory):
         cap = x.size if p0_cap is None else p0_cap
         rc = fn(x.ctypes.data, x.size, k, maxit, final_threshold, theta, ub, blo, bhi,
                 1 if p0_split else 0, cap, hist_bits, count_first, hist_compact, p0_sums,
-                ctypes.byref(r))
+                spec_mode, ctypes.byref(r))
         assert rc == 0, rc
         return r
     return run
@@ -80,7 +80,12 @@ def test_state_machine_matches_oracle(sim, oracle_mod, dist, dtype):
                          dict(hist_bits=3, final_threshold=2, theta=0.5, count_first=1),
                          dict(hist_bits=11, theta=1.0, count_first=1, hist_compact=0),
                          dict(hist_bits=2, final_threshold=1, theta=0.5, count_first=1,
-                              hist_compact=0)):
+                              hist_compact=0),
+                         dict(hist_bits=12, theta=1.0, count_first=1, spec_mode=1),
+                         dict(hist_bits=3, final_threshold=2, theta=1.0, count_first=1,
+                              spec_mode=1),
+                         dict(hist_bits=12, final_threshold=4, theta=1.0, count_first=1,
+                              spec_mode=2)):
                 _check(sim(x, k, **opts), ref, (dist, n, k, opts))
 
 
@@ -224,3 +229,23 @@ def test_count_first_then_compact(sim, oracle_mod, dist):
         assert r.passes <= most, (dist, k, r.passes)
         assert r.elements_read <= most * n + n // 4, (dist, k, r.elements_read / n)
         assert r.elements_written <= n // 4 + 8192, (dist, k, r.elements_written)
+
+
+@pytest.mark.parametrize("dist", ["normal", "uniform", "cauchy", "quantized_normal", "lognormal"])
+def test_count_first_with_likely_interval(sim, oracle_mod, dist):
+    """The counting evaluation also copies the elements of a likely interval (quantiles of a
+    strided sample around the rank); when the narrowed bracket lies inside it the copy is
+    the working set and the input is read twice in all.  An interval away from the rank
+    (spec_mode 2) is not adopted: the result is the same and a third read of x follows."""
+    n = 1 << 20
+    x = workloads.single_array(dist, n, np.float32, seed=13)
+    for k in (n // 100, (n + 1) // 2, n - n // 100):
+        ref = oracle_mod.select_kth(x, k)
+        r = sim(x, k, final_threshold=8192, theta=1.0, hist_bits=12, count_first=1, spec_mode=1)
+        _check(r, ref, (dist, k, "spec"))
+        assert r.passes == 2, (dist, k, r.passes)
+        assert r.elements_written <= n // 8, (dist, k, r.elements_written)
+        miss = sim(x, k, final_threshold=8192, theta=1.0, hist_bits=12, count_first=1,
+                   spec_mode=2)
+        _check(miss, ref, (dist, k, "miss"))
+        assert miss.passes == 3, (dist, k, miss.passes)

@@ -220,3 +220,25 @@ def test_default_path_counted_split_and_compaction(sel, oracle_mod, dtype, count
             if count_first and dist != "spike":
                 # the counting evaluation writes nothing; the compaction copies one bin
                 assert st["elements_written"] <= n // 4 + 8192, (dist, k, st["elements_written"])
+
+
+@pytest.mark.parametrize("dist", ["normal", "quantized_normal", "periodic"])
+def test_large_input_counting_with_interval_copy(sel, oracle_mod, dist):
+    """From 2^27 elements the counting evaluation also copies a likely interval (sample
+    quantiles around the rank) and the copy becomes the working set when the narrowed
+    bracket lies inside it: x is then read twice in all.  The periodic input has the
+    sample stride as its period, so every sampled element is 0 and the interval misses:
+    the copy is not adopted and a third pass over x finds the same exact result."""
+    n = (1 << 27) + 17
+    if dist == "periodic":
+        x = (np.arange(n, dtype=np.int64) % (n // 4096)).astype(np.float32)
+    else:
+        x = workloads.single_array(dist, n, np.float32, seed=8, tag="gpu-large")
+    xt = _dev(x)
+    for k in (1 + n // 100, (n + 1) // 2):
+        print(f"case large-interval {dist} n={n} k={k}", flush=True)
+        res, st = sel.select_kth(xt, k, stats=True)
+        assert_same_result(res, oracle_mod.select_kth(x, k), f"{dist} k={k}")
+        assert st["passes"] <= 3, (dist, k, st["passes"])
+    del xt
+    torch.cuda.empty_cache()
