@@ -794,12 +794,14 @@ __device__ __noinline__ int64_t gather_filtered(Walk<T> wk, T yL, T yR, int64_t 
 }
 
 // The likely interval of a counting evaluation's copy, by the whole last workgroup after pass
-// 0: kSpecSample strided elements in the key bins of the bracket's range, then the bins of
+// 0: kSpecSample elements (runs of kSpecRun neighbours at evenly spaced places, so that the
+// sample touches few pages) in the key bins of the bracket's range, then the bins of
 // the sample ranks q -/+ d around the rank's place q = p m among the m sampled elements
 // inside the bracket (p = (k - cL - 1/2) / (cR - cL), d = 4 sqrt(m p (1 - p)) + 2, four
 // binomial standard deviations).  The interval runs from the first key of the lower bin to
 // the last key of the upper one; with too few sampled elements nothing is set.
 constexpr int64_t kSpecSample = 4096;
+constexpr int64_t kSpecRun = 16;
 
 template <typename T, int BLOCK>
 __device__ __noinline__ void spec_interval(const T *x, int64_t n, const CpConfig &c,
@@ -810,10 +812,11 @@ __device__ __noinline__ void spec_interval(const T *x, int64_t n, const CpConfig
   const HistGeom<uint64_t> g = hist_geometry(s.lo, s.hi, c.dtype, c.hist_bits);
   for (int b = tid; b < g.nbins; b += BLOCK) sh.rh[b] = 0u;
   __syncthreads();
-  const int64_t S = n < kSpecSample ? n : kSpecSample, stride = n / S;
+  // (spec_min_n is far above kSpecSample: every run lies inside x)
+  const int64_t runs = kSpecSample / kSpecRun, stride = n / runs;
   const Key klo = (Key)g.klo, khi = (Key)g.khi;
-  for (int64_t i = tid; i < S; i += BLOCK) {
-    const Key K = Traits<T>::key(x[i * stride]);
+  for (int64_t i = tid; i < kSpecSample; i += BLOCK) {
+    const Key K = Traits<T>::key(x[(i / kSpecRun) * stride + i % kSpecRun]);
     if (K >= klo && K <= khi) atomicAdd(&sh.rh[(uint32_t)((K - klo) >> g.shift)], 1u);
   }
   __syncthreads();
