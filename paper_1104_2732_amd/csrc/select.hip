@@ -311,13 +311,12 @@ __device__ inline void eval_tile(const Span<T> &sp, int64_t base, int per_u, int
     T e[V];
     vec_to_arr<T>(raw[u], e);
     if (!SPLIT && HIST) {
-      // a counting evaluation: the counts on either side of t and the key bins only (the
-      // bracket narrows by the bins right after it, so f at t is not needed)
+      // a counting evaluation: the key bins of either side of t only (the bracket narrows
+      // by the bins right after it, so f at t is not needed, and the counts below and above
+      // t follow from the bins' totals and the bracket's counts)
 #pragma unroll
       for (int j = 0; j < V; ++j) {
         const bool lt = valid[u] & (e[j] < t), gt = valid[u] & (e[j] > t);
-        acc.L += lt ? 1u : 0u;
-        acc.G += gt ? 1u : 0u;
         count_part<T>(e[j], lt & (!FILTER | (e[j] > yL)), gt & (!FILTER | (e[j] < yR)), pb);
         if (SPEC) {
           const bool in = valid[u] & (e[j] >= sa) & (e[j] <= sb);
@@ -370,8 +369,6 @@ __device__ inline void eval_pass(const Walk<T> &wk, T t, T yL, T yR, T fmin, T f
     T v = have ? sp.W[edge_index(sp, lane)] : T(0);
     if (!SPLIT && HIST) {
       const bool lt = have && v < t, gt = have && v > t;
-      acc.L += lt ? 1u : 0u;
-      acc.G += gt ? 1u : 0u;
       count_part<T>(v, lt && (!FILTER || v > yL), gt && (!FILTER || v < yR), pb);
       if (SPEC) {
         if (have && v >= sa && v <= sb) {
@@ -661,6 +658,29 @@ __device__ inline void hist_walk(const Walk<T> &wk, typename Traits<T>::Key klo,
 // The bin holding rank r of a histogram's counts: an exclusive scan of the counts in a fixed
 // order.  Leaves the bin in misc[0] (-1 when no bin holds it), the count below it in
 // misc[1] and its own count in misc[2]; ends with a workgroup barrier.
+// The same on counts the caller has loaded (thread t holds bins t * BPT .. t * BPT + BPT-1).
+template <int BLOCK>
+__device__ inline void hist_pick_loaded(const uint64_t (&hv)[kHistMaxBins / BLOCK], uint64_t r,
+                                        uint64_t *wsum, int64_t *misc) {
+  const int tid = threadIdx.x;
+  constexpr int BPT = kHistMaxBins / BLOCK;
+  uint64_t tot = 0;
+#pragma unroll
+  for (int j = 0; j < BPT; ++j) tot += hv[j];
+  if (tid == 0) misc[0] = -1;
+  uint64_t cum = block_exclusive_scan<BLOCK>(tot, wsum);
+#pragma unroll
+  for (int j = 0; j < BPT; ++j) {
+    if (cum < r && r <= cum + hv[j]) {
+      misc[0] = tid * BPT + j;
+      misc[1] = (int64_t)cum;
+      misc[2] = (int64_t)hv[j];
+    }
+    cum += hv[j];
+  }
+  __syncthreads();
+}
+
 template <int BLOCK>
 __device__ inline void hist_pick(const uint64_t *gh, int nbins, uint64_t r, uint64_t *wsum,
                                  int64_t *misc) {
@@ -1237,6 +1257,27 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
       pg[0] = split_part_geometry(sh.st, 0, a.cfg);
       pg[1] = split_part_geometry(sh.st, 1, a.cfg);
     }
+    // a counting evaluation: both sides' bins, loaded once (their totals give the counts
+    // below and above t; the side that holds x_(k) is then narrowed from the same values)
+    constexpr int BPT = kHistMaxBins / BLOCK;
+    uint64_t hv0[BPT], hv1[BPT];
+    if (count_only) {
+      uint64_t t0 = 0, t1 = 0;
+#pragma unroll
+      for (int j = 0; j < BPT; ++j) {
+        const int b = tid * BPT + j;
+        hv0[j] = b < pg[0].nbins ? a.ghist[b] : 0;
+        hv1[j] = b < pg[1].nbins ? a.ghist[kHistMaxBins + b] : 0;
+        t0 += hv0[j];
+        t1 += hv1[j];
+      }
+      t0 = (uint64_t)wave_sum_i64((int64_t)t0);
+      t1 = (uint64_t)wave_sum_i64((int64_t)t1);
+      if (tid % kWave == 0) {
+        sh.i[0][tid / kWave] = (int64_t)t0;
+        sh.i[1][tid / kWave] = (int64_t)t1;
+      }
+    }
     __syncthreads();  // every thread has read the state before thread 0 advances it
     // the first wavefront folds the partials (as after pass 0)
     if (tid < kWave) {
@@ -1291,6 +1332,15 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
         EvalResult r;
         r.A = rd[0]; r.B = rd[1]; r.pred = rd[2]; r.succ = rd[3];
         r.L = ri[0]; r.G = ri[1]; r.written = ri[2];
+        if (count_only) {  // L = #(x <= yL) + the low side, G = #(x >= yR) + the high side
+          int64_t t0 = 0, t1 = 0;
+          for (int w = 0; w < BLOCK / kWave; ++w) {
+            t0 += sh.i[0][w];
+            t1 += sh.i[1][w];
+          }
+          r.L = s.cL + t0;
+          r.G = (s.n - s.cR) + t1;
+        }
         dev_after_eval(s, r, a.cfg);
       }
       if (a.stats && pidx < CPS_STATS_MAX_PASSES) {
@@ -1305,8 +1355,14 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
       if (sh.st.phase == PH_HIST && (sh.st.on_bracket || count_only)) {
         const CpState &s1 = sh.st;
         const int p = s1.side;
-        hist_pick<BLOCK>(a.ghist + p * kHistMaxBins, pg[p].nbins, (uint64_t)(s1.k - s1.cL), sh.gbase,
-                         sh.misc);
+        if (count_only) {
+          uint64_t hv[BPT];
+#pragma unroll
+          for (int j = 0; j < BPT; ++j) hv[j] = p ? hv1[j] : hv0[j];  // selects, no indexing
+          hist_pick_loaded<BLOCK>(hv, (uint64_t)(s1.k - s1.cL), sh.gbase, sh.misc);
+        } else
+          hist_pick<BLOCK>(a.ghist + p * kHistMaxBins, pg[p].nbins, (uint64_t)(s1.k - s1.cL),
+                           sh.gbase, sh.misc);
         if (tid == 0) {
           CpState &s = sh.st;
           const int32_t bsel = (int32_t)sh.misc[0];
