@@ -122,8 +122,11 @@ typedef struct cps_eval {
  *                   in those key bins instead of writing them; the bracket narrows to the
  *                   bin holding the rank, and the next pass over the input counts that
  *                   bin's elements and copies them to the workspace (when they are at most a
- *                   quarter of n).  1 (default) or 0 (the split writes both sides and counts
- *                   them as it goes). */
+ *                   quarter of n).  From 2^27 elements on, the counting evaluation also
+ *                   copies the elements of a likely interval (sample quantiles around the
+ *                   rank) to the workspace, and when the narrowed bracket lies inside it the
+ *                   copy replaces that next pass over x.  1 (default) or 0 (the split writes
+ *                   both sides and counts them as it goes). */
 typedef struct cps_options {
   int32_t maxit;
   int32_t final_threshold;
