@@ -103,9 +103,9 @@ struct Pass0Result {
 };
 
 // Results of one evaluation pass over the working set W at trial point t.  A counting
-// evaluation (CpState::counted) fills in only L and G (and its key bins): A and B are 0,
-// pred and succ -inf and +inf, since the bracket narrows by the bins right after it and
-// neither f at the ends nor their neighbours are used again.
+// evaluation (CpState::counted) gives only L and G (from its key bins' totals and the
+// bracket's counts): A and B are 0, pred and succ -inf and +inf, since the bracket narrows
+// by the bins right after it and neither f at the ends nor their neighbours are used again.
 struct EvalResult {
   double A, B;          // sums over W of (w - t) for w > t and (t - w) for w < t
   int64_t L, G;         // #(w < t), #(w > t) within W
