@@ -46,7 +46,7 @@ __global__ __launch_bounds__(kLmsBlock) void lms_residual_kernel(
         }
       }
       const double d = yi - s;
-      Rg[(c0 + c) * n + i] = d * d;
+      __builtin_nontemporal_store(d * d, &Rg[(c0 + c) * n + i]);  // written once, read later
     }
   }
 }
