@@ -132,10 +132,40 @@ __device__ inline void stage_one(T v, bool sel, T *ring, uint32_t &c, int lane) 
 // rh[kHistMaxBins..)), for a split pass that also counts the parts' elements.
 template <typename T> struct PartBins {
   typename Traits<T>::Key klo[2];
+  typename Traits<T>::Key span[2];  // khi - klo: a part's elements have klo <= key <= klo + span
+  bool has[2];                      // the part's key range is not empty
+  typename Traits<T>::Key ka, kab;  // a counting evaluation's copy: ka <= key <= ka + kab
   uint32_t last[2];  // nbins - 1
   int shift[2];
   uint32_t *rh;
 };
+
+// One element of a counting evaluation (over the input), on its ordered key alone: the low
+// side's elements are those with keys in [klo0, khi0] = [key(lo), key(t-)], the high
+// side's those in [klo1, khi1] = [key(t+), key(hi)] (the bracket's elements below and above
+// t exactly, as lo and hi bound them), so the side and the bin come from one key and two
+// unsigned range tests.  SPEC: an element of the copy's interval is staged in the lane's
+// LDS column.
+template <typename T, bool SPEC>
+__device__ inline void count_key(T v, bool valid, const PartBins<T> &pb, WaveOut<T> &o,
+                                 int lane) {
+  using Key = typename Traits<T>::Key;
+  const Key K = Traits<T>::key(v);
+  const Key d0 = K - pb.klo[0], d1 = K - pb.klo[1];
+  const bool l = valid & pb.has[0] & (d0 <= pb.span[0]);
+  const bool h = valid & pb.has[1] & (d1 <= pb.span[1]);
+  if (l | h) {
+    const uint32_t bin = l ? (uint32_t)(d0 >> pb.shift[0])
+                           : (uint32_t)(d1 >> pb.shift[1]) + (uint32_t)kHistMaxBins;
+    atomicAdd(&pb.rh[bin], 1u);
+  }
+  if (SPEC) {
+    if (valid & (K - pb.ka <= pb.kab)) {
+      o.ring_lo[(o.cl & (Stage<T>::kS - 1)) * kWave + lane] = v;
+      o.cl += 1;
+    }
+  }
+}
 
 // Count an element of the low part (l) or the high part (h) in that part's key bins.
 template <typename T>
@@ -293,13 +323,13 @@ __device__ inline void drain_inside(WaveOut<T> &o, int lane, uint32_t cap) {
 
 // One tile of an evaluation pass: U vectors per thread.  FULL: every vector of the tile
 // lies inside the span (no bounds tests; every tile but a span's last is full).
-// SPEC (a counting evaluation only): the elements of [sa, sb] also go to the wavefront's
-// region of split buffer 0, staged in its LDS columns.
+// SPEC (a counting evaluation only): the elements of the copy's key range (pb.ka, pb.kab)
+// also go to the wavefront's region of split buffer 0, staged in its LDS columns.
 template <typename T, int U, bool CLAMP, bool SPLIT, bool FILTER, bool HIST, bool FULL,
           bool SPEC = false>
 __device__ inline void eval_tile(const Span<T> &sp, int64_t base, int per_u, int me, T t, T yL,
                                  T yR, T fmin, T fmax, WaveOut<T> &o, EvalAcc<T> &acc,
-                                 const PartBins<T> &pb, T sa = T(0), T sb = T(0)) {
+                                 const PartBins<T> &pb) {
   constexpr int V = Traits<T>::kVec;
   using Vec = typename Traits<T>::Vec;
   Vec raw[U];
@@ -319,17 +349,7 @@ __device__ inline void eval_tile(const Span<T> &sp, int64_t base, int per_u, int
       // by the bins right after it, so f at t is not needed, and the counts below and above
       // t follow from the bins' totals and the bracket's counts)
 #pragma unroll
-      for (int j = 0; j < V; ++j) {
-        const bool lt = valid[u] & (e[j] < t), gt = valid[u] & (e[j] > t);
-        count_part<T>(e[j], lt & (!FILTER | (e[j] > yL)), gt & (!FILTER | (e[j] < yR)), pb);
-        if (SPEC) {
-          const bool in = valid[u] & (e[j] >= sa) & (e[j] <= sb);
-          if (in) {
-            o.ring_lo[(o.cl & (Stage<T>::kS - 1)) * kWave + me % kWave] = e[j];
-            o.cl += 1;
-          }
-        }
-      }
+      for (int j = 0; j < V; ++j) count_key<T, SPEC>(e[j], valid[u], pb, o, me % kWave);
       if (SPEC) flush_inside<T>(o, me % kWave, o.top + 1);
       continue;
     }
@@ -351,8 +371,7 @@ __device__ inline void eval_tile(const Span<T> &sp, int64_t base, int per_u, int
 template <typename T, int BLOCK, int U, bool CLAMP, bool SPLIT, bool FILTER, bool HIST,
           bool SPEC = false>
 __device__ inline void eval_pass(const Walk<T> &wk, T t, T yL, T yR, T fmin, T fmax,
-                                       WaveOut<T> &o, EvalAcc<T> &acc, const PartBins<T> &pb,
-                                       T sa = T(0), T sb = T(0)) {
+                                       WaveOut<T> &o, EvalAcc<T> &acc, const PartBins<T> &pb) {
   const int tid = threadIdx.x, lane = tid % kWave;
   const Span<T> &sp = wk.sp;
   const int64_t step_vecs = wk.wave_mode ? (int64_t)kWave * U : (int64_t)BLOCK * U;
@@ -363,24 +382,17 @@ __device__ inline void eval_pass(const Walk<T> &wk, T t, T yL, T yR, T fmin, T f
   for (int64_t base = first; base < sp.nvec; base += stride) {
     if (base + (int64_t)U * per_u <= sp.nvec)
       eval_tile<T, U, CLAMP, SPLIT, FILTER, HIST, true, SPEC>(sp, base, per_u, me, t, yL, yR, fmin,
-                                                              fmax, o, acc, pb, sa, sb);
+                                                              fmax, o, acc, pb);
     else
       eval_tile<T, U, CLAMP, SPLIT, FILTER, HIST, false, SPEC>(sp, base, per_u, me, t, yL, yR, fmin,
-                                                               fmax, o, acc, pb, sa, sb);
+                                                               fmax, o, acc, pb);
   }
   if (sp.nedge > 0 && wk.edge_owner && (wk.wave_mode || tid < kWave)) {
     const bool have = lane < sp.nedge;
     T v = have ? sp.W[edge_index(sp, lane)] : T(0);
     if (!SPLIT && HIST) {
-      const bool lt = have && v < t, gt = have && v > t;
-      count_part<T>(v, lt && (!FILTER || v > yL), gt && (!FILTER || v < yR), pb);
-      if (SPEC) {
-        if (have && v >= sa && v <= sb) {
-          o.ring_lo[(o.cl & (Stage<T>::kS - 1)) * kWave + lane] = v;
-          o.cl += 1;
-        }
-        flush_inside<T>(o, lane, o.top + 1);
-      }
+      count_key<T, SPEC>(v, have, pb, o, lane);
+      if (SPEC) flush_inside<T>(o, lane, o.top + 1);
     } else {
       T a_part = 0, b_part = 0;
       eval_one<T, CLAMP>(v, have, t, fmin, fmax, a_part, b_part, acc);
@@ -1071,20 +1083,28 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
     pb.rh = sh.rh;
     int nb[2] = {0, 0};
     if (hist) {
+      using Key = typename Traits<T>::Key;
       for (int p = 0; p < 2; ++p) {
         const HistGeom<uint64_t> g = split_part_geometry(s, p, a.cfg);
-        pb.klo[p] = (typename Traits<T>::Key)g.klo;
+        pb.klo[p] = (Key)g.klo;
+        pb.has[p] = g.nbins > 0;
+        pb.span[p] = g.nbins > 0 ? (Key)(g.khi - g.klo) : (Key)0;
         pb.last[p] = g.nbins > 0 ? (uint32_t)(g.nbins - 1) : 0u;
         pb.shift[p] = g.shift;
         nb[p] = g.nbins;
         for (int b = tid; b < g.nbins; b += BLOCK) sh.rh[p * kHistMaxBins + b] = 0u;
+      }
+      pb.ka = pb.kab = 0;
+      if (s.counted && s.spec) {  // spec_a <= spec_b, both values of T
+        pb.ka = Traits<T>::key((T)s.spec_a);
+        pb.kab = Traits<T>::key((T)s.spec_b) - pb.ka;
       }
       __syncthreads();
     }
     if (s.counted) {  // (never with infinities: those inputs do not split or count)
       if (s.spec && Rw > 0) {
         eval_pass<T, BLOCK, UNROLL, false, false, true, true, true>(
-            wk, t, yL, yR, fmn, fmx, o, acc, pb, (T)s.spec_a, (T)s.spec_b);
+            wk, t, yL, yR, fmn, fmx, o, acc, pb);
         if (lane == 0) {
           sh.wseg[0][wv] = o.lo;
           sh.wseg[1][wv] = 0;
