@@ -210,29 +210,30 @@ __device__ void block_hist(const Span<T> &sp, typename Traits<T>::Key klo,
 // rh[0..) for the low side, rh[kHistMaxBins / 2..) for the high side).  Nothing is written.
 template <typename T> struct SideBins {
   typename Traits<T>::Key klo[2];
-  uint32_t last[2];  // nbins - 1
+  typename Traits<T>::Key span[2];  // khi - klo
+  bool has[2];                      // the side's key range is not empty
   int shift[2];
 };
 
+// On the element's ordered key alone: the low side's elements are those with keys in
+// [key(lo), key(t-)], the high side's those in [key(t+), key(hi)] (the bracket's elements
+// below and above t exactly); the counts below and above t follow from the bins' totals.
 template <typename T>
-__device__ inline void count_side(T v, bool valid, T t, T yL, T yR, const SideBins<T> &sb,
-                                  uint32_t *rh, EvalAcc<T> &acc) {
-  const bool lt = valid && v < t, gt = valid && v > t;
-  acc.L += lt ? 1u : 0u;
-  acc.G += gt ? 1u : 0u;
-  const bool l = lt && v > yL, h = gt && v < yR;
-  if (l || h) {
-    // an element of a side lies in that side's key range; the clamp keeps LDS safe
-    const int p = l ? 0 : 1;
-    uint32_t bin = (uint32_t)((Traits<T>::key(v) - sb.klo[p]) >> sb.shift[p]);
-    bin = bin < sb.last[p] ? bin : sb.last[p];
-    atomicAdd(&rh[p * (kHistMaxBins / 2) + bin], 1u);
+__device__ inline void count_side(T v, bool valid, const SideBins<T> &sb, uint32_t *rh) {
+  using Key = typename Traits<T>::Key;
+  const Key K = Traits<T>::key(v);
+  const Key d0 = K - sb.klo[0], d1 = K - sb.klo[1];
+  const bool l = valid & sb.has[0] & (d0 <= sb.span[0]);
+  const bool h = valid & sb.has[1] & (d1 <= sb.span[1]);
+  if (l | h) {
+    const uint32_t bin = l ? (uint32_t)(d0 >> sb.shift[0])
+                           : (uint32_t)(d1 >> sb.shift[1]) + (uint32_t)(kHistMaxBins / 2);
+    atomicAdd(&rh[bin], 1u);
   }
 }
 
 template <typename T, int BLOCK, int U>
-__device__ void block_count(const Span<T> &sp, T t, T yL, T yR, const SideBins<T> &sb,
-                            uint32_t *rh, EvalAcc<T> &acc) {
+__device__ void block_count(const Span<T> &sp, const SideBins<T> &sb, uint32_t *rh) {
   constexpr int V = Traits<T>::kVec;
   using Vec = typename Traits<T>::Vec;
   const int tid = threadIdx.x;
@@ -250,11 +251,10 @@ __device__ void block_count(const Span<T> &sp, T t, T yL, T yR, const SideBins<T
       T e[V];
       vec_to_arr<T>(raw[u], e);
 #pragma unroll
-      for (int j = 0; j < V; ++j) count_side<T>(e[j], valid[u], t, yL, yR, sb, rh, acc);
+      for (int j = 0; j < V; ++j) count_side<T>(e[j], valid[u], sb, rh);
     }
   }
-  if (sp.nedge > 0 && tid < sp.nedge)
-    count_side<T>(sp.W[edge_index(sp, tid)], true, t, yL, yR, sb, rh, acc);
+  if (sp.nedge > 0 && tid < sp.nedge) count_side<T>(sp.W[edge_index(sp, tid)], true, sb, rh);
 }
 
 // The bin holding rank r of `nbins` LDS counters: an exclusive scan in a fixed order.
@@ -442,23 +442,30 @@ __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out,
       for (int p = 0; p < 2; ++p) {
         pg[p] = split_part_geometry(s, p, cs);
         sb.klo[p] = (typename Traits<T>::Key)pg[p].klo;
-        sb.last[p] = pg[p].nbins > 0 ? (uint32_t)(pg[p].nbins - 1) : 0u;
+        sb.has[p] = pg[p].nbins > 0;
+        sb.span[p] = pg[p].nbins > 0 ? (typename Traits<T>::Key)(pg[p].khi - pg[p].klo) : 0;
         sb.shift[p] = pg[p].shift;
       }
       for (int b = tid; b < kHistMaxBins; b += BLOCK) sh.rh[b] = 0u;
       __syncthreads();
-      block_count<T, BLOCK, U>(sp, t, yL, yR, sb, sh.rh, acc);
+      block_count<T, BLOCK, U>(sp, sb, sh.rh);
+      __syncthreads();
+      // each side's total: L = #(x <= yL) + the low side, G = #(x >= yR) + the high side
       double dv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       int dop[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      int64_t iv[8] = {(int64_t)acc.L, (int64_t)acc.G, 0, 0, 0, 0, 0, 0};
+      int64_t iv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      for (int b = tid; b < kHistMaxBins / 2; b += BLOCK) {
+        iv[0] += sh.rh[b];
+        iv[1] += sh.rh[kHistMaxBins / 2 + b];
+      }
       block_reduce<BLOCK, 0, 2>(dv, dop, iv, false, sh.d, sh.i);
       if (tid == 0) {
         EvalResult r;
         r.A = r.B = 0.0;
         r.pred = -__builtin_inf();
         r.succ = __builtin_inf();
-        r.L = iv[0];
-        r.G = iv[1];
+        r.L = sh.st.cL + iv[0];
+        r.G = (sh.st.n - sh.st.cR) + iv[1];
         r.written = 0;
         bdev_after_eval(sh.st, r, a.cfg);
       }
