@@ -195,7 +195,8 @@ __device__ void block_hist(const Span<T> &sp, typename Traits<T>::Key klo,
 #pragma unroll
       for (int j = 0; j < V; ++j) {
         const Key K = Traits<T>::key(e[j]);
-        if (valid[u] && K >= klo && K <= khi) atomicAdd(&rh[(uint32_t)((K - klo) >> shift)], 1u);
+        const Key d = K - klo;  // in range: klo <= K <= khi
+        if (valid[u] & (d <= (Key)(khi - klo))) atomicAdd(&rh[(uint32_t)(d >> shift)], 1u);
       }
     }
   }
@@ -306,9 +307,24 @@ __device__ void block_pass0(const Span<T> &sp, P0Acc<T> &acc) {
       T e[V];
       vec_to_arr<T>(raw[u], e);
       T s_part = 0, aa = 0, bA = 0, ab = 0, bB = 0;
+      if (!CLASSIFY) {
+        // the running extremes change only where a lane's element reaches them (as in the
+        // single-array pass 0: the wavefront tests first, NaN compares false in both)
+        bool near = false;
 #pragma unroll
-      for (int j = 0; j < V; ++j)
-        pass0_one<T, CLASSIFY, false>(e[j], valid[u], ba, bb, s_part, aa, bA, ab, bB, acc);
+        for (int j = 0; j < V; ++j) near |= valid[u] & ((e[j] <= acc.mn) | (e[j] >= acc.mx));
+        if (ballot(near) != 0) {
+#pragma unroll
+          for (int j = 0; j < V; ++j) p0_extremes<T>(e[j], valid[u], acc);
+        }
+#pragma unroll
+        for (int j = 0; j < V; ++j)
+          pass0_one<T, false, false, true>(e[j], valid[u], ba, bb, s_part, aa, bA, ab, bB, acc);
+      } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j)
+          pass0_one<T, true, false>(e[j], valid[u], ba, bb, s_part, aa, bA, ab, bB, acc);
+      }
       acc.sum += (double)s_part;
     }
   }
