@@ -8,14 +8,18 @@
 //               proposed bracket;
 //   eval passes A(t), B(t), #(w<t), #(w>t), largest w<t and smallest w>t over the working
 //               set at the trial point t (the objective and subgradient of Section 3 in
-//               one fused reduction); once the bracket is small the same pass splits the
+//               one fused reduction).  Once the bracket is small enough the exact finish
+//               starts: by default the evaluation at that trial point only counts the
+//               bracket's elements on either side of t in key bins (and, for large
+//               inputs, copies a likely interval of values sampled after pass 0), and the
+//               bracket narrows to the bin of the rank; otherwise the pass splits the
 //               bracket's elements at t into per-wavefront private regions of a
 //               workspace buffer (count-and-compact, with no atomics), and later passes
 //               read only the side that holds x_(k);
-//   histogram   once the bracket's elements are compacted, each pass counts them in
-//               key bins of the bracket's value range and narrows the bracket to the
-//               bin holding the remaining rank (an exact select on the compacted
-//               elements, in place of the paper's sort of them);
+//   histogram   each pass counts the working set in key bins of the bracket's value range
+//               and narrows the bracket to the bin holding the remaining rank (an exact
+//               select, in place of the paper's sort of the compacted elements); a pass
+//               over x also copies the narrowed bracket's elements when they are few;
 //   gather      the bracket's remaining elements are copied into one contiguous buffer;
 //   final       one workgroup selects the remaining rank exactly (radix select on the
 //               ordered keys).
@@ -110,8 +114,8 @@ __device__ inline bool goes_high(T v, bool valid, T t, T hi_ex) {
 
 // Per-wavefront split output: the low part grows up from the start of the wavefront's
 // region, the high part down from its end.  lo / hi count the elements in the region
-// (wave-uniform).  The pass-0 compaction writes the low part directly; evaluation splits
-// stage both parts in LDS first (per lane: cl / ch elements staged, fl / fh of them moved).
+// (wave-uniform).  Every writer stages in LDS first (per lane: cl / ch elements staged,
+// fl / fh of them moved): splits both parts, the compactions and copies the low part.
 template <typename T> struct WaveOut {
   CPS_GLOBAL T *region;  // wave-uniform
   uint32_t top;          // Rw - 1
