@@ -122,7 +122,7 @@ typedef struct cps_eval {
  *                   in those key bins instead of writing them; the bracket narrows to the
  *                   bin holding the rank, and the next pass over the input counts that
  *                   bin's elements and copies them to the workspace (when they are at most a
- *                   quarter of n).  From 2^27 elements on, the counting evaluation also
+ *                   quarter of n).  From 256 MiB of input on, the counting evaluation also
  *                   copies the elements of a likely interval (sample quantiles around the
  *                   rank) to the workspace, and when the narrowed bracket lies inside it the
  *                   copy replaces that next pass over x.  1 (default) or 0 (the split writes

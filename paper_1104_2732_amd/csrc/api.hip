@@ -146,11 +146,12 @@ int resolve(cps_handle *h, int64_t n, int dtype, const cps_options *opt, Resolve
   r.cfg.hist_bits = o.hist_bits;
   r.cfg.hist_compact = 1;  // the single-array kernel compacts in its histogram passes
   r.cfg.count_first = o.count_first ? 1 : 0;
-  // from 2^27 elements on, the counting evaluation also copies a likely interval (below,
-  // the pass over x that the copy saves costs less than the copy and the interval: measured
-  // 2^24 float32 selections 0.169-0.21 ms with it against 0.156-0.196 without, 2^28 ones
-  // 0.64-0.66 against 0.69-0.73)
-  r.cfg.spec_min_n = (int64_t)1 << 27;
+  // from 256 MiB of input on (2^26 float or 2^25 double elements), the counting evaluation
+  // also copies a likely interval; below, the pass over x that the copy saves costs about
+  // what the copy and the interval's sample cost (measured: 2^24 float32 selections 0.169-
+  // 0.21 ms with it against 0.156-0.196 without; 2^25 float32 even; 2^26 float32 5 %,
+  // 2^25 float64 4 %, 2^26 float64 10 % and 2^28 ones ~20 % faster with it)
+  r.cfg.spec_min_n = ((int64_t)1 << 28) / (int64_t)dtype_size(dtype);
   const int per_cu = dtype == CPS_F32 ? h->max_blocks_f32 : h->max_blocks_f64;
   const int gmax = h->cu_count * per_cu;
   if (gmax < 1) return CPS_ENODEV;

@@ -224,7 +224,7 @@ def test_default_path_counted_split_and_compaction(sel, oracle_mod, dtype, count
 
 @pytest.mark.parametrize("dist", ["normal", "quantized_normal", "periodic"])
 def test_large_input_counting_with_interval_copy(sel, oracle_mod, dist):
-    """From 2^27 elements the counting evaluation also copies a likely interval (sample
+    """From 256 MiB of input the counting evaluation also copies a likely interval (sample
     quantiles around the rank) and the copy becomes the working set when the narrowed
     bracket lies inside it: x is then read twice in all.  The periodic input has the
     sample stride as its period, so every sampled element is 0 and the interval misses:
