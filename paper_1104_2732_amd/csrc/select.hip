@@ -259,10 +259,32 @@ __device__ inline void split_drain(WaveOut<T> &o, int lane) {
 // Key bins of a proposal's interior, counted by pass 0 (one set of counters in LDS).
 template <typename T> struct InteriorBins {
   typename Traits<T>::Key klo;
+  typename Traits<T>::Key span;    // khi - klo: the interior's keys are klo .. klo + span
+  typename Traits<T>::Key ka, kb;  // keys of the proposed ends
   uint32_t last;  // nbins - 1
   int shift;
   uint32_t *rh;
 };
+
+// The device proposal's pass 0 on one element's ordered key (after its extremes and sum):
+// #(x <= a) and #(x < b) by key compares, and an interior element (key in [key(a+),
+// key(b-)]) staged in the lane's column and counted in its bin.  The keys order the values
+// as the compares do (NaN aside: a NaN makes this fast pass 0 repeat with the
+// classification, whose counts are taken by value).
+template <typename T>
+__device__ inline void p0_key(T v, bool valid, const InteriorBins<T> &ib, P0Acc<T> &acc,
+                              WaveOut<T> &o, int lane) {
+  using Key = typename Traits<T>::Key;
+  const Key K = Traits<T>::key(v);
+  acc.cle_a += (valid & (K <= ib.ka)) ? 1u : 0u;
+  acc.clt_b += (valid & (K < ib.kb)) ? 1u : 0u;
+  const Key d = K - ib.klo;
+  if (valid & (d <= ib.span)) {
+    o.ring_lo[(o.cl & (Stage<T>::kS - 1)) * kWave + lane] = v;
+    o.cl += 1;
+    atomicAdd(&ib.rh[(uint32_t)(d >> ib.shift)], 1u);
+  }
+}
 
 // An interior element goes to this lane's staging column (low part) and, with HIST, to its
 // key bin.
@@ -440,16 +462,26 @@ __device__ inline void pass0_tile(const Span<T> &sp, int64_t base, int per_u, in
 #pragma unroll
         for (int j = 0; j < V; ++j) p0_extremes<T>(e[j], valid[u], acc);
       }
+      if (BRACKET && SPLIT && HIST) {  // the device proposal that counts its interior
 #pragma unroll
-      for (int j = 0; j < V; ++j)
-        pass0_one<T, false, BRACKET, true, !HIST>(e[j], valid[u], ba, bb, s_part, aa, bA, ab, bB,
-                                                  acc);
+        for (int j = 0; j < V; ++j)
+          pass0_one<T, false, false, true>(e[j], valid[u], ba, bb, s_part, aa, bA, ab, bB, acc);
+        const int lane = me % kWave;
+#pragma unroll
+        for (int j = 0; j < V; ++j) p0_key<T>(e[j], valid[u], ib, acc, o, lane);
+        flush_inside<T>(o, lane, cap);
+      } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j)
+          pass0_one<T, false, BRACKET, true, !HIST>(e[j], valid[u], ba, bb, s_part, aa, bA, ab,
+                                                    bB, acc);
+      }
     } else {
 #pragma unroll
       for (int j = 0; j < V; ++j)
         pass0_one<T, true, BRACKET>(e[j], valid[u], ba, bb, s_part, aa, bA, ab, bB, acc);
     }
-    if (SPLIT) {
+    if (SPLIT && !(BRACKET && HIST && !CLASSIFY)) {
       // staged in LDS and moved in 16-byte vectors (per-element stores of a small interior
       // cost a store instruction per element position)
       const int lane = me % kWave;
@@ -930,6 +962,9 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
     const bool p0h = p0s && !p0_slow && g0.nbins > 0;
     InteriorBins<T> ib;
     ib.klo = (typename Traits<T>::Key)g0.klo;
+    ib.span = g0.nbins > 0 ? (typename Traits<T>::Key)(g0.khi - g0.klo) : 0;
+    ib.ka = Traits<T>::key(ba);
+    ib.kb = Traits<T>::key(bb);
     ib.last = g0.nbins > 0 ? (uint32_t)(g0.nbins - 1) : 0u;
     ib.shift = g0.shift;
     ib.rh = sh.rh;
