@@ -22,8 +22,10 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 
 HBM traffic of the selection kernel comes from two rocprofv3 counter runs of
 this same program with --copy-calibration (FETCH_SIZE, then WRITE_SIZE), each
-scaled by what the counter reads for a plain elementwise copy of 2^28 float32
-values (1 GiB read, 1 GiB written) in the same run:
+scaled by what the counter reads for dispatches of known traffic in the same run:
+the selection kernel's own pass 0 over 2^28 float32 values (1 GiB read with its
+nontemporal loads) for FETCH_SIZE, a plain elementwise copy of 2^28 float32
+values (1 GiB written) for WRITE_SIZE:
     rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR_F -- python3 bench.py \
         --steps 1 --warmup 0 --no-cpu-baseline --copy-calibration
     rocprofv3 --pmc WRITE_SIZE ... (same, into DIR_W)
@@ -87,22 +89,34 @@ def _counter_rows(directory: str, counter: str):
 
 
 def traffic_from(fetch_dir: str, write_dir: str) -> dict:
-    """Calibrate FETCH_SIZE and WRITE_SIZE on the copy of known size and scale the selection
-    kernel's per-dispatch readings; writes and returns the traffic record."""
-    copy_bytes = float(4 << 28)
+    """Calibrate FETCH_SIZE and WRITE_SIZE on dispatches of known traffic and scale the
+    selection kernel's per-dispatch readings; writes and returns the traffic record.
+    FETCH_SIZE is scaled by what it reads for the selection kernel's own pass 0 over 2^28
+    float32 values (rank 1 of an input with a unique minimum: one nontemporal read of 1 GiB,
+    the first two selection dispatches of the run); the plain copy's factor is reported
+    beside it.  WRITE_SIZE is scaled by the copy's (1 GiB written)."""
+    gib = float(4 << 28)
     out = {"kernel_source_hash": kernel_source_hash(), "kernel": "cp_select_kernel"}
     per_launch = 0.0
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = _counter_rows(d, counter)
         copies = [v for (name, v) in rows if "neg_kernel" in name]
         sel = [v for (name, v) in rows if "cp_select_kernel" in name]
-        if not copies or not sel:
-            raise SystemExit(f"{counter}: no calibration copy or no selection dispatch in {d}")
-        factor = copy_bytes / (float(np.mean(copies)) * 1024.0)
-        kib = float(np.mean(sel))
-        out[counter] = {"copy_KiB": float(np.mean(copies)), "factor": factor,
-                        "select_KiB_per_dispatch": kib, "select_dispatches": len(sel),
-                        "bytes_per_launch": kib * 1024.0 * factor}
+        if not copies or len(sel) < 3:
+            raise SystemExit(f"{counter}: no calibration dispatches or no selection dispatch in {d}")
+        cal, sweep = sel[:2], sel[2:]
+        copy_factor = gib / (float(np.mean(copies)) * 1024.0)
+        rec = {"copy_KiB": float(np.mean(copies)), "copy_factor": copy_factor}
+        if counter == "FETCH_SIZE":
+            factor = gib / (float(np.mean(cal)) * 1024.0)
+            rec["pass0_read_KiB"] = float(np.mean(cal))
+            rec["pass0_read_factor"] = factor
+        else:
+            factor = copy_factor
+        kib = float(np.mean(sweep))
+        rec.update({"factor": factor, "select_KiB_per_dispatch": kib,
+                    "select_dispatches": len(sweep), "bytes_per_launch": kib * 1024.0 * factor})
+        out[counter] = rec
         per_launch += kib * 1024.0 * factor
     out["bytes_per_launch"] = per_launch
     os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
@@ -240,6 +254,7 @@ def schedules_leg(sel, cps, torch, reps: int = 3) -> dict:
               "split_at_first_trial_point": dict(count_first=0),
               "default_count_at_first_trial_point": dict()}
     out = {"workload": "n=2^28 N(0,1), k in {n/100, median}", "cases": {}}
+    evals = []
     res = sel.new_results(1)
     stats = sel.new_stats()
     for dtype in DTYPES:
@@ -254,12 +269,86 @@ def schedules_leg(sel, cps, torch, reps: int = 3) -> dict:
                 sel.select_kth_async(xt, k, res, stats, options=o)
                 torch.cuda.synchronize()
                 st = stats.cpu().numpy().view(cps.STATS_DTYPE)[0]
-                out["cases"][f"{np.dtype(dtype).name} k={k} {name}"] = {
-                    "ms": round(ms, 4), "passes_over_x": int(st["passes"]),
-                    "work_passes": int(st["work_passes"]), "kelley_steps": int(st["kelley_steps"])}
+                case = {"ms": round(ms, 4), "passes_over_x": int(st["passes"]),
+                        "work_passes": int(st["work_passes"]),
+                        "kelley_steps": int(st["kelley_steps"])}
+                if name == "cutting_plane_to_the_end":
+                    # the iterated fused evaluation (Section 4, Algorithm 1): each pass's time
+                    # from the publication of the state before it to the last workgroup's
+                    # arrival after it (device clock, 100 MHz), n * sizeof(T) bytes per pass
+                    np_ = min(int(st["work_passes"]), cps.STATS_MAX_PASSES)
+                    us = [(int(st["t_arrive"][i]) - int(st["t_publish"][i - 1])) * 1e-2
+                          for i in range(1, np_) if st["kind"][i] == cps.PASS_EVAL
+                          and st["working"][i] == n]
+                    gbps = [n * np.dtype(dtype).itemsize / (u * 1e-6) / 1e9 for u in us]
+                    case["eval_passes"] = len(us)
+                    case["eval_pass_us_mean"] = round(float(np.mean(us)), 2)
+                    case["eval_pass_GBps_mean"] = round(float(np.mean(gbps)), 1)
+                    case["eval_pass_frac_of_peak"] = round(float(np.mean(gbps)) / HBM_PEAK_GBS, 3)
+                    evals.extend(gbps)
+                out["cases"][f"{np.dtype(dtype).name} k={k} {name}"] = case
         del xt
         torch.cuda.empty_cache()
+    # the fused evaluation pass iterated by the cutting plane, over the whole 2^28 array: its
+    # own roofline (per-pass algorithmic bytes n * sizeof(T) over the per-pass device time)
+    out["iterated_eval_pass"] = {
+        "passes": len(evals), "GBps_mean": round(float(np.mean(evals)), 1),
+        "frac_of_peak": round(float(np.mean(evals)) / HBM_PEAK_GBS, 3),
+        "note": "evaluation passes of the cutting-plane-to-the-end schedule, both dtypes"}
     return out
+
+
+def small_leg(sel, cps, torch, seeds=range(10), reps: int = 10) -> dict:
+    """n = 2^20 float32 uniform[0,1), median rank: the plain method from the full [min, max]
+    bracket plus the exact finish, on seeds 0..9 (each timed over `reps` calls with events on
+    the launch stream), checked against the oracle per seed."""
+    import oracle
+    import workloads
+    n = 1 << 20
+    k = (n + 1) // 2
+    out = {"workload": "n=2^20 float32 uniform[0,1), k=(n+1)/2, seeds 0..9", "cases": {}}
+    res = sel.new_results(1)
+    stats = sel.new_stats()
+    scheds = {"default": None,
+              "cutting_plane_to_the_end": cps.default_options(partition_fraction=0.0,
+                                                              hist_bits=0)}
+    ok = True
+    for name, o in scheds.items():
+        per_seed, passes = [], []
+        for seed in seeds:
+            x = workloads.single_array("uniform", n, np.float32, seed=seed, tag="bench-small")
+            xt = torch.from_numpy(x).cuda()
+            ms = _time_ms(torch, lambda: sel.select_kth_async(xt, k, res, options=o), reps)
+            sel.select_kth_async(xt, k, res, stats, options=o)
+            torch.cuda.synchronize()
+            r = res.cpu().numpy().view(cps.RESULT_DTYPE)[0]
+            ref = oracle.select_kth(x, k)
+            ok &= bool(r["status"] == 0 and int(r["value_bits"]) == ref["value_bits"] and
+                       int(r["less"]) == ref["less"] and int(r["equal"]) == ref["equal"])
+            per_seed.append(ms)
+            passes.append(int(stats.cpu().numpy().view(cps.STATS_DTYPE)[0]["passes"]))
+        a = np.array(per_seed)
+        out["cases"][name] = {"ms_mean": round(float(a.mean()), 4),
+                              "ms_median": round(float(np.median(a)), 4),
+                              "ms_min": round(float(a.min()), 4),
+                              "elements_per_s_mean": n / (a.mean() * 1e-3),
+                              "passes_over_x_mean": float(np.mean(passes))}
+    out["parity_ok"] = ok
+    out["parity_checked"] = len(scheds) * len(list(seeds))
+    return out
+
+
+def host_info() -> dict:
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
 
 
 def cpu_baseline(budget_s: float = 20.0):
@@ -270,6 +359,7 @@ def cpu_baseline(budget_s: float = 20.0):
     elems = 0
     spent = 0.0
     done = 0
+    results = {}  # (lg, dtype name, dist, k) -> the oracle's result, for the parity check
     for lg, dtypes in ((24, DTYPES), (28, (np.float32,))):
         for dtype in dtypes:
             for dist in DISTS:
@@ -278,15 +368,18 @@ def cpu_baseline(budget_s: float = 20.0):
                 x = workloads.single_array(dist, 1 << lg, dtype, seed=0, tag="bench")
                 for k in workloads.ks_for(x.size):
                     t0 = time.perf_counter()
-                    oracle.select_kth(x, k)
+                    r = oracle.select_kth(x, k)
                     spent += time.perf_counter() - t0
                     elems += x.size
                     done += 1
+                    results[(lg, np.dtype(dtype).name, dist, int(k))] = r
                 del x
-    return {"value": elems / spent, "unit": "elements/s", "cores": 1, "kind": "oracle",
+    line = {"value": elems / spent, "unit": "elements/s", "cores": 1, "kind": "oracle",
             "sample": f"{done} of the 64 calls (all n=2^24, then n=2^28 float32 until "
                       f"~{budget_s:.0f} s), single-threaded quickselect with its counting scan, "
-                      f"{spent:.1f} s"}
+                      f"{spent:.1f} s",
+            "host": host_info()}
+    return line, results
 
 
 def main():
@@ -322,6 +415,7 @@ def main():
     # ---- resident inputs
     t_gen = time.time()
     inputs = []  # (tensor, n, k, dtype)
+    keys = []    # (lg, dtype name, distribution, k) of each call
     for lg in SIZES:
         n = 1 << lg
         for dtype in DTYPES:
@@ -331,18 +425,28 @@ def main():
                 del x
                 for k in workloads.ks_for(n):
                     inputs.append((xt, n, k, np.dtype(dtype)))
+                    keys.append((lg, np.dtype(dtype).name, dist, int(k)))
     for dtype in DTYPES:
         sel.reserve(1 << max(SIZES), cps.CPS_F32 if dtype == np.float32 else cps.CPS_F64)
     torch.cuda.synchronize()
     gen_s = time.time() - t_gen
 
     if args.copy_calibration:
+        # a plain copy of 2^28 float32 values (1 GiB read and written), then two selections of
+        # rank 1 on a 2^28 float32 input whose minimum is unique: pass 0 alone, one read of
+        # 1 GiB with the selection kernel's own nontemporal loads, and nothing written
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         for _ in range(2):
             torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
+        cal = torch.arange(1 << 28, dtype=torch.float32, device=dev)
+        cal_out = sel.new_results(1)
+        for _ in range(2):
+            sel.select_kth_async(cal, 1, cal_out)
+        torch.cuda.synchronize()
+        del cal
 
     outs = sel.new_results(len(inputs))
     res_views = [outs[i * 48:(i + 1) * 48] for i in range(len(inputs))]
@@ -430,8 +534,28 @@ def main():
         "detail": detail,
         "setup_s": round(gen_s, 1),
     }
+    # parity of every call of the sweep at full size: the defining property of x_(k)
+    # (Section 1: #(x < m) < k <= #(x <= m) with m an element of x), counted on the host
+    inv_ok, inv_checked = True, 0
+    for xt in {id(t): t for (t, _, _, _) in inputs}.values():
+        xh = xt.cpu().numpy()
+        for i, (t, n, k, dt) in enumerate(inputs):
+            if t is not xt:
+                continue
+            v = np.array([res[i]["value"]], dtype=dt)[0]
+            less = int(np.count_nonzero(xh < v))
+            eq = int(np.count_nonzero(xh == v))
+            inv_ok &= bool(eq >= 1 and less < k <= less + eq and
+                           (int(res[i]["less"]), int(res[i]["equal"])) == (less, eq))
+            inv_checked += 1
+        del xh
+    line["parity"] = {"invariant_checked": inv_checked, "invariant_ok": inv_ok,
+                      "note": "every call of the sweep: #(x<m) < k <= #(x<=m), m in x, and "
+                              "the reported counts, on the host copy of each input"}
     if not args.no_extras:
         del inputs
+        torch.cuda.empty_cache()
+        line["small"] = small_leg(sel, cps, torch)
         torch.cuda.empty_cache()
         line["batched"] = batched_leg(sel, cps, torch)
         torch.cuda.empty_cache()
@@ -441,7 +565,18 @@ def main():
         torch.cuda.empty_cache()
         line["schedules"] = schedules_leg(sel, cps, torch)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline()
+        line["cpu_baseline"], oracle_res = cpu_baseline()
+        # the oracle's own results on the calls it timed, against the GPU's
+        ok = True
+        for i, key in enumerate(keys):
+            ref = oracle_res.get(key)
+            if ref is None:
+                continue
+            ok &= bool(int(res[i]["value_bits"]) == ref["value_bits"] and
+                       int(res[i]["less"]) == ref["less"] and
+                       int(res[i]["equal"]) == ref["equal"] and res[i]["status"] == 0)
+        line["parity"]["oracle_checked"] = len(oracle_res)
+        line["parity"]["oracle_ok"] = ok
     print(json.dumps(line), flush=True)
     sel.close()
 

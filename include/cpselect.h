@@ -50,7 +50,9 @@ enum cps_error {
   CPS_EHIP = -3,     /* a HIP runtime call failed (see cps_last_hip_error) */
   CPS_ECAPTURE = -4, /* the call would have to allocate while the stream is being captured */
   CPS_ENODEV = -5,   /* no usable gfx950 device */
-  CPS_ESTATE = -6    /* the handle is in an unusable state */
+  CPS_ESTATE = -6,   /* the handle is in an unusable state */
+  CPS_EIO = -7,      /* a network file could not be opened, read or written */
+  CPS_EFORMAT = -8   /* a network file is not a valid file of this network (see cps_model_load) */
 };
 
 /* Asynchronous status, written by the device into cps_result.status. */
@@ -156,7 +158,19 @@ typedef struct cps_options {
  * t_start, t_arrive[i], t_publish[i]: device wall clock (100 MHz ticks) at the launch, when
  *               the last workgroup finished pass i, and when the state after pass i was
  *               published (the difference is the cutting-plane update and, on the last
- *               pass, the exact select). */
+ *               pass, the exact select).
+ * kind[i]:      what pass i was (enum cps_pass_kind).  The remaining arrays hold what the
+ *               pass's own reduction produced, as the cutting-plane update used it:
+ *   CPS_PASS_ZERO (Section 4, step 0): trial = minimum, A = sum(x) - n_f min (A at the
+ *               minimum), B = n_f max - sum(x) (B at the maximum), L = #min, G = #max,
+ *               pred = minimum, succ = maximum (n_f: finite elements, sum over those).
+ *   CPS_PASS_EVAL (Section 3, Eq. 2, one cutting-plane evaluation at trial[i]): A, B, L, G
+ *               of the whole array (a pass over the bracket's compacted elements adds the
+ *               parts outside the bracket), pred / succ: the largest / smallest element of
+ *               the pass's working set below / above the trial point (-inf / +inf if none).
+ *   CPS_PASS_COUNT (the counting evaluation): L, G of the whole array at trial[i]; A and B
+ *               are not formed (0).
+ *   the others: only kind and working. */
 typedef struct cps_stats {
   int32_t passes;
   int32_t work_passes;
@@ -171,7 +185,22 @@ typedef struct cps_stats {
   uint64_t t_start;
   uint64_t t_arrive[CPS_STATS_MAX_PASSES];
   uint64_t t_publish[CPS_STATS_MAX_PASSES];
+  int32_t kind[CPS_STATS_MAX_PASSES];
+  double trial[CPS_STATS_MAX_PASSES];
+  double A[CPS_STATS_MAX_PASSES], B[CPS_STATS_MAX_PASSES];
+  int64_t L[CPS_STATS_MAX_PASSES], G[CPS_STATS_MAX_PASSES];
+  double pred[CPS_STATS_MAX_PASSES], succ[CPS_STATS_MAX_PASSES];
 } cps_stats;
+
+/* Pass kinds of cps_stats.kind. */
+enum cps_pass_kind {
+  CPS_PASS_ZERO = 0,   /* pass 0: extremes, their multiplicities and the sum */
+  CPS_PASS_EVAL = 1,   /* fused evaluation of A, B, counts and neighbours at a trial point */
+  CPS_PASS_COUNT = 2,  /* counting evaluation: the two sides of a trial point in key bins */
+  CPS_PASS_HIST = 3,   /* key-histogram pass of the exact finish */
+  CPS_PASS_GATHER = 4, /* gather of the bracket's elements */
+  CPS_PASS_FINAL = 5   /* one-workgroup exact select */
+};
 
 typedef struct cps_handle cps_handle;
 
@@ -179,7 +208,14 @@ typedef struct cps_handle cps_handle;
 
 /* Create a handle bound to HIP device `device` (which must be gfx950).  The handle owns
  * the workspace (grown on demand outside stream capture) and the launch configuration.
- * Returns CPS_ENODEV when the device is missing or not gfx950. */
+ * Returns CPS_ENODEV when the device is missing or not gfx950.
+ *
+ * Streams: the calls made with one handle share its workspaces (the selection state, its
+ * synchronisation counters, split and gather buffers, the batched queue, the proposal's
+ * bracket), so the device work of two calls with one handle must not overlap.  Calls on
+ * one stream are ordered by the stream; calls on different streams with one handle must
+ * be ordered by the caller (events), or use one handle per stream.  The host side of a
+ * handle is thread-safe (a mutex), which orders the launches but not their device work. */
 int cps_create(int device, cps_handle **out);
 
 /* Destroy a handle.  The caller must have synchronised every stream used with it. */
@@ -213,8 +249,11 @@ int select_kth_ex(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
                   void *stream);
 
 /* f, A, B, counts, neighbours and subgradient end points at each of ny points ys_dev
- * (device doubles), for the rank-k objective of x[0..n) (Section 3, Eq. 2).  This is the
- * evaluation each cutting-plane pass performs; it is exported for checking.
+ * (device doubles), for the rank-k objective of x[0..n) (Section 3, Eq. 2): the quantities a
+ * cutting-plane pass forms, computed here by a separate two-stage kernel that widens every
+ * element to double before comparing and summing (a reference evaluation on the device, not
+ * the hot path's own pass: what the selection's passes formed is in cps_stats' per-pass
+ * trace).  Uses its own region of the handle's workspace.
  * out_dev: device pointer to ny cps_eval records. */
 int cps_objective(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
                   const double *ys_dev, int64_t ny, cps_eval *out_dev, void *stream);
@@ -409,6 +448,24 @@ int select_kth_learned(cps_handle *h, const void *x, int64_t n, int64_t k, int d
 int select_kth_sampled(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype, double z,
                        const cps_options *opt, cps_result *out_dev, cps_stats *stats_dev,
                        void *stream);
+
+/* Network files.  A trained proposal network is kept in a little-endian binary file of 8-byte
+ * header words followed by the parameters:
+ *   bytes  0..7    magic "CPSMLP01"
+ *   uint32 8       format version (1)
+ *   uint32 12..23  inputs, hidden units per layer, outputs (67, 64, 2)
+ *   uint32 24      feature specification (1: the features and outputs documented above)
+ *   uint32 28      parameter count (CPS_MLP_PARAMS)
+ *   uint64 32      FNV-1a 64-bit hash (Fowler, Noll, Vo) of the parameter bytes
+ *   float  40..    the CPS_MLP_PARAMS parameters in the layout documented above.
+ * cps_model_save copies params_dev (device, CPS_MLP_PARAMS floats) to the host and writes the
+ * file (replacing it); cps_model_load checks every header field and the hash, then copies the
+ * parameters to params_dev.  Both synchronise the device (hipMemcpy) and need no handle.
+ * Errors: CPS_EINVAL for null arguments, CPS_EIO when the file cannot be opened, read or
+ * written, CPS_EFORMAT for a wrong magic, version, shape, feature specification, count, hash
+ * or length (params_dev is then left unchanged), CPS_EHIP for a failed copy. */
+int cps_model_save(const float *params_dev, const char *path);
+int cps_model_load(const char *path, float *params_dev);
 
 /* Training driver: draws n_arrays arrays of array_size elements (cps_mixture_generate,
  * seed, ids 0..n_arrays-1), labels them exactly with select_kth_batched, and runs `epochs`

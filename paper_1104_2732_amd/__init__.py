@@ -30,6 +30,7 @@ LIB_PATH = os.path.join(_HERE, "libcpselect.so")
 
 CPS_F32, CPS_F64 = 0, 1
 CPS_OK = 0
+CPS_EIO, CPS_EFORMAT = -7, -8
 STATUS_OK, STATUS_NAN, STATUS_TIMEOUT, STATUS_INTERNAL = 0, 1, 2, 3
 STATS_MAX_PASSES = 96
 
@@ -47,7 +48,16 @@ STATS_DTYPE = np.dtype([("passes", "<i4"), ("work_passes", "<i4"), ("kelley_step
                         ("working", "<i8", (STATS_MAX_PASSES,)),
                         ("t_start", "<u8"),
                         ("t_arrive", "<u8", (STATS_MAX_PASSES,)),
-                        ("t_publish", "<u8", (STATS_MAX_PASSES,))])
+                        ("t_publish", "<u8", (STATS_MAX_PASSES,)),
+                        ("kind", "<i4", (STATS_MAX_PASSES,)),
+                        ("trial", "<f8", (STATS_MAX_PASSES,)),
+                        ("A", "<f8", (STATS_MAX_PASSES,)),
+                        ("B", "<f8", (STATS_MAX_PASSES,)),
+                        ("L", "<i8", (STATS_MAX_PASSES,)),
+                        ("G", "<i8", (STATS_MAX_PASSES,)),
+                        ("pred", "<f8", (STATS_MAX_PASSES,)),
+                        ("succ", "<f8", (STATS_MAX_PASSES,))])
+PASS_ZERO, PASS_EVAL, PASS_COUNT, PASS_HIST, PASS_GATHER, PASS_FINAL = range(6)
 assert RESULT_DTYPE.itemsize == 48 and EVAL_DTYPE.itemsize == 80
 
 
@@ -105,7 +115,7 @@ EXPORTS = ("cps_create", "cps_destroy", "cps_status_string", "cps_last_hip_error
            "cps_reserve_batched", "cps_autotune_batched", "lms_median_sq_residuals",
            "cps_mixture_generate", "cps_features", "cps_mlp_forward", "cps_mlp_loss_grad",
            "cps_mlp_adam", "cps_mlp_init", "cps_learned_bracket", "select_kth_learned",
-           "cps_mlp_train", "select_kth_sampled")
+           "cps_mlp_train", "select_kth_sampled", "cps_model_save", "cps_model_load")
 STATUS_BADARG = 4
 
 
@@ -164,9 +174,11 @@ def lib() -> ctypes.CDLL:
                                 vp]
     L.select_kth_sampled.argtypes = [vp, vp, i64, i64, c_int, ctypes.c_double,
                                      ctypes.POINTER(Options), vp, vp, vp]
+    L.cps_model_save.argtypes = [vp, ctypes.c_char_p]
+    L.cps_model_load.argtypes = [ctypes.c_char_p, vp]
     for name in ("cps_mixture_generate", "cps_features", "cps_mlp_forward", "cps_mlp_loss_grad",
                  "cps_mlp_adam", "cps_mlp_init", "cps_learned_bracket", "select_kth_learned",
-                 "cps_mlp_train", "select_kth_sampled"):
+                 "cps_mlp_train", "select_kth_sampled", "cps_model_save", "cps_model_load"):
         getattr(L, name).restype = c_int
     _lib = L
     return L
@@ -502,6 +514,18 @@ class Selector:
         if stats:
             return res, _as_records(st, STATS_DTYPE)[0]
         return res
+
+    def model_save(self, params, path: str) -> None:
+        """Write the network's parameters to a versioned, hashed file (cps_model_save)."""
+        _check(lib().cps_model_save(self._float_params(params), os.fsencode(path)),
+               "cps_model_save")
+
+    def model_load(self, path: str, params=None):
+        """Read a network file into `params` (a new device tensor when None)."""
+        params = self.new_params() if params is None else params
+        _check(lib().cps_model_load(os.fsencode(path), self._float_params(params)),
+               "cps_model_load")
+        return params
 
     def mlp_train(self, params, seed: int, n_arrays: int, array_size: int, epochs: int,
                   batch: int = 256, lr: float = 1e-3, init: bool = True, holdout: int = 0,

@@ -3,6 +3,7 @@
 
 #include <cstdio>
 #include <cstring>
+#include <string>
 #include <mutex>
 #include <vector>
 
@@ -34,6 +35,8 @@ struct cps_handle {
   size_t lws_bytes = 0;
   void *mws = nullptr;  // per-workgroup gradient partials of the proposal network
   size_t mws_bytes = 0;
+  void *ows = nullptr;  // partials of the reference objective (cps_objective)
+  size_t ows_bytes = 0;
   double *bracket = nullptr;  // the learned proposal handed to the selection (a, b, use)
   uint64_t *phist = nullptr;  // counters of the proposal's interior (same allocation)
   cps_batch_options tuned[2];
@@ -485,6 +488,8 @@ const char *cps_status_string(int code) {
     case CPS_ECAPTURE: return "allocation needed during stream capture";
     case CPS_ENODEV: return "no usable gfx950 device";
     case CPS_ESTATE: return "handle in an unusable state";
+    case CPS_EIO: return "network file could not be opened, read or written";
+    case CPS_EFORMAT: return "not a valid network file";
     default: break;
   }
   return "unknown code";
@@ -534,6 +539,7 @@ int cps_destroy(cps_handle *h) {
   if (h->bws) (void)hipFree(h->bws);
   if (h->lws) (void)hipFree(h->lws);
   if (h->mws) (void)hipFree(h->mws);
+  if (h->ows) (void)hipFree(h->ows);
   if (h->bracket) (void)hipFree(h->bracket);
   delete h;
   return CPS_OK;
@@ -582,13 +588,10 @@ int cps_objective(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
   if (nb < 1) nb = 1;
   const size_t pd_bytes = align_up((size_t)ny * nb * 4 * sizeof(double), 256);
   const size_t pi_bytes = align_up((size_t)ny * nb * 3 * sizeof(int64_t), 256);
-  // keep clear of the select layout's state and synchronisation words at the start
-  const size_t off = align_up(sizeof(cps::CpState), 256) + align_up(sizeof(cps::SyncCtl), 256) +
-                     align_up(cps::kHistWords * sizeof(uint64_t), 256);
-  rc = ensure_workspace(h, off + pd_bytes + pi_bytes, s);
+  rc = ensure_buffer(h->ows, h->ows_bytes, pd_bytes + pi_bytes, s);
   if (rc) return rc;
-  double *pd = (double *)((char *)h->ws + off);
-  int64_t *pi = (int64_t *)((char *)h->ws + off + pd_bytes);
+  double *pd = (double *)h->ows;
+  int64_t *pi = (int64_t *)((char *)h->ows + pd_bytes);
   hipError_t e;
   if (dtype == CPS_F32)
     e = cps::launch_objective<float>((const float *)x, n, k, ys_dev, ny, out_dev, pd, pi, (int)nb, s);
@@ -874,6 +877,98 @@ int cps_mlp_train(cps_handle *h, const cps_train_options *opt, float *params_dev
     report->examples = N;
   }
   return CPS_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ network files
+
+namespace {
+
+constexpr char kModelMagic[8] = {'C', 'P', 'S', 'M', 'L', 'P', '0', '1'};
+constexpr uint32_t kModelVersion = 1;
+constexpr uint32_t kFeatureSpec = 1;
+constexpr size_t kModelHeader = 40;
+
+// FNV-1a, 64-bit (offset basis and prime as published by Fowler, Noll and Vo).
+uint64_t fnv1a64(const unsigned char *p, size_t n) {
+  uint64_t h = 14695981039346656037ull;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+void put_u32(unsigned char *p, uint32_t v) {
+  for (int i = 0; i < 4; ++i) p[i] = (unsigned char)(v >> (8 * i));
+}
+void put_u64(unsigned char *p, uint64_t v) {
+  for (int i = 0; i < 8; ++i) p[i] = (unsigned char)(v >> (8 * i));
+}
+uint32_t get_u32(const unsigned char *p) {
+  uint32_t v = 0;
+  for (int i = 0; i < 4; ++i) v |= (uint32_t)p[i] << (8 * i);
+  return v;
+}
+uint64_t get_u64(const unsigned char *p) {
+  uint64_t v = 0;
+  for (int i = 0; i < 8; ++i) v |= (uint64_t)p[i] << (8 * i);
+  return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cps_model_save(const float *params_dev, const char *path) {
+  if (!params_dev || !path) return CPS_EINVAL;
+  std::vector<unsigned char> buf(kModelHeader + CPS_MLP_PARAMS * sizeof(float));
+  hipError_t e = hipMemcpy(buf.data() + kModelHeader, params_dev, CPS_MLP_PARAMS * sizeof(float),
+                           hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e);
+  std::memcpy(buf.data(), kModelMagic, 8);
+  put_u32(buf.data() + 8, kModelVersion);
+  put_u32(buf.data() + 12, CPS_MLP_INPUTS);
+  put_u32(buf.data() + 16, CPS_MLP_HIDDEN);
+  put_u32(buf.data() + 20, CPS_MLP_OUTPUTS);
+  put_u32(buf.data() + 24, kFeatureSpec);
+  put_u32(buf.data() + 28, CPS_MLP_PARAMS);
+  put_u64(buf.data() + 32, fnv1a64(buf.data() + kModelHeader, CPS_MLP_PARAMS * sizeof(float)));
+  // write a sibling file, then rename it over the target, so a failed write leaves no
+  // truncated network behind
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE *f = std::fopen(tmp.c_str(), "wb");
+  if (!f) return CPS_EIO;
+  const bool ok = std::fwrite(buf.data(), 1, buf.size(), f) == buf.size();
+  const bool closed = std::fclose(f) == 0;
+  if (!ok || !closed || std::rename(tmp.c_str(), path) != 0) {
+    std::remove(tmp.c_str());
+    return CPS_EIO;
+  }
+  return CPS_OK;
+}
+
+int cps_model_load(const char *path, float *params_dev) {
+  if (!path || !params_dev) return CPS_EINVAL;
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return CPS_EIO;
+  const size_t want = kModelHeader + CPS_MLP_PARAMS * sizeof(float);
+  std::vector<unsigned char> buf(want + 1);
+  const size_t got = std::fread(buf.data(), 1, buf.size(), f);
+  const bool err = std::ferror(f) != 0;
+  std::fclose(f);
+  if (err) return CPS_EIO;
+  if (got != want) return CPS_EFORMAT;  // truncated, or trailing bytes
+  if (std::memcmp(buf.data(), kModelMagic, 8) != 0 || get_u32(buf.data() + 8) != kModelVersion ||
+      get_u32(buf.data() + 12) != CPS_MLP_INPUTS || get_u32(buf.data() + 16) != CPS_MLP_HIDDEN ||
+      get_u32(buf.data() + 20) != CPS_MLP_OUTPUTS || get_u32(buf.data() + 24) != kFeatureSpec ||
+      get_u32(buf.data() + 28) != CPS_MLP_PARAMS ||
+      get_u64(buf.data() + 32) != fnv1a64(buf.data() + kModelHeader, CPS_MLP_PARAMS * sizeof(float)))
+    return CPS_EFORMAT;
+  hipError_t e = hipMemcpy(params_dev, buf.data() + kModelHeader, CPS_MLP_PARAMS * sizeof(float),
+                           hipMemcpyHostToDevice);
+  return e == hipSuccess ? CPS_OK : hip_fail(e);
 }
 
 }  // extern "C"

@@ -9,6 +9,7 @@
 // workgroup barrier, so workgroups never wait on each other and the launch needs no
 // co-residency.  The queue and exit counters reset themselves at the end, so the launch
 // can be captured in a graph and replayed.
+#include "batch_queue.h"
 #include "cps_device.h"
 #include "cps_kernels.h"
 #include "cps_passes.h"
@@ -306,7 +307,7 @@ __device__ void block_pass0(const Span<T> &sp, P0Acc<T> &acc) {
     for (int u = 0; u < U; ++u) {
       T e[V];
       vec_to_arr<T>(raw[u], e);
-      T s_part = 0, aa = 0, bA = 0, ab = 0, bB = 0;
+      T aa = 0, bA = 0, ab = 0, bB = 0;
       if (!CLASSIFY) {
         // the running extremes change only where a lane's element reaches them (as in the
         // single-array pass 0: the wavefront tests first, NaN compares false in both)
@@ -319,21 +320,19 @@ __device__ void block_pass0(const Span<T> &sp, P0Acc<T> &acc) {
         }
 #pragma unroll
         for (int j = 0; j < V; ++j)
-          pass0_one<T, false, false, true>(e[j], valid[u], ba, bb, s_part, aa, bA, ab, bB, acc);
+          pass0_one<T, false, false, true>(e[j], valid[u], ba, bb, aa, bA, ab, bB, acc);
       } else {
 #pragma unroll
         for (int j = 0; j < V; ++j)
-          pass0_one<T, true, false>(e[j], valid[u], ba, bb, s_part, aa, bA, ab, bB, acc);
+          pass0_one<T, true, false>(e[j], valid[u], ba, bb, aa, bA, ab, bB, acc);
       }
-      acc.sum += (double)s_part;
     }
   }
   if (sp.nedge > 0) {
     const bool have = tid < sp.nedge;
     const T v = have ? sp.W[edge_index(sp, tid)] : T(0);
-    T s_part = 0, aa = 0, bA = 0, ab = 0, bB = 0;
-    pass0_one<T, CLASSIFY, false>(v, have, ba, bb, s_part, aa, bA, ab, bB, acc);
-    acc.sum += (double)s_part;
+    T aa = 0, bA = 0, ab = 0, bB = 0;
+    pass0_one<T, CLASSIFY, false>(v, have, ba, bb, aa, bA, ab, bB, acc);
   }
 }
 
@@ -364,7 +363,7 @@ __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out,
   CPS_GLOBAL T *zb[2] = {(CPS_GLOBAL T *)(a.zbuf + (int64_t)blockIdx.x * a.ws_stride),
                          (CPS_GLOBAL T *)(a.zbuf + (int64_t)blockIdx.x * a.ws_stride + cap)};
   CPS_GLOBAL T *gb = (CPS_GLOBAL T *)(a.zbuf + (int64_t)blockIdx.x * a.ws_stride + 2 * cap);
-  if (!x || n < 1 || k < 1 || k > n || ((uintptr_t)x % sizeof(T)) != 0) {
+  if (!batch_array_valid((uint64_t)(uintptr_t)x, n, k, (uint32_t)sizeof(T))) {
     if (tid == 0) {
       cps_result r = {};
       r.status = ST_BADARG;
@@ -557,31 +556,12 @@ void batched_select_kernel(BatchArgs<T> a) {
   if (sorted) {
     int64_t m = 1;
     while (m < count) m <<= 1;
-    for (int64_t j = tid; j < m; j += BLOCK) {
-      uint64_t key = 0;
-      if (j < count) {
-        int64_t sz = a.sizes[j];
-        if (sz < 0) sz = 0;
-        if (sz > ((int64_t)1 << 50)) sz = (int64_t)1 << 50;
-        key = ((uint64_t)sz << 12) | (uint64_t)(kBatchSortMax - 1 - j);
-      }
-      sh.order[j] = key;
-    }
+    for (int64_t j = tid; j < m; j += BLOCK) sh.order[j] = j < count ? lpt_key(a.sizes[j], j) : 0;
     __syncthreads();
     // bitonic sort, descending
     for (int64_t kk = 2; kk <= m; kk <<= 1) {
       for (int64_t jj = kk >> 1; jj > 0; jj >>= 1) {
-        for (int64_t i = tid; i < m; i += BLOCK) {
-          const int64_t p = i ^ jj;
-          if (p > i) {
-            const uint64_t x0 = sh.order[i], x1 = sh.order[p];
-            const bool desc = (i & kk) == 0;
-            if (desc ? (x0 < x1) : (x0 > x1)) {
-              sh.order[i] = x1;
-              sh.order[p] = x0;
-            }
-          }
-        }
+        for (int64_t i = tid; i < m; i += BLOCK) bitonic_exchange(sh.order, i, jj, kk);
         __syncthreads();
       }
     }
@@ -592,7 +572,7 @@ void batched_select_kernel(BatchArgs<T> a) {
     const int64_t j = sh.job;
     __syncthreads();
     if (j >= count) break;
-    const int64_t i = sorted ? (int64_t)(kBatchSortMax - 1 - (sh.order[j] & (kBatchSortMax - 1))) : j;
+    const int64_t i = sorted ? lpt_index(sh.order[j]) : j;
     select_one<T, BLOCK, U>(a.ptrs[i], a.sizes[i], a.ks[i], a.out + i, a, sh);
   }
   // the last workgroup out resets the queue for the next launch (graph replays included)

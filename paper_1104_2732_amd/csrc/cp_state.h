@@ -255,10 +255,18 @@ CPS_HD inline double cp_trial_point(CpState &s, const CpConfig &c) {
   return t;
 }
 
+// Bound on the passes of one selection.  Every kind of pass provably shrinks the bracket
+// (a cutting-plane step removes at least one distinct value and the bisection after maxit
+// steps halves its key range; a histogram pass keeps one of at least two bins, or finishes;
+// a gather is followed by the final select), so this is never reached; it only turns a
+// broken invariant into an error instead of an endless loop.
+constexpr int32_t kMaxWorkPasses = 4 * 96;
+
 // Decide what the next pass does, given the current bracket.
 CPS_HD inline void cp_plan(CpState &s, const CpConfig &c) {
   const int64_t pop = s.cR - s.cL;
-  if (pop < 1) {  // the bracket always holds x_(k); anything else is a bug
+  if (pop < 1 || s.work_passes >= kMaxWorkPasses) {
+    // the bracket always holds x_(k), and the passes are bounded; anything else is a bug
     s.status = ST_INTERNAL;
     cp_finish(s, 0.0, 0, 0);
     return;
@@ -420,22 +428,40 @@ CPS_HD inline void cp_after_pass0(CpState &s, const Pass0Result &r, const CpConf
   cp_plan(s, c);
 }
 
+// A, B, L and G of the whole array at the trial point s.t, from an evaluation pass over the
+// working set: over the bracket's compacted elements the parts outside the bracket are
+// added (every term non-negative).
+struct FullEval {
+  double A, B;
+  int64_t L, G;
+};
+
+CPS_HD inline FullEval cp_full_eval(const CpState &s, const EvalResult &r) {
+  FullEval f;
+  f.L = r.L;
+  f.G = r.G;
+  f.A = r.A;
+  f.B = r.B;
+  if (s.on_bracket) {
+    f.L += s.cL;
+    f.G += s.n - s.cR;
+    f.A += s.AR + (double)(s.n - s.cR) * (s.yR - s.t);
+    f.B += s.BL + (double)s.cL * (s.t - s.yL);
+  }
+  return f;
+}
+
 // After an evaluation pass at s.t over the working set.
 CPS_HD inline void cp_after_eval(CpState &s, const EvalResult &r, const CpConfig &c) {
   const int64_t n = s.n, k = s.k;
   const double t = s.t;
+  const FullEval fe = cp_full_eval(s, r);
   s.work_passes++;
   if (s.wbuf < 0) s.passes++;
   s.elements_read += s.wlen;
   s.elements_written += r.written;
-  int64_t L = r.L, G = r.G;
-  double A = r.A, B = r.B;
-  if (s.on_bracket) {
-    L += s.cL;
-    G += n - s.cR;
-    A += s.AR + (double)(n - s.cR) * (s.yR - t);
-    B += s.BL + (double)s.cL * (t - s.yL);
-  }
+  const int64_t L = fe.L, G = fe.G;
+  const double A = fe.A, B = fe.B;
   const int64_t E = n - L - G;
   const bool did_split = s.split != 0;
   const bool did_count = s.counted != 0;
@@ -481,11 +507,6 @@ CPS_HD inline void cp_after_eval(CpState &s, const EvalResult &r, const CpConfig
   // counted: the plan asks for a histogram step, and the caller narrows the bracket with
   // those counts (cp_hist_narrow on split_part_geometry of part `side`) before any pass.
   if (did_count) s.narrowed = 1;
-  if (s.work_passes >= 4 * 96) {  // cannot happen with the bisection bound; guard anyway
-    s.status = ST_INTERNAL;
-    cp_finish(s, 0.0, 0, 0);
-    return;
-  }
   cp_plan(s, c);
 }
 

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "../../include/cpselect.h"
+#include "batch_queue.h"
 #include "cp_state.h"
 
 namespace cps {
@@ -31,13 +32,17 @@ constexpr int kMaxGroups = 256;  // so at most 4096 workgroups
 // Grid-synchronisation words of the single-array kernel, each on its own 128-byte line.
 // Workgroups arrive on grp[bid / kGroup]; the last of each group arrives on `top`; the last
 // overall advances the state and bumps `gen`, on which the others wait.  gcur hands out
-// write offsets in the gather buffer.
+// write offsets in the gather buffer.  `exits` counts the workgroups that have left the
+// launch: the last one clears the arrival counters, which a wait that timed out can leave
+// part-way counted, so every launch starts from zeroed counters.
 struct SyncCtl {
   uint32_t top;
   uint32_t gen;
   uint32_t pad0[30];
   uint64_t gcur;
   uint64_t pad1[15];
+  uint32_t exits;
+  uint32_t pad2[31];
   uint32_t grp[kMaxGroups][32];
 };
 
@@ -66,7 +71,6 @@ template <typename T> struct SelectArgs {
 
 // ---- batched selection
 
-constexpr int kBatchSortMax = 4096;  // arrays sorted largest-first in LDS up to this count
 
 // Work queue of the batched kernel (each counter on its own 128-byte line).  Both reset
 // to zero when the last workgroup leaves, so consecutive launches need no clearing.

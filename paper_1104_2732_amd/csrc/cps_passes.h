@@ -67,7 +67,7 @@ template <typename T> __device__ inline void p0_extremes(T v, bool fin, P0Acc<T>
 // SUMS: with a proposed bracket, also the finite-element parts of A and B at its ends
 // (otherwise only the two counts).
 template <typename T, bool CLASSIFY, bool BRACKET, bool SKIP_EXTREMES = false, bool SUMS = true>
-__device__ inline void pass0_one(T v, bool valid, T ba, T bb, T &s_part, T &aa, T &bA, T &ab,
+__device__ inline void pass0_one(T v, bool valid, T ba, T bb, T &aa, T &bA, T &ab,
                                  T &bB, P0Acc<T> &acc) {
   bool fin = valid;
   if (CLASSIFY) {
@@ -80,7 +80,7 @@ __device__ inline void pass0_one(T v, bool valid, T ba, T bb, T &s_part, T &aa, 
     fin = valid && !isnan_ && !ni && !pi;
   }
   if (!SKIP_EXTREMES) p0_extremes<T>(v, fin, acc);
-  s_part += fin ? v : T(0);
+  acc.sum += fin ? (double)v : 0.0;  // widened per element: the sum is formed in double
   if (BRACKET) {
     acc.cle_a += (valid && v <= ba) ? 1u : 0u;
     acc.clt_b += (valid && v < bb) ? 1u : 0u;

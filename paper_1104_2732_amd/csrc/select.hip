@@ -449,7 +449,7 @@ __device__ inline void pass0_tile(const Span<T> &sp, int64_t base, int per_u, in
   for (int u = 0; u < U; ++u) {
     T e[V];
     vec_to_arr<T>(raw[u], e);
-    T s_part = 0, aa = 0, bA = 0, ab = 0, bB = 0;
+    T aa = 0, bA = 0, ab = 0, bB = 0;
     if (!CLASSIFY) {
       // Past the first tiles an element rarely reaches the running extremes: the wavefront
       // tests that first (compares only) and updates the extremes and their counts only
@@ -465,7 +465,7 @@ __device__ inline void pass0_tile(const Span<T> &sp, int64_t base, int per_u, in
       if (BRACKET && SPLIT && HIST) {  // the device proposal that counts its interior
 #pragma unroll
         for (int j = 0; j < V; ++j)
-          pass0_one<T, false, false, true>(e[j], valid[u], ba, bb, s_part, aa, bA, ab, bB, acc);
+          pass0_one<T, false, false, true>(e[j], valid[u], ba, bb, aa, bA, ab, bB, acc);
         const int lane = me % kWave;
 #pragma unroll
         for (int j = 0; j < V; ++j) p0_key<T>(e[j], valid[u], ib, acc, o, lane);
@@ -473,13 +473,13 @@ __device__ inline void pass0_tile(const Span<T> &sp, int64_t base, int per_u, in
       } else {
 #pragma unroll
         for (int j = 0; j < V; ++j)
-          pass0_one<T, false, BRACKET, true, !HIST>(e[j], valid[u], ba, bb, s_part, aa, bA, ab,
+          pass0_one<T, false, BRACKET, true, !HIST>(e[j], valid[u], ba, bb, aa, bA, ab,
                                                     bB, acc);
       }
     } else {
 #pragma unroll
       for (int j = 0; j < V; ++j)
-        pass0_one<T, true, BRACKET>(e[j], valid[u], ba, bb, s_part, aa, bA, ab, bB, acc);
+        pass0_one<T, true, BRACKET>(e[j], valid[u], ba, bb, aa, bA, ab, bB, acc);
     }
     if (SPLIT && !(BRACKET && HIST && !CLASSIFY)) {
       // staged in LDS and moved in 16-byte vectors (per-element stores of a small interior
@@ -489,7 +489,6 @@ __device__ inline void pass0_tile(const Span<T> &sp, int64_t base, int per_u, in
       for (int j = 0; j < V; ++j) stage_inside<T, HIST>(e[j], valid[u], ba, bb, o, lane, ib);
       flush_inside<T>(o, lane, cap);
     }
-    acc.sum += (double)s_part;
     if (BRACKET) {
       acc.Aa += (double)aa;
       acc.Ba += (double)bA;
@@ -517,13 +516,12 @@ __device__ inline void pass0(const Walk<T> &wk, T ba, T bb, P0Acc<T> &acc, WaveO
   if (sp.nedge > 0 && wk.edge_owner && tid < kWave) {
     const bool have = lane < sp.nedge;
     const T v = have ? sp.W[edge_index(sp, lane)] : T(0);
-    T s_part = 0, aa = 0, bA = 0, ab = 0, bB = 0;
-    pass0_one<T, CLASSIFY, BRACKET, false, !HIST>(v, have, ba, bb, s_part, aa, bA, ab, bB, acc);
+    T aa = 0, bA = 0, ab = 0, bB = 0;
+    pass0_one<T, CLASSIFY, BRACKET, false, !HIST>(v, have, ba, bb, aa, bA, ab, bB, acc);
     if (SPLIT) {
       stage_inside<T, HIST>(v, have, ba, bb, o, lane, ib);
       flush_inside<T>(o, lane, cap);
     }
-    acc.sum += (double)s_part;
     if (BRACKET) {
       acc.Aa += (double)aa;
       acc.Ba += (double)bA;
@@ -1185,6 +1183,28 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
   block_reduce<BLOCK, 4, 3>(dv, dop, iv, false, sh.d, sh.i);
 }
 
+// Trace of pass i in the stats record (thread 0 of the last workgroup only).
+__device__ inline void trace_pass(cps_stats *st, int i, int32_t kind, double t, double A, double B,
+                                  int64_t L, int64_t G, double pred, double succ) {
+  if (!st || i >= CPS_STATS_MAX_PASSES) return;
+  st->kind[i] = kind;
+  st->trial[i] = t;
+  st->A[i] = A;
+  st->B[i] = B;
+  st->L[i] = L;
+  st->G[i] = G;
+  st->pred[i] = pred;
+  st->succ[i] = succ;
+}
+
+// Pass 0's reduction as the state machine takes it: f at the extremes from the sum
+// (Section 4, step 0), the extremes and their multiplicities.
+__device__ inline void trace_pass0(cps_stats *st, int i, int64_t n, const Pass0Result &r) {
+  const double nf = (double)(n - r.nneg - r.npos - r.nnan);
+  trace_pass(st, i, CPS_PASS_ZERO, r.fmin, r.sum - nf * r.fmin, nf * r.fmax - r.sum, r.cmin,
+             r.cmax, r.fmin, r.fmax);
+}
+
 // The last workgroup to arrive: reduce every workgroup's partial in a fixed order, advance
 // the cutting-plane state, run the exact select when the bracket is small, and write the
 // new state to global memory (the caller then releases it).
@@ -1263,6 +1283,7 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
       }
       pidx = s.work_passes;
       s.phase = PH_PASS0;
+      trace_pass0(a.stats, pidx, a.n, r);
       dev_after_pass0(s, r, c);
       if (a.stats && pidx < CPS_STATS_MAX_PASSES) {
         a.stats->population[pidx] = s.phase == PH_DONE ? 0 : s.cR - s.cL;
@@ -1303,6 +1324,7 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
       pidx = s.work_passes;
       const int64_t wl = s.wlen;
       const int32_t bsel = (int32_t)sh.misc[0];
+      trace_pass(a.stats, pidx, CPS_PASS_HIST, 0, 0, 0, 0, 0, 0, 0);
       dev_after_hist(s, bsel, bsel < 0 ? 0 : sh.misc[1], bsel < 0 ? 0 : sh.misc[2], a.cfg);
       if (a.stats && pidx < CPS_STATS_MAX_PASSES) {
         a.stats->population[pidx] = s.phase == PH_DONE ? 0 : s.cR - s.cL;
@@ -1390,6 +1412,7 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
       pidx = s.work_passes;
       const int64_t wl = s.wlen;
       if (s.phase == PH_GATHER) {
+        trace_pass(a.stats, pidx, CPS_PASS_GATHER, 0, 0, 0, 0, 0, 0, 0);
         dev_after_gather(s, ri[2]);
       } else {
         EvalResult r;
@@ -1403,6 +1426,10 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
           }
           r.L = s.cL + t0;
           r.G = (s.n - s.cR) + t1;
+          trace_pass(a.stats, pidx, CPS_PASS_COUNT, s.t, 0, 0, r.L, r.G, r.pred, r.succ);
+        } else {
+          const FullEval fe = cp_full_eval(s, r);
+          trace_pass(a.stats, pidx, CPS_PASS_EVAL, s.t, fe.A, fe.B, fe.L, fe.G, r.pred, r.succ);
         }
         dev_after_eval(s, r, a.cfg);
       }
@@ -1464,6 +1491,7 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
       const int fi = w.work_passes;
       const int64_t wl = w.wlen;
       dev_after_final(w, (double)Traits<T>::unkey(key), below, eq);
+      trace_pass(a.stats, fi, CPS_PASS_FINAL, 0, 0, 0, 0, 0, 0, 0);
       if (a.stats && fi < CPS_STATS_MAX_PASSES) {
         a.stats->population[fi] = 0;
         a.stats->working[fi] = wl;
@@ -1562,6 +1590,20 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_num_vgpr(128))) void c
     phase = sh.st.phase;
     p0_slow = sh.st.p0_slow != 0;
     if (phase == PH_DONE) break;
+  }
+  // Leave the launch.  Normally every arrival counter is back at zero here; after a wait
+  // that timed out, a workgroup that went on alone has left its group counter (and maybe
+  // the top counter) part-way counted.  Every wait is bounded, so every workgroup gets here,
+  // and the last one clears the counters for the next launch on this workspace.
+  if (tid == 0) {
+    const uint32_t e = __hip_atomic_fetch_add(&a.sync->exits, 1u, __ATOMIC_ACQ_REL,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+    if (e == (uint32_t)G - 1u) {
+      const int ng = (G + kGroup - 1) / kGroup;
+      for (int g = 0; g < ng; ++g) store_relaxed(&a.sync->grp[g][0], 0u);
+      store_relaxed(&a.sync->top, 0u);
+      store_release(&a.sync->exits, 0u);
+    }
   }
 }
 

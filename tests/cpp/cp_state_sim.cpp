@@ -11,6 +11,7 @@
 #include <cstring>
 #include <vector>
 
+#include "../../paper_1104_2732_amd/csrc/batch_queue.h"
 #include "../../paper_1104_2732_amd/csrc/cp_state.h"
 
 using namespace cps;
@@ -26,7 +27,7 @@ template <typename T>
 static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_threshold,
                double theta, int use_bracket, double blo, double bhi, int p0_split,
                int64_t p0_cap, int hist_bits, int count_first, int hist_compact, int p0_sums,
-               int spec_mode, SimResult *out) {
+               int spec_mode, SimResult *out, int side_bits = -1) {
   CpConfig c{};
   c.maxit = maxit;
   c.dtype = sizeof(T) == 4 ? 0 : 1;
@@ -180,9 +181,12 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
     int64_t nspec = 0;  // elements of [spec_a, spec_b] copied to buffer 0
     HistGeom<uint64_t> pg[2] = {};
     std::vector<int64_t> ph[2];
+    // the two sides' bins (the batched kernel's counting evaluation uses fewer per side)
+    CpConfig cs = c;
+    if (count_only && side_bits >= 0 && side_bits < c.hist_bits) cs.hist_bits = side_bits;
     if (counted)
       for (int p = 0; p < 2; ++p) {
-        pg[p] = split_part_geometry(s, p, c);
+        pg[p] = split_part_geometry(s, p, cs);
         ph[p].assign((size_t)pg[p].nbins, 0);
       }
     EvalResult e{};
@@ -266,7 +270,66 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
   return 0;
 }
 
+// Replay of the batched kernel's work queue on the host: the descriptor checks and the
+// largest-first order of the kernel's bitonic network (batch_queue.h, the kernel's own code),
+// then every valid array through the state machine with the batched kernel's configuration:
+// the counting evaluation with 2^side_bits key bins per side, histogram passes over the array
+// itself (no compaction), the gather and the exact select.  addrs: the descriptor pointers as
+// the kernel would see them; data[off[i]..] the values of array i (off < 0: not readable).
+// order_out: the array taken at each queue position; status_out: 4 (BADARG), the state
+// machine's status, or a negative driver error.
+template <typename T>
+static void replay_batch(const T *data, const uint64_t *addrs, const int64_t *off,
+                         const int64_t *sizes, const int64_t *ks, int64_t count, int64_t ft,
+                         int hist_bits, int side_bits, int64_t *order_out, int32_t *status_out,
+                         double *value_out, int64_t *less_out, int64_t *equal_out,
+                         int32_t *passes_out) {
+  const bool sorted = count <= kBatchSortMax;
+  int64_t m = 1;
+  while (m < count) m <<= 1;
+  std::vector<uint64_t> order(sorted ? (size_t)m : 0);
+  if (sorted) {
+    for (int64_t j = 0; j < m; ++j) order[(size_t)j] = j < count ? lpt_key(sizes[j], j) : 0;
+    for (int64_t kk = 2; kk <= m; kk <<= 1)
+      for (int64_t jj = kk >> 1; jj > 0; jj >>= 1)
+        for (int64_t i = 0; i < m; ++i) bitonic_exchange(order.data(), i, jj, kk);
+  }
+  for (int64_t j = 0; j < count; ++j) {
+    const int64_t i = sorted ? lpt_index(order[(size_t)j]) : j;
+    order_out[j] = i;
+    value_out[i] = 0.0;
+    less_out[i] = equal_out[i] = 0;
+    passes_out[i] = 0;
+    if (!batch_array_valid(addrs[i], sizes[i], ks[i], (uint32_t)sizeof(T))) {
+      status_out[i] = ST_BADARG;
+      continue;
+    }
+    if (off[i] < 0) {  // a descriptor the kernel would read but the replay has no data for
+      status_out[i] = -100;
+      continue;
+    }
+    SimResult r{};
+    const int rc = sim<T>(data + off[i], sizes[i], ks[i], 64, ft, 1.0, 0, 0.0, 0.0, 0, 0,
+                          hist_bits, 1, 0, 1, 0, &r, side_bits);
+    status_out[i] = rc != 0 ? rc : r.status;
+    value_out[i] = r.value;
+    less_out[i] = r.less;
+    equal_out[i] = r.equal;
+    passes_out[i] = r.work_passes;
+  }
+}
+
 extern "C" {
+
+int replay_batch_f32(const float *data, const uint64_t *addrs, const int64_t *off,
+                     const int64_t *sizes, const int64_t *ks, int64_t count, int64_t ft,
+                     int hist_bits, int side_bits, int64_t *order_out, int32_t *status_out,
+                     double *value_out, int64_t *less_out, int64_t *equal_out,
+                     int32_t *passes_out) {
+  replay_batch<float>(data, addrs, off, sizes, ks, count, ft, hist_bits, side_bits, order_out,
+                      status_out, value_out, less_out, equal_out, passes_out);
+  return 0;
+}
 
 int sim_select_f32(const float *x, int64_t n, int64_t k, int maxit, int64_t ft, double theta,
                    int ub, double blo, double bhi, int p0_split, int64_t p0_cap, int hist_bits,

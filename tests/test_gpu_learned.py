@@ -301,3 +301,52 @@ def test_sampled_proposal_parity(sel, oracle_mod, dtype):
     r_plain = sel.select_kth(_dev(x), k)
     r_s = sel.select_kth_sampled(_dev(x), k, z=4.0)
     assert r_s["passes"] < r_plain["passes"]
+
+
+def _fnv1a64(data: bytes) -> int:
+    h = 14695981039346656037
+    for b in data:
+        h = ((h ^ b) * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def test_model_file_round_trip(sel, tmp_path):
+    """cps_model_save writes the documented layout (magic, version, shape, feature
+    specification, count, FNV-1a hash, parameters); cps_model_load gives back the same bits
+    and rejects a file with any field, the hash or the length wrong, leaving the target as it
+    was."""
+    import struct
+
+    import paper_1104_2732_amd as cps
+    print("case model file round trip", flush=True)
+    P = sel.mlp_init(11)
+    path = str(tmp_path / "net.cpsmlp")
+    sel.model_save(P, path)
+    raw = open(path, "rb").read()
+    assert len(raw) == 40 + 4 * cps.MLP_PARAMS
+    assert raw[:8] == b"CPSMLP01"
+    assert struct.unpack("<6I", raw[8:32]) == (1, 67, 64, 2, 1, cps.MLP_PARAMS)
+    params = np.frombuffer(raw[40:], dtype="<f4")
+    assert np.array_equal(params.view(np.uint32), P.cpu().numpy().view(np.uint32))
+    assert struct.unpack("<Q", raw[32:40])[0] == _fnv1a64(raw[40:])
+    Q = sel.model_load(path)
+    assert torch.equal(Q.view(torch.int32), P.view(torch.int32))
+    # damaged files: a flipped parameter bit, a wrong version, a truncated or longer file
+    sentinel = torch.full_like(P, 7.0)
+    for name, blob in (("bit", raw[:100] + bytes([raw[100] ^ 1]) + raw[101:]),
+                       ("version", raw[:8] + struct.pack("<I", 2) + raw[12:]),
+                       ("shape", raw[:16] + struct.pack("<I", 32) + raw[20:]),
+                       ("short", raw[:-4]), ("long", raw + b"\0")):
+        bad = tmp_path / f"bad_{name}"
+        bad.write_bytes(blob)
+        with pytest.raises(cps.CpsError) as ei:
+            sel.model_load(str(bad), sentinel)
+        assert ei.value.code == cps.CPS_EFORMAT, name
+        assert torch.all(sentinel == 7.0), name
+    with pytest.raises(cps.CpsError) as ei:
+        sel.model_load(str(tmp_path / "missing"), sentinel)
+    assert ei.value.code == cps.CPS_EIO
+    # a loaded network proposes exactly what the saved one did
+    x = workloads.single_array("normal", 1 << 16, np.float32, seed=2, tag="model-io")
+    xt = _dev(x)
+    assert sel.learned_bracket(xt, 1000, P) == sel.learned_bracket(xt, 1000, Q)

@@ -46,3 +46,86 @@ def test_objective_parity(sel, oracle_mod, dist, dtype):
                         assert g[f] == 0
                     else:
                         assert abs(g[f] - r[f]) <= TOL[dtype] * abs(r[f]), (f, g[f], r[f])
+
+
+ALPHA_BETA = lambda n, k: (k - 0.5, n - k + 0.5)  # noqa: E731  (Section 3, Eq. 2)
+
+SCHEDULES = {
+    # every pass an evaluation of A, B, the counts and the neighbours over the whole array,
+    # then the gather and the exact select (Algorithm 1 iterated)
+    "cutting_plane": dict(partition_fraction=0.0, hist_bits=0, final_threshold=4096),
+    # the split at the first trial point: later evaluations read the compacted bracket and
+    # rebuild A and B of the whole array from the bracket's sums
+    "split": dict(count_first=0, hist_bits=0, final_threshold=4096),
+    # the default: pass 0, the counting evaluation, histogram passes
+    "default": dict(),
+}
+
+
+def _close(g, r, tol):
+    return g == r if r == 0 else abs(g - r) <= tol * abs(r)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("schedule", list(SCHEDULES))
+def test_hot_path_pass_trace(sel, oracle_mod, dtype, schedule):
+    """What the selection's own passes computed (the per-pass trace of cps_stats) against the
+    float64 objective of the oracle at the same points: pass 0's f at the extremes from the
+    sum (Section 4, step 0) and the extremes' multiplicities; every evaluation's A, B and
+    f = alpha A + beta B within the tolerance, its counts and neighbours exactly; a counting
+    evaluation's counts exactly."""
+    import paper_1104_2732_amd as cps
+    n = (1 << 22) + 17
+    dists = ["normal", "uniform", "cauchy", "quantized_normal"]
+    if schedule != "cutting_plane":
+        dists = dists[:2]
+    tol = TOL[dtype]
+    for dist in dists:
+        x = workloads.single_array(dist, n, dtype, seed=31, tag="gpu-trace")
+        xt = torch.from_numpy(x).cuda()
+        for k in (n // 100, (n + 1) // 2):
+            print(f"case pass-trace {schedule} {dist} n={n} k={k} dtype={x.dtype}", flush=True)
+            res, st = sel.select_kth(xt, k, options=cps.default_options(**SCHEDULES[schedule]),
+                                     stats=True)
+            ref = oracle_mod.select_kth(x, k)
+            assert res["status"] == 0 and res["value_bits"] == ref["value_bits"]
+            npass = min(int(st["work_passes"]), cps.STATS_MAX_PASSES)
+            kinds = st["kind"][:npass]
+            assert kinds[0] == cps.PASS_ZERO
+            ys = np.array([st["trial"][i] for i in range(npass)
+                           if kinds[i] in (cps.PASS_EVAL, cps.PASS_COUNT)]
+                          + [float(x.min()), float(x.max())], dtype=np.float64)
+            ev = oracle_mod.objective(x, k, ys)
+            by_y = {float(y): e for y, e in zip(ys, ev)}
+            alpha, beta = ALPHA_BETA(n, k)
+            lo, hi = by_y[float(x.min())], by_y[float(x.max())]
+            # pass 0: A at the minimum, B at the maximum, the extremes and multiplicities
+            assert st["pred"][0] == x.min() and st["succ"][0] == x.max()
+            assert (st["L"][0], st["G"][0]) == (lo["E"], hi["E"])
+            assert _close(st["A"][0], lo["A"], tol), (st["A"][0], lo["A"])
+            assert _close(st["B"][0], hi["B"], tol), (st["B"][0], hi["B"])
+            assert _close(alpha * st["A"][0], lo["f"], tol) and _close(beta * st["B"][0], hi["f"], tol)
+            n_eval = 0
+            for i in range(1, npass):
+                if kinds[i] not in (cps.PASS_EVAL, cps.PASS_COUNT):
+                    continue
+                r = by_y[float(st["trial"][i])]
+                ctx = (schedule, dist, k, i, int(kinds[i]))
+                assert (st["L"][i], st["G"][i]) == (r["L"], r["G"]), ctx
+                if kinds[i] == cps.PASS_COUNT:
+                    continue
+                n_eval += 1
+                assert _close(st["A"][i], r["A"], tol), (ctx, st["A"][i], r["A"])
+                assert _close(st["B"][i], r["B"], tol), (ctx, st["B"][i], r["B"])
+                f = alpha * st["A"][i] + beta * st["B"][i]
+                assert _close(f, r["f"], tol), (ctx, f, r["f"])
+                # neighbours of the working set: those of the whole array when it is read,
+                # else the same wherever the working set holds one (the bracket's elements
+                # below / above t include the array's nearest ones)
+                if st["working"][i] == n or np.isfinite(st["pred"][i]):
+                    assert st["pred"][i] == r["pred"], ctx
+                if st["working"][i] == n or np.isfinite(st["succ"][i]):
+                    assert st["succ"][i] == r["succ"], ctx
+            if schedule == "cutting_plane":
+                assert n_eval >= 3, (dist, k, n_eval)
+        del xt

@@ -242,3 +242,55 @@ def test_large_input_counting_with_interval_copy(sel, oracle_mod, dist):
         assert st["passes"] <= 3, (dist, k, st["passes"])
     del xt
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dist", ["normal", "cauchy", "quantized_normal"])
+def test_float64_counting_with_interval_copy(sel, oracle_mod, dist):
+    """float64 from 256 MiB of input (2^25 elements): the counting evaluation copies the
+    likely interval as 8-byte elements (two per 16-byte vector) and the copy becomes the
+    working set when the narrowed bracket lies inside it."""
+    n = (1 << 25) + 17
+    x = workloads.single_array(dist, n, np.float64, seed=9, tag="gpu-large64")
+    xt = _dev(x)
+    for k in (n // 100, (n + 1) // 2):
+        print(f"case large-interval-f64 {dist} n={n} k={k}", flush=True)
+        res, st = sel.select_kth(xt, k, stats=True)
+        assert_same_result(res, oracle_mod.select_kth(x, k), f"{dist} k={k}")
+        assert st["passes"] <= 3, (dist, k, st["passes"])
+    del xt
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dist", ["uniform", "cauchy"])
+def test_float32_counting_with_interval_copy_more_distributions(sel, oracle_mod, dist):
+    n = (1 << 26) + 17
+    x = workloads.single_array(dist, n, np.float32, seed=10, tag="gpu-large32")
+    xt = _dev(x)
+    for k in (1 + n // 100, (n + 1) // 2, n - n // 100):
+        print(f"case large-interval-f32 {dist} n={n} k={k}", flush=True)
+        res, st = sel.select_kth(xt, k, stats=True)
+        assert_same_result(res, oracle_mod.select_kth(x, k), f"{dist} k={k}")
+        assert st["passes"] <= 3, (dist, k, st["passes"])
+    del xt
+    torch.cuda.empty_cache()
+
+
+def test_timeout_leaves_the_handle_usable(sel, oracle_mod):
+    """A call whose waits give up at once (spin limit 1: the waiting workgroups leave with
+    status TIMEOUT, the one that went on alone leaves at its next wait) must not leave the
+    grid's arrival counters part-way counted for the next call on the same handle."""
+    import paper_1104_2732_amd as cps
+    n = (1 << 22) + 5
+    x = workloads.single_array("normal", n, np.float32, seed=4, tag="gpu-timeout")
+    xt = _dev(x)
+    k = (n + 1) // 2
+    ref = oracle_mod.select_kth(x, k)
+    for rep in range(2):
+        print(f"case timeout rep={rep} n={n}", flush=True)
+        res = sel.select_kth(xt, k, options=cps.default_options(spin_limit=1))
+        assert res["status"] in (cps.STATUS_OK, cps.STATUS_TIMEOUT), res
+        if res["status"] == cps.STATUS_OK:
+            assert_same_result(res, ref)
+        for kk in (1 + n // 100, k):
+            assert_same_result(sel.select_kth(xt, kk), oracle_mod.select_kth(x, kk), f"after {rep}")
+    del xt

@@ -170,6 +170,48 @@ def test_nonfinite_sample_gives_no_proposal():
     assert mlp.sample_features(x, 3) is not None
 
 
+def test_forward_weight_orientation():
+    """A single path through distinct units, feature 10 -> hidden unit 3 -> hidden unit 7 ->
+    output 0, pins each weight matrix as (output unit, input unit): any transposed block
+    routes the signal through a unit that carries nothing and the output is 0."""
+    p = np.zeros(mlp.N_PARAMS)
+    blocks = mlp.unpack(p)
+    blocks["W1"][3, 10] = 1.0
+    blocks["W2"][7, 3] = 2.0
+    blocks["W3"][0, 7] = 0.5
+    blocks["b3"][1] = -0.25
+    F = np.zeros((3, mlp.N_IN))
+    F[:, 10] = [0.1, 0.4, 0.9]
+    o, _ = mlp.forward(p, F)
+    assert np.array_equal(o[:, 0], [0.1, 0.4, 0.9]) and np.all(o[:, 1] == -0.25)
+    # each block with its one weight transposed (W3: on the other output's row)
+    for name, idx in (("W1", (10, 3)), ("W2", (3, 7)), ("W3", (1, 7))):
+        q = np.zeros(mlp.N_PARAMS)
+        qb = mlp.unpack(q)
+        qb["W1"][3, 10], qb["W2"][7, 3], qb["W3"][0, 7] = 1.0, 2.0, 0.5
+        w = qb[name][np.nonzero(qb[name])][0]
+        qb[name][:] = 0.0
+        qb[name][idx] = w
+        o2, _ = mlp.forward(q, F)
+        assert np.all(o2[:, 0] == 0.0), name
+
+
+def test_adam_constant_gradient_closed_form():
+    """With the same gradient g at every step the moments are m_t = (1 - b1^t) g and
+    v_t = (1 - b2^t) g^2, their bias-corrected values g and g^2 at every t, so each step moves
+    by lr g / (|g| + eps): a bias correction frozen at any step fails from t = 2 on."""
+    rng = np.random.default_rng(3)
+    theta0 = rng.standard_normal(40)
+    g = rng.standard_normal(40)
+    theta, m, v = theta0.copy(), np.zeros(40), np.zeros(40)
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    for t in range(1, 8):
+        theta, m, v = mlp.adam_step(theta, g, m, v, t, lr=lr, beta1=b1, beta2=b2, eps=eps)
+        assert np.allclose(m, (1 - b1 ** t) * g, rtol=1e-14, atol=0)
+        assert np.allclose(v, (1 - b2 ** t) * g * g, rtol=1e-12, atol=0)
+        assert np.allclose(theta, theta0 - t * lr * g / (np.abs(g) + eps), rtol=0, atol=1e-14)
+
+
 def test_adam_first_step_closed_form():
     rng = np.random.default_rng(2)
     theta = rng.standard_normal(50)
