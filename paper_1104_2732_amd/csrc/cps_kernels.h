@@ -34,7 +34,9 @@ constexpr int kMaxGroups = 256;  // so at most 4096 workgroups
 // overall advances the state and bumps `gen`, on which the others wait.  gcur hands out
 // write offsets in the gather buffer.  `exits` counts the workgroups that have left the
 // launch: the last one clears the arrival counters, which a wait that timed out can leave
-// part-way counted, so every launch starts from zeroed counters.
+// part-way counted, so every launch starts from zeroed counters.  A workgroup whose wait
+// timed out sets `tmo`; the last one out then also clears the histogram counters, which a
+// pass that was abandoned half-way may have left counted.
 struct SyncCtl {
   uint32_t top;
   uint32_t gen;
@@ -43,6 +45,8 @@ struct SyncCtl {
   uint64_t pad1[15];
   uint32_t exits;
   uint32_t pad2[31];
+  uint32_t tmo;
+  uint32_t pad3[31];
   uint32_t grp[kMaxGroups][32];
 };
 

@@ -1565,6 +1565,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_num_vgpr(128))) void c
         }
         sh.timed_out = timed_out ? 1 : 0;
         if (!timed_out) gen = gen + 1u;
+        else store_relaxed(&a.sync->tmo, 1u);
       }
       __syncthreads();
       if (sh.timed_out) {
@@ -1593,15 +1594,23 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_num_vgpr(128))) void c
   }
   // Leave the launch.  Normally every arrival counter is back at zero here; after a wait
   // that timed out, a workgroup that went on alone has left its group counter (and maybe
-  // the top counter) part-way counted.  Every wait is bounded, so every workgroup gets here,
-  // and the last one clears the counters for the next launch on this workspace.
+  // the top counter) part-way counted, and an abandoned histogram pass its counters.  Every
+  // wait is bounded, so every workgroup gets here, and the last one clears them for the
+  // next launch on this workspace.
   if (tid == 0) {
     const uint32_t e = __hip_atomic_fetch_add(&a.sync->exits, 1u, __ATOMIC_ACQ_REL,
                                               __HIP_MEMORY_SCOPE_AGENT);
-    if (e == (uint32_t)G - 1u) {
+    sh.last = e == (uint32_t)G - 1u ? 1 : 0;
+  }
+  __syncthreads();
+  if (sh.last) {
+    if (load_relaxed(&a.sync->tmo) != 0u)
+      for (int b = tid; b < kHistWords; b += BLOCK) a.ghist[b] = 0;
+    if (tid == 0) {
       const int ng = (G + kGroup - 1) / kGroup;
       for (int g = 0; g < ng; ++g) store_relaxed(&a.sync->grp[g][0], 0u);
       store_relaxed(&a.sync->top, 0u);
+      store_relaxed(&a.sync->tmo, 0u);
       store_release(&a.sync->exits, 0u);
     }
   }
