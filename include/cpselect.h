@@ -52,7 +52,8 @@ enum cps_error {
   CPS_ENODEV = -5,   /* no usable gfx950 device */
   CPS_ESTATE = -6,   /* the handle is in an unusable state */
   CPS_EIO = -7,      /* a network file could not be opened, read or written */
-  CPS_EFORMAT = -8   /* a network file is not a valid file of this network (see cps_model_load) */
+  CPS_EFORMAT = -8,  /* a network file is not a valid file of this network (see cps_model_load) */
+  CPS_ESCRATCH = -9  /* select_kth_noalloc: the call needs more than its static scratch array */
 };
 
 /* Asynchronous status, written by the device into cps_result.status. */
@@ -247,6 +248,29 @@ int select_kth(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
 int select_kth_ex(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
                   const cps_options *opt, cps_result *out_dev, cps_stats *stats_dev,
                   void *stream);
+
+/* select_kth for callers that cannot allocate device memory: code under stream capture,
+ * serving loops, harnesses that forbid hipMalloc.  The call allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine) and takes none of the handle's workspace: its
+ * scratch words (the selection state, the grid's synchronisation words, 2 x 4096 histogram
+ * counters, the workgroups' partials and a gather buffer of 8192 elements) live in one
+ * file-scope device array of 1 MiB per GPU, which that GPU holds until the process ends.
+ * cps_create takes the array's device address for its device.
+ * The selection is that of select_kth's defaults without the split buffers: pass 0, the
+ * counting evaluation at the first trial point, then key-histogram passes over x that count
+ * the narrowed bracket without copying it (each keeps one of 4096 bins), the gather of the
+ * last few thousand elements and the exact select.  Results (value, counts, status) are
+ * identical to select_kth's; it reads x about twice as often on large inputs.
+ * The launch is a fill kernel that zeroes the synchronisation words and histogram counters,
+ * then the selection kernel: both may be captured in a graph.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's contents:
+ * calls whose device work overlaps on one GPU (different streams, or different handles of
+ * the same device) race and give wrong results; the caller must order them.
+ * Arguments, layout and errors as select_kth, and CPS_ESTATE when the handle's device has
+ * no scratch address, CPS_ESCRATCH when the launch shape would need more than the array
+ * (it does not on any device of up to 1024 resident workgroups). */
+int select_kth_noalloc(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
+                       cps_result *out_dev, void *stream);
 
 /* f, A, B, counts, neighbours and subgradient end points at each of ny points ys_dev
  * (device doubles), for the rank-k objective of x[0..n) (Section 3, Eq. 2): the quantities a

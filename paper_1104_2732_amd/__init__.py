@@ -30,7 +30,7 @@ LIB_PATH = os.path.join(_HERE, "libcpselect.so")
 
 CPS_F32, CPS_F64 = 0, 1
 CPS_OK = 0
-CPS_EIO, CPS_EFORMAT = -7, -8
+CPS_EIO, CPS_EFORMAT, CPS_ESCRATCH = -7, -8, -9
 STATUS_OK, STATUS_NAN, STATUS_TIMEOUT, STATUS_INTERNAL = 0, 1, 2, 3
 STATS_MAX_PASSES = 96
 
@@ -115,7 +115,8 @@ EXPORTS = ("cps_create", "cps_destroy", "cps_status_string", "cps_last_hip_error
            "cps_reserve_batched", "cps_autotune_batched", "lms_median_sq_residuals",
            "cps_mixture_generate", "cps_features", "cps_mlp_forward", "cps_mlp_loss_grad",
            "cps_mlp_adam", "cps_mlp_init", "cps_learned_bracket", "select_kth_learned",
-           "cps_mlp_train", "select_kth_sampled", "cps_model_save", "cps_model_load")
+           "cps_mlp_train", "select_kth_sampled", "cps_model_save", "cps_model_load",
+           "select_kth_noalloc")
 STATUS_BADARG = 4
 
 
@@ -144,6 +145,8 @@ def lib() -> ctypes.CDLL:
     L.select_kth.restype = c_int
     L.select_kth_ex.argtypes = [vp, vp, i64, i64, c_int, ctypes.POINTER(Options), vp, vp, vp]
     L.select_kth_ex.restype = c_int
+    L.select_kth_noalloc.argtypes = [vp, vp, i64, i64, c_int, vp, vp]
+    L.select_kth_noalloc.restype = c_int
     L.cps_objective.argtypes = [vp, vp, i64, i64, c_int, vp, i64, vp, vp]
     L.cps_objective.restype = c_int
     L.cps_default_batch_options.argtypes = [ctypes.POINTER(BatchOptions)]
@@ -271,6 +274,15 @@ class Selector:
                                  ctypes.c_void_p(stats.data_ptr()) if stats is not None else None,
                                  ctypes.c_void_p(_stream_ptr(self.device)))
         _check(rc, "select_kth_ex")
+
+    def select_kth_noalloc_async(self, x, k: int, out) -> None:
+        """Enqueue select_kth_noalloc on the current stream (no allocation, static scratch)."""
+        if not x.is_cuda or not x.is_contiguous():
+            raise ValueError("x must be a contiguous CUDA tensor")
+        rc = lib().select_kth_noalloc(self._h, ctypes.c_void_p(x.data_ptr()), x.numel(), int(k),
+                                      _dtype_code(x), ctypes.c_void_p(out.data_ptr()),
+                                      ctypes.c_void_p(_stream_ptr(self.device)))
+        _check(rc, "select_kth_noalloc")
 
     def reserve(self, n: int, dtype_code: int) -> None:
         _check(lib().cps_reserve(self._h, int(n), int(dtype_code)), "cps_reserve")

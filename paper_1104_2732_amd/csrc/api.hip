@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <mutex>
 #include <vector>
 
@@ -490,6 +491,7 @@ const char *cps_status_string(int code) {
     case CPS_ESTATE: return "handle in an unusable state";
     case CPS_EIO: return "network file could not be opened, read or written";
     case CPS_EFORMAT: return "not a valid network file";
+    case CPS_ESCRATCH: return "the call needs more than the static scratch of select_kth_noalloc";
     default: break;
   }
   return "unknown code";
@@ -512,6 +514,9 @@ int cps_create(int device, cps_handle **out) {
   (void)hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device);
   if (!coop) return CPS_ENODEV;
   e = hipSetDevice(device);
+  if (e != hipSuccess) return hip_fail(e);
+  // the device address of select_kth_noalloc's scratch array on this device (once per device)
+  e = cps::noalloc_bind(device);
   if (e != hipSuccess) return hip_fail(e);
   cps_handle *h = new cps_handle();
   h->device = device;
@@ -573,6 +578,60 @@ int select_kth_ex(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
 int select_kth(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
                cps_result *out_dev, void *stream) {
   return select_kth_ex(h, x, n, k, dtype, nullptr, out_dev, nullptr, stream);
+}
+
+int select_kth_noalloc(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
+                       cps_result *out_dev, void *stream) {
+  int rc = check_common(h, x, n, k, dtype);
+  if (rc) return rc;
+  if (!out_dev) return CPS_EINVAL;
+  char *base = (char *)cps::noalloc_scratch(h->device);
+  if (!base) return CPS_ESTATE;
+  std::lock_guard<std::mutex> lk(h->mu);
+  hipStream_t s = (hipStream_t)stream;
+  Resolved r;
+  rc = resolve(h, n, dtype, nullptr, r);
+  if (rc) return rc;
+  // The defaults without the split buffers: the counting evaluation at the first trial point,
+  // then histogram passes over x that count the narrowed bracket without copying it, and the
+  // gather of its last few elements.  No likely-interval copy.
+  r.cfg.hist_compact = 0;
+  r.cfg.spec_min_n = 0;
+  r.seg_R = 0;
+  if (r.grid > cps::kNoAllocMaxGrid) r.grid = cps::kNoAllocMaxGrid;
+  const size_t es = dtype_size(dtype);
+  const SelectLayout L = select_layout(0, r.grid, r.cfg.zcap, r.grid, es);
+  if (L.total > cps::kNoAllocScratchBytes) return CPS_ESCRATCH;
+  // every word the kernel expects zero at launch: the synchronisation words and the
+  // histogram counters (the state and the partials are written before they are read)
+  hipError_t e = cps::launch_scratch_clear(base + L.sync, L.sd - L.sync, s);
+  if (e != hipSuccess) return hip_fail(e);
+  auto fill = [&](auto *xt) {
+    using T = std::remove_const_t<std::remove_pointer_t<decltype(xt)>>;
+    cps::SelectArgs<T> a{};
+    a.x = xt;
+    a.n = n;
+    a.k = k;
+    a.st = (cps::CpState *)(base + L.st);
+    a.sync = (cps::SyncCtl *)(base + L.sync);
+    a.sd = (double *)(base + L.sd);
+    a.si = (int64_t *)(base + L.si);
+    a.slot_stride = L.slot_stride;
+    a.z[0] = a.z[1] = nullptr;
+    a.seg_R = 0;
+    a.zf = (T *)(base + L.zf);
+    a.out = out_dev;
+    a.stats = nullptr;
+    a.cfg = r.cfg;
+    a.spin_limit = r.spin_limit;
+    a.bracket = nullptr;
+    a.p0_cap = 0;
+    a.ghist = (uint64_t *)(base + L.gh);
+    a.phist = nullptr;
+    return cps::launch_select<T>(a, r.grid, s);
+  };
+  e = dtype == CPS_F32 ? fill((const float *)x) : fill((const double *)x);
+  return e == hipSuccess ? CPS_OK : hip_fail(e);
 }
 
 int cps_objective(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,

@@ -112,6 +112,22 @@ template <typename T>
 hipError_t launch_objective(const T *x, int64_t n, int64_t k, const double *ys, int64_t ny,
                             cps_eval *out, double *pd, int64_t *pi, int nb, hipStream_t stream);
 
+// ---- the selection without allocation (select_kth_noalloc)
+
+// Size of the per-device scratch array, and the largest grid it serves: the state, the
+// synchronisation words, 2 x 4096 histogram counters, 16 partial words per workgroup and a
+// gather buffer of the final threshold (8192 elements): about 300 KiB at 1024 workgroups.
+constexpr size_t kNoAllocScratchBytes = (size_t)1 << 20;
+constexpr int kNoAllocMaxGrid = 1024;
+
+// Take the scratch array's device address on `device`, which must be current (once per
+// device; later calls return at once).
+hipError_t noalloc_bind(int device);
+// That address, or null when noalloc_bind has not run for the device.
+void *noalloc_scratch(int device);
+// Zero `bytes` (a multiple of 8) at p with a fill kernel.
+hipError_t launch_scratch_clear(void *p, size_t bytes, hipStream_t stream);
+
 // ---- learned bracket proposal
 
 hipError_t launch_mixture_gen(uint64_t seed, int64_t first_id, int64_t count, int64_t n,
