@@ -285,7 +285,8 @@ int cps_objective(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
 /* ------------------------------------------------------------------ batched selection */
 
 /* Tuning of the batched kernel.  Fill with cps_default_batch_options first (1024 threads,
- * split capacity 2^17, final threshold 4096, split fraction 1, 2^12 bins, count first);
+ * split capacity 2^17, final threshold 4096, split fraction 1, 2^12 bins, count first, the
+ * sampled bracket, one workgroup per array);
  * 0 fields pick the tuned (or default) value.
  * block_threads:   workgroup size, 256, 512 or 1024 (one workgroup runs one array at a time).
  * blocks_per_cu:   resident workgroups per compute unit.
@@ -297,7 +298,31 @@ int cps_objective(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
  * count_first:     as in cps_options, with 2^11 bins per side (the two sides share the
  *                  workgroup's LDS histogram); the bin's elements are then counted by
  *                  histogram passes over the array (no copy) until few are left for the
- *                  gather.  The split capacity does not limit it.  1 (default) or 0. */
+ *                  gather.  The split capacity does not limit it.  1 (default) or 0.
+ * proposal:        1 (default): an array of at least 2^15 elements starts from a sampled
+ *                  bracket (not in the paper): 4096 of its elements (256 runs of 16
+ *                  neighbours) counted in 2^12 key bins over their range, and the values just
+ *                  outside the bins of sample ranks S p -/+ (4 sqrt(S p (1 - p)) + 2), p =
+ *                  (k - 1/2) / n, S = 4096.  Pass 0 counts #(x <= a) and #(x < b), keeps each
+ *                  end only where the counts prove it (as cps_options.use_bracket), counts the
+ *                  elements strictly inside in key bins and copies every 16-byte vector of x
+ *                  that holds one to a buffer; when both ends hold, the bracket narrows to the
+ *                  bin of the rank at once and every later pass reads only the copy.  The
+ *                  result never depends on it.  Needs hist_bits > 0 (ignored otherwise).
+ *                  0: every array from [min, max].
+ * blocks_per_array, elements_per_block: with the proposal, an array of n > elements_per_block
+ *                  elements is split into min(blocks_per_array, ceil(n / elements_per_block))
+ *                  contiguous parts, each taken by its own workgroup for pass 0 (the one pass
+ *                  over the whole array); the last part to arrive folds the parts' partials
+ *                  (in part order) and finishes the array alone.  Only the 1024 largest arrays
+ *                  of a batch of at most 4096 may be split.  blocks_per_array in [1, 16]
+ *                  (default 1: one workgroup per array), elements_per_block >= 2^15
+ *                  (default 2^18).
+ * team_capacity:   elements of the buffer that holds an array's copied vectors (default 2^18:
+ *                  enough for arrays of about a million elements); a copy that does not fit
+ *                  makes pass 0's counts decide alone and the array continues over its full
+ *                  length (exact, slower).  Each workgroup has one such buffer, and each
+ *                  split array one more. */
 typedef struct cps_batch_options {
   int32_t block_threads;
   int32_t blocks_per_cu;
@@ -307,6 +332,10 @@ typedef struct cps_batch_options {
   double partition_fraction;
   int32_t hist_bits;
   int32_t count_first;
+  int32_t proposal;
+  int32_t blocks_per_array;
+  int64_t elements_per_block;
+  int64_t team_capacity;
 } cps_batch_options;
 
 void cps_default_batch_options(cps_batch_options *opt);
@@ -334,12 +363,13 @@ int select_kth_batched_ex(cps_handle *h, const void *const *ptrs_dev, const int6
 /* Allocate the batched workspace for `opt` (NULL: the current choice) ahead of stream capture. */
 int cps_reserve_batched(cps_handle *h, int dtype, const cps_batch_options *opt);
 
-/* Autotuner: time each candidate launch shape (256, 512, 1024 threads) with the counting
- * evaluation at split fractions 0.5 and 1, and with splits at every split capacity
- * (2^15 .. 2^20) and fraction, on this very batch (the call synchronises `stream`); keep
- * the fastest as the handle's choice for `dtype`, and return it in best (may be NULL)
- * with its time in *best_ms (may be NULL).  The results in out_dev are those of the last
- * timed candidate. */
+/* Autotuner: time each candidate launch shape (256, 512, 1024 threads) with the sampled
+ * bracket and one workgroup per array or 4, 8 or 16 per array at 2^16 .. 2^18 elements per
+ * workgroup, without it (the counting evaluation from [min, max]), and with splits at split
+ * capacities 2^17 and 2^19, on this very batch (the call synchronises `stream`); keep the
+ * fastest as the handle's choice for `dtype`, and return it in best (may be NULL) with its
+ * time in *best_ms (may be NULL).  The results in out_dev are those of the last timed
+ * candidate. */
 int cps_autotune_batched(cps_handle *h, const void *const *ptrs_dev, const int64_t *sizes_dev,
                          const int64_t *ks_dev, int64_t count, int dtype, cps_result *out_dev,
                          void *stream, cps_batch_options *best, double *best_ms);

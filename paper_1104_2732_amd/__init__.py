@@ -76,7 +76,9 @@ class BatchOptions(ctypes.Structure):
     _fields_ = [("block_threads", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("split_capacity", ctypes.c_int64), ("final_threshold", ctypes.c_int32),
                 ("maxit", ctypes.c_int32), ("partition_fraction", ctypes.c_double),
-                ("hist_bits", ctypes.c_int32), ("count_first", ctypes.c_int32)]
+                ("hist_bits", ctypes.c_int32), ("count_first", ctypes.c_int32),
+                ("proposal", ctypes.c_int32), ("blocks_per_array", ctypes.c_int32),
+                ("elements_per_block", ctypes.c_int64), ("team_capacity", ctypes.c_int64)]
 
 
 class TrainOptions(ctypes.Structure):

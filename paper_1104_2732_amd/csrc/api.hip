@@ -32,6 +32,7 @@ struct cps_handle {
   size_t ws_bytes = 0;
   void *bws = nullptr;  // batched workspace (queue counters first)
   size_t bws_bytes = 0;
+  cps::TeamCtl *tws = nullptr;  // team records of the batched kernel (zeroed once)
   void *lws = nullptr;  // least-median-of-squares residuals and descriptors
   size_t lws_bytes = 0;
   void *mws = nullptr;  // per-workgroup gradient partials of the proposal network
@@ -115,6 +116,33 @@ int ensure_buffer(void *&buf, size_t &have, size_t bytes, hipStream_t stream) {
   e = hipMemset(buf, 0, want < (1 << 21) ? want : (1 << 21));
   if (e != hipSuccess) return hip_fail(e);
   have = want;
+  return CPS_OK;
+}
+
+// The team records of the batched kernel: allocated and zeroed once per handle (every use
+// leaves them zero again).
+int ensure_team_records(cps_handle *h, hipStream_t stream) {
+  if (h->tws) return CPS_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (stream != nullptr) {
+    hipError_t e = hipStreamIsCapturing(stream, &cs);
+    if (e != hipSuccess) return hip_fail(e);
+    if (cs != hipStreamCaptureStatusNone) return CPS_ECAPTURE;
+  }
+  const size_t bytes = (size_t)cps::kTeamRecords * sizeof(cps::TeamCtl);
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    g_last_hip = (int)e;
+    return CPS_ENOMEM;
+  }
+  e = hipMemset(p, 0, bytes);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    (void)hipFree(p);
+    return hip_fail(e);
+  }
+  h->tws = (cps::TeamCtl *)p;
   return CPS_OK;
 }
 
@@ -246,11 +274,14 @@ int check_common(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype) 
 struct BatchResolved {
   cps::CpConfig cfg;
   int grid, block;
-  int64_t cap, ws_stride;
-  size_t bytes;
+  int64_t cap, ws_stride, gb_off;
+  int32_t proposal, team_max;
+  int64_t team_chunk, team_cap, team_records;
+  size_t wg_off, bytes;  // per-workgroup buffers at wg_off (after the team buffers)
 };
 
-int resolve_batched(cps_handle *h, int dtype, const cps_batch_options *opt, BatchResolved &r) {
+int resolve_batched(cps_handle *h, int dtype, int64_t count, const cps_batch_options *opt,
+                    BatchResolved &r) {
   cps_batch_options o;
   cps_default_batch_options(&o);
   const int di = dtype == CPS_F32 ? 0 : 1;
@@ -260,7 +291,10 @@ int resolve_batched(cps_handle *h, int dtype, const cps_batch_options *opt, Batc
   if (o.block_threads != 256 && o.block_threads != 512 && o.block_threads != 1024) return CPS_EINVAL;
   if (o.blocks_per_cu < 0 || o.split_capacity < 0 || o.final_threshold < 0 || o.maxit < 0 ||
       !(o.partition_fraction >= 0.0) || o.partition_fraction > 1.0 || o.hist_bits < 0 ||
-      (1 << o.hist_bits) > cps::kHistMaxBins)
+      (1 << o.hist_bits) > cps::kHistMaxBins || o.proposal < 0 || o.proposal > 1 ||
+      o.blocks_per_array < 0 || o.blocks_per_array > cps::kTeamMax || o.elements_per_block < 0 ||
+      (o.elements_per_block > 0 && o.elements_per_block < ((int64_t)1 << 15)) ||
+      o.team_capacity < 0)
     return CPS_EINVAL;
   const size_t es = dtype_size(dtype);
   const int per_cu = dtype == CPS_F32 ? cps::batched_max_blocks_per_cu<float>(o.block_threads)
@@ -271,13 +305,27 @@ int resolve_batched(cps_handle *h, int dtype, const cps_batch_options *opt, Batc
   r.block = o.block_threads;
   r.grid = h->cu_count * bpc;
   const int64_t ft = o.final_threshold ? o.final_threshold : 4096;
+  r.proposal = (o.proposal && o.hist_bits > 0) ? 1 : 0;
+  r.team_max = r.proposal ? (o.blocks_per_array ? o.blocks_per_array : 1) : 1;
+  r.team_chunk = o.elements_per_block ? o.elements_per_block : ((int64_t)1 << 18);
+  r.team_cap = ((o.team_capacity ? o.team_capacity : ((int64_t)1 << 18)) + 63) / 64 * 64;
   r.cap = o.split_capacity ? o.split_capacity : ((int64_t)1 << 17);
-  // with the counting evaluation (and key bins) nothing is ever split: no split buffers
-  if (o.count_first && o.hist_bits > 0) r.cap = ft;
+  // with the counting evaluation (and key bins) nothing is ever split: no split buffers,
+  // except one for the sampled bracket's copy of an array taken by one workgroup (the team
+  // capacity: the copied vectors are ~23 % of a float array, ~12 % of a double one)
+  if (o.count_first && o.hist_bits > 0) r.cap = !r.proposal ? ft : r.team_cap;
   if (r.cap < ft) r.cap = ft;
   r.cap = (r.cap + 63) / 64 * 64;
-  r.ws_stride = 2 * r.cap + (ft + 63) / 64 * 64;
-  r.bytes = align_up(sizeof(cps::BatchCtl), 256) + (size_t)r.grid * r.ws_stride * es;
+  // (the counting evaluation never splits: the second split buffer is not needed)
+  r.gb_off = ((o.count_first && o.hist_bits > 0) ? 1 : 2) * r.cap;
+  r.ws_stride = r.gb_off + (ft + 63) / 64 * 64;
+  // team records for the largest-first slots that may be split (sorted batches only)
+  r.team_records = 0;
+  if (r.team_max > 1 && count <= cps::kBatchSortMax)
+    r.team_records = count < cps::kTeamRecords ? count : cps::kTeamRecords;
+  r.wg_off = align_up(sizeof(cps::BatchCtl), 256) +
+             align_up((size_t)r.team_records * r.team_cap * es, 256);
+  r.bytes = r.wg_off + (size_t)r.grid * r.ws_stride * es;
   r.cfg = cps::CpConfig{};
   r.cfg.maxit = o.maxit ? o.maxit : 64;
   r.cfg.dtype = dtype;
@@ -295,10 +343,11 @@ template <typename T>
 int run_batched(cps_handle *h, const void *const *ptrs, const int64_t *sizes, const int64_t *ks,
                 int64_t count, const cps_batch_options *opt, cps_result *out, hipStream_t stream) {
   BatchResolved r;
-  int rc = resolve_batched(h, sizeof(T) == 4 ? CPS_F32 : CPS_F64, opt, r);
+  int rc = resolve_batched(h, sizeof(T) == 4 ? CPS_F32 : CPS_F64, count, opt, r);
   if (rc) return rc;
   rc = ensure_buffer(h->bws, h->bws_bytes, r.bytes, stream);
   if (rc) return rc;
+  if (r.team_records > 0 && (rc = ensure_team_records(h, stream))) return rc;
   cps::BatchArgs<T> a;
   a.ptrs = (const T *const *)ptrs;
   a.sizes = sizes;
@@ -306,10 +355,18 @@ int run_batched(cps_handle *h, const void *const *ptrs, const int64_t *sizes, co
   a.count = count;
   a.out = out;
   a.ctl = (cps::BatchCtl *)h->bws;
-  a.zbuf = (T *)((char *)h->bws + align_up(sizeof(cps::BatchCtl), 256));
+  a.tbuf = (T *)((char *)h->bws + align_up(sizeof(cps::BatchCtl), 256));
+  a.zbuf = (T *)((char *)h->bws + r.wg_off);
   a.cap = r.cap;
   a.ws_stride = r.ws_stride;
+  a.gb_off = r.gb_off;
   a.cfg = r.cfg;
+  a.proposal = r.proposal;
+  a.team_max = r.team_max;
+  a.team_chunk = r.team_chunk;
+  a.team_cap = r.team_cap;
+  a.team_records = r.team_records;
+  a.teams = h->tws;
   hipError_t e = cps::launch_batched<T>(a, r.grid, r.block, stream);
   if (e != hipSuccess) return hip_fail(e);
   return CPS_OK;
@@ -336,6 +393,10 @@ void cps_default_batch_options(cps_batch_options *opt) {
   opt->partition_fraction = 1.0;
   opt->hist_bits = 12;
   opt->count_first = 1;
+  opt->proposal = 1;
+  opt->blocks_per_array = 1;
+  opt->elements_per_block = (int64_t)1 << 18;
+  opt->team_capacity = (int64_t)1 << 18;
 }
 
 int select_kth_batched_ex(cps_handle *h, const void *const *ptrs_dev, const int64_t *sizes_dev,
@@ -359,9 +420,12 @@ int cps_reserve_batched(cps_handle *h, int dtype, const cps_batch_options *opt) 
   if (!h || !dtype_size(dtype)) return CPS_EINVAL;
   std::lock_guard<std::mutex> lk(h->mu);
   BatchResolved r;
-  int rc = resolve_batched(h, dtype, opt, r);
+  // workspace for the largest batch that may split arrays
+  int rc = resolve_batched(h, dtype, cps::kBatchSortMax, opt, r);
   if (rc) return rc;
-  return ensure_buffer(h->bws, h->bws_bytes, r.bytes, nullptr);
+  rc = ensure_buffer(h->bws, h->bws_bytes, r.bytes, nullptr);
+  if (rc) return rc;
+  return r.team_records > 0 ? ensure_team_records(h, nullptr) : CPS_OK;
 }
 
 int lms_median_sq_residuals(cps_handle *h, const double *X_dev, const double *y_dev,
@@ -406,31 +470,39 @@ int cps_autotune_batched(cps_handle *h, const void *const *ptrs_dev, const int64
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   const int blocks[3] = {256, 512, 1024};
-  constexpr int kCaps = 4;
-  const int64_t caps[kCaps] = {(int64_t)1 << 15, (int64_t)1 << 17, (int64_t)1 << 19,
-                               (int64_t)1 << 20};
-  const double fracs[2] = {0.5, 1.0};
+  // candidates per workgroup size: the sampled bracket with one workgroup per array, or
+  // 4, 8 or 16 per array at 2^16 .. 2^18 elements per workgroup; the counting evaluation
+  // from [min, max]; splits at capacities 2^17 and 2^19
+  struct Cand {
+    int proposal, bpa;
+    int64_t epb;
+    int count_first;
+    int64_t cap;
+  };
+  const Cand cands[] = {{1, 1, 0, 1, 0},
+                        {1, 4, (int64_t)1 << 18, 1, 0},
+                        {1, 8, (int64_t)1 << 17, 1, 0},
+                        {1, 16, (int64_t)1 << 16, 1, 0},
+                        {1, 16, (int64_t)1 << 18, 1, 0},
+                        {0, 1, 0, 1, 0},
+                        {0, 1, 0, 0, (int64_t)1 << 17},
+                        {0, 1, 0, 0, (int64_t)1 << 19}};
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return CPS_EHIP;
   double best_t = 1e300;
   cps_batch_options best_o;
   cps_default_batch_options(&best_o);
   int last_rc = CPS_OK;
-  // per workgroup size: the counting evaluation at either split fraction (the split
-  // capacity does not matter to it), then every split capacity and fraction with splits
   for (int b : blocks) {
-    for (int ci = 0; ci < 2 + 2 * kCaps && !last_rc; ++ci) {
+    for (const Cand &cd : cands) {
       cps_batch_options o;
       cps_default_batch_options(&o);
       o.block_threads = b;
-      if (ci < 2) {
-        o.count_first = 1;
-        o.partition_fraction = fracs[ci];
-      } else {
-        o.count_first = 0;
-        o.split_capacity = caps[(ci - 2) % kCaps];
-        o.partition_fraction = fracs[(ci - 2) / kCaps];
-      }
+      o.proposal = cd.proposal;
+      o.blocks_per_array = cd.bpa;
+      if (cd.epb) o.elements_per_block = cd.epb;
+      o.count_first = cd.count_first;
+      if (cd.cap) o.split_capacity = cd.cap;
       rc = select_kth_batched_ex(h, ptrs_dev, sizes_dev, ks_dev, count, dtype, &o, out_dev, stream);
       if (rc == CPS_ENOMEM) continue;  // this candidate's workspace does not fit
       if (rc) { last_rc = rc; break; }
@@ -542,6 +614,7 @@ int cps_destroy(cps_handle *h) {
   if (!h) return CPS_EINVAL;
   if (h->ws) (void)hipFree(h->ws);
   if (h->bws) (void)hipFree(h->bws);
+  if (h->tws) (void)hipFree(h->tws);
   if (h->lws) (void)hipFree(h->lws);
   if (h->mws) (void)hipFree(h->mws);
   if (h->ows) (void)hipFree(h->ows);

@@ -50,7 +50,13 @@ template <typename T, int BLOCK> struct BShared {
   int64_t cur[2];
   uint64_t wsum[BLOCK / kWave];  // wavefront totals of a workgroup scan
   int64_t job;
-  uint64_t order[kBatchSortMax];  // (size << 12 | index), sorted by size, largest first
+  int64_t items;                  // work items of the launch
+  int64_t jslot, jindex;          // the current item's largest-first slot and array index
+  int32_t jpart, jparts;          // its part, and the parts of that array
+  int32_t flag;                   // workgroup-wide flags (sampled bracket, last arrival)
+  uint64_t kext[2];               // sampled keys' minimum and maximum
+  uint64_t order[kBatchSortMax];  // (size << 12 | index) sorted by size, largest first; then
+                                  // item_entry(first work item, index) per slot
   uint32_t rh[kHistMaxBins];      // key histogram of a histogram pass
 };
 
@@ -336,6 +342,227 @@ __device__ void block_pass0(const Span<T> &sp, P0Acc<T> &acc) {
   }
 }
 
+// ------------------------------------------------------------------ sampled bracket
+
+// The sampled bracket of one array (used by arrays of at least kBatchPropMin elements):
+// kPropSample elements (runs of kPropRun neighbours at evenly spaced places, so the sample
+// touches few lines) counted in 2^12 key bins over the sample's own range; the bracket runs
+// from just below the bin that holds sample rank floor(q - d) to just above the bin that holds
+// rank ceil(q + d), where q = S (k - 1/2) / n is the rank's place among the S sampled
+// elements and d = 4 sqrt(S p (1 - p)) + 2, p = (k - 1/2) / n (four binomial standard
+// deviations).  An end whose rank falls outside the sample is open (-inf or +inf).  Pass 0's
+// counts decide whether each end holds, so the result never depends on the sample.  Every
+// workgroup of an array computes the same bracket.  False (no bracket) when the sample holds
+// NaN or an infinity, only one value, or both ends would be open.
+template <typename T> __device__ constexpr int32_t c_dtype() { return sizeof(T) == 4 ? 0 : 1; }
+
+constexpr int kPropSample = 4096;
+constexpr int kPropRun = 16;
+constexpr int64_t kBatchPropMin = (int64_t)1 << 15;
+
+template <typename T, int BLOCK>
+__device__ __noinline__ bool sample_bracket(const T *x, int64_t n, int64_t k, BShared<T, BLOCK> &sh, T &pa,
+                               T &pb) {
+  using Key = typename Traits<T>::Key;
+  const int tid = threadIdx.x;
+  constexpr int PER = kPropSample / BLOCK;
+  // (n >= kBatchPropMin: the runs lie inside x and do not overlap)
+  const int64_t stride = n / (kPropSample / kPropRun);
+  if (tid == 0) {
+    sh.kext[0] = ~0ull;
+    sh.kext[1] = 0ull;
+    sh.flag = 0;
+    sh.misc[4] = sh.misc[5] = 0;
+  }
+  __syncthreads();
+  Key kv[PER];
+  Key kmn = (Key)~(Key)0, kmx = 0;
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int i = tid + j * BLOCK;
+    const T v = x[(int64_t)(i / kPropRun) * stride + i % kPropRun];
+    bad = bad || !(v == v) || v == t_inf<T>() || v == -t_inf<T>();
+    kv[j] = Traits<T>::key(v);
+    kmn = kv[j] < kmn ? kv[j] : kmn;
+    kmx = kv[j] > kmx ? kv[j] : kmx;
+  }
+  atomicMin(reinterpret_cast<unsigned long long *>(&sh.kext[0]), (unsigned long long)kmn);
+  atomicMax(reinterpret_cast<unsigned long long *>(&sh.kext[1]), (unsigned long long)kmx);
+  if (bad) atomicOr(&sh.flag, 1);
+  __syncthreads();
+  const uint64_t klo = sh.kext[0], khi = sh.kext[1];
+  if (sh.flag != 0 || klo >= khi) return false;  // (uniform)
+  int shift = 0;
+  while (((khi - klo) >> shift) >= (uint64_t)kHistMaxBins) ++shift;
+  const int nbins = (int)((khi - klo) >> shift) + 1;
+  for (int b = tid; b < nbins; b += BLOCK) sh.rh[b] = 0u;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < PER; ++j) atomicAdd(&sh.rh[(uint32_t)(((uint64_t)kv[j] - klo) >> shift)], 1u);
+  __syncthreads();
+  const double S = (double)kPropSample;
+  const double p = ((double)k - 0.5) / (double)n;
+  const double q = S * p, d = 4.0 * __builtin_sqrt(S * p * (1.0 - p)) + 2.0;
+  const double r0 = __builtin_floor(q - d), r1 = __builtin_ceil(q + d);
+  const bool open0 = r0 < 1.0, open1 = r1 > S;
+  if (open0 && open1) return false;
+  const uint64_t rank0 = open0 ? 1 : (uint64_t)r0, rank1 = open1 ? (uint64_t)S : (uint64_t)r1;
+  // the bins holding the two sample ranks: an exclusive scan of the bins in a fixed order
+  constexpr int BPT = kHistMaxBins / BLOCK;
+  uint64_t hv[BPT];
+  uint64_t tot = 0;
+#pragma unroll
+  for (int j = 0; j < BPT; ++j) {
+    const int b = tid * BPT + j;
+    hv[j] = b < nbins ? sh.rh[b] : 0u;
+    tot += hv[j];
+  }
+  uint64_t cum = block_exclusive_scan<BLOCK>(tot, sh.wsum);
+#pragma unroll
+  for (int j = 0; j < BPT; ++j) {
+    if (cum < rank0 && rank0 <= cum + hv[j]) sh.misc[4] = tid * BPT + j;
+    if (cum < rank1 && rank1 <= cum + hv[j]) sh.misc[5] = tid * BPT + j;
+    cum += hv[j];
+  }
+  __syncthreads();
+  const uint64_t b0 = (uint64_t)sh.misc[4], b1 = (uint64_t)sh.misc[5];
+  __syncthreads();
+  // the largest value below the lower bin, the smallest above the upper one (keys of
+  // finite values, so both neighbours are keys of values: +-inf at worst)
+  const uint64_t first0 = klo + (b0 << shift);
+  uint64_t last1 = klo + ((b1 + 1) << shift) - 1;
+  if (last1 > khi || last1 < klo) last1 = khi;
+  pa = open0 ? -t_inf<T>() : Traits<T>::unkey((Key)(first0 - 1));
+  pb = open1 ? t_inf<T>() : Traits<T>::unkey((Key)(last1 + 1));
+  // the interior (a, b) holds at least one value of T (its key bins are not empty)
+  return pa < pb && next_up((double)pa, c_dtype<T>()) <= next_down((double)pb, c_dtype<T>());
+}
+
+// Pass 0 of an array with a sampled bracket (a, b), over one part of it: the extremes and
+// their multiplicities, #(x <= a) and #(a < x < b) (on the ordered keys, which order the
+// values as the compares do), the interior's keys in the bins `ib` (LDS), and every 16-byte
+// vector of x that holds an interior element copied whole to `out` (one coalesced store per
+// vector slot, at places reserved with one atomic per wavefront and tile on `cursor`: the
+// workgroup's LDS cursor, or the team's device cursor when TEAM, counted in vectors), at most
+// `cap` elements; `ovf` is set when some did not fit.  The copy is a superset of the
+// interior: its other elements lie at or below a or at or above b, outside the bracket that
+// pass 0 leaves, and the later passes skip them.  The sum of x is not formed: it only places
+// cutting-plane trial points, and a bracket that holds at either end is finished by key
+// histograms (one that holds at neither end falls back to trial points inside the bracket,
+// bisection at worst, with the same exact result).  NaN is counted; NaN or an infinity (an
+// infinite extreme) makes the state machine repeat pass 0 with the classification.
+template <typename T> struct PropBins {
+  typename Traits<T>::Key ka, kb;   // keys of a and b
+  typename Traits<T>::Key klo;      // first key of the interior (a's successor)
+  typename Traits<T>::Key span;     // last key - klo
+  int shift;
+};
+
+// Reserve `tot` vectors on the cursor for the wavefront (lane 0's atomic, broadcast).
+template <bool TEAM>
+__device__ inline int64_t prop_reserve(uint32_t tot, unsigned long long *cursor) {
+  unsigned long long base = 0;
+  if (threadIdx.x % kWave == 0) {
+    if (TEAM)
+      base = __hip_atomic_fetch_add(cursor, (unsigned long long)tot, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+    else
+      base = atomicAdd(cursor, (unsigned long long)tot);
+  }
+  return (int64_t)__shfl(base, 0);
+}
+
+template <typename T, int BLOCK, int U, bool TEAM>
+__device__ void block_pass0_prop(const Span<T> &sp, T pa, const PropBins<T> &ib, uint32_t *rh,
+                                 P0Acc<T> &acc, CPS_GLOBAL T *out, int64_t cap,
+                                 unsigned long long *cursor, uint32_t &ovf) {
+  constexpr int V = Traits<T>::kVec;
+  using Vec = typename Traits<T>::Vec;
+  using Key = typename Traits<T>::Key;
+  const int tid = threadIdx.x;
+  CPS_GLOBAL Vec *outv = (CPS_GLOBAL Vec *)out;
+  const int64_t capv = cap / V;
+  auto one = [&](T v, bool valid) -> bool {
+    acc.nnan += (valid & (v != v)) ? 1u : 0u;
+    const Key K = Traits<T>::key(v);
+    acc.cle_a += (valid & (K <= ib.ka)) ? 1u : 0u;
+    const Key d = K - ib.klo;
+    const bool in = valid & (d <= ib.span);
+    acc.clt_b += in ? 1u : 0u;  // (here: the interior's count)
+    if (in) atomicAdd(&rh[(uint32_t)(d >> ib.shift)], 1u);
+    return in;
+  };
+  for (int64_t base = 0; base < sp.nvec; base += (int64_t)BLOCK * U) {
+    Vec raw[U];
+    bool valid[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t vi = base + (int64_t)u * BLOCK + tid;
+      valid[u] = vi < sp.nvec;
+      if (valid[u]) raw[u] = __builtin_nontemporal_load(&sp.V[vi]);
+    }
+    bool hit[U];
+    uint64_t mv[U];
+    uint32_t tot = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      T w[V];
+      vec_to_arr<T>(raw[u], w);
+      bool near = false;
+#pragma unroll
+      for (int j = 0; j < V; ++j) near |= valid[u] & ((w[j] <= acc.mn) | (w[j] >= acc.mx));
+      if (ballot(near) != 0) {
+#pragma unroll
+        for (int j = 0; j < V; ++j) p0_extremes<T>(w[j], valid[u], acc);
+      }
+      hit[u] = false;
+#pragma unroll
+      for (int j = 0; j < V; ++j) hit[u] |= one(w[j], valid[u]);
+      mv[u] = ballot(hit[u]);
+      tot += popc(mv[u]);
+    }
+    if (tot != 0) {  // (wave-uniform)
+      int64_t off = prop_reserve<TEAM>(tot, cursor);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t at = off + lane_rank(mv[u]);
+        if (hit[u]) {
+          if (at < capv) outv[at] = raw[u];
+          else ovf = 1u;
+        }
+        off += popc(mv[u]);
+      }
+    }
+  }
+  if (sp.nedge > 0) {
+    // the unaligned head and tail, one element per lane of the first wavefront; an interior
+    // one is copied as a vector padded with a (which lies outside the bracket)
+    const bool have = tid < sp.nedge;
+    const T v = have ? sp.W[edge_index(sp, tid)] : T(0);
+    p0_extremes<T>(v, have, acc);
+    const bool in = one(v, have);
+    if (tid < kWave) {
+      const uint64_t m = ballot(in);
+      if (m != 0) {
+        const int64_t off = prop_reserve<TEAM>(popc(m), cursor);
+        if (in) {
+          T w[V];
+          w[0] = v;
+#pragma unroll
+          for (int j = 1; j < V; ++j) w[j] = pa;
+          Vec vv;
+#pragma unroll
+          for (int j = 0; j < V; ++j) vv[j] = w[j];
+          const int64_t at = off + lane_rank(m);
+          if (at < capv) outv[at] = vv;
+          else ovf = 1u;
+        }
+      }
+    }
+  }
+}
+
 template <typename T> __device__ inline void write_batch_result(cps_result *out, const CpState &s) {
   cps_result r;
   const T v = (T)s.value + T(0);
@@ -353,27 +580,191 @@ template <typename T> __device__ inline void write_batch_result(cps_result *out,
   *out = r;
 }
 
-// The whole method on one array, by this workgroup.
+// Pass 0 of one array (or of its part `part` of `parts`) from the sampled bracket (pa, pb),
+// then the state after it.  A split array's parts leave their partials in the team record;
+// the last to arrive folds them in part order (deterministic) and returns true, the others
+// false (they are done with the array).  With one part the workgroup goes on at once.
+template <typename T, int BLOCK, int U>
+__device__ __noinline__ bool prop_pass0(const T *x, int64_t n, int64_t k, T pa, T pb, int part, int parts,
+                           TeamCtl *tc, CPS_GLOBAL T *ibuf, int64_t icap,
+                           const BatchArgs<T> &a, BShared<T, BLOCK> &sh) {
+  using Key = typename Traits<T>::Key;
+  const int tid = threadIdx.x;
+  const int32_t dt = a.cfg.dtype;
+  const HistGeom<uint64_t> g0 =
+      hist_geometry(next_up((double)pa, dt), next_down((double)pb, dt), dt, a.cfg.hist_bits);
+  PropBins<T> ib;
+  ib.ka = Traits<T>::key(pa);
+  ib.kb = Traits<T>::key(pb);
+  ib.klo = (Key)g0.klo;
+  ib.span = (Key)(g0.khi - g0.klo);
+  ib.shift = g0.shift;
+  for (int b = tid; b < g0.nbins; b += BLOCK) sh.rh[b] = 0u;
+  if (tid == 0) sh.cur[0] = 0;
+  __syncthreads();
+  // this part: [lo, lo + len), parts of n / parts elements and the remainder spread first
+  const int64_t q = n / parts, rem = n % parts;
+  const int64_t lo = q * part + (part < rem ? part : rem);
+  const int64_t len = q + (part < rem ? 1 : 0);
+  const Span<T> sp = make_span(x + lo, len);
+  P0Acc<T> acc;
+  acc.sum = 0;
+  acc.mn = t_inf<T>();
+  acc.mx = -t_inf<T>();
+  acc.cmn = acc.cmx = 0;
+  acc.nnan = acc.nneg = acc.npos = acc.cle_a = acc.clt_b = 0;
+  acc.Aa = acc.Ba = acc.Ab = acc.Bb = 0;
+  uint32_t ovf = 0;
+  if (parts > 1)
+    block_pass0_prop<T, BLOCK, U, true>(sp, pa, ib, sh.rh, acc, ibuf, icap, &tc->cursor, ovf);
+  else
+    block_pass0_prop<T, BLOCK, U, false>(sp, pa, ib, sh.rh, acc, ibuf, icap,
+                                         reinterpret_cast<unsigned long long *>(&sh.cur[0]), ovf);
+  double mn = (double)acc.mn, mx = (double)acc.mx;
+  int64_t cmn = acc.cmn, cmx = acc.cmx;
+  block_pair_fold<BLOCK>(mn, cmn, mx, cmx, sh.d, sh.i);
+  double dv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t iv[8] = {(int64_t)acc.cle_a, (int64_t)acc.nnan, (int64_t)ovf, (int64_t)acc.clt_b, 0, 0,
+                   0, 0};
+  int dop[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  block_reduce<BLOCK, 0, 4>(dv, dop, iv, false, sh.d, sh.i);
+  int64_t written = 0;
+  if (parts > 1) {
+    // leave the partial, add the bins, arrive; the last part folds
+    for (int b = tid; b < g0.nbins; b += BLOCK) {
+      const uint32_t c = sh.rh[b];
+      if (c) __hip_atomic_fetch_add(&tc->hist[b], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (tid == 0) {
+      tc->pd[part][0] = mn;
+      tc->pd[part][1] = mx;
+      tc->pi[part][0] = cmn;
+      tc->pi[part][1] = cmx;
+      tc->pi[part][2] = iv[0];
+      tc->pi[part][3] = iv[1];
+      tc->pi[part][4] = iv[3];
+      if (iv[2]) __hip_atomic_fetch_or(&tc->overflow, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // the workgroup barrier completes every wavefront's stores to this XCD's L2; thread 0's
+    // release then writes them back for the other XCDs, and the last part's acquire makes
+    // them visible to its whole workgroup (one L2 write-back and invalidation per part)
+    __syncthreads();
+    if (tid == 0) sh.flag = atomic_add_acq_rel(&tc->arrive, 1u) == (uint32_t)parts - 1 ? 1 : 0;
+    __syncthreads();
+    if (!sh.flag) return false;
+    // the last part: the bins of every part, then the team record back to zero
+    for (int b = tid; b < g0.nbins; b += BLOCK) {
+      sh.rh[b] = __hip_atomic_load(&tc->hist[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      tc->hist[b] = 0u;
+    }
+    if (tid == 0) {
+      double fmn = __builtin_inf(), fmx = -__builtin_inf();
+      int64_t c0 = 0, c1 = 0, le = 0, nan = 0, inner = 0;
+      for (int p = 0; p < parts; ++p) {
+        const double m0 = tc->pd[p][0], m1 = tc->pd[p][1];
+        if (m0 < fmn) { fmn = m0; c0 = tc->pi[p][0]; } else if (m0 == fmn) c0 += tc->pi[p][0];
+        if (m1 > fmx) { fmx = m1; c1 = tc->pi[p][1]; } else if (m1 == fmx) c1 += tc->pi[p][1];
+        le += tc->pi[p][2];
+        nan += tc->pi[p][3];
+        inner += tc->pi[p][4];
+      }
+      mn = fmn; cmn = c0; mx = fmx; cmx = c1;
+      iv[0] = le;
+      iv[1] = nan;
+      iv[3] = inner;
+      iv[2] = __hip_atomic_load(&tc->overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      written = (int64_t)__hip_atomic_load(&tc->cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) *
+                Traits<T>::kVec;
+      __hip_atomic_store(&tc->cursor, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&tc->overflow, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&tc->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  } else if (tid == 0) {
+    written = sh.cur[0] * Traits<T>::kVec;
+  }
+  if (tid == 0) {
+    Pass0Result r = {};
+    r.classified = 0;
+    r.sums = 0;  // only the counts at the ends were formed: an adopted bracket ends by histograms
+    r.sum = iv[1] > 0 ? __builtin_nan("") : 0.0;  // (NaN: repeat with the classification)
+    r.fmin = mn;
+    r.fmax = mx;
+    r.cmin = cmn;
+    r.cmax = cmx;
+    r.c_le_a = iv[0];
+    r.c_lt_b = iv[0] + iv[3];  // the interior's keys lie between those of a and b
+    r.split_overflow = iv[2] != 0 ? 1 : 0;
+    r.split_written = written;  // whole vectors: a superset of the interior
+    CpState &st = sh.st;
+    st = CpState{};
+    st.n = n;
+    st.k = k;
+    st.phase = PH_PASS0;
+    CpConfig c = a.cfg;
+    c.use_bracket = 1;
+    c.bracket_lo = (double)pa;
+    c.bracket_hi = (double)pb;
+    c.p0_split = 1;
+    bdev_after_pass0(st, r, c);
+  }
+  __syncthreads();
+  // both ends proven and the interior's bins are those of the bracket: narrow at once
+  const CpState &s1 = sh.st;
+  if (s1.phase == PH_HIST && s1.bracket_used == 3 && s1.wbuf == 0) {
+    const HistGeom<uint64_t> g = hist_geometry(s1.lo, s1.hi, dt, a.cfg.hist_bits);
+    if (g.klo == g0.klo && g.khi == g0.khi && g.shift == g0.shift) {
+      block_pick<T, BLOCK>(sh.rh, g.nbins, (uint64_t)(s1.k - s1.cL), sh);
+      if (tid == 0) {
+        const int32_t bsel = (int32_t)sh.misc[0];
+        bdev_hist_narrow(sh.st, g, bsel, bsel < 0 ? 0 : sh.misc[1], bsel < 0 ? 0 : sh.misc[2],
+                         a.cfg);
+      }
+      __syncthreads();
+    }
+  }
+  return true;
+}
+
+// The whole method on one array (part `part` of `parts` of it; slot: its largest-first slot,
+// which names its team record), by this workgroup.
 template <typename T, int BLOCK, int U>
 __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out,
-                           const BatchArgs<T> &a, BShared<T, BLOCK> &sh) {
+                           const BatchArgs<T> &a, BShared<T, BLOCK> &sh, int64_t slot, int part,
+                           int parts) {
   const int tid = threadIdx.x;
   constexpr int SU = U / 2 > 0 ? U / 2 : 1;
   const int64_t cap = a.cap;
   CPS_GLOBAL T *zb[2] = {(CPS_GLOBAL T *)(a.zbuf + (int64_t)blockIdx.x * a.ws_stride),
                          (CPS_GLOBAL T *)(a.zbuf + (int64_t)blockIdx.x * a.ws_stride + cap)};
-  CPS_GLOBAL T *gb = (CPS_GLOBAL T *)(a.zbuf + (int64_t)blockIdx.x * a.ws_stride + 2 * cap);
+  CPS_GLOBAL T *gb = (CPS_GLOBAL T *)(a.zbuf + (int64_t)blockIdx.x * a.ws_stride + a.gb_off);
   if (!batch_array_valid((uint64_t)(uintptr_t)x, n, k, (uint32_t)sizeof(T))) {
-    if (tid == 0) {
+    if (tid == 0 && part == 0) {
       cps_result r = {};
       r.status = ST_BADARG;
       *out = r;
     }
     return;
   }
+  bool slow = false, p0_done = false;
+  if (a.proposal && a.cfg.hist_bits > 0 && n >= kBatchPropMin) {
+    T pa, pb;
+    const bool prop = sample_bracket<T, BLOCK>(x, n, k, sh, pa, pb);
+    if (!prop && part > 0) return;  // no bracket: the first part runs the array alone
+    if (prop) {
+      TeamCtl *tc = parts > 1 ? a.teams + slot : nullptr;
+      CPS_GLOBAL T *ibuf = parts > 1 ? (CPS_GLOBAL T *)(a.tbuf + slot * a.team_cap) : zb[0];
+      if (!prop_pass0<T, BLOCK, U>(x, n, k, pa, pb, part, parts, tc, ibuf, parts > 1 ? a.team_cap : cap,
+                                   a, sh))
+        return;
+      zb[0] = ibuf;  // the interior's elements are the working set from here on
+      if (sh.st.phase == PH_PASS0 && sh.st.p0_slow) slow = true;  // NaN or an infinity
+      else p0_done = true;
+    }
+  } else if (part > 0) {
+    return;  // (parts are formed only for arrays that take the sampled bracket)
+  }
   const Span<T> sx = make_span(x, n);
-  bool slow = false;
-  for (;;) {  // pass 0 (repeated once with infinity classification if needed)
+  while (!p0_done) {  // pass 0 (repeated once with infinity classification if needed)
     P0Acc<T> acc;
     acc.sum = 0;
     acc.mn = t_inf<T>();
@@ -566,14 +957,63 @@ void batched_select_kernel(BatchArgs<T> a) {
       }
     }
   }
+  if (sorted) {
+    // the work items: each slot's array in team_blocks parts (the largest arrays, in the
+    // slots that have a team record), one part otherwise; slot j becomes
+    // item_entry(its first item, its array's index)
+    constexpr int PER = kBatchSortMax / BLOCK;
+    const int64_t j0 = (int64_t)tid * PER;
+    int64_t mine = 0;
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int64_t j = j0 + p;
+      if (j < count)
+        mine += j < a.team_records ? team_blocks((int64_t)(sh.order[j] >> 12), a.team_chunk, a.team_max)
+                                   : 1;
+    }
+    int64_t first = (int64_t)block_exclusive_scan<BLOCK>((uint64_t)mine, sh.wsum);
+    if (tid == BLOCK - 1) sh.items = first + mine;
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int64_t j = j0 + p;
+      if (j < count) {
+        const uint64_t key = sh.order[j];
+        sh.order[j] = item_entry(first, lpt_index(key));
+        first += j < a.team_records ? team_blocks((int64_t)(key >> 12), a.team_chunk, a.team_max) : 1;
+      }
+    }
+    __syncthreads();
+  } else if (tid == 0) {
+    sh.items = count;
+  }
   for (;;) {
-    if (tid == 0) sh.job = (int64_t)atomic_add_relaxed(&a.ctl->queue, 1ull);
+    if (tid == 0) {
+      const int64_t q = (int64_t)atomic_add_relaxed(&a.ctl->queue, 1ull);
+      sh.job = q;
+      if (q < sh.items) {
+        if (sorted) {
+          const int64_t j = item_slot(sh.order, count, q);
+          const int64_t f = item_first(sh.order[j]);
+          const int64_t nf = j + 1 < count ? item_first(sh.order[j + 1]) : sh.items;
+          sh.jslot = j;
+          sh.jindex = item_index(sh.order[j]);
+          sh.jpart = (int32_t)(q - f);
+          sh.jparts = (int32_t)(nf - f);
+        } else {
+          sh.jslot = q;
+          sh.jindex = q;
+          sh.jpart = 0;
+          sh.jparts = 1;
+        }
+      }
+    }
     __syncthreads();
-    const int64_t j = sh.job;
+    const int64_t q = sh.job, items = sh.items;
+    const int64_t j = sh.jslot, i = sh.jindex;
+    const int part = sh.jpart, parts = sh.jparts;
     __syncthreads();
-    if (j >= count) break;
-    const int64_t i = sorted ? lpt_index(sh.order[j]) : j;
-    select_one<T, BLOCK, U>(a.ptrs[i], a.sizes[i], a.ks[i], a.out + i, a, sh);
+    if (q >= items) break;
+    select_one<T, BLOCK, U>(a.ptrs[i], a.sizes[i], a.ks[i], a.out + i, a, sh, j, part, parts);
   }
   // the last workgroup out resets the queue for the next launch (graph replays included)
   if (tid == 0) {

@@ -100,6 +100,10 @@ struct Pass0Result {
   // pass 0 that also wrote the elements strictly inside (a, b) to split buffer 0: the
   // number of wavefronts whose share did not fit their region (0 = all written)
   int64_t split_overflow;
+  // 0: the written elements are exactly those strictly inside (a, b); otherwise how many
+  // were written, a superset (whole 16-byte vectors that hold an interior element, and
+  // elements equal to a): every extra lies outside the open bracket that pass 0 leaves
+  int64_t split_written;
 };
 
 // Results of one evaluation pass over the working set W at trial point t.  A counting
@@ -410,16 +414,18 @@ CPS_HD inline void cp_after_pass0(CpState &s, const Pass0Result &r, const CpConf
     const bool left_ok = (s.bracket_used & 1) || a <= r.fmin;
     const bool right_ok = (s.bracket_used & 2) || b >= r.fmax;
     if (c.p0_split && r.split_overflow == 0 && left_ok && right_ok && a < b) {
-      if (s.bracket_used == 3) {
+      if (s.bracket_used == 3 && r.split_written == 0) {
         s.wbuf = 0;
         s.side = 0;
         s.wlen = s.cR - s.cL;
         s.on_bracket = 1;
         s.elements_written += s.wlen;
       } else if (c.hist_bits > 0) {
+        // the written elements hold the bracket's and others outside it, which the
+        // histogram passes skip
         s.wbuf = 0;
         s.side = 0;
-        s.wlen = r.c_lt_b - r.c_le_a;
+        s.wlen = r.split_written > 0 ? r.split_written : r.c_lt_b - r.c_le_a;
         s.narrowed = 1;
         s.elements_written += s.wlen;
       }

@@ -85,6 +85,23 @@ struct BatchCtl {
   uint64_t pad1[15];
 };
 
+// An array split over several workgroups (a team): each takes a contiguous part of pass 0
+// and leaves its partial here; the last to arrive folds them and finishes the array alone.
+// Every field is back at zero when that workgroup is done, so records are reused across
+// launches without clearing (the records live in a buffer of their own, zeroed once).
+constexpr int kTeamMax = 16;        // workgroups per array at most
+constexpr int kTeamRecords = 1024;  // arrays that may be split (the largest ones)
+struct TeamCtl {
+  uint32_t arrive;
+  uint32_t overflow;         // some part's interior did not fit the team buffer
+  uint32_t pad0[30];
+  unsigned long long cursor; // 16-byte vectors written to the team buffer
+  uint64_t pad1[15];
+  double pd[kTeamMax][2];    // per part: min, max
+  int64_t pi[kTeamMax][6];   // per part: #min, #max, #(x <= a), #NaN, #(a < x < b), unused
+  uint32_t hist[kHistMaxBins];  // the interior's key bins, summed over the parts
+};
+
 template <typename T> struct BatchArgs {
   const T *const *ptrs;  // device array of `count` device pointers
   const int64_t *sizes;  // device array
@@ -92,10 +109,20 @@ template <typename T> struct BatchArgs {
   int64_t count;
   cps_result *out;       // device array of `count` results
   BatchCtl *ctl;
-  T *zbuf;               // per workgroup: two split buffers of `cap` and a gather buffer
+  T *zbuf;               // per workgroup: split buffers of `cap` (two, or one when nothing is
+                         // ever split) and a gather buffer
   int64_t cap;
   int64_t ws_stride;     // elements of workspace per workgroup
+  int64_t gb_off;        // the gather buffer's offset in a workgroup's workspace
   CpConfig cfg;
+  int32_t proposal;      // 1: arrays of at least kBatchPropMin elements start from a sampled
+                         // bracket checked by pass 0's counts (hist_bits > 0 required)
+  int32_t team_max;      // workgroups per array at most (1: one per array)
+  int64_t team_chunk;    // elements per workgroup of a split array
+  int64_t team_cap;      // elements of each team buffer
+  int64_t team_records;  // records (and team buffers): largest-first slots below this may split
+  TeamCtl *teams;        // team_records records
+  T *tbuf;               // team_records buffers of team_cap elements
 };
 
 template <typename T>

@@ -1,0 +1,190 @@
+// k nearest neighbours (Section 6, last paragraph): for each query point, the squared
+// Euclidean distances to every data point, their k-th smallest d_k by the batched selection,
+// and the mean ordinate of the k nearest points, formed by a reduction with the weight of
+// Section 6's rho adapted to an indicator: 1 below d_k, a/b at d_k (b points at d_k, a = k -
+// #(d < d_k) of them count), 0 above.
+//
+// The distance kernel forms d_i = sum_j (P_ij - q_j)^2 for a group of queries per thread row
+// (each data point read once per group), left to right in j with every difference, square
+// and sum rounded on its own in float (the library is built without fused multiply-add), and
+// writes them query-major, one array of n per query.  The reduction recomputes the same
+// distances from the points (cheaper than reading the distance arrays again: the points stay
+// in the caches across queries) and sums the ordinates below and at d_k in double precision,
+// per block in a fixed order, then per query in block order.
+#include "cps_device.h"
+#include "cps_kernels.h"
+#include "cps_passes.h"
+
+namespace cps {
+
+constexpr int kKnnGroup = 16;  // queries per thread row of the distance kernel
+constexpr int kKnnBlock = 256;
+constexpr int kKnnRedBlocks = 8;  // reduction blocks per query
+
+template <int D>
+__device__ inline float knn_dist(const float (&row)[D > 0 ? D : 16], const float *q, int dim) {
+  const int dd = D > 0 ? D : dim;
+  float s = 0.0f;
+#pragma unroll
+  for (int j = 0; j < (D > 0 ? D : 16); ++j) {
+    if (j < dd) {
+      const float e = row[j] - q[j];
+      const float sq = e * e;
+      s = j == 0 ? sq : s + sq;
+    }
+  }
+  return s;
+}
+
+template <int D>
+__global__ __launch_bounds__(kKnnBlock) void knn_distance_kernel(
+    const float *__restrict__ P, const float *__restrict__ Q, int64_t n, int32_t dim, int64_t nq,
+    float *__restrict__ Dst) {
+  __shared__ float sq[kKnnGroup * 16];
+  const int64_t c0 = (int64_t)blockIdx.y * kKnnGroup;
+  const int nc = (int)((nq - c0) < kKnnGroup ? (nq - c0) : kKnnGroup);
+  for (int t = threadIdx.x; t < nc * dim; t += kKnnBlock) sq[t] = Q[c0 * dim + t];
+  __syncthreads();
+  const CPS_GLOBAL float *Pg = (const CPS_GLOBAL float *)P;
+  CPS_GLOBAL float *Dg = (CPS_GLOBAL float *)Dst;
+  for (int64_t i = (int64_t)blockIdx.x * kKnnBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kKnnBlock) {
+    float row[D > 0 ? D : 16];
+    const int dd = D > 0 ? D : dim;
+#pragma unroll
+    for (int j = 0; j < (D > 0 ? D : 16); ++j)
+      if (j < dd) row[j] = Pg[i * dd + j];
+    for (int c = 0; c < nc; ++c)
+      __builtin_nontemporal_store(knn_dist<D>(row, sq + c * dd, dim), &Dg[(c0 + c) * n + i]);
+  }
+}
+
+__global__ void knn_descriptor_kernel(const float *Dst, int64_t n, int64_t nq, int64_t k,
+                                      const float **ptrs, int64_t *sizes, int64_t *ks) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nq;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    ptrs[c] = Dst + c * n;
+    sizes[c] = n;
+    ks[c] = k;
+  }
+}
+
+// Partial sums of the ordinates below and at d_k over this block's slice of the points.
+template <int D>
+__global__ __launch_bounds__(kKnnBlock) void knn_partial_kernel(
+    const float *__restrict__ P, const float *__restrict__ f, const float *__restrict__ Q,
+    int64_t n, int32_t dim, const cps_result *__restrict__ sel, double *__restrict__ pd,
+    int64_t *__restrict__ pi) {
+  __shared__ double sd[8][kKnnBlock / kWave];
+  __shared__ int64_t si[8][kKnnBlock / kWave];
+  __shared__ float sq[16];
+  const int64_t c = blockIdx.y;
+  if (threadIdx.x < dim) sq[threadIdx.x] = Q[c * dim + threadIdx.x];
+  __syncthreads();
+  const float dk = (float)sel[c].value;
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = (int64_t)blockIdx.x * per;
+  const int64_t hi = lo + per < n ? lo + per : n;
+  double sb = 0.0, se = 0.0;
+  int64_t nb = 0, ne = 0;
+  const int dd = D > 0 ? D : dim;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kKnnBlock) {
+    float row[D > 0 ? D : 16];
+#pragma unroll
+    for (int j = 0; j < (D > 0 ? D : 16); ++j)
+      if (j < dd) row[j] = P[i * dd + j];
+    const float d = knn_dist<D>(row, sq, dim);
+    const double fi = (double)f[i];
+    if (d < dk) {
+      sb += fi;
+      ++nb;
+    } else if (d == dk) {
+      se += fi;
+      ++ne;
+    }
+  }
+  double dv[8] = {sb, se, 0, 0, 0, 0, 0, 0};
+  int dop[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t iv[8] = {nb, ne, 0, 0, 0, 0, 0, 0};
+  block_reduce<kKnnBlock, 2, 2>(dv, dop, iv, false, sd, si);
+  if (threadIdx.x == 0) {
+    const int64_t slot = c * gridDim.x + blockIdx.x;
+    pd[2 * slot] = dv[0];
+    pd[2 * slot + 1] = dv[1];
+    pi[2 * slot] = iv[0];
+    pi[2 * slot + 1] = iv[1];
+  }
+}
+
+__global__ void knn_final_kernel(int64_t nq, int64_t k, int nb, const cps_result *__restrict__ sel,
+                                 const double *__restrict__ pd, const int64_t *__restrict__ pi,
+                                 cps_knn *__restrict__ out) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nq;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    double sb = 0.0, se = 0.0;
+    int64_t below = 0, eq = 0;
+    for (int b = 0; b < nb; ++b) {
+      sb += pd[2 * (c * nb + b)];
+      se += pd[2 * (c * nb + b) + 1];
+      below += pi[2 * (c * nb + b)];
+      eq += pi[2 * (c * nb + b) + 1];
+    }
+    const cps_result r = sel[c];
+    cps_knn o;
+    o.dk = (float)r.value;
+    o.status = r.status;
+    o.below = below;
+    o.equal = eq;
+    // the reduction's counts are the selection's (anything else: the data changed)
+    if (r.status == 0 && (below != r.less || eq != r.equal)) o.status = CPS_STATUS_INTERNAL;
+    const double a = (double)(k - below);
+    o.mean = (o.status == 0 && eq > 0) ? (sb + a * se / (double)eq) / (double)k
+                                       : __builtin_nan("");
+    out[c] = o;
+  }
+}
+
+size_t knn_workspace(int64_t n, int64_t nq) {
+  const size_t dbytes = ((size_t)nq * (size_t)n * sizeof(float) + 255) / 256 * 256;
+  const size_t desc = 3 * (((size_t)nq * 8 + 255) / 256 * 256);
+  const size_t sel = ((size_t)nq * sizeof(cps_result) + 255) / 256 * 256;
+  const size_t part = 2 * (((size_t)nq * kKnnRedBlocks * 2 * 8 + 255) / 256 * 256);
+  return dbytes + desc + sel + part;
+}
+
+hipError_t launch_knn_distances(const float *P, const float *Q, int64_t n, int32_t dim, int64_t nq,
+                                int64_t k, float *Dst, const float **ptrs, int64_t *sizes,
+                                int64_t *ks, int cu_count, hipStream_t stream) {
+  const int64_t groups = (nq + kKnnGroup - 1) / kKnnGroup;
+  int64_t bx = (n + kKnnBlock - 1) / kKnnBlock;
+  const int64_t want = (int64_t)cu_count * 8 / (groups < 1 ? 1 : groups) + 1;
+  if (bx > want) bx = want;
+  if (bx < 1) bx = 1;
+  const dim3 grid((unsigned)bx, (unsigned)groups);
+  if (dim == 8)
+    knn_distance_kernel<8><<<grid, dim3(kKnnBlock), 0, stream>>>(P, Q, n, dim, nq, Dst);
+  else
+    knn_distance_kernel<0><<<grid, dim3(kKnnBlock), 0, stream>>>(P, Q, n, dim, nq, Dst);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  knn_descriptor_kernel<<<dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, stream>>>(
+      Dst, n, nq, k, ptrs, sizes, ks);
+  return hipGetLastError();
+}
+
+hipError_t launch_knn_reduce(const float *P, const float *f, const float *Q, int64_t n,
+                             int32_t dim, int64_t nq, int64_t k, const cps_result *sel,
+                             double *pd, int64_t *pi, cps_knn *out, hipStream_t stream) {
+  const dim3 grid((unsigned)kKnnRedBlocks, (unsigned)nq);
+  if (dim == 8)
+    knn_partial_kernel<8><<<grid, dim3(kKnnBlock), 0, stream>>>(P, f, Q, n, dim, sel, pd, pi);
+  else
+    knn_partial_kernel<0><<<grid, dim3(kKnnBlock), 0, stream>>>(P, f, Q, n, dim, sel, pd, pi);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  knn_final_kernel<<<dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, stream>>>(
+      nq, k, kKnnRedBlocks, sel, pd, pi, out);
+  return hipGetLastError();
+}
+
+}  // namespace cps

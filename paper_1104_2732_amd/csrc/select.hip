@@ -1265,6 +1265,7 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
       r.nnan = ri[0]; r.nneg = ri[1]; r.npos = ri[2]; r.c_le_a = ri[3]; r.c_lt_b = ri[4];
       r.fmin = mn; r.fmax = mx; r.cmin = cmn; r.cmax = cmx;
       r.split_overflow = ri[5];
+      r.split_written = 0;  // (exactly the interior)
       // the pass that counted the interior formed only the two counts at the ends
       r.sums = (!p0_slow && a.phist && a.bracket && a.bracket[2] != 0.0 && a.p0_cap > 0 &&
                 interior_geometry(a, (T)a.bracket[0], (T)a.bracket[1]).nbins > 0) ? 0 : 1;
