@@ -17,6 +17,13 @@ What each function computes, with the passage it follows:
 - ``lms_residuals`` / ``lms_median_sq``: squared regression residuals summed
   in fixed order without fused multiply-add, and their lower median for each
   candidate parameter vector (Section 6, least median of squares).
+- ``trimmed_sum`` / ``lts_objective``: the sum of the h smallest values (sorted
+  copy, compensated sum of its first h entries), with the h-th smallest m,
+  #(r < m), a = h - #(r < m) and #(r = m) (Section 6, least trimmed squares).
+- ``knn_distances`` / ``knn_mean``: squared Euclidean distances in float, left
+  to right over the coordinates without fused multiply-add; the k-th smallest
+  distance and the mean ordinate of the k nearest points with the weight a / b
+  on ties at the k-th distance (Section 6, k nearest neighbours).
 """
 from __future__ import annotations
 
@@ -74,6 +81,13 @@ def lib() -> ctypes.CDLL:
         L.orc_lms_residuals.restype = ctypes.c_int
         L.orc_lms_median_sq.argtypes = [vp, vp, vp, i64, i32, i64, ctypes.POINTER(_Result)]
         L.orc_lms_median_sq.restype = ctypes.c_int
+        L.orc_trimmed_sum_f64.argtypes = [vp, i64, i64, vp]
+        L.orc_lts_objective.argtypes = [vp, vp, vp, i64, i32, i64, i64, vp]
+        L.orc_knn_distances.argtypes = [vp, vp, i64, i32, vp]
+        L.orc_knn_mean.argtypes = [vp, vp, vp, i64, i32, i64, i64, vp]
+        for name in ("orc_trimmed_sum_f64", "orc_lts_objective", "orc_knn_distances",
+                     "orc_knn_mean"):
+            getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -152,3 +166,57 @@ def lms_median_sq(X, y, betas) -> list[dict]:
     _check(lib().orc_lms_median_sq(X.ctypes.data, y.ctypes.data, betas.ctypes.data, n, p, m, out),
            "lms_median_sq")
     return [_res_dict(out[i]) for i in range(m)]
+
+
+TRIM_DTYPE = np.dtype([("F", "f8"), ("m", "f8"), ("below", "i8"), ("a", "i8"), ("b", "i8")])
+KNN_DTYPE = np.dtype([("mean", "f8"), ("dk", "f4"), ("pad", "i4"), ("below", "i8"),
+                      ("equal", "i8")])
+
+
+def trimmed_sum(r, h: int) -> dict:
+    """The sum of the h smallest values of r (float64) and its h-th smallest value m, with
+    #(r < m), a = h - #(r < m) and #(r = m)."""
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    out = np.zeros(1, dtype=TRIM_DTYPE)
+    _check(lib().orc_trimmed_sum_f64(r.ctypes.data, r.size, int(h), out.ctypes.data),
+           "trimmed_sum")
+    return {k: out[0][k].item() for k in TRIM_DTYPE.names}
+
+
+def lts_objective(X, y, betas, h: int | None = None) -> np.ndarray:
+    """Least trimmed squares per candidate: the sum of the h smallest squared residuals
+    (h = floor((n+1)/2) by default, the rank of the median); TRIM_DTYPE records."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    betas = np.ascontiguousarray(betas, dtype=np.float64)
+    n, p = X.shape
+    m = betas.shape[0]
+    h = (n + 1) // 2 if h is None else int(h)
+    out = np.zeros(max(m, 1), dtype=TRIM_DTYPE)
+    _check(lib().orc_lts_objective(X.ctypes.data, y.ctypes.data, betas.ctypes.data, n, p, m, h,
+                                   out.ctypes.data), "lts_objective")
+    return out[:m]
+
+
+def knn_distances(P, q) -> np.ndarray:
+    P = np.ascontiguousarray(P, dtype=np.float32)
+    q = np.ascontiguousarray(q, dtype=np.float32)
+    n, dim = P.shape
+    d = np.empty(n, dtype=np.float32)
+    _check(lib().orc_knn_distances(P.ctypes.data, q.ctypes.data, n, dim, d.ctypes.data),
+           "knn_distances")
+    return d
+
+
+def knn_mean(P, f, Q, k: int) -> np.ndarray:
+    """Per query (rows of Q): the k-th smallest squared distance to the rows of P and the mean
+    ordinate f of the k nearest points (ties at the k-th distance weighted a / b); KNN_DTYPE."""
+    P = np.ascontiguousarray(P, dtype=np.float32)
+    f = np.ascontiguousarray(f, dtype=np.float32)
+    Q = np.ascontiguousarray(Q, dtype=np.float32)
+    n, dim = P.shape
+    nq = Q.shape[0]
+    out = np.zeros(max(nq, 1), dtype=KNN_DTYPE)
+    _check(lib().orc_knn_mean(P.ctypes.data, f.ctypes.data, Q.ctypes.data, n, dim, nq, int(k),
+                              out.ctypes.data), "knn_mean")
+    return out[:nq]

@@ -21,6 +21,14 @@
  *   - least median of squares (Section 6): r_i = (y_i - sum_j X_ij b_j)^2 with the sum
  *     taken left to right in j, each product and sum rounded (no fused multiply-add:
  *     build with -ffp-contract=off), then the lower median of r.
+ *   - least trimmed squares (Section 6): the sum of the h smallest squared residuals, by
+ *     its definition (a sorted copy, the first h entries summed with Neumaier's
+ *     compensated summation), with the h-th smallest m and the counts #(r < m), #(r = m).
+ *   - k nearest neighbours (Section 6, last paragraph): squared Euclidean distances from a
+ *     query to every data point, summed left to right over the coordinates without fused
+ *     multiply-add, and the mean of the ordinates of the k nearest points, by definition:
+ *     the points sorted by distance (ties in index order) and the first k ordinates summed
+ *     (Neumaier) and divided by k.
  *
  * NaN is not an ordered value: any NaN in x makes the calls return ORC_ENAN.
  * The returned value is canonicalised as m + 0.0, so -0.0 is reported as +0.0.
@@ -239,4 +247,138 @@ int orc_lms_median_sq(const double *X, const double *y, const double *betas, int
   }
   free(r);
   return rc;
+}
+
+/* ---------------------------------------------------------------- least trimmed squares */
+
+typedef struct {
+  double F;        /* sum of the h smallest values */
+  double m;        /* the h-th smallest value */
+  int64_t below;   /* #(r < m) */
+  int64_t a;       /* h - #(r < m): how many copies of m the sum takes */
+  int64_t b;       /* #(r = m) */
+} orc_trim;
+
+/* The sum of the h smallest of r[0..n) (1 <= h <= n): sort a copy and add its first h
+ * entries in ascending order with compensation. */
+int orc_trimmed_sum_f64(const double *r, int64_t n, int64_t h, orc_trim *out) {
+  if (!r || !out || n < 1 || h < 1 || h > n) return ORC_EINVAL;
+  for (int64_t i = 0; i < n; i++)
+    if (isnan(r[i])) return ORC_ENAN;
+  double *w = (double *)malloc((size_t)n * sizeof(double));
+  if (!w) return ORC_ENOMEM;
+  memcpy(w, r, (size_t)n * sizeof(double));
+  qsort(w, (size_t)n, sizeof(double), cmp_double);
+  double s = 0, c = 0;
+  for (int64_t i = 0; i < h; i++) neumaier_add(&s, &c, w[i]);
+  const double m = w[h - 1] + 0.0;
+  int64_t below = 0, eq = 0;
+  for (int64_t i = 0; i < n; i++) {
+    below += r[i] < m;
+    eq += r[i] == m;
+  }
+  out->F = s + c;
+  out->m = m;
+  out->below = below;
+  out->a = h - below;
+  out->b = eq;
+  free(w);
+  return ORC_OK;
+}
+
+/* For each of the m candidates: the least-trimmed-squares objective of its squared
+ * residuals (as orc_lms_residuals) with h kept. */
+int orc_lts_objective(const double *X, const double *y, const double *betas, int64_t n, int32_t p,
+                      int64_t m, int64_t h, orc_trim *out) {
+  if (!X || !y || !betas || !out || n < 1 || p < 1 || m < 0 || h < 1 || h > n) return ORC_EINVAL;
+  double *r = (double *)malloc((size_t)n * sizeof(double));
+  if (!r) return ORC_ENOMEM;
+  int rc = ORC_OK;
+  for (int64_t c = 0; c < m && rc == ORC_OK; c++) {
+    rc = orc_lms_residuals(X, y, betas + c * (int64_t)p, n, p, r);
+    if (rc == ORC_OK) rc = orc_trimmed_sum_f64(r, n, h, &out[c]);
+  }
+  free(r);
+  return rc;
+}
+
+/* ---------------------------------------------------------------- k nearest neighbours */
+
+/* d_i = sum_j (P_ij - q_j)^2 over j = 0..dim-1 left to right, every difference, square and
+ * sum rounded to float (float arithmetic, no fused multiply-add). */
+int orc_knn_distances(const float *P, const float *q, int64_t n, int32_t dim, float *d) {
+  if (!P || !q || !d || n < 1 || dim < 1) return ORC_EINVAL;
+  for (int64_t i = 0; i < n; i++) {
+    const float *row = P + i * (int64_t)dim;
+    float s = 0.0f;
+    for (int32_t j = 0; j < dim; j++) {
+      const float e = row[j] - q[j];
+      const float sq = e * e;
+      s = j == 0 ? sq : s + sq;
+    }
+    d[i] = s;
+  }
+  return ORC_OK;
+}
+
+static int cmp_float(const void *a, const void *b) {
+  const float x = *(const float *)a, y = *(const float *)b;
+  return (x > y) - (x < y);
+}
+
+typedef struct {
+  double mean;     /* mean ordinate of the k nearest points */
+  float dk;        /* the k-th smallest distance */
+  int32_t pad;
+  int64_t below;   /* #(d < dk) */
+  int64_t equal;   /* #(d = dk) */
+} orc_knn;
+
+/* For each of the nq queries (rows of Q): the k-th smallest squared Euclidean distance dk
+ * to the n points (rows of P), found by sorting, and the mean ordinate of the k nearest
+ * points: (sum of f over d < dk + (a / b) * sum of f over d = dk) / k with b = #(d = dk) and
+ * a = k - #(d < dk), the weight of Section 6 for the points at the k-th distance (exactly k
+ * points' worth; with no tie it is the plain mean of the k nearest). */
+int orc_knn_mean(const float *P, const float *f, const float *Q, int64_t n, int32_t dim, int64_t nq,
+                 int64_t k, orc_knn *out) {
+  if (!P || !f || !Q || !out || n < 1 || dim < 1 || nq < 0 || k < 1 || k > n) return ORC_EINVAL;
+  float *d = (float *)malloc((size_t)n * sizeof(float));
+  float *w = (float *)malloc((size_t)n * sizeof(float));
+  if (!d || !w) {
+    free(d);
+    free(w);
+    return ORC_ENOMEM;
+  }
+  for (int64_t c = 0; c < nq; c++) {
+    orc_knn_distances(P, Q + c * (int64_t)dim, n, dim, d);
+    for (int64_t i = 0; i < n; i++)
+      if (isnan(d[i])) {
+        free(d);
+        free(w);
+        return ORC_ENAN;
+      }
+    memcpy(w, d, (size_t)n * sizeof(float));
+    qsort(w, (size_t)n, sizeof(float), cmp_float);
+    const float dk = w[k - 1] + 0.0f;
+    int64_t below = 0, eq = 0;
+    double sb = 0, cb = 0, se = 0, ce = 0;
+    for (int64_t i = 0; i < n; i++) {
+      if (d[i] < dk) {
+        below++;
+        neumaier_add(&sb, &cb, (double)f[i]);
+      } else if (d[i] == dk) {
+        eq++;
+        neumaier_add(&se, &ce, (double)f[i]);
+      }
+    }
+    const double a = (double)(k - below);
+    out[c].mean = ((sb + cb) + a * (se + ce) / (double)eq) / (double)k;
+    out[c].dk = dk;
+    out[c].pad = 0;
+    out[c].below = below;
+    out[c].equal = eq;
+  }
+  free(d);
+  free(w);
+  return ORC_OK;
 }
