@@ -391,6 +391,65 @@ int lms_median_sq_residuals(cps_handle *h, const double *X_dev, const double *y_
                             const double *betas_dev, int64_t n, int32_t p, int64_t m,
                             cps_result *out_dev, void *stream);
 
+/* The k-th smallest element of each array (as select_kth_batched_ex) and the sum of each
+ * array's k smallest elements, ksum_dev[i] = sum_{x < v} x + (k - #(x < v)) v with v = x_(k)
+ * (Section 6: the least-trimmed-squares objective is this sum over squared residuals, and
+ * the weight rho there is 1 below v, a/b at v with a = k - #(x < v) and b = #(x = v)).
+ * Formed in double precision; with the sampled bracket the elements below the bracket's
+ * lower end are summed by pass 0 and those inside from its copy (in the copy's order, which
+ * varies from run to run, so the last bits may differ between runs), else by one more pass
+ * over the array.  ksum_dev: device array of `count` doubles (NaN for an array whose status
+ * is not OK).  Other arguments and errors as select_kth_batched_ex. */
+int select_kth_batched_ksum(cps_handle *h, const void *const *ptrs_dev, const int64_t *sizes_dev,
+                            const int64_t *ks_dev, int64_t count, int dtype,
+                            const cps_batch_options *opt, cps_result *out_dev, double *ksum_dev,
+                            void *stream);
+
+/* Least trimmed squares (Section 6), 48 bytes, device memory: for one candidate, the sum F of
+ * the h smallest squared residuals, their h-th smallest m, below = #(r < m), a = h - below,
+ * b = #(r = m), and the selection's status. */
+typedef struct cps_trim {
+  double F;
+  double m;
+  int64_t below, a, b;
+  int32_t status;
+  int32_t pad;
+} cps_trim;
+
+/* For each of m candidate parameter vectors (rows of betas_dev, m x p), the least-trimmed-
+ * squares objective: the sum of the h smallest of r_i = (y_i - sum_j X_ij b_j)^2, found
+ * through the h-th order statistic as Section 6 writes it, F = sum_{r < m} r + a m.  The
+ * residuals are formed as in lms_median_sq_residuals (bit-identical), h is 1-based
+ * (Section 6 takes h = floor((n+1)/2), the rank of the median; Rousseeuw's h = floor((n+p)/2)
+ * works the same).  out_dev receives m cps_trim records.  Errors: as
+ * lms_median_sq_residuals, and CPS_EINVAL for h outside [1, n]. */
+int lts_trimmed_sq(cps_handle *h, const double *X_dev, const double *y_dev,
+                   const double *betas_dev, int64_t n, int32_t p, int64_t m, int64_t hk,
+                   cps_trim *out_dev, void *stream);
+
+/* k nearest neighbours (Section 6, last paragraph), 32 bytes, device memory: for one query,
+ * the mean ordinate of its k nearest points, the k-th smallest squared distance dk, the
+ * counts #(d < dk) and #(d = dk), and the selection's status. */
+typedef struct cps_knn {
+  double mean;
+  float dk;
+  int32_t status;
+  int64_t below, equal;
+} cps_knn;
+
+/* For each of nq queries (rows of Q_dev, nq x dim floats, row-major), the squared Euclidean
+ * distances d_i = sum_j (P_ij - q_j)^2 to the n points (rows of P_dev, n x dim), each
+ * difference, square and sum rounded to float in order j = 0..dim-1 (no fused multiply-add);
+ * their k-th smallest dk by the batched selection; and the mean ordinate of the k nearest
+ * points, (sum_{d < dk} f_i + (a / b) sum_{d = dk} f_i) / k with b = #(d = dk),
+ * a = k - #(d < dk) (Section 6's rho as an indicator: exactly k points' worth), summed in
+ * double precision in a fixed order.  f_dev: n floats.  The distances are materialised in the
+ * handle's workspace (nq x n floats) for the selection; the reduction recomputes them.
+ * Errors: CPS_EINVAL for null pointers, n < 1, dim outside [1, 16], nq outside [1, 65535],
+ * k outside [1, n]. */
+int knn_mean(cps_handle *h, const float *P_dev, const float *f_dev, const float *Q_dev, int64_t n,
+             int32_t dim, int64_t nq, int64_t k, cps_knn *out_dev, void *stream);
+
 /* ------------------------------------------------------------------ learned bracket proposal
  *
  * An extension of the method (not in the paper): a small network reads a sketch of the

@@ -58,6 +58,10 @@ STATS_DTYPE = np.dtype([("passes", "<i4"), ("work_passes", "<i4"), ("kelley_step
                         ("pred", "<f8", (STATS_MAX_PASSES,)),
                         ("succ", "<f8", (STATS_MAX_PASSES,))])
 PASS_ZERO, PASS_EVAL, PASS_COUNT, PASS_HIST, PASS_GATHER, PASS_FINAL = range(6)
+TRIM_DTYPE = np.dtype([("F", "<f8"), ("m", "<f8"), ("below", "<i8"), ("a", "<i8"), ("b", "<i8"),
+                       ("status", "<i4"), ("pad", "<i4")])
+KNN_DTYPE = np.dtype([("mean", "<f8"), ("dk", "<f4"), ("status", "<i4"), ("below", "<i8"),
+                      ("equal", "<i8")])
 assert RESULT_DTYPE.itemsize == 48 and EVAL_DTYPE.itemsize == 80
 
 
@@ -118,7 +122,7 @@ EXPORTS = ("cps_create", "cps_destroy", "cps_status_string", "cps_last_hip_error
            "cps_mixture_generate", "cps_features", "cps_mlp_forward", "cps_mlp_loss_grad",
            "cps_mlp_adam", "cps_mlp_init", "cps_learned_bracket", "select_kth_learned",
            "cps_mlp_train", "select_kth_sampled", "cps_model_save", "cps_model_load",
-           "select_kth_noalloc")
+           "select_kth_noalloc", "select_kth_batched_ksum", "lts_trimmed_sq", "knn_mean")
 STATUS_BADARG = 4
 
 
@@ -149,6 +153,13 @@ def lib() -> ctypes.CDLL:
     L.select_kth_ex.restype = c_int
     L.select_kth_noalloc.argtypes = [vp, vp, i64, i64, c_int, vp, vp]
     L.select_kth_noalloc.restype = c_int
+    L.select_kth_batched_ksum.argtypes = [vp, vp, vp, vp, i64, c_int, ctypes.POINTER(BatchOptions),
+                                          vp, vp, vp]
+    L.select_kth_batched_ksum.restype = c_int
+    L.lts_trimmed_sq.argtypes = [vp, vp, vp, vp, i64, i32, i64, i64, vp, vp]
+    L.lts_trimmed_sq.restype = c_int
+    L.knn_mean.argtypes = [vp, vp, vp, vp, i64, i32, i64, i64, vp, vp]
+    L.knn_mean.restype = c_int
     L.cps_objective.argtypes = [vp, vp, i64, i64, c_int, vp, i64, vp, vp]
     L.cps_objective.restype = c_int
     L.cps_default_batch_options.argtypes = [ctypes.POINTER(BatchOptions)]
@@ -349,6 +360,28 @@ class Selector:
         _check(rc, "cps_autotune_batched")
         return best, ms.value
 
+    def select_kth_batched_ksum_async(self, ptrs, sizes, ks, count: int, dtype_code: int, out,
+                                      ksum, options: BatchOptions | None = None) -> None:
+        """Enqueue select_kth_batched_ksum: results in `out`, sums of the k smallest in `ksum`."""
+        rc = lib().select_kth_batched_ksum(self._h, ctypes.c_void_p(ptrs.data_ptr()),
+                                           ctypes.c_void_p(sizes.data_ptr()),
+                                           ctypes.c_void_p(ks.data_ptr()), int(count),
+                                           int(dtype_code),
+                                           ctypes.byref(options) if options is not None else None,
+                                           ctypes.c_void_p(out.data_ptr()), self._ptr(ksum),
+                                           ctypes.c_void_p(_stream_ptr(self.device)))
+        _check(rc, "select_kth_batched_ksum")
+
+    def select_kth_batched_ksum(self, arrays, ks, options: BatchOptions | None = None):
+        """(RESULT_DTYPE records, float64 sums of each array's k smallest) for CUDA tensors."""
+        import torch
+        ptrs, sizes, kk, code = self.batch_descriptors(arrays, ks)
+        out = self.new_results(len(arrays))
+        ksum = torch.empty(len(arrays), dtype=torch.float64, device=self.device)
+        self.select_kth_batched_ksum_async(ptrs, sizes, kk, len(arrays), code, out, ksum, options)
+        torch.cuda.synchronize(self.device)
+        return _as_records(out, RESULT_DTYPE).copy(), ksum.cpu().numpy()
+
     def select_kth_batched(self, arrays, ks, options: BatchOptions | None = None) -> np.ndarray:
         """Synchronous batched selection over a list of CUDA tensors; returns RESULT_DTYPE records."""
         import torch
@@ -383,6 +416,52 @@ class Selector:
         self.lms_median_sq_residuals_async(X, y, betas, out)
         torch.cuda.synchronize(self.device)
         return _as_records(out, RESULT_DTYPE).copy()
+
+    def lts_trimmed_sq_async(self, X, y, betas, h: int, out) -> None:
+        """Enqueue lts_trimmed_sq: X (n x p), y (n), betas (m x p) float64 CUDA tensors."""
+        import torch
+        for t in (X, y, betas):
+            if not t.is_cuda or not t.is_contiguous() or t.dtype != torch.float64:
+                raise ValueError("X, y and betas must be contiguous float64 CUDA tensors")
+        n, p = X.shape
+        m = betas.shape[0]
+        if y.numel() != n or betas.shape[1] != p:
+            raise ValueError("shape mismatch between X, y and betas")
+        _check(lib().lts_trimmed_sq(self._h, self._ptr(X), self._ptr(y), self._ptr(betas), n, p, m,
+                                    int(h), self._ptr(out),
+                                    ctypes.c_void_p(_stream_ptr(self.device))), "lts_trimmed_sq")
+
+    def lts_trimmed_sq(self, X, y, betas, h: int | None = None) -> np.ndarray:
+        """Least trimmed squares per candidate (h defaults to floor((n+1)/2)); TRIM_DTYPE."""
+        import torch
+        m = betas.shape[0]
+        h = (X.shape[0] + 1) // 2 if h is None else int(h)
+        out = torch.empty(m * TRIM_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
+        self.lts_trimmed_sq_async(X, y, betas, h, out)
+        torch.cuda.synchronize(self.device)
+        return _as_records(out, TRIM_DTYPE).copy()
+
+    def knn_mean_async(self, P, f, Q, k: int, out) -> None:
+        """Enqueue knn_mean: P (n x dim), f (n), Q (nq x dim) float32 CUDA tensors."""
+        import torch
+        for t in (P, f, Q):
+            if not t.is_cuda or not t.is_contiguous() or t.dtype != torch.float32:
+                raise ValueError("P, f and Q must be contiguous float32 CUDA tensors")
+        n, dim = P.shape
+        nq = Q.shape[0]
+        if f.numel() != n or Q.shape[1] != dim:
+            raise ValueError("shape mismatch between P, f and Q")
+        _check(lib().knn_mean(self._h, self._ptr(P), self._ptr(f), self._ptr(Q), n, dim, nq, int(k),
+                              self._ptr(out), ctypes.c_void_p(_stream_ptr(self.device))),
+               "knn_mean")
+
+    def knn_mean(self, P, f, Q, k: int) -> np.ndarray:
+        """The mean ordinate of each query's k nearest points; KNN_DTYPE records."""
+        import torch
+        out = torch.empty(Q.shape[0] * KNN_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
+        self.knn_mean_async(P, f, Q, k, out)
+        torch.cuda.synchronize(self.device)
+        return _as_records(out, KNN_DTYPE).copy()
 
     def objective(self, x, k: int, ys) -> np.ndarray:
         """cps_objective at every y in `ys` (array-like of float64); returns EVAL_DTYPE records."""

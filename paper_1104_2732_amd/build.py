@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcpselect.so")
-SOURCES = ["select.hip", "batched.hip", "lms.hip", "learned.hip", "noalloc.hip", "api.hip"]
+SOURCES = ["select.hip", "batched.hip", "lms.hip", "knn.hip", "learned.hip", "noalloc.hip", "api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -341,7 +341,8 @@ int resolve_batched(cps_handle *h, int dtype, int64_t count, const cps_batch_opt
 
 template <typename T>
 int run_batched(cps_handle *h, const void *const *ptrs, const int64_t *sizes, const int64_t *ks,
-                int64_t count, const cps_batch_options *opt, cps_result *out, hipStream_t stream) {
+                int64_t count, const cps_batch_options *opt, cps_result *out, double *ksum,
+                hipStream_t stream) {
   BatchResolved r;
   int rc = resolve_batched(h, sizeof(T) == 4 ? CPS_F32 : CPS_F64, count, opt, r);
   if (rc) return rc;
@@ -367,6 +368,7 @@ int run_batched(cps_handle *h, const void *const *ptrs, const int64_t *sizes, co
   a.team_cap = r.team_cap;
   a.team_records = r.team_records;
   a.teams = h->tws;
+  a.ksum = ksum;
   hipError_t e = cps::launch_batched<T>(a, r.grid, r.block, stream);
   if (e != hipSuccess) return hip_fail(e);
   return CPS_OK;
@@ -399,15 +401,25 @@ void cps_default_batch_options(cps_batch_options *opt) {
   opt->team_capacity = (int64_t)1 << 18;
 }
 
-int select_kth_batched_ex(cps_handle *h, const void *const *ptrs_dev, const int64_t *sizes_dev,
-                          const int64_t *ks_dev, int64_t count, int dtype,
-                          const cps_batch_options *opt, cps_result *out_dev, void *stream) {
+int select_kth_batched_ksum(cps_handle *h, const void *const *ptrs_dev, const int64_t *sizes_dev,
+                            const int64_t *ks_dev, int64_t count, int dtype,
+                            const cps_batch_options *opt, cps_result *out_dev, double *ksum_dev,
+                            void *stream) {
   int rc = check_batched(h, ptrs_dev, sizes_dev, ks_dev, count, dtype, out_dev);
   if (rc) return rc;
   std::lock_guard<std::mutex> lk(h->mu);
   if (dtype == CPS_F32)
-    return run_batched<float>(h, ptrs_dev, sizes_dev, ks_dev, count, opt, out_dev, (hipStream_t)stream);
-  return run_batched<double>(h, ptrs_dev, sizes_dev, ks_dev, count, opt, out_dev, (hipStream_t)stream);
+    return run_batched<float>(h, ptrs_dev, sizes_dev, ks_dev, count, opt, out_dev, ksum_dev,
+                              (hipStream_t)stream);
+  return run_batched<double>(h, ptrs_dev, sizes_dev, ks_dev, count, opt, out_dev, ksum_dev,
+                             (hipStream_t)stream);
+}
+
+int select_kth_batched_ex(cps_handle *h, const void *const *ptrs_dev, const int64_t *sizes_dev,
+                          const int64_t *ks_dev, int64_t count, int dtype,
+                          const cps_batch_options *opt, cps_result *out_dev, void *stream) {
+  return select_kth_batched_ksum(h, ptrs_dev, sizes_dev, ks_dev, count, dtype, opt, out_dev,
+                                 nullptr, stream);
 }
 
 int select_kth_batched(cps_handle *h, const void *const *ptrs_dev, const int64_t *sizes_dev,
@@ -447,8 +459,8 @@ int lms_median_sq_residuals(cps_handle *h, const double *X_dev, const double *y_
     const double **ptrs = (const double **)(base + off_desc);
     int64_t *sizes = (int64_t *)(base + off_desc + align_up((size_t)m * 8, 256));
     int64_t *ks = (int64_t *)(base + off_desc + 2 * align_up((size_t)m * 8, 256));
-    hipError_t e = cps::launch_lms_residuals(X_dev, y_dev, betas_dev, n, p, m, R, ptrs, sizes, ks,
-                                             h->cu_count, s);
+    hipError_t e = cps::launch_lms_residuals(X_dev, y_dev, betas_dev, n, p, m, (n + 1) / 2, R,
+                                             ptrs, sizes, ks, h->cu_count, s);
     if (e != hipSuccess) return hip_fail(e);
   }
   char *base = (char *)h->lws;
@@ -461,6 +473,82 @@ int lms_median_sq_residuals(cps_handle *h, const double *X_dev, const double *y_
                                (const int64_t *)(base + off_desc + align_up((size_t)m * 8, 256)),
                                (const int64_t *)(base + off_desc + 2 * align_up((size_t)m * 8, 256)),
                                m, CPS_F64, &o, out_dev, stream);
+}
+
+int lts_trimmed_sq(cps_handle *h, const double *X_dev, const double *y_dev,
+                   const double *betas_dev, int64_t n, int32_t p, int64_t m, int64_t hk,
+                   cps_trim *out_dev, void *stream) {
+  if (!h || !X_dev || !y_dev || !betas_dev || !out_dev || n < 1 || p < 1 || p > 16 || m < 1 ||
+      m > (int64_t)65535 * 16 || hk < 1 || hk > n)
+    return CPS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  // residuals, then descriptors, selections, sums and records, in the workspace
+  const size_t off_desc = align_up((size_t)m * (size_t)n * sizeof(double), 256);
+  const size_t dsz = align_up((size_t)m * 8, 256);
+  const size_t off_sel = off_desc + 3 * dsz;
+  const size_t off_sum = off_sel + align_up((size_t)m * sizeof(cps_result), 256);
+  const size_t bytes = off_sum + dsz;
+  char *base;
+  {
+    std::lock_guard<std::mutex> lk(h->mu);
+    int rc = ensure_buffer(h->lws, h->lws_bytes, bytes, s);
+    if (rc) return rc;
+    base = (char *)h->lws;
+    hipError_t e = cps::launch_lms_residuals(X_dev, y_dev, betas_dev, n, p, m, hk, (double *)base,
+                                             (const double **)(base + off_desc),
+                                             (int64_t *)(base + off_desc + dsz),
+                                             (int64_t *)(base + off_desc + 2 * dsz), h->cu_count, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  cps_batch_options o;
+  cps_default_batch_options(&o);
+  int rc = select_kth_batched_ksum(h, (const void *const *)(base + off_desc),
+                                   (const int64_t *)(base + off_desc + dsz),
+                                   (const int64_t *)(base + off_desc + 2 * dsz), m, CPS_F64, &o,
+                                   (cps_result *)(base + off_sel), (double *)(base + off_sum),
+                                   stream);
+  if (rc) return rc;
+  hipError_t e = cps::launch_lts_finish((const cps_result *)(base + off_sel),
+                                        (const double *)(base + off_sum), m, hk, out_dev, s);
+  return e == hipSuccess ? CPS_OK : hip_fail(e);
+}
+
+int knn_mean(cps_handle *h, const float *P_dev, const float *f_dev, const float *Q_dev, int64_t n,
+             int32_t dim, int64_t nq, int64_t k, cps_knn *out_dev, void *stream) {
+  if (!h || !P_dev || !f_dev || !Q_dev || !out_dev || n < 1 || dim < 1 || dim > 16 || nq < 1 ||
+      nq > 65535 || k < 1 || k > n)
+    return CPS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t off_desc = align_up((size_t)nq * (size_t)n * sizeof(float), 256);
+  const size_t dsz = align_up((size_t)nq * 8, 256);
+  const size_t off_sel = off_desc + 3 * dsz;
+  const size_t off_pd = off_sel + align_up((size_t)nq * sizeof(cps_result), 256);
+  const size_t psz = align_up((size_t)nq * 16 * 8, 256);
+  const size_t bytes = off_pd + 2 * psz;
+  char *base;
+  {
+    std::lock_guard<std::mutex> lk(h->mu);
+    int rc = ensure_buffer(h->lws, h->lws_bytes, bytes, s);
+    if (rc) return rc;
+    base = (char *)h->lws;
+    hipError_t e = cps::launch_knn_distances(P_dev, Q_dev, n, dim, nq, k, (float *)base,
+                                             (const float **)(base + off_desc),
+                                             (int64_t *)(base + off_desc + dsz),
+                                             (int64_t *)(base + off_desc + 2 * dsz), h->cu_count, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  cps_batch_options o;
+  cps_default_batch_options(&o);
+  int rc = select_kth_batched_ex(h, (const void *const *)(base + off_desc),
+                                 (const int64_t *)(base + off_desc + dsz),
+                                 (const int64_t *)(base + off_desc + 2 * dsz), nq, CPS_F32, &o,
+                                 (cps_result *)(base + off_sel), stream);
+  if (rc) return rc;
+  hipError_t e = cps::launch_knn_reduce(P_dev, f_dev, Q_dev, n, dim, nq, k,
+                                        (const cps_result *)(base + off_sel),
+                                        (double *)(base + off_pd), (int64_t *)(base + off_pd + psz),
+                                        out_dev, s);
+  return e == hipSuccess ? CPS_OK : hip_fail(e);
 }
 
 int cps_autotune_batched(cps_handle *h, const void *const *ptrs_dev, const int64_t *sizes_dev,

@@ -55,6 +55,9 @@ template <typename T, int BLOCK> struct BShared {
   int32_t jpart, jparts;          // its part, and the parts of that array
   int32_t flag;                   // workgroup-wide flags (sampled bracket, last arrival)
   uint64_t kext[2];               // sampled keys' minimum and maximum
+  int64_t kcopy;                  // elements of the sampled bracket's copy (-1: not whole)
+  double kpa, kpb;                // the sampled bracket
+  double ksuma;                   // sum of the elements at or below the bracket's lower end
   uint64_t order[kBatchSortMax];  // (size << 12 | index) sorted by size, largest first; then
                                   // item_entry(first work item, index) per slot
   uint32_t rh[kHistMaxBins];      // key histogram of a histogram pass
@@ -473,7 +476,7 @@ __device__ inline int64_t prop_reserve(uint32_t tot, unsigned long long *cursor)
   return (int64_t)__shfl(base, 0);
 }
 
-template <typename T, int BLOCK, int U, bool TEAM>
+template <typename T, int BLOCK, int U, bool TEAM, bool SUMA>
 __device__ void block_pass0_prop(const Span<T> &sp, T pa, const PropBins<T> &ib, uint32_t *rh,
                                  P0Acc<T> &acc, CPS_GLOBAL T *out, int64_t cap,
                                  unsigned long long *cursor, uint32_t &ovf) {
@@ -486,7 +489,9 @@ __device__ void block_pass0_prop(const Span<T> &sp, T pa, const PropBins<T> &ib,
   auto one = [&](T v, bool valid) -> bool {
     acc.nnan += (valid & (v != v)) ? 1u : 0u;
     const Key K = Traits<T>::key(v);
-    acc.cle_a += (valid & (K <= ib.ka)) ? 1u : 0u;
+    const bool le = valid & (K <= ib.ka);
+    acc.cle_a += le ? 1u : 0u;
+    if (SUMA) acc.Aa += le ? (double)v : 0.0;  // the sum of the elements at or below a
     const Key d = K - ib.klo;
     const bool in = valid & (d <= ib.span);
     acc.clt_b += in ? 1u : 0u;  // (here: the interior's count)
@@ -588,6 +593,7 @@ template <typename T, int BLOCK, int U>
 __device__ __noinline__ bool prop_pass0(const T *x, int64_t n, int64_t k, T pa, T pb, int part, int parts,
                            TeamCtl *tc, CPS_GLOBAL T *ibuf, int64_t icap,
                            const BatchArgs<T> &a, BShared<T, BLOCK> &sh) {
+  const bool suma = a.ksum != nullptr;
   using Key = typename Traits<T>::Key;
   const int tid = threadIdx.x;
   const int32_t dt = a.cfg.dtype;
@@ -615,19 +621,22 @@ __device__ __noinline__ bool prop_pass0(const T *x, int64_t n, int64_t k, T pa, 
   acc.nnan = acc.nneg = acc.npos = acc.cle_a = acc.clt_b = 0;
   acc.Aa = acc.Ba = acc.Ab = acc.Bb = 0;
   uint32_t ovf = 0;
-  if (parts > 1)
-    block_pass0_prop<T, BLOCK, U, true>(sp, pa, ib, sh.rh, acc, ibuf, icap, &tc->cursor, ovf);
-  else
-    block_pass0_prop<T, BLOCK, U, false>(sp, pa, ib, sh.rh, acc, ibuf, icap,
-                                         reinterpret_cast<unsigned long long *>(&sh.cur[0]), ovf);
+  unsigned long long *lcur = reinterpret_cast<unsigned long long *>(&sh.cur[0]);
+  if (parts > 1) {
+    if (suma) block_pass0_prop<T, BLOCK, U, true, true>(sp, pa, ib, sh.rh, acc, ibuf, icap, &tc->cursor, ovf);
+    else block_pass0_prop<T, BLOCK, U, true, false>(sp, pa, ib, sh.rh, acc, ibuf, icap, &tc->cursor, ovf);
+  } else {
+    if (suma) block_pass0_prop<T, BLOCK, U, false, true>(sp, pa, ib, sh.rh, acc, ibuf, icap, lcur, ovf);
+    else block_pass0_prop<T, BLOCK, U, false, false>(sp, pa, ib, sh.rh, acc, ibuf, icap, lcur, ovf);
+  }
   double mn = (double)acc.mn, mx = (double)acc.mx;
   int64_t cmn = acc.cmn, cmx = acc.cmx;
   block_pair_fold<BLOCK>(mn, cmn, mx, cmx, sh.d, sh.i);
-  double dv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double dv[8] = {acc.Aa, 0, 0, 0, 0, 0, 0, 0};
   int64_t iv[8] = {(int64_t)acc.cle_a, (int64_t)acc.nnan, (int64_t)ovf, (int64_t)acc.clt_b, 0, 0,
                    0, 0};
   int dop[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  block_reduce<BLOCK, 0, 4>(dv, dop, iv, false, sh.d, sh.i);
+  block_reduce<BLOCK, 1, 4>(dv, dop, iv, false, sh.d, sh.i);
   int64_t written = 0;
   if (parts > 1) {
     // leave the partial, add the bins, arrive; the last part folds
@@ -638,6 +647,7 @@ __device__ __noinline__ bool prop_pass0(const T *x, int64_t n, int64_t k, T pa, 
     if (tid == 0) {
       tc->pd[part][0] = mn;
       tc->pd[part][1] = mx;
+      tc->pd[part][2] = dv[0];
       tc->pi[part][0] = cmn;
       tc->pi[part][1] = cmx;
       tc->pi[part][2] = iv[0];
@@ -658,9 +668,10 @@ __device__ __noinline__ bool prop_pass0(const T *x, int64_t n, int64_t k, T pa, 
       tc->hist[b] = 0u;
     }
     if (tid == 0) {
-      double fmn = __builtin_inf(), fmx = -__builtin_inf();
+      double fmn = __builtin_inf(), fmx = -__builtin_inf(), sa = 0.0;
       int64_t c0 = 0, c1 = 0, le = 0, nan = 0, inner = 0;
       for (int p = 0; p < parts; ++p) {
+        sa += tc->pd[p][2];
         const double m0 = tc->pd[p][0], m1 = tc->pd[p][1];
         if (m0 < fmn) { fmn = m0; c0 = tc->pi[p][0]; } else if (m0 == fmn) c0 += tc->pi[p][0];
         if (m1 > fmx) { fmx = m1; c1 = tc->pi[p][1]; } else if (m1 == fmx) c1 += tc->pi[p][1];
@@ -669,6 +680,7 @@ __device__ __noinline__ bool prop_pass0(const T *x, int64_t n, int64_t k, T pa, 
         inner += tc->pi[p][4];
       }
       mn = fmn; cmn = c0; mx = fmx; cmx = c1;
+      dv[0] = sa;
       iv[0] = le;
       iv[1] = nan;
       iv[3] = inner;
@@ -695,6 +707,10 @@ __device__ __noinline__ bool prop_pass0(const T *x, int64_t n, int64_t k, T pa, 
     r.c_lt_b = iv[0] + iv[3];  // the interior's keys lie between those of a and b
     r.split_overflow = iv[2] != 0 ? 1 : 0;
     r.split_written = written;  // whole vectors: a superset of the interior
+    // for the sum of the k smallest: the copy holds every element of (a, b), and the sum of
+    // those at or below a
+    sh.kcopy = (iv[2] == 0 && iv[1] == 0) ? written : -1;
+    sh.ksuma = dv[0];
     CpState &st = sh.st;
     st = CpState{};
     st.n = n;
@@ -725,10 +741,48 @@ __device__ __noinline__ bool prop_pass0(const T *x, int64_t n, int64_t k, T pa, 
   return true;
 }
 
+// The sum of the elements w of span sp with lo_ex < w < hi_ex (w < hi_ex alone without LO),
+// in double precision (a fixed order for a fixed span); valid in thread 0.
+template <typename T, int BLOCK, int U, bool LO>
+__device__ double block_sum_range(const Span<T> &sp, T lo_ex, T hi_ex, BShared<T, BLOCK> &sh) {
+  constexpr int V = Traits<T>::kVec;
+  using Vec = typename Traits<T>::Vec;
+  const int tid = threadIdx.x;
+  double acc = 0.0;
+  for (int64_t base = 0; base < sp.nvec; base += (int64_t)BLOCK * U) {
+    Vec raw[U];
+    bool valid[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t vi = base + (int64_t)u * BLOCK + tid;
+      valid[u] = vi < sp.nvec;
+      if (valid[u]) raw[u] = __builtin_nontemporal_load(&sp.V[vi]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      T w[V];
+      vec_to_arr<T>(raw[u], w);
+#pragma unroll
+      for (int j = 0; j < V; ++j)
+        acc += (valid[u] & (!LO | (w[j] > lo_ex)) & (w[j] < hi_ex)) ? (double)w[j] : 0.0;
+    }
+  }
+  if (sp.nedge > 0 && tid < sp.nedge) {
+    const T w = sp.W[edge_index(sp, tid)];
+    acc += ((!LO || w > lo_ex) && w < hi_ex) ? (double)w : 0.0;
+  }
+  double dv[8] = {acc, 0, 0, 0, 0, 0, 0, 0};
+  int dop[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t iv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  block_reduce<BLOCK, 1, 0>(dv, dop, iv, false, sh.d, sh.i);
+  return dv[0];
+}
+
 // The whole method on one array (part `part` of `parts` of it; slot: its largest-first slot,
-// which names its team record), by this workgroup.
+// which names its team record), by this workgroup.  With ksum (not null), also the sum of
+// the array's k smallest elements.
 template <typename T, int BLOCK, int U>
-__device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out,
+__device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out, double *ksum,
                            const BatchArgs<T> &a, BShared<T, BLOCK> &sh, int64_t slot, int part,
                            int parts) {
   const int tid = threadIdx.x;
@@ -742,9 +796,11 @@ __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out,
       cps_result r = {};
       r.status = ST_BADARG;
       *out = r;
+      if (ksum) *ksum = __builtin_nan("");
     }
     return;
   }
+  if (tid == 0) sh.kcopy = -1;
   bool slow = false, p0_done = false;
   if (a.proposal && a.cfg.hist_bits > 0 && n >= kBatchPropMin) {
     T pa, pb;
@@ -757,8 +813,14 @@ __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out,
                                    a, sh))
         return;
       zb[0] = ibuf;  // the interior's elements are the working set from here on
+      if (tid == 0) {
+        sh.kpa = (double)pa;
+        sh.kpb = (double)pb;
+      }
       if (sh.st.phase == PH_PASS0 && sh.st.p0_slow) slow = true;  // NaN or an infinity
       else p0_done = true;
+      __syncthreads();
+      if (slow && tid == 0) sh.kcopy = -1;
     }
   } else if (part > 0) {
     return;  // (parts are formed only for arrays that take the sampled bracket)
@@ -932,6 +994,26 @@ __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out,
     if (tid == 0) bdev_after_final(sh.st, (double)Traits<T>::unkey(key), below, eq);
     __syncthreads();
   }
+  if (ksum) {
+    // the sum of the k smallest elements: those below x_(k), plus k - #(x < x_(k)) copies of
+    // it; the elements below come from the sampled bracket's copy and pass 0's sum at or
+    // below its lower end when x_(k) lies inside the bracket, else from a pass over x
+    __syncthreads();
+    const CpState &s = sh.st;
+    if (s.status == ST_OK) {
+      const T v = (T)s.value;
+      const T pa = (T)sh.kpa, pb = (T)sh.kpb;
+      double below;
+      if (sh.kcopy >= 0 && pa < v && v < pb)
+        below = sh.ksuma +
+                block_sum_range<T, BLOCK, U, true>(make_span((const T *)zb[0], sh.kcopy), pa, v, sh);
+      else
+        below = block_sum_range<T, BLOCK, U, false>(make_span(x, n), v, v, sh);
+      if (tid == 0) *ksum = below + (double)(s.k - s.less) * (double)v;
+    } else if (tid == 0) {
+      *ksum = __builtin_nan("");
+    }
+  }
   if (tid == 0) write_batch_result<T>(out, sh.st);
   __syncthreads();
 }
@@ -1013,7 +1095,8 @@ void batched_select_kernel(BatchArgs<T> a) {
     const int part = sh.jpart, parts = sh.jparts;
     __syncthreads();
     if (q >= items) break;
-    select_one<T, BLOCK, U>(a.ptrs[i], a.sizes[i], a.ks[i], a.out + i, a, sh, j, part, parts);
+    select_one<T, BLOCK, U>(a.ptrs[i], a.sizes[i], a.ks[i], a.out + i, a.ksum ? a.ksum + i : nullptr,
+                            a, sh, j, part, parts);
   }
   // the last workgroup out resets the queue for the next launch (graph replays included)
   if (tid == 0) {

@@ -97,7 +97,7 @@ struct TeamCtl {
   uint32_t pad0[30];
   unsigned long long cursor; // 16-byte vectors written to the team buffer
   uint64_t pad1[15];
-  double pd[kTeamMax][2];    // per part: min, max
+  double pd[kTeamMax][3];    // per part: min, max, sum of the elements at or below a
   int64_t pi[kTeamMax][6];   // per part: #min, #max, #(x <= a), #NaN, #(a < x < b), unused
   uint32_t hist[kHistMaxBins];  // the interior's key bins, summed over the parts
 };
@@ -123,6 +123,7 @@ template <typename T> struct BatchArgs {
   int64_t team_records;  // records (and team buffers): largest-first slots below this may split
   TeamCtl *teams;        // team_records records
   T *tbuf;               // team_records buffers of team_cap elements
+  double *ksum;          // per array: the sum of its k smallest elements (or null)
 };
 
 template <typename T>
@@ -130,8 +131,18 @@ hipError_t launch_batched(const BatchArgs<T> &a, int grid, int block, hipStream_
 template <typename T> int batched_max_blocks_per_cu(int block);
 
 hipError_t launch_lms_residuals(const double *X, const double *y, const double *betas, int64_t n,
-                                int32_t p, int64_t m, double *R, const double **ptrs,
+                                int32_t p, int64_t m, int64_t rank, double *R, const double **ptrs,
                                 int64_t *sizes, int64_t *ks, int cu_count, hipStream_t stream);
+hipError_t launch_lts_finish(const cps_result *sel, const double *ksum, int64_t m, int64_t h,
+                             cps_trim *out, hipStream_t stream);
+
+// ---- k nearest neighbours
+hipError_t launch_knn_distances(const float *P, const float *Q, int64_t n, int32_t dim, int64_t nq,
+                                int64_t k, float *Dst, const float **ptrs, int64_t *sizes,
+                                int64_t *ks, int cu_count, hipStream_t stream);
+hipError_t launch_knn_reduce(const float *P, const float *f, const float *Q, int64_t n,
+                             int32_t dim, int64_t nq, int64_t k, const cps_result *sel,
+                             double *pd, int64_t *pi, cps_knn *out, hipStream_t stream);
 
 template <typename T> hipError_t launch_select(const SelectArgs<T> &a, int grid, hipStream_t stream);
 template <typename T> int select_max_blocks_per_cu();

@@ -144,14 +144,6 @@ __global__ void knn_final_kernel(int64_t nq, int64_t k, int nb, const cps_result
   }
 }
 
-size_t knn_workspace(int64_t n, int64_t nq) {
-  const size_t dbytes = ((size_t)nq * (size_t)n * sizeof(float) + 255) / 256 * 256;
-  const size_t desc = 3 * (((size_t)nq * 8 + 255) / 256 * 256);
-  const size_t sel = ((size_t)nq * sizeof(cps_result) + 255) / 256 * 256;
-  const size_t part = 2 * (((size_t)nq * kKnnRedBlocks * 2 * 8 + 255) / 256 * 256);
-  return dbytes + desc + sel + part;
-}
-
 hipError_t launch_knn_distances(const float *P, const float *Q, int64_t n, int32_t dim, int64_t nq,
                                 int64_t k, float *Dst, const float **ptrs, int64_t *sizes,
                                 int64_t *ks, int cu_count, hipStream_t stream) {

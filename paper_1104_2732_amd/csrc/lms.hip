@@ -51,18 +51,44 @@ __global__ __launch_bounds__(kLmsBlock) void lms_residual_kernel(
   }
 }
 
-__global__ void lms_descriptor_kernel(const double *R, int64_t n, int64_t m, const double **ptrs,
-                                      int64_t *sizes, int64_t *ks) {
+__global__ void lms_descriptor_kernel(const double *R, int64_t n, int64_t m, int64_t rank,
+                                      const double **ptrs, int64_t *sizes, int64_t *ks) {
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < m;
        c += (int64_t)gridDim.x * blockDim.x) {
     ptrs[c] = R + c * n;
     sizes[c] = n;
-    ks[c] = (n + 1) / 2;
+    ks[c] = rank;
   }
 }
 
+// Least trimmed squares (Section 6): from the selection of rank h among a candidate's squared
+// residuals (m = r_(h), #(r < m), #(r = m)) and the sum of its h smallest, the record with
+// a = h - #(r < m), the weight of m in Section 6's rho.
+__global__ void lts_finish_kernel(const cps_result *__restrict__ sel, const double *__restrict__ ksum,
+                                  int64_t m, int64_t h, cps_trim *__restrict__ out) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < m;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const cps_result r = sel[c];
+    cps_trim t;
+    t.F = r.status == 0 ? ksum[c] : __builtin_nan("");
+    t.m = r.value;
+    t.below = r.less;
+    t.a = r.status == 0 ? h - r.less : 0;
+    t.b = r.equal;
+    t.status = r.status;
+    t.pad = 0;
+    out[c] = t;
+  }
+}
+
+hipError_t launch_lts_finish(const cps_result *sel, const double *ksum, int64_t m, int64_t h,
+                             cps_trim *out, hipStream_t stream) {
+  lts_finish_kernel<<<dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream>>>(sel, ksum, m, h, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_lms_residuals(const double *X, const double *y, const double *betas, int64_t n,
-                                int32_t p, int64_t m, double *R, const double **ptrs,
+                                int32_t p, int64_t m, int64_t rank, double *R, const double **ptrs,
                                 int64_t *sizes, int64_t *ks, int cu_count, hipStream_t stream) {
   const int64_t groups = (m + kLmsGroup - 1) / kLmsGroup;
   int64_t bx = (n + kLmsBlock - 1) / kLmsBlock;
@@ -76,7 +102,8 @@ hipError_t launch_lms_residuals(const double *X, const double *y, const double *
     lms_residual_kernel<0><<<grid, dim3(kLmsBlock), 0, stream>>>(X, y, betas, n, p, m, R);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  lms_descriptor_kernel<<<dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream>>>(R, n, m, ptrs, sizes, ks);
+  lms_descriptor_kernel<<<dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream>>>(R, n, m, rank,
+                                                                                    ptrs, sizes, ks);
   return hipGetLastError();
 }
 

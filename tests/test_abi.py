@@ -70,11 +70,12 @@ def test_record_layouts_match_the_binding(tmp_path):
     import paper_1104_2732_amd as cps
     src = tmp_path / "sizes.c"
     src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "cpselect.h"\n'
-                   'int main(void) { printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", '
+                   'int main(void) { printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", '
                    'sizeof(cps_result), sizeof(cps_eval), sizeof(cps_options), '
                    'sizeof(cps_stats), sizeof(cps_batch_options), sizeof(cps_train_options), '
                    'sizeof(cps_train_report), offsetof(cps_options, compact_proposal), '
-                   'offsetof(cps_train_options, holdout)); return 0; }\n')
+                   'offsetof(cps_train_options, holdout), sizeof(cps_trim), sizeof(cps_knn), '
+                   'offsetof(cps_batch_options, team_capacity)); return 0; }\n')
     exe = tmp_path / "sizes"
     subprocess.run(["gcc", "-std=c99", "-I", HEADER_DIR, "-o", str(exe), str(src)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
@@ -82,7 +83,8 @@ def test_record_layouts_match_the_binding(tmp_path):
     want = [cps.RESULT_DTYPE.itemsize, cps.EVAL_DTYPE.itemsize, ctypes.sizeof(cps.Options),
             cps.STATS_DTYPE.itemsize, ctypes.sizeof(cps.BatchOptions),
             ctypes.sizeof(cps.TrainOptions), ctypes.sizeof(cps.TrainReport),
-            cps.Options.compact_proposal.offset, cps.TrainOptions.holdout.offset]
+            cps.Options.compact_proposal.offset, cps.TrainOptions.holdout.offset,
+            cps.TRIM_DTYPE.itemsize, cps.KNN_DTYPE.itemsize, cps.BatchOptions.team_capacity.offset]
     assert got == want
 
 
