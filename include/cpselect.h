@@ -129,7 +129,16 @@ typedef struct cps_eval {
  *                   copies the elements of a likely interval (sample quantiles around the
  *                   rank) to the workspace, and when the narrowed bracket lies inside it the
  *                   copy replaces that next pass over x.  1 (default) or 0 (the split writes
- *                   both sides and counts them as it goes). */
+ *                   both sides and counts them as it goes).
+ * transform:        1: the cutting plane minimises the objective of F(x) = log(1 + x - min x),
+ *                   the monotone transform of Section 5.3 for data with a few huge values
+ *                   (~1e20, where the sums over x lose every smaller term): one evaluation
+ *                   at the minimum forms F's objective at both ends, then every trial point is
+ *                   Kelley's step on F's scale mapped back by F^-1, and every evaluation sums
+ *                   F(x) in double precision; counts, comparisons and the result stay on x
+ *                   (exact whatever F rounds).  Runs without splits (count_first is then
+ *                   forced on when hist_bits > 0, and partition_fraction to 0 when it is 0);
+ *                   not with use_bracket or a proposal.  0 (default): the objective of x. */
 typedef struct cps_options {
   int32_t maxit;
   int32_t final_threshold;
@@ -142,6 +151,8 @@ typedef struct cps_options {
   double bracket_lo, bracket_hi;
   int32_t hist_bits;
   int32_t count_first;
+  int32_t transform;
+  int32_t pad;
 } cps_options;
 
 #define CPS_STATS_MAX_PASSES 96

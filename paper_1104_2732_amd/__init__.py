@@ -72,7 +72,8 @@ class Options(ctypes.Structure):
                 ("block_threads", ctypes.c_int32), ("spin_limit", ctypes.c_int64),
                 ("use_bracket", ctypes.c_int32), ("compact_proposal", ctypes.c_int32),
                 ("bracket_lo", ctypes.c_double), ("bracket_hi", ctypes.c_double),
-                ("hist_bits", ctypes.c_int32), ("count_first", ctypes.c_int32)]
+                ("hist_bits", ctypes.c_int32), ("count_first", ctypes.c_int32),
+                ("transform", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class BatchOptions(ctypes.Structure):

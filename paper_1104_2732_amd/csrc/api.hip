@@ -178,6 +178,13 @@ int resolve(cps_handle *h, int64_t n, int dtype, const cps_options *opt, Resolve
   r.cfg.hist_bits = o.hist_bits;
   r.cfg.hist_compact = 1;  // the single-array kernel compacts in its histogram passes
   r.cfg.count_first = o.count_first ? 1 : 0;
+  if (o.transform) {
+    // the transformed objective runs without splits, and never with a proposed bracket
+    if (o.transform != 1 || o.use_bracket) return CPS_EINVAL;
+    r.cfg.transform = 1;
+    if (o.hist_bits > 0) r.cfg.count_first = 1;
+    else r.cfg.theta = 0.0;
+  }
   // from 256 MiB of input on (2^26 float or 2^25 double elements), the counting evaluation
   // also copies a likely interval; below, the pass over x that the copy saves costs about
   // what the copy and the interval's sample cost (measured: 2^24 float32 selections 0.169-
@@ -254,6 +261,7 @@ int run_select(cps_handle *h, const T *x, int64_t n, int64_t k, const cps_option
   // (past about two thirds of the input, the passes over x that compaction would spare
   // cost less than reading the compacted elements again)
   const bool proposal = bracket_dev != nullptr || r.cfg.use_bracket != 0;
+  if (proposal && r.cfg.transform) return CPS_EINVAL;
   a.p0_cap = (proposal && r.compact_proposal) ? L.seg_R / 2 : 0;
   a.ghist = (uint64_t *)(base + L.gh);
   hipError_t e = cps::launch_select<T>(a, r.grid, stream);

@@ -39,6 +39,7 @@
 // bracket in the ordered bit pattern of T, which bounds the number of passes.
 #pragma once
 
+#include <math.h>
 #include <stdint.h>
 
 #ifdef __HIPCC__
@@ -75,7 +76,8 @@ struct CpConfig {
                             // the evaluation counts both sides in key bins instead and writes
                             // nothing; the bracket narrows to a bin, whose elements the next
                             // pass over the input compacts (hist_compact) or counts
-  int32_t pad1;
+  int32_t transform;        // 1: the cutting plane runs on F(x) = log(1 + x - min x) (see
+                            // cp_F); counts, comparisons and the result stay on x
   int64_t spec_min_n;       // inputs of at least this many elements (0: none): the counting
                             // evaluation also copies the elements of a likely interval
                             // [spec_a, spec_b] to split buffer 0 (see cp_adopt_spec)
@@ -153,8 +155,12 @@ struct CpState {
                            // counts the elements on either side of t in key bins
   int32_t spec;            // that counting evaluation also copies every element of
                            // [spec_a, spec_b] to the low parts of split buffer 0
-  int32_t pad1;
+  int32_t tf;              // the objective's values (AL, BL, AR, BR, an evaluation's A and B)
+                           // are those of the transformed data F(x) (CpConfig::transform)
   double spec_a, spec_b;
+  int32_t fends;           // with tf: F's objective at the bracket ends is not formed yet;
+                           // the evaluation about to run at t = yL forms it
+  int32_t pad2;
 };
 
 static_assert(sizeof(CpState) % 8 == 0, "state is copied in 8-byte words");
@@ -219,6 +225,16 @@ CPS_HD inline double key_mid(double a, double b, int32_t dtype) {
 
 CPS_HD inline bool inside(double t, double a, double b) { return t > a && t < b; }
 
+// The monotone transform of the outlier discussion (Section 5.3): F(y) = log(1 + y - min x).
+// The k-th smallest is invariant under an increasing F, so the cutting plane may minimise
+// the objective of F(x) instead; its sums then stay accurate when a few elements are huge
+// (~1e20), where the sums over x lose every other term.  Here only the objective's values
+// and the trial points are formed on F(x): the counts, every comparison and the result stay
+// on x, so the answer is exact whether F rounds distinct values together or not.
+CPS_HD inline double cp_F(const CpState &s, double y) {
+  return s.tf ? log1p(y - s.fmin) : y;
+}
+
 // ---------------------------------------------------------------- transitions
 
 CPS_HD inline void cp_finish(CpState &s, double value, int64_t less, int64_t equal) {
@@ -241,8 +257,13 @@ CPS_HD inline double cp_trial_point(CpState &s, const CpConfig &c) {
     const double gR = n * ((double)s.cR - k + 0.5);
     const double fL = alpha * s.AL + beta * s.BL;
     const double fR = alpha * s.AR + beta * s.BR;
-    const double D = s.yR - s.yL;
-    t = s.yL + (fR - fL - gR * D) / (gL - gR);
+    // (with tf, the step is taken on F's scale, y = F(x), and mapped back by F^-1; while F's
+    // objective at the ends is not formed, the midpoint on that scale)
+    const double uL = cp_F(s, s.yL), uR = cp_F(s, s.yR);
+    const double D = uR - uL;
+    double u = s.fends ? 0.5 * uL + 0.5 * uR : uL + (fR - fL - gR * D) / (gL - gR);
+    if (s.tf && !inside(u, uL, uR)) u = 0.5 * uL + 0.5 * uR;
+    t = s.tf ? s.fmin + expm1(u) : u;
     ok = inside(t, s.yL, s.yR);
     if (!ok) {
       t = 0.5 * s.yL + 0.5 * s.yR;
@@ -322,6 +343,13 @@ CPS_HD inline void cp_plan(CpState &s, const CpConfig &c) {
     }
   }
   s.phase = PH_EVAL;
+  if (s.fends && !s.counted && !s.split && s.wbuf < 0) {
+    // F's objective at both ends from one evaluation at the left end (F(yL) = 0 there):
+    // A_F(yL) = sum F(x), and B_F(yR) = n F(yR) - sum F(x)
+    s.filter = 0;
+    s.t = s.yL;
+    return;
+  }
   s.t = cp_trial_point(s, c);
 }
 
@@ -374,6 +402,8 @@ CPS_HD inline void cp_after_pass0(CpState &s, const Pass0Result &r, const CpConf
   s.lo = next_up(s.yL, c.dtype);
   s.hi = next_down(s.yR, c.dtype);
   s.lo_data = s.hi_data = 0;
+  s.tf = c.transform ? 1 : 0;
+  s.fends = s.tf;
   s.wbuf = -1;
   s.side = 0;
   s.wlen = n;
@@ -451,8 +481,8 @@ CPS_HD inline FullEval cp_full_eval(const CpState &s, const EvalResult &r) {
   if (s.on_bracket) {
     f.L += s.cL;
     f.G += s.n - s.cR;
-    f.A += s.AR + (double)(s.n - s.cR) * (s.yR - s.t);
-    f.B += s.BL + (double)s.cL * (s.t - s.yL);
+    f.A += s.AR + (double)(s.n - s.cR) * (cp_F(s, s.yR) - cp_F(s, s.t));
+    f.B += s.BL + (double)s.cL * (cp_F(s, s.t) - cp_F(s, s.yL));
   }
   return f;
 }
@@ -461,6 +491,20 @@ CPS_HD inline FullEval cp_full_eval(const CpState &s, const EvalResult &r) {
 CPS_HD inline void cp_after_eval(CpState &s, const EvalResult &r, const CpConfig &c) {
   const int64_t n = s.n, k = s.k;
   const double t = s.t;
+  if (s.fends && t == s.yL && s.wbuf < 0 && !s.counted) {
+    // the evaluation at the left end (cp_plan): F's objective at both ends
+    s.work_passes++;
+    s.passes++;
+    s.elements_read += s.wlen;
+    s.AL = r.A;
+    s.BL = 0.0;
+    s.AR = 0.0;
+    const double br = (double)n * cp_F(s, s.yR) - r.A;
+    s.BR = br > 0.0 ? br : 0.0;
+    s.fends = 0;
+    cp_plan(s, c);
+    return;
+  }
   const FullEval fe = cp_full_eval(s, r);
   s.work_passes++;
   if (s.wbuf < 0) s.passes++;

@@ -393,6 +393,54 @@ __device__ inline void eval_tile(const Span<T> &sp, int64_t base, int per_u, int
   }
 }
 
+// An evaluation pass on the transformed scale (CpConfig::transform): the counts below and
+// above t and t's neighbours on x, the sums A and B on F(x) = log(1 + x - xmin) (double
+// precision; with CLAMP, infinities first clamped to the finite extremes).  Ft = F(t).
+template <typename T, int BLOCK, int U, bool CLAMP>
+__device__ inline void eval_pass_log(const Walk<T> &wk, T t, double xmin, double Ft, T fmin,
+                                     T fmax, EvalAcc<T> &acc) {
+  constexpr int V = Traits<T>::kVec;
+  using Vec = typename Traits<T>::Vec;
+  const int tid = threadIdx.x, lane = tid % kWave;
+  const Span<T> &sp = wk.sp;
+  auto one = [&](T v, bool valid) {
+    if (CLAMP) v = tmin(tmax(v, fmin), fmax);
+    const bool l = valid && (v < t);
+    const bool g = valid && (v > t);
+    const double F = log1p((double)v - xmin);
+    acc.A += g ? F - Ft : 0.0;
+    acc.B += l ? Ft - F : 0.0;
+    acc.pred = tmax(acc.pred, l ? v : -t_inf<T>());
+    acc.succ = tmin(acc.succ, g ? v : t_inf<T>());
+    acc.L += l ? 1u : 0u;
+    acc.G += g ? 1u : 0u;
+  };
+  // (the working set is x: the transform runs without splits)
+  const int64_t step_vecs = (int64_t)BLOCK * U;
+  for (int64_t base = (int64_t)blockIdx.x * step_vecs; base < sp.nvec;
+       base += (int64_t)gridDim.x * step_vecs) {
+    Vec raw[U];
+    bool valid[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t vi = base + (int64_t)u * BLOCK + tid;
+      valid[u] = vi < sp.nvec;
+      if (valid[u]) raw[u] = __builtin_nontemporal_load(&sp.V[vi]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      T e[V];
+      vec_to_arr<T>(raw[u], e);
+#pragma unroll
+      for (int j = 0; j < V; ++j) one(e[j], valid[u]);
+    }
+  }
+  if (sp.nedge > 0 && wk.edge_owner && tid < kWave) {
+    const bool have = lane < sp.nedge;
+    one(have ? sp.W[edge_index(sp, lane)] : T(0), have);
+  }
+}
+
 // One evaluation pass (optionally splitting) over this thread's share of the walk.
 template <typename T, int BLOCK, int U, bool CLAMP, bool SPLIT, bool FILTER, bool HIST,
           bool SPEC = false>
@@ -1151,8 +1199,15 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
         eval_pass<T, BLOCK, UNROLL, false, false, true, true>(wk, t, yL, yR, fmn, fmx, o, acc, pb);
       }
     } else if (!s.split) {
-      if (clamp) eval_pass<T, BLOCK, SU, true, false, false, false>(wk, t, yL, yR, fmn, fmx, o, acc, pb);
-      else eval_pass<T, BLOCK, UNROLL, false, false, false, false>(wk, t, yL, yR, fmn, fmx, o, acc, pb);
+      if (s.tf) {  // the transformed scale (x is the working set: no splits with the transform)
+        const double Ft = log1p(s.t - s.fmin);
+        if (clamp) eval_pass_log<T, BLOCK, SU, true>(wk, t, s.fmin, Ft, fmn, fmx, acc);
+        else eval_pass_log<T, BLOCK, SU, false>(wk, t, s.fmin, Ft, fmn, fmx, acc);
+      } else if (clamp) {
+        eval_pass<T, BLOCK, SU, true, false, false, false>(wk, t, yL, yR, fmn, fmx, o, acc, pb);
+      } else {
+        eval_pass<T, BLOCK, UNROLL, false, false, false, false>(wk, t, yL, yR, fmn, fmx, o, acc, pb);
+      }
     } else if (s.filter) {
       if (hist) eval_pass<T, BLOCK, SU, false, true, true, true>(wk, t, yL, yR, fmn, fmx, o, acc, pb);
       else eval_pass<T, BLOCK, SU, false, true, true, false>(wk, t, yL, yR, fmn, fmx, o, acc, pb);

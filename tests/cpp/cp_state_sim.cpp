@@ -27,8 +27,9 @@ template <typename T>
 static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_threshold,
                double theta, int use_bracket, double blo, double bhi, int p0_split,
                int64_t p0_cap, int hist_bits, int count_first, int hist_compact, int p0_sums,
-               int spec_mode, SimResult *out, int side_bits = -1) {
+               int spec_mode, SimResult *out, int side_bits = -1, int transform = 0) {
   CpConfig c{};
+  c.transform = transform;
   c.maxit = maxit;
   c.dtype = sizeof(T) == 4 ? 0 : 1;
   c.final_threshold = final_threshold;
@@ -197,8 +198,10 @@ static int sim(const T *x, int64_t n, int64_t k, int maxit, int64_t final_thresh
     for (int64_t i = 0; i < wl; i++) {
       T v = W[i];
       if (clamp) v = std::min(std::max(v, (T)s.fmin), (T)s.fmax);
-      if (v < t) { e.L++; e.B += (double)(t - v); e.pred = std::max<double>(e.pred, v); }
-      if (v > t) { e.G++; e.A += (double)(v - t); e.succ = std::min<double>(e.succ, v); }
+      // (with the transform, the sums are on F(x) = log(1 + x - min x); the counts on x)
+      const double dv = s.tf ? cp_F(s, (double)v) - cp_F(s, (double)t) : (double)(v - t);
+      if (v < t) { e.L++; e.B -= dv; e.pred = std::max<double>(e.pred, v); }
+      if (v > t) { e.G++; e.A += dv; e.succ = std::min<double>(e.succ, v); }
       if (spec && v >= (T)s.spec_a && v <= (T)s.spec_b) z[0][nspec++] = v;
       if (s.split || count_only) {
         const bool inb = !s.filter || (v > yL && v < yR);
@@ -334,15 +337,15 @@ int replay_batch_f32(const float *data, const uint64_t *addrs, const int64_t *of
 int sim_select_f32(const float *x, int64_t n, int64_t k, int maxit, int64_t ft, double theta,
                    int ub, double blo, double bhi, int p0_split, int64_t p0_cap, int hist_bits,
                    int count_first, int hist_compact, int p0_sums, int spec_mode,
-                   SimResult *out) {
+                   int transform, SimResult *out) {
   return sim<float>(x, n, k, maxit, ft, theta, ub, blo, bhi, p0_split, p0_cap, hist_bits,
-                    count_first, hist_compact, p0_sums, spec_mode, out);
+                    count_first, hist_compact, p0_sums, spec_mode, out, -1, transform);
 }
 int sim_select_f64(const double *x, int64_t n, int64_t k, int maxit, int64_t ft, double theta,
                    int ub, double blo, double bhi, int p0_split, int64_t p0_cap, int hist_bits,
                    int count_first, int hist_compact, int p0_sums, int spec_mode,
-                   SimResult *out) {
+                   int transform, SimResult *out) {
   return sim<double>(x, n, k, maxit, ft, theta, ub, blo, bhi, p0_split, p0_cap, hist_bits,
-                     count_first, hist_compact, p0_sums, spec_mode, out);
+                     count_first, hist_compact, p0_sums, spec_mode, out, -1, transform);
 }
 }

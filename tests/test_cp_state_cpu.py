@@ -37,11 +37,12 @@ def sim(tmp_path_factory):
         fn.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int64,
                        ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                        ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                       ctypes.c_int, ctypes.c_int, ctypes.POINTER(SimResult)]
+                       ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(SimResult)]
         fn.restype = ctypes.c_int
 
     def run(x, k, maxit=64, final_threshold=64, theta=0.5, bracket=None, p0_split=False,
-            p0_cap=None, hist_bits=0, count_first=0, hist_compact=1, p0_sums=1, spec_mode=0):
+            p0_cap=None, hist_bits=0, count_first=0, hist_compact=1, p0_sums=1, spec_mode=0,
+            transform=0):
         r = SimResult()
         fn = L.sim_select_f32 if x.dtype == np.float32 else L.sim_select_f64
         ub = 1 if bracket is not None else 0
@@ -49,7 +50,7 @@ def sim(tmp_path_factory):
         cap = x.size if p0_cap is None else p0_cap
         rc = fn(x.ctypes.data, x.size, k, maxit, final_threshold, theta, ub, blo, bhi,
                 1 if p0_split else 0, cap, hist_bits, count_first, hist_compact, p0_sums,
-                spec_mode, ctypes.byref(r))
+                spec_mode, transform, ctypes.byref(r))
         assert rc == 0, rc
         return r
     return run
@@ -63,7 +64,8 @@ def _check(r, ref, ctx):
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 @pytest.mark.parametrize("dist", ["uniform", "normal", "cauchy", "quantized_normal", "lognormal",
-                                  "mix2", "mix3", "smallint", "outliers", "constant", "permutation"])
+                                  "mix2", "mix3", "smallint", "outliers", "outliers20", "constant",
+                                  "permutation"])
 def test_state_machine_matches_oracle(sim, oracle_mod, dist, dtype):
     for n in (1, 2, 3, 10, 333, 4096, 50_001):
         x = workloads.single_array(dist, n, dtype, seed=n, tag="sim")
@@ -85,7 +87,10 @@ def test_state_machine_matches_oracle(sim, oracle_mod, dist, dtype):
                          dict(hist_bits=3, final_threshold=2, theta=1.0, count_first=1,
                               spec_mode=1),
                          dict(hist_bits=12, final_threshold=4, theta=1.0, count_first=1,
-                              spec_mode=2)):
+                              spec_mode=2),
+                         dict(transform=1, theta=0.0, final_threshold=4),
+                         dict(transform=1, maxit=3, theta=0.0, final_threshold=1),
+                         dict(transform=1, hist_bits=12, theta=1.0, count_first=1)):
                 _check(sim(x, k, **opts), ref, (dist, n, k, opts))
 
 
@@ -249,3 +254,22 @@ def test_count_first_with_likely_interval(sim, oracle_mod, dist):
                    spec_mode=2)
         _check(miss, ref, (dist, k, "miss"))
         assert miss.passes == 3, (dist, k, miss.passes)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_transform_with_huge_outliers(sim, oracle_mod, dtype):
+    """Section 5.3: a few elements near 1e20 make the sums over x lose every other term, and
+    the cutting plane on x degrades towards bisection; on F(x) = log(1 + x - min x) its steps
+    stay informative.  Exact either way; the transform takes fewer passes in total."""
+    tot_plain = tot_log = 0
+    for seed in range(4):
+        x = workloads.single_array("outliers20", 50_001, dtype, seed=seed, tag="sim-outliers")
+        for k in (5_000, 25_001, 45_000):
+            ref = oracle_mod.select_kth(x, k)
+            plain = sim(x, k, theta=0.0, final_threshold=64)
+            logt = sim(x, k, theta=0.0, final_threshold=64, transform=1)
+            _check(plain, ref, ("plain", seed, k))
+            _check(logt, ref, ("log", seed, k))
+            tot_plain += plain.work_passes
+            tot_log += logt.work_passes
+    assert tot_log < tot_plain, (tot_log, tot_plain)

@@ -129,3 +129,45 @@ def test_hot_path_pass_trace(sel, oracle_mod, dtype, schedule):
             if schedule == "cutting_plane":
                 assert n_eval >= 3, (dist, k, n_eval)
         del xt
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("dist", ["outliers20", "normal"])
+def test_transform_pass_trace(sel, oracle_mod, dtype, dist):
+    """The log transform of Section 5.3 (cps_options.transform): every evaluation's A and B are
+    those of F(x) = log(1 + x - min x) at F(t) (the oracle's objective of the transformed
+    array, formed in float64 from the exact widening of x), its counts and neighbours those
+    of x; the selected value and counts are exact."""
+    import paper_1104_2732_amd as cps
+    n = (1 << 22) + 17
+    x = workloads.single_array(dist, n, dtype, seed=5, tag="gpu-transform")
+    xt = torch.from_numpy(x).cuda()
+    F = np.log1p(x.astype(np.float64) - float(x.min()))
+    cp = dict(partition_fraction=0.0, hist_bits=0, final_threshold=4096)
+    for k in (n // 100, (n + 1) // 2):
+        print(f"case transform {dist} n={n} k={k} dtype={x.dtype}", flush=True)
+        ref = oracle_mod.select_kth(x, k)
+        res, st = sel.select_kth(xt, k, options=cps.default_options(transform=1, **cp), stats=True)
+        assert res["status"] == 0 and res["value_bits"] == ref["value_bits"]
+        assert (res["less"], res["equal"]) == (ref["less"], ref["equal"])
+        npass = min(int(st["work_passes"]), cps.STATS_MAX_PASSES)
+        evals = [i for i in range(npass) if st["kind"][i] == cps.PASS_EVAL]
+        assert evals and st["trial"][evals[0]] == x.min()  # F's objective at the ends first
+        ts = np.array([float(st["trial"][i]) for i in evals])
+        us = np.log1p(ts - float(x.min()))
+        ev = oracle_mod.objective(F, k, us)   # sums on F's scale
+        evx = oracle_mod.objective(x, k, ts)  # counts on x
+        for j, i in enumerate(evals):
+            r = ev[j]
+            assert (st["L"][i], st["G"][i]) == (evx[j]["L"], evx[j]["G"]), i
+            assert _close(st["A"][i], r["A"], 1e-12), (i, st["A"][i], r["A"])
+            assert _close(st["B"][i], r["B"], 1e-12), (i, st["B"][i], r["B"])
+        # exact with the default schedule too (the transform only places the trial point)
+        res2 = sel.select_kth(xt, k, options=cps.default_options(transform=1))
+        assert res2["value_bits"] == ref["value_bits"] and res2["less"] == ref["less"]
+        if dist == "outliers20":
+            # (the trajectory is not pinned: the passes are reported, not compared)
+            _, st0 = sel.select_kth(xt, k, options=cps.default_options(**cp), stats=True)
+            print(f"passes with the transform {int(st['work_passes'])}, on x "
+                  f"{int(st0['work_passes'])}", flush=True)
+    del xt

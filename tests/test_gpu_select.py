@@ -40,7 +40,7 @@ def _run(sel, x, k, ctx, **opt):
 
 
 SMALL_DISTS = ["uniform", "normal", "cauchy", "quantized_normal", "lognormal", "mix1", "mix2",
-               "mix3", "mix5", "smallint", "outliers", "beta25", "halfnormal"]
+               "mix3", "mix5", "smallint", "outliers", "outliers20", "beta25", "halfnormal"]
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])

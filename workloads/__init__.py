@@ -82,10 +82,15 @@ def _chunk_values(dist: str, rng: np.random.Generator, m: int, dtype) -> np.ndar
         a = np.abs(rng.standard_normal(m))
         ten = rng.random(m) < 0.1
         return np.where(ten, 10.0, a).astype(dtype)
-    if dist == "outliers":
+    if dist in ("outliers", "outliers20"):
+        # N(0,1) with about 1e-5 of the elements replaced by huge values (Section 5.3: ~1e9,
+        # and ~1e20 where the sums lose precision), at least three of them
         x = rng.standard_normal(m)
         hit = rng.random(m) < 1e-5
-        return np.where(hit, 1e9 * (1.0 + rng.random(m)), x).astype(dtype)
+        hit[:3] = True
+        rng.shuffle(hit)
+        scale = 1e9 if dist == "outliers" else 1e20
+        return np.where(hit, scale * (1.0 + rng.random(m)), x).astype(dtype)
     if dist == "smallint":
         return rng.integers(0, 16, m).astype(dtype)
     raise ValueError(f"unknown distribution {dist!r}")
