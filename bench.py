@@ -172,15 +172,109 @@ def batched_leg(sel, cps, torch, reps: int = 5) -> dict:
                 np.array_equal(res_b["less"], res_p["less"]) and
                 np.array_equal(res_b["equal"], res_p["equal"]) and np.all(res_b["status"] == 0))
     total = int(np.sum(sizes))
+    passes = res_b["passes"].astype(np.float64)
+    # the same batch from [min, max] without the sampled bracket (the paper's start)
+    o_plain = cps.default_batch_options(block_threads=best.block_threads, proposal=0)
+    nobr_ms = _time_ms(torch, lambda: sel.select_kth_batched_async(ptrs, szs, kk, len(dev), code,
+                                                                   out, o_plain), reps)
     del dev
     return {"workload": "4096 lognormal(0,1) float32 arrays, sizes log-uniform in [1e3, 1e6], "
                         "median ranks (one persistent launch, captured in a graph)",
             "elements": total, "graph_ms": graph_ms, "elements_per_s": total / (graph_ms * 1e-3),
+            "alg_GBps_one_read": total * 4 / (graph_ms * 1e-3) / 1e9,
+            "passes_per_array_mean": float(passes.mean()),
+            "passes_per_array_size_weighted": float((passes * sizes).sum() / sizes.sum()),
             "tuned": {"block_threads": best.block_threads, "split_capacity": best.split_capacity,
                       "partition_fraction": best.partition_fraction,
-                      "count_first": best.count_first},
+                      "count_first": best.count_first, "proposal": best.proposal,
+                      "blocks_per_array": best.blocks_per_array,
+                      "elements_per_block": best.elements_per_block},
+            "without_sampled_bracket_ms": nobr_ms,
             "plain_loop_ms": loop_ms, "plain_loop_elements_per_s": total / (loop_ms * 1e-3),
             "speedup_vs_plain": loop_ms / graph_ms, "results_identical": same}
+
+
+def batched_large_leg(sel, cps, torch, reps: int = 5) -> dict:
+    """Few large arrays (64 lognormal float32 arrays of 2^22 elements, median ranks): one
+    workgroup per array leaves most of the chip idle; split over 16 workgroups each they fill
+    it."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(12345)
+    x = torch.exp(torch.randn((64, 1 << 22), generator=g, device="cuda", dtype=torch.float32))
+    dev = [x[i] for i in range(64)]
+    ks = [((1 << 22) + 1) // 2] * 64
+    ptrs, szs, kk, code = sel.batch_descriptors(dev, ks)
+    out = sel.new_results(64)
+    cases = {"one_workgroup_per_array": dict(),
+             "16_workgroups_per_array": dict(blocks_per_array=16, elements_per_block=1 << 18),
+             "without_sampled_bracket": dict(proposal=0)}
+    res = {}
+    ref = None
+    for name, kw in cases.items():
+        o = cps.default_batch_options(**kw)
+        ms = _time_ms(torch, lambda: sel.select_kth_batched_async(ptrs, szs, kk, 64, code, out, o), reps)
+        r = out.cpu().numpy().view(cps.RESULT_DTYPE).copy()
+        ref = r if ref is None else ref
+        res[name] = {"ms": round(ms, 4), "elements_per_s": 64 * (1 << 22) / (ms * 1e-3),
+                     "identical": bool(np.array_equal(r["value_bits"], ref["value_bits"]))}
+    del x, dev
+    return {"workload": "64 lognormal(0,1) float32 arrays of 2^22 elements, median ranks",
+            "cases": res}
+
+
+def lts_knn_leg(sel, torch, reps: int = 5) -> dict:
+    """Section 6's other uses of the k-th order statistic: least trimmed squares at the
+    least-median-of-squares shape, and k nearest neighbours."""
+    import workloads
+    n, p, m = 1 << 20, 8, 1024
+    X, y, _, betas = workloads.lms_problem(n, p, m, seed=0)
+    Xd, yd, bd = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (X, y, betas))
+    import paper_1104_2732_amd as cps
+    out = torch.empty(m * cps.TRIM_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    lts_ms = _time_ms(torch, lambda: sel.lts_trimmed_sq_async(Xd, yd, bd, (n + 1) // 2, out), reps)
+    del Xd, yd, bd
+    nk, dim, nq, k = 1 << 20, 8, 1024, 64
+    rng = np.random.default_rng(0)
+    P = rng.standard_normal((nk, dim)).astype(np.float32)
+    Q = rng.standard_normal((nq, dim)).astype(np.float32)
+    f = (np.sin(P.sum(axis=1)) + 0.1 * rng.standard_normal(nk)).astype(np.float32)
+    Pd, fd, Qd = (torch.from_numpy(a).cuda() for a in (P, f, Q))
+    kout = torch.empty(nq * cps.KNN_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    knn_ms = _time_ms(torch, lambda: sel.knn_mean_async(Pd, fd, Qd, k, kout), reps)
+    return {"lts": {"workload": "n=2^20 rows, p=8, 1024 candidates, h=floor((n+1)/2)",
+                    "ms": lts_ms, "residuals_per_s": n * m / (lts_ms * 1e-3)},
+            "knn": {"workload": "2^20 points in 8 dimensions (N(0,1)), 1024 queries, k=64",
+                    "ms": knn_ms, "distances_per_s": nk * nq / (knn_ms * 1e-3)}}
+
+
+def transform_leg(sel, cps, torch, reps: int = 3) -> dict:
+    """Section 5.3's outliers: 2^26 float32 N(0,1) values with 64 of them near 1e20, the
+    cutting plane to the end on x and on F(x) = log(1 + x - min x)."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(777)
+    n = 1 << 26
+    x = torch.randn(n, generator=g, device="cuda", dtype=torch.float32)
+    idx = torch.randint(0, n, (64,), generator=g, device="cuda")
+    x[idx] = 1e20 * (1.0 + torch.rand(64, generator=g, device="cuda"))
+    res = sel.new_results(1)
+    stats = sel.new_stats()
+    out = {"workload": "n=2^26 float32 N(0,1) with 64 values near 1e20, median rank", "cases": {}}
+    for name, kw in {"cutting_plane_on_x": dict(partition_fraction=0.0, hist_bits=0),
+                     "cutting_plane_on_log": dict(partition_fraction=0.0, hist_bits=0, transform=1),
+                     "default_on_x": dict(), "default_on_log": dict(transform=1)}.items():
+        o = cps.default_options(**kw)
+        k = (n + 1) // 2
+        ms = _time_ms(torch, lambda: sel.select_kth_async(x, k, res, options=o), reps)
+        sel.select_kth_async(x, k, res, stats, options=o)
+        torch.cuda.synchronize()
+        st = stats.cpu().numpy().view(cps.STATS_DTYPE)[0]
+        out["cases"][name] = {"ms": round(ms, 4), "work_passes": int(st["work_passes"]),
+                              "kelley_steps": int(st["kelley_steps"]),
+                              "value_bits": int(res.cpu().numpy().view(cps.RESULT_DTYPE)[0]["value_bits"])}
+    vals = {c["value_bits"] for c in out["cases"].values()}
+    out["results_identical"] = len(vals) == 1
+    del x
+    return out
 
 
 def lms_leg(sel, torch, reps: int = 5) -> dict:
@@ -195,50 +289,75 @@ def lms_leg(sel, torch, reps: int = 5) -> dict:
             "ms": ms, "residuals_per_s": n * m / (ms * 1e-3)}
 
 
-def learned_leg(sel, cps, torch, reps: int = 5) -> dict:
+def learned_leg(sel, cps, torch, held_out: int = 128, chunk: int = 8) -> dict:
     """The learned proposal on held-out float32 mixture arrays of n = 2^26 with uniform ranks,
-    against the plain method on the same arrays (training untimed)."""
+    against the plain method and the non-learned sample-quantile proposal on the same arrays
+    (training untimed).  Arrays are generated on the device in chunks; every call is timed on
+    its own with events on the launch stream (the mean of three runs)."""
     P = sel.new_params()
     t0 = time.time()
     rep = sel.mlp_train(P, seed=1, n_arrays=100_000, array_size=1 << 18, epochs=EPOCHS,
                         batch=256, lr=2e-3, holdout=4096, holdout_seed=2)
     train_s = time.time() - t0
-    n, count = 1 << 26, 8
-    x, ks = sel.mixture_generate(3, 0, count, n)
-    ks = [int(v) for v in ks.cpu().numpy()]
-    rows = [x[a] for a in range(count)]
+    n = 1 << 26
     sel.reserve(n, cps.CPS_F32)
-    out_p, out_l = sel.new_results(count), sel.new_results(count)
-    vp = [out_p[i * 48:(i + 1) * 48] for i in range(count)]
-    vl = [out_l[i * 48:(i + 1) * 48] for i in range(count)]
-    plain_ms = _time_ms(torch, lambda: [sel.select_kth_async(r, k, o) for r, k, o in
-                                        zip(rows, ks, vp)], reps) / count
-    learned_ms = _time_ms(torch, lambda: [sel.select_kth_learned_async(r, k, P, o) for r, k, o in
-                                          zip(rows, ks, vl)], reps) / count
-    out_s = sel.new_results(count)
-    vs = [out_s[i * 48:(i + 1) * 48] for i in range(count)]
-    sampled_ms = _time_ms(torch, lambda: [sel.select_kth_sampled_async(r, k, o, 4.0) for r, k, o in
-                                          zip(rows, ks, vs)], reps) / count
-    rp = out_p.cpu().numpy().view(cps.RESULT_DTYPE)
-    rl = out_l.cpu().numpy().view(cps.RESULT_DTYPE)
-    rs = out_s.cpu().numpy().view(cps.RESULT_DTYPE)
-    same = all(bool(np.array_equal(rp[f], r[f])) for r in (rl, rs)
-               for f in ("value_bits", "less", "equal"))
-    del x, rows
-    return {"workload": "8 held-out mixture arrays (1-4 Gaussian/lognormal/uniform components), "
-                        "float32, n=2^26, k uniform in [1, n]",
-            "plain_ms_per_call": plain_ms, "learned_ms_per_call": learned_ms,
-            "speedup_vs_plain": plain_ms / learned_ms,
-            "plain_passes_over_x": float(np.mean(rp["passes"])),
-            "learned_passes_over_x": float(np.mean(rl["passes"])),
-            "sampled_ms_per_call": sampled_ms,
-            "sampled_passes_over_x": float(np.mean(rs["passes"])),
-            "sampled_note": "non-learned baseline: sorted stride sample, +-4 sd of the sample rank",
-            "results_identical": same, "train_s": round(train_s, 2),
-            "train": {"arrays": 100_000, "array_size": 1 << 18, "epochs": EPOCHS,
-                      "first_loss": rep["first_loss"], "final_loss": rep["final_loss"],
-                      "holdout_coverage": rep["holdout_coverage"],
-                      "holdout_width": rep["holdout_width"]}}
+    names = ("plain", "learned", "sampled")
+    ms = {k: [] for k in names}
+    passes = {k: [] for k in names}
+    same = True
+    outs = {k: sel.new_results(1) for k in names}
+    stream = torch.cuda.current_stream()
+
+    def call(name, row, k):
+        if name == "plain":
+            sel.select_kth_async(row, k, outs[name])
+        elif name == "learned":
+            sel.select_kth_learned_async(row, k, P, outs[name])
+        else:
+            sel.select_kth_sampled_async(row, k, outs[name], 4.0)
+
+    for c0 in range(0, held_out, chunk):
+        x, ks = sel.mixture_generate(3, c0, chunk, n)
+        ks = [int(v) for v in ks.cpu().numpy()]
+        for a in range(chunk):
+            row, k = x[a], ks[a]
+            bits = set()
+            for name in names:
+                call(name, row, k)  # warm
+                ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                      for _ in range(3)]
+                for e0, e1 in ev:
+                    e0.record(stream)
+                    call(name, row, k)
+                    e1.record(stream)
+                torch.cuda.synchronize()
+                ms[name].append(float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev])))
+                r = outs[name].cpu().numpy().view(cps.RESULT_DTYPE)[0]
+                passes[name].append(int(r["passes"]))
+                bits.add((int(r["value_bits"]), int(r["less"]), int(r["equal"]), int(r["status"])))
+            same &= len(bits) == 1
+        del x
+    out = {"workload": f"{held_out} held-out mixture arrays (1-4 Gaussian/lognormal/uniform "
+                       "components), float32, n=2^26, k uniform in [1, n]",
+           "results_identical": bool(same)}
+    for name in names:
+        a, p = np.array(ms[name]), np.array(passes[name])
+        out[name] = {"ms_mean": round(float(a.mean()), 4), "ms_median": round(float(np.median(a)), 4),
+                     "passes_over_x_mean": float(p.mean()),
+                     "passes_over_x_median": float(np.median(p))}
+    t_plain, t_learned, t_sampled = (np.array(ms[k]) for k in names)
+    out["learned_faster_than_plain"] = int(np.sum(t_learned < t_plain))
+    out["learned_faster_than_sampled"] = int(np.sum(t_learned < t_sampled))
+    out["learned_fewer_reads_than_sampled"] = int(np.sum(np.array(passes["learned"]) <
+                                                         np.array(passes["sampled"])))
+    out["speedup_vs_plain"] = float(t_plain.mean() / t_learned.mean())
+    out["sampled_note"] = "non-learned baseline: sorted stride sample, +-4 sd of the sample rank"
+    out["train_s"] = round(train_s, 2)
+    out["train"] = {"arrays": 100_000, "array_size": 1 << 18, "epochs": EPOCHS,
+                    "first_loss": rep["first_loss"], "final_loss": rep["final_loss"],
+                    "holdout_coverage": rep["holdout_coverage"],
+                    "holdout_width": rep["holdout_width"]}
+    return out
 
 
 def schedules_leg(sel, cps, torch, reps: int = 3) -> dict:
@@ -559,7 +678,13 @@ def main():
         torch.cuda.empty_cache()
         line["batched"] = batched_leg(sel, cps, torch)
         torch.cuda.empty_cache()
+        line["batched_large"] = batched_large_leg(sel, cps, torch)
+        torch.cuda.empty_cache()
         line["lms"] = lms_leg(sel, torch)
+        torch.cuda.empty_cache()
+        line.update(lts_knn_leg(sel, torch))
+        torch.cuda.empty_cache()
+        line["transform"] = transform_leg(sel, cps, torch)
         torch.cuda.empty_cache()
         line["learned"] = learned_leg(sel, cps, torch)
         torch.cuda.empty_cache()

@@ -135,7 +135,9 @@ typedef struct cps_eval {
  *                   (~1e20, where the sums over x lose every smaller term): one evaluation
  *                   at the minimum forms F's objective at both ends, then every trial point is
  *                   Kelley's step on F's scale mapped back by F^-1, and every evaluation sums
- *                   F(x) in double precision; counts, comparisons and the result stay on x
+ *                   F(x) (formed to float precision: the exact exponent of 1 + x - min x and
+ *                   the hardware base-2 logarithm of its mantissa) in double precision;
+ *                   counts, comparisons and the result stay on x
  *                   (exact whatever F rounds).  Runs without splits (count_first is then
  *                   forced on when hist_bits > 0, and partition_fraction to 0 when it is 0);
  *                   not with use_bracket or a proposal.  0 (default): the objective of x. */

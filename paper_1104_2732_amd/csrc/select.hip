@@ -393,9 +393,20 @@ __device__ inline void eval_tile(const Span<T> &sp, int64_t base, int per_u, int
   }
 }
 
+// F(x) = log(1 + d), d = x - min x >= 0, to float precision: the exponent of 1 + d taken
+// exactly and the hardware base-2 logarithm of its mantissa (the transformed scale only
+// places trial points, so a relative error of ~1e-7 costs nothing in exactness, and the
+// library logarithm's registers would spill the streaming loop).
+__device__ inline double fast_log1p(double d) {
+  int e;
+  const double m = frexp(1.0 + d, &e);  // 1 + d = m 2^e, m in [1/2, 1)
+  return 0.6931471805599453 * ((double)e + (double)__builtin_amdgcn_logf((float)m));
+}
+
 // An evaluation pass on the transformed scale (CpConfig::transform): the counts below and
-// above t and t's neighbours on x, the sums A and B on F(x) = log(1 + x - xmin) (double
-// precision; with CLAMP, infinities first clamped to the finite extremes).  Ft = F(t).
+// above t and t's neighbours on x, the sums A and B on F(x) = log(1 + x - xmin) (fast_log1p,
+// summed in double precision; with CLAMP, infinities first clamped to the finite extremes).
+// Ft = F(t).
 template <typename T, int BLOCK, int U, bool CLAMP>
 __device__ inline void eval_pass_log(const Walk<T> &wk, T t, double xmin, double Ft, T fmin,
                                      T fmax, EvalAcc<T> &acc) {
@@ -407,7 +418,7 @@ __device__ inline void eval_pass_log(const Walk<T> &wk, T t, double xmin, double
     if (CLAMP) v = tmin(tmax(v, fmin), fmax);
     const bool l = valid && (v < t);
     const bool g = valid && (v > t);
-    const double F = log1p((double)v - xmin);
+    const double F = fast_log1p((double)v - xmin);
     acc.A += g ? F - Ft : 0.0;
     acc.B += l ? Ft - F : 0.0;
     acc.pred = tmax(acc.pred, l ? v : -t_inf<T>());
@@ -1200,7 +1211,7 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
       }
     } else if (!s.split) {
       if (s.tf) {  // the transformed scale (x is the working set: no splits with the transform)
-        const double Ft = log1p(s.t - s.fmin);
+        const double Ft = fast_log1p(s.t - s.fmin);
         if (clamp) eval_pass_log<T, BLOCK, SU, true>(wk, t, s.fmin, Ft, fmn, fmx, acc);
         else eval_pass_log<T, BLOCK, SU, false>(wk, t, s.fmin, Ft, fmn, fmx, acc);
       } else if (clamp) {
