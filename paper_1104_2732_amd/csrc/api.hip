@@ -52,11 +52,12 @@ namespace {
 // partials, two split buffers (one region of seg_R elements per workgroup each) and the
 // gather buffer.
 struct SelectLayout {
-  size_t st, sync, gh, sd, si, z0, z1, zf, total;
-  int64_t slot_stride, seg_R, zcap;
+  size_t st, sync, gh, sd, si, z0, z1, zf, sm, total;
+  int64_t slot_stride, seg_R, zcap, smp_n;
 };
 
-SelectLayout select_layout(int64_t seg_R, int grid, int64_t zcap, int gmax, size_t esize) {
+SelectLayout select_layout(int64_t seg_R, int grid, int64_t zcap, int gmax, size_t esize,
+                           int64_t smp_n = 0) {
   SelectLayout L;
   size_t off = 0;
   L.st = off;
@@ -79,8 +80,21 @@ SelectLayout select_layout(int64_t seg_R, int grid, int64_t zcap, int gmax, size
   L.zcap = zcap;
   L.zf = off;
   off = align_up(off + (size_t)zcap * esize, 256);
+  L.smp_n = smp_n;
+  L.sm = off;
+  off = align_up(off + (size_t)smp_n * esize, 256);
   L.total = off;
   return L;
+}
+
+// Elements of pass 0's sample for the likely interval: one 16-byte vector per tile of x, when
+// the input is large enough for the counting evaluation's copy (0 otherwise).
+int64_t spec_sample_elems(int64_t n, size_t esize, int64_t spec_min_n) {
+  if (spec_min_n <= 0 || n < spec_min_n) return 0;
+  const int64_t vec = 16 / (int64_t)esize;
+  const int64_t tile = (int64_t)cps::kSelectBlock * cps::kSelectUnroll;  // vectors per tile
+  const int64_t tiles = (n / vec + tile - 1) / tile;
+  return (tiles < 1 ? 1 : tiles) * vec;
 }
 
 // Grow a workspace buffer to at least `bytes`.  The synchronisation words at the start of
@@ -233,7 +247,8 @@ int run_select(cps_handle *h, const T *x, int64_t n, int64_t k, const cps_option
   int rc = resolve(h, n, sizeof(T) == 4 ? CPS_F32 : CPS_F64, opt, r);
   if (rc) return rc;
   const int per_cu = sizeof(T) == 4 ? h->max_blocks_f32 : h->max_blocks_f64;
-  const SelectLayout L = select_layout(r.seg_R, r.grid, r.cfg.zcap, h->cu_count * per_cu, sizeof(T));
+  const SelectLayout L = select_layout(r.seg_R, r.grid, r.cfg.zcap, h->cu_count * per_cu, sizeof(T),
+                                       spec_sample_elems(n, sizeof(T), r.cfg.spec_min_n));
   rc = ensure_workspace(h, L.total, stream);
   if (rc) return rc;
   char *base = (char *)h->ws;
@@ -264,6 +279,8 @@ int run_select(cps_handle *h, const T *x, int64_t n, int64_t k, const cps_option
   if (proposal && r.cfg.transform) return CPS_EINVAL;
   a.p0_cap = (proposal && r.compact_proposal) ? L.seg_R / 2 : 0;
   a.ghist = (uint64_t *)(base + L.gh);
+  a.smp = L.smp_n > 0 ? (T *)(base + L.sm) : nullptr;
+  a.smp_n = L.smp_n;
   hipError_t e = cps::launch_select<T>(a, r.grid, stream);
   if (e != hipSuccess) return hip_fail(e);
   return CPS_OK;
@@ -727,7 +744,8 @@ int cps_reserve(cps_handle *h, int64_t n, int dtype) {
   if (rc) return rc;
   const int per_cu = dtype == CPS_F32 ? h->max_blocks_f32 : h->max_blocks_f64;
   const SelectLayout L =
-      select_layout(r.seg_R, r.grid, r.cfg.zcap, h->cu_count * per_cu, dtype_size(dtype));
+      select_layout(r.seg_R, r.grid, r.cfg.zcap, h->cu_count * per_cu, dtype_size(dtype),
+                    spec_sample_elems(n, dtype_size(dtype), r.cfg.spec_min_n));
   return ensure_workspace(h, L.total, nullptr);
 }
 
@@ -797,6 +815,8 @@ int select_kth_noalloc(cps_handle *h, const void *x, int64_t n, int64_t k, int d
     a.p0_cap = 0;
     a.ghist = (uint64_t *)(base + L.gh);
     a.phist = nullptr;
+    a.smp = nullptr;
+    a.smp_n = 0;
     return cps::launch_select<T>(a, r.grid, s);
   };
   e = dtype == CPS_F32 ? fill((const float *)x) : fill((const double *)x);

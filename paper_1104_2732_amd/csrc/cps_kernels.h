@@ -71,6 +71,9 @@ template <typename T> struct SelectArgs {
                        // first kHistMaxBins, a split pass that counts its parts both halves
   uint64_t *phist;     // kHistMaxBins counters, zeroed by the proposal kernel before this
                        // launch: pass 0 counts a proposal's interior in them (or null)
+  T *smp;              // pass 0's sample for the likely interval: the first vector of every
+                       // tile of x (smp_n elements), or null
+  int64_t smp_n;
 };
 
 // ---- batched selection

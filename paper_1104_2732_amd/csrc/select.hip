@@ -490,10 +490,12 @@ __device__ inline void eval_pass(const Walk<T> &wk, T t, T yL, T yR, T fmin, T f
   if (SPEC) drain_inside<T>(o, lane, o.top + 1);
 }
 
-template <typename T, int U, bool CLASSIFY, bool BRACKET, bool SPLIT, bool HIST, bool FULL>
+template <typename T, int U, bool CLASSIFY, bool BRACKET, bool SPLIT, bool HIST, bool FULL,
+          bool SAMPLE = false>
 __device__ inline void pass0_tile(const Span<T> &sp, int64_t base, int per_u, int me, T ba, T bb,
                                   P0Acc<T> &acc, WaveOut<T> &o, uint32_t cap,
-                                  const InteriorBins<T> &ib) {
+                                  const InteriorBins<T> &ib,
+                                  CPS_GLOBAL typename Traits<T>::Vec *smp, int64_t tile) {
   constexpr int V = Traits<T>::kVec;
   using Vec = typename Traits<T>::Vec;
   Vec raw[U];
@@ -555,22 +557,28 @@ __device__ inline void pass0_tile(const Span<T> &sp, int64_t base, int per_u, in
       acc.Bb += (double)bB;
     }
   }
+  // the sample of the likely interval: every tile's first vector (its first thread's)
+  if (SAMPLE && me == 0) smp[tile] = raw[0];
 }
 
 template <typename T, int BLOCK, int U, bool CLASSIFY, bool BRACKET, bool SPLIT, bool HIST = false>
 __device__ inline void pass0(const Walk<T> &wk, T ba, T bb, P0Acc<T> &acc, WaveOut<T> &o,
-                             uint32_t cap, const InteriorBins<T> &ib) {
+                             uint32_t cap, const InteriorBins<T> &ib,
+                             CPS_GLOBAL typename Traits<T>::Vec *smp = nullptr) {
   const int tid = threadIdx.x, lane = tid % kWave;
   const Span<T> &sp = wk.sp;
   const int64_t step_vecs = (int64_t)BLOCK * U;
-  for (int64_t base = (int64_t)blockIdx.x * step_vecs; base < sp.nvec;
-       base += (int64_t)gridDim.x * step_vecs) {
-    if (base + step_vecs <= sp.nvec)
-      pass0_tile<T, U, CLASSIFY, BRACKET, SPLIT, HIST, true>(sp, base, BLOCK, tid, ba, bb, acc, o,
-                                                             cap, ib);
-    else
+  for (int64_t base = (int64_t)blockIdx.x * step_vecs, tile = blockIdx.x; base < sp.nvec;
+       base += (int64_t)gridDim.x * step_vecs, tile += gridDim.x) {
+    if (base + step_vecs > sp.nvec)
       pass0_tile<T, U, CLASSIFY, BRACKET, SPLIT, HIST, false>(sp, base, BLOCK, tid, ba, bb, acc, o,
-                                                              cap, ib);
+                                                              cap, ib, smp, tile);
+    else if (!CLASSIFY && !BRACKET && smp)
+      pass0_tile<T, U, CLASSIFY, BRACKET, SPLIT, HIST, true, true>(sp, base, BLOCK, tid, ba, bb,
+                                                                   acc, o, cap, ib, smp, tile);
+    else
+      pass0_tile<T, U, CLASSIFY, BRACKET, SPLIT, HIST, true>(sp, base, BLOCK, tid, ba, bb, acc, o,
+                                                             cap, ib, smp, tile);
   }
   if (sp.nedge > 0 && wk.edge_owner && tid < kWave) {
     const bool have = lane < sp.nedge;
@@ -923,17 +931,16 @@ __device__ __noinline__ int64_t gather_filtered(Walk<T> wk, T yL, T yR, int64_t 
 }
 
 // The likely interval of a counting evaluation's copy, by the whole last workgroup after pass
-// 0: kSpecSample elements (runs of kSpecRun neighbours at evenly spaced places, so that the
-// sample touches few pages) in the key bins of the bracket's range, then the bins of
+// 0: the sample every workgroup stored during pass 0 (the first 16-byte vector of each tile of
+// the input: 4 or 2 neighbours every 16384 or 8192 elements, 64K elements at 2^28) in the key
+// bins of the bracket's range, then the bins of
 // the sample ranks q -/+ d around the rank's place q = p m among the m sampled elements
 // inside the bracket (p = (k - cL - 1/2) / (cR - cL), d = 4 sqrt(m p (1 - p)) + 2, four
 // binomial standard deviations).  The interval runs from the first key of the lower bin to
 // the last key of the upper one; with too few sampled elements nothing is set.
-constexpr int64_t kSpecSample = 4096;
-constexpr int64_t kSpecRun = 16;
 
 template <typename T, int BLOCK>
-__device__ __noinline__ void spec_interval(const T *x, int64_t n, const CpConfig &c,
+__device__ __noinline__ void spec_interval(const T *smp, int64_t nsmp, const CpConfig &c,
                                            Shared<T, BLOCK> &sh) {
   using Key = typename Traits<T>::Key;
   const int tid = threadIdx.x;
@@ -941,12 +948,26 @@ __device__ __noinline__ void spec_interval(const T *x, int64_t n, const CpConfig
   const HistGeom<uint64_t> g = hist_geometry(s.lo, s.hi, c.dtype, c.hist_bits);
   for (int b = tid; b < g.nbins; b += BLOCK) sh.rh[b] = 0u;
   __syncthreads();
-  // (spec_min_n is far above kSpecSample: every run lies inside x)
-  const int64_t runs = kSpecSample / kSpecRun, stride = n / runs;
   const Key klo = (Key)g.klo, khi = (Key)g.khi;
-  for (int64_t i = tid; i < kSpecSample; i += BLOCK) {
-    const Key K = Traits<T>::key(x[(i / kSpecRun) * stride + i % kSpecRun]);
-    if (K >= klo && K <= khi) atomicAdd(&sh.rh[(uint32_t)((K - klo) >> g.shift)], 1u);
+  // eight 16-byte loads in flight per thread, then their keys into the bins
+  using Vec = typename Traits<T>::Vec;
+  constexpr int V = Traits<T>::kVec, R = 8;
+  const Vec *sv = (const Vec *)smp;
+  const int64_t nv = nsmp / V;
+  for (int64_t i0 = tid; i0 < nv; i0 += (int64_t)BLOCK * R) {
+    Vec w[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (i0 + (int64_t)r * BLOCK < nv) w[r] = sv[i0 + (int64_t)r * BLOCK];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (i0 + (int64_t)r * BLOCK >= nv) break;
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        const Key K = Traits<T>::key(w[r][j]);
+        if (K >= klo && K <= khi) atomicAdd(&sh.rh[(uint32_t)((K - klo) >> g.shift)], 1u);
+      }
+    }
   }
   __syncthreads();
   constexpr int BPT = kHistMaxBins / BLOCK;
@@ -1050,7 +1071,8 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
       if (p0h) pass0<T, BLOCK, UNROLL, false, true, true, true>(wk, ba, bb, acc, o, cap, ib);
       else if (p0s) pass0<T, BLOCK, SU, false, true, true>(wk, ba, bb, acc, o, cap, ib);
       else if (use_br) pass0<T, BLOCK, SU, false, true, false>(wk, ba, bb, acc, o, cap, ib);
-      else pass0<T, BLOCK, UNROLL, false, false, false>(wk, ba, bb, acc, o, cap, ib);
+      else pass0<T, BLOCK, UNROLL, false, false, false>(wk, ba, bb, acc, o, cap, ib,
+                                                        (CPS_GLOBAL typename Traits<T>::Vec *)a.smp);
     } else {
       if (p0s) pass0<T, BLOCK, SU, true, true, true>(wk, ba, bb, acc, o, cap, ib);
       else if (use_br) pass0<T, BLOCK, SU, true, true, false>(wk, ba, bb, acc, o, cap, ib);
@@ -1378,9 +1400,9 @@ __device__ __noinline__ void last_update(const SelectArgs<T> &a, Shared<T, BLOCK
     }
     // a large input about to be counted from: the likely interval for the evaluation's copy
     __syncthreads();
-    if (a.cfg.spec_min_n > 0 && a.n >= a.cfg.spec_min_n && a.seg_R > 0 &&
+    if (a.cfg.spec_min_n > 0 && a.n >= a.cfg.spec_min_n && a.seg_R > 0 && a.smp &&
         sh.st.phase == PH_EVAL && sh.st.counted && sh.st.wbuf < 0)
-      spec_interval<T, BLOCK>(a.x, a.n, a.cfg, sh);
+      spec_interval<T, BLOCK>(a.smp, a.smp_n, a.cfg, sh);
   } else if (phase == PH_HIST) {
     const CpState &s0 = sh.st;
     const HistGeom<uint64_t> g = hist_geometry(s0.lo, s0.hi, a.cfg.dtype, a.cfg.hist_bits);
