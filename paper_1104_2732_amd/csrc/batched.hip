@@ -61,6 +61,15 @@ template <typename T, int BLOCK> struct BShared {
   uint64_t order[kBatchSortMax];  // (size << 12 | index) sorted by size, largest first; then
                                   // item_entry(first work item, index) per slot
   uint32_t rh[kHistMaxBins];      // key histogram of a histogram pass
+  // The state machine's arguments, built by thread 0 in LDS: as private variables whose
+  // address a call takes they would sit in scratch memory, and the compiler may write them
+  // there from every lane.
+  CpConfig cfg;        // the launch's configuration
+  CpConfig cfg_arg;    // a per-call variant of it (the sampled bracket, the sides' bins)
+  Pass0Result p0r;
+  EvalResult evr;
+  HistGeom<uint64_t> hg;
+  HistGeom<uint64_t> pg[2];  // the two sides' bins of a counting evaluation
 };
 
 // The passes load with the nontemporal hint, as the single-array kernel's (each line is read
@@ -695,7 +704,8 @@ __device__ __noinline__ bool prop_pass0(const T *x, int64_t n, int64_t k, T pa, 
     written = sh.cur[0] * Traits<T>::kVec;
   }
   if (tid == 0) {
-    Pass0Result r = {};
+    Pass0Result &r = sh.p0r;
+    r = Pass0Result{};
     r.classified = 0;
     r.sums = 0;  // only the counts at the ends were formed: an adopted bracket ends by histograms
     r.sum = iv[1] > 0 ? __builtin_nan("") : 0.0;  // (NaN: repeat with the classification)
@@ -716,7 +726,8 @@ __device__ __noinline__ bool prop_pass0(const T *x, int64_t n, int64_t k, T pa, 
     st.n = n;
     st.k = k;
     st.phase = PH_PASS0;
-    CpConfig c = a.cfg;
+    CpConfig &c = sh.cfg_arg;
+    c = sh.cfg;
     c.use_bracket = 1;
     c.bracket_lo = (double)pa;
     c.bracket_hi = (double)pb;
@@ -732,8 +743,9 @@ __device__ __noinline__ bool prop_pass0(const T *x, int64_t n, int64_t k, T pa, 
       block_pick<T, BLOCK>(sh.rh, g.nbins, (uint64_t)(s1.k - s1.cL), sh);
       if (tid == 0) {
         const int32_t bsel = (int32_t)sh.misc[0];
-        bdev_hist_narrow(sh.st, g, bsel, bsel < 0 ? 0 : sh.misc[1], bsel < 0 ? 0 : sh.misc[2],
-                         a.cfg);
+        sh.hg = g;
+        bdev_hist_narrow(sh.st, sh.hg, bsel, bsel < 0 ? 0 : sh.misc[1],
+                         bsel < 0 ? 0 : sh.misc[2], sh.cfg);
       }
       __syncthreads();
     }
@@ -788,8 +800,10 @@ __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out, do
   const int tid = threadIdx.x;
   constexpr int SU = U / 2 > 0 ? U / 2 : 1;
   const int64_t cap = a.cap;
-  CPS_GLOBAL T *zb[2] = {(CPS_GLOBAL T *)(a.zbuf + (int64_t)blockIdx.x * a.ws_stride),
-                         (CPS_GLOBAL T *)(a.zbuf + (int64_t)blockIdx.x * a.ws_stride + cap)};
+  // the two split buffers, as two scalars: a private array indexed by the state's buffer
+  // number would live in scratch memory, written by every lane on every pass
+  CPS_GLOBAL T *zb0 = (CPS_GLOBAL T *)(a.zbuf + (int64_t)blockIdx.x * a.ws_stride);
+  CPS_GLOBAL T *const zb1 = (CPS_GLOBAL T *)(a.zbuf + (int64_t)blockIdx.x * a.ws_stride + cap);
   CPS_GLOBAL T *gb = (CPS_GLOBAL T *)(a.zbuf + (int64_t)blockIdx.x * a.ws_stride + a.gb_off);
   if (!batch_array_valid((uint64_t)(uintptr_t)x, n, k, (uint32_t)sizeof(T))) {
     if (tid == 0 && part == 0) {
@@ -808,11 +822,11 @@ __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out, do
     if (!prop && part > 0) return;  // no bracket: the first part runs the array alone
     if (prop) {
       TeamCtl *tc = parts > 1 ? a.teams + slot : nullptr;
-      CPS_GLOBAL T *ibuf = parts > 1 ? (CPS_GLOBAL T *)(a.tbuf + slot * a.team_cap) : zb[0];
+      CPS_GLOBAL T *ibuf = parts > 1 ? (CPS_GLOBAL T *)(a.tbuf + slot * a.team_cap) : zb0;
       if (!prop_pass0<T, BLOCK, U>(x, n, k, pa, pb, part, parts, tc, ibuf, parts > 1 ? a.team_cap : cap,
                                    a, sh))
         return;
-      zb[0] = ibuf;  // the interior's elements are the working set from here on
+      zb0 = ibuf;  // the interior's elements are the working set from here on
       if (tid == 0) {
         sh.kpa = (double)pa;
         sh.kpb = (double)pb;
@@ -844,7 +858,8 @@ __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out, do
     int dop[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     block_reduce<BLOCK, 1, 3>(dv, dop, iv, false, sh.d, sh.i);
     if (tid == 0) {
-      Pass0Result r = {};
+      Pass0Result &r = sh.p0r;
+      r = Pass0Result{};
       r.classified = slow ? 1 : 0;
       r.sums = 1;
       r.sum = dv[0];
@@ -862,7 +877,7 @@ __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out, do
         s.k = k;
       }
       s.phase = PH_PASS0;
-      bdev_after_pass0(s, r, a.cfg);
+      bdev_after_pass0(s, r, sh.cfg);
     }
     __syncthreads();
     if (sh.st.phase == PH_PASS0 && sh.st.p0_slow && !slow) {
@@ -877,7 +892,7 @@ __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out, do
     const T *W;
     if (s.wbuf < 0) W = x;
     else if (s.wbuf == 2) W = (const T *)gb;
-    else W = (const T *)zb[s.wbuf] + (s.side == 0 ? 0 : cap - s.wlen);
+    else W = (const T *)(s.wbuf == 0 ? zb0 : zb1) + (s.side == 0 ? 0 : cap - s.wlen);
     const Span<T> sp = make_span(W, s.wbuf < 0 ? n : s.wlen);
     if (s.phase == PH_HIST) {
       // key histogram of the compacted bracket in LDS, then the bin holding rank k - cL
@@ -890,7 +905,7 @@ __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out, do
       block_pick<T, BLOCK>(sh.rh, g.nbins, (uint64_t)(s.k - s.cL), sh);
       if (tid == 0) {
         const int32_t bsel = (int32_t)sh.misc[0];
-        bdev_after_hist(sh.st, bsel, bsel < 0 ? 0 : sh.misc[1], bsel < 0 ? 0 : sh.misc[2], a.cfg);
+        bdev_after_hist(sh.st, bsel, bsel < 0 ? 0 : sh.misc[1], bsel < 0 ? 0 : sh.misc[2], sh.cfg);
       }
       __syncthreads();
       continue;
@@ -905,14 +920,20 @@ __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out, do
       // bracket to the bin of the rank on the side that holds it
       CpConfig cs = a.cfg;
       cs.hist_bits = a.cfg.hist_bits > kBatchSideBits ? kBatchSideBits : a.cfg.hist_bits;
-      HistGeom<uint64_t> pg[2];
+      const HistGeom<uint64_t> pg0 = split_part_geometry(s, 0, cs);
+      const HistGeom<uint64_t> pg1 = split_part_geometry(s, 1, cs);
       SideBins<T> sb;
-      for (int p = 0; p < 2; ++p) {
-        pg[p] = split_part_geometry(s, p, cs);
-        sb.klo[p] = (typename Traits<T>::Key)pg[p].klo;
-        sb.has[p] = pg[p].nbins > 0;
-        sb.span[p] = pg[p].nbins > 0 ? (typename Traits<T>::Key)(pg[p].khi - pg[p].klo) : 0;
-        sb.shift[p] = pg[p].shift;
+      sb.klo[0] = (typename Traits<T>::Key)pg0.klo;
+      sb.has[0] = pg0.nbins > 0;
+      sb.span[0] = pg0.nbins > 0 ? (typename Traits<T>::Key)(pg0.khi - pg0.klo) : 0;
+      sb.shift[0] = pg0.shift;
+      sb.klo[1] = (typename Traits<T>::Key)pg1.klo;
+      sb.has[1] = pg1.nbins > 0;
+      sb.span[1] = pg1.nbins > 0 ? (typename Traits<T>::Key)(pg1.khi - pg1.klo) : 0;
+      sb.shift[1] = pg1.shift;
+      if (tid == 0) {  // for the narrowing after the count (kept in LDS, not in registers)
+        sh.pg[0] = pg0;
+        sh.pg[1] = pg1;
       }
       for (int b = tid; b < kHistMaxBins; b += BLOCK) sh.rh[b] = 0u;
       __syncthreads();
@@ -928,24 +949,24 @@ __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out, do
       }
       block_reduce<BLOCK, 0, 2>(dv, dop, iv, false, sh.d, sh.i);
       if (tid == 0) {
-        EvalResult r;
+        EvalResult &r = sh.evr;
         r.A = r.B = 0.0;
         r.pred = -__builtin_inf();
         r.succ = __builtin_inf();
         r.L = sh.st.cL + iv[0];
         r.G = (sh.st.n - sh.st.cR) + iv[1];
         r.written = 0;
-        bdev_after_eval(sh.st, r, a.cfg);
+        bdev_after_eval(sh.st, r, sh.cfg);
       }
       __syncthreads();
       if (sh.st.phase == PH_HIST) {
         const int p = sh.st.side;
-        block_pick<T, BLOCK>(sh.rh + p * (kHistMaxBins / 2), pg[p].nbins,
+        block_pick<T, BLOCK>(sh.rh + p * (kHistMaxBins / 2), sh.pg[p].nbins,
                              (uint64_t)(sh.st.k - sh.st.cL), sh);
         if (tid == 0) {
           const int32_t bsel = (int32_t)sh.misc[0];
-          bdev_hist_narrow(sh.st, pg[p], bsel, bsel < 0 ? 0 : sh.misc[1],
-                           bsel < 0 ? 0 : sh.misc[2], a.cfg);
+          bdev_hist_narrow(sh.st, sh.pg[p], bsel, bsel < 0 ? 0 : sh.misc[1],
+                           bsel < 0 ? 0 : sh.misc[2], sh.cfg);
         }
         __syncthreads();
       }
@@ -962,9 +983,9 @@ __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out, do
       if (clamp) block_pass<T, BLOCK, SU, true, false, false, false>(sp, t, yL, yR, fmn, fmx, nullptr, cap, sh, acc);
       else block_pass<T, BLOCK, U, false, false, false, false>(sp, t, yL, yR, fmn, fmx, nullptr, cap, sh, acc);
     } else if (s.filter) {
-      block_pass<T, BLOCK, SU, false, true, true, false>(sp, t, yL, yR, fmn, fmx, zb[s.zout], cap, sh, acc);
+      block_pass<T, BLOCK, SU, false, true, true, false>(sp, t, yL, yR, fmn, fmx, s.zout == 0 ? zb0 : zb1, cap, sh, acc);
     } else {
-      block_pass<T, BLOCK, SU, false, true, false, false>(sp, t, yL, yR, fmn, fmx, zb[s.zout], cap, sh, acc);
+      block_pass<T, BLOCK, SU, false, true, false, false>(sp, t, yL, yR, fmn, fmx, s.zout == 0 ? zb0 : zb1, cap, sh, acc);
     }
     double dv[8] = {acc.A, acc.B, (double)acc.pred, (double)acc.succ, 0, 0, 0, 0};
     int dop[8] = {0, 0, 2, 1, 0, 0, 0, 0};
@@ -975,11 +996,11 @@ __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out, do
       if (gather) {
         bdev_after_gather(w, sh.cur[0]);
       } else {
-        EvalResult r;
+        EvalResult &r = sh.evr;
         r.A = dv[0]; r.B = dv[1]; r.pred = dv[2]; r.succ = dv[3];
         r.L = iv[0]; r.G = iv[1];
         r.written = sh.cur[0] + sh.cur[1];
-        bdev_after_eval(w, r, a.cfg);
+        bdev_after_eval(w, r, sh.cfg);
       }
     }
     __syncthreads();
@@ -1006,7 +1027,7 @@ __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out, do
       double below;
       if (sh.kcopy >= 0 && pa < v && v < pb)
         below = sh.ksuma +
-                block_sum_range<T, BLOCK, U, true>(make_span((const T *)zb[0], sh.kcopy), pa, v, sh);
+                block_sum_range<T, BLOCK, U, true>(make_span((const T *)zb0, sh.kcopy), pa, v, sh);
       else
         below = block_sum_range<T, BLOCK, U, false>(make_span(x, n), v, v, sh);
       if (tid == 0) *ksum = below + (double)(s.k - s.less) * (double)v;
@@ -1024,6 +1045,7 @@ void batched_select_kernel(BatchArgs<T> a) {
   __shared__ BShared<T, BLOCK> sh;
   const int tid = threadIdx.x;
   const int64_t count = a.count;
+  if (tid == 0) sh.cfg = a.cfg;  // (read after the barriers below)
   // Largest first: every workgroup sorts (size, index) in LDS by itself.
   const bool sorted = count <= kBatchSortMax;
   if (sorted) {

@@ -22,6 +22,12 @@ namespace cps {
 #endif
 constexpr int kWaveSize = 64;
 constexpr int kSelectBlock = CPS_SELECT_BLOCK;
+#ifndef CPS_SELECT_PREFETCH
+#define CPS_SELECT_PREFETCH 1
+#endif
+// the streaming passes over full tiles issue the next tile's loads before processing the
+// current one
+constexpr bool kSelectPrefetch = CPS_SELECT_PREFETCH != 0;
 constexpr int kSelectUnroll = CPS_SELECT_UNROLL;  // 16-byte loads in flight per thread, plain passes
 constexpr int kSplitUnroll = CPS_SPLIT_UNROLL;    // the same for passes that also write
 constexpr int kHistMaxBins = 4096;  // bins of a histogram pass (2^hist_bits, hist_bits <= 12)

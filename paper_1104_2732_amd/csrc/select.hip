@@ -351,21 +351,52 @@ __device__ inline void drain_inside(WaveOut<T> &o, int lane, uint32_t cap) {
 // lies inside the span (no bounds tests; every tile but a span's last is full).
 // SPEC (a counting evaluation only): the elements of the copy's key range (pb.ka, pb.kab)
 // also go to the wavefront's region of split buffer 0, staged in its LDS columns.
-template <typename T, int U, bool CLAMP, bool SPLIT, bool FILTER, bool HIST, bool FULL,
-          bool SPEC = false>
-__device__ inline void eval_tile(const Span<T> &sp, int64_t base, int per_u, int me, T t, T yL,
-                                 T yR, T fmin, T fmax, WaveOut<T> &o, EvalAcc<T> &acc,
-                                 const PartBins<T> &pb) {
-  constexpr int V = Traits<T>::kVec;
-  using Vec = typename Traits<T>::Vec;
-  Vec raw[U];
-  bool valid[U];
+// The U vectors of a tile that belong to thread `me` (vector base + u*per_u + me), with the
+// nontemporal hint; FULL: the whole tile lies inside the span.
+template <typename T, int U, bool FULL>
+__device__ __attribute__((always_inline)) inline void tile_load(const Span<T> &sp, int64_t base, int per_u, int me,
+                                 typename Traits<T>::Vec (&raw)[U], bool (&valid)[U]) {
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int64_t vi = base + (int64_t)u * per_u + me;
     valid[u] = FULL || vi < sp.nvec;
     if (valid[u]) raw[u] = __builtin_nontemporal_load(&sp.V[vi]);
   }
+}
+
+// Walk the full tiles of a pass from `base` on (every `stride` vectors) with the next tile's
+// loads issued before the current tile is processed, so that each wavefront keeps its loads
+// in flight while it computes; returns the base of the first tile that is not full (a last
+// partial tile, or the end), which the caller walks without the prefetch.
+template <typename T, int U, typename Body>
+__device__ __attribute__((always_inline)) inline int64_t walk_full_tiles(const Span<T> &sp, int64_t base, int64_t stride,
+                                          int per_u, int me, Body &&body) {
+  using Vec = typename Traits<T>::Vec;
+  const int64_t last_full = sp.nvec - (int64_t)U * per_u;  // tiles at base <= last_full are full
+  if (base > last_full) return base;
+  Vec cur[U];
+  bool valid[U];
+  tile_load<T, U, true>(sp, base, per_u, me, cur, valid);
+  for (;;) {
+    const int64_t nb = base + stride;
+    const bool more = nb <= last_full;  // (uniform over the walk's threads)
+    Vec nxt[U];
+    if (more) tile_load<T, U, true>(sp, nb, per_u, me, nxt, valid);
+    body(cur, base);
+    base = nb;
+    if (!more) return base;
+#pragma unroll
+    for (int u = 0; u < U; ++u) cur[u] = nxt[u];
+  }
+}
+
+template <typename T, int U, bool CLAMP, bool SPLIT, bool FILTER, bool HIST, bool FULL,
+          bool SPEC = false>
+__device__ __attribute__((always_inline)) inline void eval_tile_data(const typename Traits<T>::Vec (&raw)[U],
+                                      const bool (&valid)[U], int me, T t, T yL, T yR, T fmin,
+                                      T fmax, WaveOut<T> &o, EvalAcc<T> &acc,
+                                      const PartBins<T> &pb) {
+  constexpr int V = Traits<T>::kVec;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     T e[V];
@@ -391,6 +422,18 @@ __device__ inline void eval_tile(const Span<T> &sp, int64_t base, int per_u, int
       split_flush<T>(o, me % kWave);
     }
   }
+}
+
+template <typename T, int U, bool CLAMP, bool SPLIT, bool FILTER, bool HIST, bool FULL,
+          bool SPEC = false>
+__device__ __attribute__((always_inline)) inline void eval_tile(const Span<T> &sp, int64_t base, int per_u, int me, T t, T yL,
+                                 T yR, T fmin, T fmax, WaveOut<T> &o, EvalAcc<T> &acc,
+                                 const PartBins<T> &pb) {
+  typename Traits<T>::Vec raw[U];
+  bool valid[U];
+  tile_load<T, U, FULL>(sp, base, per_u, me, raw, valid);
+  eval_tile_data<T, U, CLAMP, SPLIT, FILTER, HIST, FULL, SPEC>(raw, valid, me, t, yL, yR, fmin,
+                                                               fmax, o, acc, pb);
 }
 
 // F(x) = log(1 + d), d = x - min x >= 0, to float precision: the exponent of 1 + d taken
@@ -464,7 +507,18 @@ __device__ inline void eval_pass(const Walk<T> &wk, T t, T yL, T yR, T fmin, T f
   const int64_t stride = wk.wave_mode ? step_vecs : (int64_t)gridDim.x * step_vecs;
   const int me = wk.wave_mode ? lane : tid;
   const int per_u = wk.wave_mode ? kWave : BLOCK;
-  for (int64_t base = first; base < sp.nvec; base += stride) {
+  int64_t base = first;
+  if (kSelectPrefetch && !SPLIT) {  // (a split's staging leaves no registers for it)
+    bool all_valid[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) all_valid[u] = true;
+    base = walk_full_tiles<T, U>(sp, base, stride, per_u, me,
+                                 [&](const typename Traits<T>::Vec (&raw)[U], int64_t) {
+                                   eval_tile_data<T, U, CLAMP, SPLIT, FILTER, HIST, true, SPEC>(
+                                       raw, all_valid, me, t, yL, yR, fmin, fmax, o, acc, pb);
+                                 });
+  }
+  for (; base < sp.nvec; base += stride) {
     if (base + (int64_t)U * per_u <= sp.nvec)
       eval_tile<T, U, CLAMP, SPLIT, FILTER, HIST, true, SPEC>(sp, base, per_u, me, t, yL, yR, fmin,
                                                               fmax, o, acc, pb);
@@ -492,20 +546,11 @@ __device__ inline void eval_pass(const Walk<T> &wk, T t, T yL, T yR, T fmin, T f
 
 template <typename T, int U, bool CLASSIFY, bool BRACKET, bool SPLIT, bool HIST, bool FULL,
           bool SAMPLE = false>
-__device__ inline void pass0_tile(const Span<T> &sp, int64_t base, int per_u, int me, T ba, T bb,
-                                  P0Acc<T> &acc, WaveOut<T> &o, uint32_t cap,
-                                  const InteriorBins<T> &ib,
-                                  CPS_GLOBAL typename Traits<T>::Vec *smp, int64_t tile) {
+__device__ __attribute__((always_inline)) inline void pass0_tile_data(const typename Traits<T>::Vec (&raw)[U],
+                                       const bool (&valid)[U], int me, T ba, T bb, P0Acc<T> &acc,
+                                       WaveOut<T> &o, uint32_t cap, const InteriorBins<T> &ib,
+                                       CPS_GLOBAL typename Traits<T>::Vec *smp, int64_t tile) {
   constexpr int V = Traits<T>::kVec;
-  using Vec = typename Traits<T>::Vec;
-  Vec raw[U];
-  bool valid[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int64_t vi = base + (int64_t)u * per_u + me;
-    valid[u] = FULL || vi < sp.nvec;
-    if (valid[u]) raw[u] = __builtin_nontemporal_load(&sp.V[vi]);
-  }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     T e[V];
@@ -561,6 +606,19 @@ __device__ inline void pass0_tile(const Span<T> &sp, int64_t base, int per_u, in
   if (SAMPLE && me == 0) smp[tile] = raw[0];
 }
 
+template <typename T, int U, bool CLASSIFY, bool BRACKET, bool SPLIT, bool HIST, bool FULL,
+          bool SAMPLE = false>
+__device__ __attribute__((always_inline)) inline void pass0_tile(const Span<T> &sp, int64_t base, int per_u, int me, T ba, T bb,
+                                  P0Acc<T> &acc, WaveOut<T> &o, uint32_t cap,
+                                  const InteriorBins<T> &ib,
+                                  CPS_GLOBAL typename Traits<T>::Vec *smp, int64_t tile) {
+  typename Traits<T>::Vec raw[U];
+  bool valid[U];
+  tile_load<T, U, FULL>(sp, base, per_u, me, raw, valid);
+  pass0_tile_data<T, U, CLASSIFY, BRACKET, SPLIT, HIST, FULL, SAMPLE>(raw, valid, me, ba, bb, acc,
+                                                                     o, cap, ib, smp, tile);
+}
+
 template <typename T, int BLOCK, int U, bool CLASSIFY, bool BRACKET, bool SPLIT, bool HIST = false>
 __device__ inline void pass0(const Walk<T> &wk, T ba, T bb, P0Acc<T> &acc, WaveOut<T> &o,
                              uint32_t cap, const InteriorBins<T> &ib,
@@ -568,7 +626,27 @@ __device__ inline void pass0(const Walk<T> &wk, T ba, T bb, P0Acc<T> &acc, WaveO
   const int tid = threadIdx.x, lane = tid % kWave;
   const Span<T> &sp = wk.sp;
   const int64_t step_vecs = (int64_t)BLOCK * U;
-  for (int64_t base = (int64_t)blockIdx.x * step_vecs, tile = blockIdx.x; base < sp.nvec;
+  int64_t base = (int64_t)blockIdx.x * step_vecs;
+  if (kSelectPrefetch && !CLASSIFY && !BRACKET && !SPLIT) {  // the plain fast pass 0
+    bool all_valid[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) all_valid[u] = true;
+    const int64_t stride = (int64_t)gridDim.x * step_vecs;
+    if (smp)
+      base = walk_full_tiles<T, U>(sp, base, stride, BLOCK, tid,
+                                   [&](const typename Traits<T>::Vec (&raw)[U], int64_t b) {
+                                     pass0_tile_data<T, U, false, false, false, HIST, true, true>(
+                                         raw, all_valid, tid, ba, bb, acc, o, cap, ib, smp,
+                                         b / step_vecs);
+                                   });
+    else
+      base = walk_full_tiles<T, U>(sp, base, stride, BLOCK, tid,
+                                   [&](const typename Traits<T>::Vec (&raw)[U], int64_t) {
+                                     pass0_tile_data<T, U, false, false, false, HIST, true>(
+                                         raw, all_valid, tid, ba, bb, acc, o, cap, ib, smp, 0);
+                                   });
+  }
+  for (int64_t tile = base / step_vecs; base < sp.nvec;
        base += (int64_t)gridDim.x * step_vecs, tile += gridDim.x) {
     if (base + step_vecs > sp.nvec)
       pass0_tile<T, U, CLASSIFY, BRACKET, SPLIT, HIST, false>(sp, base, BLOCK, tid, ba, bb, acc, o,

@@ -226,12 +226,13 @@ def test_default_path_counted_split_and_compaction(sel, oracle_mod, dtype, count
 def test_large_input_counting_with_interval_copy(sel, oracle_mod, dist):
     """From 256 MiB of input the counting evaluation also copies a likely interval (sample
     quantiles around the rank) and the copy becomes the working set when the narrowed
-    bracket lies inside it: x is then read twice in all.  The periodic input has the
-    sample stride as its period, so every sampled element is 0 and the interval misses:
-    the copy is not adopted and a third pass over x finds the same exact result."""
+    bracket lies inside it: x is then read twice in all.  The periodic input has pass 0's
+    tile (1024 threads x four 16-byte vectors = 16384 float elements) as its period, so the
+    sample (each tile's first vector) holds only 0..3 and the interval misses: the copy is
+    not adopted and a third pass over x finds the same exact result."""
     n = (1 << 27) + 17
     if dist == "periodic":
-        x = (np.arange(n, dtype=np.int64) % (n // 4096)).astype(np.float32)
+        x = (np.arange(n, dtype=np.int64) % 16384).astype(np.float32)
     else:
         x = workloads.single_array(dist, n, np.float32, seed=8, tag="gpu-large")
     xt = _dev(x)
@@ -240,6 +241,8 @@ def test_large_input_counting_with_interval_copy(sel, oracle_mod, dist):
         res, st = sel.select_kth(xt, k, stats=True)
         assert_same_result(res, oracle_mod.select_kth(x, k), f"{dist} k={k}")
         assert st["passes"] <= 3, (dist, k, st["passes"])
+        if dist == "periodic":
+            assert st["passes"] == 3, (k, st["passes"])  # the copy was not adopted
     del xt
     torch.cuda.empty_cache()
 
