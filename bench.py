@@ -48,6 +48,8 @@ SIZES = (24, 28)
 DTYPES = (np.float32, np.float64)
 DISTS = ("uniform", "normal", "cauchy", "quantized_normal")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cp_select_kernel_traffic.json")
+LEGS = ("small", "batched", "batched_large", "lms", "lts_knn", "transform", "learned",
+        "schedules")
 EPOCHS = 20  # training epochs of the learned proposal (untimed setup)
 
 
@@ -125,6 +127,34 @@ def traffic_from(fetch_dir: str, write_dir: str) -> dict:
     return out
 
 
+def legs_traffic_from(fetch_dir: str, write_dir: str) -> dict:
+    """HBM bytes of the batched and least-median-of-squares kernels from two counter runs of
+    `bench.py --no-sweep --legs batched,lms --copy-calibration`: the last dispatch of each
+    kernel (the batched leg ends with an eager call of its tuned options; the LMS leg's last
+    call is an ordinary one), each counter scaled as in traffic_from (FETCH_SIZE by the
+    selection kernel's pass 0 over 1 GiB, WRITE_SIZE by the copy's 1 GiB written)."""
+    gib = float(4 << 28)
+    kernels = {"batched_select_kernel<float": "batched float32 (4096 lognormal arrays)",
+               "batched_select_kernel<double": "batched float64 (LMS medians)",
+               "lms_residual_kernel": "LMS residuals"}
+    out = {"kernel_source_hash": kernel_source_hash()}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = _counter_rows(d, counter)
+        if counter == "FETCH_SIZE":
+            cal = [v for (name, v) in rows if "cp_select_kernel" in name][:2]
+        else:
+            cal = [v for (name, v) in rows if "neg_kernel" in name]
+        if not cal:
+            raise SystemExit(f"{counter}: no calibration dispatch in {d}")
+        factor = gib / (float(np.mean(cal)) * 1024.0)
+        out[counter + "_factor"] = factor
+        for key, label in kernels.items():
+            sel = [v for (name, v) in rows if key in name]
+            if sel:
+                out.setdefault(label, {})[counter + "_bytes"] = sel[-1] * 1024.0 * factor
+    return out
+
+
 def _time_ms(torch, fn, reps: int) -> float:
     """Mean device time of fn() over reps calls, bracketed by events on the current stream."""
     fn()
@@ -177,6 +207,9 @@ def batched_leg(sel, cps, torch, reps: int = 5) -> dict:
     o_plain = cps.default_batch_options(block_threads=best.block_threads, proposal=0)
     nobr_ms = _time_ms(torch, lambda: sel.select_kth_batched_async(ptrs, szs, kk, len(dev), code,
                                                                    out, o_plain), reps)
+    # last: one eager call of the tuned options (the dispatch the counter runs read)
+    sel.select_kth_batched_async(ptrs, szs, kk, len(dev), code, out, best)
+    torch.cuda.synchronize()
     del dev
     return {"workload": "4096 lognormal(0,1) float32 arrays, sizes log-uniform in [1e3, 1e6], "
                         "median ranks (one persistent launch, captured in a graph)",
@@ -277,7 +310,7 @@ def transform_leg(sel, cps, torch, reps: int = 3) -> dict:
     return out
 
 
-def lms_leg(sel, torch, reps: int = 5) -> dict:
+def lms_leg(sel, cps, torch, reps: int = 5) -> dict:
     """Least median of squares: 2^20 rows, p = 8, 1024 candidates, 30 % of rows shifted."""
     import workloads
     n, p, m = 1 << 20, 8, 1024
@@ -285,8 +318,12 @@ def lms_leg(sel, torch, reps: int = 5) -> dict:
     Xd, yd, bd = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (X, y, betas))
     out = sel.new_results(m)
     ms = _time_ms(torch, lambda: sel.lms_median_sq_residuals_async(Xd, yd, bd, out), reps)
+    res = out.cpu().numpy().view(cps.RESULT_DTYPE)
+    passes = res["passes"].astype(np.float64)
     return {"workload": "n=2^20 rows, p=8, 1024 candidates (residuals fixed order, no FMA)",
-            "ms": ms, "residuals_per_s": n * m / (ms * 1e-3)}
+            "ms": ms, "residuals_per_s": n * m / (ms * 1e-3),
+            "passes_per_candidate_mean": float(passes.mean()),
+            "residual_bytes_one_write_one_read": 2 * n * m * 8}
 
 
 def learned_leg(sel, cps, torch, held_out: int = 128, chunk: int = 8) -> dict:
@@ -501,6 +538,46 @@ def cpu_baseline(budget_s: float = 20.0):
     return line, results
 
 
+def calibration_dispatches(sel, torch, dev) -> None:
+    """Dispatches of known HBM traffic for the counter runs: a plain copy of 2^28 float32
+    values (1 GiB read and written), then two selections of rank 1 on a 2^28 float32 input
+    whose minimum is unique: pass 0 alone, one read of 1 GiB with the selection kernel's own
+    nontemporal loads, and nothing written."""
+    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+    cal = torch.arange(1 << 28, dtype=torch.float32, device=dev)
+    cal_out = sel.new_results(1)
+    for _ in range(2):
+        sel.select_kth_async(cal, 1, cal_out)
+    torch.cuda.synchronize()
+    del cal
+
+
+def run_legs(sel, cps, torch, legs, line: dict) -> None:
+    """The extra legs named in `legs` (all of LEGS by default), each under its own key."""
+    table = {"small": lambda: small_leg(sel, cps, torch),
+             "batched": lambda: batched_leg(sel, cps, torch),
+             "batched_large": lambda: batched_large_leg(sel, cps, torch),
+             "lms": lambda: lms_leg(sel, cps, torch),
+             "lts_knn": lambda: lts_knn_leg(sel, torch),
+             "transform": lambda: transform_leg(sel, cps, torch),
+             "learned": lambda: learned_leg(sel, cps, torch),
+             "schedules": lambda: schedules_leg(sel, cps, torch)}
+    for name in LEGS:
+        if name not in legs:
+            continue
+        torch.cuda.empty_cache()
+        r = table[name]()
+        if name == "lts_knn":
+            line.update(r)
+        else:
+            line[name] = r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -513,10 +590,24 @@ def main():
                     help="run a plain 1 GiB elementwise copy first (counter calibration)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the traffic record from two rocprofv3 counter runs and exit")
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help="comma-separated extra legs to run (default: all of " + ",".join(LEGS) + ")")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the single-array sweep and print only the extra legs (profiling)")
+    ap.add_argument("--legs-traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="print the batched and LMS kernels' traffic from two counter runs of "
+                         "--no-sweep --legs batched,lms --copy-calibration and exit")
     args = ap.parse_args()
     if args.traffic_from:
         print(json.dumps(traffic_from(*args.traffic_from)))
         return
+    if args.legs_traffic_from:
+        print(json.dumps(legs_traffic_from(*args.legs_traffic_from)))
+        return
+    legs = [l for l in args.legs.split(",") if l]
+    unknown = [l for l in legs if l not in LEGS]
+    if unknown:
+        ap.error(f"unknown legs {unknown}; known: {list(LEGS)}")
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build runs the selection on a single "
@@ -530,6 +621,14 @@ def main():
 
     dev = torch.device("cuda", 0)
     sel = cps.Selector(0)
+    if args.no_sweep:
+        line = {"legs_only": True}
+        if args.copy_calibration:
+            calibration_dispatches(sel, torch, dev)
+        run_legs(sel, cps, torch, legs, line)
+        print(json.dumps(line), flush=True)
+        sel.close()
+        return
 
     # ---- resident inputs
     t_gen = time.time()
@@ -551,21 +650,7 @@ def main():
     gen_s = time.time() - t_gen
 
     if args.copy_calibration:
-        # a plain copy of 2^28 float32 values (1 GiB read and written), then two selections of
-        # rank 1 on a 2^28 float32 input whose minimum is unique: pass 0 alone, one read of
-        # 1 GiB with the selection kernel's own nontemporal loads, and nothing written
-        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(2):
-            torch.neg(src, out=dst)
-        torch.cuda.synchronize()
-        del src, dst
-        cal = torch.arange(1 << 28, dtype=torch.float32, device=dev)
-        cal_out = sel.new_results(1)
-        for _ in range(2):
-            sel.select_kth_async(cal, 1, cal_out)
-        torch.cuda.synchronize()
-        del cal
+        calibration_dispatches(sel, torch, dev)
 
     outs = sel.new_results(len(inputs))
     res_views = [outs[i * 48:(i + 1) * 48] for i in range(len(inputs))]
@@ -673,22 +758,7 @@ def main():
                               "the reported counts, on the host copy of each input"}
     if not args.no_extras:
         del inputs
-        torch.cuda.empty_cache()
-        line["small"] = small_leg(sel, cps, torch)
-        torch.cuda.empty_cache()
-        line["batched"] = batched_leg(sel, cps, torch)
-        torch.cuda.empty_cache()
-        line["batched_large"] = batched_large_leg(sel, cps, torch)
-        torch.cuda.empty_cache()
-        line["lms"] = lms_leg(sel, torch)
-        torch.cuda.empty_cache()
-        line.update(lts_knn_leg(sel, torch))
-        torch.cuda.empty_cache()
-        line["transform"] = transform_leg(sel, cps, torch)
-        torch.cuda.empty_cache()
-        line["learned"] = learned_leg(sel, cps, torch)
-        torch.cuda.empty_cache()
-        line["schedules"] = schedules_leg(sel, cps, torch)
+        run_legs(sel, cps, torch, legs, line)
     if not args.no_cpu_baseline:
         line["cpu_baseline"], oracle_res = cpu_baseline()
         # the oracle's own results on the calls it timed, against the GPU's
