@@ -14,6 +14,10 @@ namespace cps {
 
 constexpr int kLmsGroup = 16;   // candidates per thread row
 constexpr int kLmsBlock = 256;
+#ifndef CPS_LMS_ROWS
+#define CPS_LMS_ROWS 2
+#endif
+constexpr int kLmsRows = CPS_LMS_ROWS;  // rows per thread of the 16-byte residual kernel
 
 template <int P>
 __global__ __launch_bounds__(kLmsBlock) void lms_residual_kernel(
@@ -47,6 +51,68 @@ __global__ __launch_bounds__(kLmsBlock) void lms_residual_kernel(
       }
       const double d = yi - s;
       __builtin_nontemporal_store(d * d, &Rg[(c0 + c) * n + i]);  // written once, read later
+    }
+  }
+}
+
+// The same residuals for p = P columns, R consecutive rows per thread: each thread's X rows
+// are R*P contiguous doubles (16-byte loads) and each candidate's R residuals one or two
+// 16-byte stores, so a wavefront writes R*512 contiguous bytes per candidate.  Needs n to be a
+// multiple of R (every candidate's array then starts 16-byte aligned).
+template <int P, int R>
+__global__ __launch_bounds__(kLmsBlock) void lms_residual_rows_kernel(
+    const double *__restrict__ X, const double *__restrict__ y, const double *__restrict__ betas,
+    int64_t n, int64_t m, double *__restrict__ R_out) {
+  static_assert(R % 2 == 0 && (P * R) % 2 == 0, "16-byte groups");
+  __shared__ double sb[kLmsGroup * P];
+  const int64_t c0 = (int64_t)blockIdx.y * kLmsGroup;
+  const int nc = (int)((m - c0) < kLmsGroup ? (m - c0) : kLmsGroup);
+  for (int q = threadIdx.x; q < nc * P; q += kLmsBlock) sb[q] = betas[c0 * P + q];
+  __syncthreads();
+  using D2 = double __attribute__((ext_vector_type(2)));
+  const CPS_GLOBAL D2 *Xg = (const CPS_GLOBAL D2 *)X;
+  const CPS_GLOBAL D2 *yg = (const CPS_GLOBAL D2 *)y;
+  CPS_GLOBAL double *Rg = (CPS_GLOBAL double *)R_out;
+  const int64_t groups = n / R;
+  for (int64_t g = (int64_t)blockIdx.x * kLmsBlock + threadIdx.x; g < groups;
+       g += (int64_t)gridDim.x * kLmsBlock) {
+    const int64_t i0 = g * R;
+    double row[R][P];
+#pragma unroll
+    for (int v = 0; v < R * P / 2; ++v) {
+      const D2 w = Xg[i0 * P / 2 + v];
+      row[(2 * v) / P][(2 * v) % P] = w.x;
+      row[(2 * v + 1) / P][(2 * v + 1) % P] = w.y;
+    }
+    double yi[R];
+#pragma unroll
+    for (int v = 0; v < R / 2; ++v) {
+      const D2 w = yg[i0 / 2 + v];
+      yi[2 * v] = w.x;
+      yi[2 * v + 1] = w.y;
+    }
+    for (int c = 0; c < nc; ++c) {
+      const double *b = sb + c * P;
+      double r[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        double s = row[q][0] * b[0];
+#pragma unroll
+        for (int j = 1; j < P; ++j) {
+          const double prod = row[q][j] * b[j];
+          s = s + prod;
+        }
+        const double d = yi[q] - s;
+        r[q] = d * d;
+      }
+      CPS_GLOBAL D2 *dst = (CPS_GLOBAL D2 *)(Rg + (c0 + c) * n + i0);
+#pragma unroll
+      for (int v = 0; v < R / 2; ++v) {
+        D2 w;
+        w.x = r[2 * v];
+        w.y = r[2 * v + 1];
+        __builtin_nontemporal_store(w, dst + v);  // written once, read later
+      }
     }
   }
 }
@@ -96,10 +162,16 @@ hipError_t launch_lms_residuals(const double *X, const double *y, const double *
   if (bx > want) bx = want;
   if (bx < 1) bx = 1;
   const dim3 grid((unsigned)bx, (unsigned)groups);
-  if (p == 8)
+  const bool aligned = ((uintptr_t)X % 16 == 0) && ((uintptr_t)y % 16 == 0) && ((uintptr_t)R % 16 == 0);
+  if (p == 8 && aligned && n % kLmsRows == 0) {
+    const int64_t rb = (n / kLmsRows + kLmsBlock - 1) / kLmsBlock;
+    const dim3 g2((unsigned)(bx < rb ? bx : rb), (unsigned)groups);
+    lms_residual_rows_kernel<8, kLmsRows><<<g2, dim3(kLmsBlock), 0, stream>>>(X, y, betas, n, m, R);
+  } else if (p == 8) {
     lms_residual_kernel<8><<<grid, dim3(kLmsBlock), 0, stream>>>(X, y, betas, n, p, m, R);
-  else
+  } else {
     lms_residual_kernel<0><<<grid, dim3(kLmsBlock), 0, stream>>>(X, y, betas, n, p, m, R);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   lms_descriptor_kernel<<<dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream>>>(R, n, m, rank,
