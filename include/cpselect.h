@@ -130,6 +130,15 @@ typedef struct cps_eval {
  *                   rank) to the workspace, and when the narrowed bracket lies inside it the
  *                   copy replaces that next pass over x.  1 (default) or 0 (the split writes
  *                   both sides and counts them as it goes).
+ * cooperative:      the kernel's workgroups wait for each other between passes, so all of
+ *                   them must be resident at once (the grid never exceeds what fits).  0
+ *                   (default): an ordinary launch, which on a GPU not running another such
+ *                   kernel gives exactly that; a selection started while another one (a
+ *                   different handle, another stream) still runs may find some of its
+ *                   workgroups unable to start until that one ends, and if both wait on
+ *                   each other the waits give up after spin_limit and the call reports
+ *                   CPS_STATUS_TIMEOUT.  1: a cooperative launch, for which the runtime
+ *                   guarantees residency (about 17 us more per call on this part).
  * transform:        1: the cutting plane minimises the objective of F(x) = log(1 + x - min x),
  *                   the monotone transform of Section 5.3 for data with a few huge values
  *                   (~1e20, where the sums over x lose every smaller term): one evaluation
@@ -154,7 +163,7 @@ typedef struct cps_options {
   int32_t hist_bits;
   int32_t count_first;
   int32_t transform;
-  int32_t pad;
+  int32_t cooperative;
 } cps_options;
 
 #define CPS_STATS_MAX_PASSES 96
@@ -313,10 +322,10 @@ int cps_objective(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
  *                  histogram passes over the array (no copy) until few are left for the
  *                  gather.  The split capacity does not limit it.  1 (default) or 0.
  * proposal:        1 (default): an array of at least 2^15 elements starts from a sampled
- *                  bracket (not in the paper): 4096 of its elements (256 runs of 16
- *                  neighbours) counted in 2^12 key bins over their range, and the values just
- *                  outside the bins of sample ranks S p -/+ (4 sqrt(S p (1 - p)) + 2), p =
- *                  (k - 1/2) / n, S = 4096.  Pass 0 counts #(x <= a) and #(x < b), keeps each
+ *                  bracket (not in the paper): S of its elements (S = 4096, or 16384 from
+ *                  2^18 elements on; runs of 16 neighbours) counted in 2^12 key bins over
+ *                  their range, and the values just outside the bins of sample ranks
+ *                  S p -/+ (4 sqrt(S p (1 - p)) + 2), p = (k - 1/2) / n.  Pass 0 counts #(x <= a) and #(x < b), keeps each
  *                  end only where the counts prove it (as cps_options.use_bracket), counts the
  *                  elements strictly inside in key bins and copies every 16-byte vector of x
  *                  that holds one to a buffer; when both ends hold, the bracket narrows to the

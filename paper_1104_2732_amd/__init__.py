@@ -73,7 +73,7 @@ class Options(ctypes.Structure):
                 ("use_bracket", ctypes.c_int32), ("compact_proposal", ctypes.c_int32),
                 ("bracket_lo", ctypes.c_double), ("bracket_hi", ctypes.c_double),
                 ("hist_bits", ctypes.c_int32), ("count_first", ctypes.c_int32),
-                ("transform", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("transform", ctypes.c_int32), ("cooperative", ctypes.c_int32)]
 
 
 class BatchOptions(ctypes.Structure):

@@ -168,6 +168,7 @@ struct Resolved {
   int64_t seg_R;
   int64_t spin_limit;
   int compact_proposal;
+  bool cooperative;
 };
 
 int resolve(cps_handle *h, int64_t n, int dtype, const cps_options *opt, Resolved &r) {
@@ -175,8 +176,10 @@ int resolve(cps_handle *h, int64_t n, int dtype, const cps_options *opt, Resolve
   cps_default_options(&o);
   if (opt) o = *opt;
   if (o.maxit < 0 || o.final_threshold < 1 || !(o.partition_fraction >= 0.0) ||
-      o.partition_fraction > 1.0 || o.grid_blocks < 0 || o.spin_limit < 0)
+      o.partition_fraction > 1.0 || o.grid_blocks < 0 || o.spin_limit < 0 ||
+      o.cooperative < 0 || o.cooperative > 1)
     return CPS_EINVAL;
+  r.cooperative = o.cooperative != 0;
   if (o.block_threads != 0 && o.block_threads != cps::kSelectBlock) return CPS_EINVAL;
   if (o.hist_bits < 0 || (1 << o.hist_bits) > cps::kHistMaxBins) return CPS_EINVAL;
   r.cfg = cps::CpConfig{};
@@ -281,7 +284,7 @@ int run_select(cps_handle *h, const T *x, int64_t n, int64_t k, const cps_option
   a.ghist = (uint64_t *)(base + L.gh);
   a.smp = L.smp_n > 0 ? (T *)(base + L.sm) : nullptr;
   a.smp_n = L.smp_n;
-  hipError_t e = cps::launch_select<T>(a, r.grid, stream);
+  hipError_t e = cps::launch_select<T>(a, r.grid, r.cooperative, stream);
   if (e != hipSuccess) return hip_fail(e);
   return CPS_OK;
 }
@@ -817,7 +820,7 @@ int select_kth_noalloc(cps_handle *h, const void *x, int64_t n, int64_t k, int d
     a.phist = nullptr;
     a.smp = nullptr;
     a.smp_n = 0;
-    return cps::launch_select<T>(a, r.grid, s);
+    return cps::launch_select<T>(a, r.grid, r.cooperative, s);
   };
   e = dtype == CPS_F32 ? fill((const float *)x) : fill((const double *)x);
   return e == hipSuccess ? CPS_OK : hip_fail(e);

@@ -357,8 +357,10 @@ __device__ void block_pass0(const Span<T> &sp, P0Acc<T> &acc) {
 // ------------------------------------------------------------------ sampled bracket
 
 // The sampled bracket of one array (used by arrays of at least kBatchPropMin elements):
-// kPropSample elements (runs of kPropRun neighbours at evenly spaced places, so the sample
-// touches few lines) counted in 2^12 key bins over the sample's own range; the bracket runs
+// S = kPropSample elements, or kPropSampleBig from kPropBigN elements on (the bracket's width
+// goes as 1/sqrt(S), and with it the copy pass 0 writes and the later passes read), in runs
+// of kPropRun neighbours at evenly spaced places (so the sample touches few lines), counted
+// in 2^12 key bins over the sample's own range; the bracket runs
 // from just below the bin that holds sample rank floor(q - d) to just above the bin that holds
 // rank ceil(q + d), where q = S (k - 1/2) / n is the rank's place among the S sampled
 // elements and d = 4 sqrt(S p (1 - p)) + 2, p = (k - 1/2) / n (four binomial standard
@@ -368,7 +370,9 @@ __device__ void block_pass0(const Span<T> &sp, P0Acc<T> &acc) {
 // NaN or an infinity, only one value, or both ends would be open.
 template <typename T> __device__ constexpr int32_t c_dtype() { return sizeof(T) == 4 ? 0 : 1; }
 
-constexpr int kPropSample = 4096;
+constexpr int kPropSample = 4096;       // sample elements of arrays below kPropBigN
+constexpr int kPropSampleBig = 16384;   // ... and from kPropBigN on (a quarter as wide a bracket)
+constexpr int64_t kPropBigN = (int64_t)1 << 18;
 constexpr int kPropRun = 16;
 constexpr int64_t kBatchPropMin = (int64_t)1 << 15;
 
@@ -377,9 +381,11 @@ __device__ __noinline__ bool sample_bracket(const T *x, int64_t n, int64_t k, BS
                                T &pb) {
   using Key = typename Traits<T>::Key;
   const int tid = threadIdx.x;
-  constexpr int PER = kPropSample / BLOCK;
-  // (n >= kBatchPropMin: the runs lie inside x and do not overlap)
-  const int64_t stride = n / (kPropSample / kPropRun);
+  const int S = n >= kPropBigN ? kPropSampleBig : kPropSample;
+  // (n >= kBatchPropMin, and n >= kPropBigN for the larger sample: the runs lie inside x and
+  // do not overlap)
+  const int64_t stride = n / (S / kPropRun);
+  auto sample = [&](int i) -> T { return x[(int64_t)(i / kPropRun) * stride + i % kPropRun]; };
   if (tid == 0) {
     sh.kext[0] = ~0ull;
     sh.kext[1] = 0ull;
@@ -387,17 +393,14 @@ __device__ __noinline__ bool sample_bracket(const T *x, int64_t n, int64_t k, BS
     sh.misc[4] = sh.misc[5] = 0;
   }
   __syncthreads();
-  Key kv[PER];
   Key kmn = (Key)~(Key)0, kmx = 0;
   bool bad = false;
-#pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    const int i = tid + j * BLOCK;
-    const T v = x[(int64_t)(i / kPropRun) * stride + i % kPropRun];
+  for (int i = tid; i < S; i += BLOCK) {  // the sample's key range (the keys are read again below)
+    const T v = sample(i);
     bad = bad || !(v == v) || v == t_inf<T>() || v == -t_inf<T>();
-    kv[j] = Traits<T>::key(v);
-    kmn = kv[j] < kmn ? kv[j] : kmn;
-    kmx = kv[j] > kmx ? kv[j] : kmx;
+    const Key kv = Traits<T>::key(v);
+    kmn = kv < kmn ? kv : kmn;
+    kmx = kv > kmx ? kv : kmx;
   }
   atomicMin(reinterpret_cast<unsigned long long *>(&sh.kext[0]), (unsigned long long)kmn);
   atomicMax(reinterpret_cast<unsigned long long *>(&sh.kext[1]), (unsigned long long)kmx);
@@ -410,14 +413,14 @@ __device__ __noinline__ bool sample_bracket(const T *x, int64_t n, int64_t k, BS
   const int nbins = (int)((khi - klo) >> shift) + 1;
   for (int b = tid; b < nbins; b += BLOCK) sh.rh[b] = 0u;
   __syncthreads();
-#pragma unroll
-  for (int j = 0; j < PER; ++j) atomicAdd(&sh.rh[(uint32_t)(((uint64_t)kv[j] - klo) >> shift)], 1u);
+  for (int i = tid; i < S; i += BLOCK)
+    atomicAdd(&sh.rh[(uint32_t)(((uint64_t)Traits<T>::key(sample(i)) - klo) >> shift)], 1u);
   __syncthreads();
-  const double S = (double)kPropSample;
+  const double Sd = (double)S;
   const double p = ((double)k - 0.5) / (double)n;
-  const double q = S * p, d = 4.0 * __builtin_sqrt(S * p * (1.0 - p)) + 2.0;
+  const double q = Sd * p, d = 4.0 * __builtin_sqrt(Sd * p * (1.0 - p)) + 2.0;
   const double r0 = __builtin_floor(q - d), r1 = __builtin_ceil(q + d);
-  const bool open0 = r0 < 1.0, open1 = r1 > S;
+  const bool open0 = r0 < 1.0, open1 = r1 > Sd;
   if (open0 && open1) return false;
   const uint64_t rank0 = open0 ? 1 : (uint64_t)r0, rank1 = open1 ? (uint64_t)S : (uint64_t)r1;
   // the bins holding the two sample ranks: an exclusive scan of the bins in a fixed order
@@ -601,13 +604,12 @@ template <typename T> __device__ inline void write_batch_result(cps_result *out,
 template <typename T, int BLOCK, int U>
 __device__ __noinline__ bool prop_pass0(const T *x, int64_t n, int64_t k, T pa, T pb, int part, int parts,
                            TeamCtl *tc, CPS_GLOBAL T *ibuf, int64_t icap,
-                           const BatchArgs<T> &a, BShared<T, BLOCK> &sh) {
-  const bool suma = a.ksum != nullptr;
+                           bool suma, BShared<T, BLOCK> &sh) {
   using Key = typename Traits<T>::Key;
   const int tid = threadIdx.x;
-  const int32_t dt = a.cfg.dtype;
+  const int32_t dt = sh.cfg.dtype;
   const HistGeom<uint64_t> g0 =
-      hist_geometry(next_up((double)pa, dt), next_down((double)pb, dt), dt, a.cfg.hist_bits);
+      hist_geometry(next_up((double)pa, dt), next_down((double)pb, dt), dt, sh.cfg.hist_bits);
   PropBins<T> ib;
   ib.ka = Traits<T>::key(pa);
   ib.kb = Traits<T>::key(pb);
@@ -738,7 +740,7 @@ __device__ __noinline__ bool prop_pass0(const T *x, int64_t n, int64_t k, T pa, 
   // both ends proven and the interior's bins are those of the bracket: narrow at once
   const CpState &s1 = sh.st;
   if (s1.phase == PH_HIST && s1.bracket_used == 3 && s1.wbuf == 0) {
-    const HistGeom<uint64_t> g = hist_geometry(s1.lo, s1.hi, dt, a.cfg.hist_bits);
+    const HistGeom<uint64_t> g = hist_geometry(s1.lo, s1.hi, dt, sh.cfg.hist_bits);
     if (g.klo == g0.klo && g.khi == g0.khi && g.shift == g0.shift) {
       block_pick<T, BLOCK>(sh.rh, g.nbins, (uint64_t)(s1.k - s1.cL), sh);
       if (tid == 0) {
@@ -824,7 +826,7 @@ __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out, do
       TeamCtl *tc = parts > 1 ? a.teams + slot : nullptr;
       CPS_GLOBAL T *ibuf = parts > 1 ? (CPS_GLOBAL T *)(a.tbuf + slot * a.team_cap) : zb0;
       if (!prop_pass0<T, BLOCK, U>(x, n, k, pa, pb, part, parts, tc, ibuf, parts > 1 ? a.team_cap : cap,
-                                   a, sh))
+                                   a.ksum != nullptr, sh))
         return;
       zb0 = ibuf;  // the interior's elements are the working set from here on
       if (tid == 0) {

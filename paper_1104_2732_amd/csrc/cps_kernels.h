@@ -153,7 +153,8 @@ hipError_t launch_knn_reduce(const float *P, const float *f, const float *Q, int
                              int32_t dim, int64_t nq, int64_t k, const cps_result *sel,
                              double *pd, int64_t *pi, cps_knn *out, hipStream_t stream);
 
-template <typename T> hipError_t launch_select(const SelectArgs<T> &a, int grid, hipStream_t stream);
+template <typename T>
+hipError_t launch_select(const SelectArgs<T> &a, int grid, bool cooperative, hipStream_t stream);
 template <typename T> int select_max_blocks_per_cu();
 template <typename T>
 hipError_t launch_objective(const T *x, int64_t n, int64_t k, const double *ys, int64_t ny,

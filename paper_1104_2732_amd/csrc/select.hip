@@ -98,6 +98,10 @@ template <typename T, int BLOCK> struct Shared {
   uint32_t lcnt;  // elements a gather pass staged in LDS
   uint32_t rh[kHistWords];  // key histogram of a histogram pass, or of both parts of a split
   T ring[BLOCK / kWave][2][Stage<T>::kSlots];  // split staging, per wavefront and part
+  // The launch's arguments for the out-of-line update: a reference to the kernel's own
+  // argument would make the compiler copy it to every lane's scratch memory at launch
+  // (~280 bytes per lane, ~70 MB for a full grid).
+  SelectArgs<T> args;
 };
 
 // Which side of the trial point an element goes to in a split: the bracket's elements
@@ -1686,6 +1690,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_num_vgpr(128))) void c
   const int tid = threadIdx.x, wv = tid / kWave, lane = tid % kWave;
   const int G = gridDim.x, bid = blockIdx.x;
   uint32_t gen = 0;
+  if (tid == 0) sh.args = a;  // (read by last_update, after the pass's barriers)
   if (tid == 0) {
     gen = load_relaxed(&a.sync->gen);
     if (bid == 0) {
@@ -1715,7 +1720,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_num_vgpr(128))) void c
     }
     __syncthreads();
     if (sh.last) {
-      last_update<T, BLOCK>(a, sh, phase, p0_slow);
+      last_update<T, BLOCK>(sh.args, sh, phase, p0_slow);
       __syncthreads();
       if (tid == 0) {
         store_release(&a.sync->gen, gen + 1u);
@@ -1858,7 +1863,15 @@ __global__ __launch_bounds__(BLOCK) void objective_final_kernel(int64_t n, int64
 // ------------------------------------------------------------------ launchers
 
 template <typename T>
-hipError_t launch_select(const SelectArgs<T> &a, int grid, hipStream_t stream) {
+hipError_t launch_select(const SelectArgs<T> &a, int grid, bool cooperative, hipStream_t stream) {
+  // The grid never exceeds the workgroups that fit at once (one per CU), so an ordinary launch
+  // on a GPU not running another grid-synchronising kernel has them all resident; the
+  // cooperative launch guarantees it in every case but costs ~17 us more per call (measured:
+  // an empty kernel takes ~2.5 us per ordinary launch and ~20 us per cooperative one).
+  if (!cooperative) {
+    cp_select_kernel<T, kSelectBlock, kSelectUnroll><<<dim3(grid), dim3(kSelectBlock), 0, stream>>>(a);
+    return hipGetLastError();
+  }
   SelectArgs<T> copy = a;
   void *args[] = {&copy};
   return hipLaunchCooperativeKernel((const void *)cp_select_kernel<T, kSelectBlock, kSelectUnroll>,
@@ -1884,8 +1897,8 @@ hipError_t launch_objective(const T *x, int64_t n, int64_t k, const double *ys, 
   return hipGetLastError();
 }
 
-template hipError_t launch_select<float>(const SelectArgs<float> &, int, hipStream_t);
-template hipError_t launch_select<double>(const SelectArgs<double> &, int, hipStream_t);
+template hipError_t launch_select<float>(const SelectArgs<float> &, int, bool, hipStream_t);
+template hipError_t launch_select<double>(const SelectArgs<double> &, int, bool, hipStream_t);
 template int select_max_blocks_per_cu<float>();
 template int select_max_blocks_per_cu<double>();
 template hipError_t launch_objective<float>(const float *, int64_t, int64_t, const double *,

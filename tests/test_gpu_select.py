@@ -123,6 +123,17 @@ def test_special_values(sel, oracle_mod, dtype):
                 assert_same_result(res, oracle_mod.select_kth(x, k), f"{name} k={k} {opt}")
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_cooperative_launch(sel, oracle_mod, dtype):
+    """The same selections under the cooperative launch (residency guaranteed by the runtime)
+    as under the default ordinary launch, on a ragged multi-tile input."""
+    n = (1 << 21) + 333
+    x = workloads.single_array("normal", n, dtype, seed=12, tag="gpu-coop")
+    for k in (1, n // 100, (n + 1) // 2, n):
+        res = _run(sel, x, k, "cooperative", cooperative=1)
+        assert_same_result(res, oracle_mod.select_kth(x, k), f"cooperative k={k}")
+
+
 def test_nan_status(sel):
     import paper_1104_2732_amd as cps
     x = np.array([1.0, np.nan, 3.0, 4.0], dtype=np.float32)
