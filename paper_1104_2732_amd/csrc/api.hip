@@ -572,7 +572,7 @@ int knn_mean(cps_handle *h, const float *P_dev, const float *f_dev, const float 
                                  (const int64_t *)(base + off_desc + 2 * dsz), nq, CPS_F32, &o,
                                  (cps_result *)(base + off_sel), stream);
   if (rc) return rc;
-  hipError_t e = cps::launch_knn_reduce(P_dev, f_dev, Q_dev, n, dim, nq, k,
+  hipError_t e = cps::launch_knn_reduce(P_dev, f_dev, Q_dev, (const float *)base, n, dim, nq, k,
                                         (const cps_result *)(base + off_sel),
                                         (double *)(base + off_pd), (int64_t *)(base + off_pd + psz),
                                         out_dev, s);

@@ -149,8 +149,8 @@ hipError_t launch_lts_finish(const cps_result *sel, const double *ksum, int64_t 
 hipError_t launch_knn_distances(const float *P, const float *Q, int64_t n, int32_t dim, int64_t nq,
                                 int64_t k, float *Dst, const float **ptrs, int64_t *sizes,
                                 int64_t *ks, int cu_count, hipStream_t stream);
-hipError_t launch_knn_reduce(const float *P, const float *f, const float *Q, int64_t n,
-                             int32_t dim, int64_t nq, int64_t k, const cps_result *sel,
+hipError_t launch_knn_reduce(const float *P, const float *f, const float *Q, const float *Dst,
+                             int64_t n, int32_t dim, int64_t nq, int64_t k, const cps_result *sel,
                              double *pd, int64_t *pi, cps_knn *out, hipStream_t stream);
 
 template <typename T>

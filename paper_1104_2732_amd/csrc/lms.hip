@@ -12,7 +12,10 @@
 
 namespace cps {
 
-constexpr int kLmsGroup = 16;   // candidates per thread row
+#ifndef CPS_LMS_GROUP
+#define CPS_LMS_GROUP 64
+#endif
+constexpr int kLmsGroup = CPS_LMS_GROUP;  // candidates per thread row (X read once per group)
 constexpr int kLmsBlock = 256;
 #ifndef CPS_LMS_ROWS
 #define CPS_LMS_ROWS 2
