@@ -136,7 +136,7 @@ def legs_traffic_from(fetch_dir: str, write_dir: str) -> dict:
     gib = float(4 << 28)
     kernels = {"batched_select_kernel<float": "batched float32 (4096 lognormal arrays)",
                "batched_select_kernel<double": "batched float64 (LMS medians)",
-               "lms_residual_kernel": "LMS residuals"}
+               "lms_residual": "LMS residuals"}
     out = {"kernel_source_hash": kernel_source_hash()}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = _counter_rows(d, counter)

@@ -574,11 +574,19 @@ int select_kth_learned(cps_handle *h, const void *x, int64_t n, int64_t k, int d
                        const float *params_dev, const cps_options *opt, cps_result *out_dev,
                        cps_stats *stats_dev, void *stream);
 
-/* select_kth with the non-learned baseline of the proposal: the fixed-stride sample of
- * S = min(n, 4096) elements sorted on the device, and the bracket between its order
+/* The non-learned baseline of the proposal, for one array: the fixed-stride sample of
+ * S = min(n, 4096) elements (element i * floor(n / S)) and the bracket between its order
  * statistics of 0-based ranks floor(c - z sd) - 1 and ceil(c + z sd), c = S k / n,
- * sd = sqrt(S p (1 - p)) + 1 with p = k / n (an end beyond the sample is open).  Checked
- * by counts like any proposal; results are identical to select_kth's.
+ * sd = sqrt(S p (1 - p)) + 1 with p = k / n (an end beyond the sample is open: -inf or
+ * +inf), selected on the device (one workgroup: key bins, then exact ranks inside the two
+ * bins that hold them).  bracket_dev receives three doubles (a, b, use), use = 0 when the
+ * sample holds NaN or an infinity.  Errors: CPS_EINVAL for null pointers, n < 1, k outside
+ * [1, n], a misaligned x or z < 0. */
+int cps_sample_bracket(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype, double z,
+                       double *bracket_dev, void *stream);
+
+/* select_kth with that bracket (cps_sample_bracket's kernel, then the selection whose pass 0
+ * checks it by counts like any proposal); results are identical to select_kth's.
  * Errors: as select_kth, and CPS_EINVAL for z < 0. */
 int select_kth_sampled(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype, double z,
                        const cps_options *opt, cps_result *out_dev, cps_stats *stats_dev,

@@ -122,8 +122,8 @@ EXPORTS = ("cps_create", "cps_destroy", "cps_status_string", "cps_last_hip_error
            "cps_reserve_batched", "cps_autotune_batched", "lms_median_sq_residuals",
            "cps_mixture_generate", "cps_features", "cps_mlp_forward", "cps_mlp_loss_grad",
            "cps_mlp_adam", "cps_mlp_init", "cps_learned_bracket", "select_kth_learned",
-           "cps_mlp_train", "select_kth_sampled", "cps_model_save", "cps_model_load",
-           "select_kth_noalloc", "select_kth_batched_ksum", "lts_trimmed_sq", "knn_mean")
+           "cps_mlp_train", "select_kth_sampled", "cps_sample_bracket", "cps_model_save",
+           "cps_model_load", "select_kth_noalloc", "select_kth_batched_ksum", "lts_trimmed_sq", "knn_mean")
 STATUS_BADARG = 4
 
 
@@ -191,11 +191,13 @@ def lib() -> ctypes.CDLL:
                                 vp]
     L.select_kth_sampled.argtypes = [vp, vp, i64, i64, c_int, ctypes.c_double,
                                      ctypes.POINTER(Options), vp, vp, vp]
+    L.cps_sample_bracket.argtypes = [vp, vp, i64, i64, c_int, ctypes.c_double, vp, vp]
     L.cps_model_save.argtypes = [vp, ctypes.c_char_p]
     L.cps_model_load.argtypes = [ctypes.c_char_p, vp]
     for name in ("cps_mixture_generate", "cps_features", "cps_mlp_forward", "cps_mlp_loss_grad",
                  "cps_mlp_adam", "cps_mlp_init", "cps_learned_bracket", "select_kth_learned",
-                 "cps_mlp_train", "select_kth_sampled", "cps_model_save", "cps_model_load"):
+                 "cps_mlp_train", "select_kth_sampled", "cps_sample_bracket", "cps_model_save",
+                 "cps_model_load"):
         getattr(L, name).restype = c_int
     _lib = L
     return L
@@ -550,6 +552,18 @@ class Selector:
         _check(lib().cps_mlp_init(self._h, int(seed), self._float_params(params),
                                   ctypes.c_void_p(_stream_ptr(self.device))), "cps_mlp_init")
         return params
+
+    def sample_bracket(self, x, k: int, z: float = 4.0):
+        """(a, b, use) of the non-learned sample-quantile baseline for x and rank k."""
+        import torch
+        br = torch.empty(3, dtype=torch.float64, device=self.device)
+        _check(lib().cps_sample_bracket(self._h, self._ptr(x), x.numel(), int(k), _dtype_code(x),
+                                        float(z), self._ptr(br),
+                                        ctypes.c_void_p(_stream_ptr(self.device))),
+               "cps_sample_bracket")
+        torch.cuda.synchronize(self.device)
+        a, b, use = br.cpu().tolist()
+        return a, b, int(use)
 
     def learned_bracket(self, x, k: int, params):
         """(a, b, use) the network proposes for x and rank k."""

@@ -957,6 +957,20 @@ int select_kth_learned(cps_handle *h, const void *x, int64_t n, int64_t k, int d
   return run_select<double>(h, (const double *)x, n, k, opt, out_dev, stats_dev, s, h->bracket);
 }
 
+int cps_sample_bracket(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype, double z,
+                       double *bracket_dev, void *stream) {
+  int rc = check_common(h, x, n, k, dtype);
+  if (rc) return rc;
+  if (!bracket_dev || !(z >= 0.0) || z > 1e6) return CPS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (dtype == CPS_F32)
+    e = cps::launch_sample_bracket<float>((const float *)x, n, k, z, nullptr, bracket_dev, s);
+  else
+    e = cps::launch_sample_bracket<double>((const double *)x, n, k, z, nullptr, bracket_dev, s);
+  return e == hipSuccess ? CPS_OK : hip_fail(e);
+}
+
 int select_kth_sampled(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype, double z,
                        const cps_options *opt, cps_result *out_dev, cps_stats *stats_dev,
                        void *stream) {

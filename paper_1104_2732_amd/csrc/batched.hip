@@ -642,12 +642,11 @@ __device__ __noinline__ bool prop_pass0(const T *x, int64_t n, int64_t k, T pa, 
   }
   double mn = (double)acc.mn, mx = (double)acc.mx;
   int64_t cmn = acc.cmn, cmx = acc.cmx;
-  block_pair_fold<BLOCK>(mn, cmn, mx, cmx, sh.d, sh.i);
-  double dv[8] = {acc.Aa, 0, 0, 0, 0, 0, 0, 0};
+    double dv[8] = {acc.Aa, 0, 0, 0, 0, 0, 0, 0};
   int64_t iv[8] = {(int64_t)acc.cle_a, (int64_t)acc.nnan, (int64_t)ovf, (int64_t)acc.clt_b, 0, 0,
                    0, 0};
   int dop[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  block_reduce<BLOCK, 1, 4>(dv, dop, iv, false, sh.d, sh.i);
+  block_reduce_pair<BLOCK, 1, 4>(dv, dop, iv, mn, cmn, mx, cmx, sh.d, sh.i);
   int64_t written = 0;
   if (parts > 1) {
     // leave the partial, add the bins, arrive; the last part folds
@@ -854,11 +853,10 @@ __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out, do
     else block_pass0<T, BLOCK, U, false>(sx, acc);
     double mn = (double)acc.mn, mx = (double)acc.mx;
     int64_t cmn = acc.cmn, cmx = acc.cmx;
-    block_pair_fold<BLOCK>(mn, cmn, mx, cmx, sh.d, sh.i);
-    double dv[8] = {acc.sum, 0, 0, 0, 0, 0, 0, 0};
+        double dv[8] = {acc.sum, 0, 0, 0, 0, 0, 0, 0};
     int64_t iv[8] = {(int64_t)acc.nnan, (int64_t)acc.nneg, (int64_t)acc.npos, 0, 0, 0, 0, 0};
     int dop[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    block_reduce<BLOCK, 1, 3>(dv, dop, iv, false, sh.d, sh.i);
+    block_reduce_pair<BLOCK, 1, 3>(dv, dop, iv, mn, cmn, mx, cmx, sh.d, sh.i);
     if (tid == 0) {
       Pass0Result &r = sh.p0r;
       r = Pass0Result{};

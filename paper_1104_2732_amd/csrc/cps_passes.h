@@ -121,13 +121,61 @@ template <typename T> __device__ inline int64_t edge_index(const Span<T> &s, int
   return i < s.head ? i : s.tail_start + (i - s.head);
 }
 
-// Block reduction of up to 8 double fields (op per field: 0 sum, 1 min, 2 max) and
-// 8 int64 sums.  The int fields are either per-thread or wave-uniform (`iuniform`).
-// The result is valid in thread 0.  Fixed order, hence deterministic.
-template <int BLOCK, int ND, int NI>
-__device__ inline void block_reduce(double (&dv)[8], const int (&dop)[8], int64_t (&iv)[8],
-                                    bool iuniform, double (&sd)[8][BLOCK / kWave],
-                                    int64_t (&si)[8][BLOCK / kWave]) {
+// Fold (min, multiplicity) and (max, multiplicity) pairs over the wavefront: the extreme
+// first, then the multiplicities of the lanes that hold it.  Every lane gets the result.
+__device__ inline void wave_pair_fold(double &mn, int64_t &cmn, double &mx, int64_t &cmx) {
+  const double wm = wave_min(mn), wx = wave_max(mx);
+  cmn = wave_sum_i64(mn == wm ? cmn : 0);
+  cmx = wave_sum_i64(mx == wx ? cmx : 0);
+  mn = wm;
+  mx = wx;
+}
+
+// Fold of one value per wavefront (lanes 0 .. NW-1 of wavefront 0 hold them, NW <= 16, the
+// other lanes the identity): four row shifts bring the first row's values into lane 15 in a
+// fixed order, and lane 15 is read as a scalar, so every lane of the wavefront gets it.
+template <int OP> __device__ inline double row_fold16(double v) {
+  const double id = OP == 0 ? 0.0 : (OP == 1 ? __builtin_inf() : -__builtin_inf());
+  v = dpp_op<OP>(v, dpp_move<0x111, 0xF>(v, id));  // row_shr:1
+  v = dpp_op<OP>(v, dpp_move<0x112, 0xF>(v, id));  // row_shr:2
+  v = dpp_op<OP>(v, dpp_move<0x114, 0xF>(v, id));  // row_shr:4
+  v = dpp_op<OP>(v, dpp_move<0x118, 0xF>(v, id));  // row_shr:8
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 15);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 15);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// The wavefronts' values of one field, folded by wavefront 0 (op 0 sum, 1 min, 2 max).
+template <int BLOCK>
+__device__ inline double fold_waves(const double *row, int op) {
+  const int lane = threadIdx.x % kWave;
+  const bool in = lane < BLOCK / kWave;
+  if (op == 0) return row_fold16<0>(in ? row[lane] : 0.0);
+  if (op == 1) return row_fold16<1>(in ? row[lane] : __builtin_inf());
+  return row_fold16<2>(in ? row[lane] : -__builtin_inf());
+}
+template <int BLOCK> __device__ inline int64_t fold_waves_i64(const int64_t *row) {
+  const int lane = threadIdx.x % kWave;
+  return (int64_t)row_fold16<0>(lane < BLOCK / kWave ? (double)row[lane] : 0.0);
+}
+
+// Block reduction of up to 8 double fields (op per field: 0 sum, 1 min, 2 max) and up to
+// 8 int64 sums, and with PAIR also the (minimum, multiplicity) and (maximum, multiplicity)
+// pairs (the extreme first, then the multiplicities of the lanes that hold it; ND + 2 and
+// NI + 2 fields at most then).  The int fields are either per-thread or wave-uniform
+// (`iuniform`); integer sums go through double, exact below 2^53.  Each wavefront folds its
+// fields with DPP moves, writes one value per field to LDS, and wavefront 0 folds the
+// wavefronts' values with row moves: one exchange, two barriers, a fixed order (so the
+// results are deterministic).  The results are valid in every lane of wavefront 0.  (Fold
+// cost grows with the fields; callers fold only the fields their pass forms.)
+template <int BLOCK, int ND, int NI, bool PAIR = false>
+__device__ inline void block_reduce_impl(double (&dv)[8], const int (&dop)[8], int64_t (&iv)[8],
+                                         bool iuniform, double &mn, int64_t &cmn, double &mx,
+                                         int64_t &cmx, double (&sd)[8][BLOCK / kWave],
+                                         int64_t (&si)[8][BLOCK / kWave]) {
+  static_assert(BLOCK / kWave <= 16, "one row of wavefront 0 folds the wavefronts");
+  static_assert(!PAIR || (ND + 2 <= 8 && NI + 2 <= 8), "room for the pairs");
   const int tid = threadIdx.x, wv = tid / kWave, lane = tid % kWave;
 #pragma unroll
   for (int f = 0; f < ND; ++f) {
@@ -139,86 +187,54 @@ __device__ inline void block_reduce(double (&dv)[8], const int (&dop)[8], int64_
 #pragma unroll
     for (int f = 0; f < NI; ++f) iv[f] = wave_sum_i64(iv[f]);
   }
+  if (PAIR) wave_pair_fold(mn, cmn, mx, cmx);
   if (lane == 0) {
 #pragma unroll
     for (int f = 0; f < ND; ++f) sd[f][wv] = dv[f];
 #pragma unroll
     for (int f = 0; f < NI; ++f) si[f][wv] = iv[f];
-  }
-  __syncthreads();
-  // one thread per field folds the wavefronts' values in wavefront order (fixed order,
-  // and the fields in parallel), then thread 0 collects the results
-  if (tid < ND) {
-    const int f = tid;
-    int op = 0;  // dop[f] by selects (an indexed read would move dop to scratch memory)
-#pragma unroll
-    for (int g = 0; g < ND; ++g) op = g == f ? dop[g] : op;
-    double r = sd[f][0];
-    for (int w = 1; w < BLOCK / kWave; ++w) {
-      const double x = sd[f][w];
-      r = op == 0 ? r + x : (op == 1 ? fmin(r, x) : fmax(r, x));
+    if (PAIR) {
+      sd[ND][wv] = mn;
+      sd[ND + 1][wv] = mx;
+      si[NI][wv] = cmn;
+      si[NI + 1][wv] = cmx;
     }
-    sd[f][0] = r;
-  } else if (tid >= kWave && tid < kWave + NI) {
-    const int f = tid - kWave;
-    int64_t r = 0;
-    for (int w = 0; w < BLOCK / kWave; ++w) r += si[f][w];
-    si[f][0] = r;
   }
   __syncthreads();
-  if (tid == 0) {
+  if (wv == 0) {
 #pragma unroll
-    for (int f = 0; f < ND; ++f) dv[f] = sd[f][0];
+    for (int f = 0; f < ND; ++f) dv[f] = fold_waves<BLOCK>(sd[f], dop[f]);
 #pragma unroll
-    for (int f = 0; f < NI; ++f) iv[f] = si[f][0];
+    for (int f = 0; f < NI; ++f) iv[f] = fold_waves_i64<BLOCK>(si[f]);
+    if (PAIR) {
+      const bool in = lane < BLOCK / kWave;
+      const double a = in ? sd[ND][lane] : __builtin_inf();
+      const double b = in ? sd[ND + 1][lane] : -__builtin_inf();
+      mn = row_fold16<1>(a);
+      mx = row_fold16<2>(b);
+      cmn = (int64_t)row_fold16<0>(in && a == mn ? (double)si[NI][lane] : 0.0);
+      cmx = (int64_t)row_fold16<0>(in && b == mx ? (double)si[NI + 1][lane] : 0.0);
+    }
   }
-  __syncthreads();
+  __syncthreads();  // (the exchange rows are free again)
 }
 
-// Fold (min, multiplicity) and (max, multiplicity) pairs over the wavefront: the extreme
-// first, then the multiplicities of the lanes that hold it.  Every lane gets the result.
-__device__ inline void wave_pair_fold(double &mn, int64_t &cmn, double &mx, int64_t &cmx) {
-  const double wm = wave_min(mn), wx = wave_max(mx);
-  cmn = wave_sum_i64(mn == wm ? cmn : 0);
-  cmx = wave_sum_i64(mx == wx ? cmx : 0);
-  mn = wm;
-  mx = wx;
+template <int BLOCK, int ND, int NI>
+__device__ inline void block_reduce(double (&dv)[8], const int (&dop)[8], int64_t (&iv)[8],
+                                    bool iuniform, double (&sd)[8][BLOCK / kWave],
+                                    int64_t (&si)[8][BLOCK / kWave]) {
+  double mn = 0.0, mx = 0.0;
+  int64_t cmn = 0, cmx = 0;
+  block_reduce_impl<BLOCK, ND, NI, false>(dv, dop, iv, iuniform, mn, cmn, mx, cmx, sd, si);
 }
 
-// Fold (min, multiplicity) and (max, multiplicity) pairs over the workgroup; valid in
-// thread 0.
-template <int BLOCK>
-__device__ inline void block_pair_fold(double &mn, int64_t &cmn, double &mx, int64_t &cmx,
-                                       double (&sd)[8][BLOCK / kWave],
-                                       int64_t (&si)[8][BLOCK / kWave]) {
-  const int tid = threadIdx.x, wv = tid / kWave, lane = tid % kWave;
-  wave_pair_fold(mn, cmn, mx, cmx);
-  if (lane == 0) {
-    sd[0][wv] = mn; si[0][wv] = cmn; sd[1][wv] = mx; si[1][wv] = cmx;
-  }
-  __syncthreads();
-  // the minimum in thread 0 and the maximum in the first thread of wavefront 1, in
-  // wavefront order
-  if (tid == 0) {
-    mn = sd[0][0]; cmn = si[0][0];
-    for (int w = 1; w < BLOCK / kWave; ++w) {
-      if (sd[0][w] < mn) { mn = sd[0][w]; cmn = si[0][w]; } else if (sd[0][w] == mn) cmn += si[0][w];
-    }
-  } else if (tid == kWave) {
-    double m = sd[1][0];
-    int64_t c = si[1][0];
-    for (int w = 1; w < BLOCK / kWave; ++w) {
-      if (sd[1][w] > m) { m = sd[1][w]; c = si[1][w]; } else if (sd[1][w] == m) c += si[1][w];
-    }
-    sd[1][0] = m;
-    si[1][0] = c;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    mx = sd[1][0];
-    cmx = si[1][0];
-  }
-  __syncthreads();
+// block_reduce with the extremes' pairs folded in the same exchange: valid in wavefront 0.
+template <int BLOCK, int ND, int NI>
+__device__ inline void block_reduce_pair(double (&dv)[8], const int (&dop)[8], int64_t (&iv)[8],
+                                         double &mn, int64_t &cmn, double &mx, int64_t &cmx,
+                                         double (&sd)[8][BLOCK / kWave],
+                                         int64_t (&si)[8][BLOCK / kWave]) {
+  block_reduce_impl<BLOCK, ND, NI, true>(dv, dop, iv, false, mn, cmn, mx, cmx, sd, si);
 }
 
 }  // namespace cps

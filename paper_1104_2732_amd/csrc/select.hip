@@ -1171,19 +1171,30 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
       sh.wseg[0][wv] = o.lo;
       sh.wseg[1][wv] = 0;
     }
-    if (bid == 0 && a.cfg.hist_bits > 0)
-      for (int b = tid; b < (1 << a.cfg.hist_bits); b += BLOCK)
-        a.ghist[b] = a.ghist[kHistMaxBins + b] = 0;
+    // (the histogram counters are zero here: cleared with the workspace's first part when it
+    // is allocated, by the last workgroup after every pass that counted into them, and by the
+    // last workgroup out after a wait that timed out; clearing them here too held workgroup 0
+    // at the next barrier until its 64 KB of stores had completed)
     double mn = (double)acc.mn, mx = (double)acc.mx;
     int64_t cmn = acc.cmn, cmx = acc.cmx;
-    block_pair_fold<BLOCK>(mn, cmn, mx, cmx, sh.d, sh.i);
+    if (!use_br && !p0_slow) {
+      // the plain fast pass 0 forms only the sum and the extremes' pairs (the classification
+      // counts and the proposal's fields are zero): fold those alone
+      dv[0] = acc.sum;
+      block_reduce_pair<BLOCK, 1, 0>(dv, dop, iv, mn, cmn, mx, cmx, sh.d, sh.i);
+      dv[1] = dv[2] = dv[3] = dv[4] = 0.0;
+      iv[0] = iv[1] = iv[2] = iv[3] = iv[4] = iv[5] = 0;
+      dv[5] = mn; dv[6] = mx; dv[7] = 0.0;
+      iv[6] = cmn; iv[7] = cmx;
+      return;
+    }
     dv[0] = acc.sum; dv[1] = acc.Aa; dv[2] = acc.Ba; dv[3] = acc.Ab; dv[4] = acc.Bb;
     dv[5] = dv[6] = dv[7] = 0;
     iv[0] = (int64_t)acc.nnan; iv[1] = (int64_t)acc.nneg; iv[2] = (int64_t)acc.npos;
     iv[3] = (int64_t)acc.cle_a; iv[4] = (int64_t)acc.clt_b;
     iv[5] = (p0s && lane == 0 && o.lo > cap) ? 1 : 0;  // overflowing wavefronts
     iv[6] = iv[7] = 0;
-    block_reduce<BLOCK, 5, 6>(dv, dop, iv, false, sh.d, sh.i);
+    block_reduce_pair<BLOCK, 5, 6>(dv, dop, iv, mn, cmn, mx, cmx, sh.d, sh.i);
     if (tid == 0) {
       dv[5] = mn; dv[6] = mx; iv[6] = cmn; iv[7] = cmx;
     }
@@ -1344,13 +1355,27 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
         }
     }
   }
-  dv[0] = acc.A; dv[1] = acc.B; dv[2] = (double)acc.pred; dv[3] = (double)acc.succ;
-  dop[2] = 2; dop[3] = 1;
-  dv[4] = dv[5] = dv[6] = dv[7] = 0;
-  iv[0] = (int64_t)acc.L; iv[1] = (int64_t)acc.G;
-  iv[2] = lane == 0 ? written : 0;  // per wavefront, counted once
-  iv[3] = iv[4] = iv[5] = iv[6] = iv[7] = 0;
-  block_reduce<BLOCK, 4, 3>(dv, dop, iv, false, sh.d, sh.i);
+  if (s.phase == PH_EVAL && !s.counted) {
+    dv[0] = acc.A; dv[1] = acc.B; dv[2] = (double)acc.pred; dv[3] = (double)acc.succ;
+    dop[2] = 2; dop[3] = 1;
+    dv[4] = dv[5] = dv[6] = dv[7] = 0;
+    iv[0] = (int64_t)acc.L; iv[1] = (int64_t)acc.G;
+    iv[2] = lane == 0 ? written : 0;  // per wavefront, counted once
+    iv[3] = iv[4] = iv[5] = iv[6] = iv[7] = 0;
+    block_reduce<BLOCK, 4, 3>(dv, dop, iv, false, sh.d, sh.i);
+    return;
+  }
+  // a counting evaluation, a histogram pass or a gather: only the elements written are
+  // folded (the counts come from the key bins; A, B and the neighbours are not formed), the
+  // other fields take their identities
+  iv[0] = lane == 0 ? written : 0;
+  block_reduce<BLOCK, 0, 1>(dv, dop, iv, false, sh.d, sh.i);
+  iv[2] = iv[0];
+  iv[0] = iv[1] = iv[3] = iv[4] = iv[5] = iv[6] = iv[7] = 0;
+  dv[0] = dv[1] = 0.0;
+  dv[2] = -__builtin_inf();
+  dv[3] = __builtin_inf();
+  dv[4] = dv[5] = dv[6] = dv[7] = 0.0;
 }
 
 // Trace of pass i in the stats record (thread 0 of the last workgroup only).

@@ -303,6 +303,36 @@ def test_sampled_proposal_parity(sel, oracle_mod, dtype):
     assert r_s["passes"] < r_plain["passes"]
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_sample_bracket_order_statistics(sel, dtype):
+    """The baseline's bracket is the fixed-stride sample's order statistics of ranks
+    floor(c - z sd) - 1 and ceil(c + z sd) (0-based), against a library sort of that sample;
+    heavy ties (two values, a constant) included."""
+    rng = np.random.default_rng(17)
+    cases = [("normal", 1 << 20), ("quantized_normal", 100_001), ("cauchy", 4095), ("normal", 5)]
+    for dist, n in cases:
+        x = workloads.single_array(dist, n, dtype, seed=n, tag="gpu-sample-bracket")
+        for extra in ("", "two", "const"):
+            xx = x.copy()
+            if extra == "two":
+                xx = np.where(xx > 0, 1.0, -1.0).astype(dtype)
+            elif extra == "const":
+                xx = np.full(n, 2.5, dtype=dtype)
+            S = min(n, 4096)
+            sv = np.sort(xx[:: n // S][:S].astype(np.float64))
+            for k in sorted({1, n, (n + 1) // 2, int(rng.integers(1, n + 1))}):
+                for z in (0.0, 4.0):
+                    p = k / n
+                    c = p * S
+                    sd = np.sqrt(S * p * (1 - p)) + 1.0
+                    lo, hi = int(np.floor(c - z * sd)) - 1, int(np.ceil(c + z * sd))
+                    want_a = sv[lo] if lo >= 0 else -np.inf
+                    want_b = sv[hi] if hi <= S - 1 else np.inf
+                    print(f"case sample-bracket {dist}{extra} n={n} k={k} z={z}", flush=True)
+                    a, b, use = sel.sample_bracket(_dev(xx), k, z)
+                    assert use == 1 and a == want_a and b == want_b, (dist, extra, n, k, z, a, b)
+
+
 def _fnv1a64(data: bytes) -> int:
     h = 14695981039346656037
     for b in data:
