@@ -673,10 +673,8 @@ hipError_t launch_learned_bracket(const T *x, int64_t n, int64_t k, const float 
 // The non-learned baseline of the proposal: the same fixed-stride sample, and the bracket
 // between its order statistics z standard deviations of the sample rank (binomial,
 // sqrt(S p (1 - p)) + 1) below and above the expected rank S k / n.  The two order
-// statistics are selected, not sorted for: the sample's ordered keys are counted in 2^12
-// bins over their range, the bin holding each wanted rank is found by a scan, and each
-// element of that bin takes its exact rank by counting the sample's smaller keys (ties by
-// sample index), so one element per wanted rank writes its value.
+// statistics are selected, not sorted for: the sample sits in LDS and the workgroup's radix
+// select (8-bit digits of the ordered keys) finds each wanted rank.
 
 constexpr int kSortBlock = 1024;
 
@@ -686,29 +684,16 @@ __global__ __launch_bounds__(kSortBlock) void sample_bracket_kernel(const T *x, 
                                                                    uint64_t *zero_hist,
                                                                    double *bracket) {
   constexpr int PER = kSample / kSortBlock;
-  constexpr int BPT = kHistMaxBins / kSortBlock;
-  __shared__ uint64_t sk[kSample];
-  __shared__ uint32_t bins[kHistMaxBins];
-  __shared__ uint64_t wsum[kSortBlock / kWave];
-  __shared__ unsigned long long kext[2];
+  __shared__ double sv[kSample];
+  __shared__ uint32_t hist[256];
+  __shared__ int64_t misc[4];
   __shared__ int bad;
-  __shared__ int64_t want[2], wbin[2], wcum[2];
   const int tid = threadIdx.x;
   if (zero_hist)
     for (int i = tid; i < kHistMaxBins; i += kSortBlock) zero_hist[i] = 0;
   const int64_t S = n < kSample ? n : kSample;
   const int64_t stride = n / S;
-  if (tid == 0) {
-    bad = 0;
-    kext[0] = ~0ull;
-    kext[1] = 0ull;
-    const double pr = (double)k / (double)n;
-    const double c = pr * (double)S;
-    const double sd = sqrt((double)S * pr * (1.0 - pr)) + 1.0;
-    want[0] = (int64_t)floor(c - z * sd) - 1;  // 0-based ranks in the sorted sample
-    want[1] = (int64_t)ceil(c + z * sd);
-  }
-  for (int b = tid; b < kHistMaxBins; b += kSortBlock) bins[b] = 0u;
+  if (tid == 0) bad = 0;
   __syncthreads();
   double vv[PER];
 #pragma unroll
@@ -716,73 +701,38 @@ __global__ __launch_bounds__(kSortBlock) void sample_bracket_kernel(const T *x, 
     const int i = tid + j * kSortBlock;
     vv[j] = i < S ? (double)x[i * stride] : 0.0;
   }
-  unsigned long long kmn = ~0ull, kmx = 0ull;
   bool nf = false;
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const int i = tid + j * kSortBlock;
     if (i < S) {
       nf = nf || !__builtin_isfinite(vv[j]);
-      const uint64_t kv = key64(vv[j]);
-      sk[i] = kv;
-      kmn = kv < kmn ? kv : kmn;
-      kmx = kv > kmx ? kv : kmx;
+      sv[i] = vv[j];
     }
   }
   if (nf) bad = 1;
-  atomicMin(&kext[0], kmn);
-  atomicMax(&kext[1], kmx);
   __syncthreads();
   if (bad) {
     if (tid == 0) bracket[0] = bracket[1] = bracket[2] = 0.0;
     return;
   }
-  const uint64_t klo = kext[0], khi = kext[1];
-  int shift = 0;
-  while (((khi - klo) >> shift) >= (uint64_t)kHistMaxBins) ++shift;
-  for (int i = tid; i < S; i += kSortBlock) atomicAdd(&bins[(uint32_t)((sk[i] - klo) >> shift)], 1u);
-  __syncthreads();
-  uint64_t hv[BPT], tot = 0;
+  const double pr = (double)k / (double)n;
+  const double c = pr * (double)S;
+  const double sd = sqrt((double)S * pr * (1.0 - pr)) + 1.0;
+  const int64_t want[2] = {(int64_t)floor(c - z * sd) - 1, (int64_t)ceil(c + z * sd)};  // 0-based
+  double got[2] = {-__builtin_inf(), __builtin_inf()};
 #pragma unroll
-  for (int j = 0; j < BPT; ++j) {
-    hv[j] = bins[tid * BPT + j];
-    tot += hv[j];
-  }
-  uint64_t cum = block_exclusive_scan<kSortBlock>(tot, wsum);
-#pragma unroll
-  for (int j = 0; j < BPT; ++j) {
-#pragma unroll
-    for (int w = 0; w < 2; ++w) {
-      const int64_t r = want[w];
-      if (r >= 0 && r < S && (int64_t)cum <= r && r < (int64_t)(cum + hv[j])) {
-        wbin[w] = tid * BPT + j;
-        wcum[w] = (int64_t)cum;
-      }
-    }
-    cum += hv[j];
-  }
-  __syncthreads();
-  // the exact rank of every element of a wanted bin: the sample's smaller keys, and equal
-  // keys of smaller index
-  for (int i = tid; i < S; i += kSortBlock) {
-    const uint64_t kv = sk[i];
-    const int64_t b = (int64_t)((kv - klo) >> shift);
-#pragma unroll
-    for (int w = 0; w < 2; ++w) {
-      const int64_t r = want[w];
-      if (r < 0 || r >= S || b != wbin[w]) continue;
-      int64_t rank = wcum[w];
-      for (int j = 0; j < S; ++j) {  // (only the bin's own elements are smaller or tied here)
-        const uint64_t o = sk[j];
-        if ((int64_t)((o - klo) >> shift) != b) continue;
-        rank += (o < kv || (o == kv && j < i)) ? 1 : 0;
-      }
-      if (rank == r) bracket[w] = unkey64(kv);
-    }
+  for (int w = 0; w < 2; ++w) {
+    if (want[w] < 0 || want[w] > S - 1) continue;  // (uniform) an open end
+    uint64_t key;
+    int64_t below, eq;
+    block_radix_select<double, kSortBlock>(sv, S, false, 0.0, 0.0, want[w] + 1, hist, misc, key,
+                                           below, eq);
+    got[w] = unkey64(key);
   }
   if (tid == 0) {
-    if (want[0] < 0) bracket[0] = -__builtin_inf();
-    if (want[1] > S - 1) bracket[1] = __builtin_inf();
+    bracket[0] = got[0];
+    bracket[1] = got[1];
     bracket[2] = 1.0;
   }
 }
