@@ -327,15 +327,9 @@ __device__ void block_pass0(const Span<T> &sp, P0Acc<T> &acc) {
       vec_to_arr<T>(raw[u], e);
       T aa = 0, bA = 0, ab = 0, bB = 0;
       if (!CLASSIFY) {
-        // the running extremes change only where a lane's element reaches them (as in the
-        // single-array pass 0: the wavefront tests first, NaN compares false in both)
-        bool near = false;
-#pragma unroll
-        for (int j = 0; j < V; ++j) near |= valid[u] & ((e[j] <= acc.mn) | (e[j] >= acc.mx));
-        if (ballot(near) != 0) {
-#pragma unroll
-          for (int j = 0; j < V; ++j) p0_extremes<T>(e[j], valid[u], acc);
-        }
+        // the running extremes change only where an element reaches the wavefront's (as in
+        // the single-array pass 0)
+        p0_extremes_wave<T, V>(e, valid[u], acc);
 #pragma unroll
         for (int j = 0; j < V; ++j)
           pass0_one<T, false, false, true>(e[j], valid[u], ba, bb, aa, bA, ab, bB, acc);
@@ -526,13 +520,7 @@ __device__ void block_pass0_prop(const Span<T> &sp, T pa, const PropBins<T> &ib,
     for (int u = 0; u < U; ++u) {
       T w[V];
       vec_to_arr<T>(raw[u], w);
-      bool near = false;
-#pragma unroll
-      for (int j = 0; j < V; ++j) near |= valid[u] & ((w[j] <= acc.mn) | (w[j] >= acc.mx));
-      if (ballot(near) != 0) {
-#pragma unroll
-        for (int j = 0; j < V; ++j) p0_extremes<T>(w[j], valid[u], acc);
-      }
+      p0_extremes_wave<T, V>(w, valid[u], acc);
       hit[u] = false;
 #pragma unroll
       for (int j = 0; j < V; ++j) hit[u] |= one(w[j], valid[u]);
@@ -628,6 +616,8 @@ __device__ __noinline__ bool prop_pass0(const T *x, int64_t n, int64_t k, T pa, 
   acc.sum = 0;
   acc.mn = t_inf<T>();
   acc.mx = -t_inf<T>();
+  acc.wmn = t_inf<T>();
+  acc.wmx = -t_inf<T>();
   acc.cmn = acc.cmx = 0;
   acc.nnan = acc.nneg = acc.npos = acc.cle_a = acc.clt_b = 0;
   acc.Aa = acc.Ba = acc.Ab = acc.Bb = 0;
@@ -846,6 +836,8 @@ __device__ void select_one(const T *x, int64_t n, int64_t k, cps_result *out, do
     acc.sum = 0;
     acc.mn = t_inf<T>();
     acc.mx = -t_inf<T>();
+    acc.wmn = t_inf<T>();
+    acc.wmx = -t_inf<T>();
     acc.cmn = acc.cmx = 0;
     acc.nnan = acc.nneg = acc.npos = acc.cle_a = acc.clt_b = 0;
     acc.Aa = acc.Ba = acc.Ab = acc.Bb = 0;

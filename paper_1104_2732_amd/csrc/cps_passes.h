@@ -42,6 +42,7 @@ __device__ inline void eval_one(T &v, bool valid, T t, T fmin, T fmax, T &a_part
 template <typename T> struct P0Acc {
   double sum;
   T mn, mx;
+  T wmn, wmx;  // the wavefront's running extremes (uniform; see p0_extremes_wave)
   uint32_t cmn, cmx;
   uint32_t nnan, nneg, npos;  // per lane
   uint32_t cle_a, clt_b;      // per lane
@@ -60,6 +61,28 @@ template <typename T> __device__ inline void p0_extremes(T v, bool fin, P0Acc<T>
   const bool gt = fin && v > acc.mx, eqx = fin && v == acc.mx;
   acc.cmx = gt ? 1u : acc.cmx + (eqx ? 1u : 0u);
   acc.mx = gt ? v : acc.mx;
+}
+
+// The running extremes of a fast pass 0 for one vector of V elements.  An element can be
+// the array's minimum (maximum) only if it is at most (at least) the wavefront's running
+// minimum wmn (maximum wmx), which are uniform, so the wavefront tests that first; only when
+// some lane's element passes do the lanes update their extremes and multiplicities
+// (p0_extremes) and the wavefront refold wmn and wmx from them.  Exact for the array's
+// extremes: wmn never falls below the final minimum, so every element equal to it passes
+// the test when it is read and is counted; an element that does not pass lies above the
+// final minimum (below the final maximum), and a lane's extremes over the elements that
+// passed are all the fold of the lanes needs.  NaN compares false, as in p0_extremes.
+template <typename T, int V>
+__device__ inline void p0_extremes_wave(const T (&e)[V], bool valid, P0Acc<T> &acc) {
+  bool near = false;
+#pragma unroll
+  for (int j = 0; j < V; ++j) near |= valid & ((e[j] <= acc.wmn) | (e[j] >= acc.wmx));
+  if (ballot(near) != 0) {
+#pragma unroll
+    for (int j = 0; j < V; ++j) p0_extremes<T>(e[j], valid, acc);
+    acc.wmn = (T)wave_min((double)acc.mn);
+    acc.wmx = (T)wave_max((double)acc.mx);
+  }
 }
 
 // SKIP_EXTREMES: the caller has established that no lane's element can change the running

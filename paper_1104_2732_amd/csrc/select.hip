@@ -561,17 +561,10 @@ __device__ __attribute__((always_inline)) inline void pass0_tile_data(const type
     vec_to_arr<T>(raw[u], e);
     T aa = 0, bA = 0, ab = 0, bB = 0;
     if (!CLASSIFY) {
-      // Past the first tiles an element rarely reaches the running extremes: the wavefront
-      // tests that first (compares only) and updates the extremes and their counts only
-      // when some lane's element is <= the minimum or >= the maximum.  NaN compares false
-      // here as in the update, so the result is the same.
-      bool near = false;
-#pragma unroll
-      for (int j = 0; j < V; ++j) near |= valid[u] & ((e[j] <= acc.mn) | (e[j] >= acc.mx));
-      if (ballot(near) != 0) {
-#pragma unroll
-        for (int j = 0; j < V; ++j) p0_extremes<T>(e[j], valid[u], acc);
-      }
+      // Past the first tiles an element rarely reaches the wavefront's running extremes:
+      // the wavefront tests that first (compares against uniform values) and updates the
+      // lanes' extremes and their counts only when some element passes.
+      p0_extremes_wave<T, V>(e, valid[u], acc);
       if (BRACKET && SPLIT && HIST) {  // the device proposal that counts its interior
 #pragma unroll
         for (int j = 0; j < V; ++j)
@@ -1031,7 +1024,9 @@ __device__ __noinline__ void spec_interval(const T *smp, int64_t nsmp, const CpC
   for (int b = tid; b < g.nbins; b += BLOCK) sh.rh[b] = 0u;
   __syncthreads();
   const Key klo = (Key)g.klo, khi = (Key)g.khi;
-  // eight 16-byte loads in flight per thread, then their keys into the bins
+  // eight 16-byte loads in flight per thread, then their keys into the bins (sixteen would
+  // take the whole sample of a 2^28 float input in one round trip, but spill this function's
+  // registers)
   using Vec = typename Traits<T>::Vec;
   constexpr int V = Traits<T>::kVec, R = 8;
   const Vec *sv = (const Vec *)smp;
@@ -1146,6 +1141,8 @@ __device__ inline void run_pass(const SelectArgs<T> &a, Shared<T, BLOCK> &sh, in
     acc.sum = 0;
     acc.mn = t_inf<T>();
     acc.mx = -t_inf<T>();
+    acc.wmn = t_inf<T>();
+    acc.wmx = -t_inf<T>();
     acc.cmn = acc.cmx = 0;
     acc.nnan = acc.nneg = acc.npos = acc.cle_a = acc.clt_b = 0;
     acc.Aa = acc.Ba = acc.Ab = acc.Bb = 0;
