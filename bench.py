@@ -8,15 +8,19 @@ i.e. 64 calls of select_kth on inputs already resident in HBM, enqueued
 back to back on one stream.  The metric is exact-selection elements/s
 (sum of n over the step's calls / step time); the JSON line also carries the
 HBM roofline of the selection kernel and the CPU oracle timed on a bounded
-sample of the same workload.  Three more legs compare the other forms with
-the plain single-array method on the same GPU (their own keys in the line):
-"batched" (4096 lognormal arrays of log-uniform sizes in one graph-captured
-launch vs a loop of single-array calls), "lms" (1024 least-median-of-squares
-candidates over 2^20 rows) and "learned" (the learned bracket proposal vs the
-plain method on held-out 2^26-element mixture arrays; training untimed).  A
-fourth, "schedules", times the method under four schedules of its compaction
-(cutting-plane passes to the end, split after one evaluation, split at the first
-trial point, and the default: the first evaluation counts, the next pass compacts).
+sample of the same workload.  Further legs (their own keys in the line):
+"small" (2^20 float32 uniform medians, seeds 0..9, default and cutting plane to
+the end), "batched" (4096 lognormal arrays of log-uniform sizes in one
+graph-captured launch vs a loop of single-array calls), "batched_large" (64
+arrays of 2^22 elements, one or 16 workgroups per array), "lms" (1024
+least-median-of-squares candidates over 2^20 rows), "lts" and "knn" (Section 6's
+trimmed squares at the LMS shape; 1024 queries over 2^20 points), "transform"
+(2^26 values with 1e20 outliers, cutting plane on x and on the log transform),
+"learned" (the learned bracket proposal vs the plain method and the
+sample-quantile baseline on 128 held-out 2^26-element mixture arrays; training
+untimed) and "schedules" (the method under four schedules of its compaction:
+cutting-plane passes to the end, split after one evaluation, split at the first
+trial point, and the default).  --legs and --no-sweep select legs for profiling.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 
@@ -388,7 +392,8 @@ def learned_leg(sel, cps, torch, held_out: int = 128, chunk: int = 8) -> dict:
     out["learned_fewer_reads_than_sampled"] = int(np.sum(np.array(passes["learned"]) <
                                                          np.array(passes["sampled"])))
     out["speedup_vs_plain"] = float(t_plain.mean() / t_learned.mean())
-    out["sampled_note"] = "non-learned baseline: sorted stride sample, +-4 sd of the sample rank"
+    out["sampled_note"] = ("non-learned baseline: order statistics of the same stride sample "
+                           "(radix-selected), +-4 sd of the sample rank")
     out["train_s"] = round(train_s, 2)
     out["train"] = {"arrays": 100_000, "array_size": 1 << 18, "epochs": EPOCHS,
                     "first_loss": rep["first_loss"], "final_loss": rep["final_loss"],
