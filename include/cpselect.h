@@ -406,12 +406,33 @@ int cps_autotune_batched(cps_handle *h, const void *const *ptrs_dev, const int64
  * residuals are bit-identical to that sequence in IEEE double precision; the medians are
  * then exact.  out_dev[c] receives candidate c's median with its counts among the r_i.
  * X_dev: n x p row-major doubles; y_dev: n doubles (device memory, caller-owned).
- * The residuals are materialised in the handle's workspace (m * n doubles) and selected
- * with the batched kernel, in two launches plus one for the descriptors.
+ * Same as lms_median_sq_residuals_ex with form CPS_LMS_AUTO.
  * Errors: CPS_EINVAL for null pointers, n < 1, p outside [1, 16], m < 1 or m > 1048560. */
 int lms_median_sq_residuals(cps_handle *h, const double *X_dev, const double *y_dev,
                             const double *betas_dev, int64_t n, int32_t p, int64_t m,
                             cps_result *out_dev, void *stream);
+
+/* How lms_median_sq_residuals_ex finds the medians (all forms give the same value, counts
+ * and status):
+ * CPS_LMS_MATERIALISED: every r_i is written to the handle's workspace (m * n doubles) and
+ *   the batched kernel selects within each candidate's n squares.
+ * CPS_LMS_FILTERED (n from 2^15 to 2^31 - 1): each candidate's sampled bracket (a, b) is
+ *   taken from the squares of a fixed sample of rows (as the batched kernel samples an array
+ *   of n elements), one kernel forms every r_i and keeps only those in (a, b) (and NaN),
+ *   with #(r <= a), and the kept squares are packed and selected at rank k - #(r <= a).  A
+ *   candidate whose bracket does not hold the median, or whose kept squares exceed n/8, gets
+ *   its whole array written and selected as in the materialised form.  The workspace holds
+ *   m * n + m * (n/8) doubles.  `passes` then counts the one pass that forms the residuals
+ *   plus the selection's passes over the packed squares.
+ * CPS_LMS_AUTO: the filtered form where n allows it, else the materialised one. */
+enum cps_lms_form { CPS_LMS_AUTO = 0, CPS_LMS_MATERIALISED = 1, CPS_LMS_FILTERED = 2 };
+
+/* lms_median_sq_residuals with a choice of form (above).  Errors: as
+ * lms_median_sq_residuals, and CPS_EINVAL for a form outside cps_lms_form, or
+ * CPS_LMS_FILTERED with n outside [2^15, 2^31). */
+int lms_median_sq_residuals_ex(cps_handle *h, const double *X_dev, const double *y_dev,
+                               const double *betas_dev, int64_t n, int32_t p, int64_t m,
+                               int32_t form, cps_result *out_dev, void *stream);
 
 /* The k-th smallest element of each array (as select_kth_batched_ex) and the sum of each
  * array's k smallest elements, ksum_dev[i] = sum_{x < v} x + (k - #(x < v)) v with v = x_(k)

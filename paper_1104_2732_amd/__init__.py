@@ -120,11 +120,13 @@ EXPORTS = ("cps_create", "cps_destroy", "cps_status_string", "cps_last_hip_error
            "cps_default_options", "cps_reserve", "select_kth", "select_kth_ex", "cps_objective",
            "cps_default_batch_options", "select_kth_batched", "select_kth_batched_ex",
            "cps_reserve_batched", "cps_autotune_batched", "lms_median_sq_residuals",
+           "lms_median_sq_residuals_ex",
            "cps_mixture_generate", "cps_features", "cps_mlp_forward", "cps_mlp_loss_grad",
            "cps_mlp_adam", "cps_mlp_init", "cps_learned_bracket", "select_kth_learned",
            "cps_mlp_train", "select_kth_sampled", "cps_sample_bracket", "cps_model_save",
            "cps_model_load", "select_kth_noalloc", "select_kth_batched_ksum", "lts_trimmed_sq", "knn_mean")
 STATUS_BADARG = 4
+LMS_AUTO, LMS_MATERIALISED, LMS_FILTERED = 0, 1, 2  # cps_lms_form
 
 
 def lib() -> ctypes.CDLL:
@@ -177,6 +179,8 @@ def lib() -> ctypes.CDLL:
     L.cps_autotune_batched.restype = c_int
     L.lms_median_sq_residuals.argtypes = [vp, vp, vp, vp, i64, i32, i64, vp, vp]
     L.lms_median_sq_residuals.restype = c_int
+    L.lms_median_sq_residuals_ex.argtypes = [vp, vp, vp, vp, i64, i32, i64, i32, vp, vp]
+    L.lms_median_sq_residuals_ex.restype = c_int
     u64, f32 = ctypes.c_uint64, ctypes.c_float
     L.cps_mixture_generate.argtypes = [vp, u64, i64, i64, i64, vp, vp, vp]
     L.cps_features.argtypes = [vp, vp, vp, vp, i64, c_int, vp, vp, vp, vp]
@@ -396,8 +400,9 @@ class Selector:
 
     # -- least median of squares -------------------------------------------------------
 
-    def lms_median_sq_residuals_async(self, X, y, betas, out) -> None:
-        """Enqueue lms_median_sq_residuals: X (n x p), y (n), betas (m x p), float64 CUDA tensors."""
+    def lms_median_sq_residuals_async(self, X, y, betas, out, form: int = 0) -> None:
+        """Enqueue lms_median_sq_residuals_ex: X (n x p), y (n), betas (m x p), float64 CUDA
+        tensors; form LMS_AUTO, LMS_MATERIALISED or LMS_FILTERED."""
         import torch
         for t in (X, y, betas):
             if not t.is_cuda or not t.is_contiguous() or t.dtype != torch.float64:
@@ -406,17 +411,17 @@ class Selector:
         m = betas.shape[0]
         if y.numel() != n or betas.shape[1] != p:
             raise ValueError("shape mismatch between X, y and betas")
-        rc = lib().lms_median_sq_residuals(self._h, ctypes.c_void_p(X.data_ptr()),
-                                           ctypes.c_void_p(y.data_ptr()),
-                                           ctypes.c_void_p(betas.data_ptr()), n, p, m,
-                                           ctypes.c_void_p(out.data_ptr()),
-                                           ctypes.c_void_p(_stream_ptr(self.device)))
-        _check(rc, "lms_median_sq_residuals")
+        rc = lib().lms_median_sq_residuals_ex(self._h, ctypes.c_void_p(X.data_ptr()),
+                                              ctypes.c_void_p(y.data_ptr()),
+                                              ctypes.c_void_p(betas.data_ptr()), n, p, m, form,
+                                              ctypes.c_void_p(out.data_ptr()),
+                                              ctypes.c_void_p(_stream_ptr(self.device)))
+        _check(rc, "lms_median_sq_residuals_ex")
 
-    def lms_median_sq_residuals(self, X, y, betas) -> np.ndarray:
+    def lms_median_sq_residuals(self, X, y, betas, form: int = 0) -> np.ndarray:
         import torch
         out = self.new_results(betas.shape[0])
-        self.lms_median_sq_residuals_async(X, y, betas, out)
+        self.lms_median_sq_residuals_async(X, y, betas, out, form)
         torch.cuda.synchronize(self.device)
         return _as_records(out, RESULT_DTYPE).copy()
 

@@ -468,39 +468,89 @@ int cps_reserve_batched(cps_handle *h, int dtype, const cps_batch_options *opt) 
   return r.team_records > 0 ? ensure_team_records(h, nullptr) : CPS_OK;
 }
 
+int lms_median_sq_residuals_ex(cps_handle *h, const double *X_dev, const double *y_dev,
+                               const double *betas_dev, int64_t n, int32_t p, int64_t m,
+                               int32_t form, cps_result *out_dev, void *stream) {
+  if (!h || !X_dev || !y_dev || !betas_dev || !out_dev || n < 1 || p < 1 || p > 16 || m < 1 ||
+      m > (int64_t)65535 * 16 || form < CPS_LMS_AUTO || form > CPS_LMS_FILTERED)
+    return CPS_EINVAL;
+  const bool can_filter = n >= ((int64_t)1 << 15) && n < ((int64_t)1 << 31);
+  if (form == CPS_LMS_FILTERED && !can_filter) return CPS_EINVAL;
+  const bool filtered = form == CPS_LMS_FILTERED || (form == CPS_LMS_AUTO && can_filter);
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t rank = (n + 1) / 2;
+  const size_t dsz = align_up((size_t)m * 8, 256);
+  const size_t off_desc = align_up((size_t)m * (size_t)n * sizeof(double), 256);
+  char *base;
+  const void *const *ptrs;
+  const int64_t *sizes, *ks;
+  const int64_t *side = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(h->mu);
+    if (!filtered) {
+      const size_t bytes = off_desc + 3 * dsz;
+      int rc = ensure_buffer(h->lws, h->lws_bytes, bytes, s);
+      if (rc) return rc;
+      base = (char *)h->lws;
+      hipError_t e = cps::launch_lms_residuals(X_dev, y_dev, betas_dev, n, p, m, rank,
+                                               (double *)base, (const double **)(base + off_desc),
+                                               (int64_t *)(base + off_desc + dsz),
+                                               (int64_t *)(base + off_desc + 2 * dsz), h->cu_count, s);
+      if (e != hipSuccess) return hip_fail(e);
+      ptrs = (const void *const *)(base + off_desc);
+      sizes = (const int64_t *)(base + off_desc + dsz);
+      ks = (const int64_t *)(base + off_desc + 2 * dsz);
+    } else {
+      // R (m x n), C (m x cap), sampled squares, brackets, segment counts, sides, flags,
+      // descriptors
+      cps::LmsFilterBufs w;
+      const bool vec = (uintptr_t)X_dev % 16 == 0 && (uintptr_t)y_dev % 16 == 0;
+      cps::lms_filter_shape(n, m, p, vec, h->cu_count, &w.bx, &w.nseg, &w.seg);
+      w.cap = cps::lms_filter_cap(n);
+      const size_t off_c = off_desc;
+      const size_t off_rs = off_c + align_up((size_t)m * (size_t)w.cap * sizeof(double), 256);
+      const size_t off_ab = off_rs + align_up((size_t)m * 16384 * sizeof(double), 256);
+      const size_t off_cnt = off_ab + 2 * dsz;
+      const size_t off_side = off_cnt + align_up((size_t)2 * m * w.nseg * sizeof(uint32_t), 256);
+      const size_t off_full = off_side + 2 * dsz;
+      const size_t off_ptrs = off_full + dsz;
+      const size_t bytes = off_ptrs + 3 * dsz;
+      int rc = ensure_buffer(h->lws, h->lws_bytes, bytes, s);
+      if (rc) return rc;
+      base = (char *)h->lws;
+      w.R = (double *)base;
+      w.C = (double *)(base + off_c);
+      w.Rs = (double *)(base + off_rs);
+      w.ab = (double *)(base + off_ab);
+      w.cnt = (uint32_t *)(base + off_cnt);
+      w.side = (int64_t *)(base + off_side);
+      w.full = (int32_t *)(base + off_full);
+      w.ptrs = (const double **)(base + off_ptrs);
+      w.sizes = (int64_t *)(base + off_ptrs + dsz);
+      w.ks = (int64_t *)(base + off_ptrs + 2 * dsz);
+      hipError_t e = cps::launch_lms_filtered(X_dev, y_dev, betas_dev, n, p, m, rank, w, s);
+      if (e != hipSuccess) return hip_fail(e);
+      ptrs = (const void *const *)w.ptrs;
+      sizes = w.sizes;
+      ks = w.ks;
+      side = w.side;
+    }
+  }
+  // the batched defaults: one 1024-thread workgroup per candidate at a time, the counting
+  // evaluation at the first trial point
+  cps_batch_options o;
+  cps_default_batch_options(&o);
+  int rc = select_kth_batched_ex(h, ptrs, sizes, ks, m, CPS_F64, &o, out_dev, stream);
+  if (rc || !side) return rc;
+  hipError_t e = cps::launch_lms_fixup(out_dev, side, m, s);
+  return e == hipSuccess ? CPS_OK : hip_fail(e);
+}
+
 int lms_median_sq_residuals(cps_handle *h, const double *X_dev, const double *y_dev,
                             const double *betas_dev, int64_t n, int32_t p, int64_t m,
                             cps_result *out_dev, void *stream) {
-  if (!h || !X_dev || !y_dev || !betas_dev || !out_dev || n < 1 || p < 1 || p > 16 || m < 1 ||
-      m > (int64_t)65535 * 16)
-    return CPS_EINVAL;
-  hipStream_t s = (hipStream_t)stream;
-  size_t off_desc, bytes;
-  {
-    std::lock_guard<std::mutex> lk(h->mu);
-    off_desc = align_up((size_t)m * (size_t)n * sizeof(double), 256);
-    bytes = off_desc + 3 * align_up((size_t)m * 8, 256);
-    int rc = ensure_buffer(h->lws, h->lws_bytes, bytes, s);
-    if (rc) return rc;
-    char *base = (char *)h->lws;
-    double *R = (double *)base;
-    const double **ptrs = (const double **)(base + off_desc);
-    int64_t *sizes = (int64_t *)(base + off_desc + align_up((size_t)m * 8, 256));
-    int64_t *ks = (int64_t *)(base + off_desc + 2 * align_up((size_t)m * 8, 256));
-    hipError_t e = cps::launch_lms_residuals(X_dev, y_dev, betas_dev, n, p, m, (n + 1) / 2, R,
-                                             ptrs, sizes, ks, h->cu_count, s);
-    if (e != hipSuccess) return hip_fail(e);
-  }
-  char *base = (char *)h->lws;
-  // the batched defaults: one 1024-thread workgroup per candidate at a time, the counting
-  // evaluation at the first trial point (7.7 ms for 1024 candidates x 2^20 rows, against
-  // 8.7 ms for the best split: whole-array split buffers, fraction 0.75)
-  cps_batch_options o;
-  cps_default_batch_options(&o);
-  return select_kth_batched_ex(h, (const void *const *)(base + off_desc),
-                               (const int64_t *)(base + off_desc + align_up((size_t)m * 8, 256)),
-                               (const int64_t *)(base + off_desc + 2 * align_up((size_t)m * 8, 256)),
-                               m, CPS_F64, &o, out_dev, stream);
+  return lms_median_sq_residuals_ex(h, X_dev, y_dev, betas_dev, n, p, m, CPS_LMS_AUTO, out_dev,
+                                    stream);
 }
 
 int lts_trimmed_sq(cps_handle *h, const double *X_dev, const double *y_dev,

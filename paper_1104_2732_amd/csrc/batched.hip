@@ -13,6 +13,7 @@
 #include "cps_device.h"
 #include "cps_kernels.h"
 #include "cps_passes.h"
+#include "cps_sample.h"
 
 namespace cps {
 
@@ -55,6 +56,7 @@ template <typename T, int BLOCK> struct BShared {
   int32_t jpart, jparts;          // its part, and the parts of that array
   int32_t flag;                   // workgroup-wide flags (sampled bracket, last arrival)
   uint64_t kext[2];               // sampled keys' minimum and maximum
+  SampleLds smp;                  // the sampled bracket's bins
   int64_t kcopy;                  // elements of the sampled bracket's copy (-1: not whole)
   double kpa, kpb;                // the sampled bracket
   double ksuma;                   // sum of the elements at or below the bracket's lower end
@@ -351,101 +353,16 @@ __device__ void block_pass0(const Span<T> &sp, P0Acc<T> &acc) {
 // ------------------------------------------------------------------ sampled bracket
 
 // The sampled bracket of one array (used by arrays of at least kBatchPropMin elements):
-// S = kPropSample elements, or kPropSampleBig from kPropBigN elements on (the bracket's width
-// goes as 1/sqrt(S), and with it the copy pass 0 writes and the later passes read), in runs
-// of kPropRun neighbours at evenly spaced places (so the sample touches few lines), counted
-// in 2^12 key bins over the sample's own range; the bracket runs
-// from just below the bin that holds sample rank floor(q - d) to just above the bin that holds
-// rank ceil(q + d), where q = S (k - 1/2) / n is the rank's place among the S sampled
-// elements and d = 4 sqrt(S p (1 - p)) + 2, p = (k - 1/2) / n (four binomial standard
-// deviations).  An end whose rank falls outside the sample is open (-inf or +inf).  Pass 0's
-// counts decide whether each end holds, so the result never depends on the sample.  Every
-// workgroup of an array computes the same bracket.  False (no bracket) when the sample holds
-// NaN or an infinity, only one value, or both ends would be open.
-template <typename T> __device__ constexpr int32_t c_dtype() { return sizeof(T) == 4 ? 0 : 1; }
-
-constexpr int kPropSample = 4096;       // sample elements of arrays below kPropBigN
-constexpr int kPropSampleBig = 16384;   // ... and from kPropBigN on (a quarter as wide a bracket)
-constexpr int64_t kPropBigN = (int64_t)1 << 18;
-constexpr int kPropRun = 16;
-constexpr int64_t kBatchPropMin = (int64_t)1 << 15;
-
+// sample_size(n) elements in runs of kPropRun neighbours at evenly spaced places (so the
+// sample touches few lines); the rule is sample_bracket_rule's.  Pass 0's counts decide
+// whether each end holds.  Every workgroup of an array computes the same bracket.
 template <typename T, int BLOCK>
 __device__ __noinline__ bool sample_bracket(const T *x, int64_t n, int64_t k, BShared<T, BLOCK> &sh, T &pa,
                                T &pb) {
-  using Key = typename Traits<T>::Key;
-  const int tid = threadIdx.x;
-  const int S = n >= kPropBigN ? kPropSampleBig : kPropSample;
-  // (n >= kBatchPropMin, and n >= kPropBigN for the larger sample: the runs lie inside x and
-  // do not overlap)
-  const int64_t stride = n / (S / kPropRun);
+  const int S = sample_size(n);
+  const int64_t stride = sample_stride(n, S);
   auto sample = [&](int i) -> T { return x[(int64_t)(i / kPropRun) * stride + i % kPropRun]; };
-  if (tid == 0) {
-    sh.kext[0] = ~0ull;
-    sh.kext[1] = 0ull;
-    sh.flag = 0;
-    sh.misc[4] = sh.misc[5] = 0;
-  }
-  __syncthreads();
-  Key kmn = (Key)~(Key)0, kmx = 0;
-  bool bad = false;
-  for (int i = tid; i < S; i += BLOCK) {  // the sample's key range (the keys are read again below)
-    const T v = sample(i);
-    bad = bad || !(v == v) || v == t_inf<T>() || v == -t_inf<T>();
-    const Key kv = Traits<T>::key(v);
-    kmn = kv < kmn ? kv : kmn;
-    kmx = kv > kmx ? kv : kmx;
-  }
-  atomicMin(reinterpret_cast<unsigned long long *>(&sh.kext[0]), (unsigned long long)kmn);
-  atomicMax(reinterpret_cast<unsigned long long *>(&sh.kext[1]), (unsigned long long)kmx);
-  if (bad) atomicOr(&sh.flag, 1);
-  __syncthreads();
-  const uint64_t klo = sh.kext[0], khi = sh.kext[1];
-  if (sh.flag != 0 || klo >= khi) return false;  // (uniform)
-  int shift = 0;
-  while (((khi - klo) >> shift) >= (uint64_t)kHistMaxBins) ++shift;
-  const int nbins = (int)((khi - klo) >> shift) + 1;
-  for (int b = tid; b < nbins; b += BLOCK) sh.rh[b] = 0u;
-  __syncthreads();
-  for (int i = tid; i < S; i += BLOCK)
-    atomicAdd(&sh.rh[(uint32_t)(((uint64_t)Traits<T>::key(sample(i)) - klo) >> shift)], 1u);
-  __syncthreads();
-  const double Sd = (double)S;
-  const double p = ((double)k - 0.5) / (double)n;
-  const double q = Sd * p, d = 4.0 * __builtin_sqrt(Sd * p * (1.0 - p)) + 2.0;
-  const double r0 = __builtin_floor(q - d), r1 = __builtin_ceil(q + d);
-  const bool open0 = r0 < 1.0, open1 = r1 > Sd;
-  if (open0 && open1) return false;
-  const uint64_t rank0 = open0 ? 1 : (uint64_t)r0, rank1 = open1 ? (uint64_t)S : (uint64_t)r1;
-  // the bins holding the two sample ranks: an exclusive scan of the bins in a fixed order
-  constexpr int BPT = kHistMaxBins / BLOCK;
-  uint64_t hv[BPT];
-  uint64_t tot = 0;
-#pragma unroll
-  for (int j = 0; j < BPT; ++j) {
-    const int b = tid * BPT + j;
-    hv[j] = b < nbins ? sh.rh[b] : 0u;
-    tot += hv[j];
-  }
-  uint64_t cum = block_exclusive_scan<BLOCK>(tot, sh.wsum);
-#pragma unroll
-  for (int j = 0; j < BPT; ++j) {
-    if (cum < rank0 && rank0 <= cum + hv[j]) sh.misc[4] = tid * BPT + j;
-    if (cum < rank1 && rank1 <= cum + hv[j]) sh.misc[5] = tid * BPT + j;
-    cum += hv[j];
-  }
-  __syncthreads();
-  const uint64_t b0 = (uint64_t)sh.misc[4], b1 = (uint64_t)sh.misc[5];
-  __syncthreads();
-  // the largest value below the lower bin, the smallest above the upper one (keys of
-  // finite values, so both neighbours are keys of values: +-inf at worst)
-  const uint64_t first0 = klo + (b0 << shift);
-  uint64_t last1 = klo + ((b1 + 1) << shift) - 1;
-  if (last1 > khi || last1 < klo) last1 = khi;
-  pa = open0 ? -t_inf<T>() : Traits<T>::unkey((Key)(first0 - 1));
-  pb = open1 ? t_inf<T>() : Traits<T>::unkey((Key)(last1 + 1));
-  // the interior (a, b) holds at least one value of T (its key bins are not empty)
-  return pa < pb && next_up((double)pa, c_dtype<T>()) <= next_down((double)pb, c_dtype<T>());
+  return sample_bracket_rule<T, BLOCK>(sample, S, n, k, sh, pa, pb);
 }
 
 // Pass 0 of an array with a sampled bracket (a, b), over one part of it: the extremes and

@@ -114,6 +114,18 @@ def _team_batch(dtype, seed):
     ks.append(5)
     arrays.append(np.full(120_000, 2.5, dtype=dtype))
     ks.append(60_000)
+    # an exact zero in the first sampled run, far below the rest: the sample's key bins are
+    # then too wide for its ranks, and the bracket's ends are split again
+    x = (1000.0 + workloads.single_array("normal", 180_001, dtype, seed=seed,
+                                         tag="gpu-teams-zero")).astype(dtype)
+    x[0] = 0
+    arrays.append(x)
+    ks.append(90_001)
+    x = np.abs(workloads.single_array("normal", (1 << 18) + 3, dtype, seed=seed,
+                                      tag="gpu-teams-zero2")).astype(dtype)
+    x[1] = 0
+    arrays.append(x)
+    ks.append(((1 << 18) + 3) // 3)
     return arrays, ks
 
 

@@ -2,10 +2,12 @@
 
 The residuals are formed left to right without fused multiply-add on both
 sides, so the medians must agree bit for bit and the counts exactly.  Small
-problems are compared candidate by candidate; the full-size problem (2^20 rows,
-p = 8, 1024 candidates, 30 % of rows shifted) on a seeded sample of candidates,
-and every candidate through the defining invariant (Section 1) against
-residuals recomputed by the oracle.
+problems are compared candidate by candidate in every form (materialised, and
+filtered where n allows it); the full-size problem (2^20 rows, p = 8, 1024
+candidates, 30 % of rows shifted) on a seeded sample of candidates against
+residuals recomputed by the oracle, and the two forms against each other on
+every candidate.  Inputs whose sampled rows mislead the filter's bracket check
+the fallback to the materialised form.
 """
 import numpy as np
 import pytest
@@ -32,23 +34,37 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
+FORMS = {"auto": 0, "materialised": 1, "filtered": 2}
+
+
+@pytest.mark.parametrize("form", ["auto", "materialised", "filtered"])
 @pytest.mark.parametrize("n,p,m", [(1, 1, 1), (7, 3, 5), (1001, 8, 40), (50_000, 8, 33),
-                                   (20_001, 5, 17), (4096, 16, 3)])
-def test_lms_small(sel, oracle_mod, n, p, m):
+                                   (20_001, 5, 17), (4096, 16, 3), (40_001, 5, 70),
+                                   (1 << 15, 16, 3), (300_000, 8, 65), (262_147, 3, 2)])
+def test_lms_small(sel, oracle_mod, n, p, m, form):
+    import paper_1104_2732_amd as cps
+    if form == "filtered" and n < (1 << 15):
+        with pytest.raises(cps.CpsError):
+            sel.lms_median_sq_residuals(_dev(np.zeros((n, p))), _dev(np.zeros(n)),
+                                        _dev(np.zeros((m, p))), form=FORMS[form])
+        return
     X, y, beta, betas = workloads.lms_problem(n, p, m, seed=n + p, contamination=0.3) if n >= p \
         else (np.random.default_rng(0).standard_normal((n, p)), np.zeros(n), None,
               np.random.default_rng(1).standard_normal((m, p)))
-    print(f"case lms n={n} p={p} m={m}", flush=True)
-    res = sel.lms_median_sq_residuals(_dev(X), _dev(y), _dev(betas))
+    print(f"case lms n={n} p={p} m={m} form={form}", flush=True)
+    res = sel.lms_median_sq_residuals(_dev(X), _dev(y), _dev(betas), form=FORMS[form])
     ref = oracle_mod.lms_median_sq(X, y, betas)
     for c in range(m):
         r = {f: res[c][f].item() for f in res.dtype.names}
         assert_same_result(r, ref[c], f"candidate {c}")
 
 
-def test_lms_exact_fit_zero_median(sel):
+@pytest.mark.parametrize("n", [30_001, 70_000])
+def test_lms_exact_fit_zero_median(sel, n):
+    """Residuals exactly 0 on 70 % of the rows (a median of 0 with 70 % ties; at 70 000 rows
+    the filtered form's bracket cannot hold it, and the candidate is selected whole)."""
     rng = np.random.default_rng(5)
-    n, p = 30_001, 8
+    p = 8
     X = rng.standard_normal((n, p))
     beta = rng.standard_normal(p)
     s = X[:, 0] * beta[0]
@@ -68,6 +84,9 @@ def test_lms_full_size_sampled(sel, oracle_mod):
     print("case lms full size", flush=True)
     res = sel.lms_median_sq_residuals(_dev(X), _dev(y), _dev(betas))
     assert np.all(res["status"] == 0)
+    mat = sel.lms_median_sq_residuals(_dev(X), _dev(y), _dev(betas), form=FORMS["materialised"])
+    for f in ("value_bits", "less", "equal", "greater", "status"):
+        assert np.array_equal(res[f], mat[f]), f
     k = (n + 1) // 2
     rng = np.random.default_rng(1)
     sample = rng.choice(m, size=12, replace=False)
@@ -104,6 +123,63 @@ def test_lms_nonfinite_residuals(sel, oracle_mod):
     y[5] = np.nan
     print("case lms NaN residuals", flush=True)
     res = sel.lms_median_sq_residuals(_dev(X), _dev(y), _dev(betas))
+    assert np.all(res["status"] == cps.STATUS_NAN)
+    with pytest.raises(oracle.OracleError):
+        oracle_mod.lms_median_sq(X, y, betas)
+
+
+def _sampled_rows(n):
+    """The rows whose residuals the filtered form samples for its bracket (runs of 16
+    neighbours at n / (S / 16) apart, S = 4096 below 2^18 rows, else 16384)."""
+    S = 4096 if n < (1 << 18) else 16384
+    stride = n // (S // 16)
+    i = np.arange(S)
+    return (i // 16) * stride + i % 16
+
+
+@pytest.mark.parametrize("n", [1 << 16, (1 << 18) + 6])
+def test_lms_filtered_misleading_sample(sel, oracle_mod, n):
+    """Candidates whose sampled rows fit well and the rest badly (the bracket then misses
+    the median, and the candidate's whole array is selected), beside ordinary candidates,
+    in one call: every result matches the oracle's."""
+    rng = np.random.default_rng(41)
+    p, m = 8, 9
+    X = rng.standard_normal((n, p))
+    betas = rng.standard_normal((m, p))
+    s = X[:, 0] * betas[0, 0]
+    for j in range(1, p):
+        s = s + X[:, j] * betas[0, j]
+    y = s + 10.0 + rng.uniform(0.0, 1.0, n)       # candidate 0: residuals in (100, 121)
+    rows = _sampled_rows(n)
+    y[rows] = s[rows] + rng.uniform(0.0, 1.0, rows.size)  # ... but below 1 on the sample
+    print(f"case lms misleading sample n={n}", flush=True)
+    for form in ("filtered", "auto", "materialised"):
+        res = sel.lms_median_sq_residuals(_dev(X), _dev(y), _dev(betas), form=FORMS[form])
+        ref = oracle_mod.lms_median_sq(X, y, betas)
+        for c in range(m):
+            assert_same_result({f: res[c][f].item() for f in res.dtype.names}, ref[c],
+                               f"candidate {c} form {form}")
+
+
+def test_lms_filtered_nonfinite(sel, oracle_mod):
+    """The filtered form with residuals that overflow to +inf (outside every bracket) and
+    with NaN (kept by the filter, so the packed selection reports it)."""
+    import oracle
+    import paper_1104_2732_amd as cps
+    rng = np.random.default_rng(23)
+    n, p, m = 40_001, 4, 11
+    X = rng.standard_normal((n, p))
+    y = rng.standard_normal(n)
+    betas = rng.standard_normal((m, p))
+    X[rng.choice(n, size=400, replace=False)] *= 1e200
+    print("case lms filtered +inf residuals", flush=True)
+    res = sel.lms_median_sq_residuals(_dev(X), _dev(y), _dev(betas), form=FORMS["filtered"])
+    ref = oracle_mod.lms_median_sq(X, y, betas)
+    for c in range(m):
+        assert_same_result({f: res[c][f].item() for f in res.dtype.names}, ref[c], f"candidate {c}")
+    y[7] = np.nan
+    print("case lms filtered NaN residuals", flush=True)
+    res = sel.lms_median_sq_residuals(_dev(X), _dev(y), _dev(betas), form=FORMS["filtered"])
     assert np.all(res["status"] == cps.STATUS_NAN)
     with pytest.raises(oracle.OracleError):
         oracle_mod.lms_median_sq(X, y, betas)
