@@ -481,69 +481,48 @@ int lms_median_sq_residuals_ex(cps_handle *h, const double *X_dev, const double 
   const int64_t rank = (n + 1) / 2;
   const size_t dsz = align_up((size_t)m * 8, 256);
   const size_t off_desc = align_up((size_t)m * (size_t)n * sizeof(double), 256);
-  char *base;
-  const void *const *ptrs;
-  const int64_t *sizes, *ks;
-  const int64_t *side = nullptr;
-  {
-    std::lock_guard<std::mutex> lk(h->mu);
-    if (!filtered) {
-      const size_t bytes = off_desc + 3 * dsz;
-      int rc = ensure_buffer(h->lws, h->lws_bytes, bytes, s);
-      if (rc) return rc;
-      base = (char *)h->lws;
-      hipError_t e = cps::launch_lms_residuals(X_dev, y_dev, betas_dev, n, p, m, rank,
-                                               (double *)base, (const double **)(base + off_desc),
-                                               (int64_t *)(base + off_desc + dsz),
-                                               (int64_t *)(base + off_desc + 2 * dsz), h->cu_count, s);
-      if (e != hipSuccess) return hip_fail(e);
-      ptrs = (const void *const *)(base + off_desc);
-      sizes = (const int64_t *)(base + off_desc + dsz);
-      ks = (const int64_t *)(base + off_desc + 2 * dsz);
-    } else {
-      // R (m x n), C (m x cap), sampled squares, brackets, segment counts, sides, flags,
-      // descriptors
-      cps::LmsFilterBufs w;
-      const bool vec = (uintptr_t)X_dev % 16 == 0 && (uintptr_t)y_dev % 16 == 0;
-      cps::lms_filter_shape(n, m, p, vec, h->cu_count, &w.bx, &w.nseg, &w.seg);
-      w.cap = cps::lms_filter_cap(n);
-      const size_t off_c = off_desc;
-      const size_t off_rs = off_c + align_up((size_t)m * (size_t)w.cap * sizeof(double), 256);
-      const size_t off_ab = off_rs + align_up((size_t)m * 16384 * sizeof(double), 256);
-      const size_t off_cnt = off_ab + 2 * dsz;
-      const size_t off_side = off_cnt + align_up((size_t)2 * m * w.nseg * sizeof(uint32_t), 256);
-      const size_t off_full = off_side + 2 * dsz;
-      const size_t off_ptrs = off_full + dsz;
-      const size_t bytes = off_ptrs + 3 * dsz;
-      int rc = ensure_buffer(h->lws, h->lws_bytes, bytes, s);
-      if (rc) return rc;
-      base = (char *)h->lws;
-      w.R = (double *)base;
-      w.C = (double *)(base + off_c);
-      w.Rs = (double *)(base + off_rs);
-      w.ab = (double *)(base + off_ab);
-      w.cnt = (uint32_t *)(base + off_cnt);
-      w.side = (int64_t *)(base + off_side);
-      w.full = (int32_t *)(base + off_full);
-      w.ptrs = (const double **)(base + off_ptrs);
-      w.sizes = (int64_t *)(base + off_ptrs + dsz);
-      w.ks = (int64_t *)(base + off_ptrs + 2 * dsz);
-      hipError_t e = cps::launch_lms_filtered(X_dev, y_dev, betas_dev, n, p, m, rank, w, s);
-      if (e != hipSuccess) return hip_fail(e);
-      ptrs = (const void *const *)w.ptrs;
-      sizes = w.sizes;
-      ks = w.ks;
-      side = w.side;
-    }
+  std::lock_guard<std::mutex> lk(h->mu);
+  if (filtered) {
+    // R (m x n), C (m x cap), sampled squares, brackets, segment counts, flags
+    cps::LmsFilterBufs w;
+    const bool vec = (uintptr_t)X_dev % 16 == 0 && (uintptr_t)y_dev % 16 == 0;
+    cps::lms_filter_shape(n, m, p, vec, h->cu_count, &w.bx, &w.nseg, &w.seg);
+    w.cap = cps::lms_filter_cap(n);
+    const size_t off_c = off_desc;
+    const size_t off_rs = off_c + align_up((size_t)m * (size_t)w.cap * sizeof(double), 256);
+    const size_t off_ab = off_rs + align_up((size_t)m * 16384 * sizeof(double), 256);
+    const size_t off_cnt = off_ab + 2 * dsz;
+    const size_t off_full = off_cnt + align_up((size_t)2 * m * w.nseg * sizeof(uint32_t), 256);
+    const size_t bytes = off_full + dsz;
+    int rc = ensure_buffer(h->lws, h->lws_bytes, bytes, s);
+    if (rc) return rc;
+    char *base = (char *)h->lws;
+    w.R = (double *)base;
+    w.C = (double *)(base + off_c);
+    w.Rs = (double *)(base + off_rs);
+    w.ab = (double *)(base + off_ab);
+    w.cnt = (uint32_t *)(base + off_cnt);
+    w.full = (int32_t *)(base + off_full);
+    hipError_t e = cps::launch_lms_filtered(X_dev, y_dev, betas_dev, n, p, m, rank, w, out_dev, s);
+    return e == hipSuccess ? CPS_OK : hip_fail(e);
   }
+  const size_t bytes = off_desc + 3 * dsz;
+  int rc = ensure_buffer(h->lws, h->lws_bytes, bytes, s);
+  if (rc) return rc;
+  char *base = (char *)h->lws;
+  hipError_t e = cps::launch_lms_residuals(X_dev, y_dev, betas_dev, n, p, m, rank, (double *)base,
+                                           (const double **)(base + off_desc),
+                                           (int64_t *)(base + off_desc + dsz),
+                                           (int64_t *)(base + off_desc + 2 * dsz), h->cu_count, s);
+  if (e != hipSuccess) return hip_fail(e);
   // the batched defaults: one 1024-thread workgroup per candidate at a time, the counting
   // evaluation at the first trial point
   cps_batch_options o;
   cps_default_batch_options(&o);
-  int rc = select_kth_batched_ex(h, ptrs, sizes, ks, m, CPS_F64, &o, out_dev, stream);
-  if (rc || !side) return rc;
-  hipError_t e = cps::launch_lms_fixup(out_dev, side, m, s);
-  return e == hipSuccess ? CPS_OK : hip_fail(e);
+  return run_batched<double>(h, (const void *const *)(base + off_desc),
+                             (const int64_t *)(base + off_desc + dsz),
+                             (const int64_t *)(base + off_desc + 2 * dsz), m, &o, out_dev, nullptr,
+                             s);
 }
 
 int lms_median_sq_residuals(cps_handle *h, const double *X_dev, const double *y_dev,

@@ -233,116 +233,303 @@ __global__ __launch_bounds__(kLmsBracketBlock) void lms_bracket_kernel(
   }
 }
 
-// The filter: one candidate per lane (c = blockIdx.y * kLmsBlock + thread), every row of
-// segment s = blockIdx.x (rows [s * seg, min((s + 1) * seg, n))) in order.  The rows are the
-// same for every lane: the workgroup stages them through LDS in tiles of kLmsTile rows (one
-// row per thread, the next tile's loads in flight while the current one is used; one barrier
-// per tile), and each lane reads every row of a tile as a broadcast.  A square r of candidate
-// c with a < r < b (or NaN) is kept: written to c's array of the workspace at the segment's
-// first row plus the number kept before it in the segment (so a segment's kept squares stay
-// inside the segment's own rows, in row order).  The counts land in cnt[0][c][s] (kept) and
-// cnt[1][c][s] (#(r <= a)), nseg = gridDim.x segments per candidate.  VEC: X and y are
-// 16-byte aligned and P = 8 (each staged row is four 16-byte loads).
-constexpr int kLmsTile = 128;
-template <int P, bool VEC>
+// The filter: kLmsLane candidates per lane (c = blockIdx.y * kLmsCands + u * kLmsBlock +
+// thread for u < kLmsLane), every row of segment s = blockIdx.x (rows [s * seg,
+// min((s + 1) * seg, n))) in order.  The rows are the same for every lane, so each row of X
+// and its y are scalar loads (registers shared by the wavefront, read by the vector
+// arithmetic as operands; the workgroup's wavefronts read the same rows), two rows per step,
+// and each row serves the lane's kLmsLane candidates.  A square r of candidate c with
+// a < r < b (or NaN) is kept: written to c's array of the workspace at the segment's first
+// row plus the number kept before it in the segment (so a segment's kept squares stay inside
+// the segment's own rows, in row order).  The counts land in cnt[0][c][s] (kept) and
+// cnt[1][c][s] (#(r <= a)), nseg = gridDim.x segments per candidate.
+constexpr int kLmsLane = 2;
+constexpr int kLmsCands = kLmsBlock * kLmsLane;  // candidates per workgroup
+#ifndef CPS_LMS_STAGE
+#define CPS_LMS_STAGE 4
+#endif
+constexpr int kLmsStage = CPS_LMS_STAGE;  // kept squares staged in LDS per candidate
+template <int P>
 __global__ __launch_bounds__(kLmsBlock) void lms_filter_kernel(
     const double *__restrict__ X, const double *__restrict__ y, const double *__restrict__ betas,
     const double *__restrict__ ab, int64_t n, int32_t p, int64_t m, int64_t seg,
     double *__restrict__ R_out, uint32_t *__restrict__ cnt) {
   constexpr int PM = P > 0 ? P : 16;
-  static_assert(!VEC || PM % 2 == 0, "16-byte rows");
-  // a staged row: its PM values, then y, padded to a 16-byte multiple
-  constexpr int RW = (PM + 1 + 1) / 2 * 2;
-  __shared__ double sx[2][kLmsTile][RW];
+  constexpr int U = kLmsLane;
+  // Each candidate's kept squares gather in LDS and go out kLmsStage at a time, as 16-byte
+  // stores of contiguous places (single squares scattered over many candidates' arrays left
+  // most of each written line empty).
+  __shared__ double stg[kLmsCands][kLmsStage];
+  const bool pairs = n % 2 == 0;  // (every segment then starts 16-byte aligned)
   const int pp = P > 0 ? P : p;
   const int tid = threadIdx.x;
-  const int64_t c = (int64_t)blockIdx.y * kLmsBlock + tid;
-  const bool live = c < m;
-  double b[PM];
-#pragma unroll
-  for (int j = 0; j < PM; ++j) b[j] = live && j < pp ? betas[c * pp + j] : 0.0;
-  // a lane without a candidate stores nothing
-  const double lo = live ? ab[2 * c] : __builtin_inf();
-  const double hi = live ? ab[2 * c + 1] : -__builtin_inf();
   const int64_t sg = blockIdx.x, nseg = gridDim.x;
   const int64_t rb = sg * seg;
   const int64_t re = rb + seg < n ? rb + seg : n;
-  CPS_GLOBAL double *dst = (CPS_GLOBAL double *)R_out + (live ? c : 0) * n + rb;
-  const CPS_GLOBAL double *Xg = (const CPS_GLOBAL double *)X;
-  const CPS_GLOBAL double *yg = (const CPS_GLOBAL double *)y;
-  // one row per thread of the first kLmsTile threads
-  double lx[PM], ly = 0.0;
-  auto load_row = [&](int64_t t0) {
-    const int64_t i = t0 + tid;
-    const bool ok = tid < kLmsTile && i < re;
-    if (VEC) {
+  int64_t c[U];
+  bool live[U];
+  double b[U][PM], lo[U], hi[U];
+  CPS_GLOBAL double *dst[U];
+  CPS_GLOBAL double *put[U];  // the place of the first staged square
+  uint32_t below[U];          // #(r <= a)
+  int staged[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    c[u] = (int64_t)blockIdx.y * kLmsCands + u * kLmsBlock + tid;
+    live[u] = c[u] < m;
+#pragma unroll
+    for (int j = 0; j < PM; ++j) b[u][j] = live[u] && j < pp ? betas[c[u] * pp + j] : 0.0;
+    // a lane without a candidate stores nothing
+    lo[u] = live[u] ? ab[2 * c[u]] : __builtin_inf();
+    hi[u] = live[u] ? ab[2 * c[u] + 1] : -__builtin_inf();
+    dst[u] = (CPS_GLOBAL double *)R_out + (live[u] ? c[u] : 0) * n + rb;
+    put[u] = dst[u];
+    below[u] = 0;
+    staged[u] = 0;
+  }
+  auto flush = [&](int u, int k) {
+    const double *st = &stg[u * kLmsBlock + tid][0];
+    if (k == kLmsStage && pairs) {
       using D2 = double __attribute__((ext_vector_type(2)));
 #pragma unroll
-      for (int v = 0; v < PM / 2; ++v) {
-        const D2 w = ok ? ((const CPS_GLOBAL D2 *)(Xg + i * PM))[v] : D2{0.0, 0.0};
-        lx[2 * v] = w.x;
-        lx[2 * v + 1] = w.y;
-      }
+      for (int v = 0; v < kLmsStage / 2; ++v)
+        ((CPS_GLOBAL D2 *)put[u])[v] = D2{st[2 * v], st[2 * v + 1]};
     } else {
-#pragma unroll
-      for (int j = 0; j < PM; ++j) lx[j] = ok && j < pp ? Xg[i * pp + j] : 0.0;
+      for (int v = 0; v < k; ++v) put[u][v] = st[v];
     }
-    ly = ok ? yg[i] : 0.0;
+    put[u] += k;
   };
-  auto store_row = [&](int buf) {
-    if (tid < kLmsTile) {
-#pragma unroll
-      for (int j = 0; j < PM; ++j) sx[buf][tid][j] = lx[j];
-      sx[buf][tid][PM] = ly;
+  // the squares of a step first (independent chains of dependent double additions, which
+  // the scheduler interleaves), then their tests and stores (a branch each)
+  auto keep = [&](int u, double r) {
+    const bool le = r <= lo[u];
+    if (live[u] && !le && !(r >= hi[u])) {
+      stg[u * kLmsBlock + tid][staged[u]] = r;
+      if (++staged[u] == kLmsStage) {
+        flush(u, kLmsStage);
+        staged[u] = 0;
+      }
     }
+    below[u] += le ? 1u : 0u;
   };
-  // #(r <= a), and the next kept square's place
-  uint32_t below = 0;
-  CPS_GLOBAL double *put = dst;
-  load_row(rb);
-  store_row(0);
-  __syncthreads();
-  int buf = 0;
-  for (int64_t t0 = rb; t0 < re; t0 += kLmsTile) {
-    const bool more = t0 + kLmsTile < re;
-    if (more) load_row(t0 + kLmsTile);
-    const int rows = re - t0 < kLmsTile ? (int)(re - t0) : kLmsTile;
-    // (the tile's address as a lane value, so that one register holds it through the rows)
-    const double *tile = &sx[buf][0][0] + __builtin_amdgcn_mbcnt_lo(0u, 0u);
-#pragma unroll 4
-    for (int q = 0; q < rows; ++q) {
-      double xv[PM];
+  int64_t i = rb;
+  for (; i + 1 < re; i += 2) {  // two rows per step: both rows' scalar loads issued together
+    double x0[PM], x1[PM];
 #pragma unroll
-      for (int j = 0; j < PM; ++j) xv[j] = tile[q * RW + j];
-      const double r = sq_residual<P>(xv, tile[q * RW + PM], b, pp);
-      const bool le = r <= lo;
-      if (live && !le && !(r >= hi)) *put++ = r;
-      below += le ? 1u : 0u;
+    for (int j = 0; j < PM; ++j) {
+      x0[j] = j < pp ? X[i * pp + j] : 0.0;
+      x1[j] = j < pp ? X[(i + 1) * pp + j] : 0.0;
     }
-    if (more) store_row(buf ^ 1);
-    __syncthreads();
-    buf ^= 1;
+    const double y0 = y[i], y1 = y[i + 1];
+    // the 2U sums advance together, term by term (each in its own left-to-right order), so
+    // that consecutive instructions are independent
+    double s0[U], s1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      s0[u] = x0[0] * b[u][0];
+      s1[u] = x1[0] * b[u][0];
+    }
+#pragma unroll
+    for (int j = 1; j < PM; ++j) {
+      if (j < pp) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const double q0 = x0[j] * b[u][j], q1 = x1[j] * b[u][j];
+          s0[u] = s0[u] + q0;
+          s1[u] = s1[u] + q1;
+        }
+      }
+    }
+    double r0[U], r1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double d0 = y0 - s0[u], d1 = y1 - s1[u];
+      r0[u] = d0 * d0;
+      r1[u] = d1 * d1;
+    }
+    // (an empty statement that takes every square: the compiler would otherwise move each
+    // chain down to its branch, and the chains would run one after another)
+#pragma unroll
+    for (int u = 0; u < U; ++u) asm volatile("" : "+v"(r0[u]), "+v"(r1[u]));
+#pragma unroll
+    for (int u = 0; u < U; ++u) keep(u, r0[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) keep(u, r1[u]);
   }
-  const uint32_t kept = (uint32_t)(put - dst);
-  if (live) {
-    cnt[c * nseg + sg] = kept;
-    cnt[(m + c) * nseg + sg] = below;
+  if (i < re) {
+    double x0[PM];
+#pragma unroll
+    for (int j = 0; j < PM; ++j) x0[j] = j < pp ? X[i * pp + j] : 0.0;
+    const double y0 = y[i];
+#pragma unroll
+    for (int u = 0; u < U; ++u) keep(u, sq_residual<P>(x0, y0, b[u], pp));
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (live[u]) {
+      flush(u, staged[u]);
+      cnt[c[u] * nseg + sg] = (uint32_t)(put[u] - dst[u]);
+      cnt[(m + c[u]) * nseg + sg] = below[u];
+    }
   }
 }
 
 constexpr int kLmsGatherBlock = 256;
 constexpr int kLmsMaxSegs = 4096;  // segments per candidate (the gather's scan in LDS)
+// Filter workgroups per resident set: one set left some CUs a second, lone workgroup (1.5 ms
+// against 1.2 ms with four); more segments cost the gather more
+constexpr int kLmsRounds = 2;
 
-// One workgroup per candidate: the segments' counts, the bracket's test, and, where it holds,
-// the kept squares packed into C + c * cap in segment order; then the batched call's
-// descriptors and side[2c], side[2c+1] = #(r <= a), #(r >= b) (-1, -1 and full[c] = 1 where
-// the candidate takes the materialised path).
+// ---- the filtered form's finish: one workgroup's exact select over an array in memory
+
+constexpr int kLmsSelCap = 1024;  // elements a narrowed key range may hold to finish in LDS
+
+struct WgSelLds {
+  unsigned long long kext[2];  // key minimum and maximum
+  uint32_t flag;               // NaN seen
+  uint32_t cursor;             // LDS copy cursor
+  int64_t misc[4];             // block_radix_select's words
+  int64_t bin, cum, inb;       // a histogram pass's bin, count below it, its own count
+  uint64_t wsum[kLmsGatherBlock / kWave];
+};
+
+struct WgSelOut {
+  uint64_t key;
+  int64_t less, equal;
+  int32_t passes;
+};
+
+// f(W[i]) for every i < len of this workgroup's share (i = thread + j * BLOCK), eight loads
+// issued before the eight calls (a single workgroup's pass is otherwise bound by the latency
+// of one load after another).
+template <int BLOCK, typename F>
+__device__ __forceinline__ void for_each8(const CPS_GLOBAL double *W, int64_t len, F f) {
+  constexpr int U = 8;
+  for (int64_t i0 = threadIdx.x; i0 < len; i0 += U * BLOCK) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + (int64_t)u * BLOCK;
+      v[u] = i < len ? W[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i0 + (int64_t)u * BLOCK < len) f(v[u]);
+  }
+}
+
+// The k-th smallest (1-based) of W[0, len), none NaN, given that below0 of them have keys
+// below klo and inrange0 have keys in [klo, khi] (and k lies among those): key histograms of
+// 2^12 bins narrow the key range to the bin that holds rank k (counting the elements below
+// it), until the range holds one key (every element in it equals the result) or at most
+// kLmsSelCap elements, which are copied to LDS and radix-selected there.  Every pass reads W
+// whole; `hist` is kHistMaxBins words of LDS, `buf` kLmsSelCap doubles.
+template <int BLOCK>
+__device__ __forceinline__ WgSelOut wg_select(const double *W, int64_t len, int64_t k, uint64_t klo,
+                              uint64_t khi, int64_t below0, int64_t inrange0, uint32_t *hist,
+                              double *buf, WgSelLds &sh) {
+  const int tid = threadIdx.x;
+  const CPS_GLOBAL double *Wg = (const CPS_GLOBAL double *)W;
+  int64_t below = below0, rr = k - below0, inrange = inrange0;
+  int32_t passes = 0;
+  for (;;) {
+    if (klo == khi) return {klo, below, inrange, passes};  // (uniform)
+    if (inrange <= kLmsSelCap) {
+      if (tid == 0) sh.cursor = 0u;
+      __syncthreads();
+      for_each8<BLOCK>(Wg, len, [&](double v) {
+        const uint64_t kk = Traits<double>::key(v);
+        if (kk >= klo && kk <= khi) buf[atomicAdd(&sh.cursor, 1u)] = v;
+      });
+      __syncthreads();
+      uint64_t key;
+      int64_t b_in, eq;
+      block_radix_select<double, BLOCK>(buf, inrange, false, 0.0, 0.0, rr, hist, sh.misc, key,
+                                        b_in, eq);
+      return {key, below + b_in, eq, passes + 1};
+    }
+    int shift = 0;
+    while (((khi - klo) >> shift) >= (uint64_t)kHistMaxBins) ++shift;
+    for (int b = tid; b < kHistMaxBins; b += BLOCK) hist[b] = 0u;
+    __syncthreads();
+    for_each8<BLOCK>(Wg, len, [&](double v) {
+      const uint64_t kk = Traits<double>::key(v);
+      if (kk >= klo && kk <= khi) atomicAdd(&hist[(uint32_t)((kk - klo) >> shift)], 1u);
+    });
+    __syncthreads();
+    ++passes;
+    constexpr int BPT = kHistMaxBins / BLOCK;
+    uint64_t hv[BPT];
+    uint64_t tot = 0;
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      hv[j] = hist[tid * BPT + j];
+      tot += hv[j];
+    }
+    uint64_t cum = block_exclusive_scan<BLOCK>(tot, sh.wsum);
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      if (cum < (uint64_t)rr && (uint64_t)rr <= cum + hv[j]) {
+        sh.bin = tid * BPT + j;
+        sh.cum = (int64_t)cum;
+        sh.inb = (int64_t)hv[j];
+      }
+      cum += hv[j];
+    }
+    __syncthreads();
+    const uint64_t b = (uint64_t)sh.bin;
+    below += sh.cum;
+    rr -= sh.cum;
+    inrange = sh.inb;
+    __syncthreads();
+    const uint64_t nlo = klo + (b << shift);
+    uint64_t nhi = nlo + ((1ull << shift) - 1);
+    if (nhi > khi || nhi < nlo) nhi = khi;
+    klo = nlo;
+    khi = nhi;
+  }
+}
+
+// The record of a selection among all n squares.
+__device__ inline void lms_write_result(cps_result *out, uint64_t key, int64_t less,
+                                        int64_t equal, int64_t n, int32_t passes) {
+  cps_result r;
+  const double v = Traits<double>::unkey(key);
+  r.value_bits = __builtin_bit_cast(uint64_t, v);
+  r.value = v;
+  r.less = less;
+  r.equal = equal;
+  r.greater = n - less - equal;
+  r.passes = passes;
+  r.status = CPS_STATUS_OK;
+  *out = r;
+}
+
+__device__ inline void lms_write_nan(cps_result *out, int32_t passes) {
+  cps_result r;
+  r.value = __builtin_nan("");
+  r.value_bits = __builtin_bit_cast(uint64_t, r.value);
+  r.less = r.equal = r.greater = 0;
+  r.passes = passes;
+  r.status = CPS_STATUS_NAN;
+  *out = r;
+}
+
+// One workgroup per candidate: the segments' counts and the bracket's test; where it holds,
+// the kept squares packed into C + c * cap in segment order, counted on the way in 2^12 key
+// bins over the bracket's open interval (a, b) (NaN noted), and the select of rank
+// k - #(r <= a) among them from that histogram on, written as candidate c's result over all
+// n squares.  Where it does not hold, full[c] = 1 and the candidate's whole array is formed
+// and selected by the two kernels that follow.  passes: the filter, the packing, and the
+// select's passes over the packed squares.
 __global__ __launch_bounds__(kLmsGatherBlock) void lms_gather_kernel(
     const double *__restrict__ R, const uint32_t *__restrict__ cnt, const double *__restrict__ ab,
     int64_t n, int64_t m, int64_t nseg, int64_t seg, int64_t k, int64_t cap, double *__restrict__ C,
-    const double **ptrs, int64_t *sizes, int64_t *ks, int64_t *side, int32_t *full) {
+    cps_result *__restrict__ out, int32_t *__restrict__ full) {
   __shared__ uint32_t pre[kLmsMaxSegs + 1];
-  __shared__ uint64_t wsum[kLmsGatherBlock / kWave];
+  __shared__ uint32_t hist[kHistMaxBins];
+  __shared__ double buf[kLmsSelCap];
+  __shared__ WgSelLds sh;
   __shared__ uint64_t tot[2];
   constexpr int SPT = kLmsMaxSegs / kLmsGatherBlock;
   const int64_t c = blockIdx.x;
@@ -356,68 +543,134 @@ __global__ __launch_bounds__(kLmsGatherBlock) void lms_gather_kernel(
     ksum += kv[j];
     bsum += s < nseg ? cnt[(m + c) * nseg + s] : 0u;
   }
-  uint64_t run = block_exclusive_scan<kLmsGatherBlock>(ksum, wsum);
-  const uint64_t bpre = block_exclusive_scan<kLmsGatherBlock>(bsum, wsum);
+  uint64_t run = block_exclusive_scan<kLmsGatherBlock>(ksum, sh.wsum);
+  const uint64_t bpre = block_exclusive_scan<kLmsGatherBlock>(bsum, sh.wsum);
   if (tid == kLmsGatherBlock - 1) {
     tot[0] = run + ksum;
     tot[1] = bpre + bsum;
     pre[kLmsMaxSegs] = (uint32_t)(run + ksum);
   }
+  if (tid == 0) sh.flag = 0u;
 #pragma unroll
   for (int j = 0; j < SPT; ++j) {
     pre[tid * SPT + j] = (uint32_t)run;
     run += kv[j];
   }
+  for (int b = tid; b < kHistMaxBins; b += kLmsGatherBlock) hist[b] = 0u;
   __syncthreads();
   const int64_t inside = (int64_t)tot[0], bel = (int64_t)tot[1];
   const double lo = ab[2 * c], hi = ab[2 * c + 1];
   const bool holds = lo < hi && bel < k && k <= bel + inside && inside <= cap;
-  if (holds) {
-    // packed place j comes from the segment s with pre[s] <= j < pre[s + 1]; each thread's
-    // places rise, so its segment only moves forward (pre[kLmsMaxSegs] = inside ends it);
-    // four places per step keep four loads in flight
-    const CPS_GLOBAL double *Rc = (const CPS_GLOBAL double *)(R + c * n);
-    CPS_GLOBAL double *Cc = (CPS_GLOBAL double *)(C + c * cap);
-    constexpr int U = 4;
-    int sg = 0;
-    for (int64_t j0 = tid; j0 < inside; j0 += U * kLmsGatherBlock) {
+  if (tid == 0) full[c] = holds ? 0 : 1;
+  if (!holds) return;  // (uniform)
+  // the keys of a < r < b
+  const uint64_t ka = Traits<double>::key(lo) + 1, kb = Traits<double>::key(hi) - 1;
+  int shift = 0;
+  while (((kb - ka) >> shift) >= (uint64_t)kHistMaxBins) ++shift;
+  // each thread copies a run of consecutive segments (segment s's kept squares, from row
+  // s * seg of the candidate's array, to packed places pre[s] on), eight squares per step
+  const int ns = (int)(nseg < kLmsMaxSegs ? nseg : kLmsMaxSegs);
+  const int spt = (ns + kLmsGatherBlock - 1) / kLmsGatherBlock;
+  const CPS_GLOBAL double *Rc = (const CPS_GLOBAL double *)(R + c * n);
+  CPS_GLOBAL double *Cc = (CPS_GLOBAL double *)(C + c * cap);
+  constexpr int U = 8;
+  bool nan = false;
+  for (int q = 0; q < spt; ++q) {
+    const int sgm = tid * spt + q;
+    if (sgm >= ns) break;
+    const int64_t from = (int64_t)sgm * seg, to = pre[sgm];
+    const int64_t len = (int64_t)pre[sgm + 1] - to;
+    for (int64_t e = 0; e < len; e += U) {
       double v[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t j = j0 + (int64_t)u * kLmsGatherBlock;
-        if (j < inside) {
-          while ((int64_t)pre[sg + 1] <= j) ++sg;
-          v[u] = Rc[(int64_t)sg * seg + (j - (int64_t)pre[sg])];
-        }
-      }
+      for (int u = 0; u < U; ++u) v[u] = e + u < len ? Rc[from + e + u] : 0.0;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int64_t j = j0 + (int64_t)u * kLmsGatherBlock;
-        if (j < inside) Cc[j] = v[u];
+        if (e + u < len) {
+          Cc[to + e + u] = v[u];
+          const uint64_t kk = Traits<double>::key(v[u]);
+          nan = nan || !(v[u] == v[u]);
+          if (kk >= ka && kk <= kb) atomicAdd(&hist[(uint32_t)((kk - ka) >> shift)], 1u);
+        }
       }
     }
   }
-  if (tid == 0) {
-    ptrs[c] = holds ? C + c * cap : R + c * n;
-    sizes[c] = holds ? inside : n;
-    ks[c] = holds ? k - bel : k;
-    side[2 * c] = holds ? bel : -1;
-    side[2 * c + 1] = holds ? n - bel - inside : -1;
-    full[c] = holds ? 0 : 1;
+  if (nan) atomicOr(&sh.flag, 1u);
+  __syncthreads();  // (the packed squares, written by this workgroup, are read below)
+  if (sh.flag != 0u) {  // (uniform)
+    if (tid == 0) lms_write_nan(out + c, 2);
+    return;
   }
+  // the bin of rank k - #(r <= a) among the packed squares
+  const int64_t rr = k - bel;
+  constexpr int BPT = kHistMaxBins / kLmsGatherBlock;
+  uint64_t hv[BPT];
+  uint64_t hs = 0;
+#pragma unroll
+  for (int j = 0; j < BPT; ++j) {
+    hv[j] = hist[tid * BPT + j];
+    hs += hv[j];
+  }
+  uint64_t cum = block_exclusive_scan<kLmsGatherBlock>(hs, sh.wsum);
+#pragma unroll
+  for (int j = 0; j < BPT; ++j) {
+    if (cum < (uint64_t)rr && (uint64_t)rr <= cum + hv[j]) {
+      sh.bin = tid * BPT + j;
+      sh.cum = (int64_t)cum;
+      sh.inb = (int64_t)hv[j];
+    }
+    cum += hv[j];
+  }
+  __syncthreads();
+  const uint64_t b = (uint64_t)sh.bin;
+  const int64_t below0 = sh.cum, in0 = sh.inb;
+  __syncthreads();
+  const uint64_t nlo = ka + (b << shift);
+  uint64_t nhi = nlo + ((1ull << shift) - 1);
+  if (nhi > kb || nhi < nlo) nhi = kb;
+  const WgSelOut r = wg_select<kLmsGatherBlock>(C + c * cap, inside, rr, nlo, nhi, below0, in0,
+                                                hist, buf, sh);
+  if (tid == 0) lms_write_result(out + c, r.key, bel + r.less, r.equal, n, 3 + r.passes);
 }
 
-// After the batched selection: a packed candidate's counts over all n squares (the
-// selection saw only the kept ones), and its one pass over the residuals.
-__global__ void lms_fixup_kernel(cps_result *__restrict__ out, const int64_t *__restrict__ side,
-                                 int64_t m) {
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < m;
-       c += (int64_t)gridDim.x * blockDim.x) {
-    if (side[2 * c] < 0 || out[c].status != CPS_STATUS_OK) continue;
-    out[c].less += side[2 * c];
-    out[c].greater += side[2 * c + 1];
-    out[c].passes += 1;
+// After the fallback residual kernel: the candidates whose bracket missed, over their whole
+// arrays of n squares (a first pass for the key range and NaN, then wg_select); the others'
+// workgroups return at once.
+__global__ __launch_bounds__(kLmsGatherBlock) void lms_full_select_kernel(
+    const double *__restrict__ R, int64_t n, int64_t k, const int32_t *__restrict__ full,
+    cps_result *__restrict__ out) {
+  __shared__ uint32_t hist[kHistMaxBins];
+  __shared__ double buf[kLmsSelCap];
+  __shared__ WgSelLds sh;
+  const int64_t c = blockIdx.x;
+  const int tid = threadIdx.x;
+  if (full[c] == 0) return;  // (uniform)
+  if (tid == 0) {
+    sh.kext[0] = ~0ull;
+    sh.kext[1] = 0ull;
+    sh.flag = 0u;
   }
+  __syncthreads();
+  const CPS_GLOBAL double *Rc = (const CPS_GLOBAL double *)(R + c * n);
+  uint64_t kmn = ~0ull, kmx = 0ull;
+  bool nan = false;
+  for_each8<kLmsGatherBlock>(Rc, n, [&](double v) {
+    const uint64_t kk = Traits<double>::key(v);
+    nan = nan || !(v == v);
+    kmn = kk < kmn ? kk : kmn;
+    kmx = kk > kmx ? kk : kmx;
+  });
+  atomicMin(&sh.kext[0], (unsigned long long)kmn);
+  atomicMax(&sh.kext[1], (unsigned long long)kmx);
+  if (nan) atomicOr(&sh.flag, 1u);
+  __syncthreads();
+  if (sh.flag != 0u) {  // (uniform)
+    if (tid == 0) lms_write_nan(out + c, 3);
+    return;
+  }
+  const WgSelOut r = wg_select<kLmsGatherBlock>(R + c * n, n, k, sh.kext[0], sh.kext[1], 0, n,
+                                                hist, buf, sh);
+  if (tid == 0) lms_write_result(out + c, r.key, r.less, r.equal, n, 3 + r.passes);
 }
 
 __global__ void lms_descriptor_kernel(const double *R, int64_t n, int64_t m, int64_t rank,
@@ -485,22 +738,22 @@ hipError_t launch_lms_residuals(const double *X, const double *y, const double *
 
 void lms_filter_shape(int64_t n, int64_t m, int32_t p, bool vec, int cu_count, int64_t *bx,
                       int64_t *nseg, int64_t *seg) {
-  // the filter: as many workgroups as are resident at once over (segments x groups of
-  // kLmsBlock candidates), so that no tail of lone workgroups is left; segments of at least
-  // 256 rows, every segment holding rows
+  // the filter: kLmsRounds times as many workgroups as are resident at once over (segments x
+  // groups of kLmsCands candidates), a multiple of 16 rows per segment (at least 256), every
+  // segment holding rows
   int per_cu = 0;
+  (void)vec;
   const hipError_t e =
-      vec && p == 8
-          ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lms_filter_kernel<8, true>, kLmsBlock, 0)
-          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lms_filter_kernel<0, false>, kLmsBlock, 0);
+      p == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lms_filter_kernel<8>, kLmsBlock, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lms_filter_kernel<0>, kLmsBlock, 0);
   if (e != hipSuccess || per_cu < 1) per_cu = 4;
-  const int64_t fgroups = (m + kLmsBlock - 1) / kLmsBlock;
-  int64_t ns = (int64_t)cu_count * per_cu / fgroups;
+  const int64_t fgroups = (m + kLmsCands - 1) / kLmsCands;
+  int64_t ns = (int64_t)cu_count * per_cu * kLmsRounds / fgroups;
   const int64_t nmax = (n + 255) / 256;
   if (ns > nmax) ns = nmax;
   if (ns > kLmsMaxSegs) ns = kLmsMaxSegs;
   if (ns < 1) ns = 1;
-  const int64_t sl = (n + ns - 1) / ns;
+  const int64_t sl = ((n + ns - 1) / ns + 15) / 16 * 16;
   *nseg = (n + sl - 1) / sl;
   *seg = sl;
   // the fallback residual kernel's grid, as the materialised form's
@@ -515,11 +768,12 @@ int64_t lms_filter_cap(int64_t n) { return (n / 8 + 1 + 31) / 32 * 32; }
 
 hipError_t launch_lms_filtered(const double *X, const double *y, const double *betas, int64_t n,
                                int32_t p, int64_t m, int64_t rank, const LmsFilterBufs &w,
-                               hipStream_t stream) {
+                               cps_result *out, hipStream_t stream) {
   const int64_t groups = (m + kLmsGroup - 1) / kLmsGroup;
-  const int64_t fgroups = (m + kLmsBlock - 1) / kLmsBlock;
+  const int64_t fgroups = (m + kLmsCands - 1) / kLmsCands;
+  const int64_t sgroups = (m + kLmsBlock - 1) / kLmsBlock;
   // one run of the sample per workgroup
-  const dim3 sg((unsigned)(sample_runs(n)), (unsigned)fgroups);
+  const dim3 sg((unsigned)(sample_runs(n)), (unsigned)sgroups);
   if (p == 8)
     lms_sample_kernel<8><<<sg, dim3(kLmsBlock), 0, stream>>>(X, y, betas, n, p, m, w.Rs);
   else
@@ -531,17 +785,17 @@ hipError_t launch_lms_filtered(const double *X, const double *y, const double *b
   if (e != hipSuccess) return e;
   const bool aligned = ((uintptr_t)X % 16 == 0) && ((uintptr_t)y % 16 == 0);
   const dim3 fgrid((unsigned)w.nseg, (unsigned)fgroups);
-  if (p == 8 && aligned)
-    lms_filter_kernel<8, true><<<fgrid, dim3(kLmsBlock), 0, stream>>>(X, y, betas, w.ab, n, p, m,
-                                                                       w.seg, w.R, w.cnt);
+  if (p == 8)
+    lms_filter_kernel<8><<<fgrid, dim3(kLmsBlock), 0, stream>>>(X, y, betas, w.ab, n, p, m, w.seg,
+                                                                 w.R, w.cnt);
   else
-    lms_filter_kernel<0, false><<<fgrid, dim3(kLmsBlock), 0, stream>>>(X, y, betas, w.ab, n, p, m,
-                                                                        w.seg, w.R, w.cnt);
+    lms_filter_kernel<0><<<fgrid, dim3(kLmsBlock), 0, stream>>>(X, y, betas, w.ab, n, p, m, w.seg,
+                                                                 w.R, w.cnt);
   const dim3 grid((unsigned)w.bx, (unsigned)groups);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   lms_gather_kernel<<<dim3((unsigned)m), dim3(kLmsGatherBlock), 0, stream>>>(
-      w.R, w.cnt, w.ab, n, m, w.nseg, w.seg, rank, w.cap, w.C, w.ptrs, w.sizes, w.ks, w.side, w.full);
+      w.R, w.cnt, w.ab, n, m, w.nseg, w.seg, rank, w.cap, w.C, out, w.full);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   // the candidates whose bracket missed: their whole arrays (workgroups without one return)
@@ -555,11 +809,10 @@ hipError_t launch_lms_filtered(const double *X, const double *y, const double *b
     lms_residual_kernel<0, true><<<grid, dim3(kLmsBlock), 0, stream>>>(X, y, betas, n, p, m, w.R,
                                                                         w.full);
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_lms_fixup(cps_result *out, const int64_t *side, int64_t m, hipStream_t stream) {
-  lms_fixup_kernel<<<dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream>>>(out, side, m);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  lms_full_select_kernel<<<dim3((unsigned)m), dim3(kLmsGatherBlock), 0, stream>>>(w.R, n, rank,
+                                                                                w.full, out);
   return hipGetLastError();
 }
 
