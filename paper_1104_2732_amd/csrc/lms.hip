@@ -567,31 +567,34 @@ __global__ __launch_bounds__(kLmsGatherBlock) void lms_gather_kernel(
   const uint64_t ka = Traits<double>::key(lo) + 1, kb = Traits<double>::key(hi) - 1;
   int shift = 0;
   while (((kb - ka) >> shift) >= (uint64_t)kHistMaxBins) ++shift;
-  // each thread copies a run of consecutive segments (segment s's kept squares, from row
-  // s * seg of the candidate's array, to packed places pre[s] on), eight squares per step
-  const int ns = (int)(nseg < kLmsMaxSegs ? nseg : kLmsMaxSegs);
-  const int spt = (ns + kLmsGatherBlock - 1) / kLmsGatherBlock;
+  // packed place j comes from the segment s with pre[s] <= j < pre[s + 1]; each thread's
+  // places rise, so its segment only moves forward (pre[kLmsMaxSegs] = inside ends it); the
+  // places of a step are consecutive over the threads, so the stores are (packing by
+  // segments per thread, its own places together, took 2.5 times as long); four places per
+  // step keep four loads in flight
   const CPS_GLOBAL double *Rc = (const CPS_GLOBAL double *)(R + c * n);
   CPS_GLOBAL double *Cc = (CPS_GLOBAL double *)(C + c * cap);
-  constexpr int U = 8;
+  constexpr int U = 4;
+  int sg = 0;
   bool nan = false;
-  for (int q = 0; q < spt; ++q) {
-    const int sgm = tid * spt + q;
-    if (sgm >= ns) break;
-    const int64_t from = (int64_t)sgm * seg, to = pre[sgm];
-    const int64_t len = (int64_t)pre[sgm + 1] - to;
-    for (int64_t e = 0; e < len; e += U) {
-      double v[U];
+  for (int64_t j0 = tid; j0 < inside; j0 += U * kLmsGatherBlock) {
+    double v[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) v[u] = e + u < len ? Rc[from + e + u] : 0.0;
+    for (int u = 0; u < U; ++u) {
+      const int64_t j = j0 + (int64_t)u * kLmsGatherBlock;
+      if (j < inside) {
+        while ((int64_t)pre[sg + 1] <= j) ++sg;
+        v[u] = Rc[(int64_t)sg * seg + (j - (int64_t)pre[sg])];
+      }
+    }
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (e + u < len) {
-          Cc[to + e + u] = v[u];
-          const uint64_t kk = Traits<double>::key(v[u]);
-          nan = nan || !(v[u] == v[u]);
-          if (kk >= ka && kk <= kb) atomicAdd(&hist[(uint32_t)((kk - ka) >> shift)], 1u);
-        }
+    for (int u = 0; u < U; ++u) {
+      const int64_t j = j0 + (int64_t)u * kLmsGatherBlock;
+      if (j < inside) {
+        Cc[j] = v[u];
+        const uint64_t kk = Traits<double>::key(v[u]);
+        nan = nan || !(v[u] == v[u]);
+        if (kk >= ka && kk <= kb) atomicAdd(&hist[(uint32_t)((kk - ka) >> shift)], 1u);
       }
     }
   }
