@@ -13,7 +13,8 @@ sample of the same workload.  Further legs (their own keys in the line):
 the end), "batched" (4096 lognormal arrays of log-uniform sizes in one
 graph-captured launch vs a loop of single-array calls), "batched_large" (64
 arrays of 2^22 elements, one or 16 workgroups per array), "lms" (1024
-least-median-of-squares candidates over 2^20 rows), "lts" and "knn" (Section 6's
+least-median-of-squares candidates over 2^20 rows, filtered and materialised
+forms, their results compared), "lts" and "knn" (Section 6's
 trimmed squares at the LMS shape; 1024 queries over 2^20 points), "transform"
 (2^26 values with 1e20 outliers, cutting plane on x and on the log transform),
 "learned" (the learned bracket proposal vs the plain method and the
@@ -135,12 +136,14 @@ def legs_traffic_from(fetch_dir: str, write_dir: str) -> dict:
     """HBM bytes of the batched and least-median-of-squares kernels from two counter runs of
     `bench.py --no-sweep --legs batched,lms --copy-calibration`: the last dispatch of each
     kernel (the batched leg ends with an eager call of its tuned options; the LMS leg's last
-    call is an ordinary one), each counter scaled as in traffic_from (FETCH_SIZE by the
-    selection kernel's pass 0 over 1 GiB, WRITE_SIZE by the copy's 1 GiB written)."""
+    calls of each form are ordinary ones), each counter scaled as in traffic_from (FETCH_SIZE
+    by the selection kernel's pass 0 over 1 GiB, WRITE_SIZE by the copy's 1 GiB written)."""
     gib = float(4 << 28)
     kernels = {"batched_select_kernel<float": "batched float32 (4096 lognormal arrays)",
-               "batched_select_kernel<double": "batched float64 (LMS medians)",
-               "lms_residual": "LMS residuals"}
+               "batched_select_kernel<double": "batched float64 (LMS medians, materialised form)",
+               "lms_residual_rows_kernel<8, 2, false>": "LMS residuals (materialised form)",
+               "lms_filter_kernel": "LMS filter (filtered form)",
+               "lms_gather_kernel": "LMS packing and select (filtered form)"}
     out = {"kernel_source_hash": kernel_source_hash()}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = _counter_rows(d, counter)
