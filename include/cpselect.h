@@ -470,6 +470,17 @@ int lts_trimmed_sq(cps_handle *h, const double *X_dev, const double *y_dev,
                    const double *betas_dev, int64_t n, int32_t p, int64_t m, int64_t hk,
                    cps_trim *out_dev, void *stream);
 
+/* lts_trimmed_sq with a choice of form (cps_lms_form; CPS_LMS_AUTO is lts_trimmed_sq).  In
+ * the filtered form the bracket is taken for rank hk, the filter also sums the squares at or
+ * below its lower end (per row segment, in row order; the segments' sums added in a fixed
+ * order), and one more pass over the packed squares sums those below the selected value, so
+ * F is formed in double precision in a fixed order.  Errors: as lts_trimmed_sq, and
+ * CPS_EINVAL for a form outside cps_lms_form, or CPS_LMS_FILTERED with n outside
+ * [2^15, 2^31). */
+int lts_trimmed_sq_ex(cps_handle *h, const double *X_dev, const double *y_dev,
+                      const double *betas_dev, int64_t n, int32_t p, int64_t m, int64_t hk,
+                      int32_t form, cps_trim *out_dev, void *stream);
+
 /* k nearest neighbours (Section 6, last paragraph), 32 bytes, device memory: for one query,
  * the mean ordinate of its k nearest points, the k-th smallest squared distance dk, the
  * counts #(d < dk) and #(d = dk), and the selection's status. */

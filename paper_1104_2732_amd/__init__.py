@@ -124,7 +124,8 @@ EXPORTS = ("cps_create", "cps_destroy", "cps_status_string", "cps_last_hip_error
            "cps_mixture_generate", "cps_features", "cps_mlp_forward", "cps_mlp_loss_grad",
            "cps_mlp_adam", "cps_mlp_init", "cps_learned_bracket", "select_kth_learned",
            "cps_mlp_train", "select_kth_sampled", "cps_sample_bracket", "cps_model_save",
-           "cps_model_load", "select_kth_noalloc", "select_kth_batched_ksum", "lts_trimmed_sq", "knn_mean")
+           "cps_model_load", "select_kth_noalloc", "select_kth_batched_ksum", "lts_trimmed_sq", "lts_trimmed_sq_ex",
+           "knn_mean")
 STATUS_BADARG = 4
 LMS_AUTO, LMS_MATERIALISED, LMS_FILTERED = 0, 1, 2  # cps_lms_form
 
@@ -161,6 +162,8 @@ def lib() -> ctypes.CDLL:
     L.select_kth_batched_ksum.restype = c_int
     L.lts_trimmed_sq.argtypes = [vp, vp, vp, vp, i64, i32, i64, i64, vp, vp]
     L.lts_trimmed_sq.restype = c_int
+    L.lts_trimmed_sq_ex.argtypes = [vp, vp, vp, vp, i64, i32, i64, i64, i32, vp, vp]
+    L.lts_trimmed_sq_ex.restype = c_int
     L.knn_mean.argtypes = [vp, vp, vp, vp, i64, i32, i64, i64, vp, vp]
     L.knn_mean.restype = c_int
     L.cps_objective.argtypes = [vp, vp, i64, i64, c_int, vp, i64, vp, vp]
@@ -425,8 +428,9 @@ class Selector:
         torch.cuda.synchronize(self.device)
         return _as_records(out, RESULT_DTYPE).copy()
 
-    def lts_trimmed_sq_async(self, X, y, betas, h: int, out) -> None:
-        """Enqueue lts_trimmed_sq: X (n x p), y (n), betas (m x p) float64 CUDA tensors."""
+    def lts_trimmed_sq_async(self, X, y, betas, h: int, out, form: int = 0) -> None:
+        """Enqueue lts_trimmed_sq_ex: X (n x p), y (n), betas (m x p) float64 CUDA tensors;
+        form LMS_AUTO, LMS_MATERIALISED or LMS_FILTERED."""
         import torch
         for t in (X, y, betas):
             if not t.is_cuda or not t.is_contiguous() or t.dtype != torch.float64:
@@ -435,17 +439,17 @@ class Selector:
         m = betas.shape[0]
         if y.numel() != n or betas.shape[1] != p:
             raise ValueError("shape mismatch between X, y and betas")
-        _check(lib().lts_trimmed_sq(self._h, self._ptr(X), self._ptr(y), self._ptr(betas), n, p, m,
-                                    int(h), self._ptr(out),
-                                    ctypes.c_void_p(_stream_ptr(self.device))), "lts_trimmed_sq")
+        _check(lib().lts_trimmed_sq_ex(self._h, self._ptr(X), self._ptr(y), self._ptr(betas), n, p,
+                                       m, int(h), int(form), self._ptr(out),
+                                       ctypes.c_void_p(_stream_ptr(self.device))), "lts_trimmed_sq_ex")
 
-    def lts_trimmed_sq(self, X, y, betas, h: int | None = None) -> np.ndarray:
+    def lts_trimmed_sq(self, X, y, betas, h: int | None = None, form: int = 0) -> np.ndarray:
         """Least trimmed squares per candidate (h defaults to floor((n+1)/2)); TRIM_DTYPE."""
         import torch
         m = betas.shape[0]
         h = (X.shape[0] + 1) // 2 if h is None else int(h)
         out = torch.empty(m * TRIM_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
-        self.lts_trimmed_sq_async(X, y, betas, h, out)
+        self.lts_trimmed_sq_async(X, y, betas, h, out, form)
         torch.cuda.synchronize(self.device)
         return _as_records(out, TRIM_DTYPE).copy()
 

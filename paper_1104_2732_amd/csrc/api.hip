@@ -468,44 +468,65 @@ int cps_reserve_batched(cps_handle *h, int dtype, const cps_batch_options *opt) 
   return r.team_records > 0 ? ensure_team_records(h, nullptr) : CPS_OK;
 }
 
+// The filtered form's workspace and launches (the handle's lock held): R (m x n), C (m x cap),
+// sampled squares, brackets, segment counts, flags, and with ksum_out the segments' sums and
+// m records and sums of its own (the selections then land there, *sel_out and *ksum_out
+// point at them).
+static int lms_filtered_run(cps_handle *h, const double *X_dev, const double *y_dev,
+                            const double *betas_dev, int64_t n, int32_t p, int64_t m, int64_t rank,
+                            cps_result *out_dev, cps_result **sel_out, double **ksum_out,
+                            hipStream_t s) {
+  const size_t dsz = align_up((size_t)m * 8, 256);
+  cps::LmsFilterBufs w;
+  const bool vec = (uintptr_t)X_dev % 16 == 0 && (uintptr_t)y_dev % 16 == 0;
+  cps::lms_filter_shape(n, m, p, vec, h->cu_count, &w.bx, &w.nseg, &w.seg);
+  w.cap = cps::lms_filter_cap(n);
+  const bool sums = ksum_out != nullptr;
+  const size_t off_c = align_up((size_t)m * (size_t)n * sizeof(double), 256);
+  const size_t off_rs = off_c + align_up((size_t)m * (size_t)w.cap * sizeof(double), 256);
+  const size_t off_ab = off_rs + align_up((size_t)m * 16384 * sizeof(double), 256);
+  const size_t off_cnt = off_ab + 2 * dsz;
+  const size_t off_full = off_cnt + align_up((size_t)2 * m * w.nseg * sizeof(uint32_t), 256);
+  const size_t off_psum = off_full + dsz;
+  const size_t off_sel = off_psum + (sums ? align_up((size_t)m * w.nseg * sizeof(double), 256) : 0);
+  const size_t off_ksum = off_sel + (sums ? align_up((size_t)m * sizeof(cps_result), 256) : 0);
+  const size_t bytes = off_ksum + (sums ? dsz : 0);
+  int rc = ensure_buffer(h->lws, h->lws_bytes, bytes, s);
+  if (rc) return rc;
+  char *base = (char *)h->lws;
+  w.R = (double *)base;
+  w.C = (double *)(base + off_c);
+  w.Rs = (double *)(base + off_rs);
+  w.ab = (double *)(base + off_ab);
+  w.cnt = (uint32_t *)(base + off_cnt);
+  w.full = (int32_t *)(base + off_full);
+  w.psum = sums ? (double *)(base + off_psum) : nullptr;
+  cps_result *sel = sums ? (cps_result *)(base + off_sel) : out_dev;
+  double *ksum = sums ? (double *)(base + off_ksum) : nullptr;
+  if (sel_out) *sel_out = sel;
+  if (ksum_out) *ksum_out = ksum;
+  hipError_t e = cps::launch_lms_filtered(X_dev, y_dev, betas_dev, n, p, m, rank, w, sel, ksum, s);
+  return e == hipSuccess ? CPS_OK : hip_fail(e);
+}
+
+static bool lms_can_filter(int64_t n) { return n >= ((int64_t)1 << 15) && n < ((int64_t)1 << 31); }
+
 int lms_median_sq_residuals_ex(cps_handle *h, const double *X_dev, const double *y_dev,
                                const double *betas_dev, int64_t n, int32_t p, int64_t m,
                                int32_t form, cps_result *out_dev, void *stream) {
   if (!h || !X_dev || !y_dev || !betas_dev || !out_dev || n < 1 || p < 1 || p > 16 || m < 1 ||
       m > (int64_t)65535 * 16 || form < CPS_LMS_AUTO || form > CPS_LMS_FILTERED)
     return CPS_EINVAL;
-  const bool can_filter = n >= ((int64_t)1 << 15) && n < ((int64_t)1 << 31);
+  const bool can_filter = lms_can_filter(n);
   if (form == CPS_LMS_FILTERED && !can_filter) return CPS_EINVAL;
   const bool filtered = form == CPS_LMS_FILTERED || (form == CPS_LMS_AUTO && can_filter);
   hipStream_t s = (hipStream_t)stream;
   const int64_t rank = (n + 1) / 2;
+  std::lock_guard<std::mutex> lk(h->mu);
+  if (filtered)
+    return lms_filtered_run(h, X_dev, y_dev, betas_dev, n, p, m, rank, out_dev, nullptr, nullptr, s);
   const size_t dsz = align_up((size_t)m * 8, 256);
   const size_t off_desc = align_up((size_t)m * (size_t)n * sizeof(double), 256);
-  std::lock_guard<std::mutex> lk(h->mu);
-  if (filtered) {
-    // R (m x n), C (m x cap), sampled squares, brackets, segment counts, flags
-    cps::LmsFilterBufs w;
-    const bool vec = (uintptr_t)X_dev % 16 == 0 && (uintptr_t)y_dev % 16 == 0;
-    cps::lms_filter_shape(n, m, p, vec, h->cu_count, &w.bx, &w.nseg, &w.seg);
-    w.cap = cps::lms_filter_cap(n);
-    const size_t off_c = off_desc;
-    const size_t off_rs = off_c + align_up((size_t)m * (size_t)w.cap * sizeof(double), 256);
-    const size_t off_ab = off_rs + align_up((size_t)m * 16384 * sizeof(double), 256);
-    const size_t off_cnt = off_ab + 2 * dsz;
-    const size_t off_full = off_cnt + align_up((size_t)2 * m * w.nseg * sizeof(uint32_t), 256);
-    const size_t bytes = off_full + dsz;
-    int rc = ensure_buffer(h->lws, h->lws_bytes, bytes, s);
-    if (rc) return rc;
-    char *base = (char *)h->lws;
-    w.R = (double *)base;
-    w.C = (double *)(base + off_c);
-    w.Rs = (double *)(base + off_rs);
-    w.ab = (double *)(base + off_ab);
-    w.cnt = (uint32_t *)(base + off_cnt);
-    w.full = (int32_t *)(base + off_full);
-    hipError_t e = cps::launch_lms_filtered(X_dev, y_dev, betas_dev, n, p, m, rank, w, out_dev, s);
-    return e == hipSuccess ? CPS_OK : hip_fail(e);
-  }
   const size_t bytes = off_desc + 3 * dsz;
   int rc = ensure_buffer(h->lws, h->lws_bytes, bytes, s);
   if (rc) return rc;
@@ -532,13 +553,25 @@ int lms_median_sq_residuals(cps_handle *h, const double *X_dev, const double *y_
                                     stream);
 }
 
-int lts_trimmed_sq(cps_handle *h, const double *X_dev, const double *y_dev,
-                   const double *betas_dev, int64_t n, int32_t p, int64_t m, int64_t hk,
-                   cps_trim *out_dev, void *stream) {
+int lts_trimmed_sq_ex(cps_handle *h, const double *X_dev, const double *y_dev,
+                      const double *betas_dev, int64_t n, int32_t p, int64_t m, int64_t hk,
+                      int32_t form, cps_trim *out_dev, void *stream) {
   if (!h || !X_dev || !y_dev || !betas_dev || !out_dev || n < 1 || p < 1 || p > 16 || m < 1 ||
-      m > (int64_t)65535 * 16 || hk < 1 || hk > n)
+      m > (int64_t)65535 * 16 || hk < 1 || hk > n || form < CPS_LMS_AUTO || form > CPS_LMS_FILTERED)
     return CPS_EINVAL;
+  const bool can_filter = lms_can_filter(n);
+  if (form == CPS_LMS_FILTERED && !can_filter) return CPS_EINVAL;
+  const bool filtered = form == CPS_LMS_FILTERED || (form == CPS_LMS_AUTO && can_filter);
   hipStream_t s = (hipStream_t)stream;
+  if (filtered) {
+    std::lock_guard<std::mutex> lk(h->mu);
+    cps_result *sel = nullptr;
+    double *ksum = nullptr;
+    int rc = lms_filtered_run(h, X_dev, y_dev, betas_dev, n, p, m, hk, nullptr, &sel, &ksum, s);
+    if (rc) return rc;
+    hipError_t e = cps::launch_lts_finish(sel, ksum, m, hk, out_dev, s);
+    return e == hipSuccess ? CPS_OK : hip_fail(e);
+  }
   // residuals, then descriptors, selections, sums and records, in the workspace
   const size_t off_desc = align_up((size_t)m * (size_t)n * sizeof(double), 256);
   const size_t dsz = align_up((size_t)m * 8, 256);
@@ -568,6 +601,12 @@ int lts_trimmed_sq(cps_handle *h, const double *X_dev, const double *y_dev,
   hipError_t e = cps::launch_lts_finish((const cps_result *)(base + off_sel),
                                         (const double *)(base + off_sum), m, hk, out_dev, s);
   return e == hipSuccess ? CPS_OK : hip_fail(e);
+}
+
+int lts_trimmed_sq(cps_handle *h, const double *X_dev, const double *y_dev,
+                   const double *betas_dev, int64_t n, int32_t p, int64_t m, int64_t hk,
+                   cps_trim *out_dev, void *stream) {
+  return lts_trimmed_sq_ex(h, X_dev, y_dev, betas_dev, n, p, m, hk, CPS_LMS_AUTO, out_dev, stream);
 }
 
 int knn_mean(cps_handle *h, const float *P_dev, const float *f_dev, const float *Q_dev, int64_t n,

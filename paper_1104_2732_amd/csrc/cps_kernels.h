@@ -151,6 +151,8 @@ struct LmsFilterBufs {
   double *Rs;            // m x S: the squares of the sampled rows (S <= 16384)
   double *ab;            // 2m: the sampled brackets
   uint32_t *cnt;         // 2 x m x nseg: kept and #(r <= a) per candidate and segment
+  double *psum;          // m x nseg: the sum of the r <= a per candidate and segment (with
+                         // the trimmed sums only)
   int32_t *full;         // m: 1 where the candidate's whole array is formed and selected
   int64_t bx, nseg, seg;  // the fallback kernel's workgroups per candidate group; segments
                           // per candidate and rows per segment of the filter
@@ -159,9 +161,10 @@ void lms_filter_shape(int64_t n, int64_t m, int32_t p, bool vec, int cu_count, i
                       int64_t *nseg, int64_t *seg);
 int64_t lms_filter_cap(int64_t n);
 // Every kernel of the filtered form; the medians land in out (m records).
+// ksum (or null): m doubles, each candidate's sum of its `rank` smallest squares.
 hipError_t launch_lms_filtered(const double *X, const double *y, const double *betas, int64_t n,
                                int32_t p, int64_t m, int64_t rank, const LmsFilterBufs &w,
-                               cps_result *out, hipStream_t stream);
+                               cps_result *out, double *ksum, hipStream_t stream);
 hipError_t launch_lts_finish(const cps_result *sel, const double *ksum, int64_t m, int64_t h,
                              cps_trim *out, hipStream_t stream);
 

@@ -242,18 +242,19 @@ __global__ __launch_bounds__(kLmsBracketBlock) void lms_bracket_kernel(
 // a < r < b (or NaN) is kept: written to c's array of the workspace at the segment's first
 // row plus the number kept before it in the segment (so a segment's kept squares stay inside
 // the segment's own rows, in row order).  The counts land in cnt[0][c][s] (kept) and
-// cnt[1][c][s] (#(r <= a)), nseg = gridDim.x segments per candidate.
+// cnt[1][c][s] (#(r <= a)), nseg = gridDim.x segments per candidate; SUM: the segment's sum of
+// the r <= a (in row order) in psum[c][s].
 constexpr int kLmsLane = 2;
 constexpr int kLmsCands = kLmsBlock * kLmsLane;  // candidates per workgroup
 #ifndef CPS_LMS_STAGE
 #define CPS_LMS_STAGE 4
 #endif
 constexpr int kLmsStage = CPS_LMS_STAGE;  // kept squares staged in LDS per candidate
-template <int P>
+template <int P, bool SUM>
 __global__ __launch_bounds__(kLmsBlock) void lms_filter_kernel(
     const double *__restrict__ X, const double *__restrict__ y, const double *__restrict__ betas,
     const double *__restrict__ ab, int64_t n, int32_t p, int64_t m, int64_t seg,
-    double *__restrict__ R_out, uint32_t *__restrict__ cnt) {
+    double *__restrict__ R_out, uint32_t *__restrict__ cnt, double *__restrict__ psum) {
   constexpr int PM = P > 0 ? P : 16;
   constexpr int U = kLmsLane;
   // Each candidate's kept squares gather in LDS and go out kLmsStage at a time, as 16-byte
@@ -272,6 +273,7 @@ __global__ __launch_bounds__(kLmsBlock) void lms_filter_kernel(
   CPS_GLOBAL double *dst[U];
   CPS_GLOBAL double *put[U];  // the place of the first staged square
   uint32_t below[U];          // #(r <= a)
+  double sbelow[U];           // SUM: their sum, in row order
   int staged[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -285,6 +287,7 @@ __global__ __launch_bounds__(kLmsBlock) void lms_filter_kernel(
     dst[u] = (CPS_GLOBAL double *)R_out + (live[u] ? c[u] : 0) * n + rb;
     put[u] = dst[u];
     below[u] = 0;
+    sbelow[u] = 0.0;
     staged[u] = 0;
   }
   auto flush = [&](int u, int k) {
@@ -311,6 +314,7 @@ __global__ __launch_bounds__(kLmsBlock) void lms_filter_kernel(
       }
     }
     below[u] += le ? 1u : 0u;
+    if (SUM && le) sbelow[u] += r;
   };
   int64_t i = rb;
   for (; i + 1 < re; i += 2) {  // two rows per step: both rows' scalar loads issued together
@@ -370,6 +374,7 @@ __global__ __launch_bounds__(kLmsBlock) void lms_filter_kernel(
       flush(u, staged[u]);
       cnt[c[u] * nseg + sg] = (uint32_t)(put[u] - dst[u]);
       cnt[(m + c[u]) * nseg + sg] = below[u];
+      if (SUM) psum[c[u] * nseg + sg] = sbelow[u];
     }
   }
 }
@@ -515,6 +520,34 @@ __device__ inline void lms_write_nan(cps_result *out, int32_t passes) {
   *out = r;
 }
 
+// Sum over the workgroup in a fixed order (each wavefront's lanes by row moves, then the
+// wavefronts in order); `wred` holds one double per wavefront.  Every thread gets the sum.
+template <int BLOCK>
+__device__ inline double block_sum_fixed(double v, double *wred) {
+  const double w = wave_sum(v);
+  if (threadIdx.x % kWave == 0) wred[threadIdx.x / kWave] = w;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < BLOCK / kWave; ++i) t += wred[i];
+  __syncthreads();
+  return t;
+}
+
+// The sum of the k smallest of a candidate's n squares: below (the squares under the
+// selection's bracket, if any) plus those of W[0, len) below the selected value v, plus
+// (k - #(r < v)) v (Section 6's trimmed sum with the multiplicity of v); one more pass over W.
+template <int BLOCK>
+__device__ inline double lms_ksum(const CPS_GLOBAL double *W, int64_t len, double v, int64_t k,
+                                  int64_t less, double below, double *wred) {
+  double part = 0.0;
+  for_each8<BLOCK>(W, len, [&](double r) {
+    if (r < v) part += r;
+  });
+  const double s = block_sum_fixed<BLOCK>(part, wred);
+  return below + s + (double)(k - less) * v;
+}
+
 // One workgroup per candidate: the segments' counts and the bracket's test; where it holds,
 // the kept squares packed into C + c * cap in segment order, counted on the way in 2^12 key
 // bins over the bracket's open interval (a, b) (NaN noted), and the select of rank
@@ -525,30 +558,32 @@ __device__ inline void lms_write_nan(cps_result *out, int32_t passes) {
 __global__ __launch_bounds__(kLmsGatherBlock) void lms_gather_kernel(
     const double *__restrict__ R, const uint32_t *__restrict__ cnt, const double *__restrict__ ab,
     int64_t n, int64_t m, int64_t nseg, int64_t seg, int64_t k, int64_t cap, double *__restrict__ C,
-    cps_result *__restrict__ out, int32_t *__restrict__ full) {
+    const double *__restrict__ psum, cps_result *__restrict__ out, double *__restrict__ ksum,
+    int32_t *__restrict__ full) {
   __shared__ uint32_t pre[kLmsMaxSegs + 1];
   __shared__ uint32_t hist[kHistMaxBins];
   __shared__ double buf[kLmsSelCap];
   __shared__ WgSelLds sh;
   __shared__ uint64_t tot[2];
+  __shared__ double wred[kLmsGatherBlock / kWave];
   constexpr int SPT = kLmsMaxSegs / kLmsGatherBlock;
   const int64_t c = blockIdx.x;
   const int tid = threadIdx.x;
   uint32_t kv[SPT];
-  uint64_t ksum = 0, bsum = 0;
+  uint64_t kcount = 0, bsum = 0;
 #pragma unroll
   for (int j = 0; j < SPT; ++j) {
     const int64_t s = (int64_t)tid * SPT + j;
     kv[j] = s < nseg ? cnt[c * nseg + s] : 0u;
-    ksum += kv[j];
+    kcount += kv[j];
     bsum += s < nseg ? cnt[(m + c) * nseg + s] : 0u;
   }
-  uint64_t run = block_exclusive_scan<kLmsGatherBlock>(ksum, sh.wsum);
+  uint64_t run = block_exclusive_scan<kLmsGatherBlock>(kcount, sh.wsum);
   const uint64_t bpre = block_exclusive_scan<kLmsGatherBlock>(bsum, sh.wsum);
   if (tid == kLmsGatherBlock - 1) {
-    tot[0] = run + ksum;
+    tot[0] = run + kcount;
     tot[1] = bpre + bsum;
-    pre[kLmsMaxSegs] = (uint32_t)(run + ksum);
+    pre[kLmsMaxSegs] = (uint32_t)(run + kcount);
   }
   if (tid == 0) sh.flag = 0u;
 #pragma unroll
@@ -601,7 +636,10 @@ __global__ __launch_bounds__(kLmsGatherBlock) void lms_gather_kernel(
   if (nan) atomicOr(&sh.flag, 1u);
   __syncthreads();  // (the packed squares, written by this workgroup, are read below)
   if (sh.flag != 0u) {  // (uniform)
-    if (tid == 0) lms_write_nan(out + c, 2);
+    if (tid == 0) {
+      lms_write_nan(out + c, 2);
+      if (ksum) ksum[c] = __builtin_nan("");
+    }
     return;
   }
   // the bin of rank k - #(r <= a) among the packed squares
@@ -634,6 +672,19 @@ __global__ __launch_bounds__(kLmsGatherBlock) void lms_gather_kernel(
   const WgSelOut r = wg_select<kLmsGatherBlock>(C + c * cap, inside, rr, nlo, nhi, below0, in0,
                                                 hist, buf, sh);
   if (tid == 0) lms_write_result(out + c, r.key, bel + r.less, r.equal, n, 3 + r.passes);
+  if (ksum) {  // (uniform)
+    // the squares under a: the segments' sums, each thread's run of segments in order
+    double sb = 0.0;
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+      const int64_t s2 = (int64_t)tid * SPT + j;
+      if (s2 < nseg) sb += psum[c * nseg + s2];
+    }
+    const double below_sum = block_sum_fixed<kLmsGatherBlock>(sb, wred);
+    const double v = Traits<double>::unkey(r.key);
+    const double t = lms_ksum<kLmsGatherBlock>(Cc, inside, v, rr, r.less, below_sum, wred);
+    if (tid == 0) ksum[c] = t;
+  }
 }
 
 // After the fallback residual kernel: the candidates whose bracket missed, over their whole
@@ -641,10 +692,11 @@ __global__ __launch_bounds__(kLmsGatherBlock) void lms_gather_kernel(
 // workgroups return at once.
 __global__ __launch_bounds__(kLmsGatherBlock) void lms_full_select_kernel(
     const double *__restrict__ R, int64_t n, int64_t k, const int32_t *__restrict__ full,
-    cps_result *__restrict__ out) {
+    cps_result *__restrict__ out, double *__restrict__ ksum) {
   __shared__ uint32_t hist[kHistMaxBins];
   __shared__ double buf[kLmsSelCap];
   __shared__ WgSelLds sh;
+  __shared__ double wred[kLmsGatherBlock / kWave];
   const int64_t c = blockIdx.x;
   const int tid = threadIdx.x;
   if (full[c] == 0) return;  // (uniform)
@@ -668,12 +720,20 @@ __global__ __launch_bounds__(kLmsGatherBlock) void lms_full_select_kernel(
   if (nan) atomicOr(&sh.flag, 1u);
   __syncthreads();
   if (sh.flag != 0u) {  // (uniform)
-    if (tid == 0) lms_write_nan(out + c, 3);
+    if (tid == 0) {
+      lms_write_nan(out + c, 3);
+      if (ksum) ksum[c] = __builtin_nan("");
+    }
     return;
   }
   const WgSelOut r = wg_select<kLmsGatherBlock>(R + c * n, n, k, sh.kext[0], sh.kext[1], 0, n,
                                                 hist, buf, sh);
   if (tid == 0) lms_write_result(out + c, r.key, r.less, r.equal, n, 3 + r.passes);
+  if (ksum) {  // (uniform)
+    const double t = lms_ksum<kLmsGatherBlock>(Rc, n, Traits<double>::unkey(r.key), k, r.less,
+                                               0.0, wred);
+    if (tid == 0) ksum[c] = t;
+  }
 }
 
 __global__ void lms_descriptor_kernel(const double *R, int64_t n, int64_t m, int64_t rank,
@@ -747,8 +807,8 @@ void lms_filter_shape(int64_t n, int64_t m, int32_t p, bool vec, int cu_count, i
   int per_cu = 0;
   (void)vec;
   const hipError_t e =
-      p == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lms_filter_kernel<8>, kLmsBlock, 0)
-             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lms_filter_kernel<0>, kLmsBlock, 0);
+      p == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lms_filter_kernel<8, false>, kLmsBlock, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lms_filter_kernel<0, false>, kLmsBlock, 0);
   if (e != hipSuccess || per_cu < 1) per_cu = 4;
   const int64_t fgroups = (m + kLmsCands - 1) / kLmsCands;
   int64_t ns = (int64_t)cu_count * per_cu * kLmsRounds / fgroups;
@@ -771,7 +831,7 @@ int64_t lms_filter_cap(int64_t n) { return (n / 8 + 1 + 31) / 32 * 32; }
 
 hipError_t launch_lms_filtered(const double *X, const double *y, const double *betas, int64_t n,
                                int32_t p, int64_t m, int64_t rank, const LmsFilterBufs &w,
-                               cps_result *out, hipStream_t stream) {
+                               cps_result *out, double *ksum, hipStream_t stream) {
   const int64_t groups = (m + kLmsGroup - 1) / kLmsGroup;
   const int64_t fgroups = (m + kLmsCands - 1) / kLmsCands;
   const int64_t sgroups = (m + kLmsBlock - 1) / kLmsBlock;
@@ -788,17 +848,23 @@ hipError_t launch_lms_filtered(const double *X, const double *y, const double *b
   if (e != hipSuccess) return e;
   const bool aligned = ((uintptr_t)X % 16 == 0) && ((uintptr_t)y % 16 == 0);
   const dim3 fgrid((unsigned)w.nseg, (unsigned)fgroups);
-  if (p == 8)
-    lms_filter_kernel<8><<<fgrid, dim3(kLmsBlock), 0, stream>>>(X, y, betas, w.ab, n, p, m, w.seg,
-                                                                 w.R, w.cnt);
+  if (p == 8 && !ksum)
+    lms_filter_kernel<8, false><<<fgrid, dim3(kLmsBlock), 0, stream>>>(
+        X, y, betas, w.ab, n, p, m, w.seg, w.R, w.cnt, nullptr);
+  else if (p == 8)
+    lms_filter_kernel<8, true><<<fgrid, dim3(kLmsBlock), 0, stream>>>(
+        X, y, betas, w.ab, n, p, m, w.seg, w.R, w.cnt, w.psum);
+  else if (!ksum)
+    lms_filter_kernel<0, false><<<fgrid, dim3(kLmsBlock), 0, stream>>>(
+        X, y, betas, w.ab, n, p, m, w.seg, w.R, w.cnt, nullptr);
   else
-    lms_filter_kernel<0><<<fgrid, dim3(kLmsBlock), 0, stream>>>(X, y, betas, w.ab, n, p, m, w.seg,
-                                                                 w.R, w.cnt);
+    lms_filter_kernel<0, true><<<fgrid, dim3(kLmsBlock), 0, stream>>>(
+        X, y, betas, w.ab, n, p, m, w.seg, w.R, w.cnt, w.psum);
   const dim3 grid((unsigned)w.bx, (unsigned)groups);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   lms_gather_kernel<<<dim3((unsigned)m), dim3(kLmsGatherBlock), 0, stream>>>(
-      w.R, w.cnt, w.ab, n, m, w.nseg, w.seg, rank, w.cap, w.C, out, w.full);
+      w.R, w.cnt, w.ab, n, m, w.nseg, w.seg, rank, w.cap, w.C, w.psum, out, ksum, w.full);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   // the candidates whose bracket missed: their whole arrays (workgroups without one return)
@@ -815,7 +881,7 @@ hipError_t launch_lms_filtered(const double *X, const double *y, const double *b
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   lms_full_select_kernel<<<dim3((unsigned)m), dim3(kLmsGatherBlock), 0, stream>>>(w.R, n, rank,
-                                                                                w.full, out);
+                                                                                w.full, out, ksum);
   return hipGetLastError();
 }
 

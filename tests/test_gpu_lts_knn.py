@@ -65,13 +65,18 @@ def test_batched_ksum(sel, oracle_mod, dtype, opt):
         assert abs(ksum[i] - t["F"]) <= 1e-12 * max(_abs_scale(x, k), 1e-300), (i, ksum[i], t["F"])
 
 
-@pytest.mark.parametrize("n,p,m", [(1001, 8, 40), ((1 << 17) + 3, 8, 64), (50_000, 3, 17)])
-def test_lts_parity(sel, oracle_mod, n, p, m):
+@pytest.mark.parametrize("form", [0, 1, 2])  # automatic, materialised, filtered
+@pytest.mark.parametrize("n,p,m", [(1001, 8, 40), ((1 << 17) + 3, 8, 64), (50_000, 3, 17),
+                                   ((1 << 18) + 2, 8, 70)])
+def test_lts_parity(sel, oracle_mod, n, p, m, form):
+    import paper_1104_2732_amd as cps
+    if form == 2 and n < (1 << 15):
+        return  # (the filtered form needs 2^15 rows; the argument check is in the LMS tests)
     X, y, _, betas = workloads.lms_problem(n, p, m, seed=n % 97)
     Xd, yd, bd = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (X, y, betas))
     for h in sorted({(n + 1) // 2, (n + p) // 2, 1, n, n // 3 + 1}):
-        print(f"case lts n={n} p={p} m={m} h={h}", flush=True)
-        got = sel.lts_trimmed_sq(Xd, yd, bd, h)
+        print(f"case lts n={n} p={p} m={m} h={h} form={form}", flush=True)
+        got = sel.lts_trimmed_sq(Xd, yd, bd, h, form=form)
         ref = oracle_mod.lts_objective(X, y, betas, h)
         for c in range(m):
             assert got[c]["status"] == 0
@@ -92,6 +97,10 @@ def test_lts_full_size_sampled(sel, oracle_mod):
     got = sel.lts_trimmed_sq(Xd, yd, bd)
     lms = sel.lms_median_sq_residuals(Xd, yd, bd)
     assert np.array_equal(got["m"], lms["value"]) and np.array_equal(got["below"], lms["less"])
+    mat = sel.lts_trimmed_sq(Xd, yd, bd, form=1)  # the materialised form: same records
+    for f in ("m", "below", "a", "b", "status"):
+        assert np.array_equal(got[f], mat[f]), f
+    assert np.all(np.abs(got["F"] - mat["F"]) <= 1e-12 * mat["F"])
     pick = np.random.default_rng(1).choice(m, size=8, replace=False)
     ref = oracle_mod.lts_objective(X, y, betas[pick])
     for j, c in enumerate(pick):
