@@ -283,11 +283,14 @@ def lts_knn_leg(sel, torch, reps: int = 5) -> dict:
     Pd, fd, Qd = (torch.from_numpy(a).cuda() for a in (P, f, Q))
     kout = torch.empty(nq * cps.KNN_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
     knn_ms = _time_ms(torch, lambda: sel.knn_mean_async(Pd, fd, Qd, k, kout), reps)
+    knn_mat_ms = _time_ms(torch, lambda: sel.knn_mean_async(Pd, fd, Qd, k, kout,
+                                                            cps.LMS_MATERIALISED), reps)
     return {"lts": {"workload": "n=2^20 rows, p=8, 1024 candidates, h=floor((n+1)/2)",
                     "ms": lts_ms, "residuals_per_s": n * m / (lts_ms * 1e-3),
                     "materialised_ms": lts_mat_ms},
             "knn": {"workload": "2^20 points in 8 dimensions (N(0,1)), 1024 queries, k=64",
-                    "ms": knn_ms, "distances_per_s": nk * nq / (knn_ms * 1e-3)}}
+                    "ms": knn_ms, "distances_per_s": nk * nq / (knn_ms * 1e-3),
+                    "materialised_ms": knn_mat_ms}}
 
 
 def transform_leg(sel, cps, torch, reps: int = 3) -> dict:

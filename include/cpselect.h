@@ -497,12 +497,27 @@ typedef struct cps_knn {
  * their k-th smallest dk by the batched selection; and the mean ordinate of the k nearest
  * points, (sum_{d < dk} f_i + (a / b) sum_{d = dk} f_i) / k with b = #(d = dk),
  * a = k - #(d < dk) (Section 6's rho as an indicator: exactly k points' worth), summed in
- * double precision in a fixed order.  f_dev: n floats.  The distances are materialised in the
- * handle's workspace (nq x n floats) for the selection; the reduction recomputes them.
+ * double precision in a fixed order.  f_dev: n floats.  In the materialised form the
+ * distances are written to the handle's workspace (nq x n floats) for the selection and read
+ * back by the reduction.
  * Errors: CPS_EINVAL for null pointers, n < 1, dim outside [1, 16], nq outside [1, 65535],
  * k outside [1, n]. */
 int knn_mean(cps_handle *h, const float *P_dev, const float *f_dev, const float *Q_dev, int64_t n,
              int32_t dim, int64_t nq, int64_t k, cps_knn *out_dev, void *stream);
+
+/* knn_mean with a choice of form (cps_lms_form; CPS_LMS_AUTO is knn_mean, which takes the
+ * filtered form from n = 2^15 on).  Filtered: each query's sampled bracket (a, b) from the
+ * distances of the points the batched kernel would sample, one pass over the points that
+ * keeps the distances in (a, b) (and NaN) with their ordinates (at most 8192 per query),
+ * counting d <= a and summing its ordinates; d_k by a radix select among the kept ones, the
+ * sums below and at d_k in a fixed order.  A query whose bracket misses d_k, or that keeps
+ * more, is selected by one workgroup over its distances recomputed.  Same results (the
+ * ordinates' sum over d <= a is added over segments in no fixed order, so its last bits may
+ * vary).  Errors: as knn_mean, and CPS_EINVAL for a form outside cps_lms_form, or
+ * CPS_LMS_FILTERED with n outside [2^15, 2^31). */
+int knn_mean_ex(cps_handle *h, const float *P_dev, const float *f_dev, const float *Q_dev,
+                int64_t n, int32_t dim, int64_t nq, int64_t k, int32_t form, cps_knn *out_dev,
+                void *stream);
 
 /* ------------------------------------------------------------------ learned bracket proposal
  *

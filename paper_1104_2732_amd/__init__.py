@@ -125,7 +125,7 @@ EXPORTS = ("cps_create", "cps_destroy", "cps_status_string", "cps_last_hip_error
            "cps_mlp_adam", "cps_mlp_init", "cps_learned_bracket", "select_kth_learned",
            "cps_mlp_train", "select_kth_sampled", "cps_sample_bracket", "cps_model_save",
            "cps_model_load", "select_kth_noalloc", "select_kth_batched_ksum", "lts_trimmed_sq", "lts_trimmed_sq_ex",
-           "knn_mean")
+           "knn_mean", "knn_mean_ex")
 STATUS_BADARG = 4
 LMS_AUTO, LMS_MATERIALISED, LMS_FILTERED = 0, 1, 2  # cps_lms_form
 
@@ -166,6 +166,8 @@ def lib() -> ctypes.CDLL:
     L.lts_trimmed_sq_ex.restype = c_int
     L.knn_mean.argtypes = [vp, vp, vp, vp, i64, i32, i64, i64, vp, vp]
     L.knn_mean.restype = c_int
+    L.knn_mean_ex.argtypes = [vp, vp, vp, vp, i64, i32, i64, i64, i32, vp, vp]
+    L.knn_mean_ex.restype = c_int
     L.cps_objective.argtypes = [vp, vp, i64, i64, c_int, vp, i64, vp, vp]
     L.cps_objective.restype = c_int
     L.cps_default_batch_options.argtypes = [ctypes.POINTER(BatchOptions)]
@@ -453,8 +455,9 @@ class Selector:
         torch.cuda.synchronize(self.device)
         return _as_records(out, TRIM_DTYPE).copy()
 
-    def knn_mean_async(self, P, f, Q, k: int, out) -> None:
-        """Enqueue knn_mean: P (n x dim), f (n), Q (nq x dim) float32 CUDA tensors."""
+    def knn_mean_async(self, P, f, Q, k: int, out, form: int = 0) -> None:
+        """Enqueue knn_mean_ex: P (n x dim), f (n), Q (nq x dim) float32 CUDA tensors; form
+        LMS_AUTO, LMS_MATERIALISED or LMS_FILTERED."""
         import torch
         for t in (P, f, Q):
             if not t.is_cuda or not t.is_contiguous() or t.dtype != torch.float32:
@@ -463,15 +466,15 @@ class Selector:
         nq = Q.shape[0]
         if f.numel() != n or Q.shape[1] != dim:
             raise ValueError("shape mismatch between P, f and Q")
-        _check(lib().knn_mean(self._h, self._ptr(P), self._ptr(f), self._ptr(Q), n, dim, nq, int(k),
-                              self._ptr(out), ctypes.c_void_p(_stream_ptr(self.device))),
-               "knn_mean")
+        _check(lib().knn_mean_ex(self._h, self._ptr(P), self._ptr(f), self._ptr(Q), n, dim, nq,
+                                 int(k), int(form), self._ptr(out),
+                                 ctypes.c_void_p(_stream_ptr(self.device))), "knn_mean_ex")
 
-    def knn_mean(self, P, f, Q, k: int) -> np.ndarray:
+    def knn_mean(self, P, f, Q, k: int, form: int = 0) -> np.ndarray:
         """The mean ordinate of each query's k nearest points; KNN_DTYPE records."""
         import torch
         out = torch.empty(Q.shape[0] * KNN_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
-        self.knn_mean_async(P, f, Q, k, out)
+        self.knn_mean_async(P, f, Q, k, out, form)
         torch.cuda.synchronize(self.device)
         return _as_records(out, KNN_DTYPE).copy()
 

@@ -609,12 +609,36 @@ int lts_trimmed_sq(cps_handle *h, const double *X_dev, const double *y_dev,
   return lts_trimmed_sq_ex(h, X_dev, y_dev, betas_dev, n, p, m, hk, CPS_LMS_AUTO, out_dev, stream);
 }
 
-int knn_mean(cps_handle *h, const float *P_dev, const float *f_dev, const float *Q_dev, int64_t n,
-             int32_t dim, int64_t nq, int64_t k, cps_knn *out_dev, void *stream) {
+int knn_mean_ex(cps_handle *h, const float *P_dev, const float *f_dev, const float *Q_dev,
+                int64_t n, int32_t dim, int64_t nq, int64_t k, int32_t form, cps_knn *out_dev,
+                void *stream) {
   if (!h || !P_dev || !f_dev || !Q_dev || !out_dev || n < 1 || dim < 1 || dim > 16 || nq < 1 ||
-      nq > 65535 || k < 1 || k > n)
+      nq > 65535 || k < 1 || k > n || form < CPS_LMS_AUTO || form > CPS_LMS_FILTERED)
     return CPS_EINVAL;
+  const bool can_filter = lms_can_filter(n);
+  if (form == CPS_LMS_FILTERED && !can_filter) return CPS_EINVAL;
   hipStream_t s = (hipStream_t)stream;
+  if (form == CPS_LMS_FILTERED || (form == CPS_LMS_AUTO && can_filter)) {
+    // sampled distances, brackets, counters, ordinate sums, kept distances and ordinates
+    std::lock_guard<std::mutex> lk(h->mu);
+    cps::KnnFilterBufs w;
+    cps::knn_filter_shape(n, nq, h->cu_count, &w.nseg, &w.seg);
+    const size_t off_ab = align_up((size_t)nq * 16384 * sizeof(float), 256);
+    const size_t off_cnt = off_ab + align_up((size_t)nq * 2 * sizeof(float), 256);
+    const size_t off_fs = off_cnt + align_up((size_t)nq * 2 * sizeof(uint32_t), 256);
+    const size_t off_k = off_fs + align_up((size_t)nq * sizeof(double), 256);
+    const size_t bytes = off_k + (size_t)nq * cps::kKnnKeptCap * 2 * sizeof(float);
+    int rc = ensure_buffer(h->lws, h->lws_bytes, bytes, s);
+    if (rc) return rc;
+    char *base = (char *)h->lws;
+    w.Ds = (float *)base;
+    w.ab = (float *)(base + off_ab);
+    w.cnt = (uint32_t *)(base + off_cnt);
+    w.fsum = (double *)(base + off_fs);
+    w.K = (float *)(base + off_k);
+    hipError_t e = cps::launch_knn_filtered(P_dev, f_dev, Q_dev, n, dim, nq, k, w, out_dev, s);
+    return e == hipSuccess ? CPS_OK : hip_fail(e);
+  }
   const size_t off_desc = align_up((size_t)nq * (size_t)n * sizeof(float), 256);
   const size_t dsz = align_up((size_t)nq * 8, 256);
   const size_t off_sel = off_desc + 3 * dsz;
@@ -645,6 +669,11 @@ int knn_mean(cps_handle *h, const float *P_dev, const float *f_dev, const float 
                                         (double *)(base + off_pd), (int64_t *)(base + off_pd + psz),
                                         out_dev, s);
   return e == hipSuccess ? CPS_OK : hip_fail(e);
+}
+
+int knn_mean(cps_handle *h, const float *P_dev, const float *f_dev, const float *Q_dev, int64_t n,
+             int32_t dim, int64_t nq, int64_t k, cps_knn *out_dev, void *stream) {
+  return knn_mean_ex(h, P_dev, f_dev, Q_dev, n, dim, nq, k, CPS_LMS_AUTO, out_dev, stream);
 }
 
 int cps_autotune_batched(cps_handle *h, const void *const *ptrs_dev, const int64_t *sizes_dev,

@@ -169,6 +169,20 @@ hipError_t launch_lts_finish(const cps_result *sel, const double *ksum, int64_t 
                              cps_trim *out, hipStream_t stream);
 
 // ---- k nearest neighbours
+// The filtered kNN form's workspace (device memory) and shape.
+struct KnnFilterBufs {
+  float *Ds;           // nq x S: distances of the sampled points (S <= 16384)
+  float *ab;           // 2 nq: the sampled brackets
+  uint32_t *cnt;       // 2 nq: kept count (cursor), #(d <= a)
+  double *fsum;        // nq: the ordinates' sum over d <= a
+  float *K;            // nq x kKnnCap x 2: kept distances and ordinates
+  int64_t nseg, seg;   // the filter's segments and points per segment
+};
+constexpr int64_t kKnnKeptCap = 8192;  // kept distances per query (the filtered form)
+void knn_filter_shape(int64_t n, int64_t nq, int cu_count, int64_t *nseg, int64_t *seg);
+hipError_t launch_knn_filtered(const float *P, const float *f, const float *Q, int64_t n,
+                               int32_t dim, int64_t nq, int64_t k, const KnnFilterBufs &w,
+                               cps_knn *out, hipStream_t stream);
 hipError_t launch_knn_distances(const float *P, const float *Q, int64_t n, int32_t dim, int64_t nq,
                                 int64_t k, float *Dst, const float **ptrs, int64_t *sizes,
                                 int64_t *ks, int cu_count, hipStream_t stream);

@@ -15,6 +15,8 @@
 #include "cps_device.h"
 #include "cps_kernels.h"
 #include "cps_passes.h"
+#include "cps_sample.h"
+#include "cps_wgsel.h"
 
 namespace cps {
 
@@ -203,6 +205,308 @@ __global__ void knn_final_kernel(int64_t nq, int64_t k, int nb, const cps_result
                                        : __builtin_nan("");
     out[c] = o;
   }
+}
+
+// ------------------------------------------------------------------ the filtered form
+//
+// For small k the k nearest are a sliver of the n points: a sampled bracket (a, b) of each
+// query's distances (the batched kernel's rule over the distances of the sampled points)
+// keeps only the distances in (a, b), with their ordinates, and the selection and the
+// reductions run over those.  #(d <= a) and the ordinates' sum there come from the same
+// pass; a query whose bracket does not hold d_k (or keeps more than kKnnCap) is selected by
+// its own workgroup over recomputed distances.  Results equal the materialised form's.
+
+constexpr int kKnnCap = (int)kKnnKeptCap;  // (the select holds them in LDS)
+
+// d = sum_j (P_ij - q_j)^2 for a row and a query both in registers, in the order knn_dist uses
+template <int D>
+__device__ __forceinline__ float knn_dist_reg(const float (&row)[D > 0 ? D : 16],
+                                              const float (&qv)[D > 0 ? D : 16], int dim) {
+  const int dd = D > 0 ? D : dim;
+  float s = 0.0f;
+#pragma unroll
+  for (int j = 0; j < (D > 0 ? D : 16); ++j) {
+    if (j < dd) {
+      const float e = row[j] - qv[j];
+      const float sq = e * e;
+      s = j == 0 ? sq : s + sq;
+    }
+  }
+  return s;
+}
+
+// The distances of the sampled points (runs of kPropRun at sample_stride apart), one query
+// per lane, the points as scalar loads; one run per workgroup along x.
+template <int D>
+__global__ __launch_bounds__(kKnnBlock) void knn_sample_kernel(
+    const float *__restrict__ P, const float *__restrict__ Q, int64_t n, int32_t dim, int64_t nq,
+    float *__restrict__ Ds) {
+  constexpr int DM = D > 0 ? D : 16;
+  const int dd = D > 0 ? D : dim;
+  const int64_t q = (int64_t)blockIdx.y * kKnnBlock + threadIdx.x;
+  const bool live = q < nq;
+  float qv[DM];
+#pragma unroll
+  for (int j = 0; j < DM; ++j) qv[j] = live && j < dd ? Q[q * dd + j] : 0.0f;
+  const int S = sample_size(n);
+  const int64_t stride = sample_stride(n, S);
+  const int run = blockIdx.x;
+  for (int r = 0; r < kPropRun; ++r) {
+    const int64_t i = (int64_t)run * stride + r;
+    float row[DM];
+#pragma unroll
+    for (int j = 0; j < DM; ++j) row[j] = j < dd ? P[i * dd + j] : 0.0f;
+    const float d = knn_dist_reg<D>(row, qv, dim);
+    if (live) Ds[q * S + run * kPropRun + r] = d;
+  }
+}
+
+struct KnnBracketShared {
+  uint64_t kext[2];
+  int32_t flag;
+  SampleLds smp;
+  uint64_t wsum[kKnnBlock / kWave];
+  uint32_t rh[kHistMaxBins];
+};
+
+// One workgroup per query: its sampled bracket to ab[2c], ab[2c+1] ((+inf, -inf) where there
+// is none: the filter then keeps nothing but NaN and the select recomputes), and the filter's
+// counters of c cleared.
+__global__ __launch_bounds__(kKnnBlock) void knn_bracket_kernel(
+    const float *__restrict__ Ds, int64_t n, int64_t k, int64_t nq, float *__restrict__ ab,
+    uint32_t *__restrict__ cnt, double *__restrict__ fsum) {
+  __shared__ KnnBracketShared sh;
+  const int64_t c = blockIdx.x;
+  if (threadIdx.x < 2) cnt[threadIdx.x * nq + c] = 0u;
+  if (threadIdx.x == 2) fsum[c] = 0.0;
+  const int S = sample_size(n);
+  const CPS_GLOBAL float *src = (const CPS_GLOBAL float *)Ds + c * S;
+  auto sample = [&](int i) -> float { return src[i]; };
+  float a, b;
+  const bool use = sample_bracket_rule<float, kKnnBlock>(sample, S, n, k, sh, a, b);
+  if (threadIdx.x == 0) {
+    ab[2 * c] = use ? a : __builtin_inff();
+    ab[2 * c + 1] = use ? b : -__builtin_inff();
+  }
+}
+
+// The filter: one query per lane, the points of segment blockIdx.x as scalar loads.  A
+// distance with a < d < b (or NaN) is kept with its ordinate at a place reserved on the
+// query's cursor (rare for small k), if below kKnnCap; d <= a is counted and its ordinate
+// summed (in point order; the segments' sums added atomically).
+template <int D>
+__global__ __launch_bounds__(kKnnBlock) void knn_filter_kernel(
+    const float *__restrict__ P, const float *__restrict__ f, const float *__restrict__ Q,
+    const float *__restrict__ ab, int64_t n, int32_t dim, int64_t nq, int64_t seg,
+    float *__restrict__ K, uint32_t *__restrict__ cnt, double *__restrict__ fsum) {
+  constexpr int DM = D > 0 ? D : 16;
+  const int dd = D > 0 ? D : dim;
+  const int64_t q = (int64_t)blockIdx.y * kKnnBlock + threadIdx.x;
+  const bool live = q < nq;
+  float qv[DM];
+#pragma unroll
+  for (int j = 0; j < DM; ++j) qv[j] = live && j < dd ? Q[q * dd + j] : 0.0f;
+  const float lo = live ? ab[2 * q] : __builtin_inff();
+  const float hi = live ? ab[2 * q + 1] : -__builtin_inff();
+  const int64_t rb = (int64_t)blockIdx.x * seg;
+  const int64_t re = rb + seg < n ? rb + seg : n;
+  uint32_t below = 0;
+  double fb = 0.0;
+  for (int64_t i = rb; i < re; ++i) {
+    float row[DM];
+#pragma unroll
+    for (int j = 0; j < DM; ++j) row[j] = j < dd ? P[i * dd + j] : 0.0f;
+    const float fi = f[i];
+    const float d = knn_dist_reg<D>(row, qv, dim);
+    const bool le = d <= lo;
+    if (live && !le && !(d >= hi)) {
+      const uint32_t at = atomicAdd(&cnt[q], 1u);
+      if (at < (uint32_t)kKnnCap) {
+        K[2 * (q * kKnnCap + at)] = d;
+        K[2 * (q * kKnnCap + at) + 1] = fi;
+      }
+    }
+    if (le) {
+      ++below;
+      fb += (double)fi;
+    }
+  }
+  if (live && below) {
+    atomicAdd(&cnt[nq + q], below);
+    atomicAdd(&fsum[q], fb);
+  }
+}
+
+__device__ inline void knn_write(cps_knn *out, double mean, float dk, int32_t status,
+                                 int64_t below, int64_t equal) {
+  cps_knn o;
+  o.mean = mean;
+  o.dk = dk;
+  o.status = status;
+  o.below = below;
+  o.equal = equal;
+  *out = o;
+}
+
+// One workgroup per query: where the bracket holds d_k (#(d <= a) < k <= #(d <= a) + kept,
+// kept <= kKnnCap), the kept distances and ordinates in LDS, d_k by a radix select of rank
+// k - #(d <= a) among them, and the sums of the ordinates below and at d_k (fixed order);
+// else the same over the query's n distances recomputed (key range, histogram narrowing,
+// a last pass for the sums).  The mean as the materialised form's final kernel forms it.
+template <int D>
+__global__ __launch_bounds__(kKnnBlock) void knn_select_kernel(
+    const float *__restrict__ K, const uint32_t *__restrict__ cnt,
+    const double *__restrict__ fsum, const float *__restrict__ ab, const float *__restrict__ P,
+    const float *__restrict__ f, const float *__restrict__ Q, int64_t n, int32_t dim, int64_t nq,
+    int64_t k, cps_knn *__restrict__ out) {
+  constexpr int DM = D > 0 ? D : 16;
+  __shared__ float kd[kKnnCap];
+  __shared__ float kf[kKnnCap];
+  __shared__ uint32_t hist[kHistMaxBins];
+  __shared__ WgSelShared<kKnnBlock> sh;
+  __shared__ double wred[kKnnBlock / kWave];
+  __shared__ float sq[16];
+  const int64_t c = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int dd = D > 0 ? D : dim;
+  const int64_t len = cnt[c], below = cnt[nq + c];
+  const float lo = ab[2 * c], hi = ab[2 * c + 1];
+  const bool holds = lo < hi && below < k && k <= below + len && len <= kKnnCap;
+  if (tid < dd) sq[tid] = Q[c * dd + tid];
+  if (tid == 0) {
+    sh.flag = 0u;
+    sh.kext[0] = ~0ull;
+    sh.kext[1] = 0ull;
+  }
+  __syncthreads();
+  if (holds) {  // (uniform)
+    bool nan = false;
+    for (int64_t i = tid; i < len; i += kKnnBlock) {
+      const float d = K[2 * (c * kKnnCap + i)];
+      kd[i] = d;
+      kf[i] = K[2 * (c * kKnnCap + i) + 1];
+      nan = nan || !(d == d);
+    }
+    if (nan) atomicOr(&sh.flag, 1u);
+    __syncthreads();
+    if (sh.flag != 0u) {
+      if (tid == 0) knn_write(out + c, __builtin_nan(""), __builtin_nanf(""), CPS_STATUS_NAN, 0, 0);
+      return;
+    }
+    uint32_t key;
+    int64_t b_in, eq;
+    block_radix_select<float, kKnnBlock>(kd, len, false, 0.0f, 0.0f, k - below, hist, sh.misc,
+                                         key, b_in, eq);
+    const float dk = Traits<float>::unkey(key);
+    double slt = 0.0, seq = 0.0;
+    for (int64_t i = tid; i < len; i += kKnnBlock) {
+      if (kd[i] < dk) slt += (double)kf[i];
+      else if (kd[i] == dk) seq += (double)kf[i];
+    }
+    slt = block_sum_fixed<kKnnBlock>(slt, wred);
+    seq = block_sum_fixed<kKnnBlock>(seq, wred);
+    const int64_t less = below + b_in;
+    if (tid == 0) {
+      const double a = (double)(k - less);
+      const double mean = (fsum[c] + slt + a * seq / (double)eq) / (double)k;
+      knn_write(out + c, mean, dk, CPS_STATUS_OK, less, eq);
+    }
+    return;
+  }
+  // the query's distances, recomputed in point order from its share
+  float qv[DM];
+#pragma unroll
+  for (int j = 0; j < DM; ++j) qv[j] = j < dd ? sq[j] : 0.0f;
+  auto pass = [&](auto fn) {
+    for (int64_t i = tid; i < n; i += kKnnBlock) {
+      float row[DM];
+#pragma unroll
+      for (int j = 0; j < DM; ++j) row[j] = j < dd ? P[i * dd + j] : 0.0f;
+      fn(knn_dist_reg<D>(row, qv, dim));
+    }
+  };
+  uint32_t kmn = ~0u, kmx = 0u;
+  bool nan = false;
+  pass([&](float d) {
+    const uint32_t kk = Traits<float>::key(d);
+    nan = nan || !(d == d);
+    kmn = kk < kmn ? kk : kmn;
+    kmx = kk > kmx ? kk : kmx;
+  });
+  atomicMin(&sh.kext[0], (unsigned long long)kmn);
+  atomicMax(&sh.kext[1], (unsigned long long)kmx);
+  if (nan) atomicOr(&sh.flag, 1u);
+  __syncthreads();
+  if (sh.flag != 0u) {  // (uniform)
+    if (tid == 0) knn_write(out + c, __builtin_nan(""), __builtin_nanf(""), CPS_STATUS_NAN, 0, 0);
+    return;
+  }
+  const WgSelOut r = wg_select_pass<float, kKnnBlock>(pass, k, sh.kext[0], sh.kext[1], 0, n, hist,
+                                                      kd, kKnnCap, sh);
+  const float dk = Traits<float>::unkey((uint32_t)r.key);
+  double slt = 0.0, seq = 0.0;
+  for (int64_t i = tid; i < n; i += kKnnBlock) {
+    float row[DM];
+#pragma unroll
+    for (int j = 0; j < DM; ++j) row[j] = j < dd ? P[i * dd + j] : 0.0f;
+    const float d = knn_dist_reg<D>(row, qv, dim);
+    if (d < dk) slt += (double)f[i];
+    else if (d == dk) seq += (double)f[i];
+  }
+  slt = block_sum_fixed<kKnnBlock>(slt, wred);
+  seq = block_sum_fixed<kKnnBlock>(seq, wred);
+  if (tid == 0) {
+    const double a = (double)(k - r.less);
+    knn_write(out + c, (slt + a * seq / (double)r.equal) / (double)k, dk, CPS_STATUS_OK, r.less,
+              r.equal);
+  }
+}
+
+void knn_filter_shape(int64_t n, int64_t nq, int cu_count, int64_t *nseg, int64_t *seg) {
+  // about 4 x 8 workgroups per CU over (segments x groups of kKnnBlock queries), segments of
+  // at least 256 points
+  const int64_t groups = (nq + kKnnBlock - 1) / kKnnBlock;
+  int64_t ns = (int64_t)cu_count * 32 / groups;
+  const int64_t nmax = (n + 255) / 256;
+  if (ns > nmax) ns = nmax;
+  if (ns > 65535) ns = 65535;
+  if (ns < 1) ns = 1;
+  const int64_t sl = (n + ns - 1) / ns;
+  *nseg = (n + sl - 1) / sl;
+  *seg = sl;
+}
+
+hipError_t launch_knn_filtered(const float *P, const float *f, const float *Q, int64_t n,
+                               int32_t dim, int64_t nq, int64_t k, const KnnFilterBufs &w,
+                               cps_knn *out, hipStream_t stream) {
+  const int64_t groups = (nq + kKnnBlock - 1) / kKnnBlock;
+  const dim3 sg((unsigned)sample_runs(n), (unsigned)groups);
+  if (dim == 8)
+    knn_sample_kernel<8><<<sg, dim3(kKnnBlock), 0, stream>>>(P, Q, n, dim, nq, w.Ds);
+  else
+    knn_sample_kernel<0><<<sg, dim3(kKnnBlock), 0, stream>>>(P, Q, n, dim, nq, w.Ds);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  knn_bracket_kernel<<<dim3((unsigned)nq), dim3(kKnnBlock), 0, stream>>>(w.Ds, n, k, nq, w.ab,
+                                                                        w.cnt, w.fsum);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const dim3 fg((unsigned)w.nseg, (unsigned)groups);
+  if (dim == 8)
+    knn_filter_kernel<8><<<fg, dim3(kKnnBlock), 0, stream>>>(P, f, Q, w.ab, n, dim, nq, w.seg, w.K,
+                                                              w.cnt, w.fsum);
+  else
+    knn_filter_kernel<0><<<fg, dim3(kKnnBlock), 0, stream>>>(P, f, Q, w.ab, n, dim, nq, w.seg, w.K,
+                                                              w.cnt, w.fsum);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (dim == 8)
+    knn_select_kernel<8><<<dim3((unsigned)nq), dim3(kKnnBlock), 0, stream>>>(
+        w.K, w.cnt, w.fsum, w.ab, P, f, Q, n, dim, nq, k, out);
+  else
+    knn_select_kernel<0><<<dim3((unsigned)nq), dim3(kKnnBlock), 0, stream>>>(
+        w.K, w.cnt, w.fsum, w.ab, P, f, Q, n, dim, nq, k, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_knn_distances(const float *P, const float *Q, int64_t n, int32_t dim, int64_t nq,

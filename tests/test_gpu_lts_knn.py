@@ -120,15 +120,18 @@ def _knn_inputs(n, dim, nq, seed, grid=False):
     return P, f, Q
 
 
+@pytest.mark.parametrize("form", [0, 1, 2])  # automatic, materialised, filtered
 @pytest.mark.parametrize("n,dim,nq,grid", [(5, 2, 3, False), (4099, 8, 33, False),
                                            ((1 << 16) + 5, 8, 64, False), (30_000, 3, 20, True),
-                                           (70_001, 5, 17, False)])
-def test_knn_parity(sel, oracle_mod, n, dim, nq, grid):
+                                           (70_001, 5, 17, False), (40_000, 8, 300, True)])
+def test_knn_parity(sel, oracle_mod, n, dim, nq, grid, form):
+    if form == 2 and n < (1 << 15):
+        return  # (the filtered form needs 2^15 points)
     P, f, Q = _knn_inputs(n, dim, nq, seed=n + dim, grid=grid)
     Pd, fd, Qd = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (P, f, Q))
     for k in sorted({1, min(n, 16), min(n, 100), n, max(1, n // 3)}):
-        print(f"case knn n={n} dim={dim} nq={nq} k={k} grid={grid}", flush=True)
-        got = sel.knn_mean(Pd, fd, Qd, k)
+        print(f"case knn n={n} dim={dim} nq={nq} k={k} grid={grid} form={form}", flush=True)
+        got = sel.knn_mean(Pd, fd, Qd, k, form=form)
         ref = oracle_mod.knn_mean(P, f, Q, k)
         for c in range(nq):
             assert got[c]["status"] == 0, (k, c)
@@ -146,8 +149,37 @@ def test_knn_full_size_sampled(sel, oracle_mod):
     print("case knn full size", flush=True)
     got = sel.knn_mean(Pd, fd, Qd, k)
     assert np.all(got["status"] == 0)
+    mat = sel.knn_mean(Pd, fd, Qd, k, form=1)  # the materialised form: the same records
+    for fld in ("dk", "below", "equal", "status"):
+        assert np.array_equal(got[fld], mat[fld]), fld
+    assert np.all(np.abs(got["mean"] - mat["mean"]) <= 1e-12 * float(np.sum(np.abs(f))) / k)
     pick = np.random.default_rng(2).choice(nq, size=8, replace=False)
     ref = oracle_mod.knn_mean(P, f, Q[pick], k)
     for j, c in enumerate(pick):
         assert got[c]["dk"] == ref[j]["dk"] and got[c]["below"] == ref[j]["below"]
         assert abs(got[c]["mean"] - ref[j]["mean"]) <= 1e-12 * float(np.sum(np.abs(f))) / k
+
+
+def test_knn_filtered_misleading_sample(sel, oracle_mod):
+    """Points that the sample sees near every query and the rest far away: the sampled bracket
+    is far too narrow or too wide for some k, and those queries are selected over their
+    recomputed distances; every result matches the oracle's."""
+    n, dim, nq = 1 << 16, 4, 6
+    rng = np.random.default_rng(8)
+    P = (50.0 + rng.standard_normal((n, dim))).astype(np.float32)
+    S = 4096
+    stride = n // (S // 16)
+    i = np.arange(S)
+    rows = (i // 16) * stride + i % 16
+    P[rows] = rng.standard_normal((rows.size, dim)).astype(np.float32)  # the sampled points
+    Q = rng.standard_normal((nq, dim)).astype(np.float32)
+    f = rng.standard_normal(n).astype(np.float32)
+    Pd, fd, Qd = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (P, f, Q))
+    for k in (1, 64, 5000, 30_000):
+        print(f"case knn misleading sample k={k}", flush=True)
+        got = sel.knn_mean(Pd, fd, Qd, k, form=2)
+        ref = oracle_mod.knn_mean(P, f, Q, k)
+        for c in range(nq):
+            assert got[c]["status"] == 0 and got[c]["dk"] == ref[c]["dk"], (k, c)
+            assert (got[c]["below"], got[c]["equal"]) == (ref[c]["below"], ref[c]["equal"]), (k, c)
+            assert abs(got[c]["mean"] - ref[c]["mean"]) <= 1e-12 * float(np.sum(np.abs(f))) / k
