@@ -340,8 +340,16 @@ def lms_leg(sel, cps, torch, reps: int = 5) -> dict:
     a, b = res["filtered"], res["materialised"]
     same = all(np.array_equal(a[f], b[f]) for f in ("value_bits", "less", "equal", "greater", "status"))
     passes = b["passes"].astype(np.float64)
+    # the arithmetic every form must do: 2p - 1 products and sums, the difference and the
+    # square per residual (fixed order, no fused multiply-add: one instruction each), against
+    # the double-precision vector issue rate (256 CUs x 64 lanes x 2.4 GHz, FMA counted once)
+    ops = (2 * p + 1) * n * m
+    peak_ops = 256 * 64 * 2.4e9
     return {"workload": "n=2^20 rows, p=8, 1024 candidates (residuals fixed order, no FMA)",
             "ms": ms["filtered"], "residuals_per_s": n * m / (ms["filtered"] * 1e-3),
+            "fp64_valu": {"ops_per_residual": 2 * p + 1, "ops_per_s": ops / (ms["filtered"] * 1e-3),
+                          "peak_ops_per_s": peak_ops,
+                          "frac": ops / (ms["filtered"] * 1e-3) / peak_ops},
             "materialised_ms": ms["materialised"], "forms_identical": bool(same),
             "materialised_passes_per_candidate_mean": float(passes.mean()),
             "residual_bytes_one_write_one_read": 2 * n * m * 8}
