@@ -183,3 +183,20 @@ def test_lms_filtered_nonfinite(sel, oracle_mod):
     assert np.all(res["status"] == cps.STATUS_NAN)
     with pytest.raises(oracle.OracleError):
         oracle_mod.lms_median_sq(X, y, betas)
+
+
+@pytest.mark.parametrize("n,m", [((1 << 22) + 3, 1), ((1 << 15), 513)])
+def test_lms_filtered_shapes(sel, oracle_mod, n, m):
+    """The filtered form at the edges of its launch shapes: one candidate over 2^22 + 3 rows
+    (one candidate group, the most segments, an odd row count), and 513 candidates over the
+    smallest n it takes (two candidate groups, the second with one live candidate)."""
+    p = 8
+    X, y, _, betas = workloads.lms_problem(n, p, m, seed=n % 101)
+    print(f"case lms filtered shape n={n} m={m}", flush=True)
+    got = sel.lms_median_sq_residuals(_dev(X), _dev(y), _dev(betas), form=FORMS["filtered"])
+    mat = sel.lms_median_sq_residuals(_dev(X), _dev(y), _dev(betas), form=FORMS["materialised"])
+    for f in ("value_bits", "less", "equal", "greater", "status"):
+        assert np.array_equal(got[f], mat[f]), f
+    for c in sorted({0, m - 1}):
+        ref = oracle_mod.lms_median_sq(X, y, betas[c:c + 1])[0]
+        assert_same_result({f: got[c][f].item() for f in got.dtype.names}, ref, f"candidate {c}")

@@ -183,3 +183,18 @@ def test_knn_filtered_misleading_sample(sel, oracle_mod):
             assert got[c]["status"] == 0 and got[c]["dk"] == ref[c]["dk"], (k, c)
             assert (got[c]["below"], got[c]["equal"]) == (ref[c]["below"], ref[c]["equal"]), (k, c)
             assert abs(got[c]["mean"] - ref[c]["mean"]) <= 1e-12 * float(np.sum(np.abs(f))) / k
+
+
+def test_knn_filtered_shapes(sel, oracle_mod):
+    """The filtered form with one query over 2^21 + 7 points (one query group, many
+    segments) and with 257 queries (two groups, the second with one live query)."""
+    for n, nq, k in (((1 << 21) + 7, 1, 1000), ((1 << 16) + 1, 257, 64)):
+        P, f, Q = _knn_inputs(n, 8, nq, seed=nq)
+        Pd, fd, Qd = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (P, f, Q))
+        print(f"case knn filtered shape n={n} nq={nq} k={k}", flush=True)
+        got = sel.knn_mean(Pd, fd, Qd, k, form=2)
+        ref = oracle_mod.knn_mean(P, f, Q, k)
+        for c in range(nq):
+            assert got[c]["status"] == 0 and got[c]["dk"] == ref[c]["dk"], c
+            assert (got[c]["below"], got[c]["equal"]) == (ref[c]["below"], ref[c]["equal"]), c
+            assert abs(got[c]["mean"] - ref[c]["mean"]) <= 1e-12 * float(np.sum(np.abs(f))) / k
