@@ -174,9 +174,11 @@ CPS_HD inline double f64_from(uint64_t b) { return __builtin_bit_cast(double, b)
 
 // Monotone map from T (no NaN) to unsigned integers: a < b  <=>  key(a) < key(b),
 // with -0.0 mapped like +0.0.
+// (negative: all bits flipped; otherwise the sign bit set; written without a select: the
+// sign bit spread over the word, or'ed with the sign bit, is the mask to flip with)
 CPS_HD inline uint32_t key32(float v) {
   uint32_t b = f32_bits(v + 0.0f);
-  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+  return b ^ ((uint32_t)((int32_t)b >> 31) | 0x80000000u);
 }
 CPS_HD inline float unkey32(uint32_t k) {
   uint32_t b = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
@@ -184,7 +186,7 @@ CPS_HD inline float unkey32(uint32_t k) {
 }
 CPS_HD inline uint64_t key64(double v) {
   uint64_t b = f64_bits(v + 0.0);
-  return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+  return b ^ ((uint64_t)((int64_t)b >> 63) | 0x8000000000000000ull);
 }
 CPS_HD inline double unkey64(uint64_t k) {
   uint64_t b = (k & 0x8000000000000000ull) ? (k & 0x7fffffffffffffffull) : ~k;
