@@ -640,8 +640,8 @@ def main():
         ap.error(f"unknown legs {unknown}; known: {list(LEGS)}")
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build runs the selection on a single "
-              "MI355X; multi-GPU runs are not part of it.", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs each selection on a single "
+              "MI355X.", file=sys.stderr)
         sys.exit(2)
 
     import torch
