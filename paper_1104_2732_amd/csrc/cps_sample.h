@@ -65,6 +65,7 @@ __device__ __forceinline__ bool sample_bracket_rule(F sample, int S, int64_t n, 
   __syncthreads();
   Key kmn = (Key)~(Key)0, kmx = 0;
   bool bad = false;
+#pragma unroll 8
   for (int i = tid; i < S; i += BLOCK) {  // the sample's key range (the keys are read again below)
     const T v = sample(i);
     bad = bad || !(v == v) || v == t_inf<T>() || v == -t_inf<T>();
@@ -83,6 +84,7 @@ __device__ __forceinline__ bool sample_bracket_rule(F sample, int S, int64_t n, 
   const int nbins = (int)((khi - klo) >> shift) + 1;
   for (int b = tid; b < nbins; b += BLOCK) sh.rh[b] = 0u;
   __syncthreads();
+#pragma unroll 8
   for (int i = tid; i < S; i += BLOCK)
     atomicAdd(&sh.rh[(uint32_t)(((uint64_t)Traits<T>::key(sample(i)) - klo) >> shift)], 1u);
   __syncthreads();
