@@ -308,3 +308,25 @@ def test_timeout_leaves_the_handle_usable(sel, oracle_mod):
         for kk in (1 + n // 100, k):
             assert_same_result(sel.select_kth(xt, kk), oracle_mod.select_kth(x, kk), f"after {rep}")
     del xt
+
+
+def test_counts_past_32_bits(sel):
+    """2^32 + 17 float32 elements (16 GiB, drawn on the device; uniform [0, 1) on a 2^-24 grid,
+    so every value repeats ~256 times): counts, bins and positions past 32 bits.  The value
+    is pinned by its counts (Section 1's x_(k): less < k <= less + equal, equal >= 1), taken
+    on the device with plain comparisons, and the reported counts must equal them."""
+    n = (1 << 32) + 17
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    xt = torch.rand(n, device="cuda", generator=g, dtype=torch.float32)
+    for k in (1 + n // 100, (n + 1) // 2):
+        print(f"case counts past 32 bits n={n} k={k}", flush=True)
+        res = sel.select_kth(xt, k)
+        assert res["status"] == 0, res
+        v = torch.tensor(res["value"], dtype=torch.float32, device="cuda")
+        less = int((xt < v).sum().item())
+        equal = int((xt == v).sum().item())
+        assert (res["less"], res["equal"]) == (less, equal)
+        assert less < k <= less + equal and equal >= 1
+    del xt
+    torch.cuda.empty_cache()
