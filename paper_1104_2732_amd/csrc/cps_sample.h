@@ -44,10 +44,10 @@ struct SampleLds {
 // bracket runs from just below the bin that holds sample rank floor(q - d) to just above the
 // bin that holds rank ceil(q + d), where q = S (k - 1/2) / n is the rank's place among the S
 // sampled values and d = 4 sqrt(S p (1 - p)) + 2, p = (k - 1/2) / n (four binomial standard
-// deviations).  Where those bins hold more than twice the sampled values between the two
-// ranks (a sample whose key range is wide, as one holding an exact zero among values near
-// 1), each end's bin is split again into 2^11 sub-bins and the bracket runs from the
-// sub-bins that hold the ranks.  An end whose rank falls outside the sample is open (-inf or
+// deviations).  Where those bins hold more than 1.25 times the sampled values between the
+// two ranks (a sample whose key range is wide, as one holding an exact zero among values
+// near 1, or whose ranks fall in crowded bins), each end's bin is split again into 2^11
+// sub-bins and the bracket runs from the sub-bins that hold the ranks.  An end whose rank falls outside the sample is open (-inf or
 // +inf).  False (no bracket) when the sample holds NaN or an infinity, only one value, or
 // both ends would be open.  Every workgroup that calls it on the same sample computes the
 // same bracket.
@@ -128,7 +128,8 @@ __device__ __forceinline__ bool sample_bracket_rule(F sample, int S, int64_t n, 
   // the first key of the lower end's bin and the last key of the upper end's
   uint64_t first0 = klo + (b0 << shift);
   uint64_t last1 = klo + ((b1 + 1) << shift) - 1;
-  if (shift > 0 && below1 + in1 - below0 > 2 * (rank1 - rank0 + 1)) {  // (uniform)
+  const uint64_t want = rank1 - rank0 + 1;
+  if (shift > 0 && below1 + in1 - below0 > want + want / 4) {  // (uniform)
     // each end's bin in sub-bins: the lower end's in rh[0, 2048), the upper end's after it
     constexpr int kHalf = kHistMaxBins / 2;
     const int sub = shift > 11 ? shift - 11 : 0;
