@@ -237,7 +237,10 @@ def batched_leg(sel, cps, torch, reps: int = 5) -> dict:
 def batched_large_leg(sel, cps, torch, reps: int = 5) -> dict:
     """Few large arrays (64 lognormal float32 arrays of 2^22 elements, median ranks): one
     workgroup per array leaves most of the chip idle; split over 16 workgroups each they fill
-    it."""
+    it.  The copy of each array's sampled-bracket interior gets room for 2^20 elements (the
+    default 2^18 is sized for arrays of ~10^6 elements: an overflowing copy sends the array
+    back over its full length with one workgroup, also timed); the autotuner sizes it from
+    the batch itself."""
     g = torch.Generator(device="cuda")
     g.manual_seed(12345)
     x = torch.exp(torch.randn((64, 1 << 22), generator=g, device="cuda", dtype=torch.float32))
@@ -245,9 +248,14 @@ def batched_large_leg(sel, cps, torch, reps: int = 5) -> dict:
     ks = [((1 << 22) + 1) // 2] * 64
     ptrs, szs, kk, code = sel.batch_descriptors(dev, ks)
     out = sel.new_results(64)
-    cases = {"one_workgroup_per_array": dict(),
-             "16_workgroups_per_array": dict(blocks_per_array=16, elements_per_block=1 << 18),
+    cases = {"one_workgroup_per_array": dict(team_capacity=1 << 20),
+             "16_workgroups_per_array": dict(blocks_per_array=16, elements_per_block=1 << 18,
+                                             team_capacity=1 << 20),
+             "16_workgroups_per_array_default_capacity": dict(blocks_per_array=16,
+                                                              elements_per_block=1 << 18),
              "without_sampled_bracket": dict(proposal=0)}
+    best, _ = sel.autotune_batched(ptrs, szs, kk, 64, code, out)
+    cases["autotuned"] = {f: getattr(best, f) for f, _ in cps.BatchOptions._fields_}
     res = {}
     ref = None
     for name, kw in cases.items():
@@ -256,7 +264,11 @@ def batched_large_leg(sel, cps, torch, reps: int = 5) -> dict:
         r = out.cpu().numpy().view(cps.RESULT_DTYPE).copy()
         ref = r if ref is None else ref
         res[name] = {"ms": round(ms, 4), "elements_per_s": 64 * (1 << 22) / (ms * 1e-3),
+                     "passes_per_array_mean": float(r["passes"].mean()),
                      "identical": bool(np.array_equal(r["value_bits"], ref["value_bits"]))}
+    res["autotuned"]["options"] = {f: cases["autotuned"][f] for f in
+                                   ("block_threads", "proposal", "blocks_per_array",
+                                    "elements_per_block", "team_capacity")}
     del x, dev
     return {"workload": "64 lognormal(0,1) float32 arrays of 2^22 elements, median ranks",
             "cases": res}

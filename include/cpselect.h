@@ -344,7 +344,8 @@ int cps_objective(cps_handle *h, const void *x, int64_t n, int64_t k, int dtype,
  *                  enough for arrays of about a million elements); a copy that does not fit
  *                  makes pass 0's counts decide alone and the array continues over its full
  *                  length (exact, slower).  Each workgroup has one such buffer, and each
- *                  split array one more. */
+ *                  split array one more.  The autotuner sizes it from the batch's largest
+ *                  array. */
 typedef struct cps_batch_options {
   int32_t block_threads;
   int32_t blocks_per_cu;
@@ -388,7 +389,9 @@ int cps_reserve_batched(cps_handle *h, int dtype, const cps_batch_options *opt);
 /* Autotuner: time each candidate launch shape (256, 512, 1024 threads) with the sampled
  * bracket and one workgroup per array or 4, 8 or 16 per array at 2^16 .. 2^18 elements per
  * workgroup, without it (the counting evaluation from [min, max]), and with splits at split
- * capacities 2^17 and 2^19, on this very batch (the call synchronises `stream`); keep the
+ * capacities 2^17 and 2^19, on this very batch (the call synchronises `stream`; the
+ * candidates with the sampled bracket get a team_capacity of a quarter of the largest
+ * array's elements, between the default 2^18 and 2^22); keep the
  * fastest as the handle's choice for `dtype`, and return it in best (may be NULL) with its
  * time in *best_ms (may be NULL).  The results in out_dev are those of the last timed
  * candidate. */

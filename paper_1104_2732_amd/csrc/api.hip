@@ -700,6 +700,23 @@ int cps_autotune_batched(cps_handle *h, const void *const *ptrs_dev, const int64
                         {0, 1, 0, 1, 0},
                         {0, 1, 0, 0, (int64_t)1 << 17},
                         {0, 1, 0, 0, (int64_t)1 << 19}};
+  // A sampled bracket's copy holds the 16-byte vectors of x that hold an interior element
+  // (~23 % of a float array of ~10^6 elements, ~12 % of a double one); a copy that does not
+  // fit sends the array back over its full length with one workgroup.  The candidates that
+  // copy get room for a quarter of the batch's largest array (at least the default 2^18
+  // elements, at most 2^22).
+  int64_t team_cap = 0;
+  {
+    std::vector<int64_t> hs((size_t)count);
+    if (hipMemcpyAsync(hs.data(), sizes_dev, (size_t)count * sizeof(int64_t),
+                       hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return CPS_EHIP;
+    int64_t mx = 0;
+    for (const int64_t v : hs) mx = v > mx ? v : mx;
+    const int64_t q = (mx / 4 + 63) / 64 * 64;
+    if (q > ((int64_t)1 << 18)) team_cap = q < ((int64_t)1 << 22) ? q : ((int64_t)1 << 22);
+  }
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return CPS_EHIP;
   double best_t = 1e300;
@@ -716,6 +733,7 @@ int cps_autotune_batched(cps_handle *h, const void *const *ptrs_dev, const int64
       if (cd.epb) o.elements_per_block = cd.epb;
       o.count_first = cd.count_first;
       if (cd.cap) o.split_capacity = cd.cap;
+      if (cd.proposal && team_cap) o.team_capacity = team_cap;
       rc = select_kth_batched_ex(h, ptrs_dev, sizes_dev, ks_dev, count, dtype, &o, out_dev, stream);
       if (rc == CPS_ENOMEM) continue;  // this candidate's workspace does not fit
       if (rc) { last_rc = rc; break; }

@@ -241,3 +241,32 @@ def test_full_size_workload_sampled(sel, oracle_mod):
         r = {n: res[i][n].item() for n in res.dtype.names}
         assert_same_result(r, oracle_mod.select_kth(arrays[i], int(ks[i])), f"array {i}")
     del dev
+
+
+def test_autotuner_sizes_the_copy_capacity(oracle_mod):
+    """The autotuner on a batch holding one array of 2^21 elements: candidates with the
+    sampled bracket get a copy capacity of a quarter of the largest array (2^19 here, above
+    the default 2^18), and the tuned handle's calls without options match the oracle.  A
+    handle of its own, so the tuned choice reaches no other test."""
+    import paper_1104_2732_amd as cps
+    arrays, ks = _mixed_batch(np.float32, 12, seed=31)
+    big = workloads.single_array("lognormal", 1 << 21, np.float32, seed=31, tag="gpu-batched")
+    arrays.append(big)
+    ks.append(((1 << 21) + 1) // 2)
+    s = cps.Selector(0)
+    try:
+        dev = [torch.from_numpy(a).cuda() for a in arrays]
+        ptrs, sizes, kk, code = s.batch_descriptors(dev, ks)
+        out = s.new_results(len(dev))
+        print("case autotune with a 2^21 array", flush=True)
+        best, ms = s.autotune_batched(ptrs, sizes, kk, len(dev), code, out)
+        assert ms > 0
+        if best.proposal == 1:
+            assert best.team_capacity == (1 << 21) // 4
+        _check_all(out.cpu().numpy().view(cps.RESULT_DTYPE), arrays, ks, oracle_mod, "autotune")
+        out2 = s.new_results(len(dev))
+        s.select_kth_batched_async(ptrs, sizes, kk, len(dev), code, out2)
+        torch.cuda.synchronize()
+        _check_all(out2.cpu().numpy().view(cps.RESULT_DTYPE), arrays, ks, oracle_mod, "tuned")
+    finally:
+        s.close()
