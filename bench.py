@@ -254,7 +254,11 @@ def batched_large_leg(sel, cps, torch, reps: int = 5) -> dict:
              "16_workgroups_per_array_default_capacity": dict(blocks_per_array=16,
                                                               elements_per_block=1 << 18),
              "without_sampled_bracket": dict(proposal=0)}
-    best, _ = sel.autotune_batched(ptrs, szs, kk, 64, code, out)
+    tuner = cps.Selector(0)  # a handle of its own: the tuned choice stays out of later legs
+    try:
+        best, _ = tuner.autotune_batched(ptrs, szs, kk, 64, code, out)
+    finally:
+        tuner.close()
     cases["autotuned"] = {f: getattr(best, f) for f, _ in cps.BatchOptions._fields_}
     res = {}
     ref = None
