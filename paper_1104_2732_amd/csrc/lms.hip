@@ -388,7 +388,10 @@ constexpr int kLmsRounds = 2;
 
 // ---- the filtered form's finish: one workgroup's exact select (cps_wgsel.h) over an array
 
-constexpr int kLmsSelCap = 1024;  // elements a narrowed key range may hold to finish in LDS
+// elements a narrowed key range may hold to finish in LDS (992: the gather kernel then fits
+// four workgroups per CU, so 1024 candidates run in one round; 1024 left a second round of
+// 256 on a third of the chip)
+constexpr int kLmsSelCap = 992;
 using WgSelLds = WgSelShared<kLmsGatherBlock>;
 
 // The k-th smallest of W[0, len) (wg_select_pass over the array, eight loads per step).
