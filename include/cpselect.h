@@ -511,7 +511,7 @@ int knn_mean(cps_handle *h, const float *P_dev, const float *f_dev, const float 
 /* knn_mean with a choice of form (cps_lms_form; CPS_LMS_AUTO is knn_mean, which takes the
  * filtered form from n = 2^15 on).  Filtered: each query's sampled bracket (a, b) from the
  * distances of the points the batched kernel would sample, one pass over the points that
- * keeps the distances in (a, b) (and NaN) with their ordinates (at most 8192 per query),
+ * keeps the distances in (a, b) (and NaN) with their ordinates (at most 8128 per query),
  * counting d <= a and summing its ordinates; d_k by a radix select among the kept ones, the
  * sums below and at d_k in a fixed order.  A query whose bracket misses d_k, or that keeps
  * more, is selected by one workgroup over its distances recomputed.  Same results (the

@@ -178,7 +178,9 @@ struct KnnFilterBufs {
   float *K;            // nq x kKnnCap x 2: kept distances and ordinates
   int64_t nseg, seg;   // the filter's segments and points per segment
 };
-constexpr int64_t kKnnKeptCap = 8192;  // kept distances per query (the filtered form)
+// kept distances per query (the filtered form); 8128 keeps the select kernel under half a
+// CU's LDS (two workgroups per CU; at 8192 it was 208 bytes over and ran one)
+constexpr int64_t kKnnKeptCap = 8128;
 void knn_filter_shape(int64_t n, int64_t nq, int cu_count, int64_t *nseg, int64_t *seg);
 hipError_t launch_knn_filtered(const float *P, const float *f, const float *Q, int64_t n,
                                int32_t dim, int64_t nq, int64_t k, const KnnFilterBufs &w,
